@@ -1,0 +1,107 @@
+"""Dense per-block operators: plain definitions, no sum factorization.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Paper passages followed:
+
+* Sec. 3.1, eq. (eval_pipeline): on a Cartesian cell the volume operator is
+  the Kronecker sum K (x) M (x) M + M (x) K (x) M + M (x) M (x) K, with 1D
+  factors scaled by the cell size.  For an axis-aligned box with edge
+  lengths (h_x, h_y, h_z) the factors are M_d = h_d M_hat and K_d = K_hat/h_d;
+  for a cube this is the h^{d-2} prefactor of the equation.
+* Sec. 5.2, eq. (cell_block): the cell block D_K has the same Kronecker-sum
+  form with K replaced by A_hat = stiffness + own-side face blocks, scaled
+  as A_d = A_hat / h_d.  It is symmetric positive definite.
+* Sec. 2 (blocked storage): a block's DoFs are indexed (i_x, i_y, i_z); here
+  the canonical flat index is q = (i_x n + i_y) n + i_z, so x is the slowest
+  index and the first Kronecker slot acts on x.
+
+apply  = dense matrix-vector product with the n^3 x n^3 matrix.
+solve  = LAPACK dense solve followed by refinement steps whose residual is
+         formed in numpy long double (80-bit on x86), so the result is the
+         exact solution up to a few FP64 ulps even at condition numbers ~1e3.
+
+Pins: A 1 = 0 for the Neumann block; symmetry and definiteness; the energy
+u^T A u of interpolated polynomials equals the exact Dirichlet integral on an
+anisotropic box; isotropic scaling A(h) = h A(1); the generalized eigenvalues
+of (D, M (x) M (x) M) are the sums of the 1D ones; brute-force 3D/2D
+quadrature assembly of the volume and face integrals with an independently
+built basis; the long-double residual of the solve.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import basis
+
+NEUMANN = "neumann"     # 1D factor K: pure stiffness, the volume operator
+CELL = "cell"           # 1D factor A_hat: the SIPG cell block of eq. (cell_block)
+
+
+def reference_pair(p: int, op: str, C: float = 2.0):
+    """(M_hat, P_hat) with P_hat = K_hat (Neumann) or A_hat (cell block)."""
+    M, K = basis.mass_stiffness(p)
+    if op == NEUMANN:
+        return M, K
+    if op == CELL:
+        return M, basis.penalized_stiffness(p, C)
+    raise ValueError(f"unknown operator {op!r}")
+
+
+def direction_factors(p: int, h, op: str, C: float = 2.0):
+    """Per-direction physical 1D factors [(M_x, P_x), (M_y, P_y), (M_z, P_z)]."""
+    M, P = reference_pair(p, op, C)
+    return [(float(hd) * M, P / float(hd)) for hd in h]
+
+
+def dense_operator(p: int, h, op: str = NEUMANN, C: float = 2.0) -> np.ndarray:
+    """The n^3 x n^3 block matrix P_x(x)M_y(x)M_z + M_x(x)P_y(x)M_z + M_x(x)M_y(x)P_z."""
+    (Mx, Px), (My, Py), (Mz, Pz) = direction_factors(p, h, op, C)
+    return (np.kron(np.kron(Px, My), Mz)
+            + np.kron(np.kron(Mx, Py), Mz)
+            + np.kron(np.kron(Mx, My), Pz))
+
+
+def dense_mass(p: int, h) -> np.ndarray:
+    """M_x (x) M_y (x) M_z, the block mass matrix."""
+    M, _ = basis.mass_stiffness(p)
+    return np.kron(np.kron(h[0] * M, h[1] * M), h[2] * M)
+
+
+def apply(p: int, h_all, u_all, op: str = NEUMANN, C: float = 2.0) -> np.ndarray:
+    """v_b = A_b u_b for every block b; u_all is (nblocks, n^3), h_all is (nblocks, 3)."""
+    h_all = np.asarray(h_all, dtype=np.float64).reshape(-1, 3)
+    u_all = np.asarray(u_all, dtype=np.float64)
+    out = np.empty_like(u_all)
+    for b in range(u_all.shape[0]):
+        out[b] = dense_operator(p, h_all[b], op, C) @ u_all[b]
+    return out
+
+
+def solve_block(D: np.ndarray, r: np.ndarray, refine: int = 2) -> np.ndarray:
+    """x with D x = r: LAPACK solve, then ``refine`` steps of iterative
+    refinement with the residual r - D x accumulated in long double."""
+    x = np.linalg.solve(D, r)
+    if refine:
+        D_ld = D.astype(np.longdouble)
+        r_ld = np.asarray(r).astype(np.longdouble)
+        for _ in range(refine):
+            res = r_ld - D_ld @ x.astype(np.longdouble)
+            x = x + np.linalg.solve(D, res.astype(np.float64))
+    return x
+
+
+def solve(p: int, h_all, r_all, op: str = CELL, C: float = 2.0, refine: int = 2) -> np.ndarray:
+    """x_b = D_b^{-1} r_b for every block (dense solve, the plain definition of
+    the cell-block inverse of Sec. 5.2)."""
+    h_all = np.asarray(h_all, dtype=np.float64).reshape(-1, 3)
+    r_all = np.asarray(r_all, dtype=np.float64)
+    out = np.empty_like(r_all)
+    for b in range(r_all.shape[0]):
+        out[b] = solve_block(dense_operator(p, h_all[b], op, C), r_all[b], refine)
+    return out
+
+
+def condition_number(p: int, h, op: str = CELL, C: float = 2.0) -> float:
+    """2-norm condition number of the dense block matrix."""
+    return float(np.linalg.cond(dense_operator(p, h, op, C)))

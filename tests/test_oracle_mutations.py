@@ -1,0 +1,95 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that a pin fails.
+
+Each mutation monkeypatches one oracle function with a wrong variant; the
+listed pins must then raise.  This keeps the pins honest: a dropped term,
+wrong sign, wrong index order or wrong scaling anywhere in the oracle is
+caught by at least one of them.
+"""
+import numpy as np
+import pytest
+
+import tests.test_oracle_pins as pins
+from oracle import basis, dense
+
+
+def _wrong_sign_face_blocks(e0, g0, e1, g1, sigma):
+    N = _ORIG_FACE(e0, g0, e1, g1, sigma)
+    o = np.outer
+    N["++"] = sigma * o(e0, e0) - 0.5 * (o(e0, g0) + o(g0, e0))
+    return N
+
+
+def _dropped_face_blocks(e0, g0, e1, g1, sigma):
+    N = _ORIG_FACE(e0, g0, e1, g1, sigma)
+    N["++"] = np.zeros_like(N["++"])
+    return N
+
+
+def _low_quadrature_mass_stiffness(p):
+    nodes = basis.gll_nodes(p)
+    xq, wq = basis.gauss_legendre(p)          # one point short of exact
+    L = basis.lagrange_values(nodes, xq)
+    D = basis.lagrange_derivatives(nodes, xq)
+    return (L * wq[:, None]).T @ L, (D * wq[:, None]).T @ D
+
+
+def _swapped_slot_operator(p, h, op=dense.NEUMANN, C=2.0):
+    (Mx, Px), (My, Py), (Mz, Pz) = dense.direction_factors(p, h, op, C)
+    # x-factor put in the last slot: transposed index order
+    return (np.kron(np.kron(Mz, My), Px) + np.kron(np.kron(Mz, Py), Mx)
+            + np.kron(np.kron(Pz, My), Mx))
+
+
+def _dropped_term_operator(p, h, op=dense.NEUMANN, C=2.0):
+    (Mx, Px), (My, Py), (Mz, Pz) = dense.direction_factors(p, h, op, C)
+    return np.kron(np.kron(Px, My), Mz) + np.kron(np.kron(Mx, Py), Mz)
+
+
+def _wrong_scaling_factors(p, h, op, C=2.0):
+    M, Pm = dense.reference_pair(p, op, C)
+    return [(float(hd) * M, Pm * float(hd)) for hd in h]
+
+
+_ORIG_FACE = basis.face_blocks
+
+
+def _run_all(fns):
+    """True when at least one pin raises AssertionError."""
+    for fn in fns:
+        try:
+            fn()
+        except (AssertionError, np.linalg.LinAlgError):
+            return True
+    return False
+
+
+PIN_SUITE = [
+    lambda: pins.test_penalized_monomial_form(3, 2.0),
+    lambda: pins.test_penalized_eigenvalues_p2_closed_form(),
+    lambda: pins.test_face_blocks_reproduce_printed_hermite_stencil(),
+    lambda: pins.test_p2_mass_stiffness_textbook(),
+    lambda: pins.test_monomial_moments(3),
+    lambda: pins.test_energy_of_interpolated_polynomial(3, (1, 2, 3)),
+    lambda: pins.test_cell_block_energy_closed_form(3, (1, 2, 3), 2.0),
+    lambda: pins.test_bruteforce_quadrature_assembly(2, dense.CELL),
+    lambda: pins.test_neumann_block_properties(3),
+    lambda: pins.test_isotropic_scaling(3),
+]
+
+
+@pytest.mark.parametrize("target,replacement", [
+    ((basis, "face_blocks"), _wrong_sign_face_blocks),
+    ((basis, "face_blocks"), _dropped_face_blocks),
+    ((basis, "mass_stiffness"), _low_quadrature_mass_stiffness),
+    ((dense, "dense_operator"), _swapped_slot_operator),
+    ((dense, "dense_operator"), _dropped_term_operator),
+    ((dense, "direction_factors"), _wrong_scaling_factors),
+])
+def test_planted_mistake_is_caught(monkeypatch, target, replacement):
+    mod, name = target
+    monkeypatch.setattr(mod, name, replacement)
+    assert _run_all(PIN_SUITE), f"no pin caught the mutation of {mod.__name__}.{name}"
+
+
+def test_unmutated_suite_passes():
+    assert not _run_all(PIN_SUITE)
