@@ -1,0 +1,248 @@
+"""Benchmark of the batched tensor-product hot path on one MI355X.
+
+One step = one pass of the hot path over one batch: the volume operator
+v = A u (apply, Neumann factor K) followed by the fast-diagonalization
+inverse x = D^{-1} v of the SIPG cell block, both in the workload's precision,
+on inputs already resident in HBM.  Throughput = DoF / step time (the paper's
+N_dof / t normalisation, Sec. 6.1).  Input/output buffer sets are rotated so
+the working set exceeds the 256 MB last-level cache and the rate is an HBM
+rate.
+
+Prints ONE JSON line.  Besides the contract fields it carries:
+  roofline      the dominant kernel's algorithmic bytes per launch over its
+                average launch time (HIP events), against 8 TB/s
+  cpu_baseline  the FP64 dense oracle timed on a bounded sample on the host
+  ops           per-operation rates (apply, apply_inverse, solve)
+  solve_latency per-call wall time percentiles of the block-local solve
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    from paper_2609_04534_amd import workloads
+    table = {
+        "p3_64cube_affine": (workloads.affine_p3, "f64"),
+        "p2_8cube_h1/8": (workloads.small_p2, "f64"),
+        "p2_128cube": (workloads.large_p2, "f64"),
+        "p7_32cube_aniso": (workloads.mixed_precision_p7, "f32"),
+        "uneven_p237_20000": (workloads.uneven_degrees, "f32"),
+    }
+    fn, dt = table[name]
+    return fn(with_rhs=True), dt
+
+
+def algorithmic_bytes(wl, esize):
+    """2 n^3 s + 24 bytes per block: vector in, vector out, three FP64 lengths."""
+    return sum(g.nblocks * (2 * g.n ** 3 * esize + 24) for g in wl.groups)
+
+
+def flops(wl, which):
+    per = {"apply": lambda n: 14 * n ** 4 + 2 * n ** 3, "inverse": lambda n: 12 * n ** 4 + n ** 3}[which]
+    return sum(g.nblocks * per(g.n) for g in wl.groups)
+
+
+def time_launches(fn, stream, reps, sets):
+    """Average milliseconds per call of fn(k) over reps calls, HIP events on stream."""
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for i in range(reps):
+        fn(i % sets)
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / reps
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """Time the FP64 dense oracle (apply + solve per block) on a bounded
+    sample of the workload's blocks; report DoF/s."""
+    from oracle import dense
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    c0 = time.process_time()
+    dof = 0
+    nblk = 0
+    order = [(gi, b) for gi, g in enumerate(wl.groups) for b in range(g.nblocks)]
+    idx = rng.permutation(len(order))
+    for k in idx:
+        gi, b = order[k]
+        g = wl.groups[gi]
+        v = dense.apply(g.p, g.h[b:b + 1], g.u[b:b + 1], dense.NEUMANN)
+        dense.solve(g.p, g.h[b:b + 1], v, dense.CELL)
+        dof += g.n ** 3
+        nblk += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    return {"value": dof / wall / 1e9, "unit": "GDoF/s", "cores": max(1, int(round(cpu / wall))),
+            "kind": "oracle",
+            "sample": f"{nblk} random blocks of {wl.name} (dense Kronecker apply + dense solve with "
+                      f"long-double refinement, FP64), {wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="p3_64cube_affine")
+    ap.add_argument("--rotate", type=int, default=4)
+    ap.add_argument("--solve-calls", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the blocks are independent and each GPU would run the "
+              f"same kernels on its share; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_04534_amd import tpfdm
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    tpfdm.load()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    _log(f"workload {args.workload}")
+    wl, dtname = build_workload(args.workload)
+    dt = {"f64": tpfdm.F64, "f32": tpfdm.F32}[dtname]
+    tdt = {tpfdm.F64: torch.float64, tpfdm.F32: torch.float32}[dt]
+    esize = 8 if dt == tpfdm.F64 else 4
+    plan = tpfdm.Plan(tpfdm.groups_for_workload(wl))
+    plan.setup_inverse(tpfdm.OP_CELL)
+    ndof = plan.ndof
+    E = plan.vector_elems
+    canon_u = torch.from_numpy(np.concatenate([g.u.reshape(-1) for g in wl.groups])).cuda()
+    canon_b = torch.from_numpy(np.concatenate([g.b.reshape(-1) for g in wl.groups])).cuda()
+    R = max(1, args.rotate)
+    U, V, X = [], [], []
+    for _ in range(R):
+        bu = torch.empty(E, dtype=tdt, device="cuda")
+        plan.pack(canon_u.to(tdt), bu)
+        U.append(bu)
+        V.append(torch.empty(E, dtype=tdt, device="cuda"))
+        X.append(torch.empty(E, dtype=tdt, device="cuda"))
+    torch.cuda.synchronize()
+    _log(f"ndof={ndof} vector_elems={E} sets={R}")
+
+    def step(k):
+        plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream)
+        plan.apply_inverse(V[k], X[k], stream=stream)
+
+    for i in range(args.warmup):
+        step(i % R)
+    torch.cuda.synchronize()
+    _log("warmup done")
+    ms_step = time_launches(step, stream, args.steps, R)
+    _log(f"step {ms_step:.4f} ms")
+    reps = max(args.steps, 20)
+    ms_apply = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
+    ms_inv = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
+    _log(f"apply {ms_apply:.4f} ms, inverse {ms_inv:.4f} ms")
+
+    # solve: FP64 residual + FP32 inner, rtol 1e-10, per-call latency
+    bb = torch.empty(E, dtype=torch.float64, device="cuda")
+    plan.pack(canon_b, bb)
+    xs = torch.zeros(E, dtype=torch.float64, device="cuda")
+    lat = []
+    summ = None
+    for i in range(args.solve_calls + 3):
+        xs.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        summ = plan.solve(bb, xs, inner=tpfdm.F32, rtol=1e-10, maxit=50, stream=stream)
+        t1 = time.perf_counter()
+        if i >= 3:
+            lat.append((t1 - t0) * 1e3)
+    lat = np.array(lat)
+    _log(f"solve p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms {summ}")
+
+    bytes_launch = algorithmic_bytes(wl, esize)
+    dom_name, dom_ms = ("tp_apply_inverse", ms_inv) if ms_inv >= ms_apply else ("tp_apply", ms_apply)
+    achieved = bytes_launch / (dom_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        try:
+            tj = json.load(open(tfile))
+            ent = tj.get(args.workload, {}).get(dom_name)
+            if ent and ent.get("kernel_hash") == kernel_hash():
+                traffic = ent["bytes_per_launch"]
+        except Exception:
+            traffic = None
+
+    out = {
+        "metric": "GDoF/s apply+FDM-inverse at p=2/3/7, FP64 vs mixed; solve p50/p99 latency",
+        "value": ndof / (ms_step * 1e-3) / 1e9,
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtname,
+        "data": "synthetic (seeded uniform[-1,1] vectors, seeded cell lengths)",
+        "config": {"workload": args.workload, "nblocks": wl.nblocks, "ndof": ndof,
+                   "degrees": sorted({g.p for g in wl.groups}),
+                   "layout_B": {str(g.n): tpfdm.default_layout_B(g.n) for g in wl.groups},
+                   "buffer_sets": R, "step": "apply(Neumann) then apply_inverse(cell block)"},
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_launch, "avg_launch_ms": dom_ms},
+        "ops": {
+            "apply": {"ms": ms_apply, "GDoF/s": ndof / ms_apply / 1e6,
+                      "GB/s": bytes_launch / ms_apply / 1e6, "TFLOP/s": flops(wl, "apply") / ms_apply / 1e9},
+            "apply_inverse": {"ms": ms_inv, "GDoF/s": ndof / ms_inv / 1e6,
+                              "GB/s": bytes_launch / ms_inv / 1e6,
+                              "TFLOP/s": flops(wl, "inverse") / ms_inv / 1e9},
+        },
+        "solve_latency": {"inner": "f32", "rtol": 1e-10, "calls": int(len(lat)),
+                          "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                          "GDoF/s_p50": ndof / np.percentile(lat, 50) / 1e6,
+                          "max_iters": summ["max_iters"] if summ else None,
+                          "max_relres": summ["max_relres"] if summ else None},
+    }
+    if not args.no_cpu_baseline:
+        _log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    else:
+        out["cpu_baseline"] = None
+    plan.destroy()
+    print(json.dumps(out), flush=True)
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip",):
+        h.update(open(os.path.join(ROOT, "paper_2609_04534_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * tpfdm -- batched tensor-product operators and their fast-diagonalization
+ * inverse on AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv 2609.04534, "Adaptive Multilevel Discontinuous Galerkin
+ * Methods on GPUs".  The library implements, for a batch of independent
+ * hexahedral blocks (cells or patches) of tensor-product degree p, n = p+1
+ * points per direction:
+ *
+ *   apply          v = (P_x (x) M_y (x) M_z + M_x (x) P_y (x) M_z
+ *                       + M_x (x) M_y (x) P_z) u              Sec. 3.1, eq. (eval_pipeline)
+ *   apply_inverse  x = D^{-1} r by fast diagonalization        Sec. 5.2, eq. (cell_block)
+ *   solve          D x = b by block-local iterative refinement with a
+ *                  low-precision fast-diagonalization inner solve
+ *
+ * with per-direction factors M_d = h_d M_hat, P_d = P_hat / h_d on a block of
+ * edge lengths (h_x, h_y, h_z) (Sec. 2: every Cartesian cell is a scaled
+ * translate of the reference cube).  P_hat is either the 1D stiffness K_hat
+ * ("Neumann" volume operator) or A_hat = K_hat + the own-side blocks of both
+ * SIPG face stencils with penalty C p(p+1)/h (eq. (face_coupling), Sec. 5.2,
+ * Sec. 6.2).  The basis is the Lagrange basis on the n Gauss-Lobatto points
+ * of [0, 1]; M_hat and K_hat are its exact integrals.
+ *
+ * Vector layout (Sec. 2, blocked storage [B, n_x, n_y, n_z, n_e]): group g of
+ * a plan occupies elements [offset, offset + tiles * n^3 * B) of every vector
+ * buffer, with tiles = ceil(nblocks / B).  Block b of the group lives in tile
+ * t = b / B at lane l = b % B, and its DoF q = (i_x n + i_y) n + i_z is
+ * element  offset + (t * n^3 + q) * B + l.  B is a power of two; B = 1 is the
+ * plain block-contiguous (node-major) order.  Lanes of the last tile beyond
+ * nblocks are padding: they are never read as input and never written.
+ *
+ * Conventions shared by every call:
+ *  - Every pointer named "device" must be device memory (hipMalloc or torch);
+ *    the caller owns all vectors.  The plan owns its own copies of the block
+ *    metadata and all workspace.
+ *  - Calls taking a stream are asynchronous on that stream; argument errors
+ *    are returned synchronously, errors of a kernel surface at the caller's
+ *    next synchronisation (and as TP_ERR_HIP from later calls).
+ *  - Outputs are overwritten, never accumulated.  Input and output buffers
+ *    must not alias.
+ *  - No call aborts or prints.  On error the call returns a negative status
+ *    and tp_last_error() returns a message (thread-local).
+ *  - A plan may be used from one host thread at a time; distinct plans are
+ *    independent.
+ */
+#ifndef TPFDM_H
+#define TPFDM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TP_OK = 0,
+    TP_ERR_ARG = -1,           /* invalid argument (null, size, layout, value)     */
+    TP_ERR_UNSUPPORTED = -2,   /* n, dtype, layout or mode not supported            */
+    TP_ERR_NOT_SPD = -3,       /* Cholesky of the 1D mass matrix failed             */
+    TP_ERR_SINGULAR = -4,      /* min eigenvalue sum <= tol * max (e.g. Neumann)    */
+    TP_ERR_NOT_CONVERGED = -5, /* some block missed rtol within maxit               */
+    TP_ERR_NONFINITE = -6,     /* NaN/Inf in an input or a residual                 */
+    TP_ERR_HIP = -7,           /* a HIP runtime call failed                         */
+    TP_ERR_OOM = -8,           /* device allocation failed                          */
+    TP_ERR_STATE = -9          /* call out of order (e.g. inverse before setup)     */
+} tp_status;
+
+typedef enum { TP_F64 = 0, TP_F32 = 1, TP_F16 = 2, TP_BF16 = 3 } tp_dtype;
+
+/* Which 1D operator P_hat fills the Kronecker sum. */
+typedef enum {
+    TP_OP_NEUMANN = 0,  /* P_hat = K_hat: the volume operator of eq. (eval_pipeline); A 1 = 0 */
+    TP_OP_CELL = 1      /* P_hat = A_hat: the SIPG cell block of eq. (cell_block); SPD        */
+} tp_operator;
+
+/* How per-block eigenfactors are represented.  SCALED: one generalized
+ * eigenproblem A_hat S = M_hat S Lambda per degree; a block with lengths h_d
+ * uses S_d = S_hat / sqrt(h_d), lambda_d = lambda_hat / h_d^2, which is the
+ * exact eigen-decomposition of its own pair (P_hat/h_d, h_d M_hat). */
+typedef enum { TP_FACTOR_SCALED = 0 } tp_factor_mode;
+
+/* One group of blocks of equal degree and layout. */
+typedef struct {
+    int32_t n;            /* points per direction, 2 <= n <= 8 (degree p = n-1)       */
+    int32_t layout_B;     /* interleave width B, a power of two, 1 <= B <= 1024        */
+    int64_t nblocks;      /* number of blocks (0 allowed)                             */
+    const double* h;      /* [nblocks][3] edge lengths (x, y, z), host or device,
+                             finite and > 0; copied into the plan at creation        */
+    int64_t offset;       /* first element of the group in every vector buffer        */
+} tp_group;
+
+typedef struct {
+    double penalty_C;     /* SIPG penalty constant C of sigma = C p(p+1)/h (default 2) */
+    int32_t persistent;   /* 1: every call runs as ONE launch over all groups          */
+    int32_t reserved[7];  /* must be zero                                             */
+} tp_plan_opts;
+
+typedef struct {
+    int32_t max_iters;    /* largest per-block iteration count                        */
+    int32_t n_failed;     /* blocks that missed rtol                                  */
+    double max_relres;    /* largest per-block final ||b - D x||_2 / ||b||_2          */
+} tp_solve_summary;
+
+typedef struct tp_plan tp_plan;
+
+/* Default options: C = 2, non-persistent. */
+void tp_plan_opts_default(tp_plan_opts* opts);
+
+/* Create a plan over ngroups groups on the current HIP device.  Validates the
+ * groups (n, B, sizes, non-overlapping element ranges, h finite and > 0),
+ * copies h into plan-owned device memory, builds the 1D reference matrices
+ * for every degree used, and allocates the solve workspace.  Host-synchronous.
+ * Errors: TP_ERR_ARG, TP_ERR_UNSUPPORTED, TP_ERR_OOM, TP_ERR_HIP. */
+tp_status tp_plan_create(const tp_group* groups, int32_t ngroups,
+                         const tp_plan_opts* opts, tp_plan** out);
+
+/* Free everything the plan owns.  Null is accepted. */
+tp_status tp_plan_destroy(tp_plan* plan);
+
+/* Number of elements every vector buffer must hold:
+ * max over groups of offset + ceil(nblocks/B) * n^3 * B.  -1 on a null plan. */
+int64_t tp_plan_vector_elems(const tp_plan* plan);
+
+/* Total degrees of freedom sum_g nblocks_g * n_g^3 (padding excluded). */
+int64_t tp_plan_ndof(const tp_plan* plan);
+
+/* v <- A u for every block of every group, in dtype (storage and contraction
+ * operands); FP64 accumulates in FP64, the others in FP32.  u, v: device
+ * buffers of tp_plan_vector_elems() elements of dtype.  Sec. 3.1,
+ * eq. (eval_pipeline) with P_hat chosen by op. */
+tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v,
+                   tp_dtype dtype, hipStream_t stream);
+
+/* Fast-diagonalization setup for the operator op (Sec. 5.2): per degree,
+ * Cholesky M_hat = L L^T, symmetric Jacobi eigen-decomposition of
+ * L^{-1} P_hat L^{-T}, S_hat = L^{-T} Q, in FP64 on the host.  Fails with
+ * TP_ERR_SINGULAR when lambda_min <= singular_tol * lambda_max (the Neumann
+ * operator, whose constants are in the null space), TP_ERR_NOT_SPD when M_hat
+ * is not SPD.  singular_tol <= 0 selects 1e-12.  Host-synchronous. */
+tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode,
+                           double singular_tol);
+
+/* x <- D^{-1} r = (S (x) S (x) S) Lambda^{-1} (S (x) S (x) S)^T r for every
+ * block: six 1D contractions and one diagonal scaling (Sec. 5.2).  Lambda^{-1}
+ * is formed in FP64 for TP_F64 and FP32 otherwise.  Requires tp_setup_inverse
+ * (TP_ERR_STATE otherwise).  r, x: device, dtype, tp_plan_vector_elems(). */
+tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype,
+                           hipStream_t stream);
+
+/* Solve D x = b for every block by iterative refinement, one launch:
+ *   r = b - D x (FP64);  s = ||r||_inf;  d = D~^{-1}(r/s) in `inner` precision;
+ *   x <- x + s d  (FP64)
+ * until ||r||_2 / ||b||_2 <= rtol or maxit corrections.  A block with b = 0
+ * gets x = 0 and 0 iterations.  b, x: device FP64 vectors; x holds the initial
+ * guess on entry and the best iterate on exit.  iters (int32) and relres
+ * (double): optional device arrays of tp_plan_ndof-order block count (groups
+ * in order, blocks in order), may be null.  summary: optional host struct,
+ * filled after one synchronisation of the stream (only when non-null).
+ * Returns TP_ERR_NOT_CONVERGED when summary is requested and some block
+ * failed; TP_ERR_NONFINITE when a residual became NaN/Inf. */
+tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner,
+                   double rtol, int32_t maxit, int32_t* iters, double* relres,
+                   tp_solve_summary* summary, hipStream_t stream);
+
+/* Layout helpers: convert between the canonical order (groups in order, each
+ * group's blocks contiguous as [nblocks][n^3]) and the plan's blocked layout.
+ * Pure data movement of elements of the given dtype; the canonical buffer has
+ * tp_plan_ndof() elements.  Padding lanes of the blocked buffer are written
+ * as zero by tp_pack. */
+tp_status tp_pack(tp_plan* plan, const void* canonical, void* blocked, tp_dtype dtype,
+                  hipStream_t stream);
+tp_status tp_unpack(tp_plan* plan, const void* blocked, void* canonical, tp_dtype dtype,
+                    hipStream_t stream);
+
+/* Number of blocks in the plan (sum over groups). */
+int64_t tp_plan_nblocks(const tp_plan* plan);
+
+/* Host-side reference data (no GPU needed), for inspection and tests:
+ * M_hat, K_hat and A_hat of the n-point GLL basis (row-major n x n host
+ * arrays, any may be null), with penalty constant C. */
+tp_status tp_reference_matrices(int32_t n, double penalty_C, double* M, double* K,
+                                double* A);
+
+/* Host-side generalized eigen-decomposition P_hat S = M_hat S diag(lam) with
+ * S^T M_hat S = I, eigenvalues ascending, each column's largest-magnitude
+ * entry positive.  S: row-major n x n host array (column j = eigenvector j),
+ * lam: n host doubles. */
+tp_status tp_reference_eigen(int32_t n, double penalty_C, tp_operator op, double* S,
+                             double* lam);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* tp_last_error(void);
+
+/* Library version string. */
+const char* tp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPFDM_H */

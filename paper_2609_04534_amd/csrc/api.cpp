@@ -1,0 +1,336 @@
+// C-ABI entry points of libtpfdm: argument checking, plan ownership and
+// dispatch to the kernel launchers.  See include/tpfdm.h for the contract.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace tpfdm {
+
+namespace {
+thread_local std::string g_last_error;
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+int esize_of(tp_dtype dt) {
+    switch (dt) {
+        case TP_F64: return 8;
+        case TP_F32: return 4;
+        case TP_F16: return 2;
+        case TP_BF16: return 2;
+    }
+    return 0;
+}
+bool valid_dtype(int dt) { return dt >= TP_F64 && dt <= TP_BF16; }
+bool valid_op(int op) { return op == TP_OP_NEUMANN || op == TP_OP_CELL; }
+}  // namespace
+
+tp_status set_error(tp_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+tp_status hip_error(int err, const char* what) {
+    const char* s = hipGetErrorString(static_cast<hipError_t>(err));
+    return set_error(TP_ERR_HIP, std::string(what) + ": " + (s ? s : "unknown HIP error"));
+}
+
+static void free_plan_memory(Plan* p) {
+    for (auto& g : p->groups)
+        if (g.h) (void)hipFree(g.h), g.h = nullptr;
+    if (p->summary_dev) (void)hipFree(p->summary_dev), p->summary_dev = nullptr;
+    if (p->groups_dev) (void)hipFree(p->groups_dev), p->groups_dev = nullptr;
+    if (p->items_dev) (void)hipFree(p->items_dev), p->items_dev = nullptr;
+}
+
+static tp_status alloc_dev(void** ptr, size_t bytes, const char* what) {
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return set_error(TP_ERR_OOM, std::string("out of device memory: ") + what);
+    }
+    if (e != hipSuccess) return hip_error(e, what);
+    return TP_OK;
+}
+
+}  // namespace tpfdm
+
+using namespace tpfdm;
+
+struct tp_plan : public Plan {};
+
+extern "C" {
+
+const char* tp_last_error(void) { return g_last_error.c_str(); }
+
+const char* tp_version(void) { return "tpfdm 0.1 (gfx950)"; }
+
+void tp_plan_opts_default(tp_plan_opts* opts) {
+    if (!opts) return;
+    std::memset(opts, 0, sizeof(*opts));
+    opts->penalty_C = 2.0;
+    opts->persistent = 0;
+}
+
+tp_status tp_reference_matrices(int32_t n, double penalty_C, double* M, double* K, double* A) {
+    if (n < kMinN || n > kMaxN) return set_error(TP_ERR_UNSUPPORTED, "n must be in [2, 8]");
+    if (!(penalty_C > 0.0) || !std::isfinite(penalty_C))
+        return set_error(TP_ERR_ARG, "penalty_C must be finite and > 0");
+    reference_matrices(n, penalty_C, M, K, A);
+    return TP_OK;
+}
+
+tp_status tp_reference_eigen(int32_t n, double penalty_C, tp_operator op, double* S, double* lam) {
+    if (n < kMinN || n > kMaxN) return set_error(TP_ERR_UNSUPPORTED, "n must be in [2, 8]");
+    if (!valid_op(op)) return set_error(TP_ERR_ARG, "invalid operator");
+    if (!S || !lam) return set_error(TP_ERR_ARG, "S and lam must be non-null");
+    if (!(penalty_C > 0.0) || !std::isfinite(penalty_C))
+        return set_error(TP_ERR_ARG, "penalty_C must be finite and > 0");
+    double M[kMaxN * kMaxN], K[kMaxN * kMaxN], A[kMaxN * kMaxN];
+    reference_matrices(n, penalty_C, M, K, A);
+    if (gen_eigen(n, M, op == TP_OP_CELL ? A : K, S, lam) != 0)
+        return set_error(TP_ERR_NOT_SPD, "reference mass matrix is not SPD");
+    return TP_OK;
+}
+
+tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opts* opts, tp_plan** out) {
+    if (!out) return set_error(TP_ERR_ARG, "out must be non-null");
+    *out = nullptr;
+    if (ngroups < 0 || (ngroups > 0 && !groups)) return set_error(TP_ERR_ARG, "invalid group array");
+    tp_plan_opts o;
+    tp_plan_opts_default(&o);
+    if (opts) o = *opts;
+    if (!(o.penalty_C > 0.0) || !std::isfinite(o.penalty_C))
+        return set_error(TP_ERR_ARG, "penalty_C must be finite and > 0");
+    for (int i = 0; i < 7; ++i)
+        if (o.reserved[i] != 0) return set_error(TP_ERR_ARG, "reserved option fields must be zero");
+
+    // validate groups and their element ranges
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    for (int gi = 0; gi < ngroups; ++gi) {
+        const tp_group& g = groups[gi];
+        if (g.n < kMinN || g.n > kMaxN)
+            return set_error(TP_ERR_UNSUPPORTED, "group " + std::to_string(gi) + ": n must be in [2, 8]");
+        if (!is_pow2(g.layout_B) || g.layout_B > 1024)
+            return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": layout_B must be a power of two <= 1024");
+        if (g.nblocks < 0 || g.nblocks > (int64_t(1) << 31) - 1)
+            return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": nblocks out of range");
+        if (g.offset < 0) return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": negative offset");
+        if (g.nblocks > 0 && !g.h) return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": h is null");
+        const int64_t n3 = int64_t(g.n) * g.n * g.n;
+        const int64_t tiles = (g.nblocks + g.layout_B - 1) / g.layout_B;
+        const int64_t elems = tiles * n3 * g.layout_B;
+        if (elems > 0) ranges.push_back({g.offset, g.offset + elems});
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (size_t i = 1; i < ranges.size(); ++i)
+        if (ranges[i].first < ranges[i - 1].second)
+            return set_error(TP_ERR_ARG, "group element ranges overlap");
+
+    tp_plan* p = new (std::nothrow) tp_plan();
+    if (!p) return set_error(TP_ERR_OOM, "host allocation failed");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_error(e, "hipGetDevice");
+    }
+    p->penalty_C = o.penalty_C;
+    p->persistent = o.persistent != 0;
+    int64_t canon = 0, block0 = 0;
+    std::vector<double> hbuf;
+    for (int gi = 0; gi < ngroups; ++gi) {
+        const tp_group& g = groups[gi];
+        GroupInfo info;
+        info.n = g.n;
+        info.logB = ilog2(g.layout_B);
+        info.nblocks = g.nblocks;
+        info.offset = g.offset;
+        info.canon = canon;
+        info.block0 = block0;
+        info.h = nullptr;
+        const int64_t n3 = int64_t(g.n) * g.n * g.n;
+        canon += g.nblocks * n3;
+        block0 += g.nblocks;
+        const int64_t tiles = (g.nblocks + g.layout_B - 1) / g.layout_B;
+        p->vec_elems = std::max(p->vec_elems, g.offset + tiles * n3 * g.layout_B);
+        p->groups.push_back(info);
+        if (g.nblocks == 0) continue;
+        // stage h on the host to validate it, then copy to plan-owned memory
+        hbuf.resize(static_cast<size_t>(g.nblocks) * 3);
+        e = hipMemcpy(hbuf.data(), g.h, hbuf.size() * sizeof(double), hipMemcpyDefault);
+        if (e != hipSuccess) {
+            free_plan_memory(p);
+            delete p;
+            return hip_error(e, "copy of h");
+        }
+        for (size_t i = 0; i < hbuf.size(); ++i)
+            if (!(hbuf[i] > 0.0) || !std::isfinite(hbuf[i])) {
+                free_plan_memory(p);
+                delete p;
+                return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": h must be finite and > 0 (block " +
+                                                 std::to_string(i / 3) + ")");
+            }
+        tp_status st = alloc_dev(reinterpret_cast<void**>(&p->groups.back().h), hbuf.size() * sizeof(double), "h");
+        if (st != TP_OK) {
+            free_plan_memory(p);
+            delete p;
+            return st;
+        }
+        e = hipMemcpy(p->groups.back().h, hbuf.data(), hbuf.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_plan_memory(p);
+            delete p;
+            return hip_error(e, "copy of h");
+        }
+    }
+    p->ndof = canon;
+    p->nblocks = block0;
+    for (auto& g : p->groups) {
+        RefData& r = p->ref[g.n];
+        if (!r.built) {
+            reference_matrices(g.n, p->penalty_C, r.M, r.K, r.A);
+            r.built = true;
+        }
+    }
+    tp_status st = alloc_dev(&p->summary_dev, sizeof(SolveSummary), "solve summary");
+    if (st != TP_OK) {
+        free_plan_memory(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return TP_OK;
+}
+
+tp_status tp_plan_destroy(tp_plan* plan) {
+    if (!plan) return TP_OK;
+    free_plan_memory(plan);
+    delete plan;
+    return TP_OK;
+}
+
+int64_t tp_plan_vector_elems(const tp_plan* plan) { return plan ? plan->vec_elems : -1; }
+int64_t tp_plan_ndof(const tp_plan* plan) { return plan ? plan->ndof : -1; }
+int64_t tp_plan_nblocks(const tp_plan* plan) { return plan ? plan->nblocks : -1; }
+
+tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dtype dtype, hipStream_t stream) {
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (!valid_op(op)) return set_error(TP_ERR_ARG, "invalid operator");
+    if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
+    if (plan->vec_elems > 0 && (!u || !v)) return set_error(TP_ERR_ARG, "u and v must be non-null");
+    if (u == v && u) return set_error(TP_ERR_ARG, "u and v must not alias");
+    for (const auto& g : plan->groups) {
+        const RefData& r = plan->ref[g.n];
+        tp_status st = launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream);
+        if (st != TP_OK) return st;
+    }
+    return TP_OK;
+}
+
+tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, double singular_tol) {
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (!valid_op(op)) return set_error(TP_ERR_ARG, "invalid operator");
+    if (mode != TP_FACTOR_SCALED) return set_error(TP_ERR_UNSUPPORTED, "only TP_FACTOR_SCALED is supported");
+    if (!(singular_tol > 0.0)) singular_tol = 1e-12;
+    plan->inverse_op = -1;
+    for (int n = kMinN; n <= kMaxN; ++n) {
+        RefData& r = plan->ref[n];
+        r.eig_ready = false;
+        if (!r.built) continue;
+        if (gen_eigen(n, r.M, op == TP_OP_CELL ? r.A : r.K, r.S, r.lam) != 0)
+            return set_error(TP_ERR_NOT_SPD, "reference mass matrix of n=" + std::to_string(n) + " is not SPD");
+        // eigenvalue sums lam_i s_x + lam_j s_y + lam_k s_z of any block are
+        // bounded below by lam_min (s_x + s_y + s_z) and above by lam_max (...)
+        if (!(r.lam[0] > singular_tol * r.lam[n - 1]))
+            return set_error(TP_ERR_SINGULAR, "operator of n=" + std::to_string(n) +
+                                                  " is singular: lambda_min/lambda_max = " +
+                                                  std::to_string(r.lam[0] / r.lam[n - 1]));
+        r.eig_ready = true;
+    }
+    plan->inverse_op = op;
+    return TP_OK;
+}
+
+tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype, hipStream_t stream) {
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
+    if (plan->inverse_op < 0) return set_error(TP_ERR_STATE, "tp_setup_inverse has not succeeded on this plan");
+    if (plan->vec_elems > 0 && (!r || !x)) return set_error(TP_ERR_ARG, "r and x must be non-null");
+    if (r == x && r) return set_error(TP_ERR_ARG, "r and x must not alias");
+    for (const auto& g : plan->groups) {
+        tp_status st = launch_inverse(*plan, g, r, x, dtype, stream);
+        if (st != TP_OK) return st;
+    }
+    return TP_OK;
+}
+
+tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, double rtol, int32_t maxit,
+                   int32_t* iters, double* relres, tp_solve_summary* summary, hipStream_t stream) {
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (plan->inverse_op != TP_OP_CELL)
+        return set_error(TP_ERR_STATE, "tp_solve needs tp_setup_inverse(TP_OP_CELL) first");
+    if (inner != TP_F64 && inner != TP_F32)
+        return set_error(TP_ERR_UNSUPPORTED, "solve inner precision must be TP_F64 or TP_F32");
+    if (!(rtol >= 0.0) || !std::isfinite(rtol)) return set_error(TP_ERR_ARG, "rtol must be finite and >= 0");
+    if (maxit < 0) return set_error(TP_ERR_ARG, "maxit must be >= 0");
+    if (plan->vec_elems > 0 && (!b || !x)) return set_error(TP_ERR_ARG, "b and x must be non-null");
+    if (static_cast<const void*>(b) == static_cast<const void*>(x) && b)
+        return set_error(TP_ERR_ARG, "b and x must not alias");
+    tp_status st = launch_summary_reset(plan->summary_dev, stream);
+    if (st != TP_OK) return st;
+    for (const auto& g : plan->groups) {
+        st = launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, stream);
+        if (st != TP_OK) return st;
+    }
+    if (summary) {
+        SolveSummary hs;
+        hipError_t e = hipMemcpyAsync(&hs, plan->summary_dev, sizeof(hs), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_error(e, "solve summary readback");
+        summary->max_iters = hs.max_iters;
+        summary->n_failed = hs.n_failed;
+        double mr;
+        std::memcpy(&mr, &hs.max_relres_bits, sizeof(mr));
+        summary->max_relres = mr;
+        if (hs.nonfinite > 0)
+            return set_error(TP_ERR_NONFINITE, std::to_string(hs.nonfinite) + " blocks had a non-finite residual");
+        if (hs.n_failed > 0)
+            return set_error(TP_ERR_NOT_CONVERGED, std::to_string(hs.n_failed) + " blocks missed rtol");
+    }
+    return TP_OK;
+}
+
+tp_status tp_pack(tp_plan* plan, const void* canonical, void* blocked, tp_dtype dtype, hipStream_t stream) {
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
+    if (plan->vec_elems > 0 && (!canonical || !blocked)) return set_error(TP_ERR_ARG, "null buffer");
+    for (const auto& g : plan->groups) {
+        tp_status st = launch_pack(g, canonical, blocked, esize_of(dtype), true, stream);
+        if (st != TP_OK) return st;
+    }
+    return TP_OK;
+}
+
+tp_status tp_unpack(tp_plan* plan, const void* blocked, void* canonical, tp_dtype dtype, hipStream_t stream) {
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
+    if (plan->vec_elems > 0 && (!canonical || !blocked)) return set_error(TP_ERR_ARG, "null buffer");
+    for (const auto& g : plan->groups) {
+        tp_status st = launch_pack(g, blocked, canonical, esize_of(dtype), false, stream);
+        if (st != TP_OK) return st;
+    }
+    return TP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tpfdm.h"
+
+namespace tpfdm {
+
+constexpr int kMinN = 2;
+constexpr int kMaxN = 8;
+// degrees n <= kLaneMaxN run one block per lane; larger n one block per wave
+constexpr int kLaneMaxN = 4;  // apply / apply_inverse only
+
+// ---------------------------------------------------------------- refdata
+void gll_points(int n, double* x);
+void gauss_points(int nq, double* x, double* w);
+void reference_matrices(int n, double C, double* M, double* K, double* A);
+int gen_eigen(int n, const double* M, const double* P, double* S, double* lam);
+
+// ---------------------------------------------------------------- plan data
+struct RefData {
+    bool built = false;
+    double M[kMaxN * kMaxN];
+    double K[kMaxN * kMaxN];
+    double A[kMaxN * kMaxN];
+    // fast-diagonalization factors of the operator chosen at setup
+    bool eig_ready = false;
+    double S[kMaxN * kMaxN];
+    double lam[kMaxN];
+};
+
+struct GroupInfo {
+    int n;
+    int logB;
+    int64_t nblocks;
+    int64_t offset;       // element offset of the group in blocked vectors
+    int64_t canon;        // element offset in canonical order
+    int64_t block0;       // first global block index of the group
+    double* h;            // plan-owned device copy, [nblocks][3]
+};
+
+// One work item of the persistent kernel: a tile of lane-mapped blocks or a
+// single wave-mapped block.
+struct WorkItem {
+    int32_t group;
+    int32_t count;        // blocks in this item
+    int64_t first;        // first block index within the group
+};
+
+struct Plan {
+    int device = 0;
+    double penalty_C = 2.0;
+    bool persistent = false;
+    std::vector<GroupInfo> groups;
+    RefData ref[kMaxN + 1];
+    int inverse_op = -1;
+    int64_t vec_elems = 0;
+    int64_t ndof = 0;
+    int64_t nblocks = 0;
+    // device workspace
+    void* summary_dev = nullptr;   // solve summary counters
+    GroupInfo* groups_dev = nullptr;
+    WorkItem* items_dev = nullptr;
+    int64_t nitems = 0;
+};
+
+// Device-side solve summary, reset by a fill kernel before every solve.
+struct SolveSummary {
+    int max_iters;
+    int n_failed;
+    int nonfinite;
+    int pad;
+    unsigned long long max_relres_bits;
+};
+
+// thread-local last error
+tp_status set_error(tp_status st, const std::string& msg);
+tp_status hip_error(int err, const char* what);
+
+// ---------------------------------------------------------------- launchers
+// All return TP_OK or TP_ERR_HIP/TP_ERR_UNSUPPORTED.
+tp_status launch_apply(const Plan& plan, const GroupInfo& g, const double* Pm, const void* u,
+                       void* v, tp_dtype dt, hipStream_t s);
+tp_status launch_inverse(const Plan& plan, const GroupInfo& g, const void* r, void* x,
+                         tp_dtype dt, hipStream_t s);
+tp_status launch_solve(const Plan& plan, const GroupInfo& g, const double* b, double* x,
+                       tp_dtype inner, double rtol, int maxit, int32_t* iters,
+                       double* relres, hipStream_t s);
+// to_blocked: src canonical -> dst blocked; otherwise src blocked -> dst canonical
+tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize,
+                      bool to_blocked, hipStream_t s);
+tp_status launch_summary_reset(void* summary_dev, hipStream_t s);
+
+}  // namespace tpfdm

@@ -1,0 +1,248 @@
+// Host-side 1D reference data of the method, in FP64.
+//
+// * Gauss-Lobatto points of [0,1] and the Lagrange basis on them.
+// * Exact mass matrix M_hat (Gauss-Legendre quadrature with n+1 points, exact
+//   for the degree-2p integrand) and stiffness K_hat = D^T M_hat D, where D is
+//   the nodal differentiation matrix (l_j' is interpolated exactly by its
+//   nodal values).  Sec. 3.1, eq. (eval_pipeline) needs only these two.
+// * A_hat = K_hat + own-side SIPG face blocks of both faces, eq. (face_coupling)
+//   and eq. (cell_block), penalty sigma_hat = C p (p+1) (Sec. 6.2).
+// * Generalized symmetric eigen-decomposition P_hat S = M_hat S Lambda by
+//   Cholesky reduction and cyclic Jacobi rotations (Golub & Van Loan,
+//   "Matrix Computations", Sec. 8.5), giving the fast-diagonalization factors
+//   of Sec. 5.2.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace tpfdm {
+
+namespace {
+
+// Legendre P_k(x) and P_k'(x) by the three-term recurrence.
+void legendre(int k, double x, double* P, double* dP) {
+    double p0 = 1.0, p1 = x;
+    if (k == 0) { *P = 1.0; *dP = 0.0; return; }
+    for (int m = 1; m < k; ++m) {
+        double p2 = ((2 * m + 1) * x * p1 - m * p0) / (m + 1);
+        p0 = p1;
+        p1 = p2;
+    }
+    *P = p1;
+    // (1 - x^2) P_k' = k (P_{k-1} - x P_k)
+    *dP = k * (p0 - x * p1) / (1.0 - x * x);
+}
+
+}  // namespace
+
+// n Gauss-Lobatto points on [0,1]: the endpoints and the roots of P_{n-1}'
+// found by Newton's method from Chebyshev-Gauss-Lobatto guesses.
+void gll_points(int n, double* x) {
+    const int p = n - 1;
+    x[0] = 0.0;
+    x[p] = 1.0;
+    for (int k = 1; k < p; ++k) {
+        double xi = -std::cos(M_PI * k / p);
+        for (int it = 0; it < 100; ++it) {
+            double P, dP;
+            legendre(p, xi, &P, &dP);
+            // Legendre ODE: (1 - x^2) P'' = 2 x P' - p(p+1) P
+            double d2P = (2.0 * xi * dP - p * (p + 1) * P) / (1.0 - xi * xi);
+            double step = dP / d2P;
+            xi -= step;
+            if (std::fabs(step) < 1e-17) break;
+        }
+        x[k] = 0.5 * (1.0 + xi);
+    }
+}
+
+// nq Gauss-Legendre points and weights on [0,1] (Newton on P_nq).
+void gauss_points(int nq, double* x, double* w) {
+    for (int k = 0; k < nq; ++k) {
+        double xi = -std::cos(M_PI * (k + 0.75) / (nq + 0.5));
+        double P = 0, dP = 1;
+        for (int it = 0; it < 100; ++it) {
+            legendre(nq, xi, &P, &dP);
+            double step = P / dP;
+            xi -= step;
+            if (std::fabs(step) < 1e-17) break;
+        }
+        legendre(nq, xi, &P, &dP);
+        x[k] = 0.5 * (1.0 + xi);
+        w[k] = 1.0 / ((1.0 - xi * xi) * dP * dP);  // 2/((1-xi^2)P'^2), halved for [0,1]
+    }
+}
+
+void reference_matrices(int n, double C, double* M, double* K, double* A) {
+    std::vector<double> x(n), bw(n), D(n * n), Mm(n * n, 0.0), Km(n * n, 0.0);
+    gll_points(n, x.data());
+    for (int j = 0; j < n; ++j) {
+        double prod = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != j) prod *= (x[j] - x[k]);
+        bw[j] = 1.0 / prod;  // barycentric weights
+    }
+    // differentiation matrix D[i][j] = l_j'(x_i)
+    for (int i = 0; i < n; ++i) {
+        double diag = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            D[i * n + j] = (bw[j] / bw[i]) / (x[i] - x[j]);
+            diag -= D[i * n + j];
+        }
+        D[i * n + i] = diag;
+    }
+    // mass matrix by Gauss-Legendre quadrature, Lagrange values by the
+    // second (true) barycentric formula
+    const int nq = n + 1;
+    std::vector<double> xq(nq), wq(nq), L(n);
+    gauss_points(nq, xq.data(), wq.data());
+    for (int q = 0; q < nq; ++q) {
+        int hit = -1;
+        for (int j = 0; j < n; ++j)
+            if (xq[q] == x[j]) hit = j;
+        if (hit >= 0) {
+            for (int j = 0; j < n; ++j) L[j] = (j == hit) ? 1.0 : 0.0;
+        } else {
+            double den = 0.0;
+            for (int j = 0; j < n; ++j) den += bw[j] / (xq[q] - x[j]);
+            for (int j = 0; j < n; ++j) L[j] = (bw[j] / (xq[q] - x[j])) / den;
+        }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) Mm[i * n + j] += wq[q] * L[i] * L[j];
+    }
+    // K = D^T M D
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) s += D[i * n + a] * Mm[i * n + j] * D[j * n + b];
+            Km[a * n + b] = s;
+        }
+    // symmetrize against rounding
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < a; ++b) {
+            double m = 0.5 * (Mm[a * n + b] + Mm[b * n + a]);
+            Mm[a * n + b] = Mm[b * n + a] = m;
+            double k = 0.5 * (Km[a * n + b] + Km[b * n + a]);
+            Km[a * n + b] = Km[b * n + a] = k;
+        }
+    if (M) std::copy(Mm.begin(), Mm.end(), M);
+    if (K) std::copy(Km.begin(), Km.end(), K);
+    if (A) {
+        // own-side face blocks: right face (cell is K^-, endpoint 1) and left
+        // face (cell is K^+, endpoint 0); value vectors are unit vectors for
+        // the GLL basis, derivative vectors are rows of D.
+        const double sigma = C * (n - 1) * n;
+        std::copy(Km.begin(), Km.end(), A);
+        const int r = n - 1;
+        A[r * n + r] += sigma;
+        A[0] += sigma;
+        for (int j = 0; j < n; ++j) {
+            const double g1 = D[r * n + j], g0 = D[0 * n + j];
+            A[r * n + j] -= 0.5 * g1;
+            A[j * n + r] -= 0.5 * g1;
+            A[0 * n + j] += 0.5 * g0;
+            A[j * n + 0] += 0.5 * g0;
+        }
+    }
+}
+
+// Generalized symmetric-definite eigenproblem P S = M S diag(lam).
+// Returns 0 on success, -1 when M is not SPD.
+int gen_eigen(int n, const double* M, const double* P, double* S, double* lam) {
+    std::vector<double> L(n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double d = M[j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+        if (!(d > 0.0)) return -1;
+        L[j * n + j] = std::sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double s = M[i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = s / L[j * n + j];
+        }
+    }
+    // Y = L^{-1} P  (forward substitution on each column)
+    std::vector<double> Y(n * n), Cm(n * n);
+    for (int c = 0; c < n; ++c)
+        for (int i = 0; i < n; ++i) {
+            double s = P[i * n + c];
+            for (int k = 0; k < i; ++k) s -= L[i * n + k] * Y[k * n + c];
+            Y[i * n + c] = s / L[i * n + i];
+        }
+    // C = L^{-1} Y^T  (= L^{-1} P L^{-T}, symmetric)
+    for (int c = 0; c < n; ++c)
+        for (int i = 0; i < n; ++i) {
+            double s = Y[c * n + i];
+            for (int k = 0; k < i; ++k) s -= L[i * n + k] * Cm[k * n + c];
+            Cm[i * n + c] = s / L[i * n + i];
+        }
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < a; ++b) {
+            double m = 0.5 * (Cm[a * n + b] + Cm[b * n + a]);
+            Cm[a * n + b] = Cm[b * n + a] = m;
+        }
+    // cyclic Jacobi
+    std::vector<double> V(n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += Cm[i * n + j] * Cm[i * n + j];
+                if (i != j) off += Cm[i * n + j] * Cm[i * n + j];
+            }
+        if (off <= 1e-32 * tot) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = Cm[p * n + q];
+                if (apq == 0.0) continue;
+                const double tau = (Cm[q * n + q] - Cm[p * n + p]) / (2.0 * apq);
+                const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < n; ++k) {  // C <- C J (columns p, q)
+                    const double ckp = Cm[k * n + p], ckq = Cm[k * n + q];
+                    Cm[k * n + p] = c * ckp - s * ckq;
+                    Cm[k * n + q] = s * ckp + c * ckq;
+                }
+                for (int k = 0; k < n; ++k) {  // C <- J^T C (rows p, q)
+                    const double cpk = Cm[p * n + k], cqk = Cm[q * n + k];
+                    Cm[p * n + k] = c * cpk - s * cqk;
+                    Cm[q * n + k] = s * cpk + c * cqk;
+                }
+                for (int k = 0; k < n; ++k) {  // V <- V J
+                    const double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - s * vkq;
+                    V[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    // S = L^{-T} V (back substitution on each column)
+    std::vector<double> Sm(n * n);
+    for (int c = 0; c < n; ++c)
+        for (int i = n - 1; i >= 0; --i) {
+            double s = V[i * n + c];
+            for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * Sm[k * n + c];
+            Sm[i * n + c] = s / L[i * n + i];
+        }
+    // sort ascending, fix signs
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(),
+              [&](int a, int b) { return Cm[a * n + a] < Cm[b * n + b]; });
+    for (int jj = 0; jj < n; ++jj) {
+        const int j = order[jj];
+        lam[jj] = Cm[j * n + j];
+        int imax = 0;
+        for (int i = 1; i < n; ++i)
+            if (std::fabs(Sm[i * n + j]) > std::fabs(Sm[imax * n + j])) imax = i;
+        const double sg = Sm[imax * n + j] < 0 ? -1.0 : 1.0;
+        for (int i = 0; i < n; ++i) S[i * n + jj] = sg * Sm[i * n + j];
+    }
+    return 0;
+}
+
+}  // namespace tpfdm

@@ -1,0 +1,279 @@
+"""Thin ctypes binding of libtpfdm (include/tpfdm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the shared library.  Torch tensors supply device memory and
+streams.  There is no fallback: when the library is missing or fails to load
+every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpfdm.so")
+
+TP_OK = 0
+STATUS = {
+    0: "TP_OK", -1: "TP_ERR_ARG", -2: "TP_ERR_UNSUPPORTED", -3: "TP_ERR_NOT_SPD",
+    -4: "TP_ERR_SINGULAR", -5: "TP_ERR_NOT_CONVERGED", -6: "TP_ERR_NONFINITE",
+    -7: "TP_ERR_HIP", -8: "TP_ERR_OOM", -9: "TP_ERR_STATE",
+}
+F64, F32, F16, BF16 = 0, 1, 2, 3
+DTYPE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
+OP_NEUMANN, OP_CELL = 0, 1
+FACTOR_SCALED = 0
+
+# The public symbol set declared in include/tpfdm.h.
+EXPORTS = (
+    "tp_plan_opts_default", "tp_plan_create", "tp_plan_destroy", "tp_plan_vector_elems",
+    "tp_plan_ndof", "tp_plan_nblocks", "tp_apply", "tp_setup_inverse", "tp_apply_inverse",
+    "tp_solve", "tp_pack", "tp_unpack", "tp_reference_matrices", "tp_reference_eigen",
+    "tp_last_error", "tp_version",
+)
+
+
+class TpfdmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class _Group(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("layout_B", ctypes.c_int32), ("nblocks", ctypes.c_int64),
+                ("h", ctypes.c_void_p), ("offset", ctypes.c_int64)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("penalty_C", ctypes.c_double), ("persistent", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class _Summary(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int32), ("n_failed", ctypes.c_int32),
+                ("max_relres", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libtpfdm.so (built in-tree by paper_2609_04534_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libtpfdm.so not found at {path}; run `python -m paper_2609_04534_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "tp_plan_opts_default": (None, [ctypes.POINTER(_Opts)]),
+        "tp_plan_create": (i32, [ctypes.POINTER(_Group), i32, ctypes.POINTER(_Opts), ctypes.POINTER(vp)]),
+        "tp_plan_destroy": (i32, [vp]),
+        "tp_plan_vector_elems": (i64, [vp]),
+        "tp_plan_ndof": (i64, [vp]),
+        "tp_plan_nblocks": (i64, [vp]),
+        "tp_apply": (i32, [vp, i32, vp, vp, i32, vp]),
+        "tp_setup_inverse": (i32, [vp, i32, i32, dbl]),
+        "tp_apply_inverse": (i32, [vp, vp, vp, i32, vp]),
+        "tp_solve": (i32, [vp, vp, vp, i32, dbl, i32, vp, vp, ctypes.POINTER(_Summary), vp]),
+        "tp_pack": (i32, [vp, vp, vp, i32, vp]),
+        "tp_unpack": (i32, [vp, vp, vp, i32, vp]),
+        "tp_reference_matrices": (i32, [i32, dbl, vp, vp, vp]),
+        "tp_reference_eigen": (i32, [i32, dbl, i32, vp, vp]),
+        "tp_last_error": (ctypes.c_char_p, []),
+        "tp_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != TP_OK:
+        msg = load().tp_last_error().decode(errors="replace")
+        raise TpfdmError(status, msg)
+
+
+def version() -> str:
+    return load().tp_version().decode()
+
+
+def reference_matrices(n: int, penalty_C: float = 2.0):
+    """(M_hat, K_hat, A_hat) of the n-point GLL basis, computed by the library's host code."""
+    M = np.zeros((n, n))
+    K = np.zeros((n, n))
+    A = np.zeros((n, n))
+    _check(load().tp_reference_matrices(n, penalty_C, M.ctypes.data, K.ctypes.data, A.ctypes.data))
+    return M, K, A
+
+
+def reference_eigen(n: int, penalty_C: float = 2.0, op: int = OP_CELL):
+    """(S_hat, lam_hat) with P_hat S = M_hat S diag(lam), S^T M_hat S = I."""
+    S = np.zeros((n, n))
+    lam = np.zeros(n)
+    _check(load().tp_reference_eigen(n, penalty_C, op, S.ctypes.data, lam.ctypes.data))
+    return S, lam
+
+
+def torch_dtype_code(t) -> int:
+    import torch
+    m = {torch.float64: F64, torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class GroupSpec:
+    """One group: n points per direction, interleave width B, edge lengths h (nblocks, 3)."""
+    n: int
+    layout_B: int
+    h: object            # numpy (host) or torch tensor (host or device), float64 [nblocks, 3]
+    offset: int = -1     # element offset; -1 = place after the previous group
+
+    @property
+    def nblocks(self) -> int:
+        return int(self.h.shape[0])
+
+    def elems(self) -> int:
+        t = (self.nblocks + self.layout_B - 1) // self.layout_B
+        return t * self.n ** 3 * self.layout_B
+
+
+def default_layout_B(n: int) -> int:
+    """Interleave width used by default: 64 (one wave of lanes) for the
+    lane-per-block kernels (n <= 4), 1 (block-contiguous) otherwise."""
+    return 64 if n <= 4 else 1
+
+
+class Plan:
+    """Owning wrapper of a tp_plan."""
+
+    def __init__(self, groups, penalty_C: float = 2.0, persistent: bool = False):
+        lib = load()
+        self._keep = []
+        arr = (_Group * max(1, len(groups)))()
+        off = 0
+        self.groups = []
+        for i, g in enumerate(groups):
+            h = g.h
+            if isinstance(h, np.ndarray):
+                h = np.ascontiguousarray(h, dtype=np.float64)
+                ptr = h.ctypes.data
+            else:  # torch tensor, host or device
+                import torch
+                h = h.to(torch.float64).contiguous()
+                ptr = h.data_ptr()
+            self._keep.append(h)
+            o = off if g.offset < 0 else g.offset
+            arr[i].n = g.n
+            arr[i].layout_B = g.layout_B
+            arr[i].nblocks = g.nblocks
+            arr[i].h = ptr
+            arr[i].offset = o
+            off = o + g.elems()
+            self.groups.append(GroupSpec(g.n, g.layout_B, g.h, o))
+        opts = _Opts()
+        lib.tp_plan_opts_default(ctypes.byref(opts))
+        opts.penalty_C = penalty_C
+        opts.persistent = 1 if persistent else 0
+        handle = ctypes.c_void_p()
+        _check(lib.tp_plan_create(arr, len(groups), ctypes.byref(opts), ctypes.byref(handle)))
+        self._h = handle
+        self._keep = []
+
+    # ---------------------------------------------------------------- sizes
+    @property
+    def handle(self):
+        if self._h is None:
+            raise TpfdmError(-9, "plan destroyed")
+        return self._h
+
+    @property
+    def vector_elems(self) -> int:
+        return int(load().tp_plan_vector_elems(self.handle))
+
+    @property
+    def ndof(self) -> int:
+        return int(load().tp_plan_ndof(self.handle))
+
+    @property
+    def nblocks(self) -> int:
+        return int(load().tp_plan_nblocks(self.handle))
+
+    # ---------------------------------------------------------------- ops
+    def apply(self, u, v, op: int = OP_NEUMANN, stream=None):
+        _check(load().tp_apply(self.handle, op, _ptr(u), _ptr(v), torch_dtype_code(u), _stream(stream)))
+
+    def setup_inverse(self, op: int = OP_CELL, singular_tol: float = 0.0):
+        _check(load().tp_setup_inverse(self.handle, op, FACTOR_SCALED, singular_tol))
+
+    def apply_inverse(self, r, x, stream=None):
+        _check(load().tp_apply_inverse(self.handle, _ptr(r), _ptr(x), torch_dtype_code(r), _stream(stream)))
+
+    def solve(self, b, x, inner: int = F32, rtol: float = 1e-10, maxit: int = 50, iters=None, relres=None,
+              summary: bool = True, stream=None, raise_on_failure: bool = True):
+        """Returns the summary dict (or None when summary=False)."""
+        s = _Summary()
+        st = load().tp_solve(self.handle, _ptr(b), _ptr(x), inner, rtol, maxit, _ptr(iters), _ptr(relres),
+                             ctypes.byref(s) if summary else None, _stream(stream))
+        if st != TP_OK and (raise_on_failure or st not in (-5, -6)):
+            _check(st)
+        if not summary:
+            return None
+        return {"status": STATUS[st], "max_iters": s.max_iters, "n_failed": s.n_failed,
+                "max_relres": s.max_relres}
+
+    def pack(self, canonical, blocked, stream=None):
+        _check(load().tp_pack(self.handle, _ptr(canonical), _ptr(blocked), torch_dtype_code(canonical),
+                              _stream(stream)))
+
+    def unpack(self, blocked, canonical, stream=None):
+        _check(load().tp_unpack(self.handle, _ptr(blocked), _ptr(canonical), torch_dtype_code(blocked),
+                                _stream(stream)))
+
+    def destroy(self):
+        if self._h is not None:
+            load().tp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+def groups_for_workload(workload, layout_B=None):
+    """GroupSpecs for a workloads.Workload (one group per degree, packed one
+    after another)."""
+    specs = []
+    for g in workload.groups:
+        B = layout_B(g.n) if callable(layout_B) else (layout_B or default_layout_B(g.n))
+        specs.append(GroupSpec(n=g.n, layout_B=B, h=g.h))
+    return specs
