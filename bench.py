@@ -111,6 +111,12 @@ def main():
     ap.add_argument("--rotate", type=int, default=4)
     ap.add_argument("--solve-calls", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--suite", action="store_true",
+                    help="time apply / apply_inverse / solve for every workload and precision "
+                         "(one JSON line per case) instead of the headline step")
+    ap.add_argument("--counters", action="store_true",
+                    help="no timing: launch apply, apply_inverse and a plain device copy of one "
+                         "vector 3 times each (for hardware-counter runs), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the blocks are independent and each GPU would run the "
@@ -125,6 +131,10 @@ def main():
     tpfdm.load()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+
+    if args.suite:
+        run_suite(args, stream)
+        return
 
     _log(f"workload {args.workload}")
     wl, dtname = build_workload(args.workload)
@@ -147,6 +157,21 @@ def main():
         X.append(torch.empty(E, dtype=tdt, device="cuda"))
     torch.cuda.synchronize()
     _log(f"ndof={ndof} vector_elems={E} sets={R}")
+
+    if args.counters:
+        # calibration: a plain copy of exactly one vector (vector_elems * esize bytes
+        # read and written), then the two kernels of the step
+        for k in range(3):
+            V[k % R].copy_(U[k % R])
+        for k in range(3):
+            plan.apply(U[k % R], V[k % R], tpfdm.OP_NEUMANN, stream=stream)
+        for k in range(3):
+            plan.apply_inverse(V[k % R], X[k % R], stream=stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": args.workload, "copy_bytes": E * esize,
+                          "algorithmic_bytes_per_launch": algorithmic_bytes(wl, esize)}), flush=True)
+        plan.destroy()
+        return
 
     def step(k):
         plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream)
@@ -234,6 +259,77 @@ def main():
         out["cpu_baseline"] = None
     plan.destroy()
     print(json.dumps(out), flush=True)
+
+
+SUITE = [
+    ("p2_8cube_h1/8", ["f64", "f32"]),
+    ("p2_128cube", ["f64", "f32"]),
+    ("p3_64cube_affine", ["f64", "f32", "f16", "bf16"]),
+    ("p7_32cube_aniso", ["f64", "f32", "f16", "bf16"]),
+    ("uneven_p237_20000", ["f64", "f32"]),
+]
+
+
+def run_suite(args, stream):
+    """Per workload and storage precision: apply and apply_inverse rates with
+    rotated buffers, and solve latency with FP64 and FP32 inner solves."""
+    import torch
+    from paper_2609_04534_amd import tpfdm
+    codes = {"f64": (tpfdm.F64, torch.float64, 8), "f32": (tpfdm.F32, torch.float32, 4),
+             "f16": (tpfdm.F16, torch.float16, 2), "bf16": (tpfdm.BF16, torch.bfloat16, 2)}
+    for name, dts in SUITE:
+        wl, _ = build_workload(name)
+        plan = tpfdm.Plan(tpfdm.groups_for_workload(wl))
+        plan.setup_inverse(tpfdm.OP_CELL)
+        E, ndof = plan.vector_elems, plan.ndof
+        cu = torch.from_numpy(np.concatenate([g.u.reshape(-1) for g in wl.groups])).cuda()
+        cb = torch.from_numpy(np.concatenate([g.b.reshape(-1) for g in wl.groups])).cuda()
+        for dtn in dts:
+            code, tdt, es = codes[dtn]
+            vec_bytes = E * es
+            R = max(1, min(args.rotate, int(6e9 // max(1, 3 * vec_bytes))))
+            if 3 * R * vec_bytes < 1.2e9:       # small cases: report the cache-resident rate
+                R = 1
+            U = [torch.empty(E, dtype=tdt, device="cuda") for _ in range(R)]
+            for u in U:
+                plan.pack(cu.to(tdt), u)
+            V = [torch.empty_like(U[0]) for _ in range(R)]
+            X = [torch.empty_like(U[0]) for _ in range(R)]
+            for k in range(3):
+                plan.apply(U[k % R], V[k % R], tpfdm.OP_NEUMANN, stream=stream)
+                plan.apply_inverse(V[k % R], X[k % R], stream=stream)
+            reps = max(args.steps, 20)
+            ms_a = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
+            ms_i = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
+            ab = algorithmic_bytes(wl, es)
+            rec = {"workload": name, "dtype": dtn, "ndof": ndof, "buffer_sets": R,
+                   "cache_resident": R == 1,
+                   "apply_ms": ms_a, "apply_GDoF/s": ndof / ms_a / 1e6, "apply_GB/s": ab / ms_a / 1e6,
+                   "apply_TFLOP/s": flops(wl, "apply") / ms_a / 1e9,
+                   "inverse_ms": ms_i, "inverse_GDoF/s": ndof / ms_i / 1e6, "inverse_GB/s": ab / ms_i / 1e6,
+                   "inverse_TFLOP/s": flops(wl, "inverse") / ms_i / 1e9}
+            del U, V, X
+            print(json.dumps(rec), flush=True)
+        bb = torch.empty(E, dtype=torch.float64, device="cuda")
+        plan.pack(cb, bb)
+        xs = torch.zeros_like(bb)
+        for inner in (tpfdm.F64, tpfdm.F32):
+            lat = []
+            summ = None
+            for i in range(max(10, args.solve_calls // 4) + 2):
+                xs.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                summ = plan.solve(bb, xs, inner=inner, rtol=1e-10, maxit=50, stream=stream)
+                t1 = time.perf_counter()
+                if i >= 2:
+                    lat.append((t1 - t0) * 1e3)
+            print(json.dumps({"workload": name, "solve_inner": tpfdm.DTYPE_NAMES[inner],
+                              "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                              "max_iters": summ["max_iters"], "max_relres": summ["max_relres"]}), flush=True)
+        plan.destroy()
+        del bb, xs, cu, cb
+        torch.cuda.empty_cache()
 
 
 def kernel_hash():

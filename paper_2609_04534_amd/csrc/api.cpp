@@ -50,6 +50,7 @@ static void free_plan_memory(Plan* p) {
         if (g.h) (void)hipFree(g.h), g.h = nullptr;
     if (p->summary_dev) (void)hipFree(p->summary_dev), p->summary_dev = nullptr;
     if (p->groups_dev) (void)hipFree(p->groups_dev), p->groups_dev = nullptr;
+    if (p->eo_dev) (void)hipFree(p->eo_dev), p->eo_dev = nullptr;
     if (p->items_dev) (void)hipFree(p->items_dev), p->items_dev = nullptr;
 }
 
@@ -61,6 +62,18 @@ static tp_status alloc_dev(void** ptr, size_t bytes, const char* what) {
         return set_error(TP_ERR_OOM, std::string("out of device memory: ") + what);
     }
     if (e != hipSuccess) return hip_error(e, what);
+    return TP_OK;
+}
+
+tp_status upload_eo(Plan& plan, int n, int tab, const double* vals, int count) {
+    if (count > kEOSlot) return set_error(TP_ERR_UNSUPPORTED, "even-odd table too large");
+    float f[kEOSlot];
+    for (int i = 0; i < count; ++i) f[i] = static_cast<float>(vals[i]);
+    hipError_t e = hipMemcpy(const_cast<void*>(eo_table(plan, n, tab, 0)), vals, count * sizeof(double),
+                             hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(const_cast<void*>(eo_table(plan, n, tab, 1)), f, count * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "upload of even-odd tables");
     return TP_OK;
 }
 
@@ -196,14 +209,34 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
     }
     p->ndof = canon;
     p->nblocks = block0;
-    for (auto& g : p->groups) {
-        RefData& r = p->ref[g.n];
-        if (!r.built) {
-            reference_matrices(g.n, p->penalty_C, r.M, r.K, r.A);
-            r.built = true;
-        }
-    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+        p->wave_grid = static_cast<int64_t>(cus) * 8;
     tp_status st = alloc_dev(&p->summary_dev, sizeof(SolveSummary), "solve summary");
+    if (st == TP_OK)
+        st = alloc_dev(&p->eo_dev, static_cast<size_t>(kMaxN + 1) * EO_NTAB * 2 * kEOSlot * sizeof(double),
+                       "even-odd tables");
+    for (auto& g : p->groups) {
+        if (st != TP_OK) break;
+        RefData& r = p->ref[g.n];
+        if (r.built) continue;
+        reference_matrices(g.n, p->penalty_C, r.M, r.K, r.A);
+        r.built = true;
+        const int hc = (g.n + 1) / 2, h = g.n / 2;
+        const int cnt = 2 * (hc * hc + h * h);
+        double tab[kEOSlot];
+        if (!build_eo_apply(g.n, r.M, r.K, tab)) {
+            st = set_error(TP_ERR_UNSUPPORTED, "reference matrices are not centrosymmetric");
+            break;
+        }
+        st = upload_eo(*p, g.n, EO_APPLY_K, tab, cnt);
+        if (st != TP_OK) break;
+        if (!build_eo_apply(g.n, r.M, r.A, tab)) {
+            st = set_error(TP_ERR_UNSUPPORTED, "reference matrices are not centrosymmetric");
+            break;
+        }
+        st = upload_eo(*p, g.n, EO_APPLY_A, tab, cnt);
+    }
     if (st != TP_OK) {
         free_plan_memory(p);
         delete p;
@@ -232,7 +265,8 @@ tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dty
     if (u == v && u) return set_error(TP_ERR_ARG, "u and v must not alias");
     for (const auto& g : plan->groups) {
         const RefData& r = plan->ref[g.n];
-        tp_status st = launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream);
+        tp_status st = g.n <= kLaneMaxN ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
+                                        : launch_apply_eo(*plan, g, op, u, v, dtype, stream);
         if (st != TP_OK) return st;
     }
     return TP_OK;
@@ -256,6 +290,13 @@ tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, d
             return set_error(TP_ERR_SINGULAR, "operator of n=" + std::to_string(n) +
                                                   " is singular: lambda_min/lambda_max = " +
                                                   std::to_string(r.lam[0] / r.lam[n - 1]));
+        double tab[kEOSlot];
+        const int cnt = ((n + 1) / 2) * ((n + 1) / 2) + (n / 2) * (n / 2) + n;
+        if (!build_eo_inverse(n, r.S, r.lam, tab))
+            return set_error(TP_ERR_UNSUPPORTED, "eigenvectors of n=" + std::to_string(n) +
+                                                     " are not split into symmetric and antisymmetric ones");
+        tp_status st = upload_eo(*plan, n, EO_INV, tab, cnt);
+        if (st != TP_OK) return st;
         r.eig_ready = true;
     }
     plan->inverse_op = op;
@@ -269,7 +310,8 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
     if (plan->vec_elems > 0 && (!r || !x)) return set_error(TP_ERR_ARG, "r and x must be non-null");
     if (r == x && r) return set_error(TP_ERR_ARG, "r and x must not alias");
     for (const auto& g : plan->groups) {
-        tp_status st = launch_inverse(*plan, g, r, x, dtype, stream);
+        tp_status st = g.n <= kLaneMaxN ? launch_inverse(*plan, g, r, x, dtype, stream)
+                                        : launch_inverse_eo(*plan, g, r, x, dtype, stream);
         if (st != TP_OK) return st;
     }
     return TP_OK;

@@ -21,6 +21,20 @@ void gauss_points(int nq, double* x, double* w);
 void reference_matrices(int n, double C, double* M, double* K, double* A);
 int gen_eigen(int n, const double* M, const double* P, double* S, double* lam);
 
+// Even-odd tables of the centrosymmetric 1D factors, one slot of kEOSlot
+// elements per (n, table, element type):
+//   EO_APPLY_K / EO_APPLY_A:  ME[hc][hc] | MO[h][h] | PE[hc][hc] | PO[h][h]
+//   EO_INV:                   SE[hc][hc] | SO[h][h] | lam[n] (split order)
+// with h = n/2, hc = (n+1)/2.  Element type 0 = double, 1 = float.
+enum { EO_APPLY_K = 0, EO_APPLY_A = 1, EO_INV = 2, EO_NTAB = 3 };
+constexpr int kEOSlot = 64;
+// Builds ME|MO|PE|PO from centrosymmetric M and P; false when either is not.
+bool build_eo_apply(int n, const double* M, const double* P, double* out);
+// Builds SE|SO|lam from eigenvectors S (columns) and eigenvalues; makes every
+// column exactly symmetric or antisymmetric.  False when the parity split
+// does not have ceil(n/2) symmetric columns.
+bool build_eo_inverse(int n, const double* S, const double* lam, double* out);
+
 // ---------------------------------------------------------------- plan data
 struct RefData {
     bool built = false;
@@ -64,6 +78,8 @@ struct Plan {
     // device workspace
     void* summary_dev = nullptr;   // solve summary counters
     GroupInfo* groups_dev = nullptr;
+    void* eo_dev = nullptr;        // even-odd tables, (kMaxN+1) x EO_NTAB x 2 slots
+    int64_t wave_grid = 2048;      // persistent grid of the wave kernels
     WorkItem* items_dev = nullptr;
     int64_t nitems = 0;
 };
@@ -91,6 +107,15 @@ tp_status launch_solve(const Plan& plan, const GroupInfo& g, const double* b, do
                        tp_dtype inner, double rtol, int maxit, int32_t* iters,
                        double* relres, hipStream_t s);
 // to_blocked: src canonical -> dst blocked; otherwise src blocked -> dst canonical
+tp_status launch_apply_eo(const Plan& plan, const GroupInfo& g, int op, const void* u, void* v,
+                          tp_dtype dt, hipStream_t s);
+tp_status launch_inverse_eo(const Plan& plan, const GroupInfo& g, const void* r, void* x, tp_dtype dt,
+                            hipStream_t s);
+inline const void* eo_table(const Plan& plan, int n, int tab, int et) {
+    return static_cast<const char*>(plan.eo_dev) +
+           static_cast<size_t>(((n * EO_NTAB + tab) * 2 + et) * kEOSlot) * sizeof(double);
+}
+tp_status upload_eo(Plan& plan, int n, int tab, const double* vals, int count);
 tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize,
                       bool to_blocked, hipStream_t s);
 tp_status launch_summary_reset(void* summary_dev, hipStream_t s);

@@ -18,92 +18,15 @@
 //   D^-1 = (S (x) S (x) S) diag(1 / (lam_i s_x + lam_j s_y + lam_k s_z)) (S (x) S (x) S)^T
 // where M, P, S, lam are the reference-interval matrices (Sec. 3.1,
 // eq. (eval_pipeline); Sec. 5.2, eq. (cell_block)).
-#include <hip/hip_runtime.h>
-
-#include "internal.h"
+#include "device.h"
 
 namespace tpfdm {
 
-// ------------------------------------------------------------ storage types
-struct bf16_t {
-    uint16_t bits;
-};
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
-    return __uint_as_float(static_cast<uint32_t>(b) << 16);
-}
-
-// float -> bfloat16 with round-to-nearest-even (add half an ulp of the
-// truncated format plus the tie bit, then truncate); NaN stays quiet NaN.
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
-}
-
-template <typename TC> __device__ __forceinline__ TC ldc(const double* p) { return static_cast<TC>(*p); }
-template <typename TC> __device__ __forceinline__ TC ldc(const float* p) { return static_cast<TC>(*p); }
-template <typename TC> __device__ __forceinline__ TC ldc(const _Float16* p) {
-    return static_cast<TC>(static_cast<float>(*p));
-}
-template <typename TC> __device__ __forceinline__ TC ldc(const bf16_t* p) {
-    return static_cast<TC>(bf16_to_f32(p->bits));
-}
-__device__ __forceinline__ void stc(double* p, double v) { *p = v; }
-__device__ __forceinline__ void stc(float* p, float v) { *p = v; }
-__device__ __forceinline__ void stc(_Float16* p, float v) { *p = static_cast<_Float16>(v); }
-__device__ __forceinline__ void stc(bf16_t* p, float v) { p->bits = f32_to_bf16(v); }
-
-// ------------------------------------------------------------ kernel params
-template <int N, typename T>
-struct Pair {      // reference mass M and operator P (K or A_hat), row-major
-    T m[N * N];
-    T p[N * N];
-};
-template <int N, typename T>
-struct Eig {       // reference eigenvectors S (column j = vector j) and eigenvalues
-    T s[N * N];
-    T lam[N];
-};
-
-struct GArgs {
-    const double* h;
-    int64_t nblocks;
-    int64_t offset;
-    int logB;
-};
-
-// Element offset of block g's DoF 0 inside its group; DoF q sits at
-// base + (q << logB).
-__device__ __forceinline__ int64_t block_base(int64_t g, int logB, int n3) {
-    return (((g >> logB) * n3) << logB) + (g & ((int64_t(1) << logB) - 1));
-}
-
-template <typename TC>
-__device__ __forceinline__ void block_scales(const double* h, int64_t g, TC& sx, TC& sy, TC& sz) {
-    const double hx = h[3 * g], hy = h[3 * g + 1], hz = h[3 * g + 2];
-    sx = static_cast<TC>(hy * hz / hx);
-    sy = static_cast<TC>(hx * hz / hy);
-    sz = static_cast<TC>(hx * hy / hz);
-}
-
-// Reciprocal: hardware estimate refined by Newton-Raphson steps
-// r <- r + r (1 - a r), each of which roughly doubles the correct bits.
-__device__ __forceinline__ double recip(double a) {
-    double r = __builtin_amdgcn_rcp(a);
-    double e = fma(-a, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-a, r, 1.0);
-    return fma(r, e, r);
-}
-__device__ __forceinline__ float recip(float a) {
-    float r = __builtin_amdgcn_rcpf(a);
-    float e = fmaf(-a, r, 1.0f);
-    return fmaf(r, e, r);
-}
-
 // ============================================================ lane-per-block
+// Both transforms below stream the block one x-plane (n^2 DoFs) at a time and
+// load plane ip+1 before computing plane ip, so every wave keeps one plane of
+// loads in flight while it computes.
+
 // Accumulate acc = A u for one block held by this lane.  load(q) returns DoF
 // q of u.  Order: for every x-plane ip of the input, contract z (M and P)
 // and y (a = M t, b = s_y P t + s_z M w) inside the plane, then scatter the
@@ -114,11 +37,16 @@ __device__ __forceinline__ void lane_apply(LoadF load, const Pair<N, TC>& R, TC 
     constexpr int N2 = N * N;
 #pragma unroll
     for (int q = 0; q < N * N2; ++q) acc[q] = TC(0);
+    TC xb[2][N2];
+#pragma unroll
+    for (int q = 0; q < N2; ++q) xb[0][q] = load(q);
 #pragma unroll
     for (int ip = 0; ip < N; ++ip) {
-        TC x[N2];
+        TC(&x)[N2] = xb[ip & 1];
+        if (ip + 1 < N) {
 #pragma unroll
-        for (int q = 0; q < N2; ++q) x[q] = load(ip * N2 + q);
+            for (int q = 0; q < N2; ++q) xb[(ip + 1) & 1][q] = load((ip + 1) * N2 + q);
+        }
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             TC t[N], w[N];
@@ -154,10 +82,11 @@ __device__ __forceinline__ void lane_apply(LoadF load, const Pair<N, TC>& R, TC 
     }
 }
 
-// y = D^{-1} r for one block held by this lane; load(q) reads r, emit(q, v)
-// consumes output DoF q.  Forward transform S^T plane by plane into y,
-// diagonal scaling, backward transform S one output plane at a time:
-// 6 n^4 multiply-adds and n^3 reciprocals per block.
+// D^{-1} r for one block held by this lane; load(q) reads r, emit(q, v)
+// consumes output DoF q.  Forward transform S^T plane by plane accumulated
+// into y, diagonal scaling by 1/(lam_i s_x + lam_j s_y + lam_k s_z), then
+// (S (x) S) in place on every plane of y and finally the x-contraction, one
+// output DoF at a time: 6 n^4 multiply-adds and n^3 reciprocals per block.
 template <int N, typename TC, typename LoadF, typename EmitF>
 __device__ __forceinline__ void lane_inverse(LoadF load, EmitF emit, const Eig<N, TC>& E, TC sx, TC sy,
                                              TC sz) {
@@ -165,11 +94,16 @@ __device__ __forceinline__ void lane_inverse(LoadF load, EmitF emit, const Eig<N
     TC y[N * N2];
 #pragma unroll
     for (int q = 0; q < N * N2; ++q) y[q] = TC(0);
+    TC xb[2][N2];
+#pragma unroll
+    for (int q = 0; q < N2; ++q) xb[0][q] = load(q);
 #pragma unroll
     for (int ip = 0; ip < N; ++ip) {
-        TC x[N2];
+        TC(&x)[N2] = xb[ip & 1];
+        if (ip + 1 < N) {
 #pragma unroll
-        for (int q = 0; q < N2; ++q) x[q] = load(ip * N2 + q);
+            for (int q = 0; q < N2; ++q) xb[(ip + 1) & 1][q] = load((ip + 1) * N2 + q);
+        }
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             TC t[N];
@@ -206,25 +140,18 @@ __device__ __forceinline__ void lane_inverse(LoadF load, EmitF emit, const Eig<N
         for (int j = 0; j < N; ++j)
 #pragma unroll
             for (int k = 0; k < N; ++k) y[(i * N + j) * N + k] *= recip(lx[i] + ly[j] + lz[k]);
+    // (S (x) S) on every x-plane of y, in place
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
+    for (int a = 0; a < N; ++a) {
         TC z[N2];
 #pragma unroll
-        for (int q = 0; q < N2; ++q) {
-            TC s = TC(0);
-#pragma unroll
-            for (int a = 0; a < N; ++a) s = fma(E.s[i * N + a], y[a * N2 + q], s);
-            z[q] = s;
-        }
-        TC W[N2];
-#pragma unroll
-        for (int b = 0; b < N; ++b)
+        for (int bq = 0; bq < N; ++bq)
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 TC s = TC(0);
 #pragma unroll
-                for (int c = 0; c < N; ++c) s = fma(E.s[k * N + c], z[b * N + c], s);
-                W[b * N + k] = s;
+                for (int c = 0; c < N; ++c) s = fma(E.s[k * N + c], y[a * N2 + bq * N + c], s);
+                z[bq * N + k] = s;
             }
 #pragma unroll
         for (int j = 0; j < N; ++j)
@@ -232,14 +159,24 @@ __device__ __forceinline__ void lane_inverse(LoadF load, EmitF emit, const Eig<N
             for (int k = 0; k < N; ++k) {
                 TC s = TC(0);
 #pragma unroll
-                for (int b = 0; b < N; ++b) s = fma(E.s[j * N + b], W[b * N + k], s);
-                emit(i * N2 + j * N + k, s);
+                for (int bq = 0; bq < N; ++bq) s = fma(E.s[j * N + bq], z[bq * N + k], s);
+                y[a * N2 + j * N + k] = s;
             }
     }
+    // x-contraction, one output DoF at a time
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            TC s = TC(0);
+#pragma unroll
+            for (int a = 0; a < N; ++a) s = fma(E.s[i * N + a], y[a * N2 + q], s);
+            emit(i * N2 + q, s);
+        }
 }
 
 template <int N, typename TS, typename TC>
-__global__ __launch_bounds__(256) void k_apply_lane(const TS* __restrict__ u, TS* __restrict__ v, GArgs G,
+__global__ __launch_bounds__(256, 2) void k_apply_lane(const TS* __restrict__ u, TS* __restrict__ v, GArgs G,
                                                     Pair<N, TC> R) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= G.nblocks) return;
@@ -257,7 +194,7 @@ __global__ __launch_bounds__(256) void k_apply_lane(const TS* __restrict__ u, TS
 }
 
 template <int N, typename TS, typename TC>
-__global__ __launch_bounds__(256) void k_inverse_lane(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
+__global__ __launch_bounds__(256, 2) void k_inverse_lane(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
                                                       Eig<N, TC> E) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= G.nblocks) return;
@@ -285,36 +222,6 @@ __device__ __forceinline__ void record_solve(SolveSummary* sum, int32_t* iters, 
 }
 
 // ============================================================ wave-per-tile
-// A workgroup of one wave owns BPW = max(1, 64 / n^2) consecutive blocks.
-// Lane l works on block w = l / n^2 of the tile and on pencil l % n^2 of it.
-// Each block's n^3 slab sits in LDS, element (i, j, k) at (i n + j)(n+1) + k;
-// the pad of one element per pencil spreads strided pencil reads over banks.
-template <int N>
-struct Slab {
-    static constexpr int N2 = N * N;
-    static constexpr int N3 = N * N * N;
-    static constexpr int BPW = N2 >= 64 ? 1 : 64 / N2;
-    static constexpr int size = N * N * (N + 1);
-    __device__ static __forceinline__ int at(int i, int j, int k) { return (i * N + j) * (N + 1) + k; }
-    __device__ static __forceinline__ int lin(int e) { return e + e / N; }
-};
-
-// Per-lane pencil coordinates inside the tile.
-template <int N>
-struct Pencil {
-    int w;       // block within the tile
-    int pa, pb;  // pencil coordinates (meaning depends on the phase)
-    bool act;    // lane owns a pencil of an existing block
-    __device__ __forceinline__ Pencil(int nvalid) {
-        const int lane = threadIdx.x;
-        w = lane / Slab<N>::N2;
-        const int p = lane - w * Slab<N>::N2;
-        pa = p / N;
-        pb = p - pa * N;
-        act = w < Slab<N>::BPW && w < nvalid;
-    }
-};
-
 // dst = A src on the lane's LDS slab (dst may alias src); t1, t2 scratch
 // slabs.  Lane (i,j) contracts z, lane (i,k) contracts y, lane (j,k)
 // contracts x; within a phase each lane reads and writes only its pencil.
@@ -484,42 +391,6 @@ __device__ __forceinline__ void stage_out(TS* __restrict__ dst, const TC* slabs,
         stc(dst + G.offset + block_base(g0 + w, G.logB, L::N3) + (static_cast<int64_t>(q) << G.logB),
             slabs[w * L::size + L::lin(q)]);
     }
-}
-
-template <int N, typename TS, typename TC>
-__global__ __launch_bounds__(64) void k_apply_wave(const TS* __restrict__ u, TS* __restrict__ v, GArgs G,
-                                                   Pair<N, TC> R) {
-    using L = Slab<N>;
-    __shared__ TC s0[L::BPW * L::size], s1[L::BPW * L::size], s2[L::BPW * L::size];
-    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * L::BPW;
-    if (g0 >= G.nblocks) return;
-    const int nvalid = static_cast<int>(G.nblocks - g0 < L::BPW ? G.nblocks - g0 : L::BPW);
-    stage_in<N>(u, s0, G, g0, nvalid);
-    const Pencil<N> pc(nvalid);
-    TC sx = TC(1), sy = TC(1), sz = TC(1);
-    if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
-    __syncthreads();
-    const int so = (pc.w < L::BPW ? pc.w : 0) * L::size;
-    wave_apply<N, TC>(pc, s0 + so, s0 + so, s1 + so, s2 + so, R, sx, sy, sz);
-    stage_out<N>(v, s0, G, g0, nvalid);
-}
-
-template <int N, typename TS, typename TC>
-__global__ __launch_bounds__(64) void k_inverse_wave(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
-                                                     Eig<N, TC> E) {
-    using L = Slab<N>;
-    __shared__ TC s0[L::BPW * L::size], s1[L::BPW * L::size];
-    const int64_t g0 = static_cast<int64_t>(blockIdx.x) * L::BPW;
-    if (g0 >= G.nblocks) return;
-    const int nvalid = static_cast<int>(G.nblocks - g0 < L::BPW ? G.nblocks - g0 : L::BPW);
-    stage_in<N>(r, s0, G, g0, nvalid);
-    const Pencil<N> pc(nvalid);
-    TC sx = TC(1), sy = TC(1), sz = TC(1);
-    if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
-    __syncthreads();
-    const int so = (pc.w < L::BPW ? pc.w : 0) * L::size;
-    wave_inverse<N, TC>(pc, s0 + so, s1 + so, E, sx, sy, sz);
-    stage_out<N>(x, s0, G, g0, nvalid);
 }
 
 // Block-local iterative refinement (a6), one wave per tile of BPW blocks:
@@ -715,28 +586,18 @@ tp_status check_launch(const char* what) {
 template <int N, typename TS, typename TC>
 tp_status apply_n(const GroupInfo& g, const double* Mm, const double* Pm, const void* u, void* v, hipStream_t s) {
     const auto R = make_pair<N, TC>(Mm, Pm);
-    if constexpr (N <= kLaneMaxN) {
-        const unsigned grid = static_cast<unsigned>((g.nblocks + kLaneThreads - 1) / kLaneThreads);
-        hipLaunchKernelGGL((k_apply_lane<N, TS, TC>), dim3(grid), dim3(kLaneThreads), 0, s,
-                           static_cast<const TS*>(u), static_cast<TS*>(v), gargs(g), R);
-    } else {
-        hipLaunchKernelGGL((k_apply_wave<N, TS, TC>), dim3(wave_tiles<N>(g)), dim3(64), 0, s,
-                           static_cast<const TS*>(u), static_cast<TS*>(v), gargs(g), R);
-    }
+    const unsigned grid = static_cast<unsigned>((g.nblocks + kLaneThreads - 1) / kLaneThreads);
+    hipLaunchKernelGGL((k_apply_lane<N, TS, TC>), dim3(grid), dim3(kLaneThreads), 0, s,
+                       static_cast<const TS*>(u), static_cast<TS*>(v), gargs(g), R);
     return check_launch("apply launch");
 }
 
 template <int N, typename TS, typename TC>
 tp_status inverse_n(const GroupInfo& g, const RefData& ref, const void* r, void* x, hipStream_t s) {
     const auto E = make_eig<N, TC>(ref);
-    if constexpr (N <= kLaneMaxN) {
-        const unsigned grid = static_cast<unsigned>((g.nblocks + kLaneThreads - 1) / kLaneThreads);
-        hipLaunchKernelGGL((k_inverse_lane<N, TS, TC>), dim3(grid), dim3(kLaneThreads), 0, s,
-                           static_cast<const TS*>(r), static_cast<TS*>(x), gargs(g), E);
-    } else {
-        hipLaunchKernelGGL((k_inverse_wave<N, TS, TC>), dim3(wave_tiles<N>(g)), dim3(64), 0, s,
-                           static_cast<const TS*>(r), static_cast<TS*>(x), gargs(g), E);
-    }
+    const unsigned grid = static_cast<unsigned>((g.nblocks + kLaneThreads - 1) / kLaneThreads);
+    hipLaunchKernelGGL((k_inverse_lane<N, TS, TC>), dim3(grid), dim3(kLaneThreads), 0, s,
+                       static_cast<const TS*>(r), static_cast<TS*>(x), gargs(g), E);
     return check_launch("apply_inverse launch");
 }
 
@@ -759,10 +620,7 @@ tp_status apply_dispatch(const GroupInfo& g, const double* Mm, const double* Pm,
         case 2: return apply_n<2, TS, TC>(g, Mm, Pm, u, v, s);
         case 3: return apply_n<3, TS, TC>(g, Mm, Pm, u, v, s);
         case 4: return apply_n<4, TS, TC>(g, Mm, Pm, u, v, s);
-        case 5: return apply_n<5, TS, TC>(g, Mm, Pm, u, v, s);
-        case 6: return apply_n<6, TS, TC>(g, Mm, Pm, u, v, s);
-        case 7: return apply_n<7, TS, TC>(g, Mm, Pm, u, v, s);
-        case 8: return apply_n<8, TS, TC>(g, Mm, Pm, u, v, s);
+        default: break;
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
 }
@@ -773,10 +631,7 @@ tp_status inverse_dispatch(const GroupInfo& g, const RefData& ref, const void* r
         case 2: return inverse_n<2, TS, TC>(g, ref, r, x, s);
         case 3: return inverse_n<3, TS, TC>(g, ref, r, x, s);
         case 4: return inverse_n<4, TS, TC>(g, ref, r, x, s);
-        case 5: return inverse_n<5, TS, TC>(g, ref, r, x, s);
-        case 6: return inverse_n<6, TS, TC>(g, ref, r, x, s);
-        case 7: return inverse_n<7, TS, TC>(g, ref, r, x, s);
-        case 8: return inverse_n<8, TS, TC>(g, ref, r, x, s);
+        default: break;
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
 }

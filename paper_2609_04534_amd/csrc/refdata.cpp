@@ -245,4 +245,52 @@ int gen_eigen(int n, const double* M, const double* P, double* S, double* lam) {
     return 0;
 }
 
+bool build_eo_apply(int n, const double* M, const double* P, double* out) {
+    const int h = n / 2, hc = (n + 1) / 2;
+    double scale = 0.0;
+    for (int i = 0; i < n * n; ++i) scale = std::max(scale, std::max(std::fabs(M[i]), std::fabs(P[i])));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const int a = i * n + j, b = (n - 1 - i) * n + (n - 1 - j);
+            if (std::fabs(M[a] - M[b]) > 1e-12 * scale || std::fabs(P[a] - P[b]) > 1e-12 * scale) return false;
+        }
+    const double* mats[2] = {M, P};
+    double* o = out;
+    for (int m = 0; m < 2; ++m) {
+        const double* A = mats[m];
+        for (int i = 0; i < hc; ++i)
+            for (int j = 0; j < hc; ++j)
+                *o++ = (j < h) ? 0.5 * (A[i * n + j] + A[i * n + (n - 1 - j)]) : A[i * n + j];
+        for (int i = 0; i < h; ++i)
+            for (int j = 0; j < h; ++j) *o++ = 0.5 * (A[i * n + j] - A[i * n + (n - 1 - j)]);
+    }
+    return true;
+}
+
+bool build_eo_inverse(int n, const double* S, const double* lam, double* out) {
+    const int h = n / 2, hc = (n + 1) / 2;
+    std::vector<int> sym, anti;
+    std::vector<double> Sp(n * n);
+    for (int c = 0; c < n; ++c) {
+        double dot = 0.0, nrm = 0.0;
+        for (int k = 0; k < n; ++k) {
+            dot += S[k * n + c] * S[(n - 1 - k) * n + c];
+            nrm += S[k * n + c] * S[k * n + c];
+        }
+        const double sg = dot >= 0.0 ? 1.0 : -1.0;
+        if (std::fabs(std::fabs(dot) - nrm) > 1e-8 * nrm) return false;
+        for (int k = 0; k < n; ++k) Sp[k * n + c] = 0.5 * (S[k * n + c] + sg * S[(n - 1 - k) * n + c]);
+        (sg > 0 ? sym : anti).push_back(c);
+    }
+    if (static_cast<int>(sym.size()) != hc || static_cast<int>(anti.size()) != h) return false;
+    double* o = out;
+    for (int k = 0; k < hc; ++k)
+        for (int c = 0; c < hc; ++c) *o++ = Sp[k * n + sym[c]];
+    for (int k = 0; k < h; ++k)
+        for (int c = 0; c < h; ++c) *o++ = Sp[k * n + anti[c]];
+    for (int c = 0; c < hc; ++c) *o++ = lam[sym[c]];
+    for (int c = 0; c < h; ++c) *o++ = lam[anti[c]];
+    return true;
+}
+
 }  // namespace tpfdm
