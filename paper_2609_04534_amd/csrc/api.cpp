@@ -211,7 +211,7 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
     p->nblocks = block0;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
-        p->wave_grid = static_cast<int64_t>(cus) * 8;
+        p->wave_grid = static_cast<int64_t>(cus) * 8, p->cus = cus;
     tp_status st = alloc_dev(&p->summary_dev, sizeof(SolveSummary), "solve summary");
     if (st == TP_OK)
         st = alloc_dev(&p->eo_dev, static_cast<size_t>(kMaxN + 1) * EO_NTAB * 2 * kEOSlot * sizeof(double),

@@ -15,6 +15,10 @@
 // Mapping: one wave per tile of BPW blocks, each block's slab in LDS, one
 // pencil per lane and phase (see Slab/Pencil); a persistent grid loops over
 // tiles and loads tile t + grid into registers while tile t is computed.
+#include <algorithm>
+#include <climits>
+#include <type_traits>
+
 #include "device.h"
 
 namespace tpfdm {
@@ -120,105 +124,133 @@ __device__ __forceinline__ void eo_bwd(const T* SE, const T* SO, const T (&y)[N]
     eo_join<N>(E, O, x);
 }
 
-// Per-lane prefetch buffer of one tile (BPW blocks, block-linear order).
-template <int N, typename TC>
-struct TileBuf {
-    static constexpr int PER = (Slab<N>::BPW * Slab<N>::N3 + 63) / 64;
-    TC v[PER];
+// ------------------------------------------------------------ pencil I/O
+// Lane (w, i, j) of a tile owns the z-pencil (i, j, 0..n-1) of block w.  For
+// the block-contiguous layout (B = 1) a pencil is n consecutive elements and
+// is moved with 16-byte vector accesses when the address allows it.
+template <int N, typename TS>
+__device__ __forceinline__ const TS* pencil_ptr(const TS* base, const GArgs& G, int64_t g, int i, int j) {
+    return base + G.offset + block_base(g, G.logB, N * N * N) + (static_cast<int64_t>((i * N + j) * N) << G.logB);
+}
+
+// 16 bytes of storage elements.
+template <typename TS>
+union Pack16 {
+    static constexpr int n = 16 / static_cast<int>(sizeof(TS));
+    uint4 u;
+    TS s[16 / sizeof(TS)];
 };
 
-template <int N, typename TS, typename TC>
-__device__ __forceinline__ void tile_load(TileBuf<N, TC>& buf, const TS* __restrict__ src, const GArgs& G,
-                                          int64_t g0, int nvalid) {
-    using L = Slab<N>;
+// With VP the caller guarantees B = 1 and 16-byte aligned pencils.
+template <int N, bool VP, typename TS, typename TC>
+__device__ __forceinline__ void pencil_load(TC (&x)[N], const TS* __restrict__ p, int logB) {
+    constexpr int VEC = Pack16<TS>::n;
+    if constexpr (VP && N % VEC == 0) {
+        {
+            const uint4* vp = reinterpret_cast<const uint4*>(p);
 #pragma unroll
-    for (int r = 0; r < TileBuf<N, TC>::PER; ++r) {
-        const int e = r * 64 + static_cast<int>(threadIdx.x);
-        const int w = e / L::N3;
-        const int q = e - w * L::N3;
-        buf.v[r] = (w < nvalid)
-                       ? ldc<TC>(src + G.offset + block_base(g0 + w, G.logB, L::N3) + (static_cast<int64_t>(q) << G.logB))
-                       : TC(0);
+            for (int c = 0; c < N / VEC; ++c) {
+                Pack16<TS> pk;
+                pk.u = vp[c];
+#pragma unroll
+                for (int l = 0; l < VEC; ++l) x[c * VEC + l] = ldc<TC>(&pk.s[l]);
+            }
+            return;
+        }
     }
+#pragma unroll
+    for (int k = 0; k < N; ++k) x[k] = ldc<TC>(p + (static_cast<int64_t>(k) << logB));
 }
 
-template <int N, typename TC>
-__device__ __forceinline__ void tile_to_lds(const TileBuf<N, TC>& buf, TC* slabs, int nvalid) {
-    using L = Slab<N>;
+template <int N, bool VP, typename TS, typename TC>
+__device__ __forceinline__ void pencil_store(TS* __restrict__ p, const TC (&x)[N], int logB) {
+    constexpr int VEC = Pack16<TS>::n;
+    if constexpr (VP && N % VEC == 0) {
+        {
+            uint4* vp = reinterpret_cast<uint4*>(p);
 #pragma unroll
-    for (int r = 0; r < TileBuf<N, TC>::PER; ++r) {
-        const int e = r * 64 + static_cast<int>(threadIdx.x);
-        const int w = e / L::N3;
-        const int q = e - w * L::N3;
-        if (w < nvalid) slabs[w * L::size + L::lin(q)] = buf.v[r];
+            for (int c = 0; c < N / VEC; ++c) {
+                Pack16<TS> pk;
+#pragma unroll
+                for (int l = 0; l < VEC; ++l) stc(&pk.s[l], x[c * VEC + l]);
+                vp[c] = pk.u;
+            }
+            return;
+        }
     }
+#pragma unroll
+    for (int k = 0; k < N; ++k) stc(p + (static_cast<int64_t>(k) << logB), x[k]);
 }
 
-template <int N, typename TS, typename TC>
-__device__ __forceinline__ void tile_store(TS* __restrict__ dst, const TC* slabs, const GArgs& G, int64_t g0,
-                                           int nvalid) {
-    using L = Slab<N>;
+template <int N>
+__device__ __forceinline__ int nvalid_of(const GArgs& G, int64_t t) {
+    const int64_t g0 = t * Slab<N>::BPW;
+    return static_cast<int>(G.nblocks - g0 < Slab<N>::BPW ? G.nblocks - g0 : Slab<N>::BPW);
+}
+
+// Loads the 1D factor table into registers.  FP64 tables go through LDS so
+// that they land in VGPRs; FP32 tables are read with wave-uniform addresses
+// and stay in scalar registers.
+template <typename TC, int COUNT>
+__device__ __forceinline__ void load_table(TC (&dst)[COUNT], const TC* __restrict__ tab, TC* stab) {
+    if constexpr (sizeof(TC) == 8) {
+        for (int e = threadIdx.x; e < COUNT; e += 64) stab[e] = tab[e];
+        __syncthreads();
 #pragma unroll
-    for (int r = 0; r < TileBuf<N, TC>::PER; ++r) {
-        const int e = r * 64 + static_cast<int>(threadIdx.x);
-        const int w = e / L::N3;
-        const int q = e - w * L::N3;
-        if (w < nvalid)
-            stc(dst + G.offset + block_base(g0 + w, G.logB, L::N3) + (static_cast<int64_t>(q) << G.logB),
-                slabs[w * L::size + L::lin(q)]);
+        for (int i = 0; i < COUNT; ++i) dst[i] = stab[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < COUNT; ++i) dst[i] = tab[i];
     }
 }
 
 // v = A u.  Table: ME | MO | PE | PO.
-template <int N, typename TS, typename TC>
+// Per tile: z-phase from the prefetched pencil registers, y-phase and
+// x-phase through LDS, x-phase results stored straight to global memory
+// (lanes (j, k) of one output plane are consecutive addresses).
+template <int N, typename TS, typename TC, bool VP>
 __global__ __launch_bounds__(64, 2) void k_apply_eo(const TS* __restrict__ u, TS* __restrict__ v, GArgs G,
-                                                 const TC* __restrict__ tab, int64_t ntiles) {
+                                                    const TC* __restrict__ tab, int64_t ntiles) {
     using L = Slab<N>;
     using S = EOShape<N>;
     constexpr int HC = S::HC, H = S::H;
     constexpr int TAB = 2 * (S::SE + S::SO);
-    __shared__ TC s0[L::BPW * L::size], s1[L::BPW * L::size], s2[L::BPW * L::size];
+    __shared__ TC s1[L::BPW * L::size], s2[L::BPW * L::size];
     __shared__ TC stab[TAB];
-    for (int e = threadIdx.x; e < TAB; e += 64) stab[e] = tab[e];
-    __syncthreads();
-    TC ME[S::SE], MO[S::SO], PE[S::SE], PO[S::SO];
-#pragma unroll
-    for (int i = 0; i < S::SE; ++i) {
-        ME[i] = stab[i];
-        PE[i] = stab[S::SE + S::SO + i];
-    }
-#pragma unroll
-    for (int i = 0; i < S::SO; ++i) {
-        MO[i] = stab[S::SE + i];
-        PO[i] = stab[2 * S::SE + S::SO + i];
-    }
+    TC T[TAB];
+    load_table<TC, TAB>(T, tab, stab);
+    const TC* ME = T;
+    const TC* MO = T + S::SE;
+    const TC* PE = T + S::SE + S::SO;
+    const TC* PO = T + 2 * S::SE + S::SO;
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
-    TileBuf<N, TC> buf;
-    auto nvalid_of = [&](int64_t tt) {
-        const int64_t g0 = tt * L::BPW;
-        return static_cast<int>(G.nblocks - g0 < L::BPW ? G.nblocks - g0 : L::BPW);
-    };
-    tile_load<N>(buf, u, G, t * L::BPW, nvalid_of(t));
+    const int lane = threadIdx.x;
+    const int lw = lane / L::N2;
+    const int lp = lane - lw * L::N2;
+    const int li = lp / N, lj = lp - (lp / N) * N;
+    const int so = (lw < L::BPW ? lw : 0) * L::size;
+    TC* A1 = s1 + so;
+    TC* A2 = s2 + so;
+    TC pre[N];
+    {
+        const bool ok = lw < L::BPW && lw < nvalid_of<N>(G, t);
+        if (ok) pencil_load<N, VP>(pre, pencil_ptr<N>(u, G, t * L::BPW + lw, li, lj), G.logB);
+    }
     for (; t < ntiles; t += gridDim.x) {
         const int64_t g0 = t * L::BPW;
-        const int nvalid = nvalid_of(t);
-        tile_to_lds<N>(buf, s0, nvalid);
+        const Pencil<N> pc(nvalid_of<N>(G, t));
+        TC x[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) x[k] = pre[k];
         const int64_t tn = t + gridDim.x;
-        if (tn < ntiles) tile_load<N>(buf, u, G, tn * L::BPW, nvalid_of(tn));
-        const Pencil<N> pc(nvalid);
+        if (tn < ntiles && lw < L::BPW && lw < nvalid_of<N>(G, tn))
+            pencil_load<N, VP>(pre, pencil_ptr<N>(u, G, tn * L::BPW + lw, li, lj), G.logB);
         TC sx = TC(1), sy = TC(1), sz = TC(1);
         if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
-        const int so = (pc.w < L::BPW ? pc.w : 0) * L::size;
-        TC* A0 = s0 + so;
-        TC* A1 = s1 + so;
-        TC* A2 = s2 + so;
         const int pa = pc.pa, pb = pc.pb;
-        __syncthreads();
         if (pc.act) {  // z: lane (i, j); t = M x, w = P x
-            TC x[N], e[HC], o[H], E[HC], O[H], y[N];
-#pragma unroll
-            for (int k = 0; k < N; ++k) x[k] = A0[L::at(pa, pb, k)];
+            TC e[HC], o[H], E[HC], O[H], y[N];
             eo_split<N>(x, e, o);
             eo_mul<N>(ME, MO, e, o, E, O);
             eo_join<N>(E, O, y);
@@ -231,13 +263,13 @@ __global__ __launch_bounds__(64, 2) void k_apply_eo(const TS* __restrict__ u, TS
         }
         __syncthreads();
         if (pc.act) {  // y: lane (i, k); a = s_x M t, b = s_y P t + s_z M w
-            TC x[N], et[HC], ot[H], ew[HC], ow[H], E[HC], O[H], E2[HC], O2[H], y[N];
+            TC et[HC], ot[H], ew[HC], ow[H], E[HC], O[H], E2[HC], O2[H], y[N];
 #pragma unroll
-            for (int j = 0; j < N; ++j) x[j] = A1[L::at(pa, j, pb)];
-            eo_split<N>(x, et, ot);
+            for (int j = 0; j < N; ++j) y[j] = A1[L::at(pa, j, pb)];
+            eo_split<N>(y, et, ot);
 #pragma unroll
-            for (int j = 0; j < N; ++j) x[j] = A2[L::at(pa, j, pb)];
-            eo_split<N>(x, ew, ow);
+            for (int j = 0; j < N; ++j) y[j] = A2[L::at(pa, j, pb)];
+            eo_split<N>(y, ew, ow);
             eo_mul<N>(ME, MO, et, ot, E, O);
             eo_join<N>(E, O, y);
 #pragma unroll
@@ -253,14 +285,14 @@ __global__ __launch_bounds__(64, 2) void k_apply_eo(const TS* __restrict__ u, TS
             for (int j = 0; j < N; ++j) A2[L::at(pa, j, pb)] = y[j];
         }
         __syncthreads();
-        if (pc.act) {  // x: lane (j, k); v = P a + M b
-            TC x[N], ea[HC], oa[H], eb[HC], ob[H], E[HC], O[H], E2[HC], O2[H], y[N];
+        if (pc.act) {  // x: lane (j, k); v = P a + M b, stored to global
+            TC y[N], ea[HC], oa[H], eb[HC], ob[H], E[HC], O[H], E2[HC], O2[H];
 #pragma unroll
-            for (int i = 0; i < N; ++i) x[i] = A1[L::at(i, pa, pb)];
-            eo_split<N>(x, ea, oa);
+            for (int i = 0; i < N; ++i) y[i] = A1[L::at(i, pa, pb)];
+            eo_split<N>(y, ea, oa);
 #pragma unroll
-            for (int i = 0; i < N; ++i) x[i] = A2[L::at(i, pa, pb)];
-            eo_split<N>(x, eb, ob);
+            for (int i = 0; i < N; ++i) y[i] = A2[L::at(i, pa, pb)];
+            eo_split<N>(y, eb, ob);
             eo_mul<N>(PE, PO, ea, oa, E, O);
             eo_mul<N>(ME, MO, eb, ob, E2, O2);
 #pragma unroll
@@ -268,104 +300,106 @@ __global__ __launch_bounds__(64, 2) void k_apply_eo(const TS* __restrict__ u, TS
 #pragma unroll
             for (int i = 0; i < H; ++i) O[i] += O2[i];
             eo_join<N>(E, O, y);
+            TS* out = v + G.offset + block_base(g0 + pc.w, G.logB, L::N3);
 #pragma unroll
-            for (int i = 0; i < N; ++i) A0[L::at(i, pa, pb)] = y[i];
+            for (int i = 0; i < N; ++i) stc(out + (static_cast<int64_t>((i * N + pa) * N + pb) << G.logB), y[i]);
         }
-        __syncthreads();
-        tile_store<N>(v, s0, G, g0, nvalid);
         __syncthreads();
     }
 }
 
-// x = D^{-1} r.  Table: SE | SO | lamP (eigenvalues in split spectral order).
-template <int N, typename TS, typename TC>
-__global__ __launch_bounds__(64) void k_inverse_eo(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
-                                                   const TC* __restrict__ tab, int64_t ntiles) {
+// x = D^{-1} r.  Table: SE | SO | lam (eigenvalues in split spectral order).
+template <int N, typename TS, typename TC, bool VP>
+__global__ __launch_bounds__(64, 2) void k_inverse_eo(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
+                                                      const TC* __restrict__ tab, int64_t ntiles) {
     using L = Slab<N>;
     using S = EOShape<N>;
-    constexpr int TAB = S::SE + S::SO + N;
-    __shared__ TC s0[L::BPW * L::size], s1[L::BPW * L::size];
-    __shared__ TC stab[TAB];
-    for (int e = threadIdx.x; e < TAB; e += 64) stab[e] = tab[e];
+    constexpr int TABM = S::SE + S::SO;
+    __shared__ TC s1[L::BPW * L::size];
+    __shared__ TC stab[TABM + N];
+    for (int e = threadIdx.x; e < TABM + N; e += 64) stab[e] = tab[e];
     __syncthreads();
-    TC SE[S::SE], SO[S::SO];
+    TC T[TABM];
+    if constexpr (sizeof(TC) == 8) {
 #pragma unroll
-    for (int i = 0; i < S::SE; ++i) SE[i] = stab[i];
+        for (int i = 0; i < TABM; ++i) T[i] = stab[i];
+    } else {
 #pragma unroll
-    for (int i = 0; i < S::SO; ++i) SO[i] = stab[S::SE + i];
-    const TC* lam = stab + S::SE + S::SO;
+        for (int i = 0; i < TABM; ++i) T[i] = tab[i];
+    }
+    const TC* SE = T;
+    const TC* SO = T + S::SE;
+    const TC* lam = stab + TABM;
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
-    TileBuf<N, TC> buf;
-    auto nvalid_of = [&](int64_t tt) {
-        const int64_t g0 = tt * L::BPW;
-        return static_cast<int>(G.nblocks - g0 < L::BPW ? G.nblocks - g0 : L::BPW);
-    };
-    tile_load<N>(buf, r, G, t * L::BPW, nvalid_of(t));
+    const int lane = threadIdx.x;
+    const int lw = lane / L::N2;
+    const int lp = lane - lw * L::N2;
+    const int li = lp / N, lj = lp - (lp / N) * N;
+    const int so = (lw < L::BPW ? lw : 0) * L::size;
+    TC* A1 = s1 + so;
+    TC pre[N];
+    {
+        const bool ok = lw < L::BPW && lw < nvalid_of<N>(G, t);
+        if (ok) pencil_load<N, VP>(pre, pencil_ptr<N>(r, G, t * L::BPW + lw, li, lj), G.logB);
+    }
     for (; t < ntiles; t += gridDim.x) {
         const int64_t g0 = t * L::BPW;
-        const int nvalid = nvalid_of(t);
-        tile_to_lds<N>(buf, s0, nvalid);
+        const Pencil<N> pc(nvalid_of<N>(G, t));
+        TC xin[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) xin[k] = pre[k];
         const int64_t tn = t + gridDim.x;
-        if (tn < ntiles) tile_load<N>(buf, r, G, tn * L::BPW, nvalid_of(tn));
-        const Pencil<N> pc(nvalid);
+        if (tn < ntiles && lw < L::BPW && lw < nvalid_of<N>(G, tn))
+            pencil_load<N, VP>(pre, pencil_ptr<N>(r, G, tn * L::BPW + lw, li, lj), G.logB);
         TC sx = TC(1), sy = TC(1), sz = TC(1);
         if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
-        const int so = (pc.w < L::BPW ? pc.w : 0) * L::size;
-        TC* A0 = s0 + so;
-        TC* A1 = s1 + so;
         const int pa = pc.pa, pb = pc.pb;
-        __syncthreads();
         if (pc.act) {  // z forward: lane (i, j)
-            TC xin[N], y[N];
-#pragma unroll
-            for (int k = 0; k < N; ++k) xin[k] = A0[L::at(pa, pb, k)];
+            TC y[N];
             eo_fwd<N>(SE, SO, xin, y);
 #pragma unroll
             for (int c = 0; c < N; ++c) A1[L::at(pa, pb, c)] = y[c];
         }
         __syncthreads();
         if (pc.act) {  // y forward: lane (i, c)
-            TC xin[N], y[N];
+            TC a[N], y[N];
 #pragma unroll
-            for (int j = 0; j < N; ++j) xin[j] = A1[L::at(pa, j, pb)];
-            eo_fwd<N>(SE, SO, xin, y);
+            for (int j = 0; j < N; ++j) a[j] = A1[L::at(pa, j, pb)];
+            eo_fwd<N>(SE, SO, a, y);
 #pragma unroll
             for (int b = 0; b < N; ++b) A1[L::at(pa, b, pb)] = y[b];
         }
         __syncthreads();
         if (pc.act) {  // x forward, scale, x backward: lane (b, c)
-            TC xin[N], y[N];
+            TC a[N], y[N];
 #pragma unroll
-            for (int i = 0; i < N; ++i) xin[i] = A1[L::at(i, pa, pb)];
-            eo_fwd<N>(SE, SO, xin, y);
+            for (int i = 0; i < N; ++i) a[i] = A1[L::at(i, pa, pb)];
+            eo_fwd<N>(SE, SO, a, y);
             const TC mu_bc = lam[pa] * sy + lam[pb] * sz;
 #pragma unroll
-            for (int a = 0; a < N; ++a) y[a] *= recip(fma(lam[a], sx, mu_bc));
-            eo_bwd<N>(SE, SO, y, xin);
+            for (int c = 0; c < N; ++c) y[c] *= recip(fma(lam[c], sx, mu_bc));
+            eo_bwd<N>(SE, SO, y, a);
 #pragma unroll
-            for (int i = 0; i < N; ++i) A1[L::at(i, pa, pb)] = xin[i];
+            for (int i = 0; i < N; ++i) A1[L::at(i, pa, pb)] = a[i];
         }
         __syncthreads();
         if (pc.act) {  // y backward: lane (i, c)
-            TC y[N], xo[N];
+            TC y[N], a[N];
 #pragma unroll
             for (int b = 0; b < N; ++b) y[b] = A1[L::at(pa, b, pb)];
-            eo_bwd<N>(SE, SO, y, xo);
+            eo_bwd<N>(SE, SO, y, a);
 #pragma unroll
-            for (int j = 0; j < N; ++j) A1[L::at(pa, j, pb)] = xo[j];
+            for (int j = 0; j < N; ++j) A1[L::at(pa, j, pb)] = a[j];
         }
         __syncthreads();
-        if (pc.act) {  // z backward: lane (i, j)
-            TC y[N], xo[N];
+        if (pc.act) {  // z backward: lane (i, j), pencil stored to global
+            TC y[N], a[N];
 #pragma unroll
             for (int c = 0; c < N; ++c) y[c] = A1[L::at(pa, pb, c)];
-            eo_bwd<N>(SE, SO, y, xo);
-#pragma unroll
-            for (int k = 0; k < N; ++k) A0[L::at(pa, pb, k)] = xo[k];
+            eo_bwd<N>(SE, SO, y, a);
+            pencil_store<N, VP>(const_cast<TS*>(pencil_ptr<N>(x, G, g0 + pc.w, pa, pb)), a, G.logB);
         }
-        __syncthreads();
-        tile_store<N>(x, s0, G, g0, nvalid);
         __syncthreads();
     }
 }
@@ -376,6 +410,24 @@ tp_status check(const char* what) {
     return TP_OK;
 }
 
+// Pencils can move as 16-byte vectors: B = 1, n a multiple of the vector
+// width and both buffers (with the group offset) 16-byte aligned.
+template <int N, typename TS>
+bool vector_pencils(const GroupInfo& g, const void* a, const void* b) {
+    constexpr int VEC = 16 / static_cast<int>(sizeof(TS));
+    if (g.logB != 0 || N % VEC != 0) return false;
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(static_cast<const TS*>(a) + g.offset);
+    const uintptr_t pb = reinterpret_cast<uintptr_t>(static_cast<const TS*>(b) + g.offset);
+    return (pa % 16) == 0 && (pb % 16) == 0;
+}
+
+// Persistent grid: as many one-wave workgroups as fit on the device at once.
+int64_t persistent_grid(const Plan& plan, const void* kernel, int64_t ntiles) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 64, 0) != hipSuccess || occ <= 0) occ = 8;
+    return std::max<int64_t>(1, std::min<int64_t>(ntiles, static_cast<int64_t>(plan.cus) * occ));
+}
+
 template <int N>
 int64_t eo_tiles(const GroupInfo& g) {
     return (g.nblocks + Slab<N>::BPW - 1) / Slab<N>::BPW;
@@ -384,23 +436,43 @@ int64_t eo_tiles(const GroupInfo& g) {
 template <int N, typename TS, typename TC>
 tp_status apply_eo_n(const Plan& plan, const GroupInfo& g, int op, const void* u, void* v, hipStream_t s) {
     const int64_t ntiles = eo_tiles<N>(g);
-    const int64_t grid = std::min<int64_t>(ntiles, plan.wave_grid);
     const TC* tab = reinterpret_cast<const TC*>(eo_table(plan, N, op == TP_OP_CELL ? EO_APPLY_A : EO_APPLY_K,
                                                          sizeof(TC) == 8 ? 0 : 1));
     GArgs a{g.h, g.nblocks, g.offset, g.logB};
-    hipLaunchKernelGGL((k_apply_eo<N, TS, TC>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
-                       static_cast<const TS*>(u), static_cast<TS*>(v), a, tab, ntiles);
+    const bool vp = vector_pencils<N, TS>(g, u, v);
+    const void* kern = vp ? reinterpret_cast<const void*>(&k_apply_eo<N, TS, TC, true>)
+                          : reinterpret_cast<const void*>(&k_apply_eo<N, TS, TC, false>);
+    static int64_t grid_cache[2] = {0, 0};
+    int64_t& gc = grid_cache[vp ? 1 : 0];
+    if (gc == 0) gc = persistent_grid(plan, kern, INT64_MAX);
+    const int64_t grid = std::min(gc, ntiles);
+    if (vp)
+        hipLaunchKernelGGL((k_apply_eo<N, TS, TC, true>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
+                           static_cast<const TS*>(u), static_cast<TS*>(v), a, tab, ntiles);
+    else
+        hipLaunchKernelGGL((k_apply_eo<N, TS, TC, false>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
+                           static_cast<const TS*>(u), static_cast<TS*>(v), a, tab, ntiles);
     return check("apply (even-odd) launch");
 }
 
 template <int N, typename TS, typename TC>
 tp_status inverse_eo_n(const Plan& plan, const GroupInfo& g, const void* r, void* x, hipStream_t s) {
     const int64_t ntiles = eo_tiles<N>(g);
-    const int64_t grid = std::min<int64_t>(ntiles, plan.wave_grid);
     const TC* tab = reinterpret_cast<const TC*>(eo_table(plan, N, EO_INV, sizeof(TC) == 8 ? 0 : 1));
     GArgs a{g.h, g.nblocks, g.offset, g.logB};
-    hipLaunchKernelGGL((k_inverse_eo<N, TS, TC>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
-                       static_cast<const TS*>(r), static_cast<TS*>(x), a, tab, ntiles);
+    const bool vp = vector_pencils<N, TS>(g, r, x);
+    const void* kern = vp ? reinterpret_cast<const void*>(&k_inverse_eo<N, TS, TC, true>)
+                          : reinterpret_cast<const void*>(&k_inverse_eo<N, TS, TC, false>);
+    static int64_t grid_cache[2] = {0, 0};
+    int64_t& gc = grid_cache[vp ? 1 : 0];
+    if (gc == 0) gc = persistent_grid(plan, kern, INT64_MAX);
+    const int64_t grid = std::min(gc, ntiles);
+    if (vp)
+        hipLaunchKernelGGL((k_inverse_eo<N, TS, TC, true>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
+                           static_cast<const TS*>(r), static_cast<TS*>(x), a, tab, ntiles);
+    else
+        hipLaunchKernelGGL((k_inverse_eo<N, TS, TC, false>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
+                           static_cast<const TS*>(r), static_cast<TS*>(x), a, tab, ntiles);
     return check("apply_inverse (even-odd) launch");
 }
 

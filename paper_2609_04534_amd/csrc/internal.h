@@ -80,6 +80,7 @@ struct Plan {
     GroupInfo* groups_dev = nullptr;
     void* eo_dev = nullptr;        // even-odd tables, (kMaxN+1) x EO_NTAB x 2 slots
     int64_t wave_grid = 2048;      // persistent grid of the wave kernels
+    int cus = 256;                 // compute units of the plan's device
     WorkItem* items_dev = nullptr;
     int64_t nitems = 0;
 };
