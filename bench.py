@@ -332,6 +332,64 @@ def run_suite(args, stream):
         plan.destroy()
         del bb, xs, cu, cb
         torch.cuda.empty_cache()
+    run_uneven(args, stream)
+
+
+def run_uneven(args, stream):
+    """Batched uneven degrees: per-group launches vs one persistent launch vs
+    the persistent launch replayed from a HIP graph (apply, apply_inverse and
+    the FP32-inner / FP64-refined solve), with cache-resident inputs."""
+    import torch
+    from paper_2609_04534_amd import tpfdm
+    wl, _ = build_workload("uneven_p237_20000")
+    cu = torch.from_numpy(np.concatenate([g.u.reshape(-1) for g in wl.groups])).cuda()
+    cb = torch.from_numpy(np.concatenate([g.b.reshape(-1) for g in wl.groups])).cuda()
+    reps = max(args.steps, 50)
+    for mode in ("per_group", "persistent", "persistent_graph"):
+        plan = tpfdm.Plan(tpfdm.groups_for_workload(wl), persistent=(mode != "per_group"))
+        plan.setup_inverse(tpfdm.OP_CELL)
+        E = plan.vector_elems
+        u = torch.empty(E, dtype=torch.float32, device="cuda")
+        plan.pack(cu.float(), u)
+        v, x = torch.empty_like(u), torch.empty_like(u)
+        b = torch.empty(E, dtype=torch.float64, device="cuda")
+        plan.pack(cb, b)
+        xs = torch.zeros_like(b)
+        if mode == "persistent_graph":
+            ga = plan.graph(tpfdm.GRAPH_APPLY, u, v, op=tpfdm.OP_NEUMANN)
+            gi = plan.graph(tpfdm.GRAPH_INVERSE, u, x)
+            gs = plan.graph(tpfdm.GRAPH_SOLVE, b, xs, dtype=tpfdm.F32, rtol=1e-10, maxit=50)
+            fa = lambda k: ga.launch(stream)
+            fi = lambda k: gi.launch(stream)
+            fs = lambda: gs.launch(stream)
+        else:
+            fa = lambda k: plan.apply(u, v, tpfdm.OP_NEUMANN, stream=stream)
+            fi = lambda k: plan.apply_inverse(u, x, stream=stream)
+            fs = lambda: plan.solve(b, xs, inner=tpfdm.F32, rtol=1e-10, maxit=50, summary=False, stream=stream)
+        for _ in range(3):
+            fa(0), fi(0)
+        ms_a = time_launches(fa, stream, reps, 1)
+        ms_i = time_launches(fi, stream, reps, 1)
+        lat = []
+        for i in range(max(20, args.solve_calls // 2) + 3):
+            xs.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fs()
+            torch.cuda.synchronize()
+            if i >= 3:
+                lat.append((time.perf_counter() - t0) * 1e3)
+        summ = plan.solve_summary()
+        print(json.dumps({"workload": wl.name, "mode": mode, "dtype": "f32", "ndof": plan.ndof,
+                          "apply_ms": ms_a, "apply_GDoF/s": plan.ndof / ms_a / 1e6,
+                          "inverse_ms": ms_i, "inverse_GDoF/s": plan.ndof / ms_i / 1e6,
+                          "solve_p50_ms": float(np.percentile(lat, 50)),
+                          "solve_p99_ms": float(np.percentile(lat, 99)),
+                          "solve_max_iters": summ["max_iters"], "solve_max_relres": summ["max_relres"]}),
+              flush=True)
+        if mode == "persistent_graph":
+            ga.destroy(), gi.destroy(), gs.destroy()
+        plan.destroy()
 
 
 def kernel_hash():

@@ -90,10 +90,18 @@ typedef struct {
     int64_t offset;       /* first element of the group in every vector buffer        */
 } tp_group;
 
+/* Kernel mapping of a group's blocks onto the wavefront. */
+typedef enum {
+    TP_MAP_AUTO = 0,      /* lane-per-block for n <= 4, wave-per-tile otherwise        */
+    TP_MAP_LANE = 1,      /* one block per lane, registers only (n <= 4)               */
+    TP_MAP_WAVE = 2       /* one wave per tile of blocks, pencils staged through LDS   */
+} tp_mapping;
+
 typedef struct {
     double penalty_C;     /* SIPG penalty constant C of sigma = C p(p+1)/h (default 2) */
     int32_t persistent;   /* 1: every call runs as ONE launch over all groups          */
-    int32_t reserved[7];  /* must be zero                                             */
+    int32_t mapping;      /* tp_mapping for apply / apply_inverse                      */
+    int32_t reserved[6];  /* must be zero                                             */
 } tp_plan_opts;
 
 typedef struct {
@@ -104,7 +112,7 @@ typedef struct {
 
 typedef struct tp_plan tp_plan;
 
-/* Default options: C = 2, non-persistent. */
+/* Default options: C = 2, non-persistent, automatic mapping. */
 void tp_plan_opts_default(tp_plan_opts* opts);
 
 /* Create a plan over ngroups groups on the current HIP device.  Validates the
@@ -162,6 +170,29 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
 tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner,
                    double rtol, int32_t maxit, int32_t* iters, double* relres,
                    tp_solve_summary* summary, hipStream_t stream);
+
+/* The summary (max iterations, failures, max relative residual) of the most
+ * recent tp_solve on this plan, including solves replayed from a graph.
+ * Synchronises the stream.  Returns TP_ERR_NOT_CONVERGED / TP_ERR_NONFINITE
+ * like tp_solve when the recorded solve had such blocks. */
+tp_status tp_solve_summary_fetch(tp_plan* plan, tp_solve_summary* summary, hipStream_t stream);
+
+/* HIP graphs of single calls, for replay in launch-bound loops.  A graph
+ * records the kernels of ONE call on a private capture stream: what = APPLY
+ * (v = A u with `op`), INVERSE (x = D^{-1} r) or SOLVE (block-local
+ * refinement with `inner` precision, no host summary; fetch it with
+ * tp_solve_summary_fetch).  The buffers, dtype and solve parameters are baked
+ * into the graph: replay reads `in` and overwrites `out` as the call would.
+ * With a persistent plan (opts.persistent = 1) each graph holds one kernel
+ * node over all groups.  The plan must outlive its graphs.  Nothing is
+ * allocated at replay. */
+typedef enum { TP_GRAPH_APPLY = 0, TP_GRAPH_INVERSE = 1, TP_GRAPH_SOLVE = 2 } tp_graph_op;
+typedef struct tp_graph tp_graph;
+tp_status tp_graph_create(tp_plan* plan, tp_graph_op what, tp_operator op, tp_dtype dtype, const void* in,
+                          void* out, double rtol, int32_t maxit, int32_t* iters, double* relres,
+                          tp_graph** graph);
+tp_status tp_graph_launch(tp_graph* graph, hipStream_t stream);
+tp_status tp_graph_destroy(tp_graph* graph);
 
 /* Layout helpers: convert between the canonical order (groups in order, each
  * group's blocks contiguous as [nblocks][n^3]) and the plan's blocked layout.

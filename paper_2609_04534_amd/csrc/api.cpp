@@ -31,6 +31,9 @@ int esize_of(tp_dtype dt) {
     }
     return 0;
 }
+bool use_lane(const Plan& p, const GroupInfo& g) {
+    return g.n <= kLaneMaxN && p.mapping != TP_MAP_WAVE;
+}
 bool valid_dtype(int dt) { return dt >= TP_F64 && dt <= TP_BF16; }
 bool valid_op(int op) { return op == TP_OP_NEUMANN || op == TP_OP_CELL; }
 }  // namespace
@@ -49,7 +52,8 @@ static void free_plan_memory(Plan* p) {
     for (auto& g : p->groups)
         if (g.h) (void)hipFree(g.h), g.h = nullptr;
     if (p->summary_dev) (void)hipFree(p->summary_dev), p->summary_dev = nullptr;
-    if (p->groups_dev) (void)hipFree(p->groups_dev), p->groups_dev = nullptr;
+    if (p->partials_dev) (void)hipFree(p->partials_dev), p->partials_dev = nullptr;
+    if (p->segs_dev) (void)hipFree(p->segs_dev), p->segs_dev = nullptr;
     if (p->eo_dev) (void)hipFree(p->eo_dev), p->eo_dev = nullptr;
     if (p->items_dev) (void)hipFree(p->items_dev), p->items_dev = nullptr;
 }
@@ -82,6 +86,11 @@ tp_status upload_eo(Plan& plan, int n, int tab, const double* vals, int count) {
 using namespace tpfdm;
 
 struct tp_plan : public Plan {};
+
+struct tp_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -126,8 +135,9 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
     if (opts) o = *opts;
     if (!(o.penalty_C > 0.0) || !std::isfinite(o.penalty_C))
         return set_error(TP_ERR_ARG, "penalty_C must be finite and > 0");
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < 6; ++i)
         if (o.reserved[i] != 0) return set_error(TP_ERR_ARG, "reserved option fields must be zero");
+    if (o.mapping < TP_MAP_AUTO || o.mapping > TP_MAP_WAVE) return set_error(TP_ERR_ARG, "invalid mapping");
 
     // validate groups and their element ranges
     std::vector<std::pair<int64_t, int64_t>> ranges;
@@ -160,6 +170,7 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
     }
     p->penalty_C = o.penalty_C;
     p->persistent = o.persistent != 0;
+    p->mapping = o.mapping;
     int64_t canon = 0, block0 = 0;
     std::vector<double> hbuf;
     for (int gi = 0; gi < ngroups; ++gi) {
@@ -213,6 +224,9 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
         p->wave_grid = static_cast<int64_t>(cus) * 8, p->cus = cus;
     tp_status st = alloc_dev(&p->summary_dev, sizeof(SolveSummary), "solve summary");
+    p->partials_cap = static_cast<int64_t>(p->groups.size() + 1) * p->cus * kMaxWgPerCu;
+    if (st == TP_OK)
+        st = alloc_dev(&p->partials_dev, static_cast<size_t>(p->partials_cap) * sizeof(SolvePartial), "solve partials");
     if (st == TP_OK)
         st = alloc_dev(&p->eo_dev, static_cast<size_t>(kMaxN + 1) * EO_NTAB * 2 * kEOSlot * sizeof(double),
                        "even-odd tables");
@@ -236,7 +250,17 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
             break;
         }
         st = upload_eo(*p, g.n, EO_APPLY_A, tab, cnt);
+        if (st != TP_OK || g.n > kLaneMaxN) continue;
+        // plain factors for the lane-per-block kernels (2 n^2 <= kEOSlot for n <= 4)
+        const int n2 = g.n * g.n;
+        static_assert(2 * kLaneMaxN * kLaneMaxN <= kEOSlot, "plain tables exceed a slot");
+        for (int i = 0; i < n2; ++i) tab[i] = r.M[i], tab[n2 + i] = r.K[i];
+        st = upload_eo(*p, g.n, EO_PLAIN_K, tab, 2 * n2);
+        if (st != TP_OK) break;
+        for (int i = 0; i < n2; ++i) tab[n2 + i] = r.A[i];
+        st = upload_eo(*p, g.n, EO_PLAIN_A, tab, 2 * n2);
     }
+    if (st == TP_OK) st = persistent_setup(*p);
     if (st != TP_OK) {
         free_plan_memory(p);
         delete p;
@@ -263,9 +287,10 @@ tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dty
     if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
     if (plan->vec_elems > 0 && (!u || !v)) return set_error(TP_ERR_ARG, "u and v must be non-null");
     if (u == v && u) return set_error(TP_ERR_ARG, "u and v must not alias");
+    if (plan->persistent) return launch_apply_persistent(*plan, op, u, v, dtype, stream);
     for (const auto& g : plan->groups) {
         const RefData& r = plan->ref[g.n];
-        tp_status st = g.n <= kLaneMaxN ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
+        tp_status st = use_lane(*plan, g) ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
                                         : launch_apply_eo(*plan, g, op, u, v, dtype, stream);
         if (st != TP_OK) return st;
     }
@@ -297,6 +322,13 @@ tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, d
                                                      " are not split into symmetric and antisymmetric ones");
         tp_status st = upload_eo(*plan, n, EO_INV, tab, cnt);
         if (st != TP_OK) return st;
+        if (n <= kLaneMaxN) {  // plain factors for the lane-per-block kernels
+            static_assert(kLaneMaxN * kLaneMaxN + kLaneMaxN <= kEOSlot, "plain tables exceed a slot");
+            for (int i = 0; i < n * n; ++i) tab[i] = r.S[i];
+            for (int i = 0; i < n; ++i) tab[n * n + i] = r.lam[i];
+            st = upload_eo(*plan, n, EO_PLAIN_S, tab, n * n + n);
+            if (st != TP_OK) return st;
+        }
         r.eig_ready = true;
     }
     plan->inverse_op = op;
@@ -309,8 +341,9 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
     if (plan->inverse_op < 0) return set_error(TP_ERR_STATE, "tp_setup_inverse has not succeeded on this plan");
     if (plan->vec_elems > 0 && (!r || !x)) return set_error(TP_ERR_ARG, "r and x must be non-null");
     if (r == x && r) return set_error(TP_ERR_ARG, "r and x must not alias");
+    if (plan->persistent) return launch_inverse_persistent(*plan, r, x, dtype, stream);
     for (const auto& g : plan->groups) {
-        tp_status st = g.n <= kLaneMaxN ? launch_inverse(*plan, g, r, x, dtype, stream)
+        tp_status st = use_lane(*plan, g) ? launch_inverse(*plan, g, r, x, dtype, stream)
                                         : launch_inverse_eo(*plan, g, r, x, dtype, stream);
         if (st != TP_OK) return st;
     }
@@ -329,12 +362,21 @@ tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, do
     if (plan->vec_elems > 0 && (!b || !x)) return set_error(TP_ERR_ARG, "b and x must be non-null");
     if (static_cast<const void*>(b) == static_cast<const void*>(x) && b)
         return set_error(TP_ERR_ARG, "b and x must not alias");
-    tp_status st = launch_summary_reset(plan->summary_dev, stream);
-    if (st != TP_OK) return st;
-    for (const auto& g : plan->groups) {
-        st = launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, stream);
+    tp_status st = TP_OK;
+    int64_t nparts = 0;
+    if (plan->persistent) {
+        st = launch_solve_persistent(*plan, b, x, inner, rtol, maxit, iters, relres, &nparts, stream);
         if (st != TP_OK) return st;
+    } else {
+        for (const auto& g : plan->groups) {
+            int64_t np = 0;
+            st = launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream);
+            if (st != TP_OK) return st;
+            nparts += np;
+        }
     }
+    st = launch_summary_reduce(*plan, nparts, stream);
+    if (st != TP_OK) return st;
     if (summary) {
         SolveSummary hs;
         hipError_t e = hipMemcpyAsync(&hs, plan->summary_dev, sizeof(hs), hipMemcpyDeviceToHost, stream);
@@ -350,6 +392,99 @@ tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, do
         if (hs.n_failed > 0)
             return set_error(TP_ERR_NOT_CONVERGED, std::to_string(hs.n_failed) + " blocks missed rtol");
     }
+    return TP_OK;
+}
+
+tp_status tp_solve_summary_fetch(tp_plan* plan, tp_solve_summary* summary, hipStream_t stream) {
+    if (!plan || !summary) return set_error(TP_ERR_ARG, "plan and summary must be non-null");
+    SolveSummary hs;
+    hipError_t e = hipMemcpyAsync(&hs, plan->summary_dev, sizeof(hs), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_error(e, "solve summary readback");
+    summary->max_iters = hs.max_iters;
+    summary->n_failed = hs.n_failed;
+    double mr;
+    std::memcpy(&mr, &hs.max_relres_bits, sizeof(mr));
+    summary->max_relres = mr;
+    if (hs.nonfinite > 0)
+        return set_error(TP_ERR_NONFINITE, std::to_string(hs.nonfinite) + " blocks had a non-finite residual");
+    if (hs.n_failed > 0) return set_error(TP_ERR_NOT_CONVERGED, std::to_string(hs.n_failed) + " blocks missed rtol");
+    return TP_OK;
+}
+
+tp_status tp_graph_create(tp_plan* plan, tp_graph_op what, tp_operator op, tp_dtype dtype, const void* in,
+                          void* out, double rtol, int32_t maxit, int32_t* iters, double* relres, tp_graph** graph) {
+    if (!plan || !graph) return set_error(TP_ERR_ARG, "plan and graph must be non-null");
+    *graph = nullptr;
+    if (what < TP_GRAPH_APPLY || what > TP_GRAPH_SOLVE) return set_error(TP_ERR_ARG, "invalid graph op");
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_error(e, "capture stream");
+    // one untimed call first so that per-kernel launch parameters are cached
+    // outside the capture
+    tp_status st = TP_OK;
+    auto record = [&](hipStream_t s) -> tp_status {
+        switch (what) {
+            case TP_GRAPH_APPLY: return tp_apply(plan, op, in, out, dtype, s);
+            case TP_GRAPH_INVERSE: return tp_apply_inverse(plan, in, out, dtype, s);
+            case TP_GRAPH_SOLVE:
+                return tp_solve(plan, static_cast<const double*>(in), static_cast<double*>(out), dtype, rtol, maxit,
+                                iters, relres, nullptr, s);
+        }
+        return set_error(TP_ERR_ARG, "invalid graph op");
+    };
+    st = record(cs);
+    if (st == TP_OK) {
+        e = hipStreamSynchronize(cs);
+        if (e != hipSuccess) st = hip_error(e, "warm-up call");
+    }
+    tp_graph* g = nullptr;
+    if (st == TP_OK) {
+        g = new (std::nothrow) tp_graph();
+        if (!g) st = set_error(TP_ERR_OOM, "host allocation failed");
+    }
+    if (st == TP_OK) {
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) st = hip_error(e, "hipStreamBeginCapture");
+    }
+    if (st == TP_OK) {
+        tp_status rs = record(cs);
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(cs, &gr);
+        if (rs != TP_OK) st = rs;
+        else if (e != hipSuccess) st = hip_error(e, "hipStreamEndCapture");
+        g->graph = gr;
+        if (st != TP_OK && gr) (void)hipGraphDestroy(gr), g->graph = nullptr;
+    }
+    if (st == TP_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = hip_error(e, "hipGraphInstantiate");
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != TP_OK) {
+        if (g) {
+            if (g->exec) (void)hipGraphExecDestroy(g->exec);
+            if (g->graph) (void)hipGraphDestroy(g->graph);
+            delete g;
+        }
+        return st;
+    }
+    *graph = g;
+    return TP_OK;
+}
+
+tp_status tp_graph_launch(tp_graph* graph, hipStream_t stream) {
+    if (!graph || !graph->exec) return set_error(TP_ERR_ARG, "graph is null");
+    hipError_t e = hipGraphLaunch(graph->exec, stream);
+    if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+    return TP_OK;
+}
+
+tp_status tp_graph_destroy(tp_graph* graph) {
+    if (!graph) return TP_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
     return TP_OK;
 }
 

@@ -19,190 +19,11 @@
 #include <climits>
 #include <type_traits>
 
-#include "device.h"
+#include "eo.h"
 
 namespace tpfdm {
 
 namespace {
-
-template <int N>
-struct EOShape {
-    static constexpr int H = N / 2;
-    static constexpr int HC = (N + 1) / 2;
-    static constexpr int SE = HC * HC;
-    static constexpr int SO = H * H;
-};
-
-// e, o parts of a pencil.
-template <int N, typename T>
-__device__ __forceinline__ void eo_split(const T (&x)[N], T (&e)[EOShape<N>::HC], T (&o)[EOShape<N>::H]) {
-    constexpr int H = EOShape<N>::H;
-#pragma unroll
-    for (int j = 0; j < H; ++j) {
-        e[j] = x[j] + x[N - 1 - j];
-        o[j] = x[j] - x[N - 1 - j];
-    }
-    if constexpr (N % 2 == 1) e[H] = x[H];
-}
-
-// E = AE e (HC outputs), O = AO o (H outputs); matrices row-major.
-template <int N, typename T>
-__device__ __forceinline__ void eo_mul(const T* AE, const T* AO, const T (&e)[EOShape<N>::HC],
-                                       const T (&o)[EOShape<N>::H], T (&E)[EOShape<N>::HC],
-                                       T (&O)[EOShape<N>::H]) {
-    constexpr int H = EOShape<N>::H, HC = EOShape<N>::HC;
-#pragma unroll
-    for (int i = 0; i < HC; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int j = 0; j < HC; ++j) s = fma(AE[i * HC + j], e[j], s);
-        E[i] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-        T s = T(0);
-#pragma unroll
-        for (int j = 0; j < H; ++j) s = fma(AO[i * H + j], o[j], s);
-        O[i] = s;
-    }
-}
-
-template <int N, typename T>
-__device__ __forceinline__ void eo_join(const T (&E)[EOShape<N>::HC], const T (&O)[EOShape<N>::H], T (&y)[N]) {
-    constexpr int H = EOShape<N>::H;
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-        y[i] = E[i] + O[i];
-        y[N - 1 - i] = E[i] - O[i];
-    }
-    if constexpr (N % 2 == 1) y[H] = E[H];
-}
-
-// Forward spectral transform y = S^T x along a pencil: the first HC outputs
-// are the coefficients of the symmetric eigenvectors, the last H those of
-// the antisymmetric ones (SE[k][c] = S[k][sym c] for k < HC, SO likewise).
-template <int N, typename T>
-__device__ __forceinline__ void eo_fwd(const T* SE, const T* SO, const T (&x)[N], T (&y)[N]) {
-    constexpr int H = EOShape<N>::H, HC = EOShape<N>::HC;
-    T e[HC], o[H];
-    eo_split<N>(x, e, o);
-#pragma unroll
-    for (int c = 0; c < HC; ++c) {
-        T s = T(0);
-#pragma unroll
-        for (int k = 0; k < HC; ++k) s = fma(SE[k * HC + c], e[k], s);
-        y[c] = s;
-    }
-#pragma unroll
-    for (int c = 0; c < H; ++c) {
-        T s = T(0);
-#pragma unroll
-        for (int k = 0; k < H; ++k) s = fma(SO[k * H + c], o[k], s);
-        y[HC + c] = s;
-    }
-}
-
-// Backward transform x = S y (y in the split spectral order of eo_fwd).
-template <int N, typename T>
-__device__ __forceinline__ void eo_bwd(const T* SE, const T* SO, const T (&y)[N], T (&x)[N]) {
-    constexpr int H = EOShape<N>::H, HC = EOShape<N>::HC;
-    T E[HC], O[H];
-#pragma unroll
-    for (int k = 0; k < HC; ++k) {
-        T s = T(0);
-#pragma unroll
-        for (int c = 0; c < HC; ++c) s = fma(SE[k * HC + c], y[c], s);
-        E[k] = s;
-    }
-#pragma unroll
-    for (int k = 0; k < H; ++k) {
-        T s = T(0);
-#pragma unroll
-        for (int c = 0; c < H; ++c) s = fma(SO[k * H + c], y[HC + c], s);
-        O[k] = s;
-    }
-    eo_join<N>(E, O, x);
-}
-
-// ------------------------------------------------------------ pencil I/O
-// Lane (w, i, j) of a tile owns the z-pencil (i, j, 0..n-1) of block w.  For
-// the block-contiguous layout (B = 1) a pencil is n consecutive elements and
-// is moved with 16-byte vector accesses when the address allows it.
-template <int N, typename TS>
-__device__ __forceinline__ const TS* pencil_ptr(const TS* base, const GArgs& G, int64_t g, int i, int j) {
-    return base + G.offset + block_base(g, G.logB, N * N * N) + (static_cast<int64_t>((i * N + j) * N) << G.logB);
-}
-
-// 16 bytes of storage elements.
-template <typename TS>
-union Pack16 {
-    static constexpr int n = 16 / static_cast<int>(sizeof(TS));
-    uint4 u;
-    TS s[16 / sizeof(TS)];
-};
-
-// With VP the caller guarantees B = 1 and 16-byte aligned pencils.
-template <int N, bool VP, typename TS, typename TC>
-__device__ __forceinline__ void pencil_load(TC (&x)[N], const TS* __restrict__ p, int logB) {
-    constexpr int VEC = Pack16<TS>::n;
-    if constexpr (VP && N % VEC == 0) {
-        {
-            const uint4* vp = reinterpret_cast<const uint4*>(p);
-#pragma unroll
-            for (int c = 0; c < N / VEC; ++c) {
-                Pack16<TS> pk;
-                pk.u = vp[c];
-#pragma unroll
-                for (int l = 0; l < VEC; ++l) x[c * VEC + l] = ldc<TC>(&pk.s[l]);
-            }
-            return;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < N; ++k) x[k] = ldc<TC>(p + (static_cast<int64_t>(k) << logB));
-}
-
-template <int N, bool VP, typename TS, typename TC>
-__device__ __forceinline__ void pencil_store(TS* __restrict__ p, const TC (&x)[N], int logB) {
-    constexpr int VEC = Pack16<TS>::n;
-    if constexpr (VP && N % VEC == 0) {
-        {
-            uint4* vp = reinterpret_cast<uint4*>(p);
-#pragma unroll
-            for (int c = 0; c < N / VEC; ++c) {
-                Pack16<TS> pk;
-#pragma unroll
-                for (int l = 0; l < VEC; ++l) stc(&pk.s[l], x[c * VEC + l]);
-                vp[c] = pk.u;
-            }
-            return;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < N; ++k) stc(p + (static_cast<int64_t>(k) << logB), x[k]);
-}
-
-template <int N>
-__device__ __forceinline__ int nvalid_of(const GArgs& G, int64_t t) {
-    const int64_t g0 = t * Slab<N>::BPW;
-    return static_cast<int>(G.nblocks - g0 < Slab<N>::BPW ? G.nblocks - g0 : Slab<N>::BPW);
-}
-
-// Loads the 1D factor table into registers.  FP64 tables go through LDS so
-// that they land in VGPRs; FP32 tables are read with wave-uniform addresses
-// and stay in scalar registers.
-template <typename TC, int COUNT>
-__device__ __forceinline__ void load_table(TC (&dst)[COUNT], const TC* __restrict__ tab, TC* stab) {
-    if constexpr (sizeof(TC) == 8) {
-        for (int e = threadIdx.x; e < COUNT; e += 64) stab[e] = tab[e];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < COUNT; ++i) dst[i] = stab[i];
-    } else {
-#pragma unroll
-        for (int i = 0; i < COUNT; ++i) dst[i] = tab[i];
-    }
-}
 
 // v = A u.  Table: ME | MO | PE | PO.
 // Per tile: z-phase from the prefetched pencil registers, y-phase and
@@ -248,63 +69,7 @@ __global__ __launch_bounds__(64, 2) void k_apply_eo(const TS* __restrict__ u, TS
             pencil_load<N, VP>(pre, pencil_ptr<N>(u, G, tn * L::BPW + lw, li, lj), G.logB);
         TC sx = TC(1), sy = TC(1), sz = TC(1);
         if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
-        const int pa = pc.pa, pb = pc.pb;
-        if (pc.act) {  // z: lane (i, j); t = M x, w = P x
-            TC e[HC], o[H], E[HC], O[H], y[N];
-            eo_split<N>(x, e, o);
-            eo_mul<N>(ME, MO, e, o, E, O);
-            eo_join<N>(E, O, y);
-#pragma unroll
-            for (int k = 0; k < N; ++k) A1[L::at(pa, pb, k)] = y[k];
-            eo_mul<N>(PE, PO, e, o, E, O);
-            eo_join<N>(E, O, y);
-#pragma unroll
-            for (int k = 0; k < N; ++k) A2[L::at(pa, pb, k)] = y[k];
-        }
-        __syncthreads();
-        if (pc.act) {  // y: lane (i, k); a = s_x M t, b = s_y P t + s_z M w
-            TC et[HC], ot[H], ew[HC], ow[H], E[HC], O[H], E2[HC], O2[H], y[N];
-#pragma unroll
-            for (int j = 0; j < N; ++j) y[j] = A1[L::at(pa, j, pb)];
-            eo_split<N>(y, et, ot);
-#pragma unroll
-            for (int j = 0; j < N; ++j) y[j] = A2[L::at(pa, j, pb)];
-            eo_split<N>(y, ew, ow);
-            eo_mul<N>(ME, MO, et, ot, E, O);
-            eo_join<N>(E, O, y);
-#pragma unroll
-            for (int j = 0; j < N; ++j) A1[L::at(pa, j, pb)] = y[j] * sx;
-            eo_mul<N>(PE, PO, et, ot, E, O);
-            eo_mul<N>(ME, MO, ew, ow, E2, O2);
-#pragma unroll
-            for (int i = 0; i < HC; ++i) E[i] = fma(sy, E[i], sz * E2[i]);
-#pragma unroll
-            for (int i = 0; i < H; ++i) O[i] = fma(sy, O[i], sz * O2[i]);
-            eo_join<N>(E, O, y);
-#pragma unroll
-            for (int j = 0; j < N; ++j) A2[L::at(pa, j, pb)] = y[j];
-        }
-        __syncthreads();
-        if (pc.act) {  // x: lane (j, k); v = P a + M b, stored to global
-            TC y[N], ea[HC], oa[H], eb[HC], ob[H], E[HC], O[H], E2[HC], O2[H];
-#pragma unroll
-            for (int i = 0; i < N; ++i) y[i] = A1[L::at(i, pa, pb)];
-            eo_split<N>(y, ea, oa);
-#pragma unroll
-            for (int i = 0; i < N; ++i) y[i] = A2[L::at(i, pa, pb)];
-            eo_split<N>(y, eb, ob);
-            eo_mul<N>(PE, PO, ea, oa, E, O);
-            eo_mul<N>(ME, MO, eb, ob, E2, O2);
-#pragma unroll
-            for (int i = 0; i < HC; ++i) E[i] += E2[i];
-#pragma unroll
-            for (int i = 0; i < H; ++i) O[i] += O2[i];
-            eo_join<N>(E, O, y);
-            TS* out = v + G.offset + block_base(g0 + pc.w, G.logB, L::N3);
-#pragma unroll
-            for (int i = 0; i < N; ++i) stc(out + (static_cast<int64_t>((i * N + pa) * N + pb) << G.logB), y[i]);
-        }
-        __syncthreads();
+        eo_apply_body<N>(pc, x, v, G, g0, A1, A2, ME, MO, PE, PO, sx, sy, sz);
     }
 }
 
@@ -354,54 +119,32 @@ __global__ __launch_bounds__(64, 2) void k_inverse_eo(const TS* __restrict__ r, 
             pencil_load<N, VP>(pre, pencil_ptr<N>(r, G, tn * L::BPW + lw, li, lj), G.logB);
         TC sx = TC(1), sy = TC(1), sz = TC(1);
         if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
-        const int pa = pc.pa, pb = pc.pb;
-        if (pc.act) {  // z forward: lane (i, j)
-            TC y[N];
-            eo_fwd<N>(SE, SO, xin, y);
-#pragma unroll
-            for (int c = 0; c < N; ++c) A1[L::at(pa, pb, c)] = y[c];
-        }
-        __syncthreads();
-        if (pc.act) {  // y forward: lane (i, c)
-            TC a[N], y[N];
-#pragma unroll
-            for (int j = 0; j < N; ++j) a[j] = A1[L::at(pa, j, pb)];
-            eo_fwd<N>(SE, SO, a, y);
-#pragma unroll
-            for (int b = 0; b < N; ++b) A1[L::at(pa, b, pb)] = y[b];
-        }
-        __syncthreads();
-        if (pc.act) {  // x forward, scale, x backward: lane (b, c)
-            TC a[N], y[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) a[i] = A1[L::at(i, pa, pb)];
-            eo_fwd<N>(SE, SO, a, y);
-            const TC mu_bc = lam[pa] * sy + lam[pb] * sz;
-#pragma unroll
-            for (int c = 0; c < N; ++c) y[c] *= recip(fma(lam[c], sx, mu_bc));
-            eo_bwd<N>(SE, SO, y, a);
-#pragma unroll
-            for (int i = 0; i < N; ++i) A1[L::at(i, pa, pb)] = a[i];
-        }
-        __syncthreads();
-        if (pc.act) {  // y backward: lane (i, c)
-            TC y[N], a[N];
-#pragma unroll
-            for (int b = 0; b < N; ++b) y[b] = A1[L::at(pa, b, pb)];
-            eo_bwd<N>(SE, SO, y, a);
-#pragma unroll
-            for (int j = 0; j < N; ++j) A1[L::at(pa, j, pb)] = a[j];
-        }
-        __syncthreads();
-        if (pc.act) {  // z backward: lane (i, j), pencil stored to global
-            TC y[N], a[N];
-#pragma unroll
-            for (int c = 0; c < N; ++c) y[c] = A1[L::at(pa, pb, c)];
-            eo_bwd<N>(SE, SO, y, a);
-            pencil_store<N, VP>(const_cast<TS*>(pencil_ptr<N>(x, G, g0 + pc.w, pa, pb)), a, G.logB);
-        }
-        __syncthreads();
+        eo_inverse_body<N, VP>(pc, xin, x, G, g0, A1, SE, SO, lam, sx, sy, sz);
     }
+}
+
+// Block-local iterative refinement over all tiles of a group (persistent grid).
+template <int N, typename TI>
+__global__ __launch_bounds__(64, 2) void k_solve_eo(const double* __restrict__ b, double* __restrict__ x, GArgs G,
+                                                    const double* __restrict__ tabA, const TI* __restrict__ tabS,
+                                                    int64_t ntiles, double rtol, int maxit,
+                                                    int32_t* __restrict__ iters, double* __restrict__ relres,
+                                                    int64_t block0, SolvePartial* parts) {
+    using L = Slab<N>;
+    using S = EOShape<N>;
+    __shared__ SolveLds<N, TI> lds;
+    __shared__ double stabA[ApplyTab<N, double>::COUNT];
+    __shared__ TI stabS[S::SE + S::SO + N];
+    ApplyTab<N, double> A;
+    InvTab<N, TI> I;
+    table_to_regs(A.v, tabA, stabA, ApplyTab<N, double>::COUNT);
+    table_to_regs<TI, InvTab<N, TI>::COUNT, false>(I.v, tabS, stabS, S::SE + S::SO + N);
+    const TI* lam = stabS + S::SE + S::SO;
+    SolveAcc acc;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+        eo_solve_tile<N, TI>(b, x, G, t * L::BPW, nvalid_of<N>(G, t), lds, A.ME(), A.MO(), A.PE(), A.PO(), I.SE(),
+                             I.SO(), lam, rtol, maxit, iters, relres, block0, acc);
+    acc.flush(parts + blockIdx.x);
 }
 
 tp_status check(const char* what) {
@@ -476,6 +219,39 @@ tp_status inverse_eo_n(const Plan& plan, const GroupInfo& g, const void* r, void
     return check("apply_inverse (even-odd) launch");
 }
 
+template <int N, typename TI>
+tp_status solve_eo_n(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol, int maxit,
+                     int32_t* iters, double* relres, int64_t part_base, int64_t* nparts, hipStream_t s) {
+    const int64_t ntiles = eo_tiles<N>(g);
+    const double* tabA = reinterpret_cast<const double*>(eo_table(plan, N, EO_APPLY_A, 0));
+    const TI* tabS = reinterpret_cast<const TI*>(eo_table(plan, N, EO_INV, sizeof(TI) == 8 ? 0 : 1));
+    GArgs a{g.h, g.nblocks, g.offset, g.logB};
+    static int64_t gc = 0;
+    if (gc == 0) gc = persistent_grid(plan, reinterpret_cast<const void*>(&k_solve_eo<N, TI>), INT64_MAX);
+    const int64_t grid = std::min(gc, ntiles);
+    if (part_base + grid > plan.partials_cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
+    *nparts = grid;
+    hipLaunchKernelGGL((k_solve_eo<N, TI>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x, a, tabA, tabS,
+                       ntiles, rtol, maxit, iters, relres, g.block0,
+                       static_cast<SolvePartial*>(plan.partials_dev) + part_base);
+    return check("solve launch");
+}
+
+template <typename TI>
+tp_status solve_eo_dispatch(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol,
+                            int maxit, int32_t* iters, double* relres, int64_t pb, int64_t* np, hipStream_t s) {
+    switch (g.n) {
+        case 2: return solve_eo_n<2, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 3: return solve_eo_n<3, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 4: return solve_eo_n<4, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 5: return solve_eo_n<5, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 6: return solve_eo_n<6, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 7: return solve_eo_n<7, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 8: return solve_eo_n<8, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+    }
+    return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
+}
+
 template <typename TS, typename TC>
 tp_status apply_eo_dispatch(const Plan& plan, const GroupInfo& g, int op, const void* u, void* v, hipStream_t s) {
     switch (g.n) {
@@ -516,6 +292,19 @@ tp_status launch_apply_eo(const Plan& plan, const GroupInfo& g, int op, const vo
         case TP_BF16: return apply_eo_dispatch<bf16_t, float>(plan, g, op, u, v, s);
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported dtype");
+}
+
+tp_status launch_solve(const Plan& plan, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
+                       double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base, int64_t* nparts,
+                       hipStream_t s) {
+    *nparts = 0;
+    if (g.nblocks == 0) return TP_OK;
+    switch (inner) {
+        case TP_F64: return solve_eo_dispatch<double>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case TP_F32: return solve_eo_dispatch<float>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        default: break;
+    }
+    return set_error(TP_ERR_UNSUPPORTED, "solve inner precision must be TP_F64 or TP_F32");
 }
 
 tp_status launch_inverse_eo(const Plan& plan, const GroupInfo& g, const void* r, void* x, tp_dtype dt,

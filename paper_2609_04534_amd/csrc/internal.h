@@ -26,7 +26,9 @@ int gen_eigen(int n, const double* M, const double* P, double* S, double* lam);
 //   EO_APPLY_K / EO_APPLY_A:  ME[hc][hc] | MO[h][h] | PE[hc][hc] | PO[h][h]
 //   EO_INV:                   SE[hc][hc] | SO[h][h] | lam[n] (split order)
 // with h = n/2, hc = (n+1)/2.  Element type 0 = double, 1 = float.
-enum { EO_APPLY_K = 0, EO_APPLY_A = 1, EO_INV = 2, EO_NTAB = 3 };
+//   EO_PLAIN_K / EO_PLAIN_A:  M[n][n] | P[n][n]   (plain, for the lane kernels)
+//   EO_PLAIN_S:               S[n][n] | lam[n]
+enum { EO_APPLY_K = 0, EO_APPLY_A = 1, EO_INV = 2, EO_PLAIN_K = 3, EO_PLAIN_A = 4, EO_PLAIN_S = 5, EO_NTAB = 6 };
 constexpr int kEOSlot = 64;
 // Builds ME|MO|PE|PO from centrosymmetric M and P; false when either is not.
 bool build_eo_apply(int n, const double* M, const double* P, double* out);
@@ -69,6 +71,7 @@ struct Plan {
     int device = 0;
     double penalty_C = 2.0;
     bool persistent = false;
+    int mapping = 0;
     std::vector<GroupInfo> groups;
     RefData ref[kMaxN + 1];
     int inverse_op = -1;
@@ -76,8 +79,10 @@ struct Plan {
     int64_t ndof = 0;
     int64_t nblocks = 0;
     // device workspace
-    void* summary_dev = nullptr;   // solve summary counters
-    GroupInfo* groups_dev = nullptr;
+    void* summary_dev = nullptr;   // solve summary of the last solve
+    void* partials_dev = nullptr;  // SolvePartial per workgroup of the last solve
+    int64_t partials_cap = 0;
+    void* segs_dev = nullptr;      // persistent-kernel segment table (one per group)
     void* eo_dev = nullptr;        // even-odd tables, (kMaxN+1) x EO_NTAB x 2 slots
     int64_t wave_grid = 2048;      // persistent grid of the wave kernels
     int cus = 256;                 // compute units of the plan's device
@@ -85,7 +90,18 @@ struct Plan {
     int64_t nitems = 0;
 };
 
-// Device-side solve summary, reset by a fill kernel before every solve.
+// Per-workgroup partial summary of a solve launch (plain stores, no atomics).
+struct SolvePartial {
+    int max_iters;
+    int n_failed;
+    int nonfinite;
+    int pad;
+    double max_relres;
+};
+// Maximum one-wave workgroups resident per CU (sizes the partials array).
+constexpr int kMaxWgPerCu = 32;
+
+// Device-side solve summary, written by the reduction kernel after a solve.
 struct SolveSummary {
     int max_iters;
     int n_failed;
@@ -104,9 +120,11 @@ tp_status launch_apply(const Plan& plan, const GroupInfo& g, const double* Pm, c
                        void* v, tp_dtype dt, hipStream_t s);
 tp_status launch_inverse(const Plan& plan, const GroupInfo& g, const void* r, void* x,
                          tp_dtype dt, hipStream_t s);
+// Solve launchers write one SolvePartial per workgroup starting at
+// partials + part_base and report the number written in *nparts.
 tp_status launch_solve(const Plan& plan, const GroupInfo& g, const double* b, double* x,
                        tp_dtype inner, double rtol, int maxit, int32_t* iters,
-                       double* relres, hipStream_t s);
+                       double* relres, int64_t part_base, int64_t* nparts, hipStream_t s);
 // to_blocked: src canonical -> dst blocked; otherwise src blocked -> dst canonical
 tp_status launch_apply_eo(const Plan& plan, const GroupInfo& g, int op, const void* u, void* v,
                           tp_dtype dt, hipStream_t s);
@@ -117,8 +135,14 @@ inline const void* eo_table(const Plan& plan, int n, int tab, int et) {
            static_cast<size_t>(((n * EO_NTAB + tab) * 2 + et) * kEOSlot) * sizeof(double);
 }
 tp_status upload_eo(Plan& plan, int n, int tab, const double* vals, int count);
+// Persistent single-launch paths over all groups of a plan.
+tp_status persistent_setup(Plan& plan);
+tp_status launch_apply_persistent(const Plan& plan, int op, const void* u, void* v, tp_dtype dt, hipStream_t s);
+tp_status launch_inverse_persistent(const Plan& plan, const void* r, void* x, tp_dtype dt, hipStream_t s);
+tp_status launch_solve_persistent(const Plan& plan, const double* b, double* x, tp_dtype inner, double rtol,
+                                  int maxit, int32_t* iters, double* relres, int64_t* nparts, hipStream_t s);
 tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize,
                       bool to_blocked, hipStream_t s);
-tp_status launch_summary_reset(void* summary_dev, hipStream_t s);
+tp_status launch_summary_reduce(const Plan& plan, int64_t nparts, hipStream_t s);
 
 }  // namespace tpfdm

@@ -26,14 +26,17 @@ F64, F32, F16, BF16 = 0, 1, 2, 3
 DTYPE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 OP_NEUMANN, OP_CELL = 0, 1
 FACTOR_SCALED = 0
+MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 
 # The public symbol set declared in include/tpfdm.h.
 EXPORTS = (
     "tp_plan_opts_default", "tp_plan_create", "tp_plan_destroy", "tp_plan_vector_elems",
     "tp_plan_ndof", "tp_plan_nblocks", "tp_apply", "tp_setup_inverse", "tp_apply_inverse",
     "tp_solve", "tp_pack", "tp_unpack", "tp_reference_matrices", "tp_reference_eigen",
-    "tp_last_error", "tp_version",
+    "tp_last_error", "tp_version", "tp_solve_summary_fetch", "tp_graph_create", "tp_graph_launch",
+    "tp_graph_destroy",
 )
+GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
 
 
 class TpfdmError(RuntimeError):
@@ -50,7 +53,7 @@ class _Group(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("penalty_C", ctypes.c_double), ("persistent", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("mapping", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class _Summary(ctypes.Structure):
@@ -86,6 +89,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_reference_matrices": (i32, [i32, dbl, vp, vp, vp]),
         "tp_reference_eigen": (i32, [i32, dbl, i32, vp, vp]),
         "tp_last_error": (ctypes.c_char_p, []),
+        "tp_solve_summary_fetch": (i32, [vp, ctypes.POINTER(_Summary), vp]),
+        "tp_graph_create": (i32, [vp, i32, i32, i32, vp, vp, dbl, i32, vp, vp, ctypes.POINTER(vp)]),
+        "tp_graph_launch": (i32, [vp, vp]),
+        "tp_graph_destroy": (i32, [vp]),
         "tp_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -168,7 +175,7 @@ def default_layout_B(n: int) -> int:
 class Plan:
     """Owning wrapper of a tp_plan."""
 
-    def __init__(self, groups, penalty_C: float = 2.0, persistent: bool = False):
+    def __init__(self, groups, penalty_C: float = 2.0, persistent: bool = False, mapping: int = MAP_AUTO):
         lib = load()
         self._keep = []
         arr = (_Group * max(1, len(groups)))()
@@ -196,6 +203,7 @@ class Plan:
         lib.tp_plan_opts_default(ctypes.byref(opts))
         opts.penalty_C = penalty_C
         opts.persistent = 1 if persistent else 0
+        opts.mapping = mapping
         handle = ctypes.c_void_p()
         _check(lib.tp_plan_create(arr, len(groups), ctypes.byref(opts), ctypes.byref(handle)))
         self._h = handle
@@ -243,6 +251,25 @@ class Plan:
         return {"status": STATUS[st], "max_iters": s.max_iters, "n_failed": s.n_failed,
                 "max_relres": s.max_relres}
 
+    def solve_summary(self, stream=None, raise_on_failure: bool = False):
+        """Summary of the most recent solve (also one replayed from a graph)."""
+        s = _Summary()
+        st = load().tp_solve_summary_fetch(self.handle, ctypes.byref(s), _stream(stream))
+        if st != TP_OK and (raise_on_failure or st not in (-5, -6)):
+            _check(st)
+        return {"status": STATUS[st], "max_iters": s.max_iters, "n_failed": s.n_failed,
+                "max_relres": s.max_relres}
+
+    def graph(self, what: int, inp, out, op: int = OP_NEUMANN, dtype: int | None = None, rtol: float = 1e-10,
+              maxit: int = 50, iters=None, relres=None):
+        """Capture one call into a replayable HIP graph (see tp_graph_create)."""
+        if dtype is None:
+            dtype = torch_dtype_code(inp) if what != GRAPH_SOLVE else F32
+        h = ctypes.c_void_p()
+        _check(load().tp_graph_create(self.handle, what, op, dtype, _ptr(inp), _ptr(out), rtol, maxit,
+                                      _ptr(iters), _ptr(relres), ctypes.byref(h)))
+        return Graph(h, self)
+
     def pack(self, canonical, blocked, stream=None):
         _check(load().tp_pack(self.handle, _ptr(canonical), _ptr(blocked), torch_dtype_code(canonical),
                               _stream(stream)))
@@ -267,6 +294,28 @@ class Plan:
 
     def __exit__(self, *exc):
         self.destroy()
+
+
+class Graph:
+    """A captured call; launch() replays it on a stream."""
+
+    def __init__(self, handle, plan):
+        self._h = handle
+        self._plan = plan   # keeps the plan alive while the graph exists
+
+    def launch(self, stream=None):
+        _check(load().tp_graph_launch(self._h, _stream(stream)))
+
+    def destroy(self):
+        if self._h is not None:
+            load().tp_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def groups_for_workload(workload, layout_B=None):

@@ -105,6 +105,9 @@ def test_plan_argument_validation_before_device():
     opts.penalty_C = 2.0
     opts.reserved[3] = 1
     assert _create([(3, 64, 10, 0)], ctypes.byref(opts)) == -1
+    opts.reserved[3] = 0
+    opts.mapping = 3
+    assert _create([(3, 64, 10, 0)], ctypes.byref(opts)) == -1
 
 
 def test_null_plan_calls_fail_cleanly():

@@ -359,3 +359,104 @@ def test_solve_requires_cell_setup():
         with pytest.raises(tpfdm.TpfdmError) as e:
             plan.solve(buf, torch.zeros_like(buf))
         assert e.value.status == -9
+
+
+# ------------------------------------------------------------------ persistent + graphs
+MIXED_DEGREES = (1, 2, 3, 4, 5, 6, 7)
+
+
+def _mixed(nblocks=700, seed=21):
+    return workloads.mixed_degree_workload("mixed_test", nblocks, MIXED_DEGREES, (0.5, 2.0), seed=seed,
+                                           with_rhs=True)
+
+
+@pytest.mark.parametrize("dt", [tpfdm.F64, tpfdm.F32, tpfdm.F16, tpfdm.BF16])
+def test_persistent_equals_per_group_launches(dt):
+    """One persistent launch over all degrees gives bitwise the per-group results."""
+    wl = _mixed()
+    flat = canon([g.u for g in wl.groups])
+    outs = {}
+    for persistent in (False, True):
+        with make_plan(wl, persistent=persistent) as plan:
+            plan.setup_inverse()
+            a, _ = gpu_apply(plan, flat, dt, tpfdm.OP_NEUMANN)
+            c, _ = gpu_apply(plan, flat, dt, tpfdm.OP_CELL)
+            i, _ = gpu_inverse(plan, flat, dt)
+            outs[persistent] = (a, c, i)
+    for k in range(3):
+        assert np.array_equal(outs[False][k], outs[True][k]), k
+
+
+def test_persistent_mixed_matches_oracle():
+    wl = _mixed(nblocks=300, seed=22)
+    with make_plan(wl, persistent=True) as plan:
+        plan.setup_inverse()
+        flat = canon([g.u for g in wl.groups])
+        a, _ = gpu_apply(plan, flat, tpfdm.F64, tpfdm.OP_NEUMANN)
+        i, _ = gpu_inverse(plan, flat, tpfdm.F64)
+    for g, ga, gi in zip(wl.groups, split(a, wl.groups), split(i, wl.groups)):
+        assert rel_err_blocks(ga, dense.apply(g.p, g.h, g.u, dense.NEUMANN)) < F64_TOL
+        assert rel_err_blocks(gi, dense.solve(g.p, g.h, g.u)) < F64_TOL
+
+
+@pytest.mark.parametrize("inner", [tpfdm.F64, tpfdm.F32])
+def test_persistent_solve_mixed(inner):
+    torch = _torch()
+    wl = _mixed(nblocks=300, seed=23)
+    res = {}
+    for persistent in (False, True):
+        with make_plan(wl, persistent=persistent) as plan:
+            plan.setup_inverse()
+            bb = to_blocked(plan, canon([g.b for g in wl.groups]), tpfdm.F64)
+            bx = torch.zeros_like(bb)
+            iters = torch.zeros(plan.nblocks, dtype=torch.int32, device="cuda")
+            s = plan.solve(bb, bx, inner=inner, rtol=1e-10, maxit=30, iters=iters)
+            res[persistent] = (from_blocked(plan, bx, tpfdm.F64), iters.cpu().numpy(), s)
+    assert np.array_equal(res[False][0], res[True][0])
+    assert np.array_equal(res[False][1], res[True][1])
+    assert res[True][2]["n_failed"] == 0
+    for g, gx in zip(wl.groups, split(res[True][0], wl.groups)):
+        ref = dense.solve(g.p, g.h, g.b)
+        kappa = max(dense.condition_number(g.p, h) for h in g.h[:3])
+        assert rel_err_blocks(gx, ref) < 4e-10 * kappa
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_graph_replay_matches_eager(persistent):
+    """Captured apply / inverse / solve graphs replayed several times, with
+    eager work and synchronisations in between, reproduce the eager results
+    bitwise on every replay."""
+    torch = _torch()
+    wl = _mixed(nblocks=400, seed=24)
+    with make_plan(wl, persistent=persistent) as plan:
+        plan.setup_inverse()
+        bu = to_blocked(plan, canon([g.u for g in wl.groups]), tpfdm.F32)
+        bb = to_blocked(plan, canon([g.b for g in wl.groups]), tpfdm.F64)
+        ref_v = torch.empty_like(bu)
+        ref_x = torch.empty_like(bu)
+        ref_s = torch.zeros_like(bb)
+        plan.apply(bu, ref_v, tpfdm.OP_NEUMANN)
+        plan.apply_inverse(bu, ref_x)
+        plan.solve(bb, ref_s, inner=tpfdm.F32, rtol=1e-10, maxit=30)
+        torch.cuda.synchronize()
+        gv, gx, gs = torch.empty_like(bu), torch.empty_like(bu), torch.zeros_like(bb)
+        graphs = [plan.graph(tpfdm.GRAPH_APPLY, bu, gv, op=tpfdm.OP_NEUMANN),
+                  plan.graph(tpfdm.GRAPH_INVERSE, bu, gx),
+                  plan.graph(tpfdm.GRAPH_SOLVE, bb, gs, dtype=tpfdm.F32, rtol=1e-10, maxit=30)]
+        for rep in range(4):
+            gv.fill_(float("nan"))
+            gx.fill_(float("nan"))
+            gs.zero_()
+            scratch = torch.empty_like(bu)
+            plan.apply(bu, scratch, tpfdm.OP_CELL)      # eager work between replays
+            torch.cuda.synchronize()
+            for g in graphs:
+                g.launch()
+            torch.cuda.synchronize()
+            # compare the blocks' entries (padding lanes are never written)
+            for got, ref, dt in ((gv, ref_v, tpfdm.F32), (gx, ref_x, tpfdm.F32), (gs, ref_s, tpfdm.F64)):
+                assert np.array_equal(from_blocked(plan, got, dt), from_blocked(plan, ref, dt)), rep
+            summ = plan.solve_summary()
+            assert summ["n_failed"] == 0 and summ["max_iters"] >= 1
+        for g in graphs:
+            g.destroy()
