@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--suite", action="store_true",
                     help="time apply / apply_inverse / solve for every workload and precision "
                          "(one JSON line per case) instead of the headline step")
+    ap.add_argument("--dtype", default=None, choices=["f64", "f32", "f16", "bf16"],
+                    help="storage precision of the step (default: the workload's)")
     ap.add_argument("--counters", action="store_true",
                     help="no timing: launch apply, apply_inverse and a plain device copy of one "
                          "vector 3 times each (for hardware-counter runs), then exit")
@@ -138,9 +140,12 @@ def main():
 
     _log(f"workload {args.workload}")
     wl, dtname = build_workload(args.workload)
-    dt = {"f64": tpfdm.F64, "f32": tpfdm.F32}[dtname]
-    tdt = {tpfdm.F64: torch.float64, tpfdm.F32: torch.float32}[dt]
-    esize = 8 if dt == tpfdm.F64 else 4
+    if args.dtype:
+        dtname = args.dtype
+    dt = {"f64": tpfdm.F64, "f32": tpfdm.F32, "f16": tpfdm.F16, "bf16": tpfdm.BF16}[dtname]
+    tdt = {tpfdm.F64: torch.float64, tpfdm.F32: torch.float32, tpfdm.F16: torch.float16,
+           tpfdm.BF16: torch.bfloat16}[dt]
+    esize = {tpfdm.F64: 8, tpfdm.F32: 4, tpfdm.F16: 2, tpfdm.BF16: 2}[dt]
     plan = tpfdm.Plan(tpfdm.groups_for_workload(wl))
     plan.setup_inverse(tpfdm.OP_CELL)
     ndof = plan.ndof

@@ -34,6 +34,9 @@ int esize_of(tp_dtype dt) {
 bool use_lane(const Plan& p, const GroupInfo& g) {
     return g.n <= kLaneMaxN && p.mapping != TP_MAP_WAVE;
 }
+bool use_mfma(const Plan& p, const GroupInfo& g, tp_dtype dt, const void* a, const void* b) {
+    return p.mapping != TP_MAP_WAVE && mfma_eligible(g, dt, a, b);
+}
 bool valid_dtype(int dt) { return dt >= TP_F64 && dt <= TP_BF16; }
 bool valid_op(int op) { return op == TP_OP_NEUMANN || op == TP_OP_CELL; }
 }  // namespace
@@ -55,6 +58,11 @@ static void free_plan_memory(Plan* p) {
     if (p->partials_dev) (void)hipFree(p->partials_dev), p->partials_dev = nullptr;
     if (p->segs_dev) (void)hipFree(p->segs_dev), p->segs_dev = nullptr;
     if (p->eo_dev) (void)hipFree(p->eo_dev), p->eo_dev = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        for (int j = 0; j < 2; ++j)
+            if (p->mfma_apply_dev[i][j]) (void)hipFree(p->mfma_apply_dev[i][j]), p->mfma_apply_dev[i][j] = nullptr;
+        if (p->mfma_inv_dev[i]) (void)hipFree(p->mfma_inv_dev[i]), p->mfma_inv_dev[i] = nullptr;
+    }
     if (p->items_dev) (void)hipFree(p->items_dev), p->items_dev = nullptr;
 }
 
@@ -261,6 +269,20 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
         st = upload_eo(*p, g.n, EO_PLAIN_A, tab, 2 * n2);
     }
     if (st == TP_OK) st = persistent_setup(*p);
+    if (st == TP_OK && p->ref[8].built) {  // MFMA operand tables of n = 8
+        const RefData& r8 = p->ref[8];
+        for (int op = 0; op < 2 && st == TP_OK; ++op)
+            for (int et = 0; et < 2 && st == TP_OK; ++et) {
+                std::vector<uint16_t> tabv;
+                build_mfma_tables(r8.M, op == 1 ? r8.A : r8.K, nullptr, nullptr, et == 1, &tabv, nullptr);
+                st = alloc_dev(&p->mfma_apply_dev[op][et], tabv.size() * 2, "MFMA tables");
+                if (st == TP_OK) {
+                    hipError_t he = hipMemcpy(p->mfma_apply_dev[op][et], tabv.data(), tabv.size() * 2,
+                                              hipMemcpyHostToDevice);
+                    if (he != hipSuccess) st = hip_error(he, "MFMA table upload");
+                }
+            }
+    }
     if (st != TP_OK) {
         free_plan_memory(p);
         delete p;
@@ -290,8 +312,9 @@ tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dty
     if (plan->persistent) return launch_apply_persistent(*plan, op, u, v, dtype, stream);
     for (const auto& g : plan->groups) {
         const RefData& r = plan->ref[g.n];
-        tp_status st = use_lane(*plan, g) ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
-                                        : launch_apply_eo(*plan, g, op, u, v, dtype, stream);
+        tp_status st = use_lane(*plan, g)    ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
+                       : use_mfma(*plan, g, dtype, u, v) ? launch_apply_mfma(*plan, g, op, u, v, dtype, stream)
+                                                          : launch_apply_eo(*plan, g, op, u, v, dtype, stream);
         if (st != TP_OK) return st;
     }
     return TP_OK;
@@ -329,6 +352,18 @@ tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, d
             st = upload_eo(*plan, n, EO_PLAIN_S, tab, n * n + n);
             if (st != TP_OK) return st;
         }
+        if (n == 8) {  // MFMA operand tables of the inverse
+            for (int et = 0; et < 2; ++et) {
+                std::vector<uint8_t> tabv;
+                build_mfma_tables(r.M, r.A, r.S, r.lam, et == 1, nullptr, &tabv);
+                if (!plan->mfma_inv_dev[et]) {
+                    st = alloc_dev(&plan->mfma_inv_dev[et], tabv.size(), "MFMA tables");
+                    if (st != TP_OK) return st;
+                }
+                hipError_t he = hipMemcpy(plan->mfma_inv_dev[et], tabv.data(), tabv.size(), hipMemcpyHostToDevice);
+                if (he != hipSuccess) return hip_error(he, "MFMA table upload");
+            }
+        }
         r.eig_ready = true;
     }
     plan->inverse_op = op;
@@ -343,8 +378,9 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
     if (r == x && r) return set_error(TP_ERR_ARG, "r and x must not alias");
     if (plan->persistent) return launch_inverse_persistent(*plan, r, x, dtype, stream);
     for (const auto& g : plan->groups) {
-        tp_status st = use_lane(*plan, g) ? launch_inverse(*plan, g, r, x, dtype, stream)
-                                        : launch_inverse_eo(*plan, g, r, x, dtype, stream);
+        tp_status st = use_lane(*plan, g)    ? launch_inverse(*plan, g, r, x, dtype, stream)
+                       : use_mfma(*plan, g, dtype, r, x) ? launch_inverse_mfma(*plan, g, r, x, dtype, stream)
+                                                          : launch_inverse_eo(*plan, g, r, x, dtype, stream);
         if (st != TP_OK) return st;
     }
     return TP_OK;

@@ -87,6 +87,18 @@ __device__ __forceinline__ float recip(float a) {
     return fmaf(r, e, r);
 }
 
+// Synchronises the lanes of one wave around an LDS exchange.  Every kernel
+// that uses it runs one wave per workgroup; a wave's LDS instructions execute
+// in program order, so only the compiler must be kept from moving LDS
+// accesses across this point.  Wavefront-scope fences do that without the
+// global-memory wait of a workgroup barrier, which would drain the loads a
+// kernel has in flight for its next tiles.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------ wave tiles
 // A workgroup of one wave owns BPW = max(1, 64 / n^2) consecutive blocks.
 // Lane l works on block w = l / n^2 of the tile and on pencil l % n^2 of it.

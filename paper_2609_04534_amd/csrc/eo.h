@@ -177,7 +177,7 @@ template <typename TC, int COUNT>
 __device__ __forceinline__ void load_table(TC (&dst)[COUNT], const TC* __restrict__ tab, TC* stab) {
     if constexpr (sizeof(TC) == 8) {
         for (int e = threadIdx.x; e < COUNT; e += 64) stab[e] = tab[e];
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int i = 0; i < COUNT; ++i) dst[i] = stab[i];
     } else {
@@ -211,7 +211,7 @@ __device__ __forceinline__ void eo_apply_body(const Pencil<N>& pc, const TC (&x)
 #pragma unroll
         for (int k = 0; k < N; ++k) A2[L::at(pa, pb, k)] = y[k];
     }
-    __syncthreads();
+    wave_sync();
     if (pc.act) {  // y: lane (i, k); a = s_x M t, b = s_y P t + s_z M w
         TC et[HC], ot[H], ew[HC], ow[H], E[HC], O[H], E2[HC], O2[H], y[N];
 #pragma unroll
@@ -234,7 +234,7 @@ __device__ __forceinline__ void eo_apply_body(const Pencil<N>& pc, const TC (&x)
 #pragma unroll
         for (int j = 0; j < N; ++j) A2[L::at(pa, j, pb)] = y[j];
     }
-    __syncthreads();
+    wave_sync();
     if (pc.act) {  // x: lane (j, k); v = P a + M b, stored to global
         TC y[N], ea[HC], oa[H], eb[HC], ob[H], E[HC], O[H], E2[HC], O2[H];
 #pragma unroll
@@ -254,7 +254,7 @@ __device__ __forceinline__ void eo_apply_body(const Pencil<N>& pc, const TC (&x)
 #pragma unroll
         for (int i = 0; i < N; ++i) stc(out + (static_cast<int64_t>((i * N + pa) * N + pb) << G.logB), y[i]);
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // The three middle phases of D^{-1} on the lane's slab A1, which on entry
@@ -273,7 +273,7 @@ __device__ __forceinline__ void eo_inverse_mid(const Pencil<N>& pc, TC* A1, cons
 #pragma unroll
         for (int b = 0; b < N; ++b) A1[L::at(pa, b, pb)] = y[b];
     }
-    __syncthreads();
+    wave_sync();
     if (pc.act) {  // x forward, scale, x backward: lane (b, c)
         TC a[N], y[N];
 #pragma unroll
@@ -286,7 +286,7 @@ __device__ __forceinline__ void eo_inverse_mid(const Pencil<N>& pc, TC* A1, cons
 #pragma unroll
         for (int i = 0; i < N; ++i) A1[L::at(i, pa, pb)] = a[i];
     }
-    __syncthreads();
+    wave_sync();
     if (pc.act) {  // y backward: lane (i, c)
         TC y[N], a[N];
 #pragma unroll
@@ -295,7 +295,7 @@ __device__ __forceinline__ void eo_inverse_mid(const Pencil<N>& pc, TC* A1, cons
 #pragma unroll
         for (int j = 0; j < N; ++j) A1[L::at(pa, j, pb)] = a[j];
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // x = D^{-1} r for one tile: r's z-pencil in registers, result stored to
@@ -312,7 +312,7 @@ __device__ __forceinline__ void eo_inverse_body(const Pencil<N>& pc, const TC (&
 #pragma unroll
         for (int c = 0; c < N; ++c) A1[L::at(pa, pb, c)] = y[c];
     }
-    __syncthreads();
+    wave_sync();
     eo_inverse_mid<N>(pc, A1, SE, SO, lam, sx, sy, sz);
     if (pc.act) {  // z backward: lane (i, j), pencil stored to global
         TC y[N], a[N];
@@ -321,7 +321,7 @@ __device__ __forceinline__ void eo_inverse_body(const Pencil<N>& pc, const TC (&
         eo_bwd<N>(SE, SO, y, a);
         pencil_store<N, VP>(const_cast<TS*>(pencil_ptr<N>(x, G, g0 + pc.w, pa, pb)), a, G.logB);
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // dst = A src entirely in LDS (dst may alias src); t1, t2 scratch slabs.
@@ -346,7 +346,7 @@ __device__ __forceinline__ void eo_apply_lds(const Pencil<N>& pc, const TC* src,
 #pragma unroll
         for (int k = 0; k < N; ++k) t2[L::at(pa, pb, k)] = y[k];
     }
-    __syncthreads();
+    wave_sync();
     if (pc.act) {
         TC et[HC], ot[H], ew[HC], ow[H], E[HC], O[H], E2[HC], O2[H], y[N];
 #pragma unroll
@@ -369,7 +369,7 @@ __device__ __forceinline__ void eo_apply_lds(const Pencil<N>& pc, const TC* src,
 #pragma unroll
         for (int j = 0; j < N; ++j) t2[L::at(pa, j, pb)] = y[j];
     }
-    __syncthreads();
+    wave_sync();
     if (pc.act) {
         TC y[N], ea[HC], oa[H], eb[HC], ob[H], E[HC], O[H], E2[HC], O2[H];
 #pragma unroll
@@ -388,7 +388,7 @@ __device__ __forceinline__ void eo_apply_lds(const Pencil<N>& pc, const TC* src,
 #pragma unroll
         for (int i = 0; i < N; ++i) dst[L::at(i, pa, pb)] = y[i];
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // slab <- D^{-1} slab entirely in LDS (each phase updates its own pencils).
@@ -405,7 +405,7 @@ __device__ __forceinline__ void eo_inverse_lds(const Pencil<N>& pc, TC* slab, co
 #pragma unroll
         for (int c = 0; c < N; ++c) slab[L::at(pa, pb, c)] = y[c];
     }
-    __syncthreads();
+    wave_sync();
     eo_inverse_mid<N>(pc, slab, SE, SO, lam, sx, sy, sz);
     if (pc.act) {
         TC y[N], a[N];
@@ -415,7 +415,7 @@ __device__ __forceinline__ void eo_inverse_lds(const Pencil<N>& pc, TC* slab, co
 #pragma unroll
         for (int k = 0; k < N; ++k) slab[L::at(pa, pb, k)] = a[k];
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // ------------------------------------------------------------ solve tile
@@ -493,7 +493,7 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
     double sx = 1.0, sy = 1.0, sz = 1.0;
     if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
     const TI sxi = static_cast<TI>(sx), syi = static_cast<TI>(sy), szi = static_cast<TI>(sz);
-    __syncthreads();
+    wave_sync();
     double bsq = 0.0;
     if (pc.act)
         for (int k = 0; k < N; ++k) {
@@ -501,14 +501,14 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
             bsq = fma(bv, bv, bsq);
         }
     S.part[0][lane] = bsq;
-    __syncthreads();
+    wave_sync();
     if (pc.act && pc.pa == 0 && pc.pb == 0) {
         double sacc = 0.0;
         for (int l = 0; l < L::N2; ++l) sacc += S.part[0][lane + l];
         S.red[0][pc.w] = sacc;
         S.done[pc.w] = 0;
     }
-    __syncthreads();
+    wave_sync();
     int it = 0;
     const double bn = pc.act ? S.red[0][pc.w] : 0.0;
     double rel = 0.0;
@@ -527,7 +527,7 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
             }
         S.part[0][lane] = rr;
         S.part[1][lane] = rmax;
-        __syncthreads();
+        wave_sync();
         if (pc.act && pc.pa == 0 && pc.pb == 0) {
             double s2 = 0.0, m = 0.0;
             for (int l = 0; l < L::N2; ++l) {
@@ -537,13 +537,13 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
             S.red[1][pc.w] = s2;
             S.red[2][pc.w] = m;
         }
-        __syncthreads();
+        wave_sync();
         bool mine_done = true;
         if (pc.act && !S.done[pc.w]) {
             rel = bn == 0.0 ? 0.0 : sqrt(S.red[1][pc.w] / bn);
             mine_done = !(rel > rtol) || it >= maxit;
         }
-        __syncthreads();
+        wave_sync();
         if (pc.act && pc.pa == 0 && pc.pb == 0 && mine_done) S.done[pc.w] = 1;
         if (!__any(pc.act && !mine_done)) break;
         const double rmax_b = pc.act ? S.red[2][pc.w] : 0.0;
@@ -553,7 +553,7 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
                 const int a = so + L::at(pc.pa, pc.pb, k);
                 S.rs[a] = static_cast<TI>(S.ra[a] * inv_s);
             }
-        __syncthreads();
+        wave_sync();
         eo_inverse_lds<N, TI>(pc, S.rs + so, SE, SO, lam, sxi, syi, szi);
         if (pc.act && !mine_done) {
             for (int k = 0; k < N; ++k) {
@@ -562,7 +562,7 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
             }
             ++it;
         }
-        __syncthreads();
+        wave_sync();
     }
     for (int e = threadIdx.x; e < nvalid * L::N3; e += 64) {
         const int w = e / L::N3;
@@ -576,7 +576,7 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
         if (relres) relres[gidx] = rel;
         acc.add(it, rel, rtol);
     }
-    __syncthreads();
+    wave_sync();
 }
 
 // Factor tables of a tile kernel, in registers.  FP64 tables go through LDS
@@ -603,9 +603,9 @@ struct InvTab {
 // VREG selects the vector-register copy (default: for 8-byte entries).
 template <typename TC, int COUNT, bool VREG = (sizeof(TC) == 8)>
 __device__ __forceinline__ void table_to_regs(TC (&dst)[COUNT], const TC* __restrict__ tab, TC* stab, int count) {
-    __syncthreads();
+    wave_sync();
     for (int e = threadIdx.x; e < count; e += 64) stab[e] = tab[e];
-    __syncthreads();
+    wave_sync();
     if constexpr (VREG) {
 #pragma unroll
         for (int i = 0; i < COUNT; ++i) dst[i] = stab[i];

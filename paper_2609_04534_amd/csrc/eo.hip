@@ -83,7 +83,7 @@ __global__ __launch_bounds__(64, 2) void k_inverse_eo(const TS* __restrict__ r, 
     __shared__ TC s1[L::BPW * L::size];
     __shared__ TC stab[TABM + N];
     for (int e = threadIdx.x; e < TABM + N; e += 64) stab[e] = tab[e];
-    __syncthreads();
+    wave_sync();
     TC T[TABM];
     if constexpr (sizeof(TC) == 8) {
 #pragma unroll

@@ -82,6 +82,9 @@ struct Plan {
     void* summary_dev = nullptr;   // solve summary of the last solve
     void* partials_dev = nullptr;  // SolvePartial per workgroup of the last solve
     int64_t partials_cap = 0;
+    // MFMA operand tables for n = 8 FP16 / BF16: apply [K or A][f16 or bf16], inverse [f16 or bf16]
+    void* mfma_apply_dev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    void* mfma_inv_dev[2] = {nullptr, nullptr};
     void* segs_dev = nullptr;      // persistent-kernel segment table (one per group)
     void* eo_dev = nullptr;        // even-odd tables, (kMaxN+1) x EO_NTAB x 2 slots
     int64_t wave_grid = 2048;      // persistent grid of the wave kernels
@@ -135,6 +138,15 @@ inline const void* eo_table(const Plan& plan, int n, int tab, int et) {
            static_cast<size_t>(((n * EO_NTAB + tab) * 2 + et) * kEOSlot) * sizeof(double);
 }
 tp_status upload_eo(Plan& plan, int n, int tab, const double* vals, int count);
+// MFMA path (n = 8, FP16 / BF16, B = 1, 16-byte aligned vectors).
+bool build_mfma_tables(const double* M, const double* P, const double* S, const double* lam, bool bf16,
+                       std::vector<uint16_t>* apply, std::vector<uint8_t>* inverse);
+bool mfma_eligible(const GroupInfo& g, tp_dtype dt, const void* a, const void* b);
+tp_status launch_apply_mfma(const Plan& plan, const GroupInfo& g, int op, const void* u, void* v, tp_dtype dt,
+                            hipStream_t s);
+tp_status launch_inverse_mfma(const Plan& plan, const GroupInfo& g, const void* r, void* x, tp_dtype dt,
+                              hipStream_t s);
+
 // Persistent single-launch paths over all groups of a plan.
 tp_status persistent_setup(Plan& plan);
 tp_status launch_apply_persistent(const Plan& plan, int op, const void* u, void* v, tp_dtype dt, hipStream_t s);

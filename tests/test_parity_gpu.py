@@ -460,3 +460,39 @@ def test_graph_replay_matches_eager(persistent):
             assert summ["n_failed"] == 0 and summ["max_iters"] >= 1
         for g in graphs:
             g.destroy()
+
+
+# ------------------------------------------------------------------ MFMA (n = 8, FP16 / BF16)
+@pytest.mark.parametrize("dt", [tpfdm.F16, tpfdm.BF16])
+@pytest.mark.parametrize("nb", [1, 2, 63, 130])
+def test_mfma_path_matches_oracle(dt, nb):
+    """The matrix-core path (n = 8, 16-bit storage, B = 1) against the FP64
+    oracle, for odd and even block counts (tiles hold two blocks)."""
+    wl = workloads.random_blocks(7, nb, seed=500 + nb, h_range=(0.5, 4.0))
+    g = wl.groups[0]
+    with make_plan(wl) as plan:
+        plan.setup_inverse()
+        a, _ = gpu_apply(plan, canon([g.u]), dt, tpfdm.OP_NEUMANN)
+        c, _ = gpu_apply(plan, canon([g.u]), dt, tpfdm.OP_CELL)
+        i, _ = gpu_inverse(plan, canon([g.u]), dt)
+    ea = rel_err_blocks(a.reshape(nb, -1), dense.apply(7, g.h, g.u, dense.NEUMANN))
+    ec = rel_err_blocks(c.reshape(nb, -1), dense.apply(7, g.h, g.u, dense.CELL))
+    ei = rel_err_blocks(i.reshape(nb, -1), dense.solve(7, g.h, g.u))
+    print(f"MFMA dtype={tpfdm.DTYPE_NAMES[dt]} nb={nb} apply {ea:.2e} cell {ec:.2e} inverse {ei:.2e}")
+    assert ea < TOL_APPLY[dt] and ec < TOL_APPLY[dt] and ei < TOL_INV[dt]
+
+
+@pytest.mark.parametrize("dt", [tpfdm.F16, tpfdm.BF16])
+def test_mfma_and_vector_paths_agree(dt):
+    """MFMA and the even-odd vector path (mapping = WAVE) compute the same
+    operator; their difference stays within the storage precision bound."""
+    wl = workloads.random_blocks(7, 40, seed=77, h_range=(0.5, 4.0))
+    flat = canon([wl.groups[0].u])
+    res = {}
+    for mapping in (tpfdm.MAP_AUTO, tpfdm.MAP_WAVE):
+        with make_plan(wl, mapping=mapping) as plan:
+            plan.setup_inverse()
+            res[mapping] = (gpu_apply(plan, flat, dt)[0], gpu_inverse(plan, flat, dt)[0])
+    for k, tol in ((0, TOL_APPLY[dt]), (1, TOL_INV[dt])):
+        got, ref = res[tpfdm.MAP_AUTO][k].reshape(40, -1), res[tpfdm.MAP_WAVE][k].reshape(40, -1)
+        assert rel_err_blocks(got, ref) < 2 * tol
