@@ -308,9 +308,12 @@ def run_suite(args, stream):
             reps = max(args.steps, 20)
             ms_a = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
             ms_i = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
+            # a plain device copy of the same vector: the bandwidth reachable at this size
+            ms_c = time_launches(lambda k: X[k].copy_(U[k]), stream, reps, R)
             ab = algorithmic_bytes(wl, es)
             rec = {"workload": name, "dtype": dtn, "ndof": ndof, "buffer_sets": R,
                    "cache_resident": 3 * R * vec_bytes < 0.75e9,
+                   "copy_ms": ms_c, "copy_GB/s": 2 * vec_bytes / ms_c / 1e6,
                    "apply_ms": ms_a, "apply_GDoF/s": ndof / ms_a / 1e6, "apply_GB/s": ab / ms_a / 1e6,
                    "apply_TFLOP/s": flops(wl, "apply") / ms_a / 1e9,
                    "inverse_ms": ms_i, "inverse_GDoF/s": ndof / ms_i / 1e6, "inverse_GB/s": ab / ms_i / 1e6,
@@ -400,7 +403,7 @@ def run_uneven(args, stream):
 def kernel_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip",):
+    for f in ("kernels.hip", "lane.h", "device.h"):
         h.update(open(os.path.join(ROOT, "paper_2609_04534_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
