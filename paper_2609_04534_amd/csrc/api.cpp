@@ -231,6 +231,12 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
         p->wave_grid = static_cast<int64_t>(cus) * 8, p->cus = cus;
+    // The lane solve runs one wave (64 blocks) per SIMD; below one tile per
+    // SIMD the wave-per-tile solve spreads a group over more waves (AUTO).
+    // TP_MAP_LANE asks for the lane solve at any size.
+    for (auto& g : p->groups)
+        g.lane_solve = use_lane(*p, g) &&
+                       (p->mapping == TP_MAP_LANE || (g.nblocks + 63) / 64 >= static_cast<int64_t>(p->cus) * 4);
     tp_status st = alloc_dev(&p->summary_dev, sizeof(SolveSummary), "solve summary");
     p->partials_cap = static_cast<int64_t>(p->groups.size() + 1) * p->cus * kMaxWgPerCu;
     if (st == TP_OK)
@@ -391,8 +397,8 @@ tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, do
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
     if (plan->inverse_op != TP_OP_CELL)
         return set_error(TP_ERR_STATE, "tp_solve needs tp_setup_inverse(TP_OP_CELL) first");
-    if (inner != TP_F64 && inner != TP_F32)
-        return set_error(TP_ERR_UNSUPPORTED, "solve inner precision must be TP_F64 or TP_F32");
+    if (inner != TP_F64 && inner != TP_F32 && inner != TP_F16 && inner != TP_BF16)
+        return set_error(TP_ERR_ARG, "invalid inner precision");
     if (!(rtol >= 0.0) || !std::isfinite(rtol)) return set_error(TP_ERR_ARG, "rtol must be finite and >= 0");
     if (maxit < 0) return set_error(TP_ERR_ARG, "maxit must be >= 0");
     if (plan->vec_elems > 0 && (!b || !x)) return set_error(TP_ERR_ARG, "b and x must be non-null");
@@ -406,7 +412,10 @@ tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, do
     } else {
         for (const auto& g : plan->groups) {
             int64_t np = 0;
-            st = launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream);
+            st = g.lane_solve ? launch_solve_lane(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts,
+                                                        &np, stream)
+                                    : launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np,
+                                                   stream);
             if (st != TP_OK) return st;
             nparts += np;
         }

@@ -251,8 +251,15 @@ __device__ __forceinline__ void eo_apply_body(const Pencil<N>& pc, const TC (&x)
         for (int i = 0; i < H; ++i) O[i] += O2[i];
         eo_join<N>(E, O, y);
         TS* out = v + G.offset + block_base(g0 + pc.w, G.logB, L::N3);
+        // a wave's store covers whole 128-byte lines only when an x-plane
+        // does; only then does the streaming hint not split lines
+        constexpr bool kWholeLines = (N * N * sizeof(TS)) % 128 == 0;
 #pragma unroll
-        for (int i = 0; i < N; ++i) stc(out + (static_cast<int64_t>((i * N + pa) * N + pb) << G.logB), y[i]);
+        for (int i = 0; i < N; ++i) {
+            TS* o = out + (static_cast<int64_t>((i * N + pa) * N + pb) << G.logB);
+            if constexpr (kWholeLines) stg(o, y[i]);
+            else stc(o, y[i]);
+        }
     }
     wave_sync();
 }
@@ -419,43 +426,6 @@ __device__ __forceinline__ void eo_inverse_lds(const Pencil<N>& pc, TC* slab, co
 }
 
 // ------------------------------------------------------------ solve tile
-// Per-lane accumulation of block results; flush() reduces over the wave and
-// lane 0 stores the workgroup's partial summary (no atomics: a solve over
-// millions of blocks would otherwise serialise on one summary address).
-struct SolveAcc {
-    int max_iters = 0;
-    int n_failed = 0;
-    int nonfinite = 0;
-    double max_relres = 0.0;
-    __device__ __forceinline__ void add(int it, double rel, double rtol) {
-        max_iters = it > max_iters ? it : max_iters;
-        const bool finite = (rel == rel) && rel <= 1.7976931348623157e308;
-        if (!(rel <= rtol)) ++n_failed;
-        if (!finite) ++nonfinite;
-        else if (rel > max_relres) max_relres = rel;
-    }
-    __device__ __forceinline__ void flush(SolvePartial* out) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const int mi = __shfl_xor(max_iters, o, 64);
-            max_iters = mi > max_iters ? mi : max_iters;
-            n_failed += __shfl_xor(n_failed, o, 64);
-            nonfinite += __shfl_xor(nonfinite, o, 64);
-            const double mr = __shfl_xor(max_relres, o, 64);
-            max_relres = mr > max_relres ? mr : max_relres;
-        }
-        if (threadIdx.x == 0) {
-            SolvePartial p;
-            p.max_iters = max_iters;
-            p.n_failed = n_failed;
-            p.nonfinite = nonfinite;
-            p.pad = 0;
-            p.max_relres = max_relres;
-            *out = p;
-        }
-    }
-};
-
 // LDS workspace of one solve tile.
 template <int N, typename TI>
 struct SolveLds {
@@ -468,11 +438,12 @@ struct SolveLds {
 };
 
 // Block-local iterative refinement of one tile (a wave, BPW blocks):
-//   r = b - D x (FP64), s = ||r||_inf, d = D~^{-1} (r / s) in precision TI,
+//   r = b - D x (FP64), s = ||r||_inf, d = D~^{-1} (r / s) in precision TI
+//   (input and output rounded to FP16 / BF16 for RND),
 //   x <- x + s d (FP64), until ||r||_2 <= rtol ||b||_2 or maxit corrections.
 // x and b stay in LDS for all iterations (b read once, x written once);
 // per-block norms are reduced over the block's pencils through LDS.
-template <int N, typename TI>
+template <int N, typename TI, int RND>
 __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, double* __restrict__ x, const GArgs& G,
                                               int64_t g0, int nvalid, SolveLds<N, TI>& S, const double* ME,
                                               const double* MO, const double* PE, const double* PO, const TI* SE,
@@ -480,13 +451,19 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
                                               int32_t* __restrict__ iters, double* __restrict__ relres,
                                               int64_t block0, SolveAcc& acc) {
     using L = Slab<N>;
+    bool nz = false;
     for (int e = threadIdx.x; e < nvalid * L::N3; e += 64) {
         const int w = e / L::N3;
         const int q = e - w * L::N3;
         const int64_t a = G.offset + block_base(g0 + w, G.logB, L::N3) + (static_cast<int64_t>(q) << G.logB);
         S.bs[w * L::size + L::lin(q)] = b[a];
-        S.xs[w * L::size + L::lin(q)] = x[a];
+        const double xv = x[a];
+        S.xs[w * L::size + L::lin(q)] = xv;
+        nz = nz || xv != 0.0;
     }
+    // the residual of an all-zero x is b: the first product is skipped
+    // when every x of the tile is zero on entry
+    bool need_apply = __any(nz);
     const Pencil<N> pc(nvalid);
     const int lane = threadIdx.x;
     const int so = (pc.w < L::BPW ? pc.w : 0) * L::size;
@@ -515,12 +492,13 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
     if (pc.act && bn == 0.0)
         for (int k = 0; k < N; ++k) S.xs[so + L::at(pc.pa, pc.pb, k)] = 0.0;
     for (;;) {
-        eo_apply_lds<N, double>(pc, S.xs + so, S.ra + so, S.t1 + so, S.t2 + so, ME, MO, PE, PO, sx, sy, sz);
+        if (need_apply)
+            eo_apply_lds<N, double>(pc, S.xs + so, S.ra + so, S.t1 + so, S.t2 + so, ME, MO, PE, PO, sx, sy, sz);
         double rr = 0.0, rmax = 0.0;
         if (pc.act)
             for (int k = 0; k < N; ++k) {
                 const int a = so + L::at(pc.pa, pc.pb, k);
-                const double rv = S.bs[a] - S.ra[a];
+                const double rv = need_apply ? S.bs[a] - S.ra[a] : S.bs[a];
                 S.ra[a] = rv;
                 rr = fma(rv, rv, rr);
                 rmax = fmax(rmax, fabs(rv));
@@ -551,17 +529,18 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
         if (pc.act)
             for (int k = 0; k < N; ++k) {
                 const int a = so + L::at(pc.pa, pc.pb, k);
-                S.rs[a] = static_cast<TI>(S.ra[a] * inv_s);
+                S.rs[a] = round_to<RND>(static_cast<TI>(S.ra[a] * inv_s));
             }
         wave_sync();
         eo_inverse_lds<N, TI>(pc, S.rs + so, SE, SO, lam, sxi, syi, szi);
         if (pc.act && !mine_done) {
             for (int k = 0; k < N; ++k) {
                 const int a = so + L::at(pc.pa, pc.pb, k);
-                S.xs[a] = fma(rmax_b, static_cast<double>(S.rs[a]), S.xs[a]);
+                S.xs[a] = fma(rmax_b, static_cast<double>(round_to<RND>(S.rs[a])), S.xs[a]);
             }
             ++it;
         }
+        need_apply = true;
         wave_sync();
     }
     for (int e = threadIdx.x; e < nvalid * L::N3; e += 64) {

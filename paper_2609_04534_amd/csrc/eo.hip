@@ -124,7 +124,7 @@ __global__ __launch_bounds__(64, 2) void k_inverse_eo(const TS* __restrict__ r, 
 }
 
 // Block-local iterative refinement over all tiles of a group (persistent grid).
-template <int N, typename TI>
+template <int N, typename TI, int RND>
 __global__ __launch_bounds__(64, 2) void k_solve_eo(const double* __restrict__ b, double* __restrict__ x, GArgs G,
                                                     const double* __restrict__ tabA, const TI* __restrict__ tabS,
                                                     int64_t ntiles, double rtol, int maxit,
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(64, 2) void k_solve_eo(const double* __restrict__ b
     const TI* lam = stabS + S::SE + S::SO;
     SolveAcc acc;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-        eo_solve_tile<N, TI>(b, x, G, t * L::BPW, nvalid_of<N>(G, t), lds, A.ME(), A.MO(), A.PE(), A.PO(), I.SE(),
+        eo_solve_tile<N, TI, RND>(b, x, G, t * L::BPW, nvalid_of<N>(G, t), lds, A.ME(), A.MO(), A.PE(), A.PO(), I.SE(),
                              I.SO(), lam, rtol, maxit, iters, relres, block0, acc);
     acc.flush(parts + blockIdx.x);
 }
@@ -219,7 +219,7 @@ tp_status inverse_eo_n(const Plan& plan, const GroupInfo& g, const void* r, void
     return check("apply_inverse (even-odd) launch");
 }
 
-template <int N, typename TI>
+template <int N, typename TI, int RND>
 tp_status solve_eo_n(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol, int maxit,
                      int32_t* iters, double* relres, int64_t part_base, int64_t* nparts, hipStream_t s) {
     const int64_t ntiles = eo_tiles<N>(g);
@@ -227,27 +227,27 @@ tp_status solve_eo_n(const Plan& plan, const GroupInfo& g, const double* b, doub
     const TI* tabS = reinterpret_cast<const TI*>(eo_table(plan, N, EO_INV, sizeof(TI) == 8 ? 0 : 1));
     GArgs a{g.h, g.nblocks, g.offset, g.logB};
     static int64_t gc = 0;
-    if (gc == 0) gc = persistent_grid(plan, reinterpret_cast<const void*>(&k_solve_eo<N, TI>), INT64_MAX);
+    if (gc == 0) gc = persistent_grid(plan, reinterpret_cast<const void*>(&k_solve_eo<N, TI, RND>), INT64_MAX);
     const int64_t grid = std::min(gc, ntiles);
     if (part_base + grid > plan.partials_cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
     *nparts = grid;
-    hipLaunchKernelGGL((k_solve_eo<N, TI>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x, a, tabA, tabS,
+    hipLaunchKernelGGL((k_solve_eo<N, TI, RND>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x, a, tabA, tabS,
                        ntiles, rtol, maxit, iters, relres, g.block0,
                        static_cast<SolvePartial*>(plan.partials_dev) + part_base);
     return check("solve launch");
 }
 
-template <typename TI>
+template <typename TI, int RND>
 tp_status solve_eo_dispatch(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol,
                             int maxit, int32_t* iters, double* relres, int64_t pb, int64_t* np, hipStream_t s) {
     switch (g.n) {
-        case 2: return solve_eo_n<2, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 3: return solve_eo_n<3, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 4: return solve_eo_n<4, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 5: return solve_eo_n<5, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 6: return solve_eo_n<6, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 7: return solve_eo_n<7, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 8: return solve_eo_n<8, TI>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 2: return solve_eo_n<2, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 3: return solve_eo_n<3, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 4: return solve_eo_n<4, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 5: return solve_eo_n<5, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 6: return solve_eo_n<6, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 7: return solve_eo_n<7, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 8: return solve_eo_n<8, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
 }
@@ -300,11 +300,16 @@ tp_status launch_solve(const Plan& plan, const GroupInfo& g, const double* b, do
     *nparts = 0;
     if (g.nblocks == 0) return TP_OK;
     switch (inner) {
-        case TP_F64: return solve_eo_dispatch<double>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
-        case TP_F32: return solve_eo_dispatch<float>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
-        default: break;
+        case TP_F64:
+            return solve_eo_dispatch<double, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case TP_F32:
+            return solve_eo_dispatch<float, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case TP_F16:
+            return solve_eo_dispatch<float, RND_F16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case TP_BF16:
+            return solve_eo_dispatch<float, RND_BF16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
     }
-    return set_error(TP_ERR_UNSUPPORTED, "solve inner precision must be TP_F64 or TP_F32");
+    return set_error(TP_ERR_UNSUPPORTED, "unsupported inner precision");
 }
 
 tp_status launch_inverse_eo(const Plan& plan, const GroupInfo& g, const void* r, void* x, tp_dtype dt,

@@ -57,6 +57,7 @@ struct GroupInfo {
     int64_t canon;        // element offset in canonical order
     int64_t block0;       // first global block index of the group
     double* h;            // plan-owned device copy, [nblocks][3]
+    bool lane_solve;      // solve with one block per lane (else one wave per tile)
 };
 
 // One work item of the persistent kernel: a tile of lane-mapped blocks or a
@@ -128,6 +129,10 @@ tp_status launch_inverse(const Plan& plan, const GroupInfo& g, const void* r, vo
 tp_status launch_solve(const Plan& plan, const GroupInfo& g, const double* b, double* x,
                        tp_dtype inner, double rtol, int maxit, int32_t* iters,
                        double* relres, int64_t part_base, int64_t* nparts, hipStream_t s);
+// Lane-per-block solve (n <= 4); same contract as launch_solve.
+tp_status launch_solve_lane(const Plan& plan, const GroupInfo& g, const double* b, double* x,
+                            tp_dtype inner, double rtol, int maxit, int32_t* iters,
+                            double* relres, int64_t part_base, int64_t* nparts, hipStream_t s);
 // to_blocked: src canonical -> dst blocked; otherwise src blocked -> dst canonical
 tp_status launch_apply_eo(const Plan& plan, const GroupInfo& g, int op, const void* u, void* v,
                           tp_dtype dt, hipStream_t s);

@@ -18,12 +18,14 @@
 //   D^-1 = (S (x) S (x) S) diag(1 / (lam_i s_x + lam_j s_y + lam_k s_z)) (S (x) S (x) S)^T
 // where M, P, S, lam are the reference-interval matrices (Sec. 3.1,
 // eq. (eval_pipeline); Sec. 5.2, eq. (cell_block)).
+#include <algorithm>
+
 #include "lane.h"
 
 namespace tpfdm {
 
-template <int N, typename TS, typename TC>
-__global__ __launch_bounds__(256, 2) void k_apply_lane(const TS* __restrict__ u, TS* __restrict__ v, GArgs G,
+template <int N, typename TS, typename TC, bool NT>
+__global__ __launch_bounds__(64, 2) void k_apply_lane(const TS* __restrict__ u, TS* __restrict__ v, GArgs G,
                                                     Pair<N, TC> R) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= G.nblocks) return;
@@ -34,14 +36,14 @@ __global__ __launch_bounds__(256, 2) void k_apply_lane(const TS* __restrict__ u,
     TC sx, sy, sz;
     block_scales(G.h, g, sx, sy, sz);
     TC acc[N * N * N];
-    lane_apply<N, TC>([&](int q) { return ldc<TC>(ub + (static_cast<int64_t>(q) << lb)); }, R, sx, sy, sz,
+    lane_apply<N, TC>([&](int q) { return ldv<NT, TC>(ub + (static_cast<int64_t>(q) << lb)); }, R, sx, sy, sz,
                       acc);
 #pragma unroll
-    for (int q = 0; q < N * N * N; ++q) stc(vb + (static_cast<int64_t>(q) << lb), acc[q]);
+    for (int q = 0; q < N * N * N; ++q) stv<NT>(vb + (static_cast<int64_t>(q) << lb), acc[q]);
 }
 
-template <int N, typename TS, typename TC>
-__global__ __launch_bounds__(256, 2) void k_inverse_lane(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
+template <int N, typename TS, typename TC, bool NT>
+__global__ __launch_bounds__(64, 2) void k_inverse_lane(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
                                                       Eig<N, TC> E) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= G.nblocks) return;
@@ -51,8 +53,27 @@ __global__ __launch_bounds__(256, 2) void k_inverse_lane(const TS* __restrict__ 
     const int lb = G.logB;
     TC sx, sy, sz;
     block_scales(G.h, g, sx, sy, sz);
-    lane_inverse<N, TC>([&](int q) { return ldc<TC>(rb + (static_cast<int64_t>(q) << lb)); },
-                        [&](int q, TC val) { stc(xb + (static_cast<int64_t>(q) << lb), val); }, E, sx, sy, sz);
+    lane_inverse<N, TC>([&](int q) { return ldv<NT, TC>(rb + (static_cast<int64_t>(q) << lb)); },
+                        [&](int q, TC val) { stv<NT>(xb + (static_cast<int64_t>(q) << lb), val); }, E, sx, sy, sz);
+}
+
+// Block-local iterative refinement, one block per lane (n <= 4); the body
+// is lane_solve_tile (lane.h).  The factor tables come in as kernel
+// arguments; M_hat and A_hat are read through their symmetry classes so the
+// scalar registers hold each distinct value once (full FP64 tables of both
+// operators plus the eigenvectors would not fit).
+template <int N, typename TI, int RND, bool NT>
+__global__ __launch_bounds__(64, 1) void k_solve_lane(const double* __restrict__ b, double* __restrict__ x, GArgs G,
+                                                      Pair<N, double> PA, Eig<N, TI> E, int64_t ntiles, double rtol,
+                                                      int maxit, int32_t* __restrict__ iters,
+                                                      double* __restrict__ relres, int64_t block0,
+                                                      SolvePartial* __restrict__ parts) {
+    const Pair<N, double> RA = sym_pair<N>(PA.m, PA.p);
+    __shared__ double xs[N * N * N][64];
+    SolveAcc acc;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+        lane_solve_tile<N, TI, RND, NT>(b, x, G, RA, E, t, rtol, maxit, iters, relres, block0, acc, xs);
+    acc.flush(parts + blockIdx.x);
 }
 
 // ============================================================ layout + misc
@@ -121,7 +142,7 @@ __global__ __launch_bounds__(256) void k_summary_reduce(const SolvePartial* __re
 // ============================================================ host launchers
 namespace {
 
-constexpr int kLaneThreads = 256;
+constexpr int kLaneThreads = 64;   // one wave per workgroup (measured best for n = 4)
 
 template <int N, typename T>
 Pair<N, T> make_pair(const double* M, const double* P) {
@@ -160,8 +181,12 @@ template <int N, typename TS, typename TC>
 tp_status apply_n(const GroupInfo& g, const double* Mm, const double* Pm, const void* u, void* v, hipStream_t s) {
     const auto R = make_pair<N, TC>(Mm, Pm);
     const unsigned grid = static_cast<unsigned>((g.nblocks + kLaneThreads - 1) / kLaneThreads);
-    hipLaunchKernelGGL((k_apply_lane<N, TS, TC>), dim3(grid), dim3(kLaneThreads), 0, s,
-                       static_cast<const TS*>(u), static_cast<TS*>(v), gargs(g), R);
+    if (lane_whole_lines<TS>(g.logB))
+        hipLaunchKernelGGL((k_apply_lane<N, TS, TC, true>), dim3(grid), dim3(kLaneThreads), 0, s,
+                           static_cast<const TS*>(u), static_cast<TS*>(v), gargs(g), R);
+    else
+        hipLaunchKernelGGL((k_apply_lane<N, TS, TC, false>), dim3(grid), dim3(kLaneThreads), 0, s,
+                           static_cast<const TS*>(u), static_cast<TS*>(v), gargs(g), R);
     return check_launch("apply launch");
 }
 
@@ -169,8 +194,12 @@ template <int N, typename TS, typename TC>
 tp_status inverse_n(const GroupInfo& g, const RefData& ref, const void* r, void* x, hipStream_t s) {
     const auto E = make_eig<N, TC>(ref);
     const unsigned grid = static_cast<unsigned>((g.nblocks + kLaneThreads - 1) / kLaneThreads);
-    hipLaunchKernelGGL((k_inverse_lane<N, TS, TC>), dim3(grid), dim3(kLaneThreads), 0, s,
-                       static_cast<const TS*>(r), static_cast<TS*>(x), gargs(g), E);
+    if (lane_whole_lines<TS>(g.logB))
+        hipLaunchKernelGGL((k_inverse_lane<N, TS, TC, true>), dim3(grid), dim3(kLaneThreads), 0, s,
+                           static_cast<const TS*>(r), static_cast<TS*>(x), gargs(g), E);
+    else
+        hipLaunchKernelGGL((k_inverse_lane<N, TS, TC, false>), dim3(grid), dim3(kLaneThreads), 0, s,
+                           static_cast<const TS*>(r), static_cast<TS*>(x), gargs(g), E);
     return check_launch("apply_inverse launch");
 }
 
@@ -197,6 +226,45 @@ tp_status inverse_dispatch(const GroupInfo& g, const RefData& ref, const void* r
     return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
 }
 
+
+template <int N, typename TI, int RND>
+tp_status solve_lane_n(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol, int maxit,
+                       int32_t* iters, double* relres, int64_t part_base, int64_t* nparts, hipStream_t s) {
+    const RefData& ref = plan.ref[N];
+    const auto PA = make_pair<N, double>(ref.M, ref.A);
+    const auto E = make_eig<N, TI>(ref);
+    const int64_t ntiles = (g.nblocks + 63) / 64;
+    const bool nt = lane_whole_lines<double>(g.logB);
+    const void* kern = nt ? reinterpret_cast<const void*>(&k_solve_lane<N, TI, RND, true>)
+                          : reinterpret_cast<const void*>(&k_solve_lane<N, TI, RND, false>);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64, 0) != hipSuccess || occ <= 0) occ = 1;
+    occ = std::min(occ, kMaxWgPerCu);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ntiles, static_cast<int64_t>(plan.cus) * occ));
+    if (part_base + grid > plan.partials_cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
+    SolvePartial* parts = static_cast<SolvePartial*>(plan.partials_dev) + part_base;
+    const int64_t block0 = g.block0;
+    if (nt)
+        hipLaunchKernelGGL((k_solve_lane<N, TI, RND, true>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x,
+                           gargs(g), PA, E, ntiles, rtol, maxit, iters, relres, block0, parts);
+    else
+        hipLaunchKernelGGL((k_solve_lane<N, TI, RND, false>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b,
+                           x, gargs(g), PA, E, ntiles, rtol, maxit, iters, relres, block0, parts);
+    *nparts = grid;
+    return check_launch("solve (lane) launch");
+}
+
+template <typename TI, int RND>
+tp_status solve_lane_dispatch(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol, int maxit,
+                              int32_t* iters, double* relres, int64_t part_base, int64_t* nparts, hipStream_t s) {
+    switch (g.n) {
+        case 2: return solve_lane_n<2, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case 3: return solve_lane_n<3, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case 4: return solve_lane_n<4, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        default: break;
+    }
+    return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
+}
 }  // namespace
 
 tp_status launch_apply(const Plan& plan, const GroupInfo& g, const double* Pm, const void* u, void* v,
@@ -223,6 +291,24 @@ tp_status launch_inverse(const Plan& plan, const GroupInfo& g, const void* r, vo
         case TP_BF16: return inverse_dispatch<bf16_t, float>(g, ref, r, x, s);
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported dtype");
+}
+
+tp_status launch_solve_lane(const Plan& plan, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
+                            double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base,
+                            int64_t* nparts, hipStream_t s) {
+    *nparts = 0;
+    if (g.nblocks == 0) return TP_OK;
+    switch (inner) {
+        case TP_F64:
+            return solve_lane_dispatch<double, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case TP_F32:
+            return solve_lane_dispatch<float, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case TP_F16:
+            return solve_lane_dispatch<float, RND_F16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case TP_BF16:
+            return solve_lane_dispatch<float, RND_BF16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+    }
+    return set_error(TP_ERR_UNSUPPORTED, "unsupported inner precision");
 }
 
 tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize, bool to_blocked,

@@ -31,7 +31,7 @@ struct PSeg {
     int32_t logB;
     int32_t n;
     int32_t lane;         // apply / apply_inverse use the lane-per-block mapping
-    int32_t pad;
+    int32_t lane_solve;   // the solve uses the lane-per-block mapping
 };
 
 namespace {
@@ -43,9 +43,10 @@ constexpr size_t solve_lds_bytes() {
     return sizeof(SolveLds<N, double>) + 64 * sizeof(double) + 64 * sizeof(double);
 }
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kSolveLdsBytes =
+constexpr size_t kSolveLdsBytes = cmax(
     cmax(cmax(cmax(solve_lds_bytes<2>(), solve_lds_bytes<3>()), cmax(solve_lds_bytes<4>(), solve_lds_bytes<5>())),
-         cmax(cmax(solve_lds_bytes<6>(), solve_lds_bytes<7>()), solve_lds_bytes<8>()));
+         cmax(cmax(solve_lds_bytes<6>(), solve_lds_bytes<7>()), solve_lds_bytes<8>())),
+    static_cast<size_t>(kLaneMaxN * kLaneMaxN * kLaneMaxN) * 64 * sizeof(double));  // lane solve: x of 64 blocks
 
 __device__ __forceinline__ const char* dev_table(const char* base, int n, int tab, int et) {
     return base + static_cast<size_t>(((n * EO_NTAB + tab) * 2 + et) * kEOSlot) * sizeof(double);
@@ -61,7 +62,7 @@ __device__ __forceinline__ GArgs seg_args(const PSeg& sg) {
 }
 
 // ------------------------------------------------------------ apply
-template <int N, typename TS, typename TC>
+template <int N, typename TS, typename TC, bool NT>
 __device__ __forceinline__ void seg_apply_lane(const TS* __restrict__ u, TS* __restrict__ v, const PSeg& sg,
                                                const TC* __restrict__ ptab, int64_t t0) {
     Pair<N, TC> R;
@@ -80,9 +81,9 @@ __device__ __forceinline__ void seg_apply_lane(const TS* __restrict__ u, TS* __r
         TC sx, sy, sz;
         block_scales(sg.h, g, sx, sy, sz);
         TC acc[N * N * N];
-        lane_apply<N, TC>([&](int q) { return ldc<TC>(ub + (static_cast<int64_t>(q) << lb)); }, R, sx, sy, sz, acc);
+        lane_apply<N, TC>([&](int q) { return ldv<NT, TC>(ub + (static_cast<int64_t>(q) << lb)); }, R, sx, sy, sz, acc);
 #pragma unroll
-        for (int q = 0; q < N * N * N; ++q) stc(vb + (static_cast<int64_t>(q) << lb), acc[q]);
+        for (int q = 0; q < N * N * N; ++q) stv<NT>(vb + (static_cast<int64_t>(q) << lb), acc[q]);
     }
 }
 
@@ -116,9 +117,12 @@ __device__ __noinline__ void seg_apply(const TS* u, TS* v, const PSeg& sg, const
     const int et = sizeof(TC) == 8 ? 0 : 1;
     if constexpr (N <= kLaneMaxN) {
         if (sg.lane) {
-            seg_apply_lane<N, TS, TC>(
-                u, v, sg, reinterpret_cast<const TC*>(dev_table(tabs, N, op == TP_OP_CELL ? EO_PLAIN_A : EO_PLAIN_K, et)),
-                t0);
+            const TC* pt =
+                reinterpret_cast<const TC*>(dev_table(tabs, N, op == TP_OP_CELL ? EO_PLAIN_A : EO_PLAIN_K, et));
+            if ((static_cast<int64_t>(sizeof(TS)) << sg.logB) >= 128)
+                seg_apply_lane<N, TS, TC, true>(u, v, sg, pt, t0);
+            else
+                seg_apply_lane<N, TS, TC, false>(u, v, sg, pt, t0);
             return;
         }
     }
@@ -130,7 +134,7 @@ __device__ __noinline__ void seg_apply(const TS* u, TS* v, const PSeg& sg, const
 }
 
 // ------------------------------------------------------------ inverse
-template <int N, typename TS, typename TC>
+template <int N, typename TS, typename TC, bool NT>
 __device__ __forceinline__ void seg_inverse_lane(const TS* __restrict__ r, TS* __restrict__ x, const PSeg& sg,
                                                  const TC* __restrict__ ptab, int64_t t0) {
     Eig<N, TC> E;
@@ -147,8 +151,8 @@ __device__ __forceinline__ void seg_inverse_lane(const TS* __restrict__ r, TS* _
         TS* xb = x + base;
         TC sx, sy, sz;
         block_scales(sg.h, g, sx, sy, sz);
-        lane_inverse<N, TC>([&](int q) { return ldc<TC>(rb + (static_cast<int64_t>(q) << lb)); },
-                            [&](int q, TC val) { stc(xb + (static_cast<int64_t>(q) << lb), val); }, E, sx, sy, sz);
+        lane_inverse<N, TC>([&](int q) { return ldv<NT, TC>(rb + (static_cast<int64_t>(q) << lb)); },
+                            [&](int q, TC val) { stv<NT>(xb + (static_cast<int64_t>(q) << lb), val); }, E, sx, sy, sz);
     }
 }
 
@@ -184,7 +188,11 @@ __device__ __noinline__ void seg_inverse(const TS* r, TS* x, const PSeg& sg, con
     const int et = sizeof(TC) == 8 ? 0 : 1;
     if constexpr (N <= kLaneMaxN) {
         if (sg.lane) {
-            seg_inverse_lane<N, TS, TC>(r, x, sg, reinterpret_cast<const TC*>(dev_table(tabs, N, EO_PLAIN_S, et)), t0);
+            const TC* pt = reinterpret_cast<const TC*>(dev_table(tabs, N, EO_PLAIN_S, et));
+            if ((static_cast<int64_t>(sizeof(TS)) << sg.logB) >= 128)
+                seg_inverse_lane<N, TS, TC, true>(r, x, sg, pt, t0);
+            else
+                seg_inverse_lane<N, TS, TC, false>(r, x, sg, pt, t0);
             return;
         }
     }
@@ -196,11 +204,35 @@ __device__ __noinline__ void seg_inverse(const TS* r, TS* x, const PSeg& sg, con
 }
 
 // ------------------------------------------------------------ solve
-template <int N, typename TI>
+template <int N, typename TI, int RND>
 __device__ __noinline__ void seg_solve(const double* b, double* x, const PSeg& sg, const char* tabs, char* lds,
                                           int64_t t0, double rtol, int maxit, int32_t* iters, double* relres,
                                           SolveAcc& acc) {
     using S = EOShape<N>;
+    if constexpr (N <= kLaneMaxN) {
+        if (sg.lane_solve) {  // one block per lane, as the per-group lane solve
+            const double* pa = reinterpret_cast<const double*>(dev_table(tabs, N, EO_PLAIN_A, 0));
+            const TI* ps = reinterpret_cast<const TI*>(dev_table(tabs, N, EO_PLAIN_S, sizeof(TI) == 8 ? 0 : 1));
+            const Pair<N, double> RA = sym_pair<N, double, double>(pa, pa + N * N);
+            Eig<N, TI> E;
+#pragma unroll
+            for (int i = 0; i < N * N; ++i) E.s[i] = ps[i];
+#pragma unroll
+            for (int i = 0; i < N; ++i) E.lam[i] = ps[N * N + i];
+            double(*xs)[64] = reinterpret_cast<double(*)[64]>(lds);
+            const GArgs G = seg_args(sg);
+            if ((static_cast<int64_t>(sizeof(double)) << sg.logB) >= 128) {
+                for (int64_t t = t0; t < sg.tiles_lane; t += gridDim.x)
+                    lane_solve_tile<N, TI, RND, true>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0, acc,
+                                                      xs);
+            } else {
+                for (int64_t t = t0; t < sg.tiles_lane; t += gridDim.x)
+                    lane_solve_tile<N, TI, RND, false>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0, acc,
+                                                       xs);
+            }
+            return;
+        }
+    }
     SolveLds<N, TI>& L = *reinterpret_cast<SolveLds<N, TI>*>(lds);
     double* stabA = reinterpret_cast<double*>(lds + sizeof(SolveLds<N, TI>));
     TI* stabS = reinterpret_cast<TI*>(stabA + 64);
@@ -214,7 +246,7 @@ __device__ __noinline__ void seg_solve(const double* b, double* x, const PSeg& s
     const TI* lam = stabS + S::SE + S::SO;
     const GArgs G = seg_args(sg);
     for (int64_t t = t0; t < sg.tiles_wave; t += gridDim.x)
-        eo_solve_tile<N, TI>(b, x, G, t * Slab<N>::BPW, nvalid_of<N>(G, t), L, A.ME(), A.MO(), A.PE(), A.PO(),
+        eo_solve_tile<N, TI, RND>(b, x, G, t * Slab<N>::BPW, nvalid_of<N>(G, t), L, A.ME(), A.MO(), A.PE(), A.PO(),
                              I.SE(), I.SO(), lam, rtol, maxit, iters, relres, sg.block0, acc);
 }
 
@@ -272,8 +304,8 @@ __global__ __launch_bounds__(64, 2) void k_persist_inverse(const TS* __restrict_
     }
 }
 
-template <typename TI>
-__global__ __launch_bounds__(64, 2) void k_persist_solve(const double* __restrict__ b, double* __restrict__ x,
+template <typename TI, int RND>
+__global__ __launch_bounds__(64, 1) void k_persist_solve(const double* __restrict__ b, double* __restrict__ x,
                                                          const PSeg* __restrict__ segs, int nseg,
                                                          const char* __restrict__ tabs, double rtol, int maxit,
                                                          int32_t* __restrict__ iters, double* __restrict__ relres,
@@ -285,16 +317,16 @@ __global__ __launch_bounds__(64, 2) void k_persist_solve(const double* __restric
         const PSeg sg = segs[si];
         const int64_t t0 = first_tile(rot);
         switch (sg.n) {
-            case 2: seg_solve<2, TI>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 3: seg_solve<3, TI>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 4: seg_solve<4, TI>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 5: seg_solve<5, TI>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 6: seg_solve<6, TI>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 7: seg_solve<7, TI>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 8: seg_solve<8, TI>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
+            case 2: seg_solve<2, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
+            case 3: seg_solve<3, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
+            case 4: seg_solve<4, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
+            case 5: seg_solve<5, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
+            case 6: seg_solve<6, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
+            case 7: seg_solve<7, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
+            case 8: seg_solve<8, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
             default: break;
         }
-        rot = (rot + sg.tiles_wave) % gridDim.x;
+        rot = (rot + (sg.lane_solve ? sg.tiles_lane : sg.tiles_wave)) % gridDim.x;
     }
     acc.flush(parts + blockIdx.x);
 }
@@ -321,10 +353,10 @@ int64_t pgrid(const Plan& plan, const void* kern) {
     return static_cast<int64_t>(plan.cus) * occ;
 }
 
-int64_t total_tiles(const Plan& plan, bool wave_only) {
+int64_t total_tiles(const Plan& plan, bool solve) {
     int64_t t = 0;
     for (const auto& g : plan.groups) {
-        const bool lane = !wave_only && g.n <= kLaneMaxN && plan.mapping != TP_MAP_WAVE;
+        const bool lane = solve ? g.lane_solve : (g.n <= kLaneMaxN && plan.mapping != TP_MAP_WAVE);
         t += lane ? (g.nblocks + 63) / 64 : (g.nblocks + bpw_of(g.n) - 1) / bpw_of(g.n);
     }
     return t;
@@ -362,16 +394,16 @@ tp_status pinverse(const Plan& plan, const void* r, void* x, hipStream_t s) {
     return check_p("persistent apply_inverse launch");
 }
 
-template <typename TI>
+template <typename TI, int RND>
 tp_status psolve(const Plan& plan, const double* b, double* x, double rtol, int maxit, int32_t* iters,
                  double* relres, int64_t* nparts, hipStream_t s) {
-    const void* kern = reinterpret_cast<const void*>(&k_persist_solve<TI>);
+    const void* kern = reinterpret_cast<const void*>(&k_persist_solve<TI, RND>);
     static int64_t gc = 0;
     if (gc == 0) gc = pgrid(plan, kern);
     const int64_t grid = std::max<int64_t>(1, std::min(gc, total_tiles(plan, true)));
     if (grid > plan.partials_cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
     *nparts = grid;
-    hipLaunchKernelGGL((k_persist_solve<TI>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x,
+    hipLaunchKernelGGL((k_persist_solve<TI, RND>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x,
                        static_cast<const PSeg*>(plan.segs_dev), static_cast<int>(plan.groups.size()),
                        static_cast<const char*>(plan.eo_dev), rtol, maxit, iters, relres,
                        static_cast<SolvePartial*>(plan.partials_dev));
@@ -393,6 +425,7 @@ tp_status persistent_setup(Plan& plan) {
         s.logB = g.logB;
         s.n = g.n;
         s.lane = (g.n <= kLaneMaxN && plan.mapping != TP_MAP_WAVE) ? 1 : 0;
+        s.lane_solve = g.lane_solve ? 1 : 0;
         segs.push_back(s);
     }
     if (segs.empty()) return TP_OK;
@@ -430,11 +463,12 @@ tp_status launch_solve_persistent(const Plan& plan, const double* b, double* x, 
     *nparts = 0;
     if (plan.groups.empty() || plan.nblocks == 0) return TP_OK;
     switch (inner) {
-        case TP_F64: return psolve<double>(plan, b, x, rtol, maxit, iters, relres, nparts, s);
-        case TP_F32: return psolve<float>(plan, b, x, rtol, maxit, iters, relres, nparts, s);
-        default: break;
+        case TP_F64: return psolve<double, RND_NONE>(plan, b, x, rtol, maxit, iters, relres, nparts, s);
+        case TP_F32: return psolve<float, RND_NONE>(plan, b, x, rtol, maxit, iters, relres, nparts, s);
+        case TP_F16: return psolve<float, RND_F16>(plan, b, x, rtol, maxit, iters, relres, nparts, s);
+        case TP_BF16: return psolve<float, RND_BF16>(plan, b, x, rtol, maxit, iters, relres, nparts, s);
     }
-    return set_error(TP_ERR_UNSUPPORTED, "solve inner precision must be TP_F64 or TP_F32");
+    return set_error(TP_ERR_UNSUPPORTED, "unsupported inner precision");
 }
 
 }  // namespace tpfdm

@@ -276,13 +276,24 @@ def test_low_precision_error_vs_f64_oracle(dt, p):
 
 
 # ------------------------------------------------------------------ solve
-@pytest.mark.parametrize("inner", [tpfdm.F64, tpfdm.F32])
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 7])
-def test_solve_matches_dense_solve(inner, p):
+# iteration caps per inner precision: the inner FDM is exact up to its own
+# rounding, so each correction gains about -log10(kappa * u) digits
+# (kappa <= 6e2 for h ~ U[0.5, 4]; u = 2^-24, 2^-11, 2^-8)
+SOLVE_MAXIT = {tpfdm.F64: 2, tpfdm.F32: 4, tpfdm.F16: 10, tpfdm.BF16: 16}
+SOLVE_CASES = ([(inner, p, tpfdm.MAP_AUTO, None) for inner in (tpfdm.F64, tpfdm.F32, tpfdm.F16, tpfdm.BF16)
+                for p in (1, 2, 3, 4, 7)]
+               + [(inner, p, tpfdm.MAP_LANE, None) for inner in (tpfdm.F64, tpfdm.F32, tpfdm.F16, tpfdm.BF16)
+                  for p in (1, 2, 3)]
+               + [(inner, p, tpfdm.MAP_WAVE, None) for inner in (tpfdm.F64, tpfdm.F32, tpfdm.BF16) for p in (1, 2, 3)]
+               + [(tpfdm.F32, 3, tpfdm.MAP_LANE, 8), (tpfdm.F64, 2, tpfdm.MAP_LANE, 1)])
+
+
+@pytest.mark.parametrize("inner,p,mapping,layout_B", SOLVE_CASES)
+def test_solve_matches_dense_solve(inner, p, mapping, layout_B):
     torch = _torch()
     wl = workloads.random_blocks(p, 65, seed=400 + p, h_range=(0.5, 4.0), with_rhs=True)
     g = wl.groups[0]
-    with make_plan(wl) as plan:
+    with make_plan(wl, layout_B, mapping=mapping) as plan:
         plan.setup_inverse(tpfdm.OP_CELL)
         bb = to_blocked(plan, canon([g.b]), tpfdm.F64)
         bx = torch.zeros_like(bb)
@@ -293,22 +304,23 @@ def test_solve_matches_dense_solve(inner, p):
         it = iters.cpu().numpy()
         rr = relres.cpu().numpy()
     ref = dense.solve(p, g.h, g.b)
-    print(f"inner={tpfdm.DTYPE_NAMES[inner]} p={p} summary={s}")
+    print(f"inner={tpfdm.DTYPE_NAMES[inner]} p={p} mapping={mapping} B={layout_B} summary={s}")
     assert s["n_failed"] == 0 and s["max_relres"] <= 1e-10
-    assert np.all(rr <= 1e-10) and np.all(it >= 1) and np.all(it <= (2 if inner == tpfdm.F64 else 4))
+    assert np.all(rr <= 1e-10) and np.all(it >= 1) and np.all(it <= SOLVE_MAXIT[inner])
     assert s["max_iters"] == it.max()
     # forward error bounded by condition number times the residual tolerance
     kappa = max(dense.condition_number(p, h) for h in g.h[:5])
     assert rel_err_blocks(split(x, wl.groups)[0], ref) < 1e-10 * kappa * 4
 
 
-def test_solve_zero_rhs_and_initial_guess():
+@pytest.mark.parametrize("mapping", [tpfdm.MAP_AUTO, tpfdm.MAP_LANE, tpfdm.MAP_WAVE])
+def test_solve_zero_rhs_and_initial_guess(mapping):
     torch = _torch()
     wl = workloads.random_blocks(3, 70, seed=12, with_rhs=True)
     g = wl.groups[0]
     b = g.b.copy()
     b[5] = 0.0
-    with make_plan(wl) as plan:
+    with make_plan(wl, mapping=mapping) as plan:
         plan.setup_inverse()
         bb = to_blocked(plan, canon([b]), tpfdm.F64)
         # start from the exact solution for block 7: zero iterations there
@@ -399,13 +411,14 @@ def test_persistent_mixed_matches_oracle():
         assert rel_err_blocks(gi, dense.solve(g.p, g.h, g.u)) < F64_TOL
 
 
-@pytest.mark.parametrize("inner", [tpfdm.F64, tpfdm.F32])
-def test_persistent_solve_mixed(inner):
+@pytest.mark.parametrize("inner,mapping", [(tpfdm.F64, tpfdm.MAP_AUTO), (tpfdm.F32, tpfdm.MAP_AUTO),
+                                           (tpfdm.F64, tpfdm.MAP_LANE), (tpfdm.F16, tpfdm.MAP_LANE)])
+def test_persistent_solve_mixed(inner, mapping):
     torch = _torch()
     wl = _mixed(nblocks=300, seed=23)
     res = {}
     for persistent in (False, True):
-        with make_plan(wl, persistent=persistent) as plan:
+        with make_plan(wl, persistent=persistent, mapping=mapping) as plan:
             plan.setup_inverse()
             bb = to_blocked(plan, canon([g.b for g in wl.groups]), tpfdm.F64)
             bx = torch.zeros_like(bb)
