@@ -344,17 +344,18 @@ def run_suite(args, stream):
 
 
 def run_uneven(args, stream):
-    """Batched uneven degrees: per-group launches vs one persistent launch vs
-    the persistent launch replayed from a HIP graph (apply, apply_inverse and
-    the FP32-inner / FP64-refined solve), with cache-resident inputs."""
+    """Batched uneven degrees: per-group launches (eager, or replayed from a HIP
+    graph whose groups are parallel branches) vs one persistent launch (eager
+    or from a graph), for apply, apply_inverse and the FP32-inner /
+    FP64-refined solve, with cache-resident inputs."""
     import torch
     from paper_2609_04534_amd import tpfdm
     wl, _ = build_workload("uneven_p237_20000")
     cu = torch.from_numpy(np.concatenate([g.u.reshape(-1) for g in wl.groups])).cuda()
     cb = torch.from_numpy(np.concatenate([g.b.reshape(-1) for g in wl.groups])).cuda()
     reps = max(args.steps, 50)
-    for mode in ("per_group", "persistent", "persistent_graph"):
-        plan = tpfdm.Plan(tpfdm.groups_for_workload(wl), persistent=(mode != "per_group"))
+    for mode in ("per_group", "per_group_graph", "persistent", "persistent_graph"):
+        plan = tpfdm.Plan(tpfdm.groups_for_workload(wl), persistent=mode.startswith("persistent"))
         plan.setup_inverse(tpfdm.OP_CELL)
         E = plan.vector_elems
         u = torch.empty(E, dtype=torch.float32, device="cuda")
@@ -363,7 +364,7 @@ def run_uneven(args, stream):
         b = torch.empty(E, dtype=torch.float64, device="cuda")
         plan.pack(cb, b)
         xs = torch.zeros_like(b)
-        if mode == "persistent_graph":
+        if mode.endswith("_graph"):
             ga = plan.graph(tpfdm.GRAPH_APPLY, u, v, op=tpfdm.OP_NEUMANN)
             gi = plan.graph(tpfdm.GRAPH_INVERSE, u, x)
             gs = plan.graph(tpfdm.GRAPH_SOLVE, b, xs, dtype=tpfdm.F32, rtol=1e-10, maxit=50)
@@ -395,7 +396,7 @@ def run_uneven(args, stream):
                           "solve_p99_ms": float(np.percentile(lat, 99)),
                           "solve_max_iters": summ["max_iters"], "solve_max_relres": summ["max_relres"]}),
               flush=True)
-        if mode == "persistent_graph":
+        if mode.endswith("_graph"):
             ga.destroy(), gi.destroy(), gs.destroy()
         plan.destroy()
 

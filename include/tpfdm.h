@@ -92,8 +92,10 @@ typedef struct {
 
 /* Kernel mapping of a group's blocks onto the wavefront. */
 typedef enum {
-    TP_MAP_AUTO = 0,      /* lane-per-block for n <= 4, wave-per-tile otherwise        */
-    TP_MAP_LANE = 1,      /* one block per lane, registers only (n <= 4)               */
+    TP_MAP_AUTO = 0,      /* lane-per-block for n <= 4, wave-per-tile otherwise; the
+                             solve goes lane-per-block only for groups of at least
+                             one 64-block tile per SIMD (smaller ones spread wider) */
+    TP_MAP_LANE = 1,      /* one block per lane (n <= 4), for the solve too            */
     TP_MAP_WAVE = 2       /* one wave per tile of blocks, pencils staged through LDS   */
 } tp_mapping;
 
@@ -156,10 +158,14 @@ tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode,
 tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype,
                            hipStream_t stream);
 
-/* Solve D x = b for every block by iterative refinement, one launch:
+/* Solve D x = b for every block by iterative refinement, one launch per
+ * group (one in all for a persistent plan):
  *   r = b - D x (FP64);  s = ||r||_inf;  d = D~^{-1}(r/s) in `inner` precision;
  *   x <- x + s d  (FP64)
- * until ||r||_2 / ||b||_2 <= rtol or maxit corrections.  A block with b = 0
+ * until ||r||_2 / ||b||_2 <= rtol or maxit corrections.  inner: TP_F64 and
+ * TP_F32 compute the inner fast diagonalization in that precision; TP_F16 and
+ * TP_BF16 round r/s and d to that format and compute in FP32 (as
+ * tp_apply_inverse does for vectors stored in it).  A block with b = 0
  * gets x = 0 and 0 iterations.  b, x: device FP64 vectors; x holds the initial
  * guess on entry and the best iterate on exit.  iters (int32) and relres
  * (double): optional device arrays of tp_plan_ndof-order block count (groups
@@ -184,8 +190,8 @@ tp_status tp_solve_summary_fetch(tp_plan* plan, tp_solve_summary* summary, hipSt
  * tp_solve_summary_fetch).  The buffers, dtype and solve parameters are baked
  * into the graph: replay reads `in` and overwrites `out` as the call would.
  * With a persistent plan (opts.persistent = 1) each graph holds one kernel
- * node over all groups.  The plan must outlive its graphs.  Nothing is
- * allocated at replay. */
+ * node over all groups, otherwise the per-group kernels in order.  The plan
+ * must outlive its graphs.  Nothing is allocated at replay. */
 typedef enum { TP_GRAPH_APPLY = 0, TP_GRAPH_INVERSE = 1, TP_GRAPH_SOLVE = 2 } tp_graph_op;
 typedef struct tp_graph tp_graph;
 tp_status tp_graph_create(tp_plan* plan, tp_graph_op what, tp_operator op, tp_dtype dtype, const void* in,

@@ -54,12 +54,19 @@ def direction_factors(p: int, h, op: str, C: float = 2.0):
     return [(float(hd) * M, P / float(hd)) for hd in h]
 
 
-def dense_operator(p: int, h, op: str = NEUMANN, C: float = 2.0) -> np.ndarray:
-    """The n^3 x n^3 block matrix P_x(x)M_y(x)M_z + M_x(x)P_y(x)M_z + M_x(x)M_y(x)P_z."""
-    (Mx, Px), (My, Py), (Mz, Pz) = direction_factors(p, h, op, C)
+def kronecker_sum(pairs) -> np.ndarray:
+    """P_x(x)M_y(x)M_z + M_x(x)P_y(x)M_z + M_x(x)M_y(x)P_z for explicit
+    per-direction pairs [(M_x, P_x), (M_y, P_y), (M_z, P_z)] (the form of
+    eq. (eval_pipeline) and eq. (cell_block) with per-cell factors)."""
+    (Mx, Px), (My, Py), (Mz, Pz) = pairs
     return (np.kron(np.kron(Px, My), Mz)
             + np.kron(np.kron(Mx, Py), Mz)
             + np.kron(np.kron(Mx, My), Pz))
+
+
+def dense_operator(p: int, h, op: str = NEUMANN, C: float = 2.0) -> np.ndarray:
+    """The n^3 x n^3 block matrix P_x(x)M_y(x)M_z + M_x(x)P_y(x)M_z + M_x(x)M_y(x)P_z."""
+    return kronecker_sum(direction_factors(p, h, op, C))
 
 
 def dense_mass(p: int, h) -> np.ndarray:
@@ -105,3 +112,26 @@ def solve(p: int, h_all, r_all, op: str = CELL, C: float = 2.0, refine: int = 2)
 def condition_number(p: int, h, op: str = CELL, C: float = 2.0) -> float:
     """2-norm condition number of the dense block matrix."""
     return float(np.linalg.cond(dense_operator(p, h, op, C)))
+
+
+def apply_factors(M_all, P_all, u_all) -> np.ndarray:
+    """v_b = A_b u_b with explicit per-block, per-direction factors:
+    M_all and P_all are (nblocks, 3, n, n), u_all is (nblocks, n^3)."""
+    u_all = np.asarray(u_all, dtype=np.float64)
+    out = np.empty_like(u_all)
+    for b in range(u_all.shape[0]):
+        pairs = [(np.asarray(M_all[b][d], dtype=np.float64), np.asarray(P_all[b][d], dtype=np.float64))
+                 for d in range(3)]
+        out[b] = kronecker_sum(pairs) @ u_all[b]
+    return out
+
+
+def solve_factors(M_all, P_all, r_all, refine: int = 2) -> np.ndarray:
+    """x_b = A_b^{-1} r_b with explicit per-block factors (dense solve)."""
+    r_all = np.asarray(r_all, dtype=np.float64)
+    out = np.empty_like(r_all)
+    for b in range(r_all.shape[0]):
+        pairs = [(np.asarray(M_all[b][d], dtype=np.float64), np.asarray(P_all[b][d], dtype=np.float64))
+                 for d in range(3)]
+        out[b] = solve_block(kronecker_sum(pairs), r_all[b], refine)
+    return out

@@ -39,6 +39,7 @@ bool use_mfma(const Plan& p, const GroupInfo& g, tp_dtype dt, const void* a, con
 }
 bool valid_dtype(int dt) { return dt >= TP_F64 && dt <= TP_BF16; }
 bool valid_op(int op) { return op == TP_OP_NEUMANN || op == TP_OP_CELL; }
+
 }  // namespace
 
 tp_status set_error(tp_status st, const std::string& msg) {
@@ -316,14 +317,15 @@ tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dty
     if (plan->vec_elems > 0 && (!u || !v)) return set_error(TP_ERR_ARG, "u and v must be non-null");
     if (u == v && u) return set_error(TP_ERR_ARG, "u and v must not alias");
     if (plan->persistent) return launch_apply_persistent(*plan, op, u, v, dtype, stream);
-    for (const auto& g : plan->groups) {
+    tp_status st = TP_OK;
+    for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
+        const GroupInfo& g = plan->groups[i];
         const RefData& r = plan->ref[g.n];
-        tp_status st = use_lane(*plan, g)    ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
-                       : use_mfma(*plan, g, dtype, u, v) ? launch_apply_mfma(*plan, g, op, u, v, dtype, stream)
-                                                          : launch_apply_eo(*plan, g, op, u, v, dtype, stream);
-        if (st != TP_OK) return st;
+        st = use_lane(*plan, g)                ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
+             : use_mfma(*plan, g, dtype, u, v) ? launch_apply_mfma(*plan, g, op, u, v, dtype, stream)
+                                               : launch_apply_eo(*plan, g, op, u, v, dtype, stream);
     }
-    return TP_OK;
+    return st;
 }
 
 tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, double singular_tol) {
@@ -383,13 +385,14 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
     if (plan->vec_elems > 0 && (!r || !x)) return set_error(TP_ERR_ARG, "r and x must be non-null");
     if (r == x && r) return set_error(TP_ERR_ARG, "r and x must not alias");
     if (plan->persistent) return launch_inverse_persistent(*plan, r, x, dtype, stream);
-    for (const auto& g : plan->groups) {
-        tp_status st = use_lane(*plan, g)    ? launch_inverse(*plan, g, r, x, dtype, stream)
-                       : use_mfma(*plan, g, dtype, r, x) ? launch_inverse_mfma(*plan, g, r, x, dtype, stream)
-                                                          : launch_inverse_eo(*plan, g, r, x, dtype, stream);
-        if (st != TP_OK) return st;
+    tp_status st = TP_OK;
+    for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
+        const GroupInfo& g = plan->groups[i];
+        st = use_lane(*plan, g)                ? launch_inverse(*plan, g, r, x, dtype, stream)
+             : use_mfma(*plan, g, dtype, r, x) ? launch_inverse_mfma(*plan, g, r, x, dtype, stream)
+                                               : launch_inverse_eo(*plan, g, r, x, dtype, stream);
     }
-    return TP_OK;
+    return st;
 }
 
 tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, double rtol, int32_t maxit,
@@ -410,15 +413,14 @@ tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, do
         st = launch_solve_persistent(*plan, b, x, inner, rtol, maxit, iters, relres, &nparts, stream);
         if (st != TP_OK) return st;
     } else {
-        for (const auto& g : plan->groups) {
-            int64_t np = 0;
-            st = g.lane_solve ? launch_solve_lane(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts,
-                                                        &np, stream)
-                                    : launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np,
-                                                   stream);
-            if (st != TP_OK) return st;
+        for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
+            const GroupInfo& g = plan->groups[i];
+                int64_t np = 0;
+            st = g.lane_solve ? launch_solve_lane(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream)
+                              : launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream);
             nparts += np;
         }
+        if (st != TP_OK) return st;
     }
     st = launch_summary_reduce(*plan, nparts, stream);
     if (st != TP_OK) return st;

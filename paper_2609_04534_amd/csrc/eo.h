@@ -437,19 +437,20 @@ struct SolveLds {
     int done[Slab<N>::BPW];
 };
 
-// Block-local iterative refinement of one tile (a wave, BPW blocks):
+// Block-local iterative refinement of one tile (a wave, BPW blocks), with
+// the block operator and the inner inverse given as callables on the LDS
+// slabs (apply_lds(pc, src, dst, t1, t2) in FP64, inverse_lds(pc, slab) in
+// TI, both for the lane's pencil pc):
 //   r = b - D x (FP64), s = ||r||_inf, d = D~^{-1} (r / s) in precision TI
 //   (input and output rounded to FP16 / BF16 for RND),
 //   x <- x + s d (FP64), until ||r||_2 <= rtol ||b||_2 or maxit corrections.
 // x and b stay in LDS for all iterations (b read once, x written once);
 // per-block norms are reduced over the block's pencils through LDS.
-template <int N, typename TI, int RND>
-__device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, double* __restrict__ x, const GArgs& G,
-                                              int64_t g0, int nvalid, SolveLds<N, TI>& S, const double* ME,
-                                              const double* MO, const double* PE, const double* PO, const TI* SE,
-                                              const TI* SO, const TI* lam, double rtol, int maxit,
-                                              int32_t* __restrict__ iters, double* __restrict__ relres,
-                                              int64_t block0, SolveAcc& acc) {
+template <int N, typename TI, int RND, typename ApplyF, typename InvF>
+__device__ __forceinline__ void solve_tile(const double* __restrict__ b, double* __restrict__ x, const GArgs& G,
+                                           int64_t g0, int nvalid, SolveLds<N, TI>& S, ApplyF apply_lds,
+                                           InvF inverse_lds, double rtol, int maxit, int32_t* __restrict__ iters,
+                                           double* __restrict__ relres, int64_t block0, SolveAcc& acc) {
     using L = Slab<N>;
     bool nz = false;
     for (int e = threadIdx.x; e < nvalid * L::N3; e += 64) {
@@ -467,9 +468,6 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
     const Pencil<N> pc(nvalid);
     const int lane = threadIdx.x;
     const int so = (pc.w < L::BPW ? pc.w : 0) * L::size;
-    double sx = 1.0, sy = 1.0, sz = 1.0;
-    if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
-    const TI sxi = static_cast<TI>(sx), syi = static_cast<TI>(sy), szi = static_cast<TI>(sz);
     wave_sync();
     double bsq = 0.0;
     if (pc.act)
@@ -492,8 +490,7 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
     if (pc.act && bn == 0.0)
         for (int k = 0; k < N; ++k) S.xs[so + L::at(pc.pa, pc.pb, k)] = 0.0;
     for (;;) {
-        if (need_apply)
-            eo_apply_lds<N, double>(pc, S.xs + so, S.ra + so, S.t1 + so, S.t2 + so, ME, MO, PE, PO, sx, sy, sz);
+        if (need_apply) apply_lds(pc, S.xs + so, S.ra + so, S.t1 + so, S.t2 + so);
         double rr = 0.0, rmax = 0.0;
         if (pc.act)
             for (int k = 0; k < N; ++k) {
@@ -532,7 +529,7 @@ __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, doub
                 S.rs[a] = round_to<RND>(static_cast<TI>(S.ra[a] * inv_s));
             }
         wave_sync();
-        eo_inverse_lds<N, TI>(pc, S.rs + so, SE, SO, lam, sxi, syi, szi);
+        inverse_lds(pc, S.rs + so);
         if (pc.act && !mine_done) {
             for (int k = 0; k < N; ++k) {
                 const int a = so + L::at(pc.pa, pc.pb, k);
@@ -576,6 +573,27 @@ struct InvTab {
     __device__ __forceinline__ const TC* SE() const { return v; }
     __device__ __forceinline__ const TC* SO() const { return v + EOShape<N>::SE; }
 };
+
+// The solve tile with the even-odd reference operators: per-block scalings
+// from the edge lengths, factor tables in registers.
+template <int N, typename TI, int RND>
+__device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, double* __restrict__ x, const GArgs& G,
+                                              int64_t g0, int nvalid, SolveLds<N, TI>& S,
+                                              const ApplyTab<N, double>& A, const InvTab<N, TI>& I, const TI* lam,
+                                              double rtol, int maxit, int32_t* __restrict__ iters,
+                                              double* __restrict__ relres, int64_t block0, SolveAcc& acc) {
+    const Pencil<N> pc(nvalid);
+    double sx = 1.0, sy = 1.0, sz = 1.0;
+    if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
+    const TI sxi = static_cast<TI>(sx), syi = static_cast<TI>(sy), szi = static_cast<TI>(sz);
+    solve_tile<N, TI, RND>(
+        b, x, G, g0, nvalid, S,
+        [&](const Pencil<N>& p, const double* src, double* dst, double* t1, double* t2) {
+            eo_apply_lds<N, double>(p, src, dst, t1, t2, A.ME(), A.MO(), A.PE(), A.PO(), sx, sy, sz);
+        },
+        [&](const Pencil<N>& p, TI* slab) { eo_inverse_lds<N, TI>(p, slab, I.SE(), I.SO(), lam, sxi, syi, szi); },
+        rtol, maxit, iters, relres, block0, acc);
+}
 
 // Copies `count` table entries to LDS (always: the eigenvalues are indexed
 // per lane) and into the register array; stab must hold count entries.

@@ -142,8 +142,8 @@ __global__ __launch_bounds__(64, 2) void k_solve_eo(const double* __restrict__ b
     const TI* lam = stabS + S::SE + S::SO;
     SolveAcc acc;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-        eo_solve_tile<N, TI, RND>(b, x, G, t * L::BPW, nvalid_of<N>(G, t), lds, A.ME(), A.MO(), A.PE(), A.PO(), I.SE(),
-                             I.SO(), lam, rtol, maxit, iters, relres, block0, acc);
+        eo_solve_tile<N, TI, RND>(b, x, G, t * L::BPW, nvalid_of<N>(G, t), lds, A, I, lam, rtol, maxit, iters, relres,
+                                  block0, acc);
     acc.flush(parts + blockIdx.x);
 }
 

@@ -24,7 +24,7 @@
 
 namespace tpfdm {
 
-template <int N, typename TS, typename TC, bool NT>
+template <int N, typename TS, typename TC, bool NT, int LB>
 __global__ __launch_bounds__(64, 2) void k_apply_lane(const TS* __restrict__ u, TS* __restrict__ v, GArgs G,
                                                     Pair<N, TC> R) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(64, 2) void k_apply_lane(const TS* __restrict__ u, 
     const int64_t base = G.offset + block_base(g, G.logB, N * N * N);
     const TS* ub = u + base;
     TS* vb = v + base;
-    const int lb = G.logB;
+    const int lb = LB >= 0 ? LB : G.logB;
     TC sx, sy, sz;
     block_scales(G.h, g, sx, sy, sz);
     TC acc[N * N * N];
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64, 2) void k_apply_lane(const TS* __restrict__ u, 
     for (int q = 0; q < N * N * N; ++q) stv<NT>(vb + (static_cast<int64_t>(q) << lb), acc[q]);
 }
 
-template <int N, typename TS, typename TC, bool NT>
+template <int N, typename TS, typename TC, bool NT, int LB>
 __global__ __launch_bounds__(64, 2) void k_inverse_lane(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
                                                       Eig<N, TC> E) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -50,11 +50,15 @@ __global__ __launch_bounds__(64, 2) void k_inverse_lane(const TS* __restrict__ r
     const int64_t base = G.offset + block_base(g, G.logB, N * N * N);
     const TS* rb = r + base;
     TS* xb = x + base;
-    const int lb = G.logB;
+    const int lb = LB >= 0 ? LB : G.logB;
     TC sx, sy, sz;
     block_scales(G.h, g, sx, sy, sz);
-    lane_inverse<N, TC>([&](int q) { return ldv<NT, TC>(rb + (static_cast<int64_t>(q) << lb)); },
-                        [&](int q, TC val) { stv<NT>(xb + (static_cast<int64_t>(q) << lb), val); }, E, sx, sy, sz);
+    TC v[N * N * N];
+#pragma unroll
+    for (int q = 0; q < N * N * N; ++q) v[q] = ldv<NT, TC>(rb + (static_cast<int64_t>(q) << lb));
+    lane_fdm_inplace<N, TC>(v, E, sx, sy, sz);
+#pragma unroll
+    for (int q = 0; q < N * N * N; ++q) stv<NT>(xb + (static_cast<int64_t>(q) << lb), v[q]);
 }
 
 // Block-local iterative refinement, one block per lane (n <= 4); the body
@@ -181,11 +185,16 @@ template <int N, typename TS, typename TC>
 tp_status apply_n(const GroupInfo& g, const double* Mm, const double* Pm, const void* u, void* v, hipStream_t s) {
     const auto R = make_pair<N, TC>(Mm, Pm);
     const unsigned grid = static_cast<unsigned>((g.nblocks + kLaneThreads - 1) / kLaneThreads);
-    if (lane_whole_lines<TS>(g.logB))
-        hipLaunchKernelGGL((k_apply_lane<N, TS, TC, true>), dim3(grid), dim3(kLaneThreads), 0, s,
+    // B = 64 (the default) is a compile-time layout: every DoF address is
+    // the block base plus a constant offset
+    if (g.logB == 6)
+        hipLaunchKernelGGL((k_apply_lane<N, TS, TC, true, 6>), dim3(grid), dim3(kLaneThreads), 0, s,
+                           static_cast<const TS*>(u), static_cast<TS*>(v), gargs(g), R);
+    else if (lane_whole_lines<TS>(g.logB))
+        hipLaunchKernelGGL((k_apply_lane<N, TS, TC, true, -1>), dim3(grid), dim3(kLaneThreads), 0, s,
                            static_cast<const TS*>(u), static_cast<TS*>(v), gargs(g), R);
     else
-        hipLaunchKernelGGL((k_apply_lane<N, TS, TC, false>), dim3(grid), dim3(kLaneThreads), 0, s,
+        hipLaunchKernelGGL((k_apply_lane<N, TS, TC, false, -1>), dim3(grid), dim3(kLaneThreads), 0, s,
                            static_cast<const TS*>(u), static_cast<TS*>(v), gargs(g), R);
     return check_launch("apply launch");
 }
@@ -194,11 +203,14 @@ template <int N, typename TS, typename TC>
 tp_status inverse_n(const GroupInfo& g, const RefData& ref, const void* r, void* x, hipStream_t s) {
     const auto E = make_eig<N, TC>(ref);
     const unsigned grid = static_cast<unsigned>((g.nblocks + kLaneThreads - 1) / kLaneThreads);
-    if (lane_whole_lines<TS>(g.logB))
-        hipLaunchKernelGGL((k_inverse_lane<N, TS, TC, true>), dim3(grid), dim3(kLaneThreads), 0, s,
+    if (g.logB == 6)
+        hipLaunchKernelGGL((k_inverse_lane<N, TS, TC, true, 6>), dim3(grid), dim3(kLaneThreads), 0, s,
+                           static_cast<const TS*>(r), static_cast<TS*>(x), gargs(g), E);
+    else if (lane_whole_lines<TS>(g.logB))
+        hipLaunchKernelGGL((k_inverse_lane<N, TS, TC, true, -1>), dim3(grid), dim3(kLaneThreads), 0, s,
                            static_cast<const TS*>(r), static_cast<TS*>(x), gargs(g), E);
     else
-        hipLaunchKernelGGL((k_inverse_lane<N, TS, TC, false>), dim3(grid), dim3(kLaneThreads), 0, s,
+        hipLaunchKernelGGL((k_inverse_lane<N, TS, TC, false, -1>), dim3(grid), dim3(kLaneThreads), 0, s,
                            static_cast<const TS*>(r), static_cast<TS*>(x), gargs(g), E);
     return check_launch("apply_inverse launch");
 }

@@ -151,8 +151,12 @@ __device__ __forceinline__ void seg_inverse_lane(const TS* __restrict__ r, TS* _
         TS* xb = x + base;
         TC sx, sy, sz;
         block_scales(sg.h, g, sx, sy, sz);
-        lane_inverse<N, TC>([&](int q) { return ldv<NT, TC>(rb + (static_cast<int64_t>(q) << lb)); },
-                            [&](int q, TC val) { stv<NT>(xb + (static_cast<int64_t>(q) << lb), val); }, E, sx, sy, sz);
+        TC v[N * N * N];
+#pragma unroll
+        for (int q = 0; q < N * N * N; ++q) v[q] = ldv<NT, TC>(rb + (static_cast<int64_t>(q) << lb));
+        lane_fdm_inplace<N, TC>(v, E, sx, sy, sz);
+#pragma unroll
+        for (int q = 0; q < N * N * N; ++q) stv<NT>(xb + (static_cast<int64_t>(q) << lb), v[q]);
     }
 }
 
@@ -246,8 +250,8 @@ __device__ __noinline__ void seg_solve(const double* b, double* x, const PSeg& s
     const TI* lam = stabS + S::SE + S::SO;
     const GArgs G = seg_args(sg);
     for (int64_t t = t0; t < sg.tiles_wave; t += gridDim.x)
-        eo_solve_tile<N, TI, RND>(b, x, G, t * Slab<N>::BPW, nvalid_of<N>(G, t), L, A.ME(), A.MO(), A.PE(), A.PO(),
-                             I.SE(), I.SO(), lam, rtol, maxit, iters, relres, sg.block0, acc);
+        eo_solve_tile<N, TI, RND>(b, x, G, t * Slab<N>::BPW, nvalid_of<N>(G, t), L, A, I, lam, rtol, maxit, iters,
+                                  relres, sg.block0, acc);
 }
 
 __device__ __forceinline__ int64_t first_tile(int64_t rot) {

@@ -360,3 +360,61 @@ def test_solve_recovers_unit_vectors():
     X = dense.solve(p, np.tile(h, (n3, 1)), E)
     D = dense.dense_operator(p, h, dense.CELL)
     assert np.max(np.abs(X @ D.T - E)) < 1e-13
+
+
+# ---------------------------------------------------------------- explicit per-block factors
+def _brute_kronecker_sum(pairs):
+    """Entry by entry: A[(i,j,k),(a,b,c)] = Px[i,a] My[j,b] Mz[k,c] + Mx[i,a] Py[j,b] Mz[k,c]
+    + Mx[i,a] My[j,b] Pz[k,c], with the DoF index q = (i n + j) n + k."""
+    (Mx, Px), (My, Py), (Mz, Pz) = pairs
+    n = Mx.shape[0]
+    A = np.zeros((n ** 3, n ** 3))
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                for a in range(n):
+                    for b in range(n):
+                        for c in range(n):
+                            A[(i * n + j) * n + k, (a * n + b) * n + c] = (
+                                Px[i, a] * My[j, b] * Mz[k, c] + Mx[i, a] * Py[j, b] * Mz[k, c]
+                                + Mx[i, a] * My[j, b] * Pz[k, c])
+    return A
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_kronecker_sum_entrywise(n):
+    rng = np.random.default_rng(90 + n)
+    pairs = [(rng.standard_normal((n, n)), rng.standard_normal((n, n))) for _ in range(3)]
+    assert np.allclose(dense.kronecker_sum(pairs), _brute_kronecker_sum(pairs), rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_explicit_factors_reduce_to_scaled_operator(p):
+    rng = np.random.default_rng(7 + p)
+    h = rng.uniform(0.5, 2.0, size=(4, 3))
+    u = rng.uniform(-1, 1, size=(4, (p + 1) ** 3))
+    for op in (dense.NEUMANN, dense.CELL):
+        M_all = np.array([[f[0] for f in dense.direction_factors(p, hb, op)] for hb in h])
+        P_all = np.array([[f[1] for f in dense.direction_factors(p, hb, op)] for hb in h])
+        assert np.array_equal(dense.apply_factors(M_all, P_all, u), dense.apply(p, h, u, op))
+    x = dense.solve_factors(M_all, P_all, u)
+    assert np.allclose(x, dense.solve(p, h, u), rtol=1e-13, atol=0)
+
+
+def test_solve_factors_residual():
+    rng = np.random.default_rng(5)
+    n = 3
+    M_all = np.empty((2, 3, n, n))
+    P_all = np.empty((2, 3, n, n))
+    for b in range(2):
+        for d in range(3):
+            G = rng.standard_normal((n, n))
+            M_all[b, d] = G @ G.T + n * np.eye(n)
+            H = rng.standard_normal((n, n))
+            P_all[b, d] = H @ H.T + np.eye(n)
+    r = rng.standard_normal((2, n ** 3))
+    x = dense.solve_factors(M_all, P_all, r)
+    for b in range(2):
+        A = _brute_kronecker_sum([(M_all[b, d], P_all[b, d]) for d in range(3)]).astype(np.longdouble)
+        res = r[b].astype(np.longdouble) - A @ x[b].astype(np.longdouble)
+        assert float(np.abs(res).max()) < 1e-14 * float(np.abs(r[b]).max()) * 10
