@@ -74,20 +74,35 @@ typedef enum {
     TP_OP_CELL = 1      /* P_hat = A_hat: the SIPG cell block of eq. (cell_block); SPD        */
 } tp_operator;
 
-/* How per-block eigenfactors are represented.  SCALED: one generalized
- * eigenproblem A_hat S = M_hat S Lambda per degree; a block with lengths h_d
- * uses S_d = S_hat / sqrt(h_d), lambda_d = lambda_hat / h_d^2, which is the
- * exact eigen-decomposition of its own pair (P_hat/h_d, h_d M_hat). */
-typedef enum { TP_FACTOR_SCALED = 0 } tp_factor_mode;
+/* How per-block eigenfactors are represented (Sec. 5.2).
+ * SCALED: one generalized eigenproblem P_hat S = M_hat S Lambda per degree; a
+ *   block with lengths h_d uses S_d = S_hat / sqrt(h_d), lambda_d =
+ *   lambda_hat / h_d^2, the exact eigen-decomposition of its own pair
+ *   (P_hat/h_d, h_d M_hat).  Only for groups given by edge lengths.
+ * GENERAL: one eigenproblem P_d S_d = M_d S_d Lambda_d per block and
+ *   direction (3 nblocks problems of n x n), stored per block: for groups
+ *   given by their own factors, and for length groups from (P_hat/h_d,
+ *   h_d M_hat), where it agrees with SCALED up to rounding. */
+typedef enum { TP_FACTOR_SCALED = 0, TP_FACTOR_GENERAL = 1 } tp_factor_mode;
 
-/* One group of blocks of equal degree and layout. */
+/* One group of blocks of equal degree and layout.  A group is given either
+ * by edge lengths h (the blocks are axis-aligned boxes and use the reference
+ * matrices) or by per-block factors M and P (h null): block b's operator is
+ * P_x (x) M_y (x) M_z + M_x (x) P_y (x) M_z + M_x (x) M_y (x) P_z with the
+ * pairs (M_d, P_d) = (M[b][d], P[b][d]), d = x, y, z. */
 typedef struct {
     int32_t n;            /* points per direction, 2 <= n <= 8 (degree p = n-1)       */
     int32_t layout_B;     /* interleave width B, a power of two, 1 <= B <= 1024        */
     int64_t nblocks;      /* number of blocks (0 allowed)                             */
     const double* h;      /* [nblocks][3] edge lengths (x, y, z), host or device,
-                             finite and > 0; copied into the plan at creation        */
+                             finite and > 0; copied into the plan at creation;
+                             null for a factor group                                 */
     int64_t offset;       /* first element of the group in every vector buffer        */
+    const double* M;      /* factor group: [nblocks][3][n][n] row-major per-direction
+                             mass factors, host or device, copied at creation; M_d
+                             must be symmetric positive definite for the inverse    */
+    const double* P;      /* factor group: [nblocks][3][n][n] operator factors (the
+                             stiffness K or the penalized cell operator A)           */
 } tp_group;
 
 /* Kernel mapping of a group's blocks onto the wavefront. */
@@ -138,16 +153,24 @@ int64_t tp_plan_ndof(const tp_plan* plan);
 /* v <- A u for every block of every group, in dtype (storage and contraction
  * operands); FP64 accumulates in FP64, the others in FP32.  u, v: device
  * buffers of tp_plan_vector_elems() elements of dtype.  Sec. 3.1,
- * eq. (eval_pipeline) with P_hat chosen by op. */
+ * eq. (eval_pipeline) with P_hat chosen by op (length groups); factor groups
+ * use their own P and ignore op. */
 tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v,
                    tp_dtype dtype, hipStream_t stream);
 
-/* Fast-diagonalization setup for the operator op (Sec. 5.2): per degree,
- * Cholesky M_hat = L L^T, symmetric Jacobi eigen-decomposition of
- * L^{-1} P_hat L^{-T}, S_hat = L^{-T} Q, in FP64 on the host.  Fails with
- * TP_ERR_SINGULAR when lambda_min <= singular_tol * lambda_max (the Neumann
- * operator, whose constants are in the null space), TP_ERR_NOT_SPD when M_hat
- * is not SPD.  singular_tol <= 0 selects 1e-12.  Host-synchronous. */
+/* Fast-diagonalization setup for the operator op (Sec. 5.2): Cholesky
+ * M = L L^T, symmetric Jacobi eigen-decomposition of L^{-1} P L^{-T},
+ * S = L^{-T} Q, in FP64 on the host: per degree (SCALED) or per block and
+ * direction (GENERAL, host threads; P symmetrized as (P + P^T)/2 first).
+ * op selects P_hat for length groups; factor groups use their own P and
+ * need GENERAL (TP_ERR_UNSUPPORTED with SCALED); a persistent plan supports
+ * SCALED only.  Fails with
+ * TP_ERR_SINGULAR when the smallest eigenvalue sum of a block is <=
+ * singular_tol times its largest (the Neumann operator, whose constants are
+ * in the null space), TP_ERR_NOT_SPD when a mass factor is not SPD; the
+ * message names the first offending block.  singular_tol <= 0 selects
+ * 1e-12.  Host-synchronous; a failed setup leaves the plan without an
+ * inverse (TP_ERR_STATE from later inverse calls). */
 tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode,
                            double singular_tol);
 

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libtpfdm.so")
 
 ARCH = "gfx950"
 HOST_SOURCES = ["api.cpp", "refdata.cpp"]
-DEVICE_SOURCES = ["kernels.hip", "eo.hip", "persistent.hip", "mfma.hip"]
+DEVICE_SOURCES = ["kernels.hip", "eo.hip", "persistent.hip", "mfma.hip", "general.hip"]
 
 
 def hipcc() -> str:
@@ -56,7 +56,7 @@ def build_library(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-pthread"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -3,10 +3,12 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -32,7 +34,7 @@ int esize_of(tp_dtype dt) {
     return 0;
 }
 bool use_lane(const Plan& p, const GroupInfo& g) {
-    return g.n <= kLaneMaxN && p.mapping != TP_MAP_WAVE;
+    return !g.factors && g.n <= kLaneMaxN && p.mapping != TP_MAP_WAVE;
 }
 bool use_mfma(const Plan& p, const GroupInfo& g, tp_dtype dt, const void* a, const void* b) {
     return p.mapping != TP_MAP_WAVE && mfma_eligible(g, dt, a, b);
@@ -52,9 +54,21 @@ tp_status hip_error(int err, const char* what) {
     return set_error(TP_ERR_HIP, std::string(what) + ": " + (s ? s : "unknown HIP error"));
 }
 
+// Frees the per-block eigen-decompositions (and with all, the factors).
+static void free_block_factors(GroupInfo& g, bool all) {
+    if (g.eig) (void)hipFree(g.eig), g.eig = nullptr;
+    if (g.eig32) (void)hipFree(g.eig32), g.eig32 = nullptr;
+    if (all || !g.factors) {
+        if (g.fac) (void)hipFree(g.fac), g.fac = nullptr;
+        if (g.fac32) (void)hipFree(g.fac32), g.fac32 = nullptr;
+    }
+}
+
 static void free_plan_memory(Plan* p) {
-    for (auto& g : p->groups)
+    for (auto& g : p->groups) {
         if (g.h) (void)hipFree(g.h), g.h = nullptr;
+        free_block_factors(g, true);
+    }
     if (p->summary_dev) (void)hipFree(p->summary_dev), p->summary_dev = nullptr;
     if (p->partials_dev) (void)hipFree(p->partials_dev), p->partials_dev = nullptr;
     if (p->segs_dev) (void)hipFree(p->segs_dev), p->segs_dev = nullptr;
@@ -76,6 +90,42 @@ static tp_status alloc_dev(void** ptr, size_t bytes, const char* what) {
     }
     if (e != hipSuccess) return hip_error(e, what);
     return TP_OK;
+}
+
+// Uploads a host FP64 array to new device memory as FP64 and as FP32.
+static tp_status upload_both(const std::vector<double>& h, double** d64, float** d32, const char* what) {
+    tp_status st = alloc_dev(reinterpret_cast<void**>(d64), h.size() * sizeof(double), what);
+    if (st != TP_OK) return st;
+    hipError_t e = hipMemcpy(*d64, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, what);
+    std::vector<float> f(h.begin(), h.end());
+    st = alloc_dev(reinterpret_cast<void**>(d32), f.size() * sizeof(float), what);
+    if (st != TP_OK) return st;
+    e = hipMemcpy(*d32, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, what);
+    return TP_OK;
+}
+
+// Copies a factor group's M and P (host or device, [nblocks][3][n][n]) into
+// plan-owned memory interleaved as [nblocks][3][2][n][n].
+static tp_status copy_factors(GroupInfo& g, const double* M, const double* P, int gi) {
+    const size_t nn = static_cast<size_t>(g.n) * g.n;
+    const size_t cnt = static_cast<size_t>(g.nblocks) * 3 * nn;
+    std::vector<double> hm(cnt), hp(cnt);
+    hipError_t e = hipMemcpy(hm.data(), M, cnt * sizeof(double), hipMemcpyDefault);
+    if (e == hipSuccess) e = hipMemcpy(hp.data(), P, cnt * sizeof(double), hipMemcpyDefault);
+    if (e != hipSuccess) return hip_error(e, "copy of block factors");
+    std::vector<double> fac(2 * cnt);
+    for (size_t bd = 0; bd < static_cast<size_t>(g.nblocks) * 3; ++bd)
+        for (size_t e2 = 0; e2 < nn; ++e2) {
+            const double m = hm[bd * nn + e2], q = hp[bd * nn + e2];
+            if (!std::isfinite(m) || !std::isfinite(q))
+                return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": non-finite factor in block " +
+                                                 std::to_string(bd / 3));
+            fac[(2 * bd) * nn + e2] = m;
+            fac[(2 * bd + 1) * nn + e2] = q;
+        }
+    return upload_both(fac, &g.fac, &g.fac32, "block factors");
 }
 
 tp_status upload_eo(Plan& plan, int n, int tab, const double* vals, int count) {
@@ -100,6 +150,80 @@ struct tp_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
+
+// GENERAL setup of one group: the block factors (given, or built from h
+// and the reference pair of op), then P_d S_d = M_d S_d Lambda_d for every
+// block and direction on host threads, the singularity check per block, and
+// the upload of S and lambda (and of the factors of a length group, which
+// the solve's residual needs).
+static tp_status setup_general(Plan& plan, GroupInfo& g, int gi, int op, double tol) {
+    if (g.nblocks == 0) return TP_OK;
+    const int n = g.n;
+    const size_t nn = static_cast<size_t>(n) * n;
+    const size_t nbd = static_cast<size_t>(g.nblocks) * 3;
+    std::vector<double> fac(nbd * 2 * nn);
+    if (g.factors) {
+        hipError_t e = hipMemcpy(fac.data(), g.fac, fac.size() * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_error(e, "readback of block factors");
+    } else {
+        std::vector<double> h(nbd);
+        hipError_t e = hipMemcpy(h.data(), g.h, h.size() * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_error(e, "readback of h");
+        const RefData& r = plan.ref[n];
+        const double* Ph = op == TP_OP_CELL ? r.A : r.K;
+        for (size_t bd = 0; bd < nbd; ++bd)
+            for (size_t k = 0; k < nn; ++k) {
+                fac[(2 * bd) * nn + k] = h[bd] * r.M[k];
+                fac[(2 * bd + 1) * nn + k] = Ph[k] / h[bd];
+            }
+    }
+    const size_t ne = nn + n;
+    std::vector<double> eig(nbd * ne);
+    std::vector<int64_t> bad_spd(16, INT64_MAX);
+    const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto work = [&](unsigned t) {
+        const size_t lo = nbd * t / nth, hi = nbd * (t + 1) / nth;
+        std::vector<double> M(nn), P(nn);
+        for (size_t bd = lo; bd < hi; ++bd) {
+            const double* Fm = &fac[(2 * bd) * nn];
+            const double* Fp = &fac[(2 * bd + 1) * nn];
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    M[i * n + j] = 0.5 * (Fm[i * n + j] + Fm[j * n + i]);
+                    P[i * n + j] = 0.5 * (Fp[i * n + j] + Fp[j * n + i]);
+                }
+            if (gen_eigen(n, M.data(), P.data(), &eig[bd * ne], &eig[bd * ne + nn]) != 0) {
+                bad_spd[t] = static_cast<int64_t>(bd);
+                return;
+            }
+        }
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nth; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto& th : pool) th.join();
+    const int64_t bad = *std::min_element(bad_spd.begin(), bad_spd.end());
+    if (bad != INT64_MAX)
+        return set_error(TP_ERR_NOT_SPD, "group " + std::to_string(gi) + ": mass factor of block " +
+                                             std::to_string(bad / 3) + " direction " + std::to_string(bad % 3) +
+                                             " is not SPD");
+    for (int64_t b = 0; b < g.nblocks; ++b) {
+        double lo = 0.0, hi = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double* lam = &eig[(3 * b + d) * ne + nn];
+            lo += lam[0];
+            hi += lam[n - 1];
+        }
+        if (!(lo > tol * hi))
+            return set_error(TP_ERR_SINGULAR, "group " + std::to_string(gi) + ": block " + std::to_string(b) +
+                                                  " is singular: smallest/largest eigenvalue sum = " +
+                                                  std::to_string(lo / hi));
+    }
+    tp_status st = TP_OK;
+    if (!g.factors) st = upload_both(fac, &g.fac, &g.fac32, "block factors");
+    if (st == TP_OK) st = upload_both(eig, &g.eig, &g.eig32, "block eigen-decompositions");
+    return st;
+}
 
 extern "C" {
 
@@ -159,7 +283,15 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
         if (g.nblocks < 0 || g.nblocks > (int64_t(1) << 31) - 1)
             return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": nblocks out of range");
         if (g.offset < 0) return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": negative offset");
-        if (g.nblocks > 0 && !g.h) return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": h is null");
+        if ((g.M == nullptr) != (g.P == nullptr))
+            return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": M and P must be given together");
+        if (g.M && g.h)
+            return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": a factor group takes no h");
+        if (g.M && o.persistent)
+            return set_error(TP_ERR_UNSUPPORTED, "group " + std::to_string(gi) +
+                                                     ": factor groups are not supported by persistent plans");
+        if (g.nblocks > 0 && !g.h && !g.M)
+            return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": h is null");
         const int64_t n3 = int64_t(g.n) * g.n * g.n;
         const int64_t tiles = (g.nblocks + g.layout_B - 1) / g.layout_B;
         const int64_t elems = tiles * n3 * g.layout_B;
@@ -197,8 +329,18 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
         block0 += g.nblocks;
         const int64_t tiles = (g.nblocks + g.layout_B - 1) / g.layout_B;
         p->vec_elems = std::max(p->vec_elems, g.offset + tiles * n3 * g.layout_B);
+        info.factors = g.M != nullptr;
         p->groups.push_back(info);
         if (g.nblocks == 0) continue;
+        if (info.factors) {
+            tp_status st = copy_factors(p->groups.back(), g.M, g.P, gi);
+            if (st != TP_OK) {
+                free_plan_memory(p);
+                delete p;
+                return st;
+            }
+            continue;
+        }
         // stage h on the host to validate it, then copy to plan-owned memory
         hbuf.resize(static_cast<size_t>(g.nblocks) * 3);
         e = hipMemcpy(hbuf.data(), g.h, hbuf.size() * sizeof(double), hipMemcpyDefault);
@@ -321,7 +463,8 @@ tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dty
     for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
         const GroupInfo& g = plan->groups[i];
         const RefData& r = plan->ref[g.n];
-        st = use_lane(*plan, g)                ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
+        st = g.factors                         ? launch_apply_gen(*plan, g, u, v, dtype, stream)
+             : use_lane(*plan, g)              ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
              : use_mfma(*plan, g, dtype, u, v) ? launch_apply_mfma(*plan, g, op, u, v, dtype, stream)
                                                : launch_apply_eo(*plan, g, op, u, v, dtype, stream);
     }
@@ -331,9 +474,27 @@ tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dty
 tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, double singular_tol) {
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
     if (!valid_op(op)) return set_error(TP_ERR_ARG, "invalid operator");
-    if (mode != TP_FACTOR_SCALED) return set_error(TP_ERR_UNSUPPORTED, "only TP_FACTOR_SCALED is supported");
+    if (mode != TP_FACTOR_SCALED && mode != TP_FACTOR_GENERAL) return set_error(TP_ERR_ARG, "invalid factor mode");
     if (!(singular_tol > 0.0)) singular_tol = 1e-12;
     plan->inverse_op = -1;
+    for (auto& g : plan->groups) free_block_factors(g, false);
+    if (mode == TP_FACTOR_GENERAL) {
+        if (plan->persistent) return set_error(TP_ERR_UNSUPPORTED, "persistent plans support TP_FACTOR_SCALED only");
+        for (size_t gi = 0; gi < plan->groups.size(); ++gi) {
+            tp_status st = setup_general(*plan, plan->groups[gi], static_cast<int>(gi), op, singular_tol);
+            if (st != TP_OK) {
+                for (auto& g : plan->groups) free_block_factors(g, false);
+                return st;
+            }
+        }
+        plan->factor_mode = TP_FACTOR_GENERAL;
+        plan->inverse_op = op;
+        return TP_OK;
+    }
+    for (const auto& g : plan->groups)
+        if (g.factors)
+            return set_error(TP_ERR_UNSUPPORTED, "groups given by block factors need TP_FACTOR_GENERAL");
+    plan->factor_mode = TP_FACTOR_SCALED;
     for (int n = kMinN; n <= kMaxN; ++n) {
         RefData& r = plan->ref[n];
         r.eig_ready = false;
@@ -388,9 +549,10 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
     tp_status st = TP_OK;
     for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
         const GroupInfo& g = plan->groups[i];
-        st = use_lane(*plan, g)                ? launch_inverse(*plan, g, r, x, dtype, stream)
-             : use_mfma(*plan, g, dtype, r, x) ? launch_inverse_mfma(*plan, g, r, x, dtype, stream)
-                                               : launch_inverse_eo(*plan, g, r, x, dtype, stream);
+        st = plan->factor_mode == TP_FACTOR_GENERAL ? launch_inverse_gen(*plan, g, r, x, dtype, stream)
+             : use_lane(*plan, g)                   ? launch_inverse(*plan, g, r, x, dtype, stream)
+             : use_mfma(*plan, g, dtype, r, x)      ? launch_inverse_mfma(*plan, g, r, x, dtype, stream)
+                                                    : launch_inverse_eo(*plan, g, r, x, dtype, stream);
     }
     return st;
 }
@@ -398,7 +560,7 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
 tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, double rtol, int32_t maxit,
                    int32_t* iters, double* relres, tp_solve_summary* summary, hipStream_t stream) {
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
-    if (plan->inverse_op != TP_OP_CELL)
+    if (plan->inverse_op < 0 || (plan->factor_mode == TP_FACTOR_SCALED && plan->inverse_op != TP_OP_CELL))
         return set_error(TP_ERR_STATE, "tp_solve needs tp_setup_inverse(TP_OP_CELL) first");
     if (inner != TP_F64 && inner != TP_F32 && inner != TP_F16 && inner != TP_BF16)
         return set_error(TP_ERR_ARG, "invalid inner precision");
@@ -416,8 +578,11 @@ tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, do
         for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
             const GroupInfo& g = plan->groups[i];
                 int64_t np = 0;
-            st = g.lane_solve ? launch_solve_lane(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream)
-                              : launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream);
+            st = plan->factor_mode == TP_FACTOR_GENERAL
+                     ? launch_solve_gen(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream)
+                 : g.lane_solve
+                     ? launch_solve_lane(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream)
+                     : launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream);
             nparts += np;
         }
         if (st != TP_OK) return st;

@@ -58,6 +58,12 @@ struct GroupInfo {
     int64_t block0;       // first global block index of the group
     double* h;            // plan-owned device copy, [nblocks][3]
     bool lane_solve;      // solve with one block per lane (else one wave per tile)
+    // GENERAL mode (plan-owned device memory, null when unused)
+    bool factors = false;     // the group is given by per-block factors (no h)
+    double* fac = nullptr;    // [nblocks][3][2][n][n] (M_d, P_d) FP64
+    float* fac32 = nullptr;   // same in FP32
+    double* eig = nullptr;    // [nblocks][3][n*n + n] (S_d, lam_d) FP64
+    float* eig32 = nullptr;   // same in FP32
 };
 
 // One work item of the persistent kernel: a tile of lane-mapped blocks or a
@@ -76,6 +82,7 @@ struct Plan {
     std::vector<GroupInfo> groups;
     RefData ref[kMaxN + 1];
     int inverse_op = -1;
+    int factor_mode = 0;           // tp_factor_mode of the last successful setup
     int64_t vec_elems = 0;
     int64_t ndof = 0;
     int64_t nblocks = 0;
@@ -133,6 +140,14 @@ tp_status launch_solve(const Plan& plan, const GroupInfo& g, const double* b, do
 tp_status launch_solve_lane(const Plan& plan, const GroupInfo& g, const double* b, double* x,
                             tp_dtype inner, double rtol, int maxit, int32_t* iters,
                             double* relres, int64_t part_base, int64_t* nparts, hipStream_t s);
+// GENERAL mode: per-block factors and eigen-decompositions (general.hip).
+tp_status launch_apply_gen(const Plan& plan, const GroupInfo& g, const void* u, void* v, tp_dtype dt,
+                           hipStream_t s);
+tp_status launch_inverse_gen(const Plan& plan, const GroupInfo& g, const void* r, void* x, tp_dtype dt,
+                             hipStream_t s);
+tp_status launch_solve_gen(const Plan& plan, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
+                           double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base,
+                           int64_t* nparts, hipStream_t s);
 // to_blocked: src canonical -> dst blocked; otherwise src blocked -> dst canonical
 tp_status launch_apply_eo(const Plan& plan, const GroupInfo& g, int op, const void* u, void* v,
                           tp_dtype dt, hipStream_t s);

@@ -25,7 +25,7 @@ STATUS = {
 F64, F32, F16, BF16 = 0, 1, 2, 3
 DTYPE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 OP_NEUMANN, OP_CELL = 0, 1
-FACTOR_SCALED = 0
+FACTOR_SCALED, FACTOR_GENERAL = 0, 1
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 
 # The public symbol set declared in include/tpfdm.h.
@@ -48,7 +48,8 @@ class TpfdmError(RuntimeError):
 
 class _Group(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("layout_B", ctypes.c_int32), ("nblocks", ctypes.c_int64),
-                ("h", ctypes.c_void_p), ("offset", ctypes.c_int64)]
+                ("h", ctypes.c_void_p), ("offset", ctypes.c_int64), ("M", ctypes.c_void_p),
+                ("P", ctypes.c_void_p)]
 
 
 class _Opts(ctypes.Structure):
@@ -151,15 +152,18 @@ def _stream(stream):
 
 @dataclass
 class GroupSpec:
-    """One group: n points per direction, interleave width B, edge lengths h (nblocks, 3)."""
+    """One group: n points per direction, interleave width B, and either edge
+    lengths h (nblocks, 3) or per-block factors M, P (nblocks, 3, n, n)."""
     n: int
     layout_B: int
-    h: object            # numpy (host) or torch tensor (host or device), float64 [nblocks, 3]
+    h: object            # numpy (host) or torch tensor (host or device), float64 [nblocks, 3]; None with M, P
     offset: int = -1     # element offset; -1 = place after the previous group
+    M: object = None     # factor group: float64 [nblocks, 3, n, n] mass factors
+    P: object = None     # factor group: float64 [nblocks, 3, n, n] operator factors
 
     @property
     def nblocks(self) -> int:
-        return int(self.h.shape[0])
+        return int((self.h if self.h is not None else self.M).shape[0])
 
     def elems(self) -> int:
         t = (self.nblocks + self.layout_B - 1) // self.layout_B
@@ -181,24 +185,29 @@ class Plan:
         arr = (_Group * max(1, len(groups)))()
         off = 0
         self.groups = []
+        def host_or_device(a):
+            if a is None:
+                return None
+            if isinstance(a, np.ndarray):
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                self._keep.append(a)
+                return a.ctypes.data
+            import torch  # torch tensor, host or device
+            a = a.to(torch.float64).contiguous()
+            self._keep.append(a)
+            return a.data_ptr()
+
         for i, g in enumerate(groups):
-            h = g.h
-            if isinstance(h, np.ndarray):
-                h = np.ascontiguousarray(h, dtype=np.float64)
-                ptr = h.ctypes.data
-            else:  # torch tensor, host or device
-                import torch
-                h = h.to(torch.float64).contiguous()
-                ptr = h.data_ptr()
-            self._keep.append(h)
             o = off if g.offset < 0 else g.offset
             arr[i].n = g.n
             arr[i].layout_B = g.layout_B
             arr[i].nblocks = g.nblocks
-            arr[i].h = ptr
+            arr[i].h = host_or_device(g.h)
             arr[i].offset = o
+            arr[i].M = host_or_device(g.M)
+            arr[i].P = host_or_device(g.P)
             off = o + g.elems()
-            self.groups.append(GroupSpec(g.n, g.layout_B, g.h, o))
+            self.groups.append(GroupSpec(g.n, g.layout_B, g.h, o, g.M, g.P))
         opts = _Opts()
         lib.tp_plan_opts_default(ctypes.byref(opts))
         opts.penalty_C = penalty_C
@@ -232,8 +241,12 @@ class Plan:
     def apply(self, u, v, op: int = OP_NEUMANN, stream=None):
         _check(load().tp_apply(self.handle, op, _ptr(u), _ptr(v), torch_dtype_code(u), _stream(stream)))
 
-    def setup_inverse(self, op: int = OP_CELL, singular_tol: float = 0.0):
-        _check(load().tp_setup_inverse(self.handle, op, FACTOR_SCALED, singular_tol))
+    def setup_inverse(self, op: int = OP_CELL, singular_tol: float = 0.0, mode: int | None = None):
+        """Fast-diagonalization setup; mode defaults to GENERAL when the plan has
+        factor groups, SCALED otherwise."""
+        if mode is None:
+            mode = FACTOR_GENERAL if any(g.M is not None for g in self.groups) else FACTOR_SCALED
+        _check(load().tp_setup_inverse(self.handle, op, mode, singular_tol))
 
     def apply_inverse(self, r, x, stream=None):
         _check(load().tp_apply_inverse(self.handle, _ptr(r), _ptr(x), torch_dtype_code(r), _stream(stream)))

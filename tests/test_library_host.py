@@ -127,3 +127,33 @@ def test_no_device_gives_hip_error():
         pytest.skip("a GPU is present")
     assert _create([(3, 64, 10, 0)]) == -7
     assert "hip" in tpfdm.load().tp_last_error().decode().lower()
+
+
+def _create_factor(n, nb, with_h=False, only_M=False, persistent=False):
+    lib = tpfdm.load()
+    arr = (tpfdm._Group * 1)()
+    M = np.tile(np.eye(n), (nb, 3, 1, 1))
+    h = np.ones((nb, 3))
+    arr[0].n, arr[0].layout_B, arr[0].nblocks, arr[0].offset = n, 1, nb, 0
+    arr[0].h = h.ctypes.data if with_h else None
+    arr[0].M = M.ctypes.data
+    arr[0].P = None if only_M else M.ctypes.data
+    opts = tpfdm._Opts()
+    lib.tp_plan_opts_default(ctypes.byref(opts))
+    opts.persistent = 1 if persistent else 0
+    out = ctypes.c_void_p()
+    st = lib.tp_plan_create(arr, 1, ctypes.byref(opts), ctypes.byref(out))
+    if st == 0:
+        lib.tp_plan_destroy(out)
+    return st
+
+
+def test_factor_group_validation_before_device():
+    assert _create_factor(3, 4, only_M=True) == -1       # M without P
+    assert _create_factor(3, 4, with_h=True) == -1       # factors and h together
+    assert _create_factor(3, 4, persistent=True) == -2   # persistent plans take no factor groups
+
+
+def test_setup_inverse_rejects_unknown_mode():
+    lib = tpfdm.load()
+    assert lib.tp_setup_inverse(None, 1, 7, 0.0) == -1
