@@ -305,8 +305,12 @@ __device__ __forceinline__ void eo_inverse_mid(const Pencil<N>& pc, TC* A1, cons
     wave_sync();
 }
 
-// x = D^{-1} r for one tile: r's z-pencil in registers, result stored to
-// global memory pencil by pencil.
+// x = D^{-1} r for one tile: r's z-pencil in registers, the result stored
+// to global memory from x-pencils.  The 1D transforms along different axes
+// commute, so the phases run z, x forward, then y forward + scaling + y
+// backward, then z and x backward: the last phase is along x, whose lanes
+// (j, k) write consecutive addresses of an x-plane (whole 128-byte lines for
+// n = 8 at every storage type and n = 4 in FP64), like the apply's output.
 template <int N, bool VP, typename TS, typename TC>
 __device__ __forceinline__ void eo_inverse_body(const Pencil<N>& pc, const TC (&r)[N], TS* __restrict__ x,
                                                 const GArgs& G, int64_t g0, TC* A1, const TC* SE, const TC* SO,
@@ -320,13 +324,50 @@ __device__ __forceinline__ void eo_inverse_body(const Pencil<N>& pc, const TC (&
         for (int c = 0; c < N; ++c) A1[L::at(pa, pb, c)] = y[c];
     }
     wave_sync();
-    eo_inverse_mid<N>(pc, A1, SE, SO, lam, sx, sy, sz);
-    if (pc.act) {  // z backward: lane (i, j), pencil stored to global
+    if (pc.act) {  // x forward: lane (j, c)
+        TC a[N], y[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) a[i] = A1[L::at(i, pa, pb)];
+        eo_fwd<N>(SE, SO, a, y);
+#pragma unroll
+        for (int i = 0; i < N; ++i) A1[L::at(i, pa, pb)] = y[i];
+    }
+    wave_sync();
+    if (pc.act) {  // y forward, scaling, y backward: lane (a, c)
+        TC a[N], y[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) a[j] = A1[L::at(pa, j, pb)];
+        eo_fwd<N>(SE, SO, a, y);
+        const TC mu_ac = lam[pa] * sx + lam[pb] * sz;
+#pragma unroll
+        for (int b = 0; b < N; ++b) y[b] *= recip(fma(lam[b], sy, mu_ac));
+        eo_bwd<N>(SE, SO, y, a);
+#pragma unroll
+        for (int j = 0; j < N; ++j) A1[L::at(pa, j, pb)] = a[j];
+    }
+    wave_sync();
+    if (pc.act) {  // z backward: lane (a, j)
         TC y[N], a[N];
 #pragma unroll
         for (int c = 0; c < N; ++c) y[c] = A1[L::at(pa, pb, c)];
         eo_bwd<N>(SE, SO, y, a);
-        pencil_store<N, VP>(const_cast<TS*>(pencil_ptr<N>(x, G, g0 + pc.w, pa, pb)), a, G.logB);
+#pragma unroll
+        for (int k = 0; k < N; ++k) A1[L::at(pa, pb, k)] = a[k];
+    }
+    wave_sync();
+    if (pc.act) {  // x backward: lane (j, k), x-plane rows stored to global memory
+        TC y[N], a[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) y[i] = A1[L::at(i, pa, pb)];
+        eo_bwd<N>(SE, SO, y, a);
+        TS* out = x + G.offset + block_base(g0 + pc.w, G.logB, L::N3);
+        constexpr bool kWholeLines = (N * N * sizeof(TS)) % 128 == 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            TS* o = out + (static_cast<int64_t>((i * N + pa) * N + pb) << G.logB);
+            if constexpr (kWholeLines) stg(o, a[i]);
+            else stc(o, a[i]);
+        }
     }
     wave_sync();
 }
