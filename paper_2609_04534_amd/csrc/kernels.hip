@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64, 2) void k_inverse_lane(const TS* __restrict__ r
 // arguments; M_hat and A_hat are read through their symmetry classes so the
 // scalar registers hold each distinct value once (full FP64 tables of both
 // operators plus the eigenvectors would not fit).
-template <int N, typename TI, int RND, bool NT>
+template <int N, typename TI, int RND, bool NT, int LB>
 __global__ __launch_bounds__(64, 1) void k_solve_lane(const double* __restrict__ b, double* __restrict__ x, GArgs G,
                                                       Pair<N, double> PA, Eig<N, TI> E, int64_t ntiles, double rtol,
                                                       int maxit, int32_t* __restrict__ iters,
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(64, 1) void k_solve_lane(const double* __restrict__
     __shared__ double xs[N * N * N][64];
     SolveAcc acc;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-        lane_solve_tile<N, TI, RND, NT>(b, x, G, RA, E, t, rtol, maxit, iters, relres, block0, acc, xs);
+        lane_solve_tile<N, TI, RND, NT, LB>(b, x, G, RA, E, t, rtol, maxit, iters, relres, block0, acc, xs);
     acc.flush(parts + blockIdx.x);
 }
 
@@ -247,8 +247,9 @@ tp_status solve_lane_n(const Plan& plan, const GroupInfo& g, const double* b, do
     const auto E = make_eig<N, TI>(ref);
     const int64_t ntiles = (g.nblocks + 63) / 64;
     const bool nt = lane_whole_lines<double>(g.logB);
-    const void* kern = nt ? reinterpret_cast<const void*>(&k_solve_lane<N, TI, RND, true>)
-                          : reinterpret_cast<const void*>(&k_solve_lane<N, TI, RND, false>);
+    const void* kern = g.logB == 6 ? reinterpret_cast<const void*>(&k_solve_lane<N, TI, RND, true, 6>)
+                       : nt        ? reinterpret_cast<const void*>(&k_solve_lane<N, TI, RND, true, -1>)
+                                   : reinterpret_cast<const void*>(&k_solve_lane<N, TI, RND, false, -1>);
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64, 0) != hipSuccess || occ <= 0) occ = 1;
     occ = std::min(occ, kMaxWgPerCu);
@@ -256,12 +257,15 @@ tp_status solve_lane_n(const Plan& plan, const GroupInfo& g, const double* b, do
     if (part_base + grid > plan.partials_cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
     SolvePartial* parts = static_cast<SolvePartial*>(plan.partials_dev) + part_base;
     const int64_t block0 = g.block0;
-    if (nt)
-        hipLaunchKernelGGL((k_solve_lane<N, TI, RND, true>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x,
-                           gargs(g), PA, E, ntiles, rtol, maxit, iters, relres, block0, parts);
-    else
-        hipLaunchKernelGGL((k_solve_lane<N, TI, RND, false>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b,
+    if (g.logB == 6)
+        hipLaunchKernelGGL((k_solve_lane<N, TI, RND, true, 6>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b,
                            x, gargs(g), PA, E, ntiles, rtol, maxit, iters, relres, block0, parts);
+    else if (nt)
+        hipLaunchKernelGGL((k_solve_lane<N, TI, RND, true, -1>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b,
+                           x, gargs(g), PA, E, ntiles, rtol, maxit, iters, relres, block0, parts);
+    else
+        hipLaunchKernelGGL((k_solve_lane<N, TI, RND, false, -1>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
+                           b, x, gargs(g), PA, E, ntiles, rtol, maxit, iters, relres, block0, parts);
     *nparts = grid;
     return check_launch("solve (lane) launch");
 }

@@ -179,8 +179,10 @@ __device__ __forceinline__ Pair<N, double> sym_pair(const double (&m)[N * N], co
 // global memory for every residual (cached loads: it stays in L2/MALL), so
 // the register file holds one block-sized array at a time.  A residual of an
 // all-zero x is b itself: the first product is skipped when every x of the
-// wave is zero on entry.  NT: the vectors' rows are whole cache lines.
-template <int N, typename TI, int RND, bool NT>
+// wave is zero on entry.  NT: the vectors' rows are whole cache lines; LB:
+// log2 of the layout width when known at compile time (-1: G.logB), which
+// turns the n^3 element offsets into constants instead of scalar registers.
+template <int N, typename TI, int RND, bool NT, int LB = -1>
 __device__ __forceinline__ void lane_solve_tile(const double* __restrict__ b, double* __restrict__ x, const GArgs& G,
                                                 const Pair<N, double>& RA, const Eig<N, TI>& E, int64_t t,
                                                 double rtol, int maxit, int32_t* __restrict__ iters,
@@ -190,7 +192,7 @@ __device__ __forceinline__ void lane_solve_tile(const double* __restrict__ b, do
     const int lane = threadIdx.x;
     const int64_t g = t * 64 + lane;
     const bool valid = g < G.nblocks;
-    const int lb = G.logB;
+    const int lb = LB >= 0 ? LB : G.logB;
     // lanes past the end read block 0 (in bounds) and discard it: the
     // loads stay unconditional, with no branch per element
     const int64_t base = G.offset + block_base(valid ? g : 0, lb, N3);
@@ -249,7 +251,12 @@ __device__ __forceinline__ void lane_solve_tile(const double* __restrict__ b, do
         TI d[N3];  // scaled residual in the inner precision; r is dead from here on
 #pragma unroll
         for (int q = 0; q < N3; ++q) d[q] = round_to<RND>(static_cast<TI>(r[q] * inv_s));
-        lane_fdm_inplace<N, TI>(d, E, static_cast<TI>(sx), static_cast<TI>(sy), static_cast<TI>(sz));
+        // the n^3 eigenvalue scalings are loop-invariant; recomputing them per
+        // correction is cheaper than the registers the compiler would hold
+        // them in across the loop (an empty asm makes the scalings opaque)
+        TI fsx = static_cast<TI>(sx), fsy = static_cast<TI>(sy), fsz = static_cast<TI>(sz);
+        asm volatile("" : "+v"(fsx), "+v"(fsy), "+v"(fsz));
+        lane_fdm_inplace<N, TI>(d, E, fsx, fsy, fsz);
 #pragma unroll
         for (int q = 0; q < N3; ++q) xs[q][lane] = fma(s, static_cast<double>(round_to<RND>(d[q])), xs[q][lane]);
         if (!done) ++it;

@@ -225,7 +225,11 @@ __device__ __noinline__ void seg_solve(const double* b, double* x, const PSeg& s
             for (int i = 0; i < N; ++i) E.lam[i] = ps[N * N + i];
             double(*xs)[64] = reinterpret_cast<double(*)[64]>(lds);
             const GArgs G = seg_args(sg);
-            if ((static_cast<int64_t>(sizeof(double)) << sg.logB) >= 128) {
+            if (sg.logB == 6) {
+                for (int64_t t = t0; t < sg.tiles_lane; t += gridDim.x)
+                    lane_solve_tile<N, TI, RND, true, 6>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0,
+                                                         acc, xs);
+            } else if ((static_cast<int64_t>(sizeof(double)) << sg.logB) >= 128) {
                 for (int64_t t = t0; t < sg.tiles_lane; t += gridDim.x)
                     lane_solve_tile<N, TI, RND, true>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0, acc,
                                                       xs);
