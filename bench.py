@@ -193,22 +193,30 @@ def main():
     ms_inv = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
     _log(f"apply {ms_apply:.4f} ms, inverse {ms_inv:.4f} ms")
 
-    # solve: FP64 residual + FP32 inner, rtol 1e-10, per-call latency
+    # solve: FP64 residual, rtol 1e-10, per-call latency (launch + sync) for
+    # every inner precision (time to the same final residual)
     bb = torch.empty(E, dtype=torch.float64, device="cuda")
     plan.pack(canon_b, bb)
     xs = torch.zeros(E, dtype=torch.float64, device="cuda")
-    lat = []
-    summ = None
-    for i in range(args.solve_calls + 3):
-        xs.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        summ = plan.solve(bb, xs, inner=tpfdm.F32, rtol=1e-10, maxit=50, stream=stream)
-        t1 = time.perf_counter()
-        if i >= 3:
-            lat.append((t1 - t0) * 1e3)
-    lat = np.array(lat)
-    _log(f"solve p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms {summ}")
+    by_inner = {}
+    for inner in (tpfdm.F64, tpfdm.F32, tpfdm.F16, tpfdm.BF16):
+        lat = []
+        summ = None
+        for i in range(args.solve_calls + 3):
+            xs.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            summ = plan.solve(bb, xs, inner=inner, rtol=1e-10, maxit=50, stream=stream)
+            t1 = time.perf_counter()
+            if i >= 3:
+                lat.append((t1 - t0) * 1e3)
+        lat = np.array(lat)
+        by_inner[tpfdm.DTYPE_NAMES[inner]] = {
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "GDoF/s_p50": ndof / np.percentile(lat, 50) / 1e6, "max_iters": summ["max_iters"],
+            "max_relres": summ["max_relres"]}
+        _log(f"solve inner={tpfdm.DTYPE_NAMES[inner]} p50 {np.percentile(lat, 50):.3f} ms "
+             f"p99 {np.percentile(lat, 99):.3f} ms {summ}")
 
     bytes_launch = algorithmic_bytes(wl, esize)
     dom_name, dom_ms = ("tp_apply_inverse", ms_inv) if ms_inv >= ms_apply else ("tp_apply", ms_apply)
@@ -251,11 +259,9 @@ def main():
                               "GB/s": bytes_launch / ms_inv / 1e6,
                               "TFLOP/s": flops(wl, "inverse") / ms_inv / 1e9},
         },
-        "solve_latency": {"inner": "f32", "rtol": 1e-10, "calls": int(len(lat)),
-                          "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                          "GDoF/s_p50": ndof / np.percentile(lat, 50) / 1e6,
-                          "max_iters": summ["max_iters"] if summ else None,
-                          "max_relres": summ["max_relres"] if summ else None},
+        "solve_latency": {"rtol": 1e-10, "calls": int(args.solve_calls), "residual": "f64",
+                          "by_inner": by_inner,
+                          "fastest_inner": min(by_inner, key=lambda k: by_inner[k]["p50_ms"])},
     }
     if not args.no_cpu_baseline:
         _log("cpu baseline")
@@ -354,9 +360,11 @@ def run_uneven(args, stream):
     cu = torch.from_numpy(np.concatenate([g.u.reshape(-1) for g in wl.groups])).cuda()
     cb = torch.from_numpy(np.concatenate([g.b.reshape(-1) for g in wl.groups])).cuda()
     reps = max(args.steps, 50)
-    for mode in ("per_group", "per_group_graph", "persistent", "persistent_graph"):
+    for mode in ("per_group", "per_group_tuned", "per_group_graph", "persistent", "persistent_graph"):
         plan = tpfdm.Plan(tpfdm.groups_for_workload(wl), persistent=mode.startswith("persistent"))
         plan.setup_inverse(tpfdm.OP_CELL)
+        if mode == "per_group_tuned":
+            plan.autotune(tpfdm.F32)
         E = plan.vector_elems
         u = torch.empty(E, dtype=torch.float32, device="cuda")
         plan.pack(cu.float(), u)

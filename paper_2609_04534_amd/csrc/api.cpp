@@ -39,6 +39,31 @@ bool use_lane(const Plan& p, const GroupInfo& g) {
 bool use_mfma(const Plan& p, const GroupInfo& g, tp_dtype dt, const void* a, const void* b) {
     return p.mapping != TP_MAP_WAVE && mfma_eligible(g, dt, a, b);
 }
+// Kernel family of a group's apply / apply_inverse / solve: the autotuned
+// choice when it applies to this call, else the default rule.
+int apply_kind(const Plan& p, const GroupInfo& g, tp_dtype dt, const void* a, const void* b) {
+    if (g.factors) return KIND_GENERAL;
+    const int t = g.tune_apply[dt];
+    if (t == KIND_LANE && g.n <= kLaneMaxN) return KIND_LANE;
+    if (t == KIND_MFMA && mfma_eligible(g, dt, a, b)) return KIND_MFMA;
+    if (t == KIND_WAVE) return KIND_WAVE;
+    return use_lane(p, g) ? KIND_LANE : use_mfma(p, g, dt, a, b) ? KIND_MFMA : KIND_WAVE;
+}
+int inverse_kind(const Plan& p, const GroupInfo& g, tp_dtype dt, const void* a, const void* b) {
+    if (p.factor_mode == TP_FACTOR_GENERAL) return KIND_GENERAL;
+    const int t = g.tune_inverse[dt];
+    if (t == KIND_LANE && g.n <= kLaneMaxN) return KIND_LANE;
+    if (t == KIND_MFMA && mfma_eligible(g, dt, a, b)) return KIND_MFMA;
+    if (t == KIND_WAVE) return KIND_WAVE;
+    return use_lane(p, g) ? KIND_LANE : use_mfma(p, g, dt, a, b) ? KIND_MFMA : KIND_WAVE;
+}
+int solve_kind(const Plan& p, const GroupInfo& g) {
+    if (p.factor_mode == TP_FACTOR_GENERAL) return KIND_GENERAL;
+    if (g.tune_solve == KIND_LANE && g.n <= kLaneMaxN && !g.factors) return KIND_LANE;
+    if (g.tune_solve == KIND_WAVE) return KIND_WAVE;
+    return g.lane_solve ? KIND_LANE : KIND_WAVE;
+}
+
 bool valid_dtype(int dt) { return dt >= TP_F64 && dt <= TP_BF16; }
 bool valid_op(int op) { return op == TP_OP_NEUMANN || op == TP_OP_CELL; }
 
@@ -223,6 +248,37 @@ static tp_status setup_general(Plan& plan, GroupInfo& g, int gi, int op, double 
     if (!g.factors) st = upload_both(fac, &g.fac, &g.fac32, "block factors");
     if (st == TP_OK) st = upload_both(eig, &g.eig, &g.eig32, "block eigen-decompositions");
     return st;
+}
+
+// One group's call with the kernel family chosen by apply_kind & co.
+static tp_status group_apply(const Plan& p, const GroupInfo& g, int op, const void* u, void* v, tp_dtype dt,
+                             hipStream_t s) {
+    const RefData& r = p.ref[g.n];
+    switch (apply_kind(p, g, dt, u, v)) {
+        case KIND_GENERAL: return launch_apply_gen(p, g, u, v, dt, s);
+        case KIND_LANE: return launch_apply(p, g, op == TP_OP_CELL ? r.A : r.K, u, v, dt, s);
+        case KIND_MFMA: return launch_apply_mfma(p, g, op, u, v, dt, s);
+        default: return launch_apply_eo(p, g, op, u, v, dt, s);
+    }
+}
+static tp_status group_inverse(const Plan& p, const GroupInfo& g, const void* r, void* x, tp_dtype dt,
+                               hipStream_t s) {
+    switch (inverse_kind(p, g, dt, r, x)) {
+        case KIND_GENERAL: return launch_inverse_gen(p, g, r, x, dt, s);
+        case KIND_LANE: return launch_inverse(p, g, r, x, dt, s);
+        case KIND_MFMA: return launch_inverse_mfma(p, g, r, x, dt, s);
+        default: return launch_inverse_eo(p, g, r, x, dt, s);
+    }
+}
+static tp_status group_solve(const Plan& p, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
+                             double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base,
+                             int64_t* nparts, hipStream_t s) {
+    switch (solve_kind(p, g)) {
+        case KIND_GENERAL:
+            return launch_solve_gen(p, g, b, x, inner, rtol, maxit, iters, relres, part_base, nparts, s);
+        case KIND_LANE: return launch_solve_lane(p, g, b, x, inner, rtol, maxit, iters, relres, part_base, nparts, s);
+        default: return launch_solve(p, g, b, x, inner, rtol, maxit, iters, relres, part_base, nparts, s);
+    }
 }
 
 extern "C" {
@@ -461,12 +517,7 @@ tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dty
     if (plan->persistent) return launch_apply_persistent(*plan, op, u, v, dtype, stream);
     tp_status st = TP_OK;
     for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
-        const GroupInfo& g = plan->groups[i];
-        const RefData& r = plan->ref[g.n];
-        st = g.factors                         ? launch_apply_gen(*plan, g, u, v, dtype, stream)
-             : use_lane(*plan, g)              ? launch_apply(*plan, g, op == TP_OP_CELL ? r.A : r.K, u, v, dtype, stream)
-             : use_mfma(*plan, g, dtype, u, v) ? launch_apply_mfma(*plan, g, op, u, v, dtype, stream)
-                                               : launch_apply_eo(*plan, g, op, u, v, dtype, stream);
+        st = group_apply(*plan, plan->groups[i], op, u, v, dtype, stream);
     }
     return st;
 }
@@ -548,11 +599,7 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
     if (plan->persistent) return launch_inverse_persistent(*plan, r, x, dtype, stream);
     tp_status st = TP_OK;
     for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
-        const GroupInfo& g = plan->groups[i];
-        st = plan->factor_mode == TP_FACTOR_GENERAL ? launch_inverse_gen(*plan, g, r, x, dtype, stream)
-             : use_lane(*plan, g)                   ? launch_inverse(*plan, g, r, x, dtype, stream)
-             : use_mfma(*plan, g, dtype, r, x)      ? launch_inverse_mfma(*plan, g, r, x, dtype, stream)
-                                                    : launch_inverse_eo(*plan, g, r, x, dtype, stream);
+        st = group_inverse(*plan, plan->groups[i], r, x, dtype, stream);
     }
     return st;
 }
@@ -578,11 +625,7 @@ tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, do
         for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
             const GroupInfo& g = plan->groups[i];
                 int64_t np = 0;
-            st = plan->factor_mode == TP_FACTOR_GENERAL
-                     ? launch_solve_gen(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream)
-                 : g.lane_solve
-                     ? launch_solve_lane(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream)
-                     : launch_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream);
+            st = group_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream);
             nparts += np;
         }
         if (st != TP_OK) return st;
@@ -720,6 +763,125 @@ tp_status tp_unpack(tp_plan* plan, const void* blocked, void* canonical, tp_dtyp
         if (st != TP_OK) return st;
     }
     return TP_OK;
+}
+
+tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* us) {
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
+    if (plan->persistent) return set_error(TP_ERR_UNSUPPORTED, "persistent plans have no per-group kernel choice");
+    if (reps <= 0) reps = 10;
+    const size_t ng = plan->groups.size();
+    if (us)
+        for (size_t i = 0; i < 3 * ng; ++i) us[i] = -1.0;
+    if (plan->vec_elems == 0) return TP_OK;
+    const bool inv = plan->inverse_op >= 0 && plan->factor_mode == TP_FACTOR_SCALED;
+    const bool solve = inv && plan->inverse_op == TP_OP_CELL;
+    const size_t es = static_cast<size_t>(esize_of(dtype));
+    const size_t ne = static_cast<size_t>(plan->vec_elems);
+    void *u = nullptr, *v = nullptr, *b = nullptr, *x = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    tp_status st = alloc_dev(&u, ne * es, "autotune scratch");
+    if (st == TP_OK) st = alloc_dev(&v, ne * es, "autotune scratch");
+    if (st == TP_OK && solve) st = alloc_dev(&b, ne * sizeof(double), "autotune scratch");
+    if (st == TP_OK && solve) st = alloc_dev(&x, ne * sizeof(double), "autotune scratch");
+    hipError_t e = hipSuccess;
+    if (st == TP_OK) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (st == TP_OK && e == hipSuccess) e = hipEventCreate(&e0);
+    if (st == TP_OK && e == hipSuccess) e = hipEventCreate(&e1);
+    if (st == TP_OK && e != hipSuccess) st = hip_error(e, "autotune stream");
+    if (st == TP_OK) st = launch_fill(u, static_cast<int64_t>(ne), dtype, 1, false, s);
+    if (st == TP_OK && solve) st = launch_fill(b, static_cast<int64_t>(ne), TP_F64, 2, false, s);
+    // average microseconds of reps launches of f (after one warm-up)
+    auto timeit = [&](auto f, double* out) -> tp_status {
+        tp_status r = f();
+        for (int i = 0; r == TP_OK && i < reps; ++i) {
+            if (i == 0) {
+                hipError_t he = hipEventRecord(e0, s);
+                if (he != hipSuccess) return hip_error(he, "autotune event");
+            }
+            r = f();
+        }
+        if (r != TP_OK) return r;
+        hipError_t he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) return hip_error(he, "autotune timing");
+        *out = 1e3 * ms / reps;
+        return TP_OK;
+    };
+    for (size_t gi = 0; st == TP_OK && gi < ng; ++gi) {
+        GroupInfo& g = plan->groups[gi];
+        if (g.nblocks == 0 || g.factors) continue;
+        struct Cand { int kind, div; };
+        std::vector<Cand> cands;
+        if (g.n <= kLaneMaxN) cands.push_back({KIND_LANE, 1});
+        cands.push_back({KIND_WAVE, 1});
+        cands.push_back({KIND_WAVE, 2});
+        if (mfma_eligible(g, dtype, u, v)) cands.push_back({KIND_MFMA, 1});
+        for (int call = 0; st == TP_OK && call < (inv ? 2 : 1); ++call) {
+            int8_t* tk = call == 0 ? &g.tune_apply[dtype] : &g.tune_inverse[dtype];
+            int8_t* td = call == 0 ? &g.div_apply[dtype] : &g.div_inverse[dtype];
+            double best = 1e300;
+            Cand bc = cands[0];
+            for (const Cand& c : cands) {
+                *tk = static_cast<int8_t>(c.kind);
+                *td = static_cast<int8_t>(c.div);
+                double t = 0.0;
+                st = call == 0 ? timeit([&] { return group_apply(*plan, g, TP_OP_NEUMANN, u, v, dtype, s); }, &t)
+                               : timeit([&] { return group_inverse(*plan, g, u, v, dtype, s); }, &t);
+                if (st != TP_OK) break;
+                if (t < best) best = t, bc = c;
+            }
+            *tk = static_cast<int8_t>(bc.kind);
+            *td = static_cast<int8_t>(bc.div);
+            if (us && st == TP_OK) us[3 * gi + call] = best;
+        }
+        if (st == TP_OK && solve && g.n <= kLaneMaxN) {
+            double best = 1e300;
+            int8_t bk = KIND_WAVE;
+            for (int8_t k : {static_cast<int8_t>(KIND_LANE), static_cast<int8_t>(KIND_WAVE)}) {
+                g.tune_solve = k;
+                double t = 0.0;
+                st = timeit(
+                    [&] {
+                        int64_t np = 0;
+                        tp_status r = launch_fill(x, static_cast<int64_t>(ne), TP_F64, 0, true, s);
+                        if (r != TP_OK) return r;
+                        return group_solve(*plan, g, static_cast<const double*>(b), static_cast<double*>(x), TP_F64,
+                                           1e-10, 20, nullptr, nullptr, 0, &np, s);
+                    },
+                    &t);
+                if (st != TP_OK) break;
+                if (t < best) best = t, bk = k;
+            }
+            g.tune_solve = bk;
+            if (us && st == TP_OK) us[3 * gi + 2] = best;
+        }
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    for (void* ptr : {u, v, b, x})
+        if (ptr) (void)hipFree(ptr);
+    return st;
+}
+
+int32_t tp_plan_group_kernel(const tp_plan* plan, int32_t group, int32_t call, tp_dtype dtype) {
+    if (!plan || group < 0 || group >= static_cast<int32_t>(plan->groups.size()) || !valid_dtype(dtype)) return -1;
+    const GroupInfo& g = plan->groups[group];
+    if (plan->persistent) return -1;
+    // alignment-independent view: MFMA eligibility assumes 16-byte aligned vectors
+    alignas(16) static const double probe[2] = {0.0, 0.0};
+    const void* a = probe;
+    switch (call) {
+        case 0: return apply_kind(*plan, g, dtype, a, a);
+        case 1: return inverse_kind(*plan, g, dtype, a, a);
+        case 2: return solve_kind(*plan, g);
+    }
+    return -1;
 }
 
 }  // extern "C"

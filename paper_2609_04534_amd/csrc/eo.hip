@@ -147,6 +147,14 @@ __global__ __launch_bounds__(64, 2) void k_solve_eo(const double* __restrict__ b
     acc.flush(parts + blockIdx.x);
 }
 
+template <typename TS>
+constexpr int dtype_code() {
+    return std::is_same<TS, double>::value ? TP_F64
+           : std::is_same<TS, float>::value ? TP_F32
+           : std::is_same<TS, _Float16>::value ? TP_F16
+                                               : TP_BF16;
+}
+
 tp_status check(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, what);
@@ -188,7 +196,7 @@ tp_status apply_eo_n(const Plan& plan, const GroupInfo& g, int op, const void* u
     static int64_t grid_cache[2] = {0, 0};
     int64_t& gc = grid_cache[vp ? 1 : 0];
     if (gc == 0) gc = persistent_grid(plan, kern, INT64_MAX);
-    const int64_t grid = std::min(gc, ntiles);
+    const int64_t grid = std::min(std::max<int64_t>(1, gc / g.div_apply[dtype_code<TS>()]), ntiles);
     if (vp)
         hipLaunchKernelGGL((k_apply_eo<N, TS, TC, true>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
                            static_cast<const TS*>(u), static_cast<TS*>(v), a, tab, ntiles);
@@ -209,7 +217,7 @@ tp_status inverse_eo_n(const Plan& plan, const GroupInfo& g, const void* r, void
     static int64_t grid_cache[2] = {0, 0};
     int64_t& gc = grid_cache[vp ? 1 : 0];
     if (gc == 0) gc = persistent_grid(plan, kern, INT64_MAX);
-    const int64_t grid = std::min(gc, ntiles);
+    const int64_t grid = std::min(std::max<int64_t>(1, gc / g.div_inverse[dtype_code<TS>()]), ntiles);
     if (vp)
         hipLaunchKernelGGL((k_inverse_eo<N, TS, TC, true>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
                            static_cast<const TS*>(r), static_cast<TS*>(x), a, tab, ntiles);

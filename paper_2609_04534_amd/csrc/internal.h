@@ -64,7 +64,16 @@ struct GroupInfo {
     float* fac32 = nullptr;   // same in FP32
     double* eig = nullptr;    // [nblocks][3][n*n + n] (S_d, lam_d) FP64
     float* eig32 = nullptr;   // same in FP32
+    // choices of tp_plan_autotune (-1: the default rule), per storage dtype
+    int8_t tune_apply[4] = {-1, -1, -1, -1};    // KIND_LANE / KIND_WAVE / KIND_MFMA
+    int8_t tune_inverse[4] = {-1, -1, -1, -1};
+    int8_t tune_solve = -1;                      // KIND_LANE / KIND_WAVE
+    int8_t div_apply[4] = {1, 1, 1, 1};         // wave kernels: persistent grid divisor
+    int8_t div_inverse[4] = {1, 1, 1, 1};
 };
+
+// Kernel families of a group's call (tp_plan_group_kernel reports these).
+enum { KIND_LANE = 0, KIND_WAVE = 1, KIND_MFMA = 2, KIND_GENERAL = 3 };
 
 // One work item of the persistent kernel: a tile of lane-mapped blocks or a
 // single wave-mapped block.
@@ -148,6 +157,9 @@ tp_status launch_inverse_gen(const Plan& plan, const GroupInfo& g, const void* r
 tp_status launch_solve_gen(const Plan& plan, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
                            double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base,
                            int64_t* nparts, hipStream_t s);
+// Fills n elements of dtype dt with pseudo-random values in [-1, 1]
+// (a counter hash of the element index and seed), or zero when zero is set.
+tp_status launch_fill(void* dst, int64_t n, tp_dtype dt, uint64_t seed, bool zero, hipStream_t s);
 // to_blocked: src canonical -> dst blocked; otherwise src blocked -> dst canonical
 tp_status launch_apply_eo(const Plan& plan, const GroupInfo& g, int op, const void* u, void* v,
                           tp_dtype dt, hipStream_t s);

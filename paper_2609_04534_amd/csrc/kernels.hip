@@ -19,6 +19,7 @@
 // where M, P, S, lam are the reference-interval matrices (Sec. 3.1,
 // eq. (eval_pipeline); Sec. 5.2, eq. (cell_block)).
 #include <algorithm>
+#include <type_traits>
 
 #include "lane.h"
 
@@ -141,6 +142,20 @@ __global__ __launch_bounds__(256) void k_summary_reduce(const SolvePartial* __re
         out->pad = 0;
         out->max_relres_bits = static_cast<unsigned long long>(__double_as_longlong(smr[0]));
     }
+}
+
+// Pseudo-random fill for scratch vectors (autotuning): splitmix64 of the
+// element index and seed, mapped to [-1, 1].
+template <typename E>
+__global__ void k_fill(E* __restrict__ dst, int64_t n, uint64_t seed, int zero) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * static_cast<uint64_t>(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double v = zero ? 0.0 : static_cast<double>(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    stc(dst + i, static_cast<typename std::conditional<sizeof(E) == 8, double, float>::type>(v));
 }
 
 // ============================================================ host launchers
@@ -325,6 +340,27 @@ tp_status launch_solve_lane(const Plan& plan, const GroupInfo& g, const double* 
             return solve_lane_dispatch<float, RND_BF16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported inner precision");
+}
+
+tp_status launch_fill(void* dst, int64_t n, tp_dtype dt, uint64_t seed, bool zero, hipStream_t s) {
+    if (n <= 0) return TP_OK;
+    const unsigned grid = static_cast<unsigned>((n + 255) / 256);
+    switch (dt) {
+        case TP_F64:
+            hipLaunchKernelGGL((k_fill<double>), dim3(grid), dim3(256), 0, s, static_cast<double*>(dst), n, seed, zero);
+            break;
+        case TP_F32:
+            hipLaunchKernelGGL((k_fill<float>), dim3(grid), dim3(256), 0, s, static_cast<float*>(dst), n, seed, zero);
+            break;
+        case TP_F16:
+            hipLaunchKernelGGL((k_fill<_Float16>), dim3(grid), dim3(256), 0, s, static_cast<_Float16*>(dst), n, seed,
+                               zero);
+            break;
+        case TP_BF16:
+            hipLaunchKernelGGL((k_fill<bf16_t>), dim3(grid), dim3(256), 0, s, static_cast<bf16_t*>(dst), n, seed, zero);
+            break;
+    }
+    return check_launch("fill launch");
 }
 
 tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize, bool to_blocked,

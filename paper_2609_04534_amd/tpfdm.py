@@ -34,8 +34,9 @@ EXPORTS = (
     "tp_plan_ndof", "tp_plan_nblocks", "tp_apply", "tp_setup_inverse", "tp_apply_inverse",
     "tp_solve", "tp_pack", "tp_unpack", "tp_reference_matrices", "tp_reference_eigen",
     "tp_last_error", "tp_version", "tp_solve_summary_fetch", "tp_graph_create", "tp_graph_launch",
-    "tp_graph_destroy",
+    "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel",
 )
+KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
 
 
@@ -95,6 +96,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_graph_launch": (i32, [vp, vp]),
         "tp_graph_destroy": (i32, [vp]),
         "tp_version": (ctypes.c_char_p, []),
+        "tp_plan_autotune": (i32, [vp, i32, i32, vp]),
+        "tp_plan_group_kernel": (i32, [vp, i32, i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -282,6 +285,17 @@ class Plan:
         _check(load().tp_graph_create(self.handle, what, op, dtype, _ptr(inp), _ptr(out), rtol, maxit,
                                       _ptr(iters), _ptr(relres), ctypes.byref(h)))
         return Graph(h, self)
+
+    def autotune(self, dtype: int = F64, reps: int = 10):
+        """Time the kernel variants per group (tp_plan_autotune) and keep the
+        fastest; returns [(apply_us, inverse_us, solve_us)] per group."""
+        us = (ctypes.c_double * (3 * max(1, len(self.groups))))()
+        _check(load().tp_plan_autotune(self.handle, dtype, reps, us))
+        return [tuple(us[3 * i:3 * i + 3]) for i in range(len(self.groups))]
+
+    def kernel(self, group: int, call: int, dtype: int = F64) -> str:
+        """Kernel family a call would use for a group: lane / wave / mfma / general."""
+        return KIND_NAMES.get(load().tp_plan_group_kernel(self.handle, group, call, dtype), "none")
 
     def pack(self, canonical, blocked, stream=None):
         _check(load().tp_pack(self.handle, _ptr(canonical), _ptr(blocked), torch_dtype_code(canonical),

@@ -509,3 +509,54 @@ def test_mfma_and_vector_paths_agree(dt):
     for k, tol in ((0, TOL_APPLY[dt]), (1, TOL_INV[dt])):
         got, ref = res[tpfdm.MAP_AUTO][k].reshape(40, -1), res[tpfdm.MAP_WAVE][k].reshape(40, -1)
         assert rel_err_blocks(got, ref) < 2 * tol
+
+
+# ------------------------------------------------------------------ autotuning
+@pytest.mark.parametrize("dt", [tpfdm.F64, tpfdm.F32, tpfdm.F16])
+def test_autotune_then_calls_match_oracle(dt):
+    """The kernel chosen per group by tp_plan_autotune computes the same
+    operators (checked against the oracle after tuning)."""
+    torch = _torch()
+    wl = _mixed(nblocks=400, seed=31)
+    with make_plan(wl) as plan:
+        plan.setup_inverse()
+        times = plan.autotune(dt, reps=3)
+        assert len(times) == len(wl.groups)
+        for gi, g in enumerate(wl.groups):
+            if g.nblocks:
+                assert times[gi][0] > 0 and times[gi][1] > 0
+                assert plan.kernel(gi, 0, dt) in ("lane", "wave", "mfma")
+                assert plan.kernel(gi, 2) in ("lane", "wave")
+        print("choices", [(g.p, plan.kernel(i, 0, dt), plan.kernel(i, 1, dt), plan.kernel(i, 2)) for i, g in
+                          enumerate(wl.groups)], "times", times)
+        a, _ = gpu_apply(plan, canon([g.u for g in wl.groups]), dt)
+        i, _ = gpu_inverse(plan, canon([g.u for g in wl.groups]), dt)
+        bb = to_blocked(plan, canon([g.b for g in wl.groups]), tpfdm.F64)
+        bx = torch.zeros_like(bb)
+        s = plan.solve(bb, bx, inner=tpfdm.F32, rtol=1e-10, maxit=30)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    ta = F64_TOL if dt == tpfdm.F64 else TOL_APPLY[dt]
+    ti = F64_TOL if dt == tpfdm.F64 else TOL_INV[dt]
+    for gx, gv, gs, g in zip(split(a, wl.groups), split(i, wl.groups), split(x, wl.groups), wl.groups):
+        if not g.nblocks:
+            continue
+        scale = np.abs(dense.apply(g.p, g.h, np.abs(g.u), dense.NEUMANN)).max(axis=1, keepdims=True)
+        assert np.max(np.abs(gx - dense.apply(g.p, g.h, g.u, dense.NEUMANN)) / scale) < ta
+        assert rel_err_blocks(gv, dense.solve(g.p, g.h, g.u)) < ti
+        assert rel_err_blocks(gs, dense.solve(g.p, g.h, g.b)) < 1e-8
+    assert s["n_failed"] == 0
+
+
+def test_default_kernel_choices_and_persistent_autotune():
+    wl = _mixed(nblocks=200, seed=32)
+    with make_plan(wl) as plan:
+        for gi, g in enumerate(wl.groups):
+            want = "lane" if g.p <= 3 else "wave"
+            assert plan.kernel(gi, 0, tpfdm.F64) == want
+    # MFMA for n = 8 in FP16 when the group starts 16-byte aligned (offset 0 here)
+    with make_plan(workloads.random_blocks(7, 10, seed=33)) as plan:
+        assert plan.kernel(0, 0, tpfdm.F16) == "mfma" and plan.kernel(0, 0, tpfdm.F64) == "wave"
+    with make_plan(wl, persistent=True) as plan:
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            plan.autotune(tpfdm.F32)
+        assert e.value.status == -2
