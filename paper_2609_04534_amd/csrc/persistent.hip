@@ -1,17 +1,17 @@
-// Persistent single-launch kernels over all groups of a plan (batches of
-// uneven degree).
+// Single-launch kernels over all groups of a plan (batches of uneven
+// degree).
 //
 // Every group is a segment of work tiles: 64 blocks per tile for the
-// lane-per-block mapping (apply / apply_inverse with n <= 4) and BPW blocks
-// per tile for the wave-per-tile mapping.  One launch of a fixed grid of
-// one-wave workgroups walks the segments in order; inside a segment the
-// tiles are dealt round-robin, and the starting wave of each segment is
-// rotated by the tiles dealt so far, so the whole batch behaves like one
-// round-robin deal over the concatenated tile list (every wave ends within
-// one tile of its fair share).  The deal is static: no counters, no atomics,
-// nothing to reset, which keeps the launch capturable in a HIP graph and its
-// results bitwise reproducible.  Factor tables of a segment are loaded once
-// per wave when the wave enters the segment.
+// lane-per-block mapping and BPW blocks per tile for the wave-per-tile
+// mapping.  The tiles of all segments form one list; apply and
+// apply_inverse launch one one-wave workgroup per tile of that list, which
+// finds its segment by a scan of the (few) segment starts and runs the
+// group's tile body, inlined per degree (no calls, no scratch; each switch
+// branch has its own registers).  The solve runs a fixed grid whose
+// workgroups walk the list with the grid stride, so its per-workgroup
+// summaries fit the plan's partials.  No counters or atomics: the launch is
+// capturable in a HIP graph and its results are bitwise those of the
+// per-group launches.  Factor tables are loaded per tile.
 #include <algorithm>
 #include <climits>
 #include <vector>
@@ -32,6 +32,8 @@ struct PSeg {
     int32_t n;
     int32_t lane;         // apply / apply_inverse use the lane-per-block mapping
     int32_t lane_solve;   // the solve uses the lane-per-block mapping
+    int64_t first_tile;   // apply / apply_inverse: first tile in the flat tile list
+    int64_t first_tile_solve;  // the same for the solve's tiles
 };
 
 namespace {
@@ -72,7 +74,7 @@ __device__ __forceinline__ void seg_apply_lane(const TS* __restrict__ u, TS* __r
         R.p[i] = ptab[N * N + i];
     }
     const int lb = sg.logB;
-    for (int64_t t = t0; t < sg.tiles_lane; t += gridDim.x) {
+    for (int64_t t = t0; t < sg.tiles_lane; t = sg.tiles_lane) {
         const int64_t g = t * 64 + threadIdx.x;
         if (g >= sg.nblocks) continue;
         const int64_t base = sg.offset + block_base(g, lb, N * N * N);
@@ -99,7 +101,7 @@ __device__ __forceinline__ void seg_apply_wave(const TS* __restrict__ u, TS* __r
     const int lp = lane - lw * L::N2;
     const int li = lp / N, lj = lp - (lp / N) * N;
     const int so = (lw < L::BPW ? lw : 0) * L::size;
-    for (int64_t t = t0; t < sg.tiles_wave; t += gridDim.x) {
+    for (int64_t t = t0; t < sg.tiles_wave; t = sg.tiles_wave) {
         const int64_t g0 = t * L::BPW;
         const int nvalid = nvalid_of<N>(G, t);
         const Pencil<N> pc(nvalid);
@@ -112,7 +114,7 @@ __device__ __forceinline__ void seg_apply_wave(const TS* __restrict__ u, TS* __r
 }
 
 template <int N, typename TS, typename TC>
-__device__ __noinline__ void seg_apply(const TS* u, TS* v, const PSeg& sg, const char* tabs, int op, bool vp,
+__device__ __forceinline__ void seg_apply(const TS* u, TS* v, const PSeg& sg, const char* tabs, int op, bool vp,
                                           TC* lds, int64_t t0) {
     const int et = sizeof(TC) == 8 ? 0 : 1;
     if constexpr (N <= kLaneMaxN) {
@@ -143,7 +145,7 @@ __device__ __forceinline__ void seg_inverse_lane(const TS* __restrict__ r, TS* _
 #pragma unroll
     for (int i = 0; i < N; ++i) E.lam[i] = ptab[N * N + i];
     const int lb = sg.logB;
-    for (int64_t t = t0; t < sg.tiles_lane; t += gridDim.x) {
+    for (int64_t t = t0; t < sg.tiles_lane; t = sg.tiles_lane) {
         const int64_t g = t * 64 + threadIdx.x;
         if (g >= sg.nblocks) continue;
         const int64_t base = sg.offset + block_base(g, lb, N * N * N);
@@ -174,7 +176,7 @@ __device__ __forceinline__ void seg_inverse_wave(const TS* __restrict__ r, TS* _
     const int lp = lane - lw * L::N2;
     const int li = lp / N, lj = lp - (lp / N) * N;
     const int so = (lw < L::BPW ? lw : 0) * L::size;
-    for (int64_t t = t0; t < sg.tiles_wave; t += gridDim.x) {
+    for (int64_t t = t0; t < sg.tiles_wave; t = sg.tiles_wave) {
         const int64_t g0 = t * L::BPW;
         const int nvalid = nvalid_of<N>(G, t);
         const Pencil<N> pc(nvalid);
@@ -187,7 +189,7 @@ __device__ __forceinline__ void seg_inverse_wave(const TS* __restrict__ r, TS* _
 }
 
 template <int N, typename TS, typename TC>
-__device__ __noinline__ void seg_inverse(const TS* r, TS* x, const PSeg& sg, const char* tabs, bool vp, TC* lds,
+__device__ __forceinline__ void seg_inverse(const TS* r, TS* x, const PSeg& sg, const char* tabs, bool vp, TC* lds,
                                             int64_t t0) {
     const int et = sizeof(TC) == 8 ? 0 : 1;
     if constexpr (N <= kLaneMaxN) {
@@ -209,7 +211,7 @@ __device__ __noinline__ void seg_inverse(const TS* r, TS* x, const PSeg& sg, con
 
 // ------------------------------------------------------------ solve
 template <int N, typename TI, int RND>
-__device__ __noinline__ void seg_solve(const double* b, double* x, const PSeg& sg, const char* tabs, char* lds,
+__device__ __forceinline__ void seg_solve(const double* b, double* x, const PSeg& sg, const char* tabs, char* lds,
                                           int64_t t0, double rtol, int maxit, int32_t* iters, double* relres,
                                           SolveAcc& acc) {
     using S = EOShape<N>;
@@ -226,15 +228,15 @@ __device__ __noinline__ void seg_solve(const double* b, double* x, const PSeg& s
             double(*xs)[64] = reinterpret_cast<double(*)[64]>(lds);
             const GArgs G = seg_args(sg);
             if (sg.logB == 6) {
-                for (int64_t t = t0; t < sg.tiles_lane; t += gridDim.x)
+                for (int64_t t = t0; t < sg.tiles_lane; t = sg.tiles_lane)
                     lane_solve_tile<N, TI, RND, true, 6>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0,
                                                          acc, xs);
             } else if ((static_cast<int64_t>(sizeof(double)) << sg.logB) >= 128) {
-                for (int64_t t = t0; t < sg.tiles_lane; t += gridDim.x)
+                for (int64_t t = t0; t < sg.tiles_lane; t = sg.tiles_lane)
                     lane_solve_tile<N, TI, RND, true>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0, acc,
                                                       xs);
             } else {
-                for (int64_t t = t0; t < sg.tiles_lane; t += gridDim.x)
+                for (int64_t t = t0; t < sg.tiles_lane; t = sg.tiles_lane)
                     lane_solve_tile<N, TI, RND, false>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0, acc,
                                                        xs);
             }
@@ -253,38 +255,42 @@ __device__ __noinline__ void seg_solve(const double* b, double* x, const PSeg& s
         S::SE + S::SO + N);
     const TI* lam = stabS + S::SE + S::SO;
     const GArgs G = seg_args(sg);
-    for (int64_t t = t0; t < sg.tiles_wave; t += gridDim.x)
+    for (int64_t t = t0; t < sg.tiles_wave; t = sg.tiles_wave)
         eo_solve_tile<N, TI, RND>(b, x, G, t * Slab<N>::BPW, nvalid_of<N>(G, t), L, A, I, lam, rtol, maxit, iters,
                                   relres, sg.block0, acc);
 }
 
-__device__ __forceinline__ int64_t first_tile(int64_t rot) {
-    const int64_t G = gridDim.x;
-    return (static_cast<int64_t>(blockIdx.x) - rot % G + G) % G;
+
+// Segment of the flat tile w: segments in order, each covering the tiles
+// [first_tile, first_tile + tiles) of the launch (apply / apply_inverse).
+__device__ __forceinline__ int flat_segment(const PSeg* __restrict__ segs, int nseg, int64_t w) {
+    int si = 0;
+    while (si + 1 < nseg && segs[si + 1].first_tile <= w) ++si;
+    return si;
 }
 
+// One launch over all groups: one workgroup per tile of the concatenated
+// tile list, the group's body inlined per degree (no calls, no scratch).
+// Every tile is independent, so the hardware dispatcher balances the mix.
 template <typename TS, typename TC>
 __global__ __launch_bounds__(64, 2) void k_persist_apply(const TS* __restrict__ u, TS* __restrict__ v,
                                                          const PSeg* __restrict__ segs, int nseg,
                                                          const char* __restrict__ tabs, int op,
                                                          unsigned long long vpmask) {
     __shared__ __align__(16) TC lds[2 * kMaxSlab + 64];
-    int64_t rot = 0;
-    for (int si = 0; si < nseg; ++si) {
-        const PSeg sg = segs[si];
-        const int64_t t0 = first_tile(rot);
-        const bool vp = si < 64 && ((vpmask >> si) & 1ull);
-        switch (sg.n) {
-            case 2: seg_apply<2, TS, TC>(u, v, sg, tabs, op, vp, lds, t0); break;
-            case 3: seg_apply<3, TS, TC>(u, v, sg, tabs, op, vp, lds, t0); break;
-            case 4: seg_apply<4, TS, TC>(u, v, sg, tabs, op, vp, lds, t0); break;
-            case 5: seg_apply<5, TS, TC>(u, v, sg, tabs, op, vp, lds, t0); break;
-            case 6: seg_apply<6, TS, TC>(u, v, sg, tabs, op, vp, lds, t0); break;
-            case 7: seg_apply<7, TS, TC>(u, v, sg, tabs, op, vp, lds, t0); break;
-            case 8: seg_apply<8, TS, TC>(u, v, sg, tabs, op, vp, lds, t0); break;
-            default: break;
-        }
-        rot = (rot + (sg.lane ? sg.tiles_lane : sg.tiles_wave)) % gridDim.x;
+    const int si = flat_segment(segs, nseg, blockIdx.x);
+    const PSeg sg = segs[si];
+    const int64_t t = static_cast<int64_t>(blockIdx.x) - sg.first_tile;
+    const bool vp = si < 64 && ((vpmask >> si) & 1ull);
+    switch (sg.n) {
+        case 2: seg_apply<2, TS, TC>(u, v, sg, tabs, op, vp, lds, t); break;
+        case 3: seg_apply<3, TS, TC>(u, v, sg, tabs, op, vp, lds, t); break;
+        case 4: seg_apply<4, TS, TC>(u, v, sg, tabs, op, vp, lds, t); break;
+        case 5: seg_apply<5, TS, TC>(u, v, sg, tabs, op, vp, lds, t); break;
+        case 6: seg_apply<6, TS, TC>(u, v, sg, tabs, op, vp, lds, t); break;
+        case 7: seg_apply<7, TS, TC>(u, v, sg, tabs, op, vp, lds, t); break;
+        case 8: seg_apply<8, TS, TC>(u, v, sg, tabs, op, vp, lds, t); break;
+        default: break;
     }
 }
 
@@ -293,48 +299,47 @@ __global__ __launch_bounds__(64, 2) void k_persist_inverse(const TS* __restrict_
                                                            const PSeg* __restrict__ segs, int nseg,
                                                            const char* __restrict__ tabs, unsigned long long vpmask) {
     __shared__ __align__(16) TC lds[kMaxSlab + 64];
-    int64_t rot = 0;
-    for (int si = 0; si < nseg; ++si) {
-        const PSeg sg = segs[si];
-        const int64_t t0 = first_tile(rot);
-        const bool vp = si < 64 && ((vpmask >> si) & 1ull);
-        switch (sg.n) {
-            case 2: seg_inverse<2, TS, TC>(r, x, sg, tabs, vp, lds, t0); break;
-            case 3: seg_inverse<3, TS, TC>(r, x, sg, tabs, vp, lds, t0); break;
-            case 4: seg_inverse<4, TS, TC>(r, x, sg, tabs, vp, lds, t0); break;
-            case 5: seg_inverse<5, TS, TC>(r, x, sg, tabs, vp, lds, t0); break;
-            case 6: seg_inverse<6, TS, TC>(r, x, sg, tabs, vp, lds, t0); break;
-            case 7: seg_inverse<7, TS, TC>(r, x, sg, tabs, vp, lds, t0); break;
-            case 8: seg_inverse<8, TS, TC>(r, x, sg, tabs, vp, lds, t0); break;
-            default: break;
-        }
-        rot = (rot + (sg.lane ? sg.tiles_lane : sg.tiles_wave)) % gridDim.x;
+    const int si = flat_segment(segs, nseg, blockIdx.x);
+    const PSeg sg = segs[si];
+    const int64_t t = static_cast<int64_t>(blockIdx.x) - sg.first_tile;
+    const bool vp = si < 64 && ((vpmask >> si) & 1ull);
+    switch (sg.n) {
+        case 2: seg_inverse<2, TS, TC>(r, x, sg, tabs, vp, lds, t); break;
+        case 3: seg_inverse<3, TS, TC>(r, x, sg, tabs, vp, lds, t); break;
+        case 4: seg_inverse<4, TS, TC>(r, x, sg, tabs, vp, lds, t); break;
+        case 5: seg_inverse<5, TS, TC>(r, x, sg, tabs, vp, lds, t); break;
+        case 6: seg_inverse<6, TS, TC>(r, x, sg, tabs, vp, lds, t); break;
+        case 7: seg_inverse<7, TS, TC>(r, x, sg, tabs, vp, lds, t); break;
+        case 8: seg_inverse<8, TS, TC>(r, x, sg, tabs, vp, lds, t); break;
+        default: break;
     }
 }
 
+// The solve over all groups: workgroups walk the concatenated tile list of
+// the solve (one tile per step, the group's body inlined per degree).
 template <typename TI, int RND>
 __global__ __launch_bounds__(64, 1) void k_persist_solve(const double* __restrict__ b, double* __restrict__ x,
                                                          const PSeg* __restrict__ segs, int nseg,
                                                          const char* __restrict__ tabs, double rtol, int maxit,
                                                          int32_t* __restrict__ iters, double* __restrict__ relres,
-                                                         SolvePartial* parts) {
+                                                         int64_t total, SolvePartial* parts) {
     __shared__ __align__(16) char lds[kSolveLdsBytes];
     SolveAcc acc;
-    int64_t rot = 0;
-    for (int si = 0; si < nseg; ++si) {
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        int si = 0;
+        while (si + 1 < nseg && segs[si + 1].first_tile_solve <= w) ++si;
         const PSeg sg = segs[si];
-        const int64_t t0 = first_tile(rot);
+        const int64_t t = w - sg.first_tile_solve;
         switch (sg.n) {
-            case 2: seg_solve<2, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 3: seg_solve<3, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 4: seg_solve<4, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 5: seg_solve<5, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 6: seg_solve<6, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 7: seg_solve<7, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
-            case 8: seg_solve<8, TI, RND>(b, x, sg, tabs, lds, t0, rtol, maxit, iters, relres, acc); break;
+            case 2: seg_solve<2, TI, RND>(b, x, sg, tabs, lds, t, rtol, maxit, iters, relres, acc); break;
+            case 3: seg_solve<3, TI, RND>(b, x, sg, tabs, lds, t, rtol, maxit, iters, relres, acc); break;
+            case 4: seg_solve<4, TI, RND>(b, x, sg, tabs, lds, t, rtol, maxit, iters, relres, acc); break;
+            case 5: seg_solve<5, TI, RND>(b, x, sg, tabs, lds, t, rtol, maxit, iters, relres, acc); break;
+            case 6: seg_solve<6, TI, RND>(b, x, sg, tabs, lds, t, rtol, maxit, iters, relres, acc); break;
+            case 7: seg_solve<7, TI, RND>(b, x, sg, tabs, lds, t, rtol, maxit, iters, relres, acc); break;
+            case 8: seg_solve<8, TI, RND>(b, x, sg, tabs, lds, t, rtol, maxit, iters, relres, acc); break;
             default: break;
         }
-        rot = (rot + (sg.lane_solve ? sg.tiles_lane : sg.tiles_wave)) % gridDim.x;
     }
     acc.flush(parts + blockIdx.x);
 }
@@ -378,10 +383,8 @@ tp_status check_p(const char* what) {
 
 template <typename TS, typename TC>
 tp_status papply(const Plan& plan, int op, const void* u, void* v, hipStream_t s) {
-    const void* kern = reinterpret_cast<const void*>(&k_persist_apply<TS, TC>);
-    static int64_t gc = 0;
-    if (gc == 0) gc = pgrid(plan, kern);
-    const int64_t grid = std::max<int64_t>(1, std::min(gc, total_tiles(plan, false)));
+    const int64_t grid = total_tiles(plan, false);   // one workgroup per tile
+    if (grid <= 0) return TP_OK;
     hipLaunchKernelGGL((k_persist_apply<TS, TC>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
                        static_cast<const TS*>(u), static_cast<TS*>(v), static_cast<const PSeg*>(plan.segs_dev),
                        static_cast<int>(plan.groups.size()), static_cast<const char*>(plan.eo_dev), op,
@@ -391,10 +394,8 @@ tp_status papply(const Plan& plan, int op, const void* u, void* v, hipStream_t s
 
 template <typename TS, typename TC>
 tp_status pinverse(const Plan& plan, const void* r, void* x, hipStream_t s) {
-    const void* kern = reinterpret_cast<const void*>(&k_persist_inverse<TS, TC>);
-    static int64_t gc = 0;
-    if (gc == 0) gc = pgrid(plan, kern);
-    const int64_t grid = std::max<int64_t>(1, std::min(gc, total_tiles(plan, false)));
+    const int64_t grid = total_tiles(plan, false);
+    if (grid <= 0) return TP_OK;
     hipLaunchKernelGGL((k_persist_inverse<TS, TC>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
                        static_cast<const TS*>(r), static_cast<TS*>(x), static_cast<const PSeg*>(plan.segs_dev),
                        static_cast<int>(plan.groups.size()), static_cast<const char*>(plan.eo_dev),
@@ -413,7 +414,7 @@ tp_status psolve(const Plan& plan, const double* b, double* x, double rtol, int 
     *nparts = grid;
     hipLaunchKernelGGL((k_persist_solve<TI, RND>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x,
                        static_cast<const PSeg*>(plan.segs_dev), static_cast<int>(plan.groups.size()),
-                       static_cast<const char*>(plan.eo_dev), rtol, maxit, iters, relres,
+                       static_cast<const char*>(plan.eo_dev), rtol, maxit, iters, relres, total_tiles(plan, true),
                        static_cast<SolvePartial*>(plan.partials_dev));
     return check_p("persistent solve launch");
 }
@@ -422,6 +423,7 @@ tp_status psolve(const Plan& plan, const double* b, double* x, double rtol, int 
 
 tp_status persistent_setup(Plan& plan) {
     std::vector<PSeg> segs;
+    int64_t first = 0, first_solve = 0;
     for (const auto& g : plan.groups) {
         PSeg s{};
         s.h = g.h;
@@ -434,6 +436,10 @@ tp_status persistent_setup(Plan& plan) {
         s.n = g.n;
         s.lane = (g.n <= kLaneMaxN && plan.mapping != TP_MAP_WAVE) ? 1 : 0;
         s.lane_solve = g.lane_solve ? 1 : 0;
+        s.first_tile = first;
+        first += s.lane ? s.tiles_lane : s.tiles_wave;
+        s.first_tile_solve = first_solve;
+        first_solve += s.lane_solve ? s.tiles_lane : s.tiles_wave;
         segs.push_back(s);
     }
     if (segs.empty()) return TP_OK;
