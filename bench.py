@@ -316,8 +316,15 @@ def run_suite(args, stream):
             ms_i = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
             # a plain device copy of the same vector: the bandwidth reachable at this size
             ms_c = time_launches(lambda k: X[k].copy_(U[k]), stream, reps, R)
+            # the same after per-group autotuning of the kernel choice
+            plan.autotune(code, reps=5)
+            ms_at = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
+            ms_it = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
+            tuned = {"apply_ms": ms_at, "inverse_ms": ms_it,
+                     "kernels": [(plan.kernel(i, 0, code, grid=True), plan.kernel(i, 1, code, grid=True))
+                                 for i in range(len(wl.groups))]}
             ab = algorithmic_bytes(wl, es)
-            rec = {"workload": name, "dtype": dtn, "ndof": ndof, "buffer_sets": R,
+            rec = {"workload": name, "dtype": dtn, "ndof": ndof, "buffer_sets": R, "tuned": tuned,
                    "cache_resident": 3 * R * vec_bytes < 0.75e9,
                    "copy_ms": ms_c, "copy_GB/s": 2 * vec_bytes / ms_c / 1e6,
                    "apply_ms": ms_a, "apply_GDoF/s": ndof / ms_a / 1e6, "apply_GB/s": ab / ms_a / 1e6,

@@ -238,7 +238,8 @@ tp_status tp_unpack(tp_plan* plan, const void* blocked, void* canonical, tp_dtyp
  * the given storage dtype, times apply (Neumann), apply_inverse (when set up
  * in SCALED mode) and the FP64-inner solve (when set up for TP_OP_CELL) with
  * every applicable variant -- one block per lane (n <= 4), one wave per tile
- * with the full or half occupancy grid, MFMA (n = 8 FP16/BF16, B = 1) -- on
+ * with the full or half occupancy grid or one workgroup per tile, MFMA
+ * (n = 8 FP16/BF16, B = 1) -- on
  * plan-sized scratch vectors of pseudo-random values, and keeps the fastest
  * per group and call for later calls in that dtype (the solve's choice for
  * every inner precision).  us: optional host array [ngroups][3] that receives
@@ -247,10 +248,12 @@ tp_status tp_unpack(tp_plan* plan, const void* blocked, void* canonical, tp_dtyp
  * and frees its scratch.  TP_ERR_UNSUPPORTED for persistent plans. */
 tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* us);
 
-/* Kernel family a call would use for a group in dtype: 0 one block per lane,
- * 1 one wave per tile, 2 MFMA, 3 per-block factors (GENERAL); call 0 apply,
- * 1 apply_inverse, 2 solve (dtype ignored).  -1 for a persistent plan or an
- * invalid argument.  MFMA assumes 16-byte aligned vectors. */
+/* Kernel family a call would use for a group in dtype, in the low 4 bits:
+ * 0 one block per lane, 1 one wave per tile, 2 MFMA, 3 per-block factors
+ * (GENERAL); for apply / apply_inverse with one wave per tile, bits 4-7 hold
+ * the grid (1 full occupancy grid, 2 half, 0 one workgroup per tile).  call
+ * 0 apply, 1 apply_inverse, 2 solve (dtype ignored).  -1 for a persistent
+ * plan or an invalid argument.  MFMA assumes 16-byte aligned vectors. */
 int32_t tp_plan_group_kernel(const tp_plan* plan, int32_t group, int32_t call, tp_dtype dtype);
 
 /* Number of blocks in the plan (sum over groups). */

@@ -778,11 +778,23 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
     const bool solve = inv && plan->inverse_op == TP_OP_CELL;
     const size_t es = static_cast<size_t>(esize_of(dtype));
     const size_t ne = static_cast<size_t>(plan->vec_elems);
+    // rotate over enough scratch pairs that one pass streams from HBM rather
+    // than from the last-level cache (>= 768 MB touched per rotation)
+    const size_t pair_bytes = 2 * ne * es;
+    const int nsets = static_cast<int>(std::max<size_t>(1, std::min<size_t>(8, (768u << 20) / pair_bytes + 1)));
+    void* U[8] = {};
+    void* V[8] = {};
     void *u = nullptr, *v = nullptr, *b = nullptr, *x = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    tp_status st = alloc_dev(&u, ne * es, "autotune scratch");
-    if (st == TP_OK) st = alloc_dev(&v, ne * es, "autotune scratch");
+    tp_status st = TP_OK;
+    for (int k = 0; st == TP_OK && k < nsets; ++k) {
+        st = alloc_dev(&U[k], ne * es, "autotune scratch");
+        if (st == TP_OK) st = alloc_dev(&V[k], ne * es, "autotune scratch");
+    }
+    u = U[0];
+    v = V[0];
+    int cur = 0;  // scratch pair of the next timed call
     if (st == TP_OK && solve) st = alloc_dev(&b, ne * sizeof(double), "autotune scratch");
     if (st == TP_OK && solve) st = alloc_dev(&x, ne * sizeof(double), "autotune scratch");
     hipError_t e = hipSuccess;
@@ -790,7 +802,7 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
     if (st == TP_OK && e == hipSuccess) e = hipEventCreate(&e0);
     if (st == TP_OK && e == hipSuccess) e = hipEventCreate(&e1);
     if (st == TP_OK && e != hipSuccess) st = hip_error(e, "autotune stream");
-    if (st == TP_OK) st = launch_fill(u, static_cast<int64_t>(ne), dtype, 1, false, s);
+    for (int k = 0; st == TP_OK && k < nsets; ++k) st = launch_fill(U[k], static_cast<int64_t>(ne), dtype, 1, false, s);
     if (st == TP_OK && solve) st = launch_fill(b, static_cast<int64_t>(ne), TP_F64, 2, false, s);
     // average microseconds of reps launches of f (after one warm-up)
     auto timeit = [&](auto f, double* out) -> tp_status {
@@ -819,6 +831,7 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
         if (g.n <= kLaneMaxN) cands.push_back({KIND_LANE, 1});
         cands.push_back({KIND_WAVE, 1});
         cands.push_back({KIND_WAVE, 2});
+        cands.push_back({KIND_WAVE, 0});
         if (mfma_eligible(g, dtype, u, v)) cands.push_back({KIND_MFMA, 1});
         for (int call = 0; st == TP_OK && call < (inv ? 2 : 1); ++call) {
             int8_t* tk = call == 0 ? &g.tune_apply[dtype] : &g.tune_inverse[dtype];
@@ -829,8 +842,18 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
                 *tk = static_cast<int8_t>(c.kind);
                 *td = static_cast<int8_t>(c.div);
                 double t = 0.0;
-                st = call == 0 ? timeit([&] { return group_apply(*plan, g, TP_OP_NEUMANN, u, v, dtype, s); }, &t)
-                               : timeit([&] { return group_inverse(*plan, g, u, v, dtype, s); }, &t);
+                st = call == 0 ? timeit(
+                                     [&] {
+                                         cur = (cur + 1) % nsets;
+                                         return group_apply(*plan, g, TP_OP_NEUMANN, U[cur], V[cur], dtype, s);
+                                     },
+                                     &t)
+                               : timeit(
+                                     [&] {
+                                         cur = (cur + 1) % nsets;
+                                         return group_inverse(*plan, g, U[cur], V[cur], dtype, s);
+                                     },
+                                     &t);
                 if (st != TP_OK) break;
                 if (t < best) best = t, bc = c;
             }
@@ -864,7 +887,11 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (s) (void)hipStreamDestroy(s);
-    for (void* ptr : {u, v, b, x})
+    for (int k = 0; k < nsets; ++k) {
+        if (U[k]) (void)hipFree(U[k]);
+        if (V[k]) (void)hipFree(V[k]);
+    }
+    for (void* ptr : {b, x})
         if (ptr) (void)hipFree(ptr);
     return st;
 }
@@ -877,8 +904,14 @@ int32_t tp_plan_group_kernel(const tp_plan* plan, int32_t group, int32_t call, t
     alignas(16) static const double probe[2] = {0.0, 0.0};
     const void* a = probe;
     switch (call) {
-        case 0: return apply_kind(*plan, g, dtype, a, a);
-        case 1: return inverse_kind(*plan, g, dtype, a, a);
+        case 0: {
+            const int k = apply_kind(*plan, g, dtype, a, a);
+            return k == KIND_WAVE ? k | (g.div_apply[dtype] << 4) : k;
+        }
+        case 1: {
+            const int k = inverse_kind(*plan, g, dtype, a, a);
+            return k == KIND_WAVE ? k | (g.div_inverse[dtype] << 4) : k;
+        }
         case 2: return solve_kind(*plan, g);
     }
     return -1;

@@ -196,7 +196,8 @@ tp_status apply_eo_n(const Plan& plan, const GroupInfo& g, int op, const void* u
     static int64_t grid_cache[2] = {0, 0};
     int64_t& gc = grid_cache[vp ? 1 : 0];
     if (gc == 0) gc = persistent_grid(plan, kern, INT64_MAX);
-    const int64_t grid = std::min(std::max<int64_t>(1, gc / g.div_apply[dtype_code<TS>()]), ntiles);
+    const int div = g.div_apply[dtype_code<TS>()];  // 0: one workgroup per tile
+    const int64_t grid = div == 0 ? ntiles : std::min(std::max<int64_t>(1, gc / div), ntiles);
     if (vp)
         hipLaunchKernelGGL((k_apply_eo<N, TS, TC, true>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
                            static_cast<const TS*>(u), static_cast<TS*>(v), a, tab, ntiles);
@@ -217,7 +218,8 @@ tp_status inverse_eo_n(const Plan& plan, const GroupInfo& g, const void* r, void
     static int64_t grid_cache[2] = {0, 0};
     int64_t& gc = grid_cache[vp ? 1 : 0];
     if (gc == 0) gc = persistent_grid(plan, kern, INT64_MAX);
-    const int64_t grid = std::min(std::max<int64_t>(1, gc / g.div_inverse[dtype_code<TS>()]), ntiles);
+    const int div = g.div_inverse[dtype_code<TS>()];
+    const int64_t grid = div == 0 ? ntiles : std::min(std::max<int64_t>(1, gc / div), ntiles);
     if (vp)
         hipLaunchKernelGGL((k_inverse_eo<N, TS, TC, true>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s,
                            static_cast<const TS*>(r), static_cast<TS*>(x), a, tab, ntiles);

@@ -68,7 +68,7 @@ struct GroupInfo {
     int8_t tune_apply[4] = {-1, -1, -1, -1};    // KIND_LANE / KIND_WAVE / KIND_MFMA
     int8_t tune_inverse[4] = {-1, -1, -1, -1};
     int8_t tune_solve = -1;                      // KIND_LANE / KIND_WAVE
-    int8_t div_apply[4] = {1, 1, 1, 1};         // wave kernels: persistent grid divisor
+    int8_t div_apply[4] = {1, 1, 1, 1};         // wave kernels: persistent grid divisor (0: one per tile)
     int8_t div_inverse[4] = {1, 1, 1, 1};
 };
 

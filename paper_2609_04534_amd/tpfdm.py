@@ -293,9 +293,14 @@ class Plan:
         _check(load().tp_plan_autotune(self.handle, dtype, reps, us))
         return [tuple(us[3 * i:3 * i + 3]) for i in range(len(self.groups))]
 
-    def kernel(self, group: int, call: int, dtype: int = F64) -> str:
-        """Kernel family a call would use for a group: lane / wave / mfma / general."""
-        return KIND_NAMES.get(load().tp_plan_group_kernel(self.handle, group, call, dtype), "none")
+    def kernel(self, group: int, call: int, dtype: int = F64, grid: bool = False) -> str:
+        """Kernel family a call would use for a group: lane / wave / mfma / general
+        (with grid=True, wave kernels also report their grid: full / half / tile)."""
+        code = load().tp_plan_group_kernel(self.handle, group, call, dtype)
+        name = KIND_NAMES.get(code & 15 if code >= 0 else code, "none")
+        if grid and name == "wave" and call != 2:
+            name += "/" + {1: "full", 2: "half", 0: "tile"}.get(code >> 4, "?")
+        return name
 
     def pack(self, canonical, blocked, stream=None):
         _check(load().tp_pack(self.handle, _ptr(canonical), _ptr(blocked), torch_dtype_code(canonical),
