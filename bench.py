@@ -117,8 +117,9 @@ def main():
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "f16", "bf16"],
                     help="storage precision of the step (default: the workload's)")
     ap.add_argument("--counters", action="store_true",
-                    help="no timing: launch apply, apply_inverse and a plain device copy of one "
-                         "vector 3 times each (for hardware-counter runs), then exit")
+                    help="no timing: launch a plain device copy of one vector, apply and "
+                         "apply_inverse 3 times each and one FP64- and one FP32-inner solve "
+                         "(for hardware-counter runs), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the blocks are independent and each GPU would run the "
@@ -172,6 +173,11 @@ def main():
             plan.apply(U[k % R], V[k % R], tpfdm.OP_NEUMANN, stream=stream)
         for k in range(3):
             plan.apply_inverse(V[k % R], X[k % R], stream=stream)
+        bb = torch.empty(E, dtype=torch.float64, device="cuda")
+        plan.pack(canon_b, bb)
+        for inner in (tpfdm.F64, tpfdm.F32):
+            xs = torch.zeros_like(bb)
+            plan.solve(bb, xs, inner=inner, rtol=1e-10, maxit=50, summary=False, stream=stream)
         torch.cuda.synchronize()
         print(json.dumps({"counters_run": args.workload, "copy_bytes": E * esize,
                           "algorithmic_bytes_per_launch": algorithmic_bytes(wl, esize)}), flush=True)

@@ -467,12 +467,14 @@ __device__ __forceinline__ void eo_inverse_lds(const Pencil<N>& pc, TC* slab, co
 }
 
 // ------------------------------------------------------------ solve tile
-// LDS workspace of one solve tile.
+// LDS workspace of one solve tile: the iterate x and two scratch slabs; the
+// product lands in t1 and the scaled residual (in the inner precision) in
+// t2, so the whole tile needs three slabs.
 template <int N, typename TI>
 struct SolveLds {
     static constexpr int SZ = Slab<N>::BPW * Slab<N>::size;
-    double xs[SZ], bs[SZ], ra[SZ], t1[SZ], t2[SZ];
-    TI rs[SZ];
+    static_assert(sizeof(TI) <= sizeof(double), "inner type wider than the slab");
+    double xs[SZ], t1[SZ], t2[SZ];
     double part[2][64];
     double red[3][Slab<N>::BPW];
     int done[Slab<N>::BPW];
@@ -480,12 +482,13 @@ struct SolveLds {
 
 // Block-local iterative refinement of one tile (a wave, BPW blocks), with
 // the block operator and the inner inverse given as callables on the LDS
-// slabs (apply_lds(pc, src, dst, t1, t2) in FP64, inverse_lds(pc, slab) in
-// TI, both for the lane's pencil pc):
+// slabs (apply_lds(pc, src, dst, t1, t2) in FP64 with dst allowed to be t1,
+// inverse_lds(pc, slab) in TI, both for the lane's pencil pc):
 //   r = b - D x (FP64), s = ||r||_inf, d = D~^{-1} (r / s) in precision TI
 //   (input and output rounded to FP16 / BF16 for RND),
 //   x <- x + s d (FP64), until ||r||_2 <= rtol ||b||_2 or maxit corrections.
-// x and b stay in LDS for all iterations (b read once, x written once);
+// x stays in LDS for all iterations (read once, written once); each lane
+// reads its z-pencil of b for every residual (from cache after the first);
 // per-block norms are reduced over the block's pencils through LDS.
 template <int N, typename TI, int RND, typename ApplyF, typename InvF>
 __device__ __forceinline__ void solve_tile(const double* __restrict__ b, double* __restrict__ x, const GArgs& G,
@@ -497,9 +500,7 @@ __device__ __forceinline__ void solve_tile(const double* __restrict__ b, double*
     for (int e = threadIdx.x; e < nvalid * L::N3; e += 64) {
         const int w = e / L::N3;
         const int q = e - w * L::N3;
-        const int64_t a = G.offset + block_base(g0 + w, G.logB, L::N3) + (static_cast<int64_t>(q) << G.logB);
-        S.bs[w * L::size + L::lin(q)] = b[a];
-        const double xv = x[a];
+        const double xv = x[G.offset + block_base(g0 + w, G.logB, L::N3) + (static_cast<int64_t>(q) << G.logB)];
         S.xs[w * L::size + L::lin(q)] = xv;
         nz = nz || xv != 0.0;
     }
@@ -509,13 +510,15 @@ __device__ __forceinline__ void solve_tile(const double* __restrict__ b, double*
     const Pencil<N> pc(nvalid);
     const int lane = threadIdx.x;
     const int so = (pc.w < L::BPW ? pc.w : 0) * L::size;
-    wave_sync();
+    TI* rs = reinterpret_cast<TI*>(S.t2) + so;
+    const double* bpen = pc.act ? pencil_ptr<N>(b, G, g0 + pc.w, pc.pa, pc.pb) : b;
     double bsq = 0.0;
-    if (pc.act)
-        for (int k = 0; k < N; ++k) {
-            const double bv = S.bs[so + L::at(pc.pa, pc.pb, k)];
-            bsq = fma(bv, bv, bsq);
-        }
+    if (pc.act) {
+        double bp[N];
+        pencil_load<N, false>(bp, bpen, G.logB);
+#pragma unroll
+        for (int k = 0; k < N; ++k) bsq = fma(bp[k], bp[k], bsq);
+    }
     S.part[0][lane] = bsq;
     wave_sync();
     if (pc.act && pc.pa == 0 && pc.pb == 0) {
@@ -531,16 +534,20 @@ __device__ __forceinline__ void solve_tile(const double* __restrict__ b, double*
     if (pc.act && bn == 0.0)
         for (int k = 0; k < N; ++k) S.xs[so + L::at(pc.pa, pc.pb, k)] = 0.0;
     for (;;) {
-        if (need_apply) apply_lds(pc, S.xs + so, S.ra + so, S.t1 + so, S.t2 + so);
+        if (need_apply) apply_lds(pc, S.xs + so, S.t1 + so, S.t1 + so, S.t2 + so);
         double rr = 0.0, rmax = 0.0;
-        if (pc.act)
+        if (pc.act) {  // the residual overwrites the product in t1; b is re-read (cached)
+            double bp[N];
+            pencil_load<N, false>(bp, bpen, G.logB);
+#pragma unroll
             for (int k = 0; k < N; ++k) {
                 const int a = so + L::at(pc.pa, pc.pb, k);
-                const double rv = need_apply ? S.bs[a] - S.ra[a] : S.bs[a];
-                S.ra[a] = rv;
+                const double rv = need_apply ? bp[k] - S.t1[a] : bp[k];
+                S.t1[a] = rv;
                 rr = fma(rv, rv, rr);
                 rmax = fmax(rmax, fabs(rv));
             }
+        }
         S.part[0][lane] = rr;
         S.part[1][lane] = rmax;
         wave_sync();
@@ -565,16 +572,17 @@ __device__ __forceinline__ void solve_tile(const double* __restrict__ b, double*
         const double rmax_b = pc.act ? S.red[2][pc.w] : 0.0;
         const double inv_s = (pc.act && !mine_done && rmax_b > 0.0) ? 1.0 / rmax_b : 0.0;
         if (pc.act)
-            for (int k = 0; k < N; ++k) {
-                const int a = so + L::at(pc.pa, pc.pb, k);
-                S.rs[a] = round_to<RND>(static_cast<TI>(S.ra[a] * inv_s));
-            }
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+                rs[L::at(pc.pa, pc.pb, k)] =
+                    round_to<RND>(static_cast<TI>(S.t1[so + L::at(pc.pa, pc.pb, k)] * inv_s));
         wave_sync();
-        inverse_lds(pc, S.rs + so);
+        inverse_lds(pc, rs);
         if (pc.act && !mine_done) {
+#pragma unroll
             for (int k = 0; k < N; ++k) {
                 const int a = so + L::at(pc.pa, pc.pb, k);
-                S.xs[a] = fma(rmax_b, static_cast<double>(round_to<RND>(S.rs[a])), S.xs[a]);
+                S.xs[a] = fma(rmax_b, static_cast<double>(round_to<RND>(rs[L::at(pc.pa, pc.pb, k)])), S.xs[a]);
             }
             ++it;
         }
