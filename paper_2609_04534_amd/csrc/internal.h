@@ -68,8 +68,11 @@ struct GroupInfo {
     int8_t tune_apply[4] = {-1, -1, -1, -1};    // KIND_LANE / KIND_WAVE / KIND_MFMA
     int8_t tune_inverse[4] = {-1, -1, -1, -1};
     int8_t tune_solve = -1;                      // KIND_LANE / KIND_WAVE
-    int8_t div_apply[4] = {1, 1, 1, 1};         // wave kernels: persistent grid divisor (0: one per tile)
-    int8_t div_inverse[4] = {1, 1, 1, 1};
+    // wave kernels: persistent grid divisor (0: one workgroup per tile); the
+    // default is the occupancy grid for FP64 and one workgroup per tile for
+    // the 2- and 4-byte types (measured faster at n = 8)
+    int8_t div_apply[4] = {1, 0, 0, 0};
+    int8_t div_inverse[4] = {1, 0, 0, 0};
 };
 
 // Kernel families of a group's call (tp_plan_group_kernel reports these).
