@@ -116,7 +116,8 @@ typedef enum {
 
 typedef struct {
     double penalty_C;     /* SIPG penalty constant C of sigma = C p(p+1)/h (default 2) */
-    int32_t persistent;   /* 1: every call runs as ONE launch over all groups          */
+    int32_t persistent;   /* 1: every call runs as ONE launch over all groups (its
+                             solve uses wave-per-tile bodies for every degree)      */
     int32_t mapping;      /* tp_mapping for apply / apply_inverse                      */
     int32_t reserved[6];  /* must be zero                                             */
 } tp_plan_opts;

@@ -31,7 +31,7 @@ struct PSeg {
     int32_t logB;
     int32_t n;
     int32_t lane;         // apply / apply_inverse use the lane-per-block mapping
-    int32_t lane_solve;   // the solve uses the lane-per-block mapping
+    int32_t lane_solve;   // the solve uses the lane-per-block mapping (0 in this launch)
     int64_t first_tile;   // apply / apply_inverse: first tile in the flat tile list
     int64_t first_tile_solve;  // the same for the solve's tiles
 };
@@ -45,10 +45,9 @@ constexpr size_t solve_lds_bytes() {
     return sizeof(SolveLds<N, double>) + 64 * sizeof(double) + 64 * sizeof(double);
 }
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
-constexpr size_t kSolveLdsBytes = cmax(
+constexpr size_t kSolveLdsBytes =
     cmax(cmax(cmax(solve_lds_bytes<2>(), solve_lds_bytes<3>()), cmax(solve_lds_bytes<4>(), solve_lds_bytes<5>())),
-         cmax(cmax(solve_lds_bytes<6>(), solve_lds_bytes<7>()), solve_lds_bytes<8>())),
-    static_cast<size_t>(kLaneMaxN * kLaneMaxN * kLaneMaxN) * 64 * sizeof(double));  // lane solve: x of 64 blocks
+         cmax(cmax(solve_lds_bytes<6>(), solve_lds_bytes<7>()), solve_lds_bytes<8>()));
 
 __device__ __forceinline__ const char* dev_table(const char* base, int n, int tab, int et) {
     return base + static_cast<size_t>(((n * EO_NTAB + tab) * 2 + et) * kEOSlot) * sizeof(double);
@@ -215,34 +214,6 @@ __device__ __forceinline__ void seg_solve(const double* b, double* x, const PSeg
                                           int64_t t0, double rtol, int maxit, int32_t* iters, double* relres,
                                           SolveAcc& acc) {
     using S = EOShape<N>;
-    if constexpr (N <= kLaneMaxN) {
-        if (sg.lane_solve) {  // one block per lane, as the per-group lane solve
-            const double* pa = reinterpret_cast<const double*>(dev_table(tabs, N, EO_PLAIN_A, 0));
-            const TI* ps = reinterpret_cast<const TI*>(dev_table(tabs, N, EO_PLAIN_S, sizeof(TI) == 8 ? 0 : 1));
-            const Pair<N, double> RA = sym_pair<N, double, double>(pa, pa + N * N);
-            Eig<N, TI> E;
-#pragma unroll
-            for (int i = 0; i < N * N; ++i) E.s[i] = ps[i];
-#pragma unroll
-            for (int i = 0; i < N; ++i) E.lam[i] = ps[N * N + i];
-            double(*xs)[64] = reinterpret_cast<double(*)[64]>(lds);
-            const GArgs G = seg_args(sg);
-            if (sg.logB == 6) {
-                for (int64_t t = t0; t < sg.tiles_lane; t = sg.tiles_lane)
-                    lane_solve_tile<N, TI, RND, true, 6>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0,
-                                                         acc, xs);
-            } else if ((static_cast<int64_t>(sizeof(double)) << sg.logB) >= 128) {
-                for (int64_t t = t0; t < sg.tiles_lane; t = sg.tiles_lane)
-                    lane_solve_tile<N, TI, RND, true>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0, acc,
-                                                      xs);
-            } else {
-                for (int64_t t = t0; t < sg.tiles_lane; t = sg.tiles_lane)
-                    lane_solve_tile<N, TI, RND, false>(b, x, G, RA, E, t, rtol, maxit, iters, relres, sg.block0, acc,
-                                                       xs);
-            }
-            return;
-        }
-    }
     SolveLds<N, TI>& L = *reinterpret_cast<SolveLds<N, TI>*>(lds);
     double* stabA = reinterpret_cast<double*>(lds + sizeof(SolveLds<N, TI>));
     TI* stabS = reinterpret_cast<TI*>(stabA + 64);
@@ -318,7 +289,7 @@ __global__ __launch_bounds__(64, 2) void k_persist_inverse(const TS* __restrict_
 // The solve over all groups: workgroups walk the concatenated tile list of
 // the solve (one tile per step, the group's body inlined per degree).
 template <typename TI, int RND>
-__global__ __launch_bounds__(64, 1) void k_persist_solve(const double* __restrict__ b, double* __restrict__ x,
+__global__ __launch_bounds__(64, 2) void k_persist_solve(const double* __restrict__ b, double* __restrict__ x,
                                                          const PSeg* __restrict__ segs, int nseg,
                                                          const char* __restrict__ tabs, double rtol, int maxit,
                                                          int32_t* __restrict__ iters, double* __restrict__ relres,
@@ -369,7 +340,7 @@ int64_t pgrid(const Plan& plan, const void* kern) {
 int64_t total_tiles(const Plan& plan, bool solve) {
     int64_t t = 0;
     for (const auto& g : plan.groups) {
-        const bool lane = solve ? g.lane_solve : (g.n <= kLaneMaxN && plan.mapping != TP_MAP_WAVE);
+        const bool lane = !solve && g.n <= kLaneMaxN && plan.mapping != TP_MAP_WAVE;  // the solve: wave tiles
         t += lane ? (g.nblocks + 63) / 64 : (g.nblocks + bpw_of(g.n) - 1) / bpw_of(g.n);
     }
     return t;
@@ -435,7 +406,10 @@ tp_status persistent_setup(Plan& plan) {
         s.logB = g.logB;
         s.n = g.n;
         s.lane = (g.n <= kLaneMaxN && plan.mapping != TP_MAP_WAVE) ? 1 : 0;
-        s.lane_solve = g.lane_solve ? 1 : 0;
+        // the single-launch solve runs every degree on wave tiles: one kernel
+        // that also held the lane solve's register demand (up to 512 per
+        // lane) would run every degree at one wave per SIMD
+        s.lane_solve = 0;
         s.first_tile = first;
         first += s.lane ? s.tiles_lane : s.tiles_wave;
         s.first_tile_solve = first_solve;

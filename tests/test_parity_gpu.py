@@ -425,9 +425,10 @@ def test_persistent_solve_mixed(inner, mapping):
             iters = torch.zeros(plan.nblocks, dtype=torch.int32, device="cuda")
             s = plan.solve(bb, bx, inner=inner, rtol=1e-10, maxit=30, iters=iters)
             res[persistent] = (from_blocked(plan, bx, tpfdm.F64), iters.cpu().numpy(), s)
-    assert np.array_equal(res[False][0], res[True][0])
-    assert np.array_equal(res[False][1], res[True][1])
-    assert res[True][2]["n_failed"] == 0
+    if mapping != tpfdm.MAP_LANE:  # the single launch solves on wave tiles, as AUTO does for these sizes
+        assert np.array_equal(res[False][0], res[True][0])
+        assert np.array_equal(res[False][1], res[True][1])
+    assert res[True][2]["n_failed"] == 0 and res[False][2]["n_failed"] == 0
     for g, gx in zip(wl.groups, split(res[True][0], wl.groups)):
         ref = dense.solve(g.p, g.h, g.b)
         kappa = max(dense.condition_number(g.p, h) for h in g.h[:3])
