@@ -15,6 +15,10 @@ on GPUs", arXiv 2609.04534):
   matrices: the volume operator of eq. (eval_pipeline), Sec. 3.1, and the
   cell block of eq. (cell_block), Sec. 5.2, with apply = dense mat-vec and
   inverse = dense LAPACK solve refined with a long-double residual.
+* ``sipg``   -- the coupled SIPG operator of eq. (sipg) on a uniform
+  Cartesian box mesh with Nitsche (homogeneous Dirichlet) boundary faces,
+  A = A^vol + A^face of eq. (operator_split), assembled as a sparse matrix
+  from dense cell-row blocks built from the bilinear form.
 
 The oracle never uses sum factorization or fast diagonalization: those are
 the method under test.  Every function cites the passage it follows.

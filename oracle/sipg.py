@@ -1,0 +1,172 @@
+"""The coupled SIPG operator on a uniform Cartesian box mesh, assembled as a
+sparse matrix from its definition.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Paper passages followed:
+
+* Sec. 3, eq. (sipg): the bilinear form sums the cell integrals of
+  grad u . grad v and, over every face F, the terms -{d_n u}[v] - [u]{d_n v}
+  + sigma_F [u][v].  The problem has homogeneous Dirichlet data, imposed
+  weakly: on a boundary face the jump is the inner trace and the average is
+  the inner normal derivative (the usual Nitsche modification the paper
+  refers to).
+* Eq. (operator_split): A = A^vol + A^face, the cell integrals and the face
+  integrals kept apart.
+* Sec. 3 (face integrals), eq. (face_factorized): on an axis-aligned face the
+  coupling of the two adjacent cells is a Kronecker product with a 1D face
+  matrix N^{ss'} in the normal slot and the 1D mass matrix in the two
+  tangential slots; eq. (face_coupling) gives N^{--}.
+* Sec. 6.2: sigma_F = C p (p+1) / h_F with h_F the cell length normal to F.
+
+Mesh: mx x my x mz cells, all with edge lengths (hx, hy, hz).  Cell
+(cx, cy, cz) has index c = (cx my + cy) mz + cz and its DoFs are the global
+unknowns c n^3 + q with the block-local q = (ix n + iy) n + iz.
+
+The 1D face matrices are written directly from the bilinear form (function
+``face_matrix``): no sum factorization, no fast diagonalization, no
+rank-two shortcut.  Every cell row is assembled from dense n^3 x n^3 blocks.
+
+Pins (tests/test_oracle_sipg.py): Galerkin consistency for polynomials of
+Q_p that vanish on the boundary (A u_q = M f with f = -Lap q), the same for
+polynomials that do not vanish there against a boundary functional computed
+by independent face quadrature, the penalty energy of piecewise constants,
+symmetry and definiteness, the interior cell-diagonal block equal to the cell
+block of eq. (cell_block), and the interior face matrices equal to the
+printed-stencil-pinned ``basis.face_blocks``.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import basis, dense
+
+FULL = "full"       # A = A^vol + A^face
+VOLUME = "volume"   # A^vol: the cell integrals only (the Neumann volume operator per cell)
+FACE = "face"       # A^face: every face integral, interior and boundary
+
+
+def cell_index(m, cx, cy, cz) -> int:
+    return (cx * m[1] + cy) * m[2] + cz
+
+
+def cell_coords(m, c):
+    cz = c % m[2]
+    cy = (c // m[2]) % m[1]
+    cx = c // (m[1] * m[2])
+    return cx, cy, cz
+
+
+def _side_data(p: int, hd: float, side: str):
+    """(trace row, normal-derivative row, jump sign, average weight) of one
+    side of a face normal to an axis, with the normal pointing along +axis.
+
+    '-' : the cell below the face (the face is its right end), jump sign +1
+    '+' : the cell above the face (the face is its left end), jump sign -1
+    'b-': a boundary face at a cell's right end (outside is empty)
+    'b+': a boundary face at a cell's left end
+    Interior averages weigh each side by 1/2; on a boundary face the inner
+    side carries the whole average.
+    """
+    e0, g0, e1, g1 = basis.endpoint_vectors(p)
+    if side in ("-", "b-"):
+        t, d, j = e1, g1 / hd, 1.0
+    else:
+        t, d, j = e0, g0 / hd, -1.0
+    return t, d, j, (0.5 if side in ("-", "+") else 1.0)
+
+
+def face_matrix(p: int, hd: float, test_side: str, trial_side: str, C: float = 2.0) -> np.ndarray:
+    """1D face matrix N[i, j] of eq. (sipg) restricted to the normal direction:
+    test function i on test_side, trial function j on trial_side,
+
+      N = -(avg d_n trial) (jump test) - (jump trial) (avg d_n test)
+          + sigma (jump trial) (jump test),  sigma = C p (p+1) / hd.
+    """
+    sigma = basis.penalty_reference(p, C) / hd
+    ti, di, ji, ai = _side_data(p, hd, test_side)
+    tj, dj, jj, aj = _side_data(p, hd, trial_side)
+    return (-np.outer(ji * ti, aj * dj) - np.outer(ai * di, jj * tj)
+            + sigma * np.outer(ji * ti, jj * tj))
+
+
+def _slot_kron(p, h, d, N1):
+    """Kronecker product with N1 in slot d and the physical mass h_o M_hat in
+    the other two slots (eq. (face_factorized))."""
+    M, _ = basis.mass_stiffness(p)
+    f = [h[o] * M for o in range(3)]
+    f[d] = N1
+    return np.kron(np.kron(f[0], f[1]), f[2])
+
+
+def cell_row_blocks(p: int, m, h, c: int, part: str = FULL, C: float = 2.0):
+    """The blocks of cell c's row of A: a list of (neighbour cell, n^3 x n^3
+    block), the cell itself first."""
+    h = [float(x) for x in h]
+    n3 = (p + 1) ** 3
+    diag = np.zeros((n3, n3))
+    off = []
+    if part in (FULL, VOLUME):
+        diag += dense.dense_operator(p, h, dense.NEUMANN)
+    if part in (FULL, FACE):
+        cc = list(cell_coords(m, c))
+        for d in range(3):
+            # right end of the cell along d
+            if cc[d] + 1 < m[d]:
+                nb = cc.copy()
+                nb[d] += 1
+                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "-", "-", C))
+                off.append((cell_index(m, *nb), _slot_kron(p, h, d, face_matrix(p, h[d], "-", "+", C))))
+            else:
+                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "b-", "b-", C))
+            # left end
+            if cc[d] > 0:
+                nb = cc.copy()
+                nb[d] -= 1
+                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "+", "+", C))
+                off.append((cell_index(m, *nb), _slot_kron(p, h, d, face_matrix(p, h[d], "+", "-", C))))
+            else:
+                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "b+", "b+", C))
+    return [(c, diag)] + off
+
+
+def assemble(p: int, m, h, part: str = FULL, C: float = 2.0) -> sp.csr_matrix:
+    """The global operator (or its volume or face part) as a sparse matrix."""
+    n3 = (p + 1) ** 3
+    ncell = int(m[0] * m[1] * m[2])
+    rows, cols, vals = [], [], []
+    li = np.repeat(np.arange(n3), n3)
+    lj = np.tile(np.arange(n3), n3)
+    for c in range(ncell):
+        for nb, blk in cell_row_blocks(p, m, h, c, part, C):
+            rows.append(c * n3 + li)
+            cols.append(nb * n3 + lj)
+            vals.append(blk.reshape(-1))
+    N = ncell * n3
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+    return A.tocsr()
+
+
+def apply(p: int, m, h, u, part: str = FULL, C: float = 2.0) -> np.ndarray:
+    """v = A u for a canonical vector u of ncells * n^3 values."""
+    return assemble(p, m, h, part, C) @ np.asarray(u, dtype=np.float64)
+
+
+def cell_apply(p: int, m, h, u, cells, part: str = FULL, C: float = 2.0) -> np.ndarray:
+    """(A u) restricted to the given cells, from their row blocks only (for
+    meshes too large to assemble): u is the canonical vector, returns
+    (len(cells), n^3)."""
+    n3 = (p + 1) ** 3
+    u = np.asarray(u, dtype=np.float64).reshape(-1, n3)
+    out = np.zeros((len(cells), n3))
+    for r, c in enumerate(cells):
+        for nb, blk in cell_row_blocks(p, m, h, int(c), part, C):
+            out[r] += blk @ u[nb]
+    return out
+
+
+def mass(p: int, m, h) -> sp.csr_matrix:
+    """Global (block-diagonal) mass matrix."""
+    ncell = int(m[0] * m[1] * m[2])
+    return sp.block_diag([dense.dense_mass(p, h)] * ncell, format="csr")

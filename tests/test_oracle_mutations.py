@@ -93,3 +93,78 @@ def test_planted_mistake_is_caught(monkeypatch, target, replacement):
 
 def test_unmutated_suite_passes():
     assert not _run_all(PIN_SUITE)
+
+
+# ---------------------------------------------------------------- coupled SIPG operator
+import tests.test_oracle_sipg as spins  # noqa: E402
+from oracle import sipg  # noqa: E402
+
+_ORIG_SIDE = sipg._side_data
+_ORIG_FACE_MATRIX = sipg.face_matrix
+_ORIG_CELL_INDEX = sipg.cell_index
+
+
+def _half_boundary_average(p, hd, side):
+    t, d, j, a = _ORIG_SIDE(p, hd, side)
+    return t, d, j, 0.5                        # boundary average weighted like an interior one
+
+
+def _flipped_coupling_penalty(p, hd, test_side, trial_side, C=2.0):
+    N = _ORIG_FACE_MATRIX(p, hd, test_side, trial_side, C)
+    if test_side != trial_side and "b" not in test_side:
+        ti, _, ji, _ = _ORIG_SIDE(p, hd, test_side)
+        tj, _, jj, _ = _ORIG_SIDE(p, hd, trial_side)
+        sigma = basis.penalty_reference(p, C) / hd
+        N = N - 2 * sigma * np.outer(ji * ti, jj * tj)
+    return N
+
+
+def _no_boundary_penalty(p, hd, test_side, trial_side, C=2.0):
+    if "b" in test_side:
+        return _ORIG_FACE_MATRIX(p, hd, test_side, trial_side, 0.0)
+    return _ORIG_FACE_MATRIX(p, hd, test_side, trial_side, C)
+
+
+def _one_sided_symmetry_term(p, hd, test_side, trial_side, C=2.0):
+    ti, di, ji, ai = _ORIG_SIDE(p, hd, test_side)
+    tj, dj, jj, aj = _ORIG_SIDE(p, hd, trial_side)
+    sigma = basis.penalty_reference(p, C) / hd
+    return -np.outer(ji * ti, aj * dj) + sigma * np.outer(ji * ti, jj * tj)   # [u]{d_n v} dropped
+
+
+def _transposed_cell_index(m, cx, cy, cz):
+    return (cx * m[2] + cz) * m[1] + cy         # y and z strides exchanged
+
+
+def _tangential_mass_of_normal_length(p, h, d, N1):
+    M, _ = basis.mass_stiffness(p)
+    f = [h[d] * M for _ in range(3)]
+    f[d] = N1
+    return np.kron(np.kron(f[0], f[1]), f[2])
+
+
+SIPG_PIN_SUITE = [
+    lambda: spins.test_consistency_for_polynomials_vanishing_on_the_boundary(3, (3, 2, 4)),
+    lambda: spins.test_consistency_with_boundary_data(3, (2, 3, 2)),
+    lambda: spins.test_penalty_energy_of_piecewise_constants(3),
+    lambda: spins.test_symmetric_positive_definite(2, (2, 3, 2)),
+    lambda: spins.test_interior_diagonal_block_is_cell_block(2),
+]
+
+
+@pytest.mark.parametrize("target,replacement", [
+    ((sipg, "_side_data"), _half_boundary_average),
+    ((sipg, "face_matrix"), _flipped_coupling_penalty),
+    ((sipg, "face_matrix"), _no_boundary_penalty),
+    ((sipg, "face_matrix"), _one_sided_symmetry_term),
+    ((sipg, "cell_index"), _transposed_cell_index),
+    ((sipg, "_slot_kron"), _tangential_mass_of_normal_length),
+])
+def test_planted_sipg_mistake_is_caught(monkeypatch, target, replacement):
+    mod, name = target
+    monkeypatch.setattr(mod, name, replacement)
+    assert _run_all(SIPG_PIN_SUITE), f"no pin caught the mutation of {mod.__name__}.{name}"
+
+
+def test_unmutated_sipg_suite_passes():
+    assert not _run_all(SIPG_PIN_SUITE)
