@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--suite", action="store_true",
                     help="time apply / apply_inverse / solve for every workload and precision "
                          "(one JSON line per case) instead of the headline step")
+    ap.add_argument("--sipg", action="store_true",
+                    help="time only the coupled SIPG operator on the unit-cube meshes (JSON lines)")
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "f16", "bf16"],
                     help="storage precision of the step (default: the workload's)")
     ap.add_argument("--counters", action="store_true",
@@ -137,6 +139,9 @@ def main():
 
     if args.suite:
         run_suite(args, stream)
+        return
+    if args.sipg:
+        run_sipg(args, stream)
         return
 
     _log(f"workload {args.workload}")
@@ -360,6 +365,51 @@ def run_suite(args, stream):
         del bb, xs, cu, cb
         torch.cuda.empty_cache()
     run_uneven(args, stream)
+    run_sipg(args, stream)
+
+
+# Coupled SIPG operator on uniformly refined unit cubes (the meshes of the
+# paper's face-kernel and operator measurements, Sec. 6.3 and 6.5).
+SIPG_SUITE = [(3, 128, ("f64", "f32")), (3, 64, ("f64",)), (2, 128, ("f64",))]
+
+
+def run_sipg(args, stream):
+    """Coupled operator v = A u (and its face part A^face u) on mesh plans:
+    HBM-resident inputs, algorithmic bytes = one vector read + one written."""
+    import torch
+    from paper_2609_04534_amd import tpfdm, workloads
+    codes = {"f64": (tpfdm.F64, torch.float64, 8), "f32": (tpfdm.F32, torch.float32, 4)}
+    for p, m, dts in SIPG_SUITE:
+        mesh = workloads.unit_cube_mesh(p, m, seed=5)
+        plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h)
+        cu = torch.from_numpy(mesh.u).cuda()
+        for dtn in dts:
+            code, tdt, es = codes[dtn]
+            E = plan.vector_elems
+            vec_bytes = E * es
+            R = int(min(8, max(1, -(-1.0e9 // (2 * vec_bytes)))))
+            U = [torch.empty(E, dtype=tdt, device="cuda") for _ in range(R)]
+            for u in U:
+                plan.pack(cu.to(tdt), u)
+            V = [torch.empty_like(U[0]) for _ in range(R)]
+            for k in range(3):
+                plan.apply(U[k % R], V[k % R], tpfdm.OP_SIPG, stream=stream)
+            reps = max(args.steps, 20)
+            ms = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_SIPG, stream=stream), stream, reps, R)
+            ms_f = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_SIPG_FACE, stream=stream), stream,
+                                 reps, R)
+            ms_v = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
+            ms_c = time_launches(lambda k: V[k].copy_(U[k]), stream, reps, R)
+            nd = mesh.ndof
+            print(json.dumps({"workload": mesh.name, "dtype": dtn, "ndof": nd, "buffer_sets": R,
+                              "sipg_ms": ms, "sipg_GDoF/s": nd / ms / 1e6, "sipg_GB/s": 2 * nd * es / ms / 1e6,
+                              "face_ms": ms_f, "face_GDoF/s": nd / ms_f / 1e6,
+                              "volume_ms": ms_v, "volume_GDoF/s": nd / ms_v / 1e6,
+                              "copy_ms": ms_c, "copy_GB/s": 2 * vec_bytes / ms_c / 1e6}), flush=True)
+            del U, V
+        plan.destroy()
+        del cu
+        torch.cuda.empty_cache()
 
 
 def run_uneven(args, stream):

@@ -71,7 +71,11 @@ typedef enum { TP_F64 = 0, TP_F32 = 1, TP_F16 = 2, TP_BF16 = 3 } tp_dtype;
 /* Which 1D operator P_hat fills the Kronecker sum. */
 typedef enum {
     TP_OP_NEUMANN = 0,  /* P_hat = K_hat: the volume operator of eq. (eval_pipeline); A 1 = 0 */
-    TP_OP_CELL = 1      /* P_hat = A_hat: the SIPG cell block of eq. (cell_block); SPD        */
+    TP_OP_CELL = 1,     /* P_hat = A_hat: the SIPG cell block of eq. (cell_block); SPD        */
+    TP_OP_SIPG = 2,     /* mesh plans only: the coupled SIPG operator A = A^vol + A^face of
+                           eq. (sipg) / eq. (operator_split) over the whole mesh        */
+    TP_OP_SIPG_FACE = 3 /* mesh plans only: its face part A^face (interior and boundary
+                           faces); TP_OP_NEUMANN on a mesh plan is A^vol             */
 } tp_operator;
 
 /* How per-block eigenfactors are represented (Sec. 5.2).
@@ -141,6 +145,30 @@ void tp_plan_opts_default(tp_plan_opts* opts);
 tp_status tp_plan_create(const tp_group* groups, int32_t ngroups,
                          const tp_plan_opts* opts, tp_plan** out);
 
+/* A uniform Cartesian box mesh (Sec. 3): cells[0] x cells[1] x cells[2]
+ * axis-aligned cells, all with edge lengths h, degree n-1 in every cell,
+ * homogeneous Dirichlet data imposed weakly by the SIPG (Nitsche) terms on
+ * the boundary faces (eq. (sipg), penalty C p(p+1)/h_F with h_F the cell
+ * length normal to the face, Sec. 6.2).  Cell (cx, cy, cz) is block
+ * c = (cx cells[1] + cy) cells[2] + cz of the plan's single group, so the B
+ * cells of a layout tile are consecutive along z. */
+typedef struct {
+    int32_t n;            /* points per direction, 2 <= n <= 8                          */
+    int32_t layout_B;     /* interleave width, a power of two <= 1024                    */
+    int32_t cells[3];     /* cells per direction (x, y, z), each >= 1, product < 2^31    */
+    int32_t reserved;     /* must be zero                                               */
+    double h[3];          /* cell edge lengths (x, y, z), finite and > 0                 */
+} tp_mesh;
+
+/* Create a plan over the cells of a mesh: one group of cells[0] cells[1]
+ * cells[2] blocks (offset 0) whose blocks all have the lengths h.  Every
+ * block call works on it as on any plan (TP_OP_CELL: the cell blocks, whose
+ * inverse is the block-Jacobi preconditioner of Sec. 5.2, with the interior
+ * stencil on boundary cells); in addition tp_apply takes TP_OP_SIPG and
+ * TP_OP_SIPG_FACE, which couple neighbouring cells.  opts->persistent must
+ * be 0 (TP_ERR_UNSUPPORTED).  Host-synchronous.  Errors as tp_plan_create. */
+tp_status tp_plan_create_mesh(const tp_mesh* mesh, const tp_plan_opts* opts, tp_plan** out);
+
 /* Free everything the plan owns.  Null is accepted. */
 tp_status tp_plan_destroy(tp_plan* plan);
 
@@ -155,11 +183,15 @@ int64_t tp_plan_ndof(const tp_plan* plan);
  * operands); FP64 accumulates in FP64, the others in FP32.  u, v: device
  * buffers of tp_plan_vector_elems() elements of dtype.  Sec. 3.1,
  * eq. (eval_pipeline) with P_hat chosen by op (length groups); factor groups
- * use their own P and ignore op. */
+ * use their own P and ignore op.
+ * TP_OP_SIPG / TP_OP_SIPG_FACE (mesh plans, TP_F64 and TP_F32, n <= 4 and
+ * n = 8; TP_ERR_UNSUPPORTED otherwise): v <- A u with the coupled operator,
+ * every cell's row reading its face neighbours' blocks of u. */
 tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v,
                    tp_dtype dtype, hipStream_t stream);
 
-/* Fast-diagonalization setup for the operator op (Sec. 5.2): Cholesky
+/* Fast-diagonalization setup for the operator op (TP_OP_NEUMANN or
+ * TP_OP_CELL; the coupled operators have no such inverse) (Sec. 5.2): Cholesky
  * M = L L^T, symmetric Jacobi eigen-decomposition of L^{-1} P L^{-T},
  * S = L^{-T} Q, in FP64 on the host: per degree (SCALED) or per block and
  * direction (GENERAL, host threads; P symmetrized as (P + P^T)/2 first).

@@ -66,6 +66,7 @@ int solve_kind(const Plan& p, const GroupInfo& g) {
 
 bool valid_dtype(int dt) { return dt >= TP_F64 && dt <= TP_BF16; }
 bool valid_op(int op) { return op == TP_OP_NEUMANN || op == TP_OP_CELL; }
+bool coupled_op(int op) { return op == TP_OP_SIPG || op == TP_OP_SIPG_FACE; }
 
 }  // namespace
 
@@ -504,16 +505,57 @@ tp_status tp_plan_destroy(tp_plan* plan) {
     return TP_OK;
 }
 
+tp_status tp_plan_create_mesh(const tp_mesh* mesh, const tp_plan_opts* opts, tp_plan** out) {
+    if (!out) return set_error(TP_ERR_ARG, "out must be non-null");
+    *out = nullptr;
+    if (!mesh) return set_error(TP_ERR_ARG, "mesh must be non-null");
+    if (mesh->reserved != 0) return set_error(TP_ERR_ARG, "reserved mesh field must be zero");
+    if (opts && opts->persistent) return set_error(TP_ERR_UNSUPPORTED, "mesh plans cannot be persistent");
+    int64_t ncells = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (mesh->cells[d] < 1) return set_error(TP_ERR_ARG, "mesh cells must be >= 1 in every direction");
+        if (!(mesh->h[d] > 0.0) || !std::isfinite(mesh->h[d]))
+            return set_error(TP_ERR_ARG, "mesh h must be finite and > 0");
+        ncells *= mesh->cells[d];
+        if (ncells > (int64_t(1) << 31) - 1) return set_error(TP_ERR_ARG, "mesh has too many cells");
+    }
+    std::vector<double> h(static_cast<size_t>(ncells) * 3);
+    for (int64_t c = 0; c < ncells; ++c)
+        for (int d = 0; d < 3; ++d) h[c * 3 + d] = mesh->h[d];
+    tp_group g;
+    g.n = mesh->n;
+    g.layout_B = mesh->layout_B;
+    g.nblocks = ncells;
+    g.h = h.data();
+    g.offset = 0;
+    g.M = nullptr;
+    g.P = nullptr;
+    tp_plan* p = nullptr;
+    tp_status st = tp_plan_create(&g, 1, opts, &p);
+    if (st != TP_OK) return st;
+    p->mesh = true;
+    for (int d = 0; d < 3; ++d) {
+        p->mesh_m[d] = mesh->cells[d];
+        p->mesh_h[d] = mesh->h[d];
+    }
+    *out = p;
+    return TP_OK;
+}
+
 int64_t tp_plan_vector_elems(const tp_plan* plan) { return plan ? plan->vec_elems : -1; }
 int64_t tp_plan_ndof(const tp_plan* plan) { return plan ? plan->ndof : -1; }
 int64_t tp_plan_nblocks(const tp_plan* plan) { return plan ? plan->nblocks : -1; }
 
 tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dtype dtype, hipStream_t stream) {
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
-    if (!valid_op(op)) return set_error(TP_ERR_ARG, "invalid operator");
+    if (!valid_op(op) && !coupled_op(op)) return set_error(TP_ERR_ARG, "invalid operator");
     if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
     if (plan->vec_elems > 0 && (!u || !v)) return set_error(TP_ERR_ARG, "u and v must be non-null");
     if (u == v && u) return set_error(TP_ERR_ARG, "u and v must not alias");
+    if (coupled_op(op)) {
+        if (!plan->mesh) return set_error(TP_ERR_UNSUPPORTED, "the coupled SIPG operator needs a mesh plan");
+        return launch_sipg(*plan, plan->groups[0], op == TP_OP_SIPG_FACE, u, v, dtype, stream);
+    }
     if (plan->persistent) return launch_apply_persistent(*plan, op, u, v, dtype, stream);
     tp_status st = TP_OK;
     for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {

@@ -20,6 +20,7 @@ void gll_points(int n, double* x);
 void gauss_points(int nq, double* x, double* w);
 void reference_matrices(int n, double C, double* M, double* K, double* A);
 int gen_eigen(int n, const double* M, const double* P, double* S, double* lam);
+void endpoint_derivatives(int n, double* g0, double* g1);
 
 // Even-odd tables of the centrosymmetric 1D factors, one slot of kEOSlot
 // elements per (n, table, element type):
@@ -111,6 +112,10 @@ struct Plan {
     int cus = 256;                 // compute units of the plan's device
     WorkItem* items_dev = nullptr;
     int64_t nitems = 0;
+    // uniform box mesh of tp_plan_create_mesh (one group, cells in mesh order)
+    bool mesh = false;
+    int mesh_m[3] = {0, 0, 0};
+    double mesh_h[3] = {0.0, 0.0, 0.0};
 };
 
 // Per-workgroup partial summary of a solve launch (plain stores, no atomics).
@@ -188,6 +193,9 @@ tp_status launch_apply_persistent(const Plan& plan, int op, const void* u, void*
 tp_status launch_inverse_persistent(const Plan& plan, const void* r, void* x, tp_dtype dt, hipStream_t s);
 tp_status launch_solve_persistent(const Plan& plan, const double* b, double* x, tp_dtype inner, double rtol,
                                   int maxit, int32_t* iters, double* relres, int64_t* nparts, hipStream_t s);
+// Coupled SIPG operator of a mesh plan (sipg.hip): A u, or A^face u when face_only.
+tp_status launch_sipg(const Plan& plan, const GroupInfo& g, bool face_only, const void* u, void* v, tp_dtype dt,
+                      hipStream_t s);
 tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize,
                       bool to_blocked, hipStream_t s);
 tp_status launch_summary_reduce(const Plan& plan, int64_t nparts, hipStream_t s);

@@ -150,6 +150,31 @@ void reference_matrices(int n, double C, double* M, double* K, double* A) {
     }
 }
 
+// Endpoint derivatives of the n Lagrange functions on [0, 1]: g0[j] =
+// l_j'(0), g1[j] = l_j'(1) (the vectors g of eq. (face_coupling) on the
+// reference interval), rows 0 and n-1 of the nodal differentiation matrix.
+void endpoint_derivatives(int n, double* g0, double* g1) {
+    std::vector<double> x(n), bw(n);
+    gll_points(n, x.data());
+    for (int j = 0; j < n; ++j) {
+        double prod = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != j) prod *= (x[j] - x[k]);
+        bw[j] = 1.0 / prod;
+    }
+    for (int r = 0; r < 2; ++r) {
+        const int i = r == 0 ? 0 : n - 1;
+        double* g = r == 0 ? g0 : g1;
+        double diag = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            g[j] = (bw[j] / bw[i]) / (x[i] - x[j]);
+            diag -= g[j];
+        }
+        g[i] = diag;
+    }
+}
+
 // Generalized symmetric-definite eigenproblem P S = M S diag(lam).
 // Returns 0 on success, -1 when M is not SPD.
 int gen_eigen(int n, const double* M, const double* P, double* S, double* lam) {

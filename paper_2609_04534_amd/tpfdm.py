@@ -24,7 +24,7 @@ STATUS = {
 }
 F64, F32, F16, BF16 = 0, 1, 2, 3
 DTYPE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
-OP_NEUMANN, OP_CELL = 0, 1
+OP_NEUMANN, OP_CELL, OP_SIPG, OP_SIPG_FACE = 0, 1, 2, 3
 FACTOR_SCALED, FACTOR_GENERAL = 0, 1
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 
@@ -34,7 +34,7 @@ EXPORTS = (
     "tp_plan_ndof", "tp_plan_nblocks", "tp_apply", "tp_setup_inverse", "tp_apply_inverse",
     "tp_solve", "tp_pack", "tp_unpack", "tp_reference_matrices", "tp_reference_eigen",
     "tp_last_error", "tp_version", "tp_solve_summary_fetch", "tp_graph_create", "tp_graph_launch",
-    "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel",
+    "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel", "tp_plan_create_mesh",
 )
 KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
@@ -56,6 +56,11 @@ class _Group(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("penalty_C", ctypes.c_double), ("persistent", ctypes.c_int32),
                 ("mapping", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("layout_B", ctypes.c_int32), ("cells", ctypes.c_int32 * 3),
+                ("reserved", ctypes.c_int32), ("h", ctypes.c_double * 3)]
 
 
 class _Summary(ctypes.Structure):
@@ -98,6 +103,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_version": (ctypes.c_char_p, []),
         "tp_plan_autotune": (i32, [vp, i32, i32, vp]),
         "tp_plan_group_kernel": (i32, [vp, i32, i32, i32]),
+        "tp_plan_create_mesh": (i32, [ctypes.POINTER(_Mesh), ctypes.POINTER(_Opts), ctypes.POINTER(vp)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -220,6 +226,35 @@ class Plan:
         _check(lib.tp_plan_create(arr, len(groups), ctypes.byref(opts), ctypes.byref(handle)))
         self._h = handle
         self._keep = []
+
+    @classmethod
+    def mesh(cls, n: int, cells, h, layout_B: int | None = None, penalty_C: float = 2.0,
+             mapping: int = MAP_AUTO) -> "Plan":
+        """Plan over a uniform box mesh of cells[0] x cells[1] x cells[2] cells
+        of edge lengths h (tp_plan_create_mesh): one group of blocks in mesh
+        order, with the coupled operators OP_SIPG and OP_SIPG_FACE."""
+        lib = load()
+        B = default_layout_B(n) if layout_B is None else layout_B
+        m = _Mesh()
+        m.n = n
+        m.layout_B = B
+        for d in range(3):
+            m.cells[d] = int(cells[d])
+            m.h[d] = float(h[d])
+        m.reserved = 0
+        opts = _Opts()
+        lib.tp_plan_opts_default(ctypes.byref(opts))
+        opts.penalty_C = penalty_C
+        opts.mapping = mapping
+        handle = ctypes.c_void_p()
+        _check(lib.tp_plan_create_mesh(ctypes.byref(m), ctypes.byref(opts), ctypes.byref(handle)))
+        self = cls.__new__(cls)
+        self._h = handle
+        self._keep = []
+        ncell = int(cells[0]) * int(cells[1]) * int(cells[2])
+        self.groups = [GroupSpec(n, B, np.broadcast_to(np.asarray(h, dtype=np.float64), (ncell, 3)), 0)]
+        self.cells = tuple(int(c) for c in cells)
+        return self
 
     # ---------------------------------------------------------------- sizes
     @property

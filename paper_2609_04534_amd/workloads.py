@@ -134,3 +134,37 @@ def random_blocks(p, nblocks, seed, h_range=(0.5, 2.0), with_rhs=False):
     """Generic seeded case used by tests (ragged sizes, edge cases)."""
     return _uniform_degree_workload(f"p{p}_n{nblocks}_s{seed}", nblocks, p, seed=seed,
                                     h_range=h_range, with_rhs=with_rhs)
+
+
+@dataclass
+class BoxMesh:
+    """A uniform Cartesian box mesh (the paper's uniformly refined unit cube
+    of Sec. 6.5): cells per direction, cell lengths, degree and a vector in
+    mesh order (cell c = (cx m_y + cy) m_z + cz, canonical DoFs per cell)."""
+    name: str
+    p: int
+    cells: tuple
+    h: tuple
+    u: np.ndarray            # (ncells * n^3,) float64
+    b: np.ndarray | None = None
+
+    @property
+    def n(self) -> int:
+        return self.p + 1
+
+    @property
+    def ncells(self) -> int:
+        return self.cells[0] * self.cells[1] * self.cells[2]
+
+    @property
+    def ndof(self) -> int:
+        return self.ncells * self.n ** 3
+
+
+def unit_cube_mesh(p: int, m: int, seed: int, with_rhs: bool = False) -> BoxMesh:
+    """m^3 cells of length 1/m on the unit cube; u (and b) ~ U[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    nd = m ** 3 * (p + 1) ** 3
+    u = rng.uniform(-1.0, 1.0, nd)
+    b = rng.uniform(-1.0, 1.0, nd) if with_rhs else None
+    return BoxMesh(f"sipg_p{p}_{m}cube", p, (m, m, m), (1.0 / m,) * 3, u, b)

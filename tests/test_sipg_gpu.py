@@ -1,0 +1,194 @@
+"""GPU parity of the coupled SIPG operator on uniform box meshes (mesh plans,
+TP_OP_SIPG / TP_OP_SIPG_FACE) against the oracle's sparse assembly of
+eq. (sipg), element by element, and at the full benchmark size on sampled
+cells."""
+import numpy as np
+import pytest
+
+from oracle import sipg
+from paper_2609_04534_amd import tpfdm
+from tests.gpu_util import from_blocked, to_blocked
+
+pytestmark = pytest.mark.gpu
+
+TOL = {tpfdm.F64: 1e-12, tpfdm.F32: 2e-6}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _u(ncell, n, seed):
+    return np.random.default_rng(seed).uniform(-1, 1, ncell * n ** 3)
+
+
+def _scaled_err(got, ref, A, u):
+    """max |got - ref| / max (|A| |u|): relative to the size of the terms."""
+    scale = np.max(np.abs(abs(A) @ np.abs(u)))
+    return float(np.max(np.abs(got - ref)) / scale)
+
+
+# (n, cells, h, layout_B): several 64-cell tiles with a ragged tail, one-cell
+# thick meshes in each direction (every cell a boundary cell, neighbours
+# across tile boundaries), non-default layouts (B = 1: no streaming hint,
+# B = 8: a wave spans eight tiles, B = 128)
+CASES = [
+    (2, (5, 7, 9), (0.2, 0.3, 0.15), None),
+    (3, (4, 6, 11), (0.7, 1.3, 0.45), None),
+    (4, (3, 5, 13), (0.25, 0.5, 1.0), None),
+    (4, (1, 1, 70), (0.3, 0.3, 0.3), None),
+    (3, (70, 1, 1), (0.1, 0.4, 0.2), None),
+    (4, (2, 33, 1), (1.0, 0.5, 2.0), None),
+    (3, (4, 5, 6), (0.7, 1.3, 0.45), 1),
+    (4, (3, 4, 5), (0.7, 1.3, 0.45), 8),
+    (2, (6, 6, 8), (0.2, 0.3, 0.15), 128),
+    (4, (1, 1, 1), (1.0, 1.0, 1.0), None),
+]
+
+
+@pytest.mark.parametrize("n,cells,h,B", CASES)
+@pytest.mark.parametrize("dt", [tpfdm.F64, tpfdm.F32])
+def test_sipg_apply_matches_oracle(n, cells, h, B, dt):
+    p = n - 1
+    ncell = cells[0] * cells[1] * cells[2]
+    u = _u(ncell, n, seed=n * 1000 + ncell)
+    A = sipg.assemble(p, cells, h)
+    Af = sipg.assemble(p, cells, h, sipg.FACE)
+    print(f"n={n} cells={cells} B={B} dtype={tpfdm.DTYPE_NAMES[dt]}", flush=True)
+    with tpfdm.Plan.mesh(n, cells, h, layout_B=B) as plan:
+        bu = to_blocked(plan, u, dt)
+        bv = _torch().full_like(bu, float("nan"))
+        plan.apply(bu, bv, tpfdm.OP_SIPG)
+        v = from_blocked(plan, bv, dt)
+        plan.apply(bu, bv, tpfdm.OP_SIPG_FACE)
+        vf = from_blocked(plan, bv, dt)
+    uq = from_blocked_input(u, dt)
+    e = _scaled_err(v, A @ uq, A, uq)
+    ef = _scaled_err(vf, Af @ uq, Af, uq)
+    print(f"  full err={e:.2e} face err={ef:.2e}")
+    assert e < TOL[dt] and ef < TOL[dt]
+
+
+def from_blocked_input(u, dt):
+    """The input as the kernel sees it (rounded to the storage type)."""
+    return u.astype(np.float32).astype(np.float64) if dt == tpfdm.F32 else u
+
+
+def test_sipg_operator_split_and_symmetry():
+    """A = A^vol + A^face on the GPU (eq. (operator_split)), and the
+    operator is symmetric: w^T (A u) = u^T (A w)."""
+    torch = _torch()
+    n, cells, h = 3, (6, 5, 7), (0.3, 0.2, 0.5)
+    ncell = 210
+    u, w = _u(ncell, n, 1), _u(ncell, n, 2)
+    with tpfdm.Plan.mesh(n, cells, h) as plan:
+        bu, bw = to_blocked(plan, u, tpfdm.F64), to_blocked(plan, w, tpfdm.F64)
+        out = {}
+        for op in (tpfdm.OP_SIPG, tpfdm.OP_NEUMANN, tpfdm.OP_SIPG_FACE):
+            bv = torch.empty_like(bu)
+            plan.apply(bu, bv, op)
+            out[op] = from_blocked(plan, bv, tpfdm.F64)
+        bv = torch.empty_like(bu)
+        plan.apply(bw, bv, tpfdm.OP_SIPG)
+        Aw = from_blocked(plan, bv, tpfdm.F64)
+    Au = out[tpfdm.OP_SIPG]
+    assert np.max(np.abs(Au - out[tpfdm.OP_NEUMANN] - out[tpfdm.OP_SIPG_FACE])) < 1e-12 * np.max(np.abs(Au))
+    assert abs(w @ Au - u @ Aw) < 1e-12 * np.abs(w) @ np.abs(Au)
+
+
+def test_sipg_graph_replay():
+    """A graph of the coupled apply replays to the eager result, with eager
+    work between replays."""
+    torch = _torch()
+    n, cells, h = 4, (3, 4, 9), (0.5, 0.5, 0.25)
+    u = _u(108, n, 3)
+    with tpfdm.Plan.mesh(n, cells, h) as plan:
+        bu = to_blocked(plan, u, tpfdm.F64)
+        ref = torch.empty_like(bu)
+        plan.apply(bu, ref, tpfdm.OP_SIPG)
+        ref_c = from_blocked(plan, ref, tpfdm.F64)
+        out = torch.full_like(bu, float("nan"))
+        g = plan.graph(tpfdm.GRAPH_APPLY, bu, out, op=tpfdm.OP_SIPG)
+        for rep in range(3):
+            out.fill_(float("nan"))
+            g.launch()
+            torch.cuda.synchronize()
+            # padding lanes of the last tile are never written: compare the cells
+            assert np.array_equal(from_blocked(plan, out, tpfdm.F64), ref_c), rep
+            plan.apply(bu, torch.empty_like(bu), tpfdm.OP_NEUMANN)
+        g.destroy()
+
+
+def test_sipg_errors():
+    torch = _torch()
+    with tpfdm.Plan([tpfdm.GroupSpec(3, 64, np.ones((10, 3)))]) as plan:
+        buf = torch.zeros(plan.vector_elems, dtype=torch.float64, device="cuda")
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            plan.apply(buf, torch.zeros_like(buf), tpfdm.OP_SIPG)
+        assert e.value.status == -2
+    with tpfdm.Plan.mesh(3, (2, 2, 2), (1, 1, 1)) as plan:
+        buf = torch.zeros(plan.vector_elems, dtype=torch.float16, device="cuda")
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            plan.apply(buf, torch.zeros_like(buf), tpfdm.OP_SIPG)
+        assert e.value.status == -2
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            plan.setup_inverse(tpfdm.OP_SIPG)
+        assert e.value.status == -1
+        # block calls work on mesh plans: the cell blocks and their inverse
+        plan.setup_inverse(tpfdm.OP_CELL)
+
+
+def test_block_jacobi_of_mesh_plan_inverts_interior_diagonal_blocks():
+    """Sec. 5.2: the cell block is the cell-diagonal part of A; on a mesh
+    plan, apply_inverse(A u) returns u on every cell whose row has no
+    off-diagonal coupling, i.e. when u vanishes on the cell's neighbours and
+    the cell has no boundary face."""
+    torch = _torch()
+    n, cells, h = 4, (3, 3, 3), (0.4, 0.6, 0.3)
+    u = np.zeros(27 * 64)
+    c = sipg.cell_index(cells, 1, 1, 1)
+    u[c * 64:(c + 1) * 64] = _u(1, n, 7)
+    with tpfdm.Plan.mesh(n, cells, h) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
+        bu = to_blocked(plan, u, tpfdm.F64)
+        bv = torch.empty_like(bu)
+        plan.apply(bu, bv, tpfdm.OP_SIPG)
+        bx = torch.empty_like(bu)
+        plan.apply_inverse(bv, bx)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    assert np.max(np.abs(x[c * 64:(c + 1) * 64] - u[c * 64:(c + 1) * 64])) < 1e-12
+
+
+@pytest.mark.parametrize("n,m,dt", [(4, 128, tpfdm.F64), (4, 64, tpfdm.F32), (3, 96, tpfdm.F64)])
+def test_sipg_fullsize_sampled_cells(n, m, dt):
+    """The benchmark meshes (up to 128^3 cells at p = 3): every sampled cell's
+    output against the oracle's row blocks, including corner, edge and face
+    cells of the box."""
+    torch = _torch()
+    p = n - 1
+    cells = (m, m, m)
+    h = (1.0 / m,) * 3
+    ncell = m ** 3
+    rng = np.random.default_rng(m)
+    print(f"n={n} cells={cells} dtype={tpfdm.DTYPE_NAMES[dt]}", flush=True)
+    u = _u(ncell, n, seed=11)
+    with tpfdm.Plan.mesh(n, cells, h) as plan:
+        bu = to_blocked(plan, u, dt)
+        bv = torch.empty_like(bu)
+        plan.apply(bu, bv, tpfdm.OP_SIPG)
+        v = from_blocked(plan, bv, dt).reshape(ncell, n ** 3)
+        del bu, bv
+    u = from_blocked_input(u, dt)
+    corners = [sipg.cell_index(cells, a, b, c) for a in (0, m - 1) for b in (0, m - 1) for c in (0, m - 1)]
+    edges = [sipg.cell_index(cells, 0, m // 2, 0), sipg.cell_index(cells, m - 1, 0, m // 3),
+             sipg.cell_index(cells, m // 2, m - 1, m - 1), sipg.cell_index(cells, 5, 0, 63),
+             sipg.cell_index(cells, 1, 2, 64 % m)]
+    sample = sorted(set(corners + edges + rng.choice(ncell, 40, replace=False).tolist()))
+    ref = sipg.cell_apply(p, cells, h, u, sample)
+    ub = np.abs(u).reshape(ncell, n ** 3)
+    scale = max(float(np.max(sum(np.abs(blk) @ ub[nb] for nb, blk in sipg.cell_row_blocks(p, cells, h, c))))
+                for c in sample)
+    err = np.max(np.abs(v[sample] - ref)) / scale
+    print(f"  sampled={len(sample)} err={err:.2e}")
+    assert err < TOL[dt]
