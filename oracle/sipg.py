@@ -33,7 +33,9 @@ polynomials that do not vanish there against a boundary functional computed
 by independent face quadrature, the penalty energy of piecewise constants,
 symmetry and definiteness, the interior cell-diagonal block equal to the cell
 block of eq. (cell_block), and the interior face matrices equal to the
-printed-stencil-pinned ``basis.face_blocks``.
+printed-stencil-pinned ``basis.face_blocks``.  ``pcg`` (textbook
+preconditioned CG) with ``block_jacobi`` (dense solves with the cell blocks,
+the preconditioner of Sec. 5.2) is pinned by the sparse direct solution.
 """
 from __future__ import annotations
 
@@ -170,3 +172,42 @@ def mass(p: int, m, h) -> sp.csr_matrix:
     """Global (block-diagonal) mass matrix."""
     ncell = int(m[0] * m[1] * m[2])
     return sp.block_diag([dense.dense_mass(p, h)] * ncell, format="csr")
+
+
+def block_jacobi(p: int, m, h, r, C: float = 2.0) -> np.ndarray:
+    """z = D^{-1} r with D the cell-diagonal blocks of Sec. 5.2: the cell block
+    of eq. (cell_block) on every cell, boundary cells included (the paper
+    keeps the interior stencil there), each solved densely."""
+    n3 = (p + 1) ** 3
+    ncell = int(m[0] * m[1] * m[2])
+    r = np.asarray(r, dtype=np.float64).reshape(ncell, n3)
+    D = dense.dense_operator(p, h, dense.CELL, C)
+    return np.linalg.solve(D, r.T).T.reshape(-1)
+
+
+def pcg(A, b, prec, rtol: float, maxit: int, x0=None):
+    """Textbook preconditioned conjugate gradients for the SPD system A x = b
+    (Hestenes-Stiefel recurrences), stopping when ||b - A x||_2 <= rtol ||b||_2
+    with the recursively updated residual.  prec(r) applies the
+    preconditioner.  Returns (x, iterations, ||r||_2 / ||b||_2)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A @ x
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return np.zeros_like(b), 0, 0.0
+    z = prec(r)
+    pdir = z.copy()
+    rz = r @ z
+    it = 0
+    while np.linalg.norm(r) > rtol * nb and it < maxit:
+        q = A @ pdir
+        alpha = rz / (pdir @ q)
+        x += alpha * pdir
+        r -= alpha * q
+        z = prec(r)
+        rz_new = r @ z
+        pdir = z + (rz_new / rz) * pdir
+        rz = rz_new
+        it += 1
+    return x, it, float(np.linalg.norm(r) / nb)

@@ -221,3 +221,38 @@ def test_cell_apply_equals_assembled_rows():
         full = sipg.apply(p, m, H, u, part).reshape(-1, 64)
         got = sipg.cell_apply(p, m, H, u, cells, part)
         assert np.allclose(got, full[cells], rtol=0, atol=1e-13 * np.max(np.abs(full)))
+
+
+@pytest.mark.parametrize("p,m", [(2, (3, 3, 4)), (3, (2, 3, 3))])
+def test_pcg_reaches_the_direct_solution(p, m):
+    """The oracle's PCG with the block-Jacobi preconditioner converges to the
+    sparse direct solution within its residual bound, and its iterates satisfy
+    the stopping rule on the true residual."""
+    import scipy.sparse.linalg as spl
+    A = sipg.assemble(p, m, H)
+    b = np.random.default_rng(3).uniform(-1, 1, A.shape[0])
+    xs = spl.spsolve(A.tocsc(), b)
+    x, it, rel = sipg.pcg(A, b, lambda r: sipg.block_jacobi(p, m, H, r), 1e-10, 500)
+    assert rel <= 1e-10 and 0 < it < 500
+    assert np.linalg.norm(b - A @ x) <= 1.01e-10 * np.linalg.norm(b)
+    cond = np.linalg.cond(A.toarray())
+    assert np.linalg.norm(x - xs) <= 2 * cond * 1e-10 * np.linalg.norm(xs)
+    # the preconditioner is the inverse of the cell-diagonal blocks
+    r = np.random.default_rng(4).uniform(-1, 1, A.shape[0])
+    z = sipg.block_jacobi(p, m, H, r)
+    n3 = (p + 1) ** 3
+    c = sipg.cell_index(m, 1, 1, 1)
+    D = dense.dense_operator(p, H, dense.CELL)
+    assert np.allclose(D @ z[c * n3:(c + 1) * n3], r[c * n3:(c + 1) * n3], atol=1e-12)
+
+
+def test_pcg_without_preconditioner_is_cg_with_exact_termination():
+    """Unpreconditioned CG on a small SPD system reaches the solution in at
+    most N iterations (exact-arithmetic termination, up to rounding)."""
+    A = sipg.assemble(1, (2, 1, 2), H)
+    b = np.random.default_rng(5).uniform(-1, 1, A.shape[0])
+    x, it, rel = sipg.pcg(A, b, lambda r: r.copy(), 1e-12, 10 * A.shape[0])
+    assert rel <= 1e-12
+    import scipy.sparse.linalg as spl
+    xs = spl.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
