@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--suite", action="store_true",
                     help="time apply / apply_inverse / solve for every workload and precision "
                          "(one JSON line per case) instead of the headline step")
+    ap.add_argument("--pcg", action="store_true",
+                    help="time preconditioned-CG solves of the SIPG system on the serving mesh sizes (JSON lines)")
     ap.add_argument("--sipg", action="store_true",
                     help="time only the coupled SIPG operator on the unit-cube meshes (JSON lines)")
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "f16", "bf16"],
@@ -140,7 +142,13 @@ def main():
     if args.suite:
         run_suite(args, stream)
         return
+    if args.pcg:
+        run_pcg(args, stream)
+        return
     if args.sipg:
+        if args.counters:
+            sipg_counters()
+            return
         run_sipg(args, stream)
         return
 
@@ -410,6 +418,66 @@ def run_sipg(args, stream):
         plan.destroy()
         del cu
         torch.cuda.empty_cache()
+
+
+# Serving meshes: unit cubes with m cells per side (the request mix of the
+# serving configuration), rtol 1e-8, FP64 outer iteration.
+PCG_SUITE = [(p, m) for p in (2, 3) for m in (8, 16, 24, 32, 48)]
+
+
+def run_pcg(args, stream):
+    """Per mesh and preconditioner precision: wall latency of whole solves
+    (launch to host summary), p50 / p99 over repeated solves, iterations."""
+    import torch
+    from paper_2609_04534_amd import tpfdm, workloads
+    for p, m in PCG_SUITE:
+        mesh = workloads.unit_cube_mesh(p, m, seed=7)
+        plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h)
+        plan.setup_inverse(tpfdm.OP_CELL)
+        b = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
+        plan.pack(torch.from_numpy(mesh.u).cuda(), b)
+        x = torch.empty_like(b)
+        solver = tpfdm.PCG(plan)
+        for inner in (tpfdm.F64, tpfdm.F32):
+            reps = 30 if m <= 24 else 10
+            lat, s = [], None
+            for i in range(reps + 2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s = solver.solve(b, x, inner=inner, rtol=1e-8, maxit=10000, stream=stream)
+                t1 = time.perf_counter()
+                if i >= 2:
+                    lat.append((t1 - t0) * 1e3)
+            p50 = float(np.percentile(lat, 50))
+            print(json.dumps({"workload": f"pcg_p{p}_{m}cube", "inner": tpfdm.DTYPE_NAMES[inner],
+                              "ndof": mesh.ndof, "iterations": s["iterations"], "relres": s["relres"],
+                              "p50_ms": p50, "p99_ms": float(np.percentile(lat, 99)),
+                              "ms_per_iteration": p50 / max(1, s["iterations"]),
+                              "solves_per_s": 1e3 / p50}), flush=True)
+        solver.destroy()
+        plan.destroy()
+        del b, x
+        torch.cuda.empty_cache()
+
+
+def sipg_counters():
+    """Hardware-counter run of the coupled operator on the p=3 128^3 mesh in
+    FP64: one plain device copy of a vector (the calibration), then three
+    applies of A and three of A^face."""
+    import torch
+    from paper_2609_04534_amd import tpfdm, workloads
+    mesh = workloads.unit_cube_mesh(3, 128, seed=5)
+    with tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h) as plan:
+        u = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
+        plan.pack(torch.from_numpy(mesh.u).cuda(), u)
+        v = torch.empty_like(u)
+        v.copy_(u)
+        for _ in range(3):
+            plan.apply(u, v, tpfdm.OP_SIPG)
+        for _ in range(3):
+            plan.apply(u, v, tpfdm.OP_SIPG_FACE)
+        torch.cuda.synchronize()
+    _log("sipg counters run done")
 
 
 def run_uneven(args, stream):

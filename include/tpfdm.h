@@ -289,6 +289,37 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
  * plan or an invalid argument.  MFMA assumes 16-byte aligned vectors. */
 int32_t tp_plan_group_kernel(const tp_plan* plan, int32_t group, int32_t call, tp_dtype dtype);
 
+/* Preconditioned conjugate gradients for the coupled SIPG system A x = b of
+ * a mesh plan (n <= 4), FP64 throughout except the preconditioner: the
+ * cell-wise fast-diagonalization block-Jacobi z = D^{-1} r of Sec. 5.2 (the
+ * cell blocks of eq. (cell_block), interior stencil on every cell), applied
+ * in `inner` precision (TP_F64, or TP_F32 on the FP64 vectors).  Needs
+ * tp_setup_inverse(plan, TP_OP_CELL, TP_FACTOR_SCALED, ...) first
+ * (TP_ERR_STATE).  tp_pcg_create allocates the solver's workspace (four
+ * plan-sized FP64 vectors and the reduction partials); the plan must outlive
+ * it.  tp_pcg_solve: b, x device FP64 vectors in the plan's layout; x is the
+ * initial guess unless x_is_zero (then x is overwritten with zero first) and
+ * holds the last iterate on return.  Stops when ||r||_2 <= rtol ||b||_2 for
+ * the recursively updated residual r, or after maxit iterations
+ * (TP_ERR_NOT_CONVERGED), or on a breakdown / non-finite value
+ * (TP_ERR_NONFINITE).  Every iteration runs on the device without host
+ * synchronisation; the host reads the solver state once per check_every
+ * iterations (<= 0 selects 16), so up to check_every - 1 iterations' kernels
+ * run after convergence and return at once.  Synchronises the stream before
+ * returning; summary (optional) receives the iterations, whether it
+ * converged and the final relative residual.  One solve at a time per
+ * solver object. */
+typedef struct {
+    int32_t iterations;
+    int32_t converged;
+    double relres;
+} tp_pcg_summary;
+typedef struct tp_pcg tp_pcg;
+tp_status tp_pcg_create(tp_plan* plan, tp_pcg** out);
+tp_status tp_pcg_solve(tp_pcg* pcg, const double* b, double* x, int32_t x_is_zero, tp_dtype inner, double rtol,
+                       int32_t maxit, int32_t check_every, tp_pcg_summary* summary, hipStream_t stream);
+tp_status tp_pcg_destroy(tp_pcg* pcg);
+
 /* Number of blocks in the plan (sum over groups). */
 int64_t tp_plan_nblocks(const tp_plan* plan);
 

@@ -170,7 +170,6 @@ tp_status upload_eo(Plan& plan, int n, int tab, const double* vals, int count) {
 
 using namespace tpfdm;
 
-struct tp_plan : public Plan {};
 
 struct tp_graph {
     hipGraph_t graph = nullptr;

@@ -201,3 +201,6 @@ tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize,
 tp_status launch_summary_reduce(const Plan& plan, int64_t nparts, hipStream_t s);
 
 }  // namespace tpfdm
+
+// The opaque handle of the C ABI is the plan itself.
+struct tp_plan : public tpfdm::Plan {};

@@ -1,0 +1,427 @@
+// Preconditioned conjugate gradients for the coupled SIPG operator of a mesh
+// plan: A x = b in FP64 with the cell-wise fast-diagonalization block-Jacobi
+// preconditioner of Sec. 5.2 (z = D^{-1} r, the cell blocks of
+// eq. (cell_block) with the interior stencil on every cell), applied in FP64
+// or FP32.  The paper's solver wraps this preconditioner in Chebyshev
+// smoothing inside a multigrid cycle (Sec. 5); here it preconditions CG
+// directly.
+//
+// One iteration is five launches, none of which needs the host:
+//   1. q = A p with the per-workgroup partial sums of (p, q)
+//   2. one workgroup: alpha = (r, z) / (p, q)
+//   3. x += alpha p, r -= alpha q, z = D^{-1} r, partial sums of (r, z), (r, r)
+//   4. one workgroup: beta = (r, z)_new / (r, z), convergence test on (r, r)
+//   5. p = z + beta p
+// The state (scalars, iteration count, done flag) lives in device memory;
+// once the flag is set every later kernel returns at its first instruction,
+// so the host enqueues iterations in chunks and reads the state once per
+// chunk.  Reductions sum per-workgroup partials in a fixed order (no
+// atomics), so a solve is deterministic.
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "sipg.h"
+
+namespace tpfdm {
+
+// Device-side solver state.  done: 0 running, 1 converged, 2 breakdown or a
+// non-finite scalar, 3 iteration limit.
+struct PcgState {
+    double rz, pq, rr, bb, alpha, beta, tol2;
+    int iter, done, maxit, pad;
+};
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ bool finite(double v) { return v == v && v <= 1.7976931348623157e308 && v >= -1.7976931348623157e308; }
+
+// 1.  q = A p, partial (p, q) per workgroup.
+template <int N, int LB>
+__global__ __launch_bounds__(64, 2) void k_pcg_aq(const double* __restrict__ p, double* __restrict__ q, MeshArgs G,
+                                                Pair<N, double> R, FaceRef<N, double> F,
+                                                const PcgState* __restrict__ st, double* __restrict__ part) {
+    if (st->done) return;
+    constexpr int N3 = N * N * N;
+    __shared__ double sa[N * N][64], sbt[N * N][64];
+    const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
+    const int lb = LB >= 0 ? LB : G.logB;
+    double dot = 0.0;
+    if (c < G.ncells) {
+        double acc[N3];
+        sipg_cell<N, double, double, LB>(p, G, R, F, c, acc, sa, sbt);
+        const int64_t base = G.offset + block_base(c, lb, N3);
+#pragma unroll
+        for (int e = 0; e < N3; ++e) {
+            const int64_t o = base + (static_cast<int64_t>(e) << lb);
+            q[o] = acc[e];
+            dot = fma(acc[e], p[o], dot);
+        }
+    }
+    dot = wave_sum(dot);
+    if (threadIdx.x == 0) part[blockIdx.x] = dot;
+}
+
+// Fixed-order sum of count partials by one 256-thread workgroup.
+__device__ __forceinline__ double block_sum(const double* __restrict__ part, int64_t count, double* red) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (static_cast<int>(threadIdx.x) < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// 0.  After the start kernel: (r, z), (r, r), (b, b) -> state.
+__global__ __launch_bounds__(256) void k_pcg_reduce_start(const double* __restrict__ part, int64_t count,
+                                                          PcgState* __restrict__ st, double rtol, int maxit) {
+    __shared__ double red[256];
+    const double rz = block_sum(part, count, red);
+    const double rr = block_sum(part + count, count, red);
+    const double bb = block_sum(part + 2 * count, count, red);
+    if (threadIdx.x == 0) {
+        PcgState s;
+        s.rz = rz;
+        s.pq = 0.0;
+        s.rr = rr;
+        s.bb = bb;
+        s.alpha = 0.0;
+        s.beta = 0.0;
+        s.tol2 = rtol * rtol * bb;
+        s.iter = 0;
+        s.maxit = maxit;
+        s.pad = 0;
+        s.done = !(finite(rz) && finite(rr) && finite(bb)) ? 2 : (rr <= s.tol2 ? 1 : (maxit <= 0 ? 3 : 0));
+        *st = s;
+    }
+}
+
+// 2.  alpha = (r, z) / (p, q).
+__global__ __launch_bounds__(256) void k_pcg_reduce_alpha(const double* __restrict__ part, int64_t count,
+                                                          PcgState* __restrict__ st) {
+    if (st->done) return;
+    __shared__ double red[256];
+    const double pq = block_sum(part, count, red);
+    if (threadIdx.x == 0) {
+        st->pq = pq;
+        if (!(pq > 0.0) || !finite(pq)) {
+            st->done = 2;
+        } else {
+            st->alpha = st->rz / pq;
+        }
+    }
+}
+
+// 4.  beta, the iteration count and the convergence test.
+__global__ __launch_bounds__(256) void k_pcg_reduce_beta(const double* __restrict__ part, int64_t count,
+                                                         PcgState* __restrict__ st) {
+    if (st->done) return;
+    __shared__ double red[256];
+    const double rz = block_sum(part, count, red);
+    const double rr = block_sum(part + count, count, red);
+    if (threadIdx.x == 0) {
+        const double rz_old = st->rz;
+        st->beta = rz / rz_old;
+        st->rz = rz;
+        st->rr = rr;
+        const int it = st->iter + 1;
+        st->iter = it;
+        if (!finite(rz) || !finite(rr)) st->done = 2;
+        else if (rr <= st->tol2) st->done = 1;
+        else if (it >= st->maxit) st->done = 3;
+    }
+}
+
+// z = D^{-1} r for the lane's cell in precision TI, read from and written to
+// FP64 vectors; returns the partial (r, z) of the cell.
+template <int N, typename TI, int LB>
+__device__ __forceinline__ double precondition(const double* __restrict__ r, double* __restrict__ z, int64_t base,
+                                               int lb, const Eig<N, TI>& E, TI sx, TI sy, TI sz) {
+    constexpr int N3 = N * N * N;
+    TI v[N3];
+#pragma unroll
+    for (int e = 0; e < N3; ++e) v[e] = static_cast<TI>(r[base + (static_cast<int64_t>(e) << lb)]);
+    lane_fdm_inplace<N, TI>(v, E, sx, sy, sz);
+    double rz = 0.0;
+#pragma unroll
+    for (int e = 0; e < N3; ++e) {
+        const int64_t o = base + (static_cast<int64_t>(e) << lb);
+        const double zv = static_cast<double>(v[e]);
+        z[o] = zv;
+        rz = fma(r[o], zv, rz);
+    }
+    return rz;
+}
+
+// Start: r = b (x <- 0) or r = b - q with q = A x; z = D^{-1} r; p = z;
+// partials (r, z), (r, r), (b, b).
+template <int N, typename TI, int LB>
+__global__ __launch_bounds__(64, 2) void k_pcg_start(const double* __restrict__ b, const double* __restrict__ q,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ z, double* __restrict__ p, MeshArgs G,
+                                                   Eig<N, TI> E, double* __restrict__ part, int64_t count) {
+    constexpr int N3 = N * N * N;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    const int lb = LB >= 0 ? LB : G.logB;
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    if (c < G.ncells) {
+        const int64_t base = G.offset + block_base(c, lb, N3);
+#pragma unroll
+        for (int e = 0; e < N3; ++e) {
+            const int64_t o = base + (static_cast<int64_t>(e) << lb);
+            const double bv = b[o];
+            const double rv = q ? bv - q[o] : bv;
+            if (!q) x[o] = 0.0;   // a zero initial guess is written, not assumed
+            r[o] = rv;
+            rr = fma(rv, rv, rr);
+            bb = fma(bv, bv, bb);
+        }
+        rz = precondition<N, TI, LB>(r, z, base, lb, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy),
+                                     static_cast<TI>(G.sz));
+#pragma unroll
+        for (int e = 0; e < N3; ++e) {
+            const int64_t o = base + (static_cast<int64_t>(e) << lb);
+            p[o] = z[o];
+        }
+    }
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rz;
+        part[count + blockIdx.x] = rr;
+        part[2 * count + blockIdx.x] = bb;
+    }
+}
+
+// 3.  x += alpha p, r -= alpha q, z = D^{-1} r; partials (r, z), (r, r).
+template <int N, typename TI, int LB>
+__global__ __launch_bounds__(64, 2) void k_pcg_update(double* __restrict__ x, double* __restrict__ r,
+                                                    double* __restrict__ z, const double* __restrict__ p,
+                                                    const double* __restrict__ q, MeshArgs G, Eig<N, TI> E,
+                                                    const PcgState* __restrict__ st, double* __restrict__ part,
+                                                    int64_t count) {
+    if (st->done) return;
+    constexpr int N3 = N * N * N;
+    const double alpha = st->alpha;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    const int lb = LB >= 0 ? LB : G.logB;
+    double rz = 0.0, rr = 0.0;
+    if (c < G.ncells) {
+        const int64_t base = G.offset + block_base(c, lb, N3);
+#pragma unroll
+        for (int e = 0; e < N3; ++e) {
+            const int64_t o = base + (static_cast<int64_t>(e) << lb);
+            x[o] = fma(alpha, p[o], x[o]);
+            const double rv = fma(-alpha, q[o], r[o]);
+            r[o] = rv;
+            rr = fma(rv, rv, rr);
+        }
+        rz = precondition<N, TI, LB>(r, z, base, lb, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy),
+                                     static_cast<TI>(G.sz));
+    }
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rz;
+        part[count + blockIdx.x] = rr;
+    }
+}
+
+// 5.  p = z + beta p over the whole vector (padding lanes included: they are
+// never read as cell data).
+__global__ __launch_bounds__(256) void k_pcg_dir(const double* __restrict__ z, double* __restrict__ p, int64_t n,
+                                                 const PcgState* __restrict__ st) {
+    if (st->done) return;
+    const double beta = st->beta;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * 256)
+        p[i] = fma(beta, p[i], z[i]);
+}
+
+tp_status check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, what);
+    return TP_OK;
+}
+
+template <int N, typename T>
+Eig<N, T> mesh_eig(const RefData& ref) {
+    Eig<N, T> E;
+    for (int i = 0; i < N * N; ++i) E.s[i] = static_cast<T>(ref.S[i]);
+    for (int i = 0; i < N; ++i) E.lam[i] = static_cast<T>(ref.lam[i]);
+    return E;
+}
+
+}  // namespace
+}  // namespace tpfdm
+
+using namespace tpfdm;
+
+// Workspace of one solver instance (plan-sized vectors and partials).
+struct tp_pcg {
+    tp_plan* plan = nullptr;
+    double* r = nullptr;
+    double* z = nullptr;
+    double* p = nullptr;
+    double* q = nullptr;
+    double* part = nullptr;     // [3][nwg]
+    PcgState* st = nullptr;     // device
+    PcgState* host = nullptr;   // pinned host copy
+    int64_t nwg = 0;
+    int64_t elems = 0;
+};
+
+namespace {
+
+void free_pcg(tp_pcg* s) {
+    for (void* ptr : {static_cast<void*>(s->r), static_cast<void*>(s->z), static_cast<void*>(s->p),
+                      static_cast<void*>(s->q), static_cast<void*>(s->part), static_cast<void*>(s->st)})
+        if (ptr) (void)hipFree(ptr);
+    if (s->host) (void)hipHostFree(s->host);
+}
+
+template <int N, typename TI, int LB>
+tp_status pcg_run(const Plan& plan, const GroupInfo& g, tp_pcg* s, const double* b, double* x, bool x_zero,
+                  double rtol, int maxit, int chunk, hipStream_t stream) {
+    const MeshArgs G = mesh_args(plan, g);
+    Pair<N, double> R;
+    FaceRef<N, double> F;
+    sipg_tables<N, double>(plan, false, R, F);
+    const Eig<N, TI> E = mesh_eig<N, TI>(plan.ref[N]);
+    const unsigned nwg = static_cast<unsigned>(s->nwg);
+    const int64_t cnt = s->nwg;
+    const unsigned dgrid = static_cast<unsigned>(std::min<int64_t>((s->elems + 255) / 256, 8192));
+    if (!x_zero) {
+        tp_status st = launch_sipg(plan, g, false, x, s->q, TP_F64, stream);
+        if (st != TP_OK) return st;
+    }
+    hipLaunchKernelGGL((k_pcg_start<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q, x,
+                       s->r, s->z, s->p, G, E, s->part, cnt);
+    hipLaunchKernelGGL(k_pcg_reduce_start, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st, rtol, maxit);
+    tp_status st = check_launch("PCG start");
+    if (st != TP_OK) return st;
+    for (;;) {
+        hipError_t e = hipMemcpyAsync(s->host, s->st, sizeof(PcgState), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_error(e, "PCG state read-back");
+        if (s->host->done) return TP_OK;
+        for (int i = 0; i < chunk; ++i) {
+            hipLaunchKernelGGL((k_pcg_aq<N, LB>), dim3(nwg), dim3(64), 0, stream, s->p, s->q, G, R, F, s->st,
+                               s->part);
+            hipLaunchKernelGGL(k_pcg_reduce_alpha, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st);
+            hipLaunchKernelGGL((k_pcg_update<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, x, s->r, s->z, s->p, s->q,
+                               G, E, s->st, s->part, cnt);
+            hipLaunchKernelGGL(k_pcg_reduce_beta, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st);
+            hipLaunchKernelGGL(k_pcg_dir, dim3(dgrid), dim3(256), 0, stream, s->z, s->p, s->elems, s->st);
+        }
+        st = check_launch("PCG iteration");
+        if (st != TP_OK) return st;
+    }
+}
+
+template <typename TI>
+tp_status pcg_dispatch(const Plan& plan, const GroupInfo& g, tp_pcg* s, const double* b, double* x, bool x_zero,
+                       double rtol, int maxit, int chunk, hipStream_t stream) {
+    const bool b64 = g.logB == 6;
+    switch (g.n) {
+        case 2: return b64 ? pcg_run<2, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
+                           : pcg_run<2, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        case 3: return b64 ? pcg_run<3, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
+                           : pcg_run<3, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        case 4: return b64 ? pcg_run<4, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
+                           : pcg_run<4, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        default: break;
+    }
+    return set_error(TP_ERR_UNSUPPORTED, "the PCG solver supports n <= 4");
+}
+
+}  // namespace
+
+extern "C" {
+
+tp_status tp_pcg_create(tp_plan* plan, tp_pcg** out) {
+    if (!out) return set_error(TP_ERR_ARG, "out must be non-null");
+    *out = nullptr;
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (!plan->mesh) return set_error(TP_ERR_UNSUPPORTED, "the PCG solver needs a mesh plan");
+    if (plan->groups[0].n > kLaneMaxN) return set_error(TP_ERR_UNSUPPORTED, "the PCG solver supports n <= 4");
+    tp_pcg* s = new (std::nothrow) tp_pcg();
+    if (!s) return set_error(TP_ERR_OOM, "host allocation failed");
+    s->plan = plan;
+    s->elems = std::max<int64_t>(plan->vec_elems, 1);
+    s->nwg = std::max<int64_t>((plan->groups[0].nblocks + 63) / 64, 1);
+    const size_t vb = static_cast<size_t>(s->elems) * sizeof(double);
+    hipError_t e = hipSuccess;
+    for (double** d : {&s->r, &s->z, &s->p, &s->q})
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(d), vb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->part), 3 * s->nwg * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->st), sizeof(PcgState));
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->host), sizeof(PcgState), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        free_pcg(s);
+        delete s;
+        (void)hipGetLastError();
+        return set_error(TP_ERR_OOM, "PCG workspace allocation failed");
+    }
+    *out = s;
+    return TP_OK;
+}
+
+tp_status tp_pcg_solve(tp_pcg* s, const double* b, double* x, int32_t x_is_zero, tp_dtype inner, double rtol,
+                       int32_t maxit, int32_t check_every, tp_pcg_summary* summary, hipStream_t stream) {
+    if (!s) return set_error(TP_ERR_ARG, "solver is null");
+    const Plan& plan = *s->plan;
+    if (plan.vec_elems > 0 && (!b || !x)) return set_error(TP_ERR_ARG, "b and x must be non-null");
+    if (static_cast<const void*>(b) == static_cast<const void*>(x) && b)
+        return set_error(TP_ERR_ARG, "b and x must not alias");
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return set_error(TP_ERR_ARG, "rtol must be finite and > 0");
+    if (maxit < 0) return set_error(TP_ERR_ARG, "maxit must be >= 0");
+    if (inner != TP_F64 && inner != TP_F32)
+        return set_error(TP_ERR_UNSUPPORTED, "the preconditioner runs in TP_F64 or TP_F32");
+    if (plan.inverse_op != TP_OP_CELL || plan.factor_mode != TP_FACTOR_SCALED)
+        return set_error(TP_ERR_STATE, "tp_pcg_solve needs tp_setup_inverse(TP_OP_CELL, TP_FACTOR_SCALED) first");
+    const int chunk = check_every > 0 ? check_every : 16;
+    const GroupInfo& g = plan.groups[0];
+    tp_status st = TP_OK;
+    if (g.nblocks == 0) {
+        if (summary) *summary = tp_pcg_summary{0, 1, 0.0};
+        return TP_OK;
+    }
+    st = inner == TP_F64 ? pcg_dispatch<double>(plan, g, s, b, x, x_is_zero != 0, rtol, maxit, chunk, stream)
+                         : pcg_dispatch<float>(plan, g, s, b, x, x_is_zero != 0, rtol, maxit, chunk, stream);
+    if (st != TP_OK) return st;
+    const PcgState h = *s->host;
+    if (summary) {
+        summary->iterations = h.iter;
+        summary->converged = h.done == 1 ? 1 : 0;
+        summary->relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    }
+    if (h.done == 2) return set_error(TP_ERR_NONFINITE, "PCG breakdown or non-finite value after " +
+                                                            std::to_string(h.iter) + " iterations");
+    if (h.done == 3)
+        return set_error(TP_ERR_NOT_CONVERGED, "PCG reached maxit = " + std::to_string(h.iter) +
+                                                   " with relative residual " +
+                                                   std::to_string(h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0));
+    return TP_OK;
+}
+
+tp_status tp_pcg_destroy(tp_pcg* s) {
+    if (!s) return TP_OK;
+    free_pcg(s);
+    delete s;
+    return TP_OK;
+}
+
+}  // extern "C"

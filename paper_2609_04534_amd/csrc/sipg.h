@@ -1,0 +1,280 @@
+// Device code of the coupled SIPG operator on a uniform Cartesian box mesh
+// (shared by sipg.hip and pcg.hip).  One fused kernel computes v = A u with A = A^vol + A^face (Sec. 3, eq. (sipg),
+// eq. (operator_split)), homogeneous Dirichlet data imposed by Nitsche's
+// terms on the boundary faces.
+//
+// Row of cell c.  The cell-diagonal block is the Kronecker sum of the cell
+// block (eq. (cell_block), A_hat = K_hat + the own-side blocks of both
+// interior face stencils) plus, on a boundary face, the difference between
+// the Nitsche own-side block and the interior one.  The off-diagonal blocks
+// couple c to its face neighbours through N^{-+} and N^{+-} of
+// eq. (face_factorized) in the normal slot and the mass matrix in the two
+// tangential slots.  With e0, e1 the endpoint values (unit vectors of the
+// Gauss-Lobatto basis) and g0, g1 the reference endpoint derivatives, every
+// face term is rank two in the normal slot (the rank-two flux structure of
+// Sec. 6.3):
+//
+//   (N w)_i = e_end,i alpha(w) + g_end,i beta(w),    then (x) M (x) M,
+//
+// where, for the face at the cell's upper end along an axis (normal slot
+// index k, source block w):
+//   interior:  w = upper neighbour, alpha = -sigma w_0 - 1/2 g0.w,  beta = +1/2 w_0
+//   boundary:  w = the cell itself, alpha = -1/2 g1.w,              beta = -1/2 w_{n-1}
+// and for the lower end:
+//   interior:  w = lower neighbour, alpha = -sigma w_{n-1} + 1/2 g1.w, beta = -1/2 w_{n-1}
+//   boundary:  w = the cell itself, alpha = +1/2 g0.w,                 beta = +1/2 w_0
+// (sigma = C p (p+1), Sec. 6.2; every term scales with s_d = h_o1 h_o2 / h_d
+// like the volume term of that axis).  The face-only operator A^face uses
+// A_hat - K_hat for the cell-diagonal Kronecker sum.
+//
+// Unlike the paper's separate face-exchange sweeps, which read and update
+// the output's face layers once per axis, the kernel is cell-centric: every
+// cell reads its six neighbours (from cache: the same blocks are its
+// neighbours' own inputs) and writes its output block once, so HBM sees one
+// read of u and one write of v.  Each interior face is evaluated from both
+// sides, which costs arithmetic, not HBM bytes.
+//
+// Mesh order: cell (cx, cy, cz) is block c = (cx m_y + cy) m_z + cz of the
+// blocked layout, so the B cells of a tile are consecutive along z.
+#pragma once
+
+#include "lane.h"
+
+namespace tpfdm {
+
+struct MeshArgs {
+    int64_t ncells;
+    int64_t offset;
+    int logB;
+    int mx, my, mz;
+    double sx, sy, sz;   // s_d = h_o1 h_o2 / h_d
+};
+
+template <int N, typename T>
+struct FaceRef {        // reference endpoint derivatives and penalty C p (p+1)
+    T g0[N];
+    T g1[N];
+    T sigma;
+};
+
+// DoF index of (normal layer k, tangential a, b) for a face normal to axis D
+// (a, b are the two other axes in increasing order).
+template <int N, int D>
+__device__ __forceinline__ constexpr int fq(int k, int a, int b) {
+    return D == 0 ? (k * N + a) * N + b : D == 1 ? (a * N + k) * N + b : (a * N + b) * N + k;
+}
+
+// Forces the values to be computed here: the compiler would otherwise sink
+// arithmetic below later loads (past scheduling barriers), keeping all the
+// loaded layers live at once.
+template <typename T, int K>
+__device__ __forceinline__ void pin(T (&a)[K]) {
+#pragma unroll
+    for (int e = 0; e < K; ++e) asm volatile("" : "+v"(a[e]));
+}
+
+// Adds one face's term to the lane's output block acc.  w: the source
+// block's DoF 0 (neighbour or the cell itself, see the header), s: s_D.
+// The source's n layers (normal index) are loaded once, layer by layer:
+// alpha = sum_k ca_k w_k accumulates in registers, and the beta slab (the
+// source's layer 0 or n-1, weighted +-1/2) is taken from the same loads.
+// Each slab gets the tangential mass contraction M (.) M in two passes:
+// rows are contracted along the second tangential index and parked in the
+// lane's LDS slabs (sa: alpha, sbt: beta; [e][lane], private to the lane);
+// columns are read back, contracted along the first and accumulated into
+// acc (alpha into layer kend, beta into every layer with weight g_end).
+template <int N, int D, bool UP, typename TS, typename TC, int LB>
+__device__ __forceinline__ void lane_face(const TS* __restrict__ w, int lb, bool interior, const TC* M,
+                                          const FaceRef<N, TC>& F, TC s, TC (&acc)[N * N * N], TC (*sa)[64],
+                                          TC (*sbt)[64]) {
+    constexpr int kend = UP ? N - 1 : 0;
+    const int l = LB >= 0 ? LB : lb;
+    const int lane = threadIdx.x;
+    auto ld = [&](int q) { return ldc<TC>(w + (static_cast<int64_t>(q) << l)); };
+    // row r (already weighted) -> dst[a][.] = M-contracted row (+ dst when ADD)
+    auto park_row = [&](TC(*dst)[64], int a, const TC* r, bool add) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            TC t = add ? dst[a * N + b][lane] : TC(0);
+#pragma unroll
+            for (int bb = 0; bb < N; ++bb) t = fma(M[b * N + bb], r[bb], t);
+            dst[a * N + b][lane] = t;
+        }
+    };
+    // column b of a parked slab, contracted along a
+    auto column = [&](TC(*src)[64], int b, TC (&out)[N]) {
+        TC col[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) col[a] = src[a * N + b][lane];
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            TC t = TC(0);
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) t = fma(M[a * N + aa], col[aa], t);
+            out[a] = t;
+        }
+    };
+    // beta comes from layer 0 when the face is interior at the upper end or
+    // boundary at the lower end, else from layer n-1
+    const bool first = (UP == interior);
+    const TC cb0 = first ? TC(0.5) * s : TC(0);    // weight of layer 0
+    const TC cbn = first ? TC(0) : TC(-0.5) * s;   // weight of layer n-1
+    TC ca[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const TC in = UP ? fma(TC(-0.5), F.g0[k], k == 0 ? -F.sigma : TC(0))
+                         : fma(TC(0.5), F.g1[k], k == N - 1 ? -F.sigma : TC(0));
+        const TC bd = UP ? TC(-0.5) * F.g1[k] : TC(0.5) * F.g0[k];
+        ca[k] = s * (interior ? in : bd);
+    }
+    {
+        // the next layer's loads in flight while one is accumulated, except
+        // where the lane's output block already fills half the register file
+        // (n = 4 in FP64)
+        constexpr bool DB = N * N * N * sizeof(TC) < 512;
+        TC sl[N][N], lay[DB ? 2 : 1][N * N];
+        auto load_layer = [&](int k, TC(&dst)[N * N]) {
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = 0; b < N; ++b) dst[a * N + b] = ld(fq<N, D>(k, a, b));
+        };
+        __builtin_amdgcn_sched_barrier(0);
+        load_layer(0, lay[0]);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (DB) {
+                if (k + 1 < N) load_layer(k + 1, lay[(k + 1) & 1]);
+            } else if (k > 0) {
+                load_layer(k, lay[0]);
+            }
+            TC* cur = lay[DB ? (k & 1) : 0];
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+                    sl[a][b] = k == 0 ? ca[0] * cur[a * N + b] : fma(ca[k], cur[a * N + b], sl[a][b]);
+                pin(sl[a]);
+            }
+            if (k == 0 || k == N - 1) {
+                // beta = cb0 w_0 + cbn w_{n-1}: one of the two weights is zero
+                // per lane, so the slab needs no per-lane branch
+                const TC cw = k == 0 ? cb0 : cbn;
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    TC r[N];
+#pragma unroll
+                    for (int b = 0; b < N; ++b) r[b] = cw * cur[a * N + b];
+                    park_row(sbt, a, r, k != 0);
+                }
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) park_row(sa, a, sl[a], false);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        TC at[N], bt[N];
+        column(sa, b, at);
+        column(sbt, b, bt);
+#pragma unroll
+        for (int a = 0; a < N; ++a) acc[fq<N, D>(kend, a, b)] += at[a];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const TC gk = UP ? F.g1[k] : F.g0[k];
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc[fq<N, D>(k, a, b)] = fma(gk, bt[a], acc[fq<N, D>(k, a, b)]);
+        }
+    }
+}
+
+// (A u) of cell c into acc (the row of eq. (sipg) for one cell, see the
+// header): the six face terms first, then the cell-diagonal Kronecker sum
+// accumulated on top, so no face state is live while the volume product
+// holds its planes.  sa, sbt: the lane's LDS slabs (N^2 x 64 each).
+template <int N, typename TS, typename TC, int LB>
+__device__ __forceinline__ void sipg_cell(const TS* __restrict__ u, const MeshArgs& G, const Pair<N, TC>& R,
+                                          const FaceRef<N, TC>& F, int64_t c, TC (&acc)[N * N * N],
+                                          TC (*sa)[64], TC (*sbt)[64]) {
+    constexpr int N3 = N * N * N;
+    const int lb = LB >= 0 ? LB : G.logB;
+    const uint32_t cu = static_cast<uint32_t>(c);
+    const uint32_t cz = cu % static_cast<uint32_t>(G.mz);
+    const uint32_t rr = cu / static_cast<uint32_t>(G.mz);
+    const uint32_t cy = rr % static_cast<uint32_t>(G.my);
+    const uint32_t cx = rr / static_cast<uint32_t>(G.my);
+    const TS* ub = u + G.offset;
+    const TS* own = ub + block_base(c, lb, N3);
+    const TC sx = static_cast<TC>(G.sx), sy = static_cast<TC>(G.sy), sz = static_cast<TC>(G.sz);
+#pragma unroll
+    for (int q = 0; q < N3; ++q) acc[q] = TC(0);
+    const int64_t syz = static_cast<int64_t>(G.my) * G.mz;
+    // the source cell of a face: the neighbour, or the cell itself on the
+    // boundary (an index select, so the kernel stays one basic block)
+    auto src = [&](bool interior, int64_t d) { return ub + block_base(interior ? c + d : c, lb, N3); };
+    {
+        const bool lo = cx > 0, hi = cx + 1 < static_cast<uint32_t>(G.mx);
+        lane_face<N, 0, false, TS, TC, LB>(src(lo, -syz), lb, lo, R.m, F, sx, acc, sa, sbt);
+        lane_face<N, 0, true, TS, TC, LB>(src(hi, syz), lb, hi, R.m, F, sx, acc, sa, sbt);
+    }
+    {
+        const bool lo = cy > 0, hi = cy + 1 < static_cast<uint32_t>(G.my);
+        lane_face<N, 1, false, TS, TC, LB>(src(lo, -G.mz), lb, lo, R.m, F, sy, acc, sa, sbt);
+        lane_face<N, 1, true, TS, TC, LB>(src(hi, G.mz), lb, hi, R.m, F, sy, acc, sa, sbt);
+    }
+    {
+        const bool lo = cz > 0, hi = cz + 1 < static_cast<uint32_t>(G.mz);
+        lane_face<N, 2, false, TS, TC, LB>(src(lo, -1), lb, lo, R.m, F, sz, acc, sa, sbt);
+        lane_face<N, 2, true, TS, TC, LB>(src(hi, 1), lb, hi, R.m, F, sz, acc, sa, sbt);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    lane_apply<N, TC, false, true>([&](int q) { return ldc<TC>(own + (static_cast<int64_t>(q) << lb)); }, R, sx, sy,
+                                   sz, acc);
+}
+
+// Tile of workgroup b in an XCD-contiguous order: workgroup b runs on XCD
+// b % 8, and each XCD gets a contiguous range of tiles so that the y and z
+// neighbours of its tiles share its L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nwg) {
+    return (nwg % 8 == 0) ? (b % 8) * (nwg / 8) + b / 8 : b;
+}
+
+// Kernel arguments of a mesh plan's group.
+inline MeshArgs mesh_args(const Plan& plan, const GroupInfo& g) {
+    MeshArgs G;
+    G.ncells = g.nblocks;
+    G.offset = g.offset;
+    G.logB = g.logB;
+    G.mx = plan.mesh_m[0];
+    G.my = plan.mesh_m[1];
+    G.mz = plan.mesh_m[2];
+    const double hx = plan.mesh_h[0], hy = plan.mesh_h[1], hz = plan.mesh_h[2];
+    G.sx = hy * hz / hx;
+    G.sy = hx * hz / hy;
+    G.sz = hx * hy / hz;
+    return G;
+}
+
+// 1D tables of the coupled operator: M_hat and the cell-diagonal P_hat
+// (A_hat, or A_hat - K_hat for the face part alone), endpoint derivatives and
+// the reference penalty.
+template <int N, typename TC>
+void sipg_tables(const Plan& plan, bool face_only, Pair<N, TC>& R, FaceRef<N, TC>& F) {
+    const RefData& ref = plan.ref[N];
+    for (int i = 0; i < N * N; ++i) {
+        R.m[i] = static_cast<TC>(ref.M[i]);
+        R.p[i] = static_cast<TC>(face_only ? ref.A[i] - ref.K[i] : ref.A[i]);
+    }
+    double g0[N], g1[N];
+    endpoint_derivatives(N, g0, g1);
+    for (int i = 0; i < N; ++i) {
+        F.g0[i] = static_cast<TC>(g0[i]);
+        F.g1[i] = static_cast<TC>(g1[i]);
+    }
+    F.sigma = static_cast<TC>(plan.penalty_C * (N - 1) * N);
+}
+
+}  // namespace tpfdm

@@ -35,6 +35,7 @@ EXPORTS = (
     "tp_solve", "tp_pack", "tp_unpack", "tp_reference_matrices", "tp_reference_eigen",
     "tp_last_error", "tp_version", "tp_solve_summary_fetch", "tp_graph_create", "tp_graph_launch",
     "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel", "tp_plan_create_mesh",
+    "tp_pcg_create", "tp_pcg_solve", "tp_pcg_destroy",
 )
 KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
@@ -61,6 +62,10 @@ class _Opts(ctypes.Structure):
 class _Mesh(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("layout_B", ctypes.c_int32), ("cells", ctypes.c_int32 * 3),
                 ("reserved", ctypes.c_int32), ("h", ctypes.c_double * 3)]
+
+
+class _PcgSummary(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("relres", ctypes.c_double)]
 
 
 class _Summary(ctypes.Structure):
@@ -104,6 +109,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_plan_autotune": (i32, [vp, i32, i32, vp]),
         "tp_plan_group_kernel": (i32, [vp, i32, i32, i32]),
         "tp_plan_create_mesh": (i32, [ctypes.POINTER(_Mesh), ctypes.POINTER(_Opts), ctypes.POINTER(vp)]),
+        "tp_pcg_create": (i32, [vp, ctypes.POINTER(vp)]),
+        "tp_pcg_solve": (i32, [vp, vp, vp, i32, i32, dbl, i32, i32, ctypes.POINTER(_PcgSummary), vp]),
+        "tp_pcg_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -348,6 +356,45 @@ class Plan:
     def destroy(self):
         if self._h is not None:
             load().tp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+class PCG:
+    """Preconditioned CG for the coupled SIPG system of a mesh plan (tp_pcg_*)."""
+
+    def __init__(self, plan: "Plan"):
+        h = ctypes.c_void_p()
+        _check(load().tp_pcg_create(plan.handle, ctypes.byref(h)))
+        self._h = h
+        self.plan = plan
+
+    def solve(self, b, x, x_is_zero: bool = True, inner: int = F64, rtol: float = 1e-8, maxit: int = 1000,
+              check_every: int = 16, stream=None, raise_on_failure: bool = True) -> dict:
+        """Solve A x = b; returns {iterations, converged, relres, status}."""
+        summ = _PcgSummary()
+        st = load().tp_pcg_solve(self._h, _ptr(b), _ptr(x), 1 if x_is_zero else 0, inner, rtol, maxit,
+                                 check_every, ctypes.byref(summ), _stream(stream))
+        out = {"iterations": summ.iterations, "converged": bool(summ.converged), "relres": summ.relres,
+               "status": st}
+        if st != TP_OK and raise_on_failure:
+            _check(st)
+        return out
+
+    def destroy(self):
+        if self._h is not None:
+            load().tp_pcg_destroy(self._h)
             self._h = None
 
     def __del__(self):
