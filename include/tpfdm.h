@@ -295,11 +295,15 @@ int32_t tp_plan_group_kernel(const tp_plan* plan, int32_t group, int32_t call, t
  * cell blocks of eq. (cell_block), interior stencil on every cell), applied
  * in `inner` precision (TP_F64, or TP_F32 on the FP64 vectors).  Needs
  * tp_setup_inverse(plan, TP_OP_CELL, TP_FACTOR_SCALED, ...) first
- * (TP_ERR_STATE).  tp_pcg_create allocates the solver's workspace (four
- * plan-sized FP64 vectors and the reduction partials); the plan must outlive
- * it.  tp_pcg_solve: b, x device FP64 vectors in the plan's layout; x is the
+ * (TP_ERR_STATE).  tp_pcg_create allocates the solver's workspace (five
+ * plan-sized FP64 vectors, the iterate included, and the reduction
+ * partials); the plan must outlive it.  The first solve in each `inner`
+ * precision captures a chunk of check_every iterations into a HIP graph that
+ * later solves replay (iterations are enqueued as graph launches).  tp_pcg_solve: b, x device FP64 vectors in the plan's layout; x is the
  * initial guess unless x_is_zero (then x is overwritten with zero first) and
- * holds the last iterate on return.  Stops when ||r||_2 <= rtol ||b||_2 for
+ * holds the last iterate on return (x is written only at the end).  b = 0
+ * with x_is_zero gives x = 0 at once; b = 0 with a non-zero guess cannot meet
+ * the relative test and runs to maxit.  Stops when ||r||_2 <= rtol ||b||_2 for
  * the recursively updated residual r, or after maxit iterations
  * (TP_ERR_NOT_CONVERGED), or on a breakdown / non-finite value
  * (TP_ERR_NONFINITE).  Every iteration runs on the device without host

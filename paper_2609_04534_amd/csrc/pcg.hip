@@ -143,15 +143,14 @@ __global__ __launch_bounds__(256) void k_pcg_reduce_beta(const double* __restric
     }
 }
 
-// z = D^{-1} r for the lane's cell in precision TI, read from and written to
-// FP64 vectors; returns the partial (r, z) of the cell.
+// z = D^{-1} r for the lane's cell in precision TI: v holds the cell's
+// residual (already rounded to TI), z is written in FP64; returns the
+// partial (r, z) of the cell with r re-read in FP64.
 template <int N, typename TI, int LB>
-__device__ __forceinline__ double precondition(const double* __restrict__ r, double* __restrict__ z, int64_t base,
-                                               int lb, const Eig<N, TI>& E, TI sx, TI sy, TI sz) {
+__device__ __forceinline__ double precondition(TI (&v)[N * N * N], const double* __restrict__ r,
+                                               double* __restrict__ z, int64_t base, int lb, const Eig<N, TI>& E,
+                                               TI sx, TI sy, TI sz) {
     constexpr int N3 = N * N * N;
-    TI v[N3];
-#pragma unroll
-    for (int e = 0; e < N3; ++e) v[e] = static_cast<TI>(r[base + (static_cast<int64_t>(e) << lb)]);
     lane_fdm_inplace<N, TI>(v, E, sx, sy, sz);
     double rz = 0.0;
 #pragma unroll
@@ -164,30 +163,33 @@ __device__ __forceinline__ double precondition(const double* __restrict__ r, dou
     return rz;
 }
 
-// Start: r = b (x <- 0) or r = b - q with q = A x; z = D^{-1} r; p = z;
+// Start: x = x0 and r = b - q with q = A x0, or x = 0 and r = b; z = D^{-1} r; p = z;
 // partials (r, z), (r, r), (b, b).
 template <int N, typename TI, int LB>
 __global__ __launch_bounds__(64, 2) void k_pcg_start(const double* __restrict__ b, const double* __restrict__ q,
-                                                   double* __restrict__ x, double* __restrict__ r,
-                                                   double* __restrict__ z, double* __restrict__ p, MeshArgs G,
-                                                   Eig<N, TI> E, double* __restrict__ part, int64_t count) {
+                                                   const double* __restrict__ x0, double* __restrict__ x,
+                                                   double* __restrict__ r, double* __restrict__ z,
+                                                   double* __restrict__ p, MeshArgs G, Eig<N, TI> E,
+                                                   double* __restrict__ part, int64_t count) {
     constexpr int N3 = N * N * N;
     const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
     const int lb = LB >= 0 ? LB : G.logB;
     double rz = 0.0, rr = 0.0, bb = 0.0;
     if (c < G.ncells) {
         const int64_t base = G.offset + block_base(c, lb, N3);
+        TI v[N3];
 #pragma unroll
         for (int e = 0; e < N3; ++e) {
             const int64_t o = base + (static_cast<int64_t>(e) << lb);
             const double bv = b[o];
             const double rv = q ? bv - q[o] : bv;
-            if (!q) x[o] = 0.0;   // a zero initial guess is written, not assumed
+            x[o] = q ? x0[o] : 0.0;   // the solver's iterate starts from the guess
             r[o] = rv;
+            v[e] = static_cast<TI>(rv);
             rr = fma(rv, rv, rr);
             bb = fma(bv, bv, bb);
         }
-        rz = precondition<N, TI, LB>(r, z, base, lb, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy),
+        rz = precondition<N, TI, LB>(v, r, z, base, lb, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy),
                                      static_cast<TI>(G.sz));
 #pragma unroll
         for (int e = 0; e < N3; ++e) {
@@ -220,15 +222,17 @@ __global__ __launch_bounds__(64, 2) void k_pcg_update(double* __restrict__ x, do
     double rz = 0.0, rr = 0.0;
     if (c < G.ncells) {
         const int64_t base = G.offset + block_base(c, lb, N3);
+        TI v[N3];
 #pragma unroll
         for (int e = 0; e < N3; ++e) {
             const int64_t o = base + (static_cast<int64_t>(e) << lb);
             x[o] = fma(alpha, p[o], x[o]);
             const double rv = fma(-alpha, q[o], r[o]);
             r[o] = rv;
+            v[e] = static_cast<TI>(rv);
             rr = fma(rv, rv, rr);
         }
-        rz = precondition<N, TI, LB>(r, z, base, lb, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy),
+        rz = precondition<N, TI, LB>(v, r, z, base, lb, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy),
                                      static_cast<TI>(G.sz));
     }
     rz = wave_sum(rz);
@@ -276,18 +280,25 @@ struct tp_pcg {
     double* z = nullptr;
     double* p = nullptr;
     double* q = nullptr;
+    double* xw = nullptr;       // the iterate (copied to the caller's x at the end)
     double* part = nullptr;     // [3][nwg]
     PcgState* st = nullptr;     // device
     PcgState* host = nullptr;   // pinned host copy
     int64_t nwg = 0;
     int64_t elems = 0;
+    // one captured chunk of iterations per preconditioner precision (F64, F32)
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int exec_chunk[2] = {0, 0};
 };
 
 namespace {
 
 void free_pcg(tp_pcg* s) {
+    for (hipGraphExec_t& ex : s->exec)
+        if (ex) (void)hipGraphExecDestroy(ex), ex = nullptr;
     for (void* ptr : {static_cast<void*>(s->r), static_cast<void*>(s->z), static_cast<void*>(s->p),
-                      static_cast<void*>(s->q), static_cast<void*>(s->part), static_cast<void*>(s->st)})
+                      static_cast<void*>(s->q), static_cast<void*>(s->xw), static_cast<void*>(s->part),
+                      static_cast<void*>(s->st)})
         if (ptr) (void)hipFree(ptr);
     if (s->host) (void)hipHostFree(s->host);
 }
@@ -308,27 +319,55 @@ tp_status pcg_run(const Plan& plan, const GroupInfo& g, tp_pcg* s, const double*
         if (st != TP_OK) return st;
     }
     hipLaunchKernelGGL((k_pcg_start<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q, x,
-                       s->r, s->z, s->p, G, E, s->part, cnt);
+                       s->xw, s->r, s->z, s->p, G, E, s->part, cnt);
     hipLaunchKernelGGL(k_pcg_reduce_start, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st, rtol, maxit);
     tp_status st = check_launch("PCG start");
     if (st != TP_OK) return st;
+    // one chunk of iterations, captured once per solver and precision: every
+    // argument is solver-owned, so the graph replays for any b, x
+    const int ti = sizeof(TI) == 8 ? 0 : 1;
+    if (!s->exec[ti] || s->exec_chunk[ti] != chunk) {
+        if (s->exec[ti]) (void)hipGraphExecDestroy(s->exec[ti]), s->exec[ti] = nullptr;
+        hipStream_t cs = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_error(e, "PCG capture stream");
+        hipGraph_t gr = nullptr;
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int i = 0; i < chunk; ++i) {
+                hipLaunchKernelGGL((k_pcg_aq<N, LB>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R, F, s->st,
+                                   s->part);
+                hipLaunchKernelGGL(k_pcg_reduce_alpha, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
+                hipLaunchKernelGGL((k_pcg_update<N, TI, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->z, s->p,
+                                   s->q, G, E, s->st, s->part, cnt);
+                hipLaunchKernelGGL(k_pcg_reduce_beta, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
+                hipLaunchKernelGGL(k_pcg_dir, dim3(dgrid), dim3(256), 0, cs, s->z, s->p, s->elems, s->st);
+            }
+            const hipError_t e2 = hipStreamEndCapture(cs, &gr);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&s->exec[ti], gr, nullptr, nullptr, 0);
+        if (gr) (void)hipGraphDestroy(gr);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            s->exec[ti] = nullptr;
+            return hip_error(e, "PCG iteration graph");
+        }
+        s->exec_chunk[ti] = chunk;
+    }
     for (;;) {
         hipError_t e = hipMemcpyAsync(s->host, s->st, sizeof(PcgState), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_error(e, "PCG state read-back");
-        if (s->host->done) return TP_OK;
-        for (int i = 0; i < chunk; ++i) {
-            hipLaunchKernelGGL((k_pcg_aq<N, LB>), dim3(nwg), dim3(64), 0, stream, s->p, s->q, G, R, F, s->st,
-                               s->part);
-            hipLaunchKernelGGL(k_pcg_reduce_alpha, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st);
-            hipLaunchKernelGGL((k_pcg_update<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, x, s->r, s->z, s->p, s->q,
-                               G, E, s->st, s->part, cnt);
-            hipLaunchKernelGGL(k_pcg_reduce_beta, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st);
-            hipLaunchKernelGGL(k_pcg_dir, dim3(dgrid), dim3(256), 0, stream, s->z, s->p, s->elems, s->st);
-        }
-        st = check_launch("PCG iteration");
-        if (st != TP_OK) return st;
+        if (s->host->done) break;
+        e = hipGraphLaunch(s->exec[ti], stream);
+        if (e != hipSuccess) return hip_error(e, "PCG iteration graph launch");
     }
+    hipError_t e = hipMemcpyAsync(x, s->xw, static_cast<size_t>(s->elems) * sizeof(double), hipMemcpyDeviceToDevice,
+                                  stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_error(e, "PCG result copy");
+    return TP_OK;
 }
 
 template <typename TI>
@@ -364,7 +403,7 @@ tp_status tp_pcg_create(tp_plan* plan, tp_pcg** out) {
     s->nwg = std::max<int64_t>((plan->groups[0].nblocks + 63) / 64, 1);
     const size_t vb = static_cast<size_t>(s->elems) * sizeof(double);
     hipError_t e = hipSuccess;
-    for (double** d : {&s->r, &s->z, &s->p, &s->q})
+    for (double** d : {&s->r, &s->z, &s->p, &s->q, &s->xw})
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(d), vb);
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->part), 3 * s->nwg * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->st), sizeof(PcgState));
