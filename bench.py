@@ -114,6 +114,8 @@ def main():
     ap.add_argument("--suite", action="store_true",
                     help="time apply / apply_inverse / solve for every workload and precision "
                          "(one JSON line per case) instead of the headline step")
+    ap.add_argument("--serve", action="store_true",
+                    help="serve Poisson arrival streams of PCG solves at several rates (JSON lines)")
     ap.add_argument("--pcg", action="store_true",
                     help="time preconditioned-CG solves of the SIPG system on the serving mesh sizes (JSON lines)")
     ap.add_argument("--sipg", action="store_true",
@@ -144,6 +146,9 @@ def main():
         return
     if args.pcg:
         run_pcg(args, stream)
+        return
+    if args.serve:
+        run_serve(args)
         return
     if args.sipg:
         if args.counters:
@@ -458,6 +463,37 @@ def run_pcg(args, stream):
         plan.destroy()
         del b, x
         torch.cuda.empty_cache()
+
+
+# Serving: arrival rates (requests/s), each with a bounded number of
+# requests drawn from the mesh mix (unit cubes with m cells per side,
+# degrees 2 and 3; FP64 outer iteration, FP32 preconditioner, rtol 1e-8).
+SERVE_RATES = [50, 200, 500, 2000]
+SERVE_MIX = [(p, m) for p in (2, 3) for m in (8, 16, 24, 32, 48)]
+
+
+def run_serve(args):
+    import torch
+    from paper_2609_04534_amd import serve, tpfdm
+    srv = serve.Server(hbm_budget=24 << 30, inner=tpfdm.F32, rtol=1e-8)
+    # warm start: plans, solver slots and their iteration graphs exist before
+    # the measured runs (one request of every class)
+    warm = [serve.poisson_requests(rate=1e6, count=1, mix=[c], seed=i)[0] for i, c in enumerate(SERVE_MIX)]
+    srv.run(warm)
+    del warm
+    for rate in SERVE_RATES:
+        count = int(min(120, max(20, rate * 1.0)))
+        reqs = serve.poisson_requests(rate=float(rate), count=count, mix=SERVE_MIX, seed=rate)
+        srv.max_concurrent = 0
+        done = srv.run(reqs)
+        st = serve.latency_stats(done)
+        st.update({"workload": "serve_pcg_mix", "rate_per_s": rate, "requests": count,
+                   "max_concurrent": srv.max_concurrent,
+                   "all_converged": all(r.summary.get("converged") for r in done)})
+        print(json.dumps(st), flush=True)
+        del reqs, done
+    srv.close()
+    torch.cuda.empty_cache()
 
 
 def sipg_counters():

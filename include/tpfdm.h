@@ -39,7 +39,8 @@
  *  - Outputs are overwritten, never accumulated.  Input and output buffers
  *    must not alias.
  *  - No call aborts or prints.  On error the call returns a negative status
- *    and tp_last_error() returns a message (thread-local).
+ *    and tp_last_error() returns a message (thread-local); the one positive
+ *    status, TP_PENDING, is not an error.
  *  - A plan may be used from one host thread at a time; distinct plans are
  *    independent.
  */
@@ -63,7 +64,8 @@ typedef enum {
     TP_ERR_NONFINITE = -6,     /* NaN/Inf in an input or a residual                 */
     TP_ERR_HIP = -7,           /* a HIP runtime call failed                         */
     TP_ERR_OOM = -8,           /* device allocation failed                          */
-    TP_ERR_STATE = -9          /* call out of order (e.g. inverse before setup)     */
+    TP_ERR_STATE = -9,         /* call out of order (e.g. inverse before setup)     */
+    TP_PENDING = 1             /* tp_pcg_poll: the solve is still running (no error) */
 } tp_status;
 
 typedef enum { TP_F64 = 0, TP_F32 = 1, TP_F16 = 2, TP_BF16 = 3 } tp_dtype;
@@ -323,6 +325,20 @@ tp_status tp_pcg_create(tp_plan* plan, tp_pcg** out);
 tp_status tp_pcg_solve(tp_pcg* pcg, const double* b, double* x, int32_t x_is_zero, tp_dtype inner, double rtol,
                        int32_t maxit, int32_t check_every, tp_pcg_summary* summary, hipStream_t stream);
 tp_status tp_pcg_destroy(tp_pcg* pcg);
+
+/* The same solve without blocking, for callers that keep several solves in
+ * flight (each solver object on its own stream).  tp_pcg_begin checks the
+ * arguments like tp_pcg_solve, enqueues the start on stream and returns.
+ * Each tp_pcg_poll call returns TP_PENDING while the last enqueued step is
+ * still running or after it has enqueued the next one (a chunk of
+ * check_every iterations, or the copy of the result into x), and, once the
+ * copy has finished, the solve's final status (as tp_pcg_solve's) with
+ * summary filled.  poll never waits.  While a solve is running the solver
+ * accepts no other solve (TP_ERR_STATE), and b and x must stay untouched by
+ * the caller until poll returns its final status. */
+tp_status tp_pcg_begin(tp_pcg* pcg, const double* b, double* x, int32_t x_is_zero, tp_dtype inner, double rtol,
+                       int32_t maxit, int32_t check_every, hipStream_t stream);
+tp_status tp_pcg_poll(tp_pcg* pcg, tp_pcg_summary* summary);
 
 /* Number of blocks in the plan (sum over groups). */
 int64_t tp_plan_nblocks(const tp_plan* plan);

@@ -289,11 +289,18 @@ struct tp_pcg {
     // one captured chunk of iterations per preconditioner precision (F64, F32)
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     int exec_chunk[2] = {0, 0};
+    // non-blocking solves (tp_pcg_begin / tp_pcg_poll)
+    hipEvent_t ev = nullptr;    // recorded after each enqueued step
+    hipStream_t stream = nullptr;
+    double* xout = nullptr;     // the caller's x
+    int ti = 0;                 // precision of the running solve
+    int phase = 0;              // 0 idle, 1 iterating, 2 copying the result out
 };
 
 namespace {
 
 void free_pcg(tp_pcg* s) {
+    if (s->ev) (void)hipEventDestroy(s->ev), s->ev = nullptr;
     for (hipGraphExec_t& ex : s->exec)
         if (ex) (void)hipGraphExecDestroy(ex), ex = nullptr;
     for (void* ptr : {static_cast<void*>(s->r), static_cast<void*>(s->z), static_cast<void*>(s->p),
@@ -303,9 +310,11 @@ void free_pcg(tp_pcg* s) {
     if (s->host) (void)hipHostFree(s->host);
 }
 
+// Enqueues the start of a solve on stream (x = x0 or 0, r, z, p and the
+// first reduction) and makes sure the chunk graph of this precision exists.
 template <int N, typename TI, int LB>
-tp_status pcg_run(const Plan& plan, const GroupInfo& g, tp_pcg* s, const double* b, double* x, bool x_zero,
-                  double rtol, int maxit, int chunk, hipStream_t stream) {
+tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const double* b, const double* x,
+                      bool x_zero, double rtol, int maxit, int chunk, hipStream_t stream) {
     const MeshArgs G = mesh_args(plan, g);
     Pair<N, double> R;
     FaceRef<N, double> F;
@@ -355,35 +364,79 @@ tp_status pcg_run(const Plan& plan, const GroupInfo& g, tp_pcg* s, const double*
         }
         s->exec_chunk[ti] = chunk;
     }
-    for (;;) {
-        hipError_t e = hipMemcpyAsync(s->host, s->st, sizeof(PcgState), hipMemcpyDeviceToHost, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return hip_error(e, "PCG state read-back");
-        if (s->host->done) break;
-        e = hipGraphLaunch(s->exec[ti], stream);
-        if (e != hipSuccess) return hip_error(e, "PCG iteration graph launch");
-    }
-    hipError_t e = hipMemcpyAsync(x, s->xw, static_cast<size_t>(s->elems) * sizeof(double), hipMemcpyDeviceToDevice,
-                                  stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_error(e, "PCG result copy");
+    s->ti = ti;
     return TP_OK;
 }
 
 template <typename TI>
-tp_status pcg_dispatch(const Plan& plan, const GroupInfo& g, tp_pcg* s, const double* b, double* x, bool x_zero,
-                       double rtol, int maxit, int chunk, hipStream_t stream) {
+tp_status pcg_prepare_dispatch(const Plan& plan, const GroupInfo& g, tp_pcg* s, const double* b, const double* x,
+                               bool x_zero, double rtol, int maxit, int chunk, hipStream_t stream) {
     const bool b64 = g.logB == 6;
     switch (g.n) {
-        case 2: return b64 ? pcg_run<2, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
-                           : pcg_run<2, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
-        case 3: return b64 ? pcg_run<3, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
-                           : pcg_run<3, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
-        case 4: return b64 ? pcg_run<4, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
-                           : pcg_run<4, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        case 2: return b64 ? pcg_prepare<2, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
+                           : pcg_prepare<2, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        case 3: return b64 ? pcg_prepare<3, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
+                           : pcg_prepare<3, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        case 4: return b64 ? pcg_prepare<4, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
+                           : pcg_prepare<4, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
         default: break;
     }
     return set_error(TP_ERR_UNSUPPORTED, "the PCG solver supports n <= 4");
+}
+
+// Argument checks shared by the blocking and the non-blocking solve.
+tp_status pcg_validate(const tp_pcg* s, const double* b, const double* x, tp_dtype inner, double rtol, int maxit) {
+    if (!s) return set_error(TP_ERR_ARG, "solver is null");
+    const Plan& plan = *s->plan;
+    if (s->phase != 0) return set_error(TP_ERR_STATE, "a non-blocking solve is still running on this solver");
+    if (plan.vec_elems > 0 && (!b || !x)) return set_error(TP_ERR_ARG, "b and x must be non-null");
+    if (static_cast<const void*>(b) == static_cast<const void*>(x) && b)
+        return set_error(TP_ERR_ARG, "b and x must not alias");
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return set_error(TP_ERR_ARG, "rtol must be finite and > 0");
+    if (maxit < 0) return set_error(TP_ERR_ARG, "maxit must be >= 0");
+    if (inner != TP_F64 && inner != TP_F32)
+        return set_error(TP_ERR_UNSUPPORTED, "the preconditioner runs in TP_F64 or TP_F32");
+    if (plan.inverse_op != TP_OP_CELL || plan.factor_mode != TP_FACTOR_SCALED)
+        return set_error(TP_ERR_STATE, "the PCG solver needs tp_setup_inverse(TP_OP_CELL, TP_FACTOR_SCALED) first");
+    return TP_OK;
+}
+
+tp_status pcg_start(tp_pcg* s, const double* b, double* x, bool x_zero, tp_dtype inner, double rtol, int maxit,
+                    int chunk, hipStream_t stream) {
+    const Plan& plan = *s->plan;
+    const GroupInfo& g = plan.groups[0];
+    return inner == TP_F64 ? pcg_prepare_dispatch<double>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
+                           : pcg_prepare_dispatch<float>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+}
+
+// Summary and status of a finished solve from the host copy of the state.
+tp_status pcg_finish(const tp_pcg* s, tp_pcg_summary* summary) {
+    const PcgState h = *s->host;
+    if (summary) {
+        summary->iterations = h.iter;
+        summary->converged = h.done == 1 ? 1 : 0;
+        summary->relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    }
+    if (h.done == 2) return set_error(TP_ERR_NONFINITE, "PCG breakdown or non-finite value after " +
+                                                            std::to_string(h.iter) + " iterations");
+    if (h.done == 3)
+        return set_error(TP_ERR_NOT_CONVERGED, "PCG reached maxit = " + std::to_string(h.iter) +
+                                                   " with relative residual " +
+                                                   std::to_string(h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0));
+    return TP_OK;
+}
+
+tp_status enqueue_state_copy(tp_pcg* s, hipStream_t stream) {
+    hipError_t e = hipMemcpyAsync(s->host, s->st, sizeof(PcgState), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_error(e, "PCG state read-back");
+    return TP_OK;
+}
+
+tp_status enqueue_result_copy(tp_pcg* s, double* x, hipStream_t stream) {
+    hipError_t e = hipMemcpyAsync(x, s->xw, static_cast<size_t>(s->elems) * sizeof(double), hipMemcpyDeviceToDevice,
+                                  stream);
+    if (e != hipSuccess) return hip_error(e, "PCG result copy");
+    return TP_OK;
 }
 
 }  // namespace
@@ -408,6 +461,7 @@ tp_status tp_pcg_create(tp_plan* plan, tp_pcg** out) {
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->part), 3 * s->nwg * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->st), sizeof(PcgState));
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->host), sizeof(PcgState), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         free_pcg(s);
         delete s;
@@ -420,40 +474,85 @@ tp_status tp_pcg_create(tp_plan* plan, tp_pcg** out) {
 
 tp_status tp_pcg_solve(tp_pcg* s, const double* b, double* x, int32_t x_is_zero, tp_dtype inner, double rtol,
                        int32_t maxit, int32_t check_every, tp_pcg_summary* summary, hipStream_t stream) {
-    if (!s) return set_error(TP_ERR_ARG, "solver is null");
-    const Plan& plan = *s->plan;
-    if (plan.vec_elems > 0 && (!b || !x)) return set_error(TP_ERR_ARG, "b and x must be non-null");
-    if (static_cast<const void*>(b) == static_cast<const void*>(x) && b)
-        return set_error(TP_ERR_ARG, "b and x must not alias");
-    if (!(rtol > 0.0) || !std::isfinite(rtol)) return set_error(TP_ERR_ARG, "rtol must be finite and > 0");
-    if (maxit < 0) return set_error(TP_ERR_ARG, "maxit must be >= 0");
-    if (inner != TP_F64 && inner != TP_F32)
-        return set_error(TP_ERR_UNSUPPORTED, "the preconditioner runs in TP_F64 or TP_F32");
-    if (plan.inverse_op != TP_OP_CELL || plan.factor_mode != TP_FACTOR_SCALED)
-        return set_error(TP_ERR_STATE, "tp_pcg_solve needs tp_setup_inverse(TP_OP_CELL, TP_FACTOR_SCALED) first");
-    const int chunk = check_every > 0 ? check_every : 16;
-    const GroupInfo& g = plan.groups[0];
-    tp_status st = TP_OK;
-    if (g.nblocks == 0) {
+    tp_status st = pcg_validate(s, b, x, inner, rtol, maxit);
+    if (st != TP_OK) return st;
+    if (s->plan->groups[0].nblocks == 0) {
         if (summary) *summary = tp_pcg_summary{0, 1, 0.0};
         return TP_OK;
     }
-    st = inner == TP_F64 ? pcg_dispatch<double>(plan, g, s, b, x, x_is_zero != 0, rtol, maxit, chunk, stream)
-                         : pcg_dispatch<float>(plan, g, s, b, x, x_is_zero != 0, rtol, maxit, chunk, stream);
+    const int chunk = check_every > 0 ? check_every : 16;
+    st = pcg_start(s, b, x, x_is_zero != 0, inner, rtol, maxit, chunk, stream);
     if (st != TP_OK) return st;
-    const PcgState h = *s->host;
-    if (summary) {
-        summary->iterations = h.iter;
-        summary->converged = h.done == 1 ? 1 : 0;
-        summary->relres = h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    for (;;) {
+        st = enqueue_state_copy(s, stream);
+        if (st != TP_OK) return st;
+        const hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_error(e, "PCG state read-back");
+        if (s->host->done) break;
+        const hipError_t e2 = hipGraphLaunch(s->exec[s->ti], stream);
+        if (e2 != hipSuccess) return hip_error(e2, "PCG iteration graph launch");
     }
-    if (h.done == 2) return set_error(TP_ERR_NONFINITE, "PCG breakdown or non-finite value after " +
-                                                            std::to_string(h.iter) + " iterations");
-    if (h.done == 3)
-        return set_error(TP_ERR_NOT_CONVERGED, "PCG reached maxit = " + std::to_string(h.iter) +
-                                                   " with relative residual " +
-                                                   std::to_string(h.bb > 0.0 ? std::sqrt(h.rr / h.bb) : 0.0));
+    st = enqueue_result_copy(s, x, stream);
+    if (st != TP_OK) return st;
+    const hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_error(e, "PCG result copy");
+    return pcg_finish(s, summary);
+}
+
+tp_status tp_pcg_begin(tp_pcg* s, const double* b, double* x, int32_t x_is_zero, tp_dtype inner, double rtol,
+                       int32_t maxit, int32_t check_every, hipStream_t stream) {
+    tp_status st = pcg_validate(s, b, x, inner, rtol, maxit);
+    if (st != TP_OK) return st;
+    s->stream = stream;
+    s->xout = x;
+    if (s->plan->groups[0].nblocks == 0) {
+        *s->host = PcgState{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 1, maxit, 0};
+        s->phase = 2;
+        const hipError_t e = hipEventRecord(s->ev, stream);
+        if (e != hipSuccess) return s->phase = 0, hip_error(e, "PCG event");
+        return TP_OK;
+    }
+    const int chunk = check_every > 0 ? check_every : 16;
+    st = pcg_start(s, b, x, x_is_zero != 0, inner, rtol, maxit, chunk, stream);
+    if (st == TP_OK) st = enqueue_state_copy(s, stream);
+    if (st != TP_OK) return st;
+    const hipError_t e = hipEventRecord(s->ev, stream);
+    if (e != hipSuccess) return hip_error(e, "PCG event");
+    s->phase = 1;
     return TP_OK;
+}
+
+tp_status tp_pcg_poll(tp_pcg* s, tp_pcg_summary* summary) {
+    if (!s) return set_error(TP_ERR_ARG, "solver is null");
+    if (s->phase == 0) return set_error(TP_ERR_STATE, "no non-blocking solve is running on this solver");
+    const hipError_t q = hipEventQuery(s->ev);
+    if (q == hipErrorNotReady) {
+        (void)hipGetLastError();   // not an error: keep it out of later launch checks
+        return TP_PENDING;
+    }
+    if (q != hipSuccess) {
+        s->phase = 0;
+        return hip_error(q, "PCG event query");
+    }
+    if (s->phase == 2) {
+        s->phase = 0;
+        return pcg_finish(s, summary);
+    }
+    // phase 1: the state copy of the last step has landed
+    tp_status st = TP_OK;
+    if (s->host->done) {
+        st = enqueue_result_copy(s, s->xout, s->stream);
+        if (st == TP_OK) s->phase = 2;
+    } else {
+        const hipError_t e = hipGraphLaunch(s->exec[s->ti], s->stream);
+        st = e == hipSuccess ? enqueue_state_copy(s, s->stream) : hip_error(e, "PCG iteration graph launch");
+    }
+    if (st == TP_OK) {
+        const hipError_t e = hipEventRecord(s->ev, s->stream);
+        if (e != hipSuccess) st = hip_error(e, "PCG event");
+    }
+    if (st != TP_OK) s->phase = 0;
+    return st == TP_OK ? TP_PENDING : st;
 }
 
 tp_status tp_pcg_destroy(tp_pcg* s) {

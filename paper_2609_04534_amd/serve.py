@@ -1,0 +1,189 @@
+"""Continuous-batching server for preconditioned-CG Poisson solves on box
+meshes (the coupled SIPG system of mesh plans, solved by tp_pcg_*).
+
+Requests arrive over time, each a mesh (degree p, m^3 unit-cube cells) and a
+right-hand side already resident in device memory.  The server keeps every
+admitted solve in flight on its own HIP stream and drives all of them from
+one host loop with the non-blocking tp_pcg_begin / tp_pcg_poll calls, so the
+kernels of different solves overlap on the GPU.  A request is admitted (in
+arrival order) as soon as a solver slot for its mesh class is free or the
+device-memory budget has room for a new one; finished solves return their
+slot to a per-class free pool, and idle slots of other classes are released
+when a new class needs the memory.  Marshalling and scheduling only: every
+step of a solve runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import tpfdm
+
+
+@dataclass
+class Request:
+    rid: int
+    p: int
+    m: int
+    arrival: float              # seconds from the start of the run
+    b: object                   # device tensor, canonical order (ncells * n^3 FP64 values)
+    x: object = None            # device tensor of the result (canonical), filled on completion
+    start: float = -1.0         # admission time
+    done: float = -1.0          # completion time
+    summary: dict = field(default_factory=dict)
+
+
+class _Slot:
+    """A solver and its blocked b, x buffers for one mesh class, on its own stream."""
+
+    def __init__(self, plan, p, m):
+        import torch
+        self.plan = plan
+        self.cls = (p, m)
+        self.stream = torch.cuda.Stream()
+        self.solver = tpfdm.PCG(plan)
+        E = plan.vector_elems
+        self.b = torch.empty(E, dtype=torch.float64, device="cuda")
+        self.x = torch.empty(E, dtype=torch.float64, device="cuda")
+        self.req = None
+
+    def destroy(self):
+        self.solver.destroy()
+        self.b = self.x = None
+
+
+def slot_bytes(plan) -> int:
+    """Device memory of one slot: the solver's five vectors and partials plus b and x."""
+    E = plan.vector_elems
+    nwg = (plan.nblocks + 63) // 64
+    return 7 * E * 8 + 3 * nwg * 8 + 256
+
+
+class Server:
+    def __init__(self, hbm_budget: int, inner: int = tpfdm.F32, rtol: float = 1e-8, maxit: int = 20000,
+                 check_every: int = 8, max_inflight: int = 32):
+        self.budget = int(hbm_budget)
+        self.max_inflight = max_inflight
+        self.inner = inner
+        self.rtol = rtol
+        self.maxit = maxit
+        self.check_every = check_every
+        self.plans = {}         # (p, m) -> plan with the cell-block inverse set up
+        self.free = {}          # (p, m) -> [idle slots]
+        self.used = 0           # bytes of live slots (busy and idle)
+        self.busy = []
+        self.max_concurrent = 0
+
+    def _plan(self, p, m):
+        key = (p, m)
+        if key not in self.plans:
+            plan = tpfdm.Plan.mesh(p + 1, (m, m, m), (1.0 / m,) * 3)
+            plan.setup_inverse(tpfdm.OP_CELL)
+            self.plans[key] = plan
+        return self.plans[key]
+
+    def _slot_for(self, p, m):
+        """An idle slot of the class, or a new one when the budget allows
+        (releasing idle slots of other classes first); None when full."""
+        key = (p, m)
+        if self.free.get(key):
+            return self.free[key].pop()
+        need = slot_bytes(self._plan(p, m))
+        for k in list(self.free):
+            while self.used + need > self.budget and self.free[k]:
+                s = self.free[k].pop()
+                self.used -= slot_bytes(s.plan)
+                s.destroy()
+        if self.used + need > self.budget:
+            return None
+        self.used += need
+        return _Slot(self._plan(p, m), p, m)
+
+    def _admit(self, req, now):
+        if len(self.busy) >= self.max_inflight:
+            return False
+        s = self._slot_for(req.p, req.m)
+        if s is None:
+            return False
+        import torch
+        with torch.cuda.stream(s.stream):
+            s.plan.pack(req.b, s.b, stream=s.stream)
+        s.solver.begin(s.b, s.x, x_is_zero=True, inner=self.inner, rtol=self.rtol, maxit=self.maxit,
+                       check_every=self.check_every, stream=s.stream)
+        s.req = req
+        req.start = now
+        self.busy.append(s)
+        self.max_concurrent = max(self.max_concurrent, len(self.busy))
+        return True
+
+    def _complete(self, s, summ):
+        import torch
+        req = s.req
+        out = torch.empty(s.plan.ndof, dtype=torch.float64, device="cuda")
+        s.plan.unpack(s.x, out, stream=s.stream)
+        s.stream.synchronize()
+        req.x = out
+        req.done = time.perf_counter() - self.t0
+        req.summary = summ
+        s.req = None
+        self.free.setdefault(s.cls, []).append(s)
+
+    def run(self, requests):
+        """Serve the requests (sorted by arrival) in real time; returns them
+        with admission and completion times filled."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        self.t0 = time.perf_counter()
+        i = 0
+        waiting = []
+        while i < len(reqs) or waiting or self.busy:
+            now = time.perf_counter() - self.t0
+            while i < len(reqs) and reqs[i].arrival <= now:
+                waiting.append(reqs[i])
+                i += 1
+            while waiting and self._admit(waiting[0], now):
+                waiting.pop(0)
+            progressed = False
+            for s in list(self.busy):
+                summ = s.solver.poll(raise_on_failure=False)
+                if summ is not None:
+                    self.busy.remove(s)
+                    self._complete(s, summ)
+                    progressed = True
+            if not progressed and not waiting and i < len(reqs) and not self.busy:
+                time.sleep(max(0.0, min(1e-3, reqs[i].arrival - now)))
+        return reqs
+
+    def close(self):
+        for lst in self.free.values():
+            for s in lst:
+                s.destroy()
+        self.free = {}
+        for plan in self.plans.values():
+            plan.destroy()
+        self.plans = {}
+
+
+def poisson_requests(rate: float, count: int, mix, seed: int):
+    """count requests with exponential inter-arrival times of mean 1/rate and
+    (p, m) drawn uniformly from mix; right-hand sides ~ U[-1, 1] (seeded),
+    placed in device memory before the run."""
+    import torch
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    out = []
+    for k in range(count):
+        p, m = mix[int(rng.integers(len(mix)))]
+        nd = m ** 3 * (p + 1) ** 3
+        b = torch.from_numpy(rng.uniform(-1.0, 1.0, nd)).cuda()
+        out.append(Request(k, p, m, float(t[k]), b))
+    return out
+
+
+def latency_stats(reqs):
+    lat = np.array([r.done - r.arrival for r in reqs]) * 1e3
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "solves_per_s": len(reqs) / span,
+            "queue_p50_ms": float(np.percentile([(r.start - r.arrival) * 1e3 for r in reqs], 50))}

@@ -20,8 +20,9 @@ TP_OK = 0
 STATUS = {
     0: "TP_OK", -1: "TP_ERR_ARG", -2: "TP_ERR_UNSUPPORTED", -3: "TP_ERR_NOT_SPD",
     -4: "TP_ERR_SINGULAR", -5: "TP_ERR_NOT_CONVERGED", -6: "TP_ERR_NONFINITE",
-    -7: "TP_ERR_HIP", -8: "TP_ERR_OOM", -9: "TP_ERR_STATE",
+    -7: "TP_ERR_HIP", -8: "TP_ERR_OOM", -9: "TP_ERR_STATE", 1: "TP_PENDING",
 }
+TP_PENDING = 1
 F64, F32, F16, BF16 = 0, 1, 2, 3
 DTYPE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 OP_NEUMANN, OP_CELL, OP_SIPG, OP_SIPG_FACE = 0, 1, 2, 3
@@ -35,7 +36,7 @@ EXPORTS = (
     "tp_solve", "tp_pack", "tp_unpack", "tp_reference_matrices", "tp_reference_eigen",
     "tp_last_error", "tp_version", "tp_solve_summary_fetch", "tp_graph_create", "tp_graph_launch",
     "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel", "tp_plan_create_mesh",
-    "tp_pcg_create", "tp_pcg_solve", "tp_pcg_destroy",
+    "tp_pcg_create", "tp_pcg_solve", "tp_pcg_destroy", "tp_pcg_begin", "tp_pcg_poll",
 )
 KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
@@ -112,6 +113,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_pcg_create": (i32, [vp, ctypes.POINTER(vp)]),
         "tp_pcg_solve": (i32, [vp, vp, vp, i32, i32, dbl, i32, i32, ctypes.POINTER(_PcgSummary), vp]),
         "tp_pcg_destroy": (i32, [vp]),
+        "tp_pcg_begin": (i32, [vp, vp, vp, i32, i32, dbl, i32, i32, vp]),
+        "tp_pcg_poll": (i32, [vp, ctypes.POINTER(_PcgSummary)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -386,6 +389,24 @@ class PCG:
         summ = _PcgSummary()
         st = load().tp_pcg_solve(self._h, _ptr(b), _ptr(x), 1 if x_is_zero else 0, inner, rtol, maxit,
                                  check_every, ctypes.byref(summ), _stream(stream))
+        out = {"iterations": summ.iterations, "converged": bool(summ.converged), "relres": summ.relres,
+               "status": st}
+        if st != TP_OK and raise_on_failure:
+            _check(st)
+        return out
+
+    def begin(self, b, x, x_is_zero: bool = True, inner: int = F64, rtol: float = 1e-8, maxit: int = 1000,
+              check_every: int = 16, stream=None):
+        """Enqueue a solve without waiting (tp_pcg_begin); drive it with poll()."""
+        _check(load().tp_pcg_begin(self._h, _ptr(b), _ptr(x), 1 if x_is_zero else 0, inner, rtol, maxit,
+                                   check_every, _stream(stream)))
+
+    def poll(self, raise_on_failure: bool = True):
+        """None while the solve runs (tp_pcg_poll), else the summary dict."""
+        summ = _PcgSummary()
+        st = load().tp_pcg_poll(self._h, ctypes.byref(summ))
+        if st == TP_PENDING:
+            return None
         out = {"iterations": summ.iterations, "converged": bool(summ.converged), "relres": summ.relres,
                "status": st}
         if st != TP_OK and raise_on_failure:
