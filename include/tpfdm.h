@@ -186,8 +186,8 @@ int64_t tp_plan_ndof(const tp_plan* plan);
  * buffers of tp_plan_vector_elems() elements of dtype.  Sec. 3.1,
  * eq. (eval_pipeline) with P_hat chosen by op (length groups); factor groups
  * use their own P and ignore op.
- * TP_OP_SIPG / TP_OP_SIPG_FACE (mesh plans, TP_F64 and TP_F32, n <= 4 and
- * n = 8; TP_ERR_UNSUPPORTED otherwise): v <- A u with the coupled operator,
+ * TP_OP_SIPG / TP_OP_SIPG_FACE (mesh plans, TP_F64 and TP_F32, every n;
+ * TP_ERR_UNSUPPORTED for FP16/BF16): v <- A u with the coupled operator,
  * every cell's row reading its face neighbours' blocks of u. */
 tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v,
                    tp_dtype dtype, hipStream_t stream);

@@ -463,6 +463,14 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
             break;
         }
         st = upload_eo(*p, g.n, EO_APPLY_A, tab, cnt);
+        if (st != TP_OK) break;
+        double F[kMaxN * kMaxN];
+        for (int i = 0; i < g.n * g.n; ++i) F[i] = r.A[i] - r.K[i];
+        if (!build_eo_apply(g.n, r.M, F, tab)) {
+            st = set_error(TP_ERR_UNSUPPORTED, "reference matrices are not centrosymmetric");
+            break;
+        }
+        st = upload_eo(*p, g.n, EO_APPLY_F, tab, cnt);
         if (st != TP_OK || g.n > kLaneMaxN) continue;
         // plain factors for the lane-per-block kernels (2 n^2 <= kEOSlot for n <= 4)
         const int n2 = g.n * g.n;

@@ -29,7 +29,12 @@ void endpoint_derivatives(int n, double* g0, double* g1);
 // with h = n/2, hc = (n+1)/2.  Element type 0 = double, 1 = float.
 //   EO_PLAIN_K / EO_PLAIN_A:  M[n][n] | P[n][n]   (plain, for the lane kernels)
 //   EO_PLAIN_S:               S[n][n] | lam[n]
-enum { EO_APPLY_K = 0, EO_APPLY_A = 1, EO_INV = 2, EO_PLAIN_K = 3, EO_PLAIN_A = 4, EO_PLAIN_S = 5, EO_NTAB = 6 };
+//   EO_APPLY_F:               ME | MO | FE | FO with F = A_hat - K_hat (the
+//                             face part of a mesh cell's diagonal block)
+enum {
+    EO_APPLY_K = 0, EO_APPLY_A = 1, EO_INV = 2, EO_PLAIN_K = 3, EO_PLAIN_A = 4, EO_PLAIN_S = 5, EO_APPLY_F = 6,
+    EO_NTAB = 7
+};
 constexpr int kEOSlot = 64;
 // Builds ME|MO|PE|PO from centrosymmetric M and P; false when either is not.
 bool build_eo_apply(int n, const double* M, const double* P, double* out);

@@ -38,6 +38,7 @@
 // blocked layout, so the B cells of a tile are consecutive along z.
 #pragma once
 
+#include "eo.h"
 #include "lane.h"
 
 namespace tpfdm {
@@ -233,6 +234,157 @@ __device__ __forceinline__ void sipg_cell(const TS* __restrict__ u, const MeshAr
     __builtin_amdgcn_sched_barrier(0);
     lane_apply<N, TC, false, true>([&](int q) { return ldc<TC>(own + (static_cast<int64_t>(q) << lb)); }, R, sx, sy,
                                    sz, acc);
+}
+
+// ============================================================ one cell per wave (n >= 5)
+// The cell's block lives in an LDS slab (Slab<N> layout, one pencil per lane
+// and phase, as in the even-odd wave kernels); the volume product is the
+// even-odd LDS apply with the cell-diagonal P_hat.  The six face terms are
+// slabs over the two tangential indices: lane (a, b) accumulates alpha and
+// beta of every face from the source block's n values along the normal at
+// (a, b); the tangential mass M (.) M of all twelve slabs runs as two LDS
+// passes of one n-pencil per task (12 n tasks per pass spread over the
+// wave); finally lane (j, k) adds the face terms to its x-pencil of the
+// volume product.
+template <int N, typename T>
+struct WaveLds {
+    T s[Slab<N>::size], t1[Slab<N>::size], t2[Slab<N>::size];
+    T fs[2][12][N * N];                                    // face slabs, two pass buffers
+    T tab[2 * (EOShape<N>::SE + EOShape<N>::SO)];          // table staging
+};
+
+// The lane's x-pencil y[i] = (A u)_c at (i, j, k) with (j, k) = (pc.pa,
+// pc.pb), for the active lanes; every lane of the wave must call it.
+// TB: ME | MO | PE | PO (even-odd halves of M_hat and of the cell-diagonal
+// P_hat); F: endpoint derivatives and the reference penalty.
+template <int N, typename T, bool VP>
+__device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const MeshArgs& G, const T* TB,
+                                               const FaceRef<N, T>& F, int64_t c, WaveLds<N, T>& L,
+                                               T (&y)[N]) {
+    using SL = Slab<N>;
+    using S = EOShape<N>;
+    constexpr int N3 = N * N * N;
+    const T* ME = TB;
+    const T* MO = TB + S::SE;
+    const T* PE = TB + S::SE + S::SO;
+    const T* PO = TB + 2 * S::SE + S::SO;
+    const Pencil<N> pc(1);
+    const int pa = pc.pa, pb = pc.pb;
+    const T* ub = u + G.offset;
+    const int lb = G.logB;
+    const uint32_t cu = static_cast<uint32_t>(c);
+    const uint32_t cz = cu % static_cast<uint32_t>(G.mz);
+    const uint32_t rr = cu / static_cast<uint32_t>(G.mz);
+    const uint32_t cy = rr % static_cast<uint32_t>(G.my);
+    const uint32_t cx = rr / static_cast<uint32_t>(G.my);
+    const T sx = static_cast<T>(G.sx), sy = static_cast<T>(G.sy), sz = static_cast<T>(G.sz);
+    // --- face slabs: alpha (2 f) and beta (2 f + 1) of face f = 2 axis + upper
+    const int64_t syz = static_cast<int64_t>(G.my) * G.mz;
+    auto face = [&](auto Dc, auto UPc, bool interior, int64_t d, T s) {
+        constexpr int D = decltype(Dc)::value;
+        constexpr bool UP = decltype(UPc)::value;
+        constexpr int f = 2 * D + (UP ? 1 : 0);
+        const T* w = ub + block_base(interior ? c + d : c, lb, N3);
+        const bool first = (UP == interior);
+        const T cb0 = first ? T(0.5) * s : T(0);
+        const T cbn = first ? T(0) : T(-0.5) * s;
+        if (pc.act) {
+            T al = T(0), be = T(0);
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const T in = UP ? fma(T(-0.5), F.g0[k], k == 0 ? -F.sigma : T(0))
+                                : fma(T(0.5), F.g1[k], k == N - 1 ? -F.sigma : T(0));
+                const T bd = UP ? T(-0.5) * F.g1[k] : T(0.5) * F.g0[k];
+                const T wk = ldc<T>(w + (static_cast<int64_t>(fq<N, D>(k, pa, pb)) << lb));
+                al = fma(s * (interior ? in : bd), wk, al);
+                if (k == 0) be = cb0 * wk;
+                if (k == N - 1) be = fma(cbn, wk, be);
+            }
+            L.fs[0][2 * f][pa * N + pb] = al;
+            L.fs[0][2 * f + 1][pa * N + pb] = be;
+        }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using BF = std::integral_constant<bool, false>;
+    using BT = std::integral_constant<bool, true>;
+    face(I0{}, BF{}, cx > 0, -syz, sx);
+    face(I0{}, BT{}, cx + 1 < static_cast<uint32_t>(G.mx), syz, sx);
+    face(I1{}, BF{}, cy > 0, -static_cast<int64_t>(G.mz), sy);
+    face(I1{}, BT{}, cy + 1 < static_cast<uint32_t>(G.my), G.mz, sy);
+    face(I2{}, BF{}, cz > 0, -1, sz);
+    face(I2{}, BT{}, cz + 1 < static_cast<uint32_t>(G.mz), 1, sz);
+    // --- the cell's own block into the slab, volume product in place
+    if (pc.act) {
+        T x[N];
+        pencil_load<N, VP>(x, ub + block_base(c, lb, N3) + (static_cast<int64_t>((pa * N + pb) * N) << lb), lb);
+#pragma unroll
+        for (int k = 0; k < N; ++k) L.s[SL::at(pa, pb, k)] = x[k];
+    }
+    wave_sync();
+    eo_apply_lds<N, T>(pc, L.s, L.s, L.t1, L.t2, ME, MO, PE, PO, sx, sy, sz);
+    // --- tangential mass of the twelve slabs: rows (second index), then columns
+    constexpr int HC = S::HC, H = S::H;
+    auto mass_pencil = [&](const T (&xin)[N], T (&out)[N]) {
+        T e[HC], o[H], E[HC], O[H];
+        eo_split<N>(xin, e, o);
+        eo_mul<N>(ME, MO, e, o, E, O);
+        eo_join<N>(E, O, out);
+    };
+    for (int task = threadIdx.x; task < 12 * N; task += 64) {
+        const int sl = task / N, a = task - (task / N) * N;
+        T xin[N], out[N];
+#pragma unroll
+        for (int b = 0; b < N; ++b) xin[b] = L.fs[0][sl][a * N + b];
+        mass_pencil(xin, out);
+#pragma unroll
+        for (int b = 0; b < N; ++b) L.fs[1][sl][a * N + b] = out[b];
+    }
+    wave_sync();
+    for (int task = threadIdx.x; task < 12 * N; task += 64) {
+        const int sl = task / N, b = task - (task / N) * N;
+        T xin[N], out[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) xin[a] = L.fs[1][sl][a * N + b];
+        mass_pencil(xin, out);
+#pragma unroll
+        for (int a = 0; a < N; ++a) L.fs[0][sl][a * N + b] = out[a];
+    }
+    wave_sync();
+    // --- the lane's x-pencil of the volume product plus the face terms
+    if (pc.act) {
+        const int j = pa, k = pb;
+        T g0j = T(0), g1j = T(0), g0k = T(0), g1k = T(0);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            g0j = j == i ? F.g0[i] : g0j;
+            g1j = j == i ? F.g1[i] : g1j;
+            g0k = k == i ? F.g0[i] : g0k;
+            g1k = k == i ? F.g1[i] : g1k;
+        }
+        const T ej0 = j == 0 ? T(1) : T(0), ejn = j == N - 1 ? T(1) : T(0);
+        const T ek0 = k == 0 ? T(1) : T(0), ekn = k == N - 1 ? T(1) : T(0);
+        const T ax0 = L.fs[0][0][j * N + k], bx0 = L.fs[0][1][j * N + k];
+        const T ax1 = L.fs[0][2][j * N + k], bx1 = L.fs[0][3][j * N + k];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T v = L.s[SL::at(i, j, k)];
+            v = fma(F.g0[i], bx0, fma(F.g1[i], bx1, v));                       // x faces, beta
+            if (i == 0) v += ax0;                                               // x faces, alpha
+            if (i == N - 1) v += ax1;
+            v = fma(ej0, L.fs[0][4][i * N + k], v);                             // y faces
+            v = fma(g0j, L.fs[0][5][i * N + k], v);
+            v = fma(ejn, L.fs[0][6][i * N + k], v);
+            v = fma(g1j, L.fs[0][7][i * N + k], v);
+            v = fma(ek0, L.fs[0][8][i * N + j], v);                             // z faces
+            v = fma(g0k, L.fs[0][9][i * N + j], v);
+            v = fma(ekn, L.fs[0][10][i * N + j], v);
+            v = fma(g1k, L.fs[0][11][i * N + j], v);
+            y[i] = v;
+        }
+    }
+    wave_sync();
 }
 
 // Tile of workgroup b in an XCD-contiguous order: workgroup b runs on XCD

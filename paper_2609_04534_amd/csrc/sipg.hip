@@ -22,6 +22,30 @@ __global__ __launch_bounds__(64, 2) void k_sipg_lane(const TS* __restrict__ u, T
     for (int q = 0; q < N3; ++q) stv<NT>(vb + (static_cast<int64_t>(q) << lb), acc[q]);
 }
 
+// One cell per wave (n >= 5).
+template <int N, typename T, bool VP>
+__global__ __launch_bounds__(64, 2) void k_sipg_wave(const T* __restrict__ u, T* __restrict__ v, MeshArgs G,
+                                                  const T* __restrict__ tab, FaceRef<N, T> F) {
+    constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
+    __shared__ WaveLds<N, T> L;
+    T TB[TAB];
+    load_table<T, TAB>(TB, tab, L.tab);
+    const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
+    T y[N];
+    wave_sipg_cell<N, T, VP>(u, G, TB, F, c, L, y);
+    const Pencil<N> pc(1);
+    if (pc.act) {
+        T* vb = v + G.offset + block_base(c, G.logB, N * N * N);
+        constexpr bool kWholeLines = (N * N * sizeof(T)) % 128 == 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T* o = vb + (static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << G.logB);
+            if constexpr (kWholeLines) stg(o, y[i]);
+            else stc(o, y[i]);
+        }
+    }
+}
+
 tp_status check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, what);
@@ -44,6 +68,26 @@ tp_status sipg_lane_n(const Plan& plan, const MeshArgs& G, bool face_only, const
     return check_launch("SIPG apply launch");
 }
 
+template <int N, typename T>
+tp_status sipg_wave_n(const Plan& plan, const MeshArgs& G, bool face_only, const void* u, void* v, hipStream_t s) {
+    Pair<N, T> R;
+    FaceRef<N, T> F;
+    sipg_tables<N, T>(plan, face_only, R, F);
+    const T* tab = reinterpret_cast<const T*>(eo_table(plan, N, face_only ? EO_APPLY_F : EO_APPLY_A,
+                                                       sizeof(T) == 8 ? 0 : 1));
+    const unsigned grid = static_cast<unsigned>(G.ncells);
+    const T* ui = static_cast<const T*>(u);
+    T* vo = static_cast<T*>(v);
+    // 16-byte pencils: block-contiguous layout and an aligned vector
+    const bool vp = G.logB == 0 && (reinterpret_cast<uintptr_t>(ui + G.offset) % 16 == 0) &&
+                    (N * sizeof(T)) % 16 == 0;
+    if (vp)
+        hipLaunchKernelGGL((k_sipg_wave<N, T, true>), dim3(grid), dim3(64), 0, s, ui, vo, G, tab, F);
+    else
+        hipLaunchKernelGGL((k_sipg_wave<N, T, false>), dim3(grid), dim3(64), 0, s, ui, vo, G, tab, F);
+    return check_launch("SIPG apply launch");
+}
+
 template <typename TS, typename TC>
 tp_status sipg_dispatch(const Plan& plan, const MeshArgs& G, int n, bool face_only, const void* u, void* v,
                         hipStream_t s) {
@@ -51,9 +95,13 @@ tp_status sipg_dispatch(const Plan& plan, const MeshArgs& G, int n, bool face_on
         case 2: return sipg_lane_n<2, TS, TC>(plan, G, face_only, u, v, s);
         case 3: return sipg_lane_n<3, TS, TC>(plan, G, face_only, u, v, s);
         case 4: return sipg_lane_n<4, TS, TC>(plan, G, face_only, u, v, s);
+        case 5: return sipg_wave_n<5, TC>(plan, G, face_only, u, v, s);
+        case 6: return sipg_wave_n<6, TC>(plan, G, face_only, u, v, s);
+        case 7: return sipg_wave_n<7, TC>(plan, G, face_only, u, v, s);
+        case 8: return sipg_wave_n<8, TC>(plan, G, face_only, u, v, s);
         default: break;
     }
-    return set_error(TP_ERR_UNSUPPORTED, "the SIPG operator supports n <= 4");
+    return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
 }
 
 }  // namespace

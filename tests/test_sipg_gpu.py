@@ -47,6 +47,56 @@ CASES = [
 ]
 
 
+# one cell per wave (n >= 5): block-contiguous layout by default, and B = 4
+WAVE_CASES = [
+    (8, (2, 3, 2), (0.7, 1.3, 0.45), None),
+    (8, (1, 1, 5), (0.5, 0.5, 0.5), None),
+    (8, (2, 2, 2), (0.3, 0.6, 0.9), 4),
+    (5, (3, 2, 4), (0.25, 0.5, 1.0), None),
+    (6, (2, 3, 3), (1.0, 0.5, 0.7), None),
+    (7, (3, 1, 2), (0.4, 0.4, 0.9), None),
+]
+
+
+def _rows_abs(p, cells, h, u):
+    """Oracle rows of all cells from their dense blocks: (A u, |A| |u|)."""
+    ncell = cells[0] * cells[1] * cells[2]
+    n3 = (p + 1) ** 3
+    ub = u.reshape(ncell, n3)
+    out = np.zeros((ncell, n3))
+    sc = np.zeros((ncell, n3))
+    outf = np.zeros((ncell, n3))
+    for c in range(ncell):
+        for nb, blk in sipg.cell_row_blocks(p, cells, h, c):
+            out[c] += blk @ ub[nb]
+            sc[c] += np.abs(blk) @ np.abs(ub[nb])
+        for nb, blk in sipg.cell_row_blocks(p, cells, h, c, sipg.FACE):
+            outf[c] += blk @ ub[nb]
+    return out.reshape(-1), outf.reshape(-1), float(sc.max())
+
+
+@pytest.mark.parametrize("n,cells,h,B", WAVE_CASES)
+@pytest.mark.parametrize("dt", [tpfdm.F64, tpfdm.F32])
+def test_sipg_wave_apply_matches_oracle(n, cells, h, B, dt):
+    p = n - 1
+    ncell = cells[0] * cells[1] * cells[2]
+    u = _u(ncell, n, seed=n * 100 + ncell)
+    print(f"n={n} cells={cells} B={B} dtype={tpfdm.DTYPE_NAMES[dt]}", flush=True)
+    with tpfdm.Plan.mesh(n, cells, h, layout_B=B) as plan:
+        bu = to_blocked(plan, u, dt)
+        bv = _torch().full_like(bu, float("nan"))
+        plan.apply(bu, bv, tpfdm.OP_SIPG)
+        v = from_blocked(plan, bv, dt)
+        plan.apply(bu, bv, tpfdm.OP_SIPG_FACE)
+        vf = from_blocked(plan, bv, dt)
+    uq = from_blocked_input(u, dt)
+    ref, reff, scale = _rows_abs(p, cells, h, uq)
+    e = float(np.max(np.abs(v - ref)) / scale)
+    ef = float(np.max(np.abs(vf - reff)) / scale)
+    print(f"  full err={e:.2e} face err={ef:.2e}")
+    assert e < TOL[dt] and ef < TOL[dt]
+
+
 @pytest.mark.parametrize("n,cells,h,B", CASES)
 @pytest.mark.parametrize("dt", [tpfdm.F64, tpfdm.F32])
 def test_sipg_apply_matches_oracle(n, cells, h, B, dt):
