@@ -427,7 +427,7 @@ def run_sipg(args, stream):
 
 # Serving meshes: unit cubes with m cells per side (the request mix of the
 # serving configuration), rtol 1e-8, FP64 outer iteration.
-PCG_SUITE = [(p, m) for p in (2, 3) for m in (8, 16, 24, 32, 48)]
+PCG_SUITE = [(p, m) for p in (2, 3) for m in (8, 16, 24, 32, 48)] + [(7, m) for m in (8, 16, 24)]
 
 
 def run_pcg(args, stream):

@@ -254,6 +254,172 @@ __global__ __launch_bounds__(256) void k_pcg_dir(const double* __restrict__ z, d
         p[i] = fma(beta, p[i], z[i]);
 }
 
+// ---------------------------------------------------------------- n >= 5
+// One cell per wave: lane (a, b) owns the z-pencil (a, b, 0..n-1) for the
+// vector updates; the preconditioner runs the even-odd FDM inverse of the
+// cell in an LDS slab; q = A p is the wave body of the coupled operator.
+
+// 1.  q = A p, partial (p, q) per workgroup (one cell).
+template <int N, bool VP>
+__global__ __launch_bounds__(64, 2) void k_pcg_aq_wave(const double* __restrict__ p, double* __restrict__ q,
+                                                     MeshArgs G, const double* __restrict__ tab,
+                                                     FaceRef<N, double> F, const PcgState* __restrict__ st,
+                                                     double* __restrict__ part) {
+    if (st->done) return;
+    constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
+    __shared__ WaveLds<N, double> L;
+    double TB[TAB];
+    load_table<double, TAB>(TB, tab, L.tab);
+    const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
+    double y[N];
+    wave_sipg_cell<N, double, VP>(p, G, TB, F, c, L, y);
+    const Pencil<N> pc(1);
+    double dot = 0.0;
+    if (pc.act) {
+        const int64_t base = G.offset + block_base(c, G.logB, N * N * N);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int64_t o = base + (static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << G.logB);
+            q[o] = y[i];
+            dot = fma(y[i], p[o], dot);
+        }
+    }
+    dot = wave_sum(dot);
+    if (threadIdx.x == 0) part[blockIdx.x] = dot;
+}
+
+// Inverse tables of the wave kernels: SE | SO in registers, lam in LDS.
+template <int N, typename TI>
+__device__ __forceinline__ void load_inverse_tables(const TI* __restrict__ tab, TI* stab,
+                                                    TI (&T)[EOShape<N>::SE + EOShape<N>::SO]) {
+    constexpr int TABM = EOShape<N>::SE + EOShape<N>::SO;
+    for (int e = threadIdx.x; e < TABM + N; e += 64) stab[e] = tab[e];
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < TABM; ++i) T[i] = stab[i];
+}
+
+// z = D^{-1} r of the wave's cell in precision TI (rv: the lane's z-pencil of
+// r in FP64), written in FP64 at zp; returns the lane's partial (r, z).
+template <int N, typename TI>
+__device__ __forceinline__ double wave_precondition(const double (&rv)[N], double* __restrict__ zp, int lb,
+                                                    const Pencil<N>& pc, TI* slab, const TI* T, const TI* lam,
+                                                    TI sx, TI sy, TI sz) {
+    using SL = Slab<N>;
+    if (pc.act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) slab[SL::at(pc.pa, pc.pb, k)] = static_cast<TI>(rv[k]);
+    }
+    wave_sync();
+    eo_inverse_lds<N, TI>(pc, slab, T, T + EOShape<N>::SE, lam, sx, sy, sz);
+    double rz = 0.0;
+    if (pc.act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double zv = static_cast<double>(slab[SL::at(pc.pa, pc.pb, k)]);
+            zp[static_cast<int64_t>(k) << lb] = zv;
+            rz = fma(rv[k], zv, rz);
+        }
+    }
+    return rz;
+}
+
+// Start (see k_pcg_start), one cell per workgroup.
+template <int N, typename TI>
+__global__ __launch_bounds__(64, 2) void k_pcg_start_wave(const double* __restrict__ b, const double* __restrict__ q,
+                                                        const double* __restrict__ x0, double* __restrict__ x,
+                                                        double* __restrict__ r, double* __restrict__ z,
+                                                        double* __restrict__ p, MeshArgs G,
+                                                        const TI* __restrict__ tab, double* __restrict__ part,
+                                                        int64_t count) {
+    constexpr int TABM = EOShape<N>::SE + EOShape<N>::SO;
+    __shared__ TI slab[Slab<N>::size];
+    __shared__ TI stab[TABM + N];
+    TI T[TABM];
+    load_inverse_tables<N, TI>(tab, stab, T);
+    const int64_t c = blockIdx.x;
+    const Pencil<N> pc(1);
+    const int lb = G.logB;
+    const int64_t pb = G.offset + block_base(c, lb, N * N * N) +
+                       (static_cast<int64_t>((pc.pa * N + pc.pb) * N) << lb);
+    double rv[N], rr = 0.0, bb = 0.0;
+    if (pc.act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const int64_t o = pb + (static_cast<int64_t>(k) << lb);
+            const double bv = b[o];
+            rv[k] = q ? bv - q[o] : bv;
+            x[o] = q ? x0[o] : 0.0;
+            r[o] = rv[k];
+            rr = fma(rv[k], rv[k], rr);
+            bb = fma(bv, bv, bb);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) rv[k] = 0.0;
+    }
+    double rz = wave_precondition<N, TI>(rv, z + pb, lb, pc, slab, T, stab + TABM, static_cast<TI>(G.sx),
+                                         static_cast<TI>(G.sy), static_cast<TI>(G.sz));
+    if (pc.act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const int64_t o = pb + (static_cast<int64_t>(k) << lb);
+            p[o] = z[o];
+        }
+    }
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    if (threadIdx.x == 0) {
+        part[c] = rz;
+        part[count + c] = rr;
+        part[2 * count + c] = bb;
+    }
+}
+
+// 3.  (see k_pcg_update), one cell per workgroup.
+template <int N, typename TI>
+__global__ __launch_bounds__(64, 2) void k_pcg_update_wave(double* __restrict__ x, double* __restrict__ r,
+                                                         double* __restrict__ z, const double* __restrict__ p,
+                                                         const double* __restrict__ q, MeshArgs G,
+                                                         const TI* __restrict__ tab, const PcgState* __restrict__ st,
+                                                         double* __restrict__ part, int64_t count) {
+    if (st->done) return;
+    constexpr int TABM = EOShape<N>::SE + EOShape<N>::SO;
+    __shared__ TI slab[Slab<N>::size];
+    __shared__ TI stab[TABM + N];
+    TI T[TABM];
+    load_inverse_tables<N, TI>(tab, stab, T);
+    const double alpha = st->alpha;
+    const int64_t c = blockIdx.x;
+    const Pencil<N> pc(1);
+    const int lb = G.logB;
+    const int64_t pb = G.offset + block_base(c, lb, N * N * N) +
+                       (static_cast<int64_t>((pc.pa * N + pc.pb) * N) << lb);
+    double rv[N], rr = 0.0;
+    if (pc.act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const int64_t o = pb + (static_cast<int64_t>(k) << lb);
+            x[o] = fma(alpha, p[o], x[o]);
+            rv[k] = fma(-alpha, q[o], r[o]);
+            r[o] = rv[k];
+            rr = fma(rv[k], rv[k], rr);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) rv[k] = 0.0;
+    }
+    double rz = wave_precondition<N, TI>(rv, z + pb, lb, pc, slab, T, stab + TABM, static_cast<TI>(G.sx),
+                                         static_cast<TI>(G.sy), static_cast<TI>(G.sz));
+    rz = wave_sum(rz);
+    rr = wave_sum(rr);
+    if (threadIdx.x == 0) {
+        part[c] = rz;
+        part[count + c] = rr;
+    }
+}
+
 tp_status check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, what);
@@ -323,12 +489,22 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
     const unsigned nwg = static_cast<unsigned>(s->nwg);
     const int64_t cnt = s->nwg;
     const unsigned dgrid = static_cast<unsigned>(std::min<int64_t>((s->elems + 255) / 256, 8192));
+    constexpr bool kLane = N <= kLaneMaxN;
+    const double* tabA = reinterpret_cast<const double*>(eo_table(plan, N, EO_APPLY_A, 0));
+    const TI* tabS = reinterpret_cast<const TI*>(eo_table(plan, N, EO_INV, sizeof(TI) == 8 ? 0 : 1));
+    // 16-byte pencils for the wave body: block-contiguous layout (the
+    // solver's vectors are allocation-aligned)
+    const bool vp = g.logB == 0 && (N * sizeof(double)) % 16 == 0;
     if (!x_zero) {
         tp_status st = launch_sipg(plan, g, false, x, s->q, TP_F64, stream);
         if (st != TP_OK) return st;
     }
-    hipLaunchKernelGGL((k_pcg_start<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q, x,
-                       s->xw, s->r, s->z, s->p, G, E, s->part, cnt);
+    if constexpr (kLane)
+        hipLaunchKernelGGL((k_pcg_start<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q, x,
+                           s->xw, s->r, s->z, s->p, G, E, s->part, cnt);
+    else
+        hipLaunchKernelGGL((k_pcg_start_wave<N, TI>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q,
+                           x, s->xw, s->r, s->z, s->p, G, tabS, s->part, cnt);
     hipLaunchKernelGGL(k_pcg_reduce_start, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st, rtol, maxit);
     tp_status st = check_launch("PCG start");
     if (st != TP_OK) return st;
@@ -344,11 +520,22 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             for (int i = 0; i < chunk; ++i) {
-                hipLaunchKernelGGL((k_pcg_aq<N, LB>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R, F, s->st,
-                                   s->part);
+                if constexpr (kLane)
+                    hipLaunchKernelGGL((k_pcg_aq<N, LB>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R, F, s->st,
+                                       s->part);
+                else if (vp)
+                    hipLaunchKernelGGL((k_pcg_aq_wave<N, true>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, tabA, F,
+                                       s->st, s->part);
+                else
+                    hipLaunchKernelGGL((k_pcg_aq_wave<N, false>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, tabA,
+                                       F, s->st, s->part);
                 hipLaunchKernelGGL(k_pcg_reduce_alpha, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
-                hipLaunchKernelGGL((k_pcg_update<N, TI, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->z, s->p,
-                                   s->q, G, E, s->st, s->part, cnt);
+                if constexpr (kLane)
+                    hipLaunchKernelGGL((k_pcg_update<N, TI, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->z,
+                                       s->p, s->q, G, E, s->st, s->part, cnt);
+                else
+                    hipLaunchKernelGGL((k_pcg_update_wave<N, TI>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->z,
+                                       s->p, s->q, G, tabS, s->st, s->part, cnt);
                 hipLaunchKernelGGL(k_pcg_reduce_beta, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
                 hipLaunchKernelGGL(k_pcg_dir, dim3(dgrid), dim3(256), 0, cs, s->z, s->p, s->elems, s->st);
             }
@@ -379,9 +566,13 @@ tp_status pcg_prepare_dispatch(const Plan& plan, const GroupInfo& g, tp_pcg* s, 
                            : pcg_prepare<3, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
         case 4: return b64 ? pcg_prepare<4, TI, 6>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream)
                            : pcg_prepare<4, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        case 5: return pcg_prepare<5, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        case 6: return pcg_prepare<6, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        case 7: return pcg_prepare<7, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
+        case 8: return pcg_prepare<8, TI, -1>(plan, g, s, b, x, x_zero, rtol, maxit, chunk, stream);
         default: break;
     }
-    return set_error(TP_ERR_UNSUPPORTED, "the PCG solver supports n <= 4");
+    return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
 }
 
 // Argument checks shared by the blocking and the non-blocking solve.
@@ -448,12 +639,13 @@ tp_status tp_pcg_create(tp_plan* plan, tp_pcg** out) {
     *out = nullptr;
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
     if (!plan->mesh) return set_error(TP_ERR_UNSUPPORTED, "the PCG solver needs a mesh plan");
-    if (plan->groups[0].n > kLaneMaxN) return set_error(TP_ERR_UNSUPPORTED, "the PCG solver supports n <= 4");
     tp_pcg* s = new (std::nothrow) tp_pcg();
     if (!s) return set_error(TP_ERR_OOM, "host allocation failed");
     s->plan = plan;
     s->elems = std::max<int64_t>(plan->vec_elems, 1);
-    s->nwg = std::max<int64_t>((plan->groups[0].nblocks + 63) / 64, 1);
+    // partial sums: one per 64-cell tile (n <= 4) or per cell (n >= 5)
+    const GroupInfo& g0 = plan->groups[0];
+    s->nwg = std::max<int64_t>(g0.n <= kLaneMaxN ? (g0.nblocks + 63) / 64 : g0.nblocks, 1);
     const size_t vb = static_cast<size_t>(s->elems) * sizeof(double);
     hipError_t e = hipSuccess;
     for (double** d : {&s->r, &s->z, &s->p, &s->q, &s->xw})

@@ -24,7 +24,10 @@ def _rhs(ncell, n, seed):
 
 
 CASES = [(2, (5, 6, 7), (0.3, 0.2, 0.5)), (3, (4, 5, 6), (0.25, 0.5, 0.4)), (4, (3, 4, 5), (1.0, 0.5, 0.7)),
-         (3, (1, 1, 70), (0.1, 0.1, 0.1)), (4, (2, 9, 1), (0.5, 0.5, 0.5))]
+         (3, (1, 1, 70), (0.1, 0.1, 0.1)), (4, (2, 9, 1), (0.5, 0.5, 0.5)),
+         # one cell per wave (n >= 5)
+         (8, (2, 2, 3), (0.5, 0.5, 0.5)), (5, (3, 2, 3), (0.3, 0.4, 0.5)), (6, (2, 2, 2), (1.0, 0.7, 0.5)),
+         (7, (1, 2, 3), (0.4, 0.4, 0.4))]
 
 
 @pytest.mark.parametrize("n,cells,h", CASES)
