@@ -10,7 +10,7 @@ from paper_2609_04534_amd import serve, tpfdm
 
 pytestmark = pytest.mark.gpu
 
-MIX = [(2, 4), (3, 4), (2, 6), (3, 6), (3, 8), (2, 8)]
+MIX = [(2, 4), (3, 4), (2, 6), (3, 6), (3, 8), (2, 8), (7, 3)]
 
 
 def _alone(req, inner):
