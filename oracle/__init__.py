@@ -19,6 +19,10 @@ on GPUs", arXiv 2609.04534):
   Cartesian box mesh with Nitsche (homogeneous Dirichlet) boundary faces,
   A = A^vol + A^face of eq. (operator_split), assembled as a sparse matrix
   from dense cell-row blocks built from the bilinear form.
+* ``mg``     -- geometric multigrid for it: Chebyshev-accelerated
+  block-Jacobi smoothing (eq. (chebyshev_weights), eq. (chebyshev_richardson)),
+  polynomial-embedding transfers, a dense coarse solve, CG preconditioned by
+  one V-cycle.
 
 The oracle never uses sum factorization or fast diagonalization: those are
 the method under test.  Every function cites the passage it follows.

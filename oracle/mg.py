@@ -1,0 +1,118 @@
+"""Geometric multigrid for the coupled SIPG operator on uniform box meshes:
+Chebyshev-accelerated block-Jacobi smoothing, level transfers by polynomial
+embedding, a dense coarse solve, and CG preconditioned by one V-cycle.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Paper passages followed:
+
+* Sec. 5.2 (block-Jacobi smoother): the cell blocks of eq. (cell_block) with
+  the interior stencil on every cell (``sipg.block_jacobi``).
+* Sec. 5.2, eq. (chebyshev_weights) and eq. (chebyshev_richardson): one
+  smoothing application is three Richardson updates
+  u <- u + omega_j D^{-1} (b - A u) with omega_j = 1 / (c - d cos((2j-1) pi / 6)),
+  c = (a+b)/2, d = (b-a)/2, on the interval [a, b] = [0.2, 2] of Sec. 6.1.
+* Sec. 5 (level transfers): on uniform refinement a coarse cell's polynomial
+  is embedded into its 2^3 children (prolongation); restriction is the
+  transpose.
+* Sec. 6.1: one pre- and one post-smoothing application per level, the
+  coarsest level solved exactly by a dense factorization, CG preconditioned
+  by one V-cycle.
+
+Levels of an m-cell-per-side unit cube: m, m/2, ... while even; the
+coarsest has the odd part of m cells per side (1 for powers of two).  Every
+level is rediscretized with its own cell size (and penalty).
+Pins (tests/test_oracle_mg.py): the Chebyshev error polynomial of
+eq. (chebyshev_error_polynomial) in closed form, exact prolongation of
+polynomials, P^T M_fine P = M_coarse, the smoother's error propagator, the
+V-cycle's symmetry, and CG iteration counts in the range the paper reports.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import basis, sipg
+
+INTERVAL = (0.2, 2.0)
+
+
+def chebyshev_weights(a: float = INTERVAL[0], b: float = INTERVAL[1], degree: int = 3):
+    """omega_j = 1 / (c - d cos((2j-1) pi / (2 degree))), j = 1..degree."""
+    c = 0.5 * (a + b)
+    d = 0.5 * (b - a)
+    return [1.0 / (c - d * math.cos((2 * j - 1) * math.pi / (2 * degree))) for j in range(1, degree + 1)]
+
+
+def levels(m: int):
+    """Cells per side of every level, finest first."""
+    out = [m]
+    while out[-1] % 2 == 0:
+        out.append(out[-1] // 2)
+    return out
+
+
+def prolongation_1d(p: int):
+    """(P_0, P_1): P_c[i, j] = l_j((x_i + c) / 2), the coarse basis function j
+    at node i of child c (left c = 0, right c = 1) in the parent's
+    coordinates."""
+    x = basis.gll_nodes(p)
+    return tuple(basis.lagrange_values(x, (x + c) / 2.0) for c in (0, 1))
+
+
+def prolongation(p: int, mc: int) -> sp.csr_matrix:
+    """Fine (2 mc cells per side) <- coarse (mc) embedding, canonical orders."""
+    n3 = (p + 1) ** 3
+    P1 = prolongation_1d(p)
+    mf = 2 * mc
+    rows, cols, vals = [], [], []
+    li = np.repeat(np.arange(n3), n3)
+    lj = np.tile(np.arange(n3), n3)
+    for f in range(mf ** 3):
+        fx, fy, fz = sipg.cell_coords((mf,) * 3, f)
+        c = sipg.cell_index((mc,) * 3, fx // 2, fy // 2, fz // 2)
+        blk = np.kron(np.kron(P1[fx % 2], P1[fy % 2]), P1[fz % 2])
+        rows.append(f * n3 + li)
+        cols.append(c * n3 + lj)
+        vals.append(blk.reshape(-1))
+    N = mf ** 3 * n3
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(N, mc ** 3 * n3)).tocsr()
+
+
+class Hierarchy:
+    """Level operators, transfers and the coarse inverse of a unit cube."""
+
+    def __init__(self, p: int, m: int, C: float = 2.0):
+        self.p = p
+        self.ms = levels(m)
+        self.A = [sipg.assemble(p, (ml,) * 3, (1.0 / ml,) * 3, sipg.FULL, C) for ml in self.ms]
+        self.P = [prolongation(p, self.ms[k + 1]) for k in range(len(self.ms) - 1)]
+        self.coarse = np.linalg.inv(self.A[-1].toarray())
+        self.omega = chebyshev_weights()
+        self.C = C
+
+    def smooth(self, k: int, u, b):
+        """One Chebyshev application (three Richardson updates) on level k."""
+        ml = self.ms[k]
+        for w in self.omega:
+            u = u + w * sipg.block_jacobi(self.p, (ml,) * 3, (1.0 / ml,) * 3, b - self.A[k] @ u, self.C)
+        return u
+
+    def vcycle(self, b, k: int = 0):
+        """Approximate A_k^{-1} b by one V-cycle from level k (0 = finest)."""
+        if k == len(self.ms) - 1:
+            return self.coarse @ b
+        u = self.smooth(k, np.zeros_like(b), b)
+        r = b - self.A[k] @ u
+        u = u + self.P[k] @ self.vcycle(self.P[k].T @ r, k + 1)
+        return self.smooth(k, u, b)
+
+
+def mg_pcg(p: int, m: int, b, rtol: float, maxit: int = 200):
+    """CG on the finest level preconditioned by one V-cycle; returns
+    (x, iterations, relative residual)."""
+    H = Hierarchy(p, m)
+    return sipg.pcg(H.A[0], b, H.vcycle, rtol, maxit)

@@ -168,3 +168,43 @@ def test_planted_sipg_mistake_is_caught(monkeypatch, target, replacement):
 
 def test_unmutated_sipg_suite_passes():
     assert not _run_all(SIPG_PIN_SUITE)
+
+
+# ---------------------------------------------------------------- multigrid
+import tests.test_oracle_mg as mpins  # noqa: E402
+from oracle import mg  # noqa: E402
+
+_ORIG_P1D = mg.prolongation_1d
+_ORIG_W = mg.chebyshev_weights
+
+
+def _swapped_children(p):
+    P0, P1 = _ORIG_P1D(p)
+    return P1, P0
+
+
+def _even_roots(a=mg.INTERVAL[0], b=mg.INTERVAL[1], degree=3):
+    c, d = 0.5 * (a + b), 0.5 * (b - a)
+    import math
+    return [1.0 / (c - d * math.cos(2 * j * math.pi / (2 * degree))) for j in range(1, degree + 1)]
+
+
+MG_PIN_SUITE = [
+    lambda: mpins.test_chebyshev_weights_give_the_chebyshev_error_polynomial(),
+    lambda: mpins.test_prolongation_embeds_polynomials(2),
+    lambda: mpins.test_prolongation_preserves_the_mass(2),
+]
+
+
+@pytest.mark.parametrize("target,replacement", [
+    ((mg, "prolongation_1d"), _swapped_children),
+    ((mg, "chebyshev_weights"), _even_roots),
+])
+def test_planted_mg_mistake_is_caught(monkeypatch, target, replacement):
+    mod, name = target
+    monkeypatch.setattr(mod, name, replacement)
+    assert _run_all(MG_PIN_SUITE), f"no pin caught the mutation of {mod.__name__}.{name}"
+
+
+def test_unmutated_mg_suite_passes():
+    assert not _run_all(MG_PIN_SUITE)
