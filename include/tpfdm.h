@@ -340,6 +340,36 @@ tp_status tp_pcg_begin(tp_pcg* pcg, const double* b, double* x, int32_t x_is_zer
                        int32_t maxit, int32_t check_every, hipStream_t stream);
 tp_status tp_pcg_poll(tp_pcg* pcg, tp_pcg_summary* summary);
 
+/* Geometric multigrid for the coupled system of a mesh plan (n <= 4, layout
+ * B = 64): the V-cycle the paper uses to precondition CG (Sec. 5, Sec. 6.1).
+ * Levels: the mesh and its uniform coarsenings (cells halved while all three
+ * counts are even, lengths doubled, each level's own operator); per level
+ * one pre- and one post-smoothing application of the degree-three
+ * Chebyshev-accelerated block-Jacobi method on [0.2, 2]
+ * (eq. (chebyshev_weights), eq. (chebyshev_richardson): three Richardson
+ * updates with the cell-block fast-diagonalization inverse); transfers by
+ * polynomial embedding into the eight children and its transpose; the
+ * coarsest level (at most 2048 unknowns, else TP_ERR_UNSUPPORTED) solved
+ * with a dense inverse assembled once by applying its operator to unit
+ * vectors and kept for the life of the process (shared by hierarchies with
+ * the same coarsest level).  Needs tp_setup_inverse(TP_OP_CELL,
+ * TP_FACTOR_SCALED) on the plan (TP_ERR_STATE).  tp_mg_create allocates the
+ * level vectors (host-synchronous); tp_mg_vcycle enqueues x <- V(b) (FP64
+ * smoothing; b, x: distinct device vectors of the plan's layout, x
+ * overwritten, TP_ERR_ARG when null or equal).  The level vectors are the
+ * object's scratch: one V-cycle at a time per object, and a solver that uses
+ * it counts as its user for the whole solve (give concurrent solvers their
+ * own objects).  tp_pcg_set_multigrid makes later solves of that solver use
+ * one V-cycle as the preconditioner, with the smoother's block inverse in
+ * the solve's `inner` precision; null restores block-Jacobi; TP_ERR_ARG for
+ * a multigrid of another plan, TP_ERR_STATE during a non-blocking solve; a
+ * multigrid is destroyed only after its solvers are destroyed or reset. */
+typedef struct tp_mg tp_mg;
+tp_status tp_mg_create(tp_plan* plan, tp_mg** out);
+tp_status tp_mg_vcycle(tp_mg* mg, const double* b, double* x, hipStream_t stream);
+tp_status tp_mg_destroy(tp_mg* mg);
+tp_status tp_pcg_set_multigrid(tp_pcg* pcg, tp_mg* mg);
+
 /* Number of blocks in the plan (sum over groups). */
 int64_t tp_plan_nblocks(const tp_plan* plan);
 

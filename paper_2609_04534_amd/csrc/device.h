@@ -109,7 +109,7 @@ struct GArgs {
 
 // Element offset of block g's DoF 0 inside its group; DoF q sits at
 // base + (q << logB).
-__device__ __forceinline__ int64_t block_base(int64_t g, int logB, int n3) {
+__host__ __device__ __forceinline__ int64_t block_base(int64_t g, int logB, int n3) {
     return (((g >> logB) * n3) << logB) + (g & ((int64_t(1) << logB) - 1));
 }
 

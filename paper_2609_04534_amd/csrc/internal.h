@@ -21,6 +21,7 @@ void gauss_points(int nq, double* x, double* w);
 void reference_matrices(int n, double C, double* M, double* K, double* A);
 int gen_eigen(int n, const double* M, const double* P, double* S, double* lam);
 void endpoint_derivatives(int n, double* g0, double* g1);
+void prolongation_1d(int n, double* P0, double* P1);
 
 // Even-odd tables of the centrosymmetric 1D factors, one slot of kEOSlot
 // elements per (n, table, element type):
@@ -198,6 +199,13 @@ tp_status launch_apply_persistent(const Plan& plan, int op, const void* u, void*
 tp_status launch_inverse_persistent(const Plan& plan, const void* r, void* x, tp_dtype dt, hipStream_t s);
 tp_status launch_solve_persistent(const Plan& plan, const double* b, double* x, tp_dtype inner, double rtol,
                                   int maxit, int32_t* iters, double* relres, int64_t* nparts, hipStream_t s);
+// Multigrid V-cycle of a mesh plan (mg.hip): u = V(b) on the finest level,
+// every kernel skipped once the PCG state st (nullable) is done; the dot
+// kernel writes per-tile partials of (a, b).
+tp_status mg_enqueue_vcycle(const tp_mg* m, const double* b, double* u, const void* st, bool f32, hipStream_t s);
+tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const double* b, double* part, const void* st,
+                         hipStream_t s);
+const tp_plan* mg_plan(const tp_mg* m);
 // Coupled SIPG operator of a mesh plan (sipg.hip): A u, or A^face u when face_only.
 tp_status launch_sipg(const Plan& plan, const GroupInfo& g, bool face_only, const void* u, void* v, tp_dtype dt,
                       hipStream_t s);

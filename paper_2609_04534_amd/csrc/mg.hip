@@ -1,0 +1,565 @@
+// Geometric multigrid for the coupled SIPG operator of a mesh plan (n <= 4):
+// the V-cycle the paper uses to precondition CG (Sec. 5, Sec. 6.1).
+//
+// Levels: the plan's box and its uniform coarsenings (cells halved in every
+// direction while all three counts are even, cell lengths doubled, the
+// operator rediscretized with the level's own lengths and penalty).  On each
+// level but the coarsest one smoothing application before and one after
+// the coarse correction; a smoothing application is the degree-three
+// Chebyshev-accelerated block-Jacobi method, three Richardson updates
+//   u <- u + omega_j D^{-1} (b - A u),  omega_j = 1 / (c - d cos((2j-1) pi / 6))
+// on the spectral interval [0.2, 2] (eq. (chebyshev_weights),
+// eq. (chebyshev_richardson)), with D^{-1} the cell-wise fast-diagonalization
+// inverse.  Transfers embed a coarse cell's polynomial into its eight
+// children (prolongation, accumulated into the fine correction) and apply
+// the transpose (restriction).  The coarsest level is solved exactly by a
+// dense inverse, assembled once by applying the level operator to unit
+// vectors (as the paper assembles its coarse LU) and inverted on the host.
+//
+// Every vector of a level is in the B = 64 blocked layout, one cell per lane;
+// every kernel returns at once when the solve state passed to it is done,
+// so a V-cycle can sit inside a captured chunk of CG iterations.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "sipg.h"
+
+namespace tpfdm {
+
+constexpr int64_t kMaxCoarse = 2048;   // unknowns of the densely solved coarsest level
+
+template <int N>
+struct ProlTab {    // 1D embeddings of the left and right child, row-major
+    double p[2][N * N];
+};
+
+namespace {
+
+__device__ __forceinline__ bool done_flag(const PcgState* st) { return st && st->done; }
+
+// t = A u on one level (one cell per lane); the consumers form b - t as
+// they load, which keeps b out of this kernel's registers.
+template <int N>
+__global__ __launch_bounds__(64, 2) void k_mg_apply(const double* __restrict__ u, double* __restrict__ t, MeshArgs G,
+                                                  Pair<N, double> R, FaceRef<N, double> F,
+                                                  const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    constexpr int N3 = N * N * N;
+    __shared__ double sa[N * N][64], sbt[N * N][64];
+    const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
+    if (c >= G.ncells) return;
+    double acc[N3];
+    sipg_cell<N, double, double, -1>(u, G, R, F, c, acc, sa, sbt);
+    const int64_t base = G.offset + block_base(c, 6, N3);
+#pragma unroll
+    for (int e = 0; e < N3; ++e) {
+        const int64_t o = base + (static_cast<int64_t>(e) << 6);
+        t[o] = acc[e];
+    }
+}
+
+// u <- u + omega D^{-1} (b - t) with t = A u, or u <- omega D^{-1} b when
+// init (u = 0); the block inverse in precision TI.
+template <int N, typename TI>
+__global__ __launch_bounds__(64, 2) void k_mg_jacobi(const double* __restrict__ b, const double* __restrict__ t,
+                                                   double* __restrict__ u, MeshArgs G, Eig<N, TI> E, double omega,
+                                                   int init, const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    constexpr int N3 = N * N * N;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    if (c >= G.ncells) return;
+    const int64_t base = G.offset + block_base(c, 6, N3);
+    TI v[N3];
+#pragma unroll
+    for (int e = 0; e < N3; ++e) {
+        const int64_t o = base + (static_cast<int64_t>(e) << 6);
+        v[e] = static_cast<TI>(init ? b[o] : b[o] - t[o]);
+    }
+    lane_fdm_inplace<N, TI>(v, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy), static_cast<TI>(G.sz));
+#pragma unroll
+    for (int e = 0; e < N3; ++e) {
+        const int64_t o = base + (static_cast<int64_t>(e) << 6);
+        const double d = omega * static_cast<double>(v[e]);
+        u[o] = init ? d : u[o] + d;
+    }
+}
+
+// acc += (X (x) Y (x) Z) w for one cell, the input streamed one x-plane at
+// a time (X acts on x, the slowest index).
+template <int N, typename LoadF>
+__device__ __forceinline__ void kron3_accumulate(LoadF load, const double* X, const double* Y, const double* Z,
+                                                 double (&acc)[N * N * N]) {
+#pragma unroll
+    for (int ip = 0; ip < N; ++ip) {
+        double pl[N * N];
+#pragma unroll
+        for (int q = 0; q < N * N; ++q) pl[q] = load(ip * N * N + q);
+        double t1[N * N];
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int kk = 0; kk < N; ++kk) sacc = fma(Z[k * N + kk], pl[j * N + kk], sacc);
+                t1[j * N + k] = sacc;
+            }
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < N; ++jj) sacc = fma(Y[j * N + jj], t1[jj * N + k], sacc);
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc[(i * N + j) * N + k] = fma(X[i * N + ip], sacc, acc[(i * N + j) * N + k]);
+            }
+    }
+}
+
+// b_coarse = P^T (b_fine - t_fine), t_fine = A u_fine: one coarse cell per
+// lane, summed over its children.
+template <int N>
+__global__ __launch_bounds__(64, 2) void k_mg_restrict(const double* __restrict__ bf, const double* __restrict__ tf,
+                                                     double* __restrict__ bc,
+                                                     MeshArgs Gf, MeshArgs Gc, ProlTab<N> PT,
+                                                     const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    constexpr int N3 = N * N * N;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    if (c >= Gc.ncells) return;
+    const uint32_t cu = static_cast<uint32_t>(c);
+    const uint32_t cz = cu % static_cast<uint32_t>(Gc.mz);
+    const uint32_t rr = cu / static_cast<uint32_t>(Gc.mz);
+    const uint32_t cy = rr % static_cast<uint32_t>(Gc.my);
+    const uint32_t cx = rr / static_cast<uint32_t>(Gc.my);
+    double acc[N3];
+#pragma unroll
+    for (int e = 0; e < N3; ++e) acc[e] = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+        const int bx = ch >> 2, by = (ch >> 1) & 1, bz = ch & 1;
+        const int64_t f = (static_cast<int64_t>(2 * cx + bx) * Gf.my + (2 * cy + by)) * Gf.mz + (2 * cz + bz);
+        const int64_t fb = Gf.offset + block_base(f, 6, N3);
+        kron3_accumulate<N>(
+            [&](int q) {
+                const int64_t o = fb + (static_cast<int64_t>(q) << 6);
+                return bf[o] - tf[o];
+            },
+            PT.p[bx], PT.p[by], PT.p[bz], acc);
+    }
+    const int64_t base = Gc.offset + block_base(c, 6, N3);
+#pragma unroll
+    for (int e = 0; e < N3; ++e) bc[base + (static_cast<int64_t>(e) << 6)] = acc[e];
+}
+
+// u_fine += P u_coarse: one fine cell per lane, the child's embedding
+// selected per lane.
+template <int N>
+__global__ __launch_bounds__(64, 2) void k_mg_prolong(const double* __restrict__ uc, double* __restrict__ uf,
+                                                    MeshArgs Gf, MeshArgs Gc, ProlTab<N> P,
+                                                    const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    constexpr int N3 = N * N * N, N2 = N * N;
+    const int64_t f = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    if (f >= Gf.ncells) return;
+    const uint32_t fu = static_cast<uint32_t>(f);
+    const uint32_t fz = fu % static_cast<uint32_t>(Gf.mz);
+    const uint32_t rr = fu / static_cast<uint32_t>(Gf.mz);
+    const uint32_t fy = rr % static_cast<uint32_t>(Gf.my);
+    const uint32_t fx = rr / static_cast<uint32_t>(Gf.my);
+    const int64_t c = (static_cast<int64_t>(fx / 2) * Gc.my + fy / 2) * Gc.mz + fz / 2;
+    double X[N2], Y[N2], Z[N2];
+#pragma unroll
+    for (int e = 0; e < N2; ++e) {
+        X[e] = (fx & 1) ? P.p[1][e] : P.p[0][e];
+        Y[e] = (fy & 1) ? P.p[1][e] : P.p[0][e];
+        Z[e] = (fz & 1) ? P.p[1][e] : P.p[0][e];
+    }
+    const double* w = uc + Gc.offset + block_base(c, 6, N3);
+    double acc[N3];
+#pragma unroll
+    for (int e = 0; e < N3; ++e) acc[e] = 0.0;
+    kron3_accumulate<N>([&](int q) { return w[static_cast<int64_t>(q) << 6]; }, X, Y, Z, acc);
+    const int64_t base = Gf.offset + block_base(f, 6, N3);
+#pragma unroll
+    for (int e = 0; e < N3; ++e) {
+        const int64_t o = base + (static_cast<int64_t>(e) << 6);
+        uf[o] += acc[e];
+    }
+}
+
+// u = A0^{-1} b on the coarsest level: b gathered into LDS in canonical
+// order, one row of the (column-major) inverse per thread.
+template <int N>
+__global__ __launch_bounds__(256) void k_mg_coarse(const double* __restrict__ inv, const double* __restrict__ b,
+                                                   double* __restrict__ u, int64_t n0, int64_t offset,
+                                                   const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    constexpr int N3 = N * N * N;
+    __shared__ double sb[kMaxCoarse];
+    for (int64_t e = threadIdx.x; e < n0; e += 256)
+        sb[e] = b[offset + block_base(e / N3, 6, N3) + ((e % N3) << 6)];
+    __syncthreads();
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n0) return;
+    double s = 0.0;
+    for (int64_t j = 0; j < n0; ++j) s = fma(inv[j * n0 + i], sb[j], s);
+    u[offset + block_base(i / N3, 6, N3) + ((i % N3) << 6)] = s;
+}
+
+// Partial (a, b) per 64-cell tile (the layout of the PCG partials).
+template <int N>
+__global__ __launch_bounds__(64) void k_mg_dot(const double* __restrict__ a, const double* __restrict__ b,
+                                               MeshArgs G, double* __restrict__ part,
+                                               const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    constexpr int N3 = N * N * N;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    double s = 0.0;
+    if (c < G.ncells) {
+        const int64_t base = G.offset + block_base(c, 6, N3);
+#pragma unroll
+        for (int e = 0; e < N3; ++e) {
+            const int64_t o = base + (static_cast<int64_t>(e) << 6);
+            s = fma(a[o], b[o], s);
+        }
+    }
+    s = wave_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+tp_status check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_error(e, what);
+    return TP_OK;
+}
+
+// Cholesky factorization and inverse of a symmetric positive definite
+// matrix (row-major), the triangular solves spread over host threads;
+// the inverse is returned column-major (equal to row-major: symmetric).
+bool spd_inverse(int64_t n, std::vector<double>& A, std::vector<double>& inv) {
+    for (int64_t j = 0; j < n; ++j) {
+        double d = A[j * n + j];
+        for (int64_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+        if (!(d > 0.0)) return false;
+        const double l = std::sqrt(d);
+        A[j * n + j] = l;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double s = A[i * n + j];
+            for (int64_t k = 0; k < j; ++k) s -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = s / l;
+        }
+    }
+    inv.assign(static_cast<size_t>(n * n), 0.0);
+    const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    auto work = [&](unsigned tid) {
+        std::vector<double> y(static_cast<size_t>(n));
+        for (int64_t col = tid; col < n; col += nt) {
+            for (int64_t i = 0; i < n; ++i) {       // L y = e_col
+                double s = i == col ? 1.0 : 0.0;
+                for (int64_t k = 0; k < i; ++k) s -= A[i * n + k] * y[k];
+                y[i] = s / A[i * n + i];
+            }
+            for (int64_t i = n - 1; i >= 0; --i) {  // L^T x = y
+                double s = y[i];
+                for (int64_t k = i + 1; k < n; ++k) s -= A[k * n + i] * inv[col * n + k];
+                inv[col * n + i] = s / A[i * n + i];
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) th.emplace_back(work, t);
+    for (auto& t : th) t.join();
+    return true;
+}
+
+}  // namespace
+
+// Coarse inverses are shared by every hierarchy with the same coarsest level
+// on a device and kept until the process ends.
+struct CoarseKey {
+    int device, n, mx, my, mz;
+    double hx, hy, hz, C;
+    bool operator<(const CoarseKey& o) const {
+        return std::tie(device, n, mx, my, mz, hx, hy, hz, C) <
+               std::tie(o.device, o.n, o.mx, o.my, o.mz, o.hx, o.hy, o.hz, o.C);
+    }
+};
+static std::mutex g_coarse_mutex;
+static std::map<CoarseKey, double*> g_coarse;
+
+}  // namespace tpfdm
+
+using namespace tpfdm;
+
+struct MgLevel {
+    MeshArgs G;
+    int64_t elems = 0;
+    double* t = nullptr;   // residual scratch
+    double* b = nullptr;   // right-hand side (levels below the finest)
+    double* u = nullptr;   // correction (levels below the finest)
+};
+
+struct tp_mg {
+    tp_plan* plan = nullptr;
+    int n = 0;
+    std::vector<MgLevel> lv;
+    double omega[3] = {0.0, 0.0, 0.0};
+    double* coarse_inv = nullptr;   // shared, not owned
+    int64_t n0 = 0;
+};
+
+namespace {
+
+template <int N, typename TI>
+tp_status vcycle_level(const tp_mg* m, size_t l, const double* b, double* u, const PcgState* st, hipStream_t s) {
+    const Plan& plan = *m->plan;
+    const MgLevel& L = m->lv[l];
+    const unsigned grid = static_cast<unsigned>((L.G.ncells + 63) / 64);
+    if (l + 1 == m->lv.size()) {
+        const unsigned cg = static_cast<unsigned>((m->n0 + 255) / 256);
+        hipLaunchKernelGGL((k_mg_coarse<N>), dim3(cg), dim3(256), 0, s, m->coarse_inv, b, u, m->n0, L.G.offset, st);
+        return check_launch("coarse solve");
+    }
+    Pair<N, double> R;
+    FaceRef<N, double> F;
+    sipg_tables<N, double>(plan, false, R, F);
+    Eig<N, TI> E;
+    for (int i = 0; i < N * N; ++i) E.s[i] = static_cast<TI>(plan.ref[N].S[i]);
+    for (int i = 0; i < N; ++i) E.lam[i] = static_cast<TI>(plan.ref[N].lam[i]);
+    ProlTab<N> P, PT;
+    prolongation_1d(N, P.p[0], P.p[1]);
+    for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) PT.p[c][i * N + j] = P.p[c][j * N + i];
+    auto smooth = [&](bool from_zero) {
+        for (int j = 0; j < 3; ++j) {
+            if (from_zero && j == 0) {
+                hipLaunchKernelGGL((k_mg_jacobi<N, TI>), dim3(grid), dim3(64), 0, s, b, L.t, u, L.G, E, m->omega[0], 1,
+                                   st);
+                continue;
+            }
+            hipLaunchKernelGGL((k_mg_apply<N>), dim3(grid), dim3(64), 0, s, u, L.t, L.G, R, F, st);
+            hipLaunchKernelGGL((k_mg_jacobi<N, TI>), dim3(grid), dim3(64), 0, s, b, L.t, u, L.G, E, m->omega[j], 0,
+                               st);
+        }
+    };
+    smooth(true);
+    const MgLevel& C = m->lv[l + 1];
+    hipLaunchKernelGGL((k_mg_apply<N>), dim3(grid), dim3(64), 0, s, u, L.t, L.G, R, F, st);
+    hipLaunchKernelGGL((k_mg_restrict<N>), dim3(static_cast<unsigned>((C.G.ncells + 63) / 64)), dim3(64), 0, s, b,
+                       L.t, C.b, L.G, C.G, PT, st);
+    tp_status stt = check_launch("level transfer");
+    if (stt != TP_OK) return stt;
+    stt = vcycle_level<N, TI>(m, l + 1, C.b, C.u, st, s);
+    if (stt != TP_OK) return stt;
+    hipLaunchKernelGGL((k_mg_prolong<N>), dim3(grid), dim3(64), 0, s, C.u, u, L.G, C.G, P, st);
+    smooth(false);
+    return check_launch("smoothing");
+}
+
+template <typename TI>
+tp_status vcycle_dispatch(const tp_mg* m, const double* b, double* u, const PcgState* st, hipStream_t s) {
+    switch (m->n) {
+        case 2: return vcycle_level<2, TI>(m, 0, b, u, st, s);
+        case 3: return vcycle_level<3, TI>(m, 0, b, u, st, s);
+        case 4: return vcycle_level<4, TI>(m, 0, b, u, st, s);
+        default: break;
+    }
+    return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
+}
+
+template <int N>
+tp_status coarse_probe_n(const tp_mg* m, std::vector<double>& A) {
+    const Plan& plan = *m->plan;
+    const MgLevel& L = m->lv.back();
+    Pair<N, double> R;
+    FaceRef<N, double> F;
+    sipg_tables<N, double>(plan, false, R, F);
+    constexpr int N3 = N * N * N;
+    const int64_t n0 = m->n0;
+    A.assign(static_cast<size_t>(n0 * n0), 0.0);
+    std::vector<double> col(static_cast<size_t>(L.elems));
+    const unsigned grid = static_cast<unsigned>((L.G.ncells + 63) / 64);
+    // column j = A e_j, with L.u = e_j as the probe
+    for (int64_t j = 0; j < n0; ++j) {
+        tp_status st = launch_fill(L.u, L.elems, TP_F64, 0, true, nullptr);
+        if (st != TP_OK) return st;
+        const double one = 1.0;
+        const int64_t pos = L.G.offset + block_base(j / N3, 6, N3) + ((j % N3) << 6);
+        hipError_t e = hipMemcpy(L.u + pos, &one, sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_error(e, "coarse probe");
+        hipLaunchKernelGGL((k_mg_apply<N>), dim3(grid), dim3(64), 0, nullptr, L.u, L.t, L.G, R, F,
+                           static_cast<const PcgState*>(nullptr));
+        e = hipMemcpy(col.data(), L.t, static_cast<size_t>(L.elems) * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_error(e, "coarse probe");
+        for (int64_t i = 0; i < n0; ++i)
+            A[i * n0 + j] = col[static_cast<size_t>(L.G.offset + block_base(i / N3, 6, N3) + ((i % N3) << 6))];
+    }
+    return TP_OK;
+}
+
+void free_mg(tp_mg* m) {
+    for (auto& L : m->lv)
+        for (double* p : {L.t, L.b, L.u})
+            if (p) (void)hipFree(p);
+    m->lv.clear();
+}
+
+}  // namespace
+
+namespace tpfdm {
+tp_status mg_enqueue_vcycle(const tp_mg* m, const double* b, double* u, const void* st, bool f32, hipStream_t s) {
+    const PcgState* ps = static_cast<const PcgState*>(st);
+    return f32 ? vcycle_dispatch<float>(m, b, u, ps, s) : vcycle_dispatch<double>(m, b, u, ps, s);
+}
+
+tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const double* b, double* part, const void* st,
+                         hipStream_t s) {
+    const MgLevel& L = m->lv[0];
+    const unsigned grid = static_cast<unsigned>((L.G.ncells + 63) / 64);
+    const PcgState* ps = static_cast<const PcgState*>(st);
+    switch (m->n) {
+        case 2: hipLaunchKernelGGL((k_mg_dot<2>), dim3(grid), dim3(64), 0, s, a, b, L.G, part, ps); break;
+        case 3: hipLaunchKernelGGL((k_mg_dot<3>), dim3(grid), dim3(64), 0, s, a, b, L.G, part, ps); break;
+        case 4: hipLaunchKernelGGL((k_mg_dot<4>), dim3(grid), dim3(64), 0, s, a, b, L.G, part, ps); break;
+        default: return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
+    }
+    return check_launch("dot");
+}
+
+const tp_plan* mg_plan(const tp_mg* m) { return m->plan; }
+}  // namespace tpfdm
+
+extern "C" {
+
+tp_status tp_mg_create(tp_plan* plan, tp_mg** out) {
+    if (!out) return set_error(TP_ERR_ARG, "out must be non-null");
+    *out = nullptr;
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (!plan->mesh) return set_error(TP_ERR_UNSUPPORTED, "multigrid needs a mesh plan");
+    const GroupInfo& g = plan->groups[0];
+    if (g.n > kLaneMaxN) return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
+    if (g.logB != 6) return set_error(TP_ERR_UNSUPPORTED, "multigrid needs the layout B = 64");
+    if (plan->inverse_op != TP_OP_CELL || plan->factor_mode != TP_FACTOR_SCALED)
+        return set_error(TP_ERR_STATE, "multigrid needs tp_setup_inverse(TP_OP_CELL, TP_FACTOR_SCALED) first");
+    tp_mg* m = new (std::nothrow) tp_mg();
+    if (!m) return set_error(TP_ERR_OOM, "host allocation failed");
+    m->plan = plan;
+    m->n = g.n;
+    const double a = 0.2, b = 2.0, c = 0.5 * (a + b), d = 0.5 * (b - a);
+    for (int j = 1; j <= 3; ++j) m->omega[j - 1] = 1.0 / (c - d * std::cos((2 * j - 1) * 3.141592653589793 / 6.0));
+    // levels
+    int mx = plan->mesh_m[0], my = plan->mesh_m[1], mz = plan->mesh_m[2];
+    double hx = plan->mesh_h[0], hy = plan->mesh_h[1], hz = plan->mesh_h[2];
+    const int64_t n3 = int64_t(g.n) * g.n * g.n;
+    hipError_t e = hipSuccess;
+    for (;;) {
+        MgLevel L;
+        L.G.ncells = int64_t(mx) * my * mz;
+        L.G.offset = 0;
+        L.G.logB = 6;
+        L.G.mx = mx;
+        L.G.my = my;
+        L.G.mz = mz;
+        L.G.sx = hy * hz / hx;
+        L.G.sy = hx * hz / hy;
+        L.G.sz = hx * hy / hz;
+        L.elems = (L.G.ncells + 63) / 64 * n3 * 64;
+        const size_t vb = static_cast<size_t>(L.elems) * sizeof(double);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&L.t), vb);
+        if (!m->lv.empty()) {
+            if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&L.b), vb);
+            if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&L.u), vb);
+        }
+        m->lv.push_back(L);
+        if (e != hipSuccess || mx % 2 || my % 2 || mz % 2) break;
+        mx /= 2, my /= 2, mz /= 2;
+        hx *= 2, hy *= 2, hz *= 2;
+    }
+    if (e != hipSuccess) {
+        free_mg(m);
+        delete m;
+        (void)hipGetLastError();
+        return set_error(TP_ERR_OOM, "multigrid workspace allocation failed");
+    }
+    const MgLevel& Lc = m->lv.back();
+    m->n0 = Lc.G.ncells * n3;
+    if (m->n0 > kMaxCoarse) {
+        free_mg(m);
+        delete m;
+        return set_error(TP_ERR_UNSUPPORTED, "the coarsest level (" + std::to_string(m->n0) +
+                                                 " unknowns) is too large for its dense solve");
+    }
+    if (m->lv.size() == 1) {   // no coarser level: the finest is solved densely; it needs b and u scratch
+        MgLevel& L0 = m->lv[0];
+        const size_t vb = static_cast<size_t>(L0.elems) * sizeof(double);
+        e = hipMalloc(reinterpret_cast<void**>(&L0.b), vb);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&L0.u), vb);
+        if (e != hipSuccess) {
+            free_mg(m);
+            delete m;
+            (void)hipGetLastError();
+            return set_error(TP_ERR_OOM, "multigrid workspace allocation failed");
+        }
+    }
+    // the coarse inverse, shared per device and coarsest level
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const CoarseKey key{dev, g.n, Lc.G.mx, Lc.G.my, Lc.G.mz, hx, hy, hz, plan->penalty_C};
+    std::lock_guard<std::mutex> lock(g_coarse_mutex);
+    auto it = g_coarse.find(key);
+    if (it != g_coarse.end()) {
+        m->coarse_inv = it->second;
+    } else {
+        std::vector<double> A, inv;
+        tp_status st = TP_OK;
+        switch (g.n) {
+            case 2: st = coarse_probe_n<2>(m, A); break;
+            case 3: st = coarse_probe_n<3>(m, A); break;
+            default: st = coarse_probe_n<4>(m, A); break;
+        }
+        if (st == TP_OK && !spd_inverse(m->n0, A, inv))
+            st = set_error(TP_ERR_NOT_SPD, "the coarsest level operator is not positive definite");
+        double* dinv = nullptr;
+        if (st == TP_OK) {
+            e = hipMalloc(reinterpret_cast<void**>(&dinv), inv.size() * sizeof(double));
+            if (e == hipSuccess)
+                e = hipMemcpy(dinv, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice);
+            if (e != hipSuccess) st = hip_error(e, "coarse inverse upload");
+        }
+        if (st != TP_OK) {
+            if (dinv) (void)hipFree(dinv);
+            free_mg(m);
+            delete m;
+            return st;
+        }
+        g_coarse[key] = dinv;
+        m->coarse_inv = dinv;
+    }
+    *out = m;
+    return TP_OK;
+}
+
+tp_status tp_mg_vcycle(tp_mg* m, const double* b, double* x, hipStream_t stream) {
+    if (!m) return set_error(TP_ERR_ARG, "multigrid is null");
+    if (!b || !x) return set_error(TP_ERR_ARG, "b and x must be non-null");
+    if (static_cast<const void*>(b) == static_cast<const void*>(x)) return set_error(TP_ERR_ARG, "b and x must not alias");
+    return mg_enqueue_vcycle(m, b, x, nullptr, false, stream);
+}
+
+tp_status tp_mg_destroy(tp_mg* m) {
+    if (!m) return TP_OK;
+    free_mg(m);
+    delete m;
+    return TP_OK;
+}
+
+}  // extern "C"

@@ -25,20 +25,7 @@
 
 namespace tpfdm {
 
-// Device-side solver state.  done: 0 running, 1 converged, 2 breakdown or a
-// non-finite scalar, 3 iteration limit.
-struct PcgState {
-    double rz, pq, rr, bb, alpha, beta, tol2;
-    int iter, done, maxit, pad;
-};
-
 namespace {
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 
 __device__ __forceinline__ bool finite(double v) { return v == v && v <= 1.7976931348623157e308 && v >= -1.7976931348623157e308; }
 
@@ -182,7 +169,7 @@ __global__ __launch_bounds__(64, 2) void k_pcg_start(const double* __restrict__ 
         for (int e = 0; e < N3; ++e) {
             const int64_t o = base + (static_cast<int64_t>(e) << lb);
             const double bv = b[o];
-            const double rv = q ? bv - q[o] : bv;
+            const double rv = q ? bv - q[o] : bv;   // (q: A x0, or null for x0 = 0)
             x[o] = q ? x0[o] : 0.0;   // the solver's iterate starts from the guess
             r[o] = rv;
             v[e] = static_cast<TI>(rv);
@@ -252,6 +239,69 @@ __global__ __launch_bounds__(256) void k_pcg_dir(const double* __restrict__ z, d
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * 256)
         p[i] = fma(beta, p[i], z[i]);
+}
+
+// ---------------------------------------------------------------- multigrid preconditioning
+// The V-cycle is a sequence of launches over all levels, so with it the
+// start and the update only form residuals; z and (r, z) come from the
+// multigrid kernels.
+
+// Start: x = x0 and r = b - q, or x = 0 and r = b; partials (r, r), (b, b).
+template <int N, int LB>
+__global__ __launch_bounds__(64) void k_pcg_start_res(const double* __restrict__ b, const double* __restrict__ q,
+                                                      const double* __restrict__ x0, double* __restrict__ x,
+                                                      double* __restrict__ r, MeshArgs G,
+                                                      double* __restrict__ part, int64_t count) {
+    constexpr int N3 = N * N * N;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    const int lb = LB >= 0 ? LB : G.logB;
+    double rr = 0.0, bb = 0.0;
+    if (c < G.ncells) {
+        const int64_t base = G.offset + block_base(c, lb, N3);
+#pragma unroll 8
+        for (int e = 0; e < N3; ++e) {
+            const int64_t o = base + (static_cast<int64_t>(e) << lb);
+            const double bv = b[o];
+            const double rv = q ? bv - q[o] : bv;   // (q: A x0, or null for x0 = 0)
+            x[o] = q ? x0[o] : 0.0;
+            r[o] = rv;
+            rr = fma(rv, rv, rr);
+            bb = fma(bv, bv, bb);
+        }
+    }
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    if (threadIdx.x == 0) {
+        part[count + blockIdx.x] = rr;
+        part[2 * count + blockIdx.x] = bb;
+    }
+}
+
+// x += alpha p, r -= alpha q; partial (r, r).
+template <int N, int LB>
+__global__ __launch_bounds__(64) void k_pcg_axpy(double* __restrict__ x, double* __restrict__ r,
+                                                 const double* __restrict__ p, const double* __restrict__ q,
+                                                 MeshArgs G, const PcgState* __restrict__ st,
+                                                 double* __restrict__ part, int64_t count) {
+    if (st->done) return;
+    constexpr int N3 = N * N * N;
+    const double alpha = st->alpha;
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    const int lb = LB >= 0 ? LB : G.logB;
+    double rr = 0.0;
+    if (c < G.ncells) {
+        const int64_t base = G.offset + block_base(c, lb, N3);
+#pragma unroll
+        for (int e = 0; e < N3; ++e) {
+            const int64_t o = base + (static_cast<int64_t>(e) << lb);
+            x[o] = fma(alpha, p[o], x[o]);
+            const double rv = fma(-alpha, q[o], r[o]);
+            r[o] = rv;
+            rr = fma(rv, rv, rr);
+        }
+    }
+    rr = wave_sum(rr);
+    if (threadIdx.x == 0) part[count + blockIdx.x] = rr;
 }
 
 // ---------------------------------------------------------------- n >= 5
@@ -461,6 +511,7 @@ struct tp_pcg {
     double* xout = nullptr;     // the caller's x
     int ti = 0;                 // precision of the running solve
     int phase = 0;              // 0 idle, 1 iterating, 2 copying the result out
+    tp_mg* mg = nullptr;        // V-cycle preconditioner (null: block-Jacobi)
 };
 
 namespace {
@@ -499,7 +550,21 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
         tp_status st = launch_sipg(plan, g, false, x, s->q, TP_F64, stream);
         if (st != TP_OK) return st;
     }
-    if constexpr (kLane)
+    const bool f32 = sizeof(TI) == 4;
+    if (s->mg) {
+        if constexpr (kLane) {
+            hipLaunchKernelGGL((k_pcg_start_res<N, LB>), dim3(nwg), dim3(64), 0, stream, b,
+                               x_zero ? nullptr : s->q, x, s->xw, s->r, G, s->part, cnt);
+            tp_status st = mg_enqueue_vcycle(s->mg, s->r, s->z, nullptr, f32, stream);
+            if (st == TP_OK) st = mg_enqueue_dot(s->mg, s->r, s->z, s->part, nullptr, stream);
+            if (st != TP_OK) return st;
+            const hipError_t e = hipMemcpyAsync(s->p, s->z, static_cast<size_t>(s->elems) * sizeof(double),
+                                                hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return hip_error(e, "PCG start");
+        } else {
+            return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
+        }
+    } else if constexpr (kLane)
         hipLaunchKernelGGL((k_pcg_start<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q, x,
                            s->xw, s->r, s->z, s->p, G, E, s->part, cnt);
     else
@@ -530,7 +595,14 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                     hipLaunchKernelGGL((k_pcg_aq_wave<N, false>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, tabA,
                                        F, s->st, s->part);
                 hipLaunchKernelGGL(k_pcg_reduce_alpha, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
-                if constexpr (kLane)
+                if (s->mg) {
+                    if constexpr (kLane) {
+                        hipLaunchKernelGGL((k_pcg_axpy<N, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->p, s->q,
+                                           G, s->st, s->part, cnt);
+                        (void)mg_enqueue_vcycle(s->mg, s->r, s->z, s->st, f32, cs);
+                        (void)mg_enqueue_dot(s->mg, s->r, s->z, s->part, s->st, cs);
+                    }
+                } else if constexpr (kLane)
                     hipLaunchKernelGGL((k_pcg_update<N, TI, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->z,
                                        s->p, s->q, G, E, s->st, s->part, cnt);
                 else
@@ -745,6 +817,16 @@ tp_status tp_pcg_poll(tp_pcg* s, tp_pcg_summary* summary) {
     }
     if (st != TP_OK) s->phase = 0;
     return st == TP_OK ? TP_PENDING : st;
+}
+
+tp_status tp_pcg_set_multigrid(tp_pcg* s, tp_mg* mg) {
+    if (!s) return set_error(TP_ERR_ARG, "solver is null");
+    if (s->phase != 0) return set_error(TP_ERR_STATE, "a non-blocking solve is still running on this solver");
+    if (mg && mg_plan(mg) != s->plan) return set_error(TP_ERR_ARG, "the multigrid belongs to another plan");
+    s->mg = mg;
+    for (hipGraphExec_t& ex : s->exec)   // the captured iterations depend on the preconditioner
+        if (ex) (void)hipGraphExecDestroy(ex), ex = nullptr;
+    return TP_OK;
 }
 
 tp_status tp_pcg_destroy(tp_pcg* s) {

@@ -175,6 +175,38 @@ void endpoint_derivatives(int n, double* g0, double* g1) {
     }
 }
 
+// Embedding of a coarse cell's polynomial into its two children along one
+// axis: P_c[i][j] = l_j((x_i + c) / 2), coarse Lagrange function j at node i
+// of child c (left c = 0, right c = 1) in the parent's coordinates
+// (barycentric evaluation; a node that coincides with a coarse node gives a
+// unit row).
+void prolongation_1d(int n, double* P0, double* P1) {
+    std::vector<double> x(n), bw(n);
+    gll_points(n, x.data());
+    for (int j = 0; j < n; ++j) {
+        double prod = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (k != j) prod *= (x[j] - x[k]);
+        bw[j] = 1.0 / prod;
+    }
+    for (int c = 0; c < 2; ++c) {
+        double* P = c == 0 ? P0 : P1;
+        for (int i = 0; i < n; ++i) {
+            const double t = 0.5 * (x[i] + c);
+            int hit = -1;
+            for (int j = 0; j < n; ++j)
+                if (t == x[j]) hit = j;
+            if (hit >= 0) {
+                for (int j = 0; j < n; ++j) P[i * n + j] = j == hit ? 1.0 : 0.0;
+                continue;
+            }
+            double den = 0.0;
+            for (int j = 0; j < n; ++j) den += bw[j] / (t - x[j]);
+            for (int j = 0; j < n; ++j) P[i * n + j] = (bw[j] / (t - x[j])) / den;
+        }
+    }
+}
+
 // Generalized symmetric-definite eigenproblem P S = M S diag(lam).
 // Returns 0 on success, -1 when M is not SPD.
 int gen_eigen(int n, const double* M, const double* P, double* S, double* lam) {

@@ -43,6 +43,21 @@
 
 namespace tpfdm {
 
+// Device-side state of a PCG solve (pcg.hip; the multigrid kernels of a
+// solve read its done flag).  done: 0 running, 1 converged, 2 breakdown or
+// a non-finite scalar, 3 iteration limit.
+struct PcgState {
+    double rz, pq, rr, bb, alpha, beta, tol2;
+    int iter, done, maxit, pad;
+};
+
+// Sum of a double over the 64 lanes of a wave.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 struct MeshArgs {
     int64_t ncells;
     int64_t offset;

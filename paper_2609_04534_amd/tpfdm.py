@@ -37,6 +37,7 @@ EXPORTS = (
     "tp_last_error", "tp_version", "tp_solve_summary_fetch", "tp_graph_create", "tp_graph_launch",
     "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel", "tp_plan_create_mesh",
     "tp_pcg_create", "tp_pcg_solve", "tp_pcg_destroy", "tp_pcg_begin", "tp_pcg_poll",
+    "tp_mg_create", "tp_mg_vcycle", "tp_mg_destroy", "tp_pcg_set_multigrid",
 )
 KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
@@ -115,6 +116,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_pcg_destroy": (i32, [vp]),
         "tp_pcg_begin": (i32, [vp, vp, vp, i32, i32, dbl, i32, i32, vp]),
         "tp_pcg_poll": (i32, [vp, ctypes.POINTER(_PcgSummary)]),
+        "tp_mg_create": (i32, [vp, ctypes.POINTER(vp)]),
+        "tp_mg_vcycle": (i32, [vp, vp, vp, vp]),
+        "tp_mg_destroy": (i32, [vp]),
+        "tp_pcg_set_multigrid": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -382,6 +387,12 @@ class PCG:
         _check(load().tp_pcg_create(plan.handle, ctypes.byref(h)))
         self._h = h
         self.plan = plan
+        self.mg = None
+
+    def set_multigrid(self, mg: "MG | None"):
+        """Precondition later solves with one V-cycle of mg (None: block-Jacobi)."""
+        _check(load().tp_pcg_set_multigrid(self._h, mg.handle if mg is not None else None))
+        self.mg = mg
 
     def solve(self, b, x, x_is_zero: bool = True, inner: int = F64, rtol: float = 1e-8, maxit: int = 1000,
               check_every: int = 16, stream=None, raise_on_failure: bool = True) -> dict:
@@ -416,6 +427,41 @@ class PCG:
     def destroy(self):
         if self._h is not None:
             load().tp_pcg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+class MG:
+    """Multigrid V-cycle for the coupled SIPG system of a mesh plan (tp_mg_*)."""
+
+    def __init__(self, plan: "Plan"):
+        h = ctypes.c_void_p()
+        _check(load().tp_mg_create(plan.handle, ctypes.byref(h)))
+        self._h = h
+        self.plan = plan
+
+    @property
+    def handle(self):
+        return self._h
+
+    def vcycle(self, b, x, stream=None):
+        """x = V(b), blocked FP64 device vectors of the plan."""
+        _check(load().tp_mg_vcycle(self._h, _ptr(b), _ptr(x), _stream(stream)))
+
+    def destroy(self):
+        if self._h is not None:
+            load().tp_mg_destroy(self._h)
             self._h = None
 
     def __del__(self):

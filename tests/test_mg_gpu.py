@@ -1,0 +1,187 @@
+"""GPU parity of the multigrid V-cycle (tp_mg_*) and of CG preconditioned by
+it (tp_pcg_set_multigrid) against the oracle's hierarchy: the same levels,
+Chebyshev-accelerated block-Jacobi smoothing, embedding transfers and dense
+coarse solve in FP64, so the V-cycle agrees element by element up to
+rounding and MG-PCG takes the same number of iterations."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+
+from oracle import mg, sipg
+from paper_2609_04534_amd import tpfdm
+from tests.gpu_util import from_blocked, to_blocked
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _rhs(nd, seed):
+    return np.random.default_rng(seed).uniform(-1, 1, nd)
+
+
+_HIER = {}
+
+
+def _hierarchy(p, m):
+    if (p, m) not in _HIER:
+        _HIER[(p, m)] = mg.Hierarchy(p, m)
+    return _HIER[(p, m)]
+
+
+def _cube_plan(p, m):
+    plan = tpfdm.Plan.mesh(p + 1, (m, m, m), (1.0 / m,) * 3)
+    plan.setup_inverse(tpfdm.OP_CELL)
+    return plan
+
+
+# (p, m): levels m, m/2, ... down to the odd part of m (1 cell, or 3^3 cells)
+VCYCLE_CASES = [(1, 8), (2, 4), (2, 6), (3, 2), (3, 4), (3, 6), (1, 12)]
+
+
+@pytest.mark.parametrize("p,m", VCYCLE_CASES)
+def test_vcycle_matches_oracle(p, m):
+    torch = _torch()
+    H = _hierarchy(p, m)
+    nd = m ** 3 * (p + 1) ** 3
+    print(f"p={p} m={m} levels={H.ms}", flush=True)
+    for seed in (1, 2):
+        b = _rhs(nd, seed + 10 * m + p)
+        xo = H.vcycle(b)
+        with _cube_plan(p, m) as plan, tpfdm.MG(plan) as V:
+            bb = to_blocked(plan, b, tpfdm.F64)
+            bx = torch.full_like(bb, float("nan"))
+            V.vcycle(bb, bx)
+            x = from_blocked(plan, bx, tpfdm.F64)
+        scale = np.abs(xo).max()
+        err = np.abs(x - xo).max()
+        print(f"  seed={seed} max|x|={scale:.3e} max err={err:.3e}")
+        # FP64 on both sides, summation orders differ: a few hundred ulps of
+        # the solution's scale through a handful of smoothing sweeps
+        assert err <= 1e-11 * scale
+
+
+def test_vcycle_single_level_is_the_exact_solve():
+    """m odd: the finest level is the coarsest, and the V-cycle is A^{-1} b."""
+    torch = _torch()
+    p, m = 2, 3
+    A = sipg.assemble(p, (m,) * 3, (1.0 / m,) * 3)
+    b = _rhs(A.shape[0], 5)
+    xs = spl.spsolve(A.tocsc(), b)
+    with _cube_plan(p, m) as plan, tpfdm.MG(plan) as V:
+        bb = to_blocked(plan, b, tpfdm.F64)
+        bx = torch.empty_like(bb)
+        V.vcycle(bb, bx)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    assert np.abs(x - xs).max() <= 1e-10 * np.abs(xs).max()
+
+
+def test_vcycle_symmetric_on_a_box():
+    """A box that the oracle's cube hierarchy does not cover (cells 4 x 8 x 2,
+    unequal lengths): the V-cycle is a symmetric operator, (V a, c) = (a, V c),
+    and positive, (V a, a) > 0."""
+    torch = _torch()
+    n, cells, h = 3, (4, 8, 2), (0.25, 0.125, 0.4)
+    nd = 64 * n ** 3
+    a, c = _rhs(nd, 7), _rhs(nd, 8)
+    with tpfdm.Plan.mesh(n, cells, h) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
+        with tpfdm.MG(plan) as V:
+            out = []
+            for v in (a, c):
+                bv = to_blocked(plan, v, tpfdm.F64)
+                bx = torch.empty_like(bv)
+                V.vcycle(bv, bx)
+                out.append(from_blocked(plan, bx, tpfdm.F64))
+    Va, Vc = out
+    assert abs(Va @ c - a @ Vc) <= 1e-11 * np.linalg.norm(Va) * np.linalg.norm(c)
+    assert Va @ a > 0 and Vc @ c > 0
+
+
+MGPCG_CASES = [(1, 8), (2, 4), (2, 6), (3, 4), (1, 12)]
+
+
+@pytest.mark.parametrize("p,m", MGPCG_CASES)
+@pytest.mark.parametrize("inner", [tpfdm.F64, tpfdm.F32])
+def test_mg_pcg_matches_oracle(p, m, inner):
+    torch = _torch()
+    H = _hierarchy(p, m)
+    nd = m ** 3 * (p + 1) ** 3
+    b = _rhs(nd, 100 + m + p)
+    rtol = 1e-10
+    xo, ito, _ = sipg.pcg(H.A[0], b, H.vcycle, rtol, 200)
+    print(f"p={p} m={m} inner={tpfdm.DTYPE_NAMES[inner]} oracle_iters={ito}", flush=True)
+    with _cube_plan(p, m) as plan, tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+        solver.set_multigrid(V)
+        bb = to_blocked(plan, b, tpfdm.F64)
+        bx = torch.full_like(bb, float("nan"))
+        s = solver.solve(bb, bx, inner=inner, rtol=rtol, maxit=200, check_every=4)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    true_rel = np.linalg.norm(b - H.A[0] @ x) / np.linalg.norm(b)
+    print(f"  {s} true={true_rel:.2e}")
+    assert s["converged"] and s["relres"] <= rtol
+    assert true_rel <= 2 * rtol
+    if inner == tpfdm.F64:
+        assert abs(s["iterations"] - ito) <= 1
+        assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+    else:
+        # FP32 block inverse in the smoother: a slightly different
+        # preconditioner, still a few iterations
+        assert s["iterations"] <= ito + 3
+
+
+def test_mg_pcg_nonblocking_and_switching_back():
+    """begin/poll with the V-cycle gives the blocking solve's result bitwise;
+    resetting to block-Jacobi restores its own (larger) iteration count."""
+    torch = _torch()
+    p, m = 2, 4
+    nd = m ** 3 * (p + 1) ** 3
+    b = _rhs(nd, 3)
+    H = _hierarchy(p, m)
+    _, it_bj, _ = sipg.pcg(H.A[0], b, lambda r: sipg.block_jacobi(p, (m,) * 3, (1.0 / m,) * 3, r), 1e-9, 2000)
+    with _cube_plan(p, m) as plan, tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+        bb = to_blocked(plan, b, tpfdm.F64)
+        solver.set_multigrid(V)
+        x1 = torch.empty_like(bb)
+        s1 = solver.solve(bb, x1, rtol=1e-9, check_every=3)
+        x2 = torch.empty_like(bb)
+        solver.begin(bb, x2, rtol=1e-9, check_every=3)
+        s2 = None
+        while s2 is None:
+            s2 = solver.poll()
+        assert s1["iterations"] == s2["iterations"] and torch.equal(x1, x2)
+        solver.set_multigrid(None)
+        x3 = torch.empty_like(bb)
+        s3 = solver.solve(bb, x3, rtol=1e-9, maxit=2000)
+    assert abs(s3["iterations"] - it_bj) <= 1
+    assert s1["iterations"] < s3["iterations"] // 4
+
+
+def test_mg_errors():
+    torch = _torch()
+    # no cell inverse set up
+    with tpfdm.Plan.mesh(3, (4, 4, 4), (0.25,) * 3) as plan:
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            tpfdm.MG(plan)
+        assert e.value.status == -9
+    # coarsest level too large for the dense solve: 5^3 cells x 27
+    with _cube_plan(2, 5) as plan:
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            tpfdm.MG(plan)
+        assert e.value.status == -2
+    # n >= 5
+    with _cube_plan(5, 2) as plan:
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            tpfdm.MG(plan)
+        assert e.value.status == -2
+    # a multigrid of another plan
+    with _cube_plan(2, 2) as p1, _cube_plan(2, 2) as p2, tpfdm.MG(p1) as V, tpfdm.PCG(p2) as solver:
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            solver.set_multigrid(V)
+        assert e.value.status == -1
+        buf = torch.zeros(p1.vector_elems, dtype=torch.float64, device="cuda")
+        with pytest.raises(tpfdm.TpfdmError):
+            V.vcycle(buf, buf)
