@@ -428,14 +428,18 @@ def run_sipg(args, stream):
 # Serving meshes: unit cubes with m cells per side (the request mix of the
 # serving configuration), rtol 1e-8, FP64 outer iteration.
 PCG_SUITE = [(p, m) for p in (2, 3) for m in (8, 16, 24, 32, 48)] + [(7, m) for m in (8, 16, 24)]
+# Larger meshes timed with the multigrid preconditioner only (block-Jacobi
+# needs over a thousand iterations there).
+PCG_MG_ONLY = [(3, 64), (2, 96)]
 
 
 def run_pcg(args, stream):
-    """Per mesh and preconditioner precision: wall latency of whole solves
-    (launch to host summary), p50 / p99 over repeated solves, iterations."""
+    """Per mesh, preconditioner (block-Jacobi; one multigrid V-cycle for
+    p <= 3) and its precision: wall latency of whole solves (launch to host
+    summary), p50 / p99 over repeated solves, iterations."""
     import torch
     from paper_2609_04534_amd import tpfdm, workloads
-    for p, m in PCG_SUITE:
+    for p, m in PCG_SUITE + PCG_MG_ONLY:
         mesh = workloads.unit_cube_mesh(p, m, seed=7)
         plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h)
         plan.setup_inverse(tpfdm.OP_CELL)
@@ -443,23 +447,31 @@ def run_pcg(args, stream):
         plan.pack(torch.from_numpy(mesh.u).cuda(), b)
         x = torch.empty_like(b)
         solver = tpfdm.PCG(plan)
-        for inner in (tpfdm.F64, tpfdm.F32):
-            reps = 30 if m <= 24 else 10
-            lat, s = [], None
-            for i in range(reps + 2):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                s = solver.solve(b, x, inner=inner, rtol=1e-8, maxit=10000, stream=stream)
-                t1 = time.perf_counter()
-                if i >= 2:
-                    lat.append((t1 - t0) * 1e3)
-            p50 = float(np.percentile(lat, 50))
-            print(json.dumps({"workload": f"pcg_p{p}_{m}cube", "inner": tpfdm.DTYPE_NAMES[inner],
-                              "ndof": mesh.ndof, "iterations": s["iterations"], "relres": s["relres"],
-                              "p50_ms": p50, "p99_ms": float(np.percentile(lat, 99)),
-                              "ms_per_iteration": p50 / max(1, s["iterations"]),
-                              "solves_per_s": 1e3 / p50}), flush=True)
+        mg = tpfdm.MG(plan) if p <= 3 else None
+        preconds = ("mg",) if (p, m) in PCG_MG_ONLY else ("block_jacobi", "mg") if mg else ("block_jacobi",)
+        for precond in preconds:
+            solver.set_multigrid(mg if precond == "mg" else None)
+            for inner in (tpfdm.F64, tpfdm.F32):
+                reps = 30 if m <= 24 or (precond == "mg" and m <= 48) else 10
+                lat, s = [], None
+                for i in range(reps + 2):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    s = solver.solve(b, x, inner=inner, rtol=1e-8, maxit=10000,
+                                     check_every=4 if precond == "mg" else 16, stream=stream)
+                    t1 = time.perf_counter()
+                    if i >= 2:
+                        lat.append((t1 - t0) * 1e3)
+                p50 = float(np.percentile(lat, 50))
+                print(json.dumps({"workload": f"pcg_p{p}_{m}cube", "precond": precond,
+                                  "inner": tpfdm.DTYPE_NAMES[inner], "ndof": mesh.ndof,
+                                  "iterations": s["iterations"], "relres": s["relres"],
+                                  "p50_ms": p50, "p99_ms": float(np.percentile(lat, 99)),
+                                  "ms_per_iteration": p50 / max(1, s["iterations"]),
+                                  "solves_per_s": 1e3 / p50}), flush=True)
         solver.destroy()
+        if mg:
+            mg.destroy()
         plan.destroy()
         del b, x
         torch.cuda.empty_cache()
@@ -475,27 +487,30 @@ SERVE_MIX = [(p, m) for p in (2, 3) for m in (8, 16, 24, 32, 48)] + [(7, 8), (7,
 
 
 def run_serve(args):
+    """The serving mix at every rate, first with the V-cycle preconditioner
+    for p <= 3 (block-Jacobi for p = 7), then with block-Jacobi throughout."""
     import torch
     from paper_2609_04534_amd import serve, tpfdm
-    srv = serve.Server(hbm_budget=24 << 30, inner=tpfdm.F32, rtol=1e-8)
-    # warm start: plans, solver slots and their iteration graphs exist before
-    # the measured runs (one request of every class)
-    warm = [serve.poisson_requests(rate=1e6, count=1, mix=[c], seed=i)[0] for i, c in enumerate(SERVE_MIX)]
-    srv.run(warm)
-    del warm
-    for rate in SERVE_RATES:
-        count = int(min(120, max(20, rate * 1.0)))
-        reqs = serve.poisson_requests(rate=float(rate), count=count, mix=SERVE_MIX, seed=rate)
-        srv.max_concurrent = 0
-        done = srv.run(reqs)
-        st = serve.latency_stats(done)
-        st.update({"workload": "serve_pcg_mix", "rate_per_s": rate, "requests": count,
-                   "max_concurrent": srv.max_concurrent,
-                   "all_converged": all(r.summary.get("converged") for r in done)})
-        print(json.dumps(st), flush=True)
-        del reqs, done
-    srv.close()
-    torch.cuda.empty_cache()
+    for multigrid in (True, False):
+        srv = serve.Server(hbm_budget=24 << 30, inner=tpfdm.F32, rtol=1e-8, multigrid=multigrid)
+        # warm start: plans, solver slots and their iteration graphs exist
+        # before the measured runs (one request of every class)
+        warm = [serve.poisson_requests(rate=1e6, count=1, mix=[c], seed=i)[0] for i, c in enumerate(SERVE_MIX)]
+        srv.run(warm)
+        del warm
+        for rate in SERVE_RATES:
+            count = int(min(120, max(20, rate * 1.0)))
+            reqs = serve.poisson_requests(rate=float(rate), count=count, mix=SERVE_MIX, seed=rate)
+            srv.max_concurrent = 0
+            done = srv.run(reqs)
+            st = serve.latency_stats(done)
+            st.update({"workload": "serve_pcg_mix", "precond": "mg" if multigrid else "block_jacobi",
+                       "rate_per_s": rate, "requests": count, "max_concurrent": srv.max_concurrent,
+                       "all_converged": all(r.summary.get("converged") for r in done)})
+            print(json.dumps(st), flush=True)
+            del reqs, done
+        srv.close()
+        torch.cuda.empty_cache()
 
 
 def sipg_counters():

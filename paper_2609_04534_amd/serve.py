@@ -9,8 +9,10 @@ kernels of different solves overlap on the GPU.  A request is admitted (in
 arrival order) as soon as a solver slot for its mesh class is free or the
 device-memory budget has room for a new one; finished solves return their
 slot to a per-class free pool, and idle slots of other classes are released
-when a new class needs the memory.  Marshalling and scheduling only: every
-step of a solve runs in the library's kernels.
+when a new class needs the memory.  With multigrid on, the solves of degree
+p <= 3 are preconditioned by one V-cycle per iteration (tp_mg_*), the others
+by block-Jacobi.  Marshalling and scheduling only: every step of a solve runs
+in the library's kernels.
 """
 from __future__ import annotations
 
@@ -36,14 +38,20 @@ class Request:
 
 
 class _Slot:
-    """A solver and its blocked b, x buffers for one mesh class, on its own stream."""
+    """A solver and its blocked b, x buffers for one mesh class, on its own
+    stream; with multigrid, the slot's own V-cycle object (its level vectors
+    are scratch that concurrent solves must not share)."""
 
-    def __init__(self, plan, p, m):
+    def __init__(self, plan, p, m, multigrid):
         import torch
         self.plan = plan
         self.cls = (p, m)
         self.stream = torch.cuda.Stream()
         self.solver = tpfdm.PCG(plan)
+        self.mg = None
+        if multigrid:
+            self.mg = tpfdm.MG(plan)
+            self.solver.set_multigrid(self.mg)
         E = plan.vector_elems
         self.b = torch.empty(E, dtype=torch.float64, device="cuda")
         self.x = torch.empty(E, dtype=torch.float64, device="cuda")
@@ -51,20 +59,48 @@ class _Slot:
 
     def destroy(self):
         self.solver.destroy()
+        if self.mg is not None:
+            self.mg.destroy()
         self.b = self.x = None
 
 
-def slot_bytes(plan) -> int:
-    """Device memory of one slot: the solver's five vectors and partials plus b and x."""
+def uses_multigrid(p: int) -> bool:
+    """The V-cycle covers degrees with one cell per lane (p <= 3)."""
+    return p <= 3
+
+
+def mg_bytes(p: int, m: int) -> int:
+    """Device memory of a V-cycle object on an m^3 cube: a residual vector on
+    every level plus right-hand side and correction below the finest (the
+    shared coarse inverse is not counted)."""
+    n3 = (p + 1) ** 3
+    total, ml, first = 0, m, True
+    while True:
+        E = (ml ** 3 + 63) // 64 * 64 * n3
+        total += (1 if first else 3) * E * 8
+        first = False
+        if ml % 2:
+            break
+        ml //= 2
+    return total
+
+
+def slot_bytes(plan, p: int = None, m: int = None, multigrid: bool = False) -> int:
+    """Device memory of one slot: the solver's five vectors and partials plus
+    b and x, and the V-cycle's levels when it has one."""
     E = plan.vector_elems
     nwg = (plan.nblocks + 63) // 64
-    return 7 * E * 8 + 3 * nwg * 8 + 256
+    out = 7 * E * 8 + 3 * nwg * 8 + 256
+    if multigrid:
+        out += mg_bytes(p, m)
+    return out
 
 
 class Server:
     def __init__(self, hbm_budget: int, inner: int = tpfdm.F32, rtol: float = 1e-8, maxit: int = 20000,
-                 check_every: int = 8, max_inflight: int = 32):
+                 check_every: int = 8, max_inflight: int = 32, multigrid: bool = False):
         self.budget = int(hbm_budget)
+        self.multigrid = multigrid      # one V-cycle as the preconditioner where it applies
         self.max_inflight = max_inflight
         self.inner = inner
         self.rtol = rtol
@@ -90,16 +126,20 @@ class Server:
         key = (p, m)
         if self.free.get(key):
             return self.free[key].pop()
-        need = slot_bytes(self._plan(p, m))
+        mgc = self._mg(p)
+        need = slot_bytes(self._plan(p, m), p, m, mgc)
         for k in list(self.free):
             while self.used + need > self.budget and self.free[k]:
                 s = self.free[k].pop()
-                self.used -= slot_bytes(s.plan)
+                self.used -= slot_bytes(s.plan, *s.cls, s.mg is not None)
                 s.destroy()
         if self.used + need > self.budget:
             return None
         self.used += need
-        return _Slot(self._plan(p, m), p, m)
+        return _Slot(self._plan(p, m), p, m, mgc)
+
+    def _mg(self, p):
+        return self.multigrid and uses_multigrid(p)
 
     def _admit(self, req, now):
         if len(self.busy) >= self.max_inflight:
@@ -111,7 +151,7 @@ class Server:
         with torch.cuda.stream(s.stream):
             s.plan.pack(req.b, s.b, stream=s.stream)
         s.solver.begin(s.b, s.x, x_is_zero=True, inner=self.inner, rtol=self.rtol, maxit=self.maxit,
-                       check_every=self.check_every, stream=s.stream)
+                       check_every=4 if s.mg is not None else self.check_every, stream=s.stream)
         s.req = req
         req.start = now
         self.busy.append(s)

@@ -133,6 +133,36 @@ def test_mg_pcg_matches_oracle(p, m, inner):
         assert s["iterations"] <= ito + 3
 
 
+@pytest.mark.parametrize("p,m,inner", [(3, 64, tpfdm.F32), (2, 96, tpfdm.F64)])
+def test_mg_pcg_full_size_sampled_residual(p, m, inner):
+    """The largest meshes the solver is timed on (seven and six levels):
+    the iteration count stays in the range of the small cubes, the solver's
+    residual bound holds, and the oracle's true residual rows on sampled
+    cells (the eight corners and random ones) of the GPU solution are small
+    against b's scale."""
+    torch = _torch()
+    from paper_2609_04534_amd import workloads
+    mesh = workloads.unit_cube_mesh(p, m, seed=9)
+    print(f"p={p} m={m} inner={tpfdm.DTYPE_NAMES[inner]}", flush=True)
+    with _cube_plan(p, m) as plan, tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+        solver.set_multigrid(V)
+        bb = to_blocked(plan, mesh.u, tpfdm.F64)
+        bx = torch.empty_like(bb)
+        s = solver.solve(bb, bx, inner=inner, rtol=1e-8, maxit=100, check_every=4)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    print(f"  {s}")
+    assert s["converged"] and s["relres"] <= 1e-8
+    assert s["iterations"] <= 16
+    cells = (m,) * 3
+    corners = [sipg.cell_index(cells, a, b_, c) for a in (0, m - 1) for b_ in (0, m - 1) for c in (0, m - 1)]
+    rng = np.random.default_rng(2)
+    sample = sorted(set(corners + rng.choice(m ** 3, 24, replace=False).tolist()))
+    n3 = (p + 1) ** 3
+    Ax = sipg.cell_apply(p, cells, (1.0 / m,) * 3, x, sample)
+    rows = mesh.u.reshape(-1, n3)[sample] - Ax
+    assert np.linalg.norm(rows) <= 1e-7 * np.linalg.norm(mesh.u)
+
+
 def test_mg_pcg_nonblocking_and_switching_back():
     """begin/poll with the V-cycle gives the blocking solve's result bitwise;
     resetting to block-Jacobi restores its own (larger) iteration count."""

@@ -13,25 +13,30 @@ pytestmark = pytest.mark.gpu
 MIX = [(2, 4), (3, 4), (2, 6), (3, 6), (3, 8), (2, 8), (7, 3)]
 
 
-def _alone(req, inner):
+def _alone(req, inner, multigrid):
     import torch
     with tpfdm.Plan.mesh(req.p + 1, (req.m,) * 3, (1.0 / req.m,) * 3) as plan:
         plan.setup_inverse(tpfdm.OP_CELL)
         bb = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
         plan.pack(req.b, bb)
         bx = torch.empty_like(bb)
+        mg = tpfdm.MG(plan) if multigrid and serve.uses_multigrid(req.p) else None
         with tpfdm.PCG(plan) as solver:
-            s = solver.solve(bb, bx, inner=inner, rtol=1e-8, maxit=20000, check_every=8)
+            solver.set_multigrid(mg)
+            s = solver.solve(bb, bx, inner=inner, rtol=1e-8, maxit=20000, check_every=4 if mg else 8)
+        if mg:
+            mg.destroy()
         out = torch.empty(plan.ndof, dtype=torch.float64, device="cuda")
         plan.unpack(bx, out)
         torch.cuda.synchronize()
     return out.cpu().numpy(), s
 
 
+@pytest.mark.parametrize("multigrid", [False, True])
 @pytest.mark.parametrize("inner", [tpfdm.F64, tpfdm.F32])
-def test_each_result_is_the_same_alone_and_in_the_mix(inner):
+def test_each_result_is_the_same_alone_and_in_the_mix(inner, multigrid):
     reqs = serve.poisson_requests(rate=5000.0, count=14, mix=MIX, seed=inner + 1)
-    srv = serve.Server(hbm_budget=1 << 30, inner=inner, rtol=1e-8)
+    srv = serve.Server(hbm_budget=1 << 30, inner=inner, rtol=1e-8, multigrid=multigrid)
     try:
         done = srv.run(reqs)
     finally:
@@ -40,18 +45,19 @@ def test_each_result_is_the_same_alone_and_in_the_mix(inner):
     assert srv.max_concurrent >= 3          # the solves did overlap
     for r in done:
         assert r.summary["status"] == 0 and r.summary["converged"]
-        x_alone, s_alone = _alone(r, inner)
+        x_alone, s_alone = _alone(r, inner, multigrid)
         assert s_alone["iterations"] == r.summary["iterations"]
         # same kernels, same fixed-order reductions: identical bits
         assert np.array_equal(r.x.cpu().numpy(), x_alone), r.rid
 
 
-def test_admission_keeps_within_the_budget():
+@pytest.mark.parametrize("multigrid", [False, True])
+def test_admission_keeps_within_the_budget(multigrid):
     import torch
     reqs = serve.poisson_requests(rate=5000.0, count=8, mix=[(3, 8)], seed=4)
     with tpfdm.Plan.mesh(4, (8, 8, 8), (0.125,) * 3) as plan:
-        one = serve.slot_bytes(plan)
-    srv = serve.Server(hbm_budget=2 * one + one // 2, inner=tpfdm.F64)
+        one = serve.slot_bytes(plan, 3, 8, multigrid)
+    srv = serve.Server(hbm_budget=2 * one + one // 2, inner=tpfdm.F64, multigrid=multigrid)
     try:
         done = srv.run(reqs)
     finally:
@@ -63,9 +69,10 @@ def test_admission_keeps_within_the_budget():
     torch.cuda.synchronize()
 
 
-def test_served_solve_matches_direct_solution():
+@pytest.mark.parametrize("multigrid", [False, True])
+def test_served_solve_matches_direct_solution(multigrid):
     reqs = serve.poisson_requests(rate=1000.0, count=3, mix=[(2, 4), (3, 4)], seed=7)
-    srv = serve.Server(hbm_budget=1 << 28, inner=tpfdm.F64, rtol=1e-10)
+    srv = serve.Server(hbm_budget=1 << 28, inner=tpfdm.F64, rtol=1e-10, multigrid=multigrid)
     try:
         done = srv.run(reqs)
     finally:
