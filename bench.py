@@ -118,6 +118,8 @@ def main():
                     help="serve Poisson arrival streams of PCG solves at several rates (JSON lines)")
     ap.add_argument("--pcg", action="store_true",
                     help="time preconditioned-CG solves of the SIPG system on the serving mesh sizes (JSON lines)")
+    ap.add_argument("--pcg-mesh", default=None, metavar="P,M",
+                    help="with --pcg: only the unit cube of degree P with M cells per side")
     ap.add_argument("--sipg", action="store_true",
                     help="time only the coupled SIPG operator on the unit-cube meshes (JSON lines)")
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "f16", "bf16"],
@@ -439,7 +441,10 @@ def run_pcg(args, stream):
     summary), p50 / p99 over repeated solves, iterations."""
     import torch
     from paper_2609_04534_amd import tpfdm, workloads
-    for p, m in PCG_SUITE + PCG_MG_ONLY:
+    suite = PCG_SUITE + PCG_MG_ONLY
+    if args.pcg_mesh:
+        suite = [tuple(int(v) for v in args.pcg_mesh.split(","))]
+    for p, m in suite:
         mesh = workloads.unit_cube_mesh(p, m, seed=7)
         plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h)
         plan.setup_inverse(tpfdm.OP_CELL)

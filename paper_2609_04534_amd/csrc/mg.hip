@@ -10,9 +10,13 @@
 //   u <- u + omega_j D^{-1} (b - A u),  omega_j = 1 / (c - d cos((2j-1) pi / 6))
 // on the spectral interval [0.2, 2] (eq. (chebyshev_weights),
 // eq. (chebyshev_richardson)), with D^{-1} the cell-wise fast-diagonalization
-// inverse.  Transfers embed a coarse cell's polynomial into its eight
-// children (prolongation, accumulated into the fine correction) and apply
-// the transpose (restriction).  The coarsest level is solved exactly by a
+// inverse.  Each update is one kernel in the factorized form the paper
+// describes (Sec. 5.2): the operator row, the residual, the block inverse
+// and the update of the lane's cell in registers, so no residual vector is
+// written; the first update from u = 0 needs no operator.  Updates alternate
+// between the correction and one scratch vector per level.  Transfers embed
+// a coarse cell's polynomial into its eight children (prolongation, added
+// to the fine correction) and apply the transpose (restriction).  The coarsest level is solved exactly by a
 // dense inverse, assembled once by applying the level operator to unit
 // vectors (as the paper assembles its coarse LU) and inverted on the host.
 //
@@ -64,12 +68,12 @@ __global__ __launch_bounds__(64, 2) void k_mg_apply(const double* __restrict__ u
     }
 }
 
-// u <- u + omega D^{-1} (b - t) with t = A u, or u <- omega D^{-1} b when
-// init (u = 0); the block inverse in precision TI.
+// u = omega D^{-1} b: the first Chebyshev update from u = 0 (no operator
+// application), the block inverse in precision TI.
 template <int N, typename TI>
-__global__ __launch_bounds__(64, 2) void k_mg_jacobi(const double* __restrict__ b, const double* __restrict__ t,
-                                                   double* __restrict__ u, MeshArgs G, Eig<N, TI> E, double omega,
-                                                   int init, const PcgState* __restrict__ st) {
+__global__ __launch_bounds__(64, 2) void k_mg_jacobi0(const double* __restrict__ b, double* __restrict__ u,
+                                                    MeshArgs G, Eig<N, TI> E, double omega,
+                                                    const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
     const int64_t c = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
@@ -77,16 +81,38 @@ __global__ __launch_bounds__(64, 2) void k_mg_jacobi(const double* __restrict__ 
     const int64_t base = G.offset + block_base(c, 6, N3);
     TI v[N3];
 #pragma unroll
-    for (int e = 0; e < N3; ++e) {
-        const int64_t o = base + (static_cast<int64_t>(e) << 6);
-        v[e] = static_cast<TI>(init ? b[o] : b[o] - t[o]);
-    }
+    for (int e = 0; e < N3; ++e) v[e] = static_cast<TI>(b[base + (static_cast<int64_t>(e) << 6)]);
+    lane_fdm_inplace<N, TI>(v, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy), static_cast<TI>(G.sz));
+#pragma unroll
+    for (int e = 0; e < N3; ++e) u[base + (static_cast<int64_t>(e) << 6)] = omega * static_cast<double>(v[e]);
+}
+
+// One Chebyshev update in a single pass (the factorized form: no residual
+// vector is stored): u_out = u_in + omega D^{-1} (b - A u_in) for the lane's
+// cell, A u_in from the cell and its six neighbours, the block inverse in
+// precision TI on the residual registers.  u_out must not alias u_in (other
+// lanes still read u_in).
+template <int N, typename TI>
+__global__ __launch_bounds__(64, 2) void k_mg_smooth(const double* __restrict__ b, const double* __restrict__ uin,
+                                                   double* __restrict__ uout, MeshArgs G, Pair<N, double> R,
+                                                   FaceRef<N, double> F, Eig<N, TI> E, double omega,
+                                                   const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    constexpr int N3 = N * N * N;
+    __shared__ double sa[N * N][64], sbt[N * N][64];
+    const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
+    if (c >= G.ncells) return;
+    double acc[N3];
+    sipg_cell<N, double, double, -1>(uin, G, R, F, c, acc, sa, sbt);
+    const int64_t base = G.offset + block_base(c, 6, N3);
+    TI v[N3];
+#pragma unroll
+    for (int e = 0; e < N3; ++e) v[e] = static_cast<TI>(b[base + (static_cast<int64_t>(e) << 6)] - acc[e]);
     lane_fdm_inplace<N, TI>(v, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy), static_cast<TI>(G.sz));
 #pragma unroll
     for (int e = 0; e < N3; ++e) {
         const int64_t o = base + (static_cast<int64_t>(e) << 6);
-        const double d = omega * static_cast<double>(v[e]);
-        u[o] = init ? d : u[o] + d;
+        uout[o] = fma(omega, static_cast<double>(v[e]), uin[o]);
     }
 }
 
@@ -159,10 +185,11 @@ __global__ __launch_bounds__(64, 2) void k_mg_restrict(const double* __restrict_
     for (int e = 0; e < N3; ++e) bc[base + (static_cast<int64_t>(e) << 6)] = acc[e];
 }
 
-// u_fine += P u_coarse: one fine cell per lane, the child's embedding
+// u_out = u_fine + P u_coarse: one fine cell per lane, the child's embedding
 // selected per lane.
 template <int N>
-__global__ __launch_bounds__(64, 2) void k_mg_prolong(const double* __restrict__ uc, double* __restrict__ uf,
+__global__ __launch_bounds__(64, 2) void k_mg_prolong(const double* __restrict__ uc, const double* __restrict__ uf,
+                                                    double* __restrict__ uout,
                                                     MeshArgs Gf, MeshArgs Gc, ProlTab<N> P,
                                                     const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -191,7 +218,7 @@ __global__ __launch_bounds__(64, 2) void k_mg_prolong(const double* __restrict__
 #pragma unroll
     for (int e = 0; e < N3; ++e) {
         const int64_t o = base + (static_cast<int64_t>(e) << 6);
-        uf[o] += acc[e];
+        uout[o] = uf[o] + acc[e];
     }
 }
 
@@ -339,19 +366,15 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const double* b, double* u, con
     for (int c = 0; c < 2; ++c)
         for (int i = 0; i < N; ++i)
             for (int j = 0; j < N; ++j) PT.p[c][i * N + j] = P.p[c][j * N + i];
-    auto smooth = [&](bool from_zero) {
-        for (int j = 0; j < 3; ++j) {
-            if (from_zero && j == 0) {
-                hipLaunchKernelGGL((k_mg_jacobi<N, TI>), dim3(grid), dim3(64), 0, s, b, L.t, u, L.G, E, m->omega[0], 1,
-                                   st);
-                continue;
-            }
-            hipLaunchKernelGGL((k_mg_apply<N>), dim3(grid), dim3(64), 0, s, u, L.t, L.G, R, F, st);
-            hipLaunchKernelGGL((k_mg_jacobi<N, TI>), dim3(grid), dim3(64), 0, s, b, L.t, u, L.G, E, m->omega[j], 0,
-                               st);
-        }
+    // Chebyshev updates ping-pong between u and the level's scratch t; the
+    // prolongation writes out of place so that the last update lands in u.
+    auto step = [&](const double* from, double* to, int j) {
+        hipLaunchKernelGGL((k_mg_smooth<N, TI>), dim3(grid), dim3(64), 0, s, b, from, to, L.G, R, F, E, m->omega[j],
+                           st);
     };
-    smooth(true);
+    hipLaunchKernelGGL((k_mg_jacobi0<N, TI>), dim3(grid), dim3(64), 0, s, b, u, L.G, E, m->omega[0], st);
+    step(u, L.t, 1);
+    step(L.t, u, 2);
     const MgLevel& C = m->lv[l + 1];
     hipLaunchKernelGGL((k_mg_apply<N>), dim3(grid), dim3(64), 0, s, u, L.t, L.G, R, F, st);
     hipLaunchKernelGGL((k_mg_restrict<N>), dim3(static_cast<unsigned>((C.G.ncells + 63) / 64)), dim3(64), 0, s, b,
@@ -360,8 +383,10 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const double* b, double* u, con
     if (stt != TP_OK) return stt;
     stt = vcycle_level<N, TI>(m, l + 1, C.b, C.u, st, s);
     if (stt != TP_OK) return stt;
-    hipLaunchKernelGGL((k_mg_prolong<N>), dim3(grid), dim3(64), 0, s, C.u, u, L.G, C.G, P, st);
-    smooth(false);
+    hipLaunchKernelGGL((k_mg_prolong<N>), dim3(grid), dim3(64), 0, s, C.u, u, L.t, L.G, C.G, P, st);
+    step(L.t, u, 0);
+    step(u, L.t, 1);
+    step(L.t, u, 2);
     return check_launch("smoothing");
 }
 
