@@ -19,6 +19,10 @@ on GPUs", arXiv 2609.04534):
   Cartesian box mesh with Nitsche (homogeneous Dirichlet) boundary faces,
   A = A^vol + A^face of eq. (operator_split), assembled as a sparse matrix
   from dense cell-row blocks built from the bilinear form.
+* ``hermite`` -- the Hermite-type 1D basis of Sec. 3.1 (eq. (hermite_conditions))
+  with its mass and stiffness matrices, endpoint data, change of basis to the
+  Lagrange basis and level transfers; ``sipg`` and ``mg`` take the basis as a
+  parameter (``bname``).
 * ``mg``     -- geometric multigrid for it: Chebyshev-accelerated
   block-Jacobi smoothing (eq. (chebyshev_weights), eq. (chebyshev_richardson)),
   polynomial-embedding transfers, a dense coarse solve, CG preconditioned by

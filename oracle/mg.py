@@ -34,7 +34,7 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-from . import basis, sipg
+from . import basis, hermite, sipg
 
 INTERVAL = (0.2, 2.0)
 
@@ -54,18 +54,21 @@ def levels(m: int):
     return out
 
 
-def prolongation_1d(p: int):
+def prolongation_1d(p: int, bname: str = sipg.LAGRANGE):
     """(P_0, P_1): P_c[i, j] = l_j((x_i + c) / 2), the coarse basis function j
     at node i of child c (left c = 0, right c = 1) in the parent's
-    coordinates."""
+    coordinates; in the Hermite-type basis the child's coefficients of the
+    same function."""
+    if bname == sipg.HERMITE:
+        return hermite.prolongation_1d(p)
     x = basis.gll_nodes(p)
     return tuple(basis.lagrange_values(x, (x + c) / 2.0) for c in (0, 1))
 
 
-def prolongation(p: int, mc: int) -> sp.csr_matrix:
+def prolongation(p: int, mc: int, bname: str = sipg.LAGRANGE) -> sp.csr_matrix:
     """Fine (2 mc cells per side) <- coarse (mc) embedding, canonical orders."""
     n3 = (p + 1) ** 3
-    P1 = prolongation_1d(p)
+    P1 = prolongation_1d(p, bname)
     mf = 2 * mc
     rows, cols, vals = [], [], []
     li = np.repeat(np.arange(n3), n3)
@@ -85,11 +88,12 @@ def prolongation(p: int, mc: int) -> sp.csr_matrix:
 class Hierarchy:
     """Level operators, transfers and the coarse inverse of a unit cube."""
 
-    def __init__(self, p: int, m: int, C: float = 2.0):
+    def __init__(self, p: int, m: int, C: float = 2.0, bname: str = sipg.LAGRANGE):
         self.p = p
+        self.bname = bname
         self.ms = levels(m)
-        self.A = [sipg.assemble(p, (ml,) * 3, (1.0 / ml,) * 3, sipg.FULL, C) for ml in self.ms]
-        self.P = [prolongation(p, self.ms[k + 1]) for k in range(len(self.ms) - 1)]
+        self.A = [sipg.assemble(p, (ml,) * 3, (1.0 / ml,) * 3, sipg.FULL, C, bname) for ml in self.ms]
+        self.P = [prolongation(p, self.ms[k + 1], bname) for k in range(len(self.ms) - 1)]
         self.coarse = np.linalg.inv(self.A[-1].toarray())
         self.omega = chebyshev_weights()
         self.C = C
@@ -98,7 +102,7 @@ class Hierarchy:
         """One Chebyshev application (three Richardson updates) on level k."""
         ml = self.ms[k]
         for w in self.omega:
-            u = u + w * sipg.block_jacobi(self.p, (ml,) * 3, (1.0 / ml,) * 3, b - self.A[k] @ u, self.C)
+            u = u + w * sipg.block_jacobi(self.p, (ml,) * 3, (1.0 / ml,) * 3, b - self.A[k] @ u, self.C, self.bname)
         return u
 
     def vcycle(self, b, k: int = 0):
@@ -111,8 +115,8 @@ class Hierarchy:
         return self.smooth(k, u, b)
 
 
-def mg_pcg(p: int, m: int, b, rtol: float, maxit: int = 200):
+def mg_pcg(p: int, m: int, b, rtol: float, maxit: int = 200, bname: str = sipg.LAGRANGE):
     """CG on the finest level preconditioned by one V-cycle; returns
     (x, iterations, relative residual)."""
-    H = Hierarchy(p, m)
+    H = Hierarchy(p, m, bname=bname)
     return sipg.pcg(H.A[0], b, H.vcycle, rtol, maxit)

@@ -19,6 +19,11 @@ Paper passages followed:
   tangential slots; eq. (face_coupling) gives N^{--}.
 * Sec. 6.2: sigma_F = C p (p+1) / h_F with h_F the cell length normal to F.
 
+Basis: every function takes ``bname``, the 1D basis of each cell's
+coefficients: the Lagrange basis on the Gauss-Lobatto nodes (default) or the
+Hermite-type basis of Sec. 3.1 (``hermite``); the operator is assembled from
+that basis' own mass and stiffness matrices and endpoint vectors.
+
 Mesh: mx x my x mz cells, all with edge lengths (hx, hy, hz).  Cell
 (cx, cy, cz) has index c = (cx my + cy) mz + cz and its DoFs are the global
 unknowns c n^3 + q with the block-local q = (ix n + iy) n + iz.
@@ -42,7 +47,10 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from . import basis, dense
+from . import basis, dense, hermite
+
+LAGRANGE = "lagrange"   # Lagrange basis on the Gauss-Lobatto nodes
+HERMITE = "hermite"     # the Hermite-type basis of Sec. 3.1 (p >= 3)
 
 FULL = "full"       # A = A^vol + A^face
 VOLUME = "volume"   # A^vol: the cell integrals only (the Neumann volume operator per cell)
@@ -60,7 +68,18 @@ def cell_coords(m, c):
     return cx, cy, cz
 
 
-def _side_data(p: int, hd: float, side: str):
+def ref_data(p: int, bname: str = LAGRANGE):
+    """(M_hat, K_hat, (e0, g0, e1, g1)) of the 1D basis."""
+    if bname == LAGRANGE:
+        M, K = basis.mass_stiffness(p)
+        return M, K, basis.endpoint_vectors(p)
+    if bname == HERMITE:
+        M, K = hermite.mass_stiffness(p)
+        return M, K, hermite.endpoint_vectors(p)
+    raise ValueError(f"unknown basis {bname!r}")
+
+
+def _side_data(p: int, hd: float, side: str, bname: str = LAGRANGE):
     """(trace row, normal-derivative row, jump sign, average weight) of one
     side of a face normal to an axis, with the normal pointing along +axis.
 
@@ -71,7 +90,7 @@ def _side_data(p: int, hd: float, side: str):
     Interior averages weigh each side by 1/2; on a boundary face the inner
     side carries the whole average.
     """
-    e0, g0, e1, g1 = basis.endpoint_vectors(p)
+    e0, g0, e1, g1 = ref_data(p, bname)[2]
     if side in ("-", "b-"):
         t, d, j = e1, g1 / hd, 1.0
     else:
@@ -79,7 +98,8 @@ def _side_data(p: int, hd: float, side: str):
     return t, d, j, (0.5 if side in ("-", "+") else 1.0)
 
 
-def face_matrix(p: int, hd: float, test_side: str, trial_side: str, C: float = 2.0) -> np.ndarray:
+def face_matrix(p: int, hd: float, test_side: str, trial_side: str, C: float = 2.0,
+                bname: str = LAGRANGE) -> np.ndarray:
     """1D face matrix N[i, j] of eq. (sipg) restricted to the normal direction:
     test function i on test_side, trial function j on trial_side,
 
@@ -87,30 +107,31 @@ def face_matrix(p: int, hd: float, test_side: str, trial_side: str, C: float = 2
           + sigma (jump trial) (jump test),  sigma = C p (p+1) / hd.
     """
     sigma = basis.penalty_reference(p, C) / hd
-    ti, di, ji, ai = _side_data(p, hd, test_side)
-    tj, dj, jj, aj = _side_data(p, hd, trial_side)
+    ti, di, ji, ai = _side_data(p, hd, test_side, bname)
+    tj, dj, jj, aj = _side_data(p, hd, trial_side, bname)
     return (-np.outer(ji * ti, aj * dj) - np.outer(ai * di, jj * tj)
             + sigma * np.outer(ji * ti, jj * tj))
 
 
-def _slot_kron(p, h, d, N1):
+def _slot_kron(p, h, d, N1, bname=LAGRANGE):
     """Kronecker product with N1 in slot d and the physical mass h_o M_hat in
     the other two slots (eq. (face_factorized))."""
-    M, _ = basis.mass_stiffness(p)
+    M = ref_data(p, bname)[0]
     f = [h[o] * M for o in range(3)]
     f[d] = N1
     return np.kron(np.kron(f[0], f[1]), f[2])
 
 
-def cell_row_blocks(p: int, m, h, c: int, part: str = FULL, C: float = 2.0):
+def cell_row_blocks(p: int, m, h, c: int, part: str = FULL, C: float = 2.0, bname: str = LAGRANGE):
     """The blocks of cell c's row of A: a list of (neighbour cell, n^3 x n^3
     block), the cell itself first."""
     h = [float(x) for x in h]
     n3 = (p + 1) ** 3
     diag = np.zeros((n3, n3))
     off = []
+    M, K, _ = ref_data(p, bname)
     if part in (FULL, VOLUME):
-        diag += dense.dense_operator(p, h, dense.NEUMANN)
+        diag += dense.kronecker_sum([(hd * M, K / hd) for hd in h])
     if part in (FULL, FACE):
         cc = list(cell_coords(m, c))
         for d in range(3):
@@ -118,22 +139,22 @@ def cell_row_blocks(p: int, m, h, c: int, part: str = FULL, C: float = 2.0):
             if cc[d] + 1 < m[d]:
                 nb = cc.copy()
                 nb[d] += 1
-                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "-", "-", C))
-                off.append((cell_index(m, *nb), _slot_kron(p, h, d, face_matrix(p, h[d], "-", "+", C))))
+                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "-", "-", C, bname), bname)
+                off.append((cell_index(m, *nb), _slot_kron(p, h, d, face_matrix(p, h[d], "-", "+", C, bname), bname)))
             else:
-                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "b-", "b-", C))
+                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "b-", "b-", C, bname), bname)
             # left end
             if cc[d] > 0:
                 nb = cc.copy()
                 nb[d] -= 1
-                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "+", "+", C))
-                off.append((cell_index(m, *nb), _slot_kron(p, h, d, face_matrix(p, h[d], "+", "-", C))))
+                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "+", "+", C, bname), bname)
+                off.append((cell_index(m, *nb), _slot_kron(p, h, d, face_matrix(p, h[d], "+", "-", C, bname), bname)))
             else:
-                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "b+", "b+", C))
+                diag += _slot_kron(p, h, d, face_matrix(p, h[d], "b+", "b+", C, bname), bname)
     return [(c, diag)] + off
 
 
-def assemble(p: int, m, h, part: str = FULL, C: float = 2.0) -> sp.csr_matrix:
+def assemble(p: int, m, h, part: str = FULL, C: float = 2.0, bname: str = LAGRANGE) -> sp.csr_matrix:
     """The global operator (or its volume or face part) as a sparse matrix."""
     n3 = (p + 1) ** 3
     ncell = int(m[0] * m[1] * m[2])
@@ -141,7 +162,7 @@ def assemble(p: int, m, h, part: str = FULL, C: float = 2.0) -> sp.csr_matrix:
     li = np.repeat(np.arange(n3), n3)
     lj = np.tile(np.arange(n3), n3)
     for c in range(ncell):
-        for nb, blk in cell_row_blocks(p, m, h, c, part, C):
+        for nb, blk in cell_row_blocks(p, m, h, c, part, C, bname):
             rows.append(c * n3 + li)
             cols.append(nb * n3 + lj)
             vals.append(blk.reshape(-1))
@@ -150,12 +171,12 @@ def assemble(p: int, m, h, part: str = FULL, C: float = 2.0) -> sp.csr_matrix:
     return A.tocsr()
 
 
-def apply(p: int, m, h, u, part: str = FULL, C: float = 2.0) -> np.ndarray:
+def apply(p: int, m, h, u, part: str = FULL, C: float = 2.0, bname: str = LAGRANGE) -> np.ndarray:
     """v = A u for a canonical vector u of ncells * n^3 values."""
-    return assemble(p, m, h, part, C) @ np.asarray(u, dtype=np.float64)
+    return assemble(p, m, h, part, C, bname) @ np.asarray(u, dtype=np.float64)
 
 
-def cell_apply(p: int, m, h, u, cells, part: str = FULL, C: float = 2.0) -> np.ndarray:
+def cell_apply(p: int, m, h, u, cells, part: str = FULL, C: float = 2.0, bname: str = LAGRANGE) -> np.ndarray:
     """(A u) restricted to the given cells, from their row blocks only (for
     meshes too large to assemble): u is the canonical vector, returns
     (len(cells), n^3)."""
@@ -163,25 +184,36 @@ def cell_apply(p: int, m, h, u, cells, part: str = FULL, C: float = 2.0) -> np.n
     u = np.asarray(u, dtype=np.float64).reshape(-1, n3)
     out = np.zeros((len(cells), n3))
     for r, c in enumerate(cells):
-        for nb, blk in cell_row_blocks(p, m, h, int(c), part, C):
+        for nb, blk in cell_row_blocks(p, m, h, int(c), part, C, bname):
             out[r] += blk @ u[nb]
     return out
 
 
-def mass(p: int, m, h) -> sp.csr_matrix:
+def mass(p: int, m, h, bname: str = LAGRANGE) -> sp.csr_matrix:
     """Global (block-diagonal) mass matrix."""
     ncell = int(m[0] * m[1] * m[2])
-    return sp.block_diag([dense.dense_mass(p, h)] * ncell, format="csr")
+    M = ref_data(p, bname)[0]
+    Mc = np.kron(np.kron(h[0] * M, h[1] * M), h[2] * M)
+    return sp.block_diag([Mc] * ncell, format="csr")
 
 
-def block_jacobi(p: int, m, h, r, C: float = 2.0) -> np.ndarray:
+def cell_block(p: int, h, C: float = 2.0, bname: str = LAGRANGE) -> np.ndarray:
+    """The cell block of eq. (cell_block): the Kronecker sum of (h_d M_hat,
+    A_hat / h_d), A_hat = K_hat + the own-side blocks of both faces."""
+    M, K, (e0, g0, e1, g1) = ref_data(p, bname)
+    N = basis.face_blocks(e0, g0, e1, g1, basis.penalty_reference(p, C))
+    A = K + N["--"] + N["++"]
+    return dense.kronecker_sum([(float(hd) * M, A / float(hd)) for hd in h])
+
+
+def block_jacobi(p: int, m, h, r, C: float = 2.0, bname: str = LAGRANGE) -> np.ndarray:
     """z = D^{-1} r with D the cell-diagonal blocks of Sec. 5.2: the cell block
     of eq. (cell_block) on every cell, boundary cells included (the paper
     keeps the interior stencil there), each solved densely."""
     n3 = (p + 1) ** 3
     ncell = int(m[0] * m[1] * m[2])
     r = np.asarray(r, dtype=np.float64).reshape(ncell, n3)
-    D = dense.dense_operator(p, h, dense.CELL, C)
+    D = cell_block(p, h, C, bname)
     return np.linalg.solve(D, r.T).T.reshape(-1)
 
 

@@ -104,30 +104,30 @@ _ORIG_FACE_MATRIX = sipg.face_matrix
 _ORIG_CELL_INDEX = sipg.cell_index
 
 
-def _half_boundary_average(p, hd, side):
-    t, d, j, a = _ORIG_SIDE(p, hd, side)
+def _half_boundary_average(p, hd, side, bname=sipg.LAGRANGE):
+    t, d, j, a = _ORIG_SIDE(p, hd, side, bname)
     return t, d, j, 0.5                        # boundary average weighted like an interior one
 
 
-def _flipped_coupling_penalty(p, hd, test_side, trial_side, C=2.0):
-    N = _ORIG_FACE_MATRIX(p, hd, test_side, trial_side, C)
+def _flipped_coupling_penalty(p, hd, test_side, trial_side, C=2.0, bname=sipg.LAGRANGE):
+    N = _ORIG_FACE_MATRIX(p, hd, test_side, trial_side, C, bname)
     if test_side != trial_side and "b" not in test_side:
-        ti, _, ji, _ = _ORIG_SIDE(p, hd, test_side)
-        tj, _, jj, _ = _ORIG_SIDE(p, hd, trial_side)
+        ti, _, ji, _ = _ORIG_SIDE(p, hd, test_side, bname)
+        tj, _, jj, _ = _ORIG_SIDE(p, hd, trial_side, bname)
         sigma = basis.penalty_reference(p, C) / hd
         N = N - 2 * sigma * np.outer(ji * ti, jj * tj)
     return N
 
 
-def _no_boundary_penalty(p, hd, test_side, trial_side, C=2.0):
+def _no_boundary_penalty(p, hd, test_side, trial_side, C=2.0, bname=sipg.LAGRANGE):
     if "b" in test_side:
-        return _ORIG_FACE_MATRIX(p, hd, test_side, trial_side, 0.0)
-    return _ORIG_FACE_MATRIX(p, hd, test_side, trial_side, C)
+        return _ORIG_FACE_MATRIX(p, hd, test_side, trial_side, 0.0, bname)
+    return _ORIG_FACE_MATRIX(p, hd, test_side, trial_side, C, bname)
 
 
-def _one_sided_symmetry_term(p, hd, test_side, trial_side, C=2.0):
-    ti, di, ji, ai = _ORIG_SIDE(p, hd, test_side)
-    tj, dj, jj, aj = _ORIG_SIDE(p, hd, trial_side)
+def _one_sided_symmetry_term(p, hd, test_side, trial_side, C=2.0, bname=sipg.LAGRANGE):
+    ti, di, ji, ai = _ORIG_SIDE(p, hd, test_side, bname)
+    tj, dj, jj, aj = _ORIG_SIDE(p, hd, trial_side, bname)
     sigma = basis.penalty_reference(p, C) / hd
     return -np.outer(ji * ti, aj * dj) + sigma * np.outer(ji * ti, jj * tj)   # [u]{d_n v} dropped
 
@@ -136,8 +136,8 @@ def _transposed_cell_index(m, cx, cy, cz):
     return (cx * m[2] + cz) * m[1] + cy         # y and z strides exchanged
 
 
-def _tangential_mass_of_normal_length(p, h, d, N1):
-    M, _ = basis.mass_stiffness(p)
+def _tangential_mass_of_normal_length(p, h, d, N1, bname=sipg.LAGRANGE):
+    M = sipg.ref_data(p, bname)[0]
     f = [h[d] * M for _ in range(3)]
     f[d] = N1
     return np.kron(np.kron(f[0], f[1]), f[2])
@@ -178,8 +178,8 @@ _ORIG_P1D = mg.prolongation_1d
 _ORIG_W = mg.chebyshev_weights
 
 
-def _swapped_children(p):
-    P0, P1 = _ORIG_P1D(p)
+def _swapped_children(p, bname=sipg.LAGRANGE):
+    P0, P1 = _ORIG_P1D(p, bname)
     return P1, P0
 
 
@@ -208,3 +208,58 @@ def test_planted_mg_mistake_is_caught(monkeypatch, target, replacement):
 
 def test_unmutated_mg_suite_passes():
     assert not _run_all(MG_PIN_SUITE)
+
+
+# ---------------------------------------------------------------- Hermite-type basis
+import tests.test_oracle_hermite as hpins  # noqa: E402
+from oracle import hermite  # noqa: E402
+
+_ORIG_MONOMIALS = hermite.monomials
+_ORIG_ENDPOINTS = hermite.endpoint_vectors
+
+
+def _flipped_right_derivative(p):
+    C = _ORIG_MONOMIALS(p).copy()
+    C[:, p - 1] = -C[:, p - 1]                  # psi_{p-1}'(1) = -1 (outward instead of +x)
+    return C
+
+
+def _single_bubble(p):
+    C = _ORIG_MONOMIALS(p).copy()
+    if p >= 4:                                  # interior function x (1-x): nonzero end derivatives
+        C[:, 2] = 0.0
+        C[:3, 2] = [0.0, 1.0, -1.0]
+    return C
+
+
+def _uniform_nodes_transform(p):
+    return hermite.values(p, np.linspace(0.0, 1.0, p + 1))
+
+
+def _swapped_derivative_ends(p):
+    e0, g0, e1, g1 = _ORIG_ENDPOINTS(p)
+    return e0, g1, e1, g0
+
+
+HERMITE_PIN_SUITE = [
+    lambda: hpins.test_endpoint_conditions(4),
+    lambda: hpins.test_mass_and_stiffness_two_routes(4),
+    lambda: hpins.test_face_stencil_on_the_two_layers(3),
+    lambda: hpins.test_assembled_operator_two_routes(3, (3, 2, 4), (0.3, 0.5, 0.25), sipg.FULL),
+]
+
+
+@pytest.mark.parametrize("target,replacement", [
+    ((hermite, "monomials"), _flipped_right_derivative),
+    ((hermite, "monomials"), _single_bubble),
+    ((hermite, "transform"), _uniform_nodes_transform),
+    ((hermite, "endpoint_vectors"), _swapped_derivative_ends),
+])
+def test_planted_hermite_mistake_is_caught(monkeypatch, target, replacement):
+    mod, name = target
+    monkeypatch.setattr(mod, name, replacement)
+    assert _run_all(HERMITE_PIN_SUITE), f"no pin caught the mutation of {mod.__name__}.{name}"
+
+
+def test_unmutated_hermite_suite_passes():
+    assert not _run_all(HERMITE_PIN_SUITE)
