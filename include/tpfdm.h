@@ -154,11 +154,26 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups,
  * length normal to the face, Sec. 6.2).  Cell (cx, cy, cz) is block
  * c = (cx cells[1] + cy) cells[2] + cz of the plan's single group, so the B
  * cells of a layout tile are consecutive along z. */
+/* The 1D basis of every cell's coefficients (Sec. 3.1).
+ * LAGRANGE: Lagrange polynomials on the n Gauss-Lobatto points of [0, 1]
+ *   (coefficients = nodal values).
+ * HERMITE: the Hermite-type basis of eq. (hermite_conditions), mesh plans
+ *   with n = 4 (p = 3) only (TP_ERR_UNSUPPORTED otherwise, and with
+ *   TP_MAP_WAVE): coefficient 0 is the value and 1 the derivative at 0,
+ *   n-2 the derivative and n-1 the value at 1, so a face term reads two
+ *   layers of the neighbour (eq. (hermite_traces_3d)).  The endpoint
+ *   functions are the cubic Hermite polynomials.  Every operator, inverse,
+ *   solve, PCG and multigrid call acts on coefficients in this basis (the
+ *   same discrete space and operator: A_H = T3^T A_L T3 with T3 = T (x) T
+ *   (x) T cell by cell, T[i][j] = psi_j(x_i)); tp_change_basis converts
+ *   to and from nodal values. */
+typedef enum { TP_BASIS_LAGRANGE = 0, TP_BASIS_HERMITE = 1 } tp_basis;
+
 typedef struct {
     int32_t n;            /* points per direction, 2 <= n <= 8                          */
     int32_t layout_B;     /* interleave width, a power of two <= 1024                    */
     int32_t cells[3];     /* cells per direction (x, y, z), each >= 1, product < 2^31    */
-    int32_t reserved;     /* must be zero                                               */
+    int32_t basis;        /* tp_basis (0: Lagrange)                                      */
     double h[3];          /* cell edge lengths (x, y, z), finite and > 0                 */
 } tp_mesh;
 
@@ -369,6 +384,16 @@ tp_status tp_mg_create(tp_plan* plan, tp_mg** out);
 tp_status tp_mg_vcycle(tp_mg* mg, const double* b, double* x, hipStream_t stream);
 tp_status tp_mg_destroy(tp_mg* mg);
 tp_status tp_pcg_set_multigrid(tp_pcg* pcg, tp_mg* mg);
+
+/* Change of basis of a mesh plan's vectors (Sec. 3.1: the fixed n x n
+ * matrix T per direction, used when interfacing with nodal data):
+ * to_nodal = 1: v = (T (x) T (x) T) u cell by cell (Hermite coefficients to
+ * nodal values); to_nodal = 0: v = (T^{-1} (x) T^{-1} (x) T^{-1}) u.  u, v:
+ * distinct FP64 device vectors in the plan's layout (padding lanes are not
+ * written).  On a Lagrange plan T = I and v is a copy of u.  Errors:
+ * TP_ERR_ARG (null, aliasing, to_nodal not 0/1), TP_ERR_UNSUPPORTED (not a
+ * mesh plan). */
+tp_status tp_change_basis(tp_plan* plan, int32_t to_nodal, const double* u, double* v, hipStream_t stream);
 
 /* Number of blocks in the plan (sum over groups). */
 int64_t tp_plan_nblocks(const tp_plan* plan);

@@ -315,7 +315,52 @@ tp_status tp_reference_eigen(int32_t n, double penalty_C, tp_operator op, double
     return TP_OK;
 }
 
-tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opts* opts, tp_plan** out) {
+}  // extern "C"
+
+namespace {
+tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opts* opts, int basis, tp_plan** out);
+
+// Reference data of the Hermite-type basis from the Lagrange data already
+// in r: the same bilinear forms in the new basis (M, K, A <- T^T X T), the
+// endpoint derivatives g <- T^T g, the child embeddings P_c <- T^{-1} P_c T.
+tp_status hermite_reference(int n, RefData& r) {
+    hermite_transform(n, r.T);
+    if (!invert_small(n, r.T, r.Ti)) return set_error(TP_ERR_NOT_SPD, "Hermite basis change is singular");
+    congruence(n, r.T, r.M);
+    congruence(n, r.T, r.K);
+    congruence(n, r.T, r.A);
+    double g0[kMaxN], g1[kMaxN];
+    for (int j = 0; j < n; ++j) {
+        g0[j] = g1[j] = 0.0;
+        for (int i = 0; i < n; ++i) g0[j] += r.T[i * n + j] * r.g0[i], g1[j] += r.T[i * n + j] * r.g1[i];
+    }
+    for (int j = 0; j < n; ++j) r.g0[j] = g0[j], r.g1[j] = g1[j];
+    for (double* P : {r.P0, r.P1}) {
+        double Y[kMaxN * kMaxN];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += P[i * n + k] * r.T[k * n + j];
+                Y[i * n + j] = s;
+            }
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += r.Ti[i * n + k] * Y[k * n + j];
+                P[i * n + j] = s;
+            }
+    }
+    return TP_OK;
+}
+}  // namespace
+
+extern "C" tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opts* opts,
+                                    tp_plan** out) {
+    return plan_create(groups, ngroups, opts, TP_BASIS_LAGRANGE, out);
+}
+
+namespace {
+tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opts* opts, int basis, tp_plan** out) {
     if (!out) return set_error(TP_ERR_ARG, "out must be non-null");
     *out = nullptr;
     if (ngroups < 0 || (ngroups > 0 && !groups)) return set_error(TP_ERR_ARG, "invalid group array");
@@ -327,6 +372,15 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
     for (int i = 0; i < 6; ++i)
         if (o.reserved[i] != 0) return set_error(TP_ERR_ARG, "reserved option fields must be zero");
     if (o.mapping < TP_MAP_AUTO || o.mapping > TP_MAP_WAVE) return set_error(TP_ERR_ARG, "invalid mapping");
+    if (basis == TP_BASIS_HERMITE) {
+        // the even-odd wave kernels need a centrosymmetric basis: the
+        // Hermite-type one is served by the lane kernels (n = 4)
+        for (int gi = 0; gi < ngroups; ++gi)
+            if (groups[gi].n != 4)
+                return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis is supported for n = 4 (p = 3)");
+        if (o.mapping == TP_MAP_WAVE)
+            return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis runs on the lane mapping");
+    }
 
     // validate groups and their element ranges
     std::vector<std::pair<int64_t, int64_t>> ranges;
@@ -366,6 +420,7 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
         return hip_error(e, "hipGetDevice");
     }
     p->penalty_C = o.penalty_C;
+    p->basis = basis;
     p->persistent = o.persistent != 0;
     p->mapping = o.mapping;
     int64_t canon = 0, block0 = 0;
@@ -434,8 +489,8 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
     // SIMD the wave-per-tile solve spreads a group over more waves (AUTO).
     // TP_MAP_LANE asks for the lane solve at any size.
     for (auto& g : p->groups)
-        g.lane_solve = use_lane(*p, g) &&
-                       (p->mapping == TP_MAP_LANE || (g.nblocks + 63) / 64 >= static_cast<int64_t>(p->cus) * 4);
+        g.lane_solve = use_lane(*p, g) && (p->mapping == TP_MAP_LANE || p->basis == TP_BASIS_HERMITE ||
+                                           (g.nblocks + 63) / 64 >= static_cast<int64_t>(p->cus) * 4);
     tp_status st = alloc_dev(&p->summary_dev, sizeof(SolveSummary), "solve summary");
     p->partials_cap = static_cast<int64_t>(p->groups.size() + 1) * p->cus * kMaxWgPerCu;
     if (st == TP_OK)
@@ -448,10 +503,25 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
         RefData& r = p->ref[g.n];
         if (r.built) continue;
         reference_matrices(g.n, p->penalty_C, r.M, r.K, r.A);
+        endpoint_derivatives(g.n, r.g0, r.g1);
+        prolongation_1d(g.n, r.P0, r.P1);
+        for (int i = 0; i < g.n; ++i)
+            for (int j = 0; j < g.n; ++j) r.T[i * g.n + j] = r.Ti[i * g.n + j] = i == j ? 1.0 : 0.0;
         r.built = true;
+        double tab[kEOSlot];
+        if (p->basis == TP_BASIS_HERMITE) {
+            st = hermite_reference(g.n, r);
+            if (st != TP_OK) break;
+            const int n2 = g.n * g.n;
+            for (int i = 0; i < n2; ++i) tab[i] = r.M[i], tab[n2 + i] = r.K[i];
+            st = upload_eo(*p, g.n, EO_PLAIN_K, tab, 2 * n2);
+            if (st != TP_OK) break;
+            for (int i = 0; i < n2; ++i) tab[n2 + i] = r.A[i];
+            st = upload_eo(*p, g.n, EO_PLAIN_A, tab, 2 * n2);
+            continue;
+        }
         const int hc = (g.n + 1) / 2, h = g.n / 2;
         const int cnt = 2 * (hc * hc + h * h);
-        double tab[kEOSlot];
         if (!build_eo_apply(g.n, r.M, r.K, tab)) {
             st = set_error(TP_ERR_UNSUPPORTED, "reference matrices are not centrosymmetric");
             break;
@@ -504,6 +574,9 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_
     *out = p;
     return TP_OK;
 }
+}  // namespace
+
+extern "C" {
 
 tp_status tp_plan_destroy(tp_plan* plan) {
     if (!plan) return TP_OK;
@@ -516,7 +589,8 @@ tp_status tp_plan_create_mesh(const tp_mesh* mesh, const tp_plan_opts* opts, tp_
     if (!out) return set_error(TP_ERR_ARG, "out must be non-null");
     *out = nullptr;
     if (!mesh) return set_error(TP_ERR_ARG, "mesh must be non-null");
-    if (mesh->reserved != 0) return set_error(TP_ERR_ARG, "reserved mesh field must be zero");
+    if (mesh->basis != TP_BASIS_LAGRANGE && mesh->basis != TP_BASIS_HERMITE)
+        return set_error(TP_ERR_ARG, "invalid basis");
     if (opts && opts->persistent) return set_error(TP_ERR_UNSUPPORTED, "mesh plans cannot be persistent");
     int64_t ncells = 1;
     for (int d = 0; d < 3; ++d) {
@@ -538,7 +612,7 @@ tp_status tp_plan_create_mesh(const tp_mesh* mesh, const tp_plan_opts* opts, tp_
     g.M = nullptr;
     g.P = nullptr;
     tp_plan* p = nullptr;
-    tp_status st = tp_plan_create(&g, 1, opts, &p);
+    tp_status st = plan_create(&g, 1, opts, mesh->basis, &p);
     if (st != TP_OK) return st;
     p->mesh = true;
     for (int d = 0; d < 3; ++d) {
@@ -609,11 +683,14 @@ tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, d
                                                   std::to_string(r.lam[0] / r.lam[n - 1]));
         double tab[kEOSlot];
         const int cnt = ((n + 1) / 2) * ((n + 1) / 2) + (n / 2) * (n / 2) + n;
-        if (!build_eo_inverse(n, r.S, r.lam, tab))
-            return set_error(TP_ERR_UNSUPPORTED, "eigenvectors of n=" + std::to_string(n) +
-                                                     " are not split into symmetric and antisymmetric ones");
-        tp_status st = upload_eo(*plan, n, EO_INV, tab, cnt);
-        if (st != TP_OK) return st;
+        tp_status st = TP_OK;
+        if (plan->basis != TP_BASIS_HERMITE) {   // the lane kernels of the Hermite basis use plain factors
+            if (!build_eo_inverse(n, r.S, r.lam, tab))
+                return set_error(TP_ERR_UNSUPPORTED, "eigenvectors of n=" + std::to_string(n) +
+                                                         " are not split into symmetric and antisymmetric ones");
+            st = upload_eo(*plan, n, EO_INV, tab, cnt);
+            if (st != TP_OK) return st;
+        }
         if (n <= kLaneMaxN) {  // plain factors for the lane-per-block kernels
             static_assert(kLaneMaxN * kLaneMaxN + kLaneMaxN <= kEOSlot, "plain tables exceed a slot");
             for (int i = 0; i < n * n; ++i) tab[i] = r.S[i];
@@ -818,6 +895,8 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
     if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
     if (plan->persistent) return set_error(TP_ERR_UNSUPPORTED, "persistent plans have no per-group kernel choice");
+    if (plan->basis == TP_BASIS_HERMITE)
+        return set_error(TP_ERR_UNSUPPORTED, "plans in the Hermite-type basis run the lane kernels only");
     if (reps <= 0) reps = 10;
     const size_t ng = plan->groups.size();
     if (us)

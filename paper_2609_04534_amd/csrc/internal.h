@@ -22,6 +22,11 @@ void reference_matrices(int n, double C, double* M, double* K, double* A);
 int gen_eigen(int n, const double* M, const double* P, double* S, double* lam);
 void endpoint_derivatives(int n, double* g0, double* g1);
 void prolongation_1d(int n, double* P0, double* P1);
+// Hermite-type basis: T[i * n + j] = psi_j(x_i) at the Gauss-Lobatto nodes (n >= 4).
+void hermite_transform(int n, double* T);
+bool invert_small(int n, const double* A, double* Ai);
+// X <- T^T X T.
+void congruence(int n, const double* T, double* X);
 
 // Even-odd tables of the centrosymmetric 1D factors, one slot of kEOSlot
 // elements per (n, table, element type):
@@ -50,6 +55,9 @@ struct RefData {
     double M[kMaxN * kMaxN];
     double K[kMaxN * kMaxN];
     double A[kMaxN * kMaxN];
+    double g0[kMaxN], g1[kMaxN];           // endpoint derivatives of the basis
+    double P0[kMaxN * kMaxN], P1[kMaxN * kMaxN];   // embeddings into the two children
+    double T[kMaxN * kMaxN], Ti[kMaxN * kMaxN];    // nodal <- basis coefficients, and back
     // fast-diagonalization factors of the operator chosen at setup
     bool eig_ready = false;
     double S[kMaxN * kMaxN];
@@ -119,6 +127,7 @@ struct Plan {
     WorkItem* items_dev = nullptr;
     int64_t nitems = 0;
     // uniform box mesh of tp_plan_create_mesh (one group, cells in mesh order)
+    int basis = 0;                 // tp_basis of every block's coefficients
     bool mesh = false;
     int mesh_m[3] = {0, 0, 0};
     double mesh_h[3] = {0.0, 0.0, 0.0};

@@ -10,7 +10,8 @@
 //   u <- u + omega_j D^{-1} (b - A u),  omega_j = 1 / (c - d cos((2j-1) pi / 6))
 // on the spectral interval [0.2, 2] (eq. (chebyshev_weights),
 // eq. (chebyshev_richardson)), with D^{-1} the cell-wise fast-diagonalization
-// inverse.  Each update is one kernel in the factorized form the paper
+// inverse.  All tables (operator, inverse, transfers) are the plan's, in the
+// plan's basis.  Each update is one kernel in the factorized form the paper
 // describes (Sec. 5.2): the operator row, the residual, the block inverse
 // and the update of the lane's cell in registers, so no residual vector is
 // written; the first update from u = 0 needs no operator.  Updates alternate
@@ -312,11 +313,11 @@ bool spd_inverse(int64_t n, std::vector<double>& A, std::vector<double>& inv) {
 // Coarse inverses are shared by every hierarchy with the same coarsest level
 // on a device and kept until the process ends.
 struct CoarseKey {
-    int device, n, mx, my, mz;
+    int device, n, basis, mx, my, mz;
     double hx, hy, hz, C;
     bool operator<(const CoarseKey& o) const {
-        return std::tie(device, n, mx, my, mz, hx, hy, hz, C) <
-               std::tie(o.device, o.n, o.mx, o.my, o.mz, o.hx, o.hy, o.hz, o.C);
+        return std::tie(device, n, basis, mx, my, mz, hx, hy, hz, C) <
+               std::tie(o.device, o.n, o.basis, o.mx, o.my, o.mz, o.hx, o.hy, o.hz, o.C);
     }
 };
 static std::mutex g_coarse_mutex;
@@ -362,7 +363,7 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const double* b, double* u, con
     for (int i = 0; i < N * N; ++i) E.s[i] = static_cast<TI>(plan.ref[N].S[i]);
     for (int i = 0; i < N; ++i) E.lam[i] = static_cast<TI>(plan.ref[N].lam[i]);
     ProlTab<N> P, PT;
-    prolongation_1d(N, P.p[0], P.p[1]);
+    for (int i = 0; i < N * N; ++i) P.p[0][i] = plan.ref[N].P0[i], P.p[1][i] = plan.ref[N].P1[i];
     for (int c = 0; c < 2; ++c)
         for (int i = 0; i < N; ++i)
             for (int j = 0; j < N; ++j) PT.p[c][i * N + j] = P.p[c][j * N + i];
@@ -538,7 +539,7 @@ tp_status tp_mg_create(tp_plan* plan, tp_mg** out) {
     // the coarse inverse, shared per device and coarsest level
     int dev = 0;
     (void)hipGetDevice(&dev);
-    const CoarseKey key{dev, g.n, Lc.G.mx, Lc.G.my, Lc.G.mz, hx, hy, hz, plan->penalty_C};
+    const CoarseKey key{dev, g.n, plan->basis, Lc.G.mx, Lc.G.my, Lc.G.mz, hx, hy, hz, plan->penalty_C};
     std::lock_guard<std::mutex> lock(g_coarse_mutex);
     auto it = g_coarse.find(key);
     if (it != g_coarse.end()) {

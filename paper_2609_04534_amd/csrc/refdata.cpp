@@ -207,6 +207,80 @@ void prolongation_1d(int n, double* P0, double* P1) {
     }
 }
 
+// The Hermite-type basis of Sec. 3.1 (eq. (hermite_conditions)) for n >= 4
+// points (degree p = n - 1 >= 3): psi_0, psi_1 carry the value and the
+// derivative at 0, psi_{p-1}, psi_p the derivative and the value at 1, each
+// the cubic Hermite polynomial with that endpoint datum; the p - 3 interior
+// functions are Lagrange polynomials on the interior Gauss-Lobatto nodes of
+// the (n-2)-point rule times the bubble x^2 (1-x)^2, so they have no value
+// and no derivative at either end.  T[i * n + j] = psi_j(x_i) at the n
+// Gauss-Lobatto nodes: nodal (Lagrange) coefficients = T * Hermite ones.
+void hermite_transform(int n, double* T) {
+    std::vector<double> x(n), z(std::max(n - 2, 2));
+    gll_points(n, x.data());
+    gll_points(std::max(n - 2, 2), z.data());
+    const int nint = n - 4;   // interior functions, nodes z[1 .. n-4]
+    for (int i = 0; i < n; ++i) {
+        const double t = x[i], t2 = t * t, t3 = t2 * t;
+        double* row = T + i * n;
+        row[0] = 1.0 - 3.0 * t2 + 2.0 * t3;
+        row[1] = t - 2.0 * t2 + t3;
+        row[n - 2] = t3 - t2;
+        row[n - 1] = 3.0 * t2 - 2.0 * t3;
+        const double bubble = t2 * (1.0 - t) * (1.0 - t);
+        for (int k = 0; k < nint; ++k) {
+            double l = 1.0;
+            for (int m = 0; m < nint; ++m)
+                if (m != k) l *= (t - z[1 + m]) / (z[1 + k] - z[1 + m]);
+            row[2 + k] = l * bubble;
+        }
+    }
+}
+
+// Inverse of a small dense matrix (row-major) by Gauss-Jordan elimination
+// with partial pivoting; false when a pivot vanishes.
+bool invert_small(int n, const double* A, double* Ai) {
+    std::vector<double> W(static_cast<size_t>(n) * 2 * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j) W[i * 2 * n + j] = j < n ? A[i * n + j] : (j - n == i ? 1.0 : 0.0);
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(W[r * 2 * n + c]) > std::fabs(W[piv * 2 * n + c])) piv = r;
+        if (!(std::fabs(W[piv * 2 * n + c]) > 0.0)) return false;
+        if (piv != c)
+            for (int j = 0; j < 2 * n; ++j) std::swap(W[c * 2 * n + j], W[piv * 2 * n + j]);
+        const double d = 1.0 / W[c * 2 * n + c];
+        for (int j = 0; j < 2 * n; ++j) W[c * 2 * n + j] *= d;
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = W[r * 2 * n + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < 2 * n; ++j) W[r * 2 * n + j] -= f * W[c * 2 * n + j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ai[i * n + j] = W[i * 2 * n + n + j];
+    return true;
+}
+
+// X <- T^T X T for a symmetric bilinear-form matrix X (row-major n x n).
+void congruence(int n, const double* T, double* X) {
+    std::vector<double> Y(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += X[i * n + k] * T[k * n + j];
+            Y[i * n + j] = s;
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < n; ++k) s += T[k * n + i] * Y[k * n + j];
+            X[i * n + j] = s;
+        }
+}
+
 // Generalized symmetric-definite eigenproblem P S = M S diag(lam).
 // Returns 0 on success, -1 when M is not SPD.
 int gen_eigen(int n, const double* M, const double* P, double* S, double* lam) {

@@ -435,11 +435,9 @@ void sipg_tables(const Plan& plan, bool face_only, Pair<N, TC>& R, FaceRef<N, TC
         R.m[i] = static_cast<TC>(ref.M[i]);
         R.p[i] = static_cast<TC>(face_only ? ref.A[i] - ref.K[i] : ref.A[i]);
     }
-    double g0[N], g1[N];
-    endpoint_derivatives(N, g0, g1);
     for (int i = 0; i < N; ++i) {
-        F.g0[i] = static_cast<TC>(g0[i]);
-        F.g1[i] = static_cast<TC>(g1[i]);
+        F.g0[i] = static_cast<TC>(ref.g0[i]);
+        F.g1[i] = static_cast<TC>(ref.g1[i]);
     }
     F.sigma = static_cast<TC>(plan.penalty_C * (N - 1) * N);
 }

@@ -28,6 +28,7 @@ DTYPE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
 OP_NEUMANN, OP_CELL, OP_SIPG, OP_SIPG_FACE = 0, 1, 2, 3
 FACTOR_SCALED, FACTOR_GENERAL = 0, 1
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
+BASIS_LAGRANGE, BASIS_HERMITE = 0, 1
 
 # The public symbol set declared in include/tpfdm.h.
 EXPORTS = (
@@ -37,7 +38,7 @@ EXPORTS = (
     "tp_last_error", "tp_version", "tp_solve_summary_fetch", "tp_graph_create", "tp_graph_launch",
     "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel", "tp_plan_create_mesh",
     "tp_pcg_create", "tp_pcg_solve", "tp_pcg_destroy", "tp_pcg_begin", "tp_pcg_poll",
-    "tp_mg_create", "tp_mg_vcycle", "tp_mg_destroy", "tp_pcg_set_multigrid",
+    "tp_mg_create", "tp_mg_vcycle", "tp_mg_destroy", "tp_pcg_set_multigrid", "tp_change_basis",
 )
 KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
@@ -63,7 +64,7 @@ class _Opts(ctypes.Structure):
 
 class _Mesh(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("layout_B", ctypes.c_int32), ("cells", ctypes.c_int32 * 3),
-                ("reserved", ctypes.c_int32), ("h", ctypes.c_double * 3)]
+                ("basis", ctypes.c_int32), ("h", ctypes.c_double * 3)]
 
 
 class _PcgSummary(ctypes.Structure):
@@ -120,6 +121,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_mg_vcycle": (i32, [vp, vp, vp, vp]),
         "tp_mg_destroy": (i32, [vp]),
         "tp_pcg_set_multigrid": (i32, [vp, vp]),
+        "tp_change_basis": (i32, [vp, i32, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -245,10 +247,11 @@ class Plan:
 
     @classmethod
     def mesh(cls, n: int, cells, h, layout_B: int | None = None, penalty_C: float = 2.0,
-             mapping: int = MAP_AUTO) -> "Plan":
+             mapping: int = MAP_AUTO, basis: int = BASIS_LAGRANGE) -> "Plan":
         """Plan over a uniform box mesh of cells[0] x cells[1] x cells[2] cells
         of edge lengths h (tp_plan_create_mesh): one group of blocks in mesh
-        order, with the coupled operators OP_SIPG and OP_SIPG_FACE."""
+        order, with the coupled operators OP_SIPG and OP_SIPG_FACE; basis is
+        BASIS_LAGRANGE (nodal) or BASIS_HERMITE (n = 4)."""
         lib = load()
         B = default_layout_B(n) if layout_B is None else layout_B
         m = _Mesh()
@@ -257,7 +260,7 @@ class Plan:
         for d in range(3):
             m.cells[d] = int(cells[d])
             m.h[d] = float(h[d])
-        m.reserved = 0
+        m.basis = basis
         opts = _Opts()
         lib.tp_plan_opts_default(ctypes.byref(opts))
         opts.penalty_C = penalty_C
@@ -352,6 +355,11 @@ class Plan:
         if grid and name == "wave" and call != 2:
             name += "/" + {1: "full", 2: "half", 0: "tile"}.get(code >> 4, "?")
         return name
+
+    def change_basis(self, u, v, to_nodal: bool, stream=None):
+        """v = (T (x) T (x) T) u (to_nodal) or the inverse, cell by cell
+        (tp_change_basis), blocked FP64 device vectors."""
+        _check(load().tp_change_basis(self.handle, 1 if to_nodal else 0, _ptr(u), _ptr(v), _stream(stream)))
 
     def pack(self, canonical, blocked, stream=None):
         _check(load().tp_pack(self.handle, _ptr(canonical), _ptr(blocked), torch_dtype_code(canonical),

@@ -1,0 +1,220 @@
+"""GPU parity of mesh plans in the Hermite-type basis (n = 4, p = 3) against
+the oracle assembled in that basis: the coupled operator and its parts
+element by element, the change of basis, the cell-block inverse, PCG, the
+multigrid V-cycle, agreement of the solution with the Lagrange plan's after
+conversion, and sampled cells at the full benchmark size."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+
+from oracle import hermite, mg, sipg
+from paper_2609_04534_amd import tpfdm
+from tests.gpu_util import from_blocked, to_blocked
+
+pytestmark = pytest.mark.gpu
+
+H = sipg.HERMITE
+TOL = {tpfdm.F64: 1e-12, tpfdm.F32: 2e-6}
+P = 3
+N = 4
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _u(ncell, seed):
+    return np.random.default_rng(seed).uniform(-1, 1, ncell * N ** 3)
+
+
+def _plan(cells, h, B=None, setup=True):
+    plan = tpfdm.Plan.mesh(N, cells, h, layout_B=B, basis=tpfdm.BASIS_HERMITE)
+    if setup:
+        plan.setup_inverse(tpfdm.OP_CELL)
+    return plan
+
+
+# several 64-cell tiles with ragged tails, one-cell-thick meshes along each
+# axis, layouts B = 1, 8, 128, a single cell
+CASES = [
+    ((3, 5, 13), (0.25, 0.5, 1.0), None),
+    ((1, 1, 70), (0.3, 0.3, 0.3), None),
+    ((70, 1, 1), (0.1, 0.4, 0.2), None),
+    ((2, 33, 1), (1.0, 0.5, 2.0), None),
+    ((4, 5, 6), (0.7, 1.3, 0.45), 1),
+    ((3, 4, 5), (0.7, 1.3, 0.45), 8),
+    ((6, 6, 8), (0.2, 0.3, 0.15), 128),
+    ((1, 1, 1), (1.0, 1.0, 1.0), None),
+]
+OPS = [(tpfdm.OP_SIPG, sipg.FULL), (tpfdm.OP_SIPG_FACE, sipg.FACE), (tpfdm.OP_NEUMANN, sipg.VOLUME)]
+
+
+@pytest.mark.parametrize("cells,h,B", CASES)
+@pytest.mark.parametrize("dt", [tpfdm.F64, tpfdm.F32])
+def test_operators_match_oracle(cells, h, B, dt):
+    torch = _torch()
+    ncell = cells[0] * cells[1] * cells[2]
+    u = _u(ncell, ncell + 11)
+    print(f"cells={cells} B={B} dt={tpfdm.DTYPE_NAMES[dt]}", flush=True)
+    with _plan(cells, h, B, setup=False) as plan:
+        bu = to_blocked(plan, u, dt)
+        for op, part in OPS:
+            A = sipg.assemble(P, cells, h, part, bname=H)
+            ref = A @ u
+            bv = torch.full_like(bu, float("nan"))
+            plan.apply(bu, bv, op=op)
+            got = from_blocked(plan, bv, dt)
+            scale = np.max(np.abs(abs(A) @ np.abs(u)))
+            err = float(np.max(np.abs(got - ref)) / scale)
+            print(f"  op={op} err={err:.2e}")
+            assert err <= TOL[dt]
+
+
+@pytest.mark.parametrize("cells,h,B", [((3, 5, 13), (0.25, 0.5, 1.0), None), ((4, 5, 6), (0.7, 1.3, 0.45), 1)])
+def test_change_basis_matches_oracle(cells, h, B):
+    torch = _torch()
+    ncell = cells[0] * cells[1] * cells[2]
+    u = _u(ncell, 4)
+    with _plan(cells, h, B, setup=False) as plan:
+        bu = to_blocked(plan, u, tpfdm.F64)
+        bv = torch.full_like(bu, float("nan"))
+        plan.change_basis(bu, bv, to_nodal=True)
+        nodal = from_blocked(plan, bv, tpfdm.F64)
+        bw = torch.full_like(bu, float("nan"))
+        plan.change_basis(bv, bw, to_nodal=False)
+        back = from_blocked(plan, bw, tpfdm.F64)
+        bh = torch.full_like(bu, float("nan"))
+        plan.change_basis(bu, bh, to_nodal=False)
+        herm = from_blocked(plan, bh, tpfdm.F64)
+    assert np.abs(nodal - hermite.to_lagrange(P, u, ncell)).max() <= 1e-14 * 8
+    assert np.abs(herm - hermite.to_hermite(P, u, ncell)).max() <= 1e-12 * np.abs(herm).max()
+    # the round trip through T and T^-1 in three directions loses up to
+    # about cond(T)^3 eps (cond(T) = 18.8 at p = 3): 1.5e-12
+    kappa = np.linalg.cond(hermite.transform(P))
+    assert np.abs(back - u).max() <= 4 * kappa ** 3 * np.finfo(float).eps
+
+
+@pytest.mark.parametrize("dt", [tpfdm.F64, tpfdm.F32])
+def test_cell_inverse_matches_oracle(dt):
+    """apply_inverse with the cell blocks (the block-Jacobi preconditioner)
+    against dense solves of the oracle's Hermite cell block."""
+    torch = _torch()
+    cells, h = (3, 5, 13), (0.25, 0.5, 1.0)
+    ncell = 195
+    r = _u(ncell, 8)
+    ref = sipg.block_jacobi(P, cells, h, r, bname=H)
+    with _plan(cells, h) as plan:
+        br = to_blocked(plan, r, dt)
+        bx = torch.full_like(br, float("nan"))
+        plan.apply_inverse(br, bx)
+        x = from_blocked(plan, bx, dt)
+    err = np.abs(x - ref).reshape(ncell, -1).max(axis=1) / np.abs(ref).reshape(ncell, -1).max(axis=1)
+    print(f"dt={tpfdm.DTYPE_NAMES[dt]} max block rel err={err.max():.2e}")
+    # FP32: the cell block's condition number in this basis (about 1e3 times
+    # that of the Lagrange one through the mass matrix) scales the rounding
+    assert err.max() <= (1e-11 if dt == tpfdm.F64 else 2e-3)
+
+
+@pytest.mark.parametrize("inner", [tpfdm.F64, tpfdm.F32])
+def test_pcg_matches_oracle(inner):
+    torch = _torch()
+    cells, h = (4, 5, 6), (0.25, 0.5, 0.4)
+    ncell = 120
+    b = _u(ncell, 21)
+    A = sipg.assemble(P, cells, h, bname=H)
+    xs = spl.spsolve(A.tocsc(), b)
+    rtol = 1e-10
+    xo, ito, _ = sipg.pcg(A, b, lambda r: sipg.block_jacobi(P, cells, h, r, bname=H), rtol, 3000)
+    with _plan(cells, h) as plan, tpfdm.PCG(plan) as solver:
+        bb = to_blocked(plan, b, tpfdm.F64)
+        bx = torch.full_like(bb, float("nan"))
+        s = solver.solve(bb, bx, inner=inner, rtol=rtol, maxit=3000, check_every=8)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    print(f"inner={tpfdm.DTYPE_NAMES[inner]} oracle_iters={ito} {s}")
+    assert s["converged"] and np.linalg.norm(b - A @ x) <= 2 * rtol * np.linalg.norm(b)
+    assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs)
+    if inner == tpfdm.F64:
+        assert abs(s["iterations"] - ito) <= 1
+    else:
+        assert abs(s["iterations"] - ito) <= max(3, ito // 10)
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_vcycle_and_mg_pcg_match_oracle(m):
+    torch = _torch()
+    Hh = mg.Hierarchy(P, m, bname=H)
+    b = _u(m ** 3, 30 + m)
+    xo = Hh.vcycle(b)
+    _, ito, _ = sipg.pcg(Hh.A[0], b, Hh.vcycle, 1e-10, 200)
+    with _plan((m,) * 3, (1.0 / m,) * 3) as plan, tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+        bb = to_blocked(plan, b, tpfdm.F64)
+        bx = torch.full_like(bb, float("nan"))
+        V.vcycle(bb, bx)
+        x = from_blocked(plan, bx, tpfdm.F64)
+        solver.set_multigrid(V)
+        by = torch.full_like(bb, float("nan"))
+        s = solver.solve(bb, by, rtol=1e-10, maxit=200, check_every=4)
+    err = np.abs(x - xo).max() / np.abs(xo).max()
+    print(f"m={m} vcycle rel err={err:.2e} oracle_iters={ito} {s}")
+    assert err <= 1e-10
+    assert s["converged"] and abs(s["iterations"] - ito) <= 1
+
+
+def test_solution_agrees_with_the_lagrange_plan():
+    """The same discrete problem in both bases: solve A_H x_H = T3^T b_L,
+    convert x_H to nodal values, compare with the Lagrange plan's solution."""
+    torch = _torch()
+    cells, h = (4, 4, 6), (0.25, 0.25, 0.2)
+    ncell = 96
+    bL = _u(ncell, 40)
+    T = hermite.transform(P)
+    T3 = np.kron(np.kron(T, T), T)
+    bH = (bL.reshape(ncell, -1) @ T3).reshape(-1)          # T3^T b per cell
+    with tpfdm.Plan.mesh(N, cells, h) as pl:
+        pl.setup_inverse(tpfdm.OP_CELL)
+        b1 = to_blocked(pl, bL, tpfdm.F64)
+        x1 = torch.empty_like(b1)
+        with tpfdm.PCG(pl) as s1:
+            s1.solve(b1, x1, rtol=1e-12, maxit=5000)
+        xL = from_blocked(pl, x1, tpfdm.F64)
+    with _plan(cells, h) as ph:
+        b2 = to_blocked(ph, bH, tpfdm.F64)
+        x2 = torch.empty_like(b2)
+        with tpfdm.PCG(ph) as s2:
+            s2.solve(b2, x2, rtol=1e-12, maxit=5000)
+        xn = torch.empty_like(x2)
+        ph.change_basis(x2, xn, to_nodal=True)
+        xH_nodal = from_blocked(ph, xn, tpfdm.F64)
+    assert np.linalg.norm(xH_nodal - xL) <= 1e-9 * np.linalg.norm(xL)
+
+
+@pytest.mark.parametrize("m,dt", [(128, tpfdm.F64), (64, tpfdm.F32)])
+def test_full_size_sampled_cells(m, dt):
+    """The benchmark meshes: the operator on sampled cells (corners, edges,
+    random) against the oracle's row blocks in this basis."""
+    torch = _torch()
+    cells, h = (m,) * 3, (1.0 / m,) * 3
+    rng = np.random.default_rng(m)
+    ncell = m ** 3
+    print(f"m={m} dt={tpfdm.DTYPE_NAMES[dt]}", flush=True)
+    u = rng.uniform(-1, 1, ncell * 64)
+    corners = [sipg.cell_index(cells, a, b, c) for a in (0, m - 1) for b in (0, m - 1) for c in (0, m - 1)]
+    edges = [sipg.cell_index(cells, 0, m // 2, m - 1), sipg.cell_index(cells, m - 1, 0, m // 3)]
+    sample = sorted(set(corners + edges + rng.choice(ncell, 24, replace=False).tolist()))
+    with _plan(cells, h, setup=False) as plan:
+        bu = to_blocked(plan, u, dt)
+        bv = torch.empty_like(bu)
+        plan.apply(bu, bv, op=tpfdm.OP_SIPG)
+        v = from_blocked(plan, bv, dt).reshape(ncell, 64)[sample]
+        del bu, bv
+    uq = u.astype(np.float32).astype(np.float64) if dt == tpfdm.F32 else u
+    ref = sipg.cell_apply(P, cells, h, uq, sample, bname=H)
+    scale = 0.0
+    ub = uq.reshape(ncell, 64)
+    for c in sample:
+        for nb, blk in sipg.cell_row_blocks(P, cells, h, c, bname=H):
+            scale = max(scale, float(np.max(np.abs(blk) @ np.abs(ub[nb]))))
+    err = np.abs(v - ref).max() / scale
+    print(f"  sampled err={err:.2e}")
+    assert err <= TOL[dt]

@@ -159,7 +159,7 @@ def test_setup_inverse_rejects_unknown_mode():
     assert lib.tp_setup_inverse(None, 1, 7, 0.0) == -1
 
 
-def _create_mesh(n=3, B=64, cells=(2, 3, 4), h=(0.5, 1.0, 0.25), reserved=0, persistent=0):
+def _create_mesh(n=3, B=64, cells=(2, 3, 4), h=(0.5, 1.0, 0.25), basis=0, persistent=0, mapping=0):
     lib = tpfdm.load()
     m = tpfdm._Mesh()
     m.n = n
@@ -167,10 +167,11 @@ def _create_mesh(n=3, B=64, cells=(2, 3, 4), h=(0.5, 1.0, 0.25), reserved=0, per
     for d in range(3):
         m.cells[d] = cells[d]
         m.h[d] = h[d]
-    m.reserved = reserved
+    m.basis = basis
     opts = tpfdm._Opts()
     lib.tp_plan_opts_default(ctypes.byref(opts))
     opts.persistent = persistent
+    opts.mapping = mapping
     out = ctypes.c_void_p()
     return lib.tp_plan_create_mesh(ctypes.byref(m), ctypes.byref(opts), ctypes.byref(out))
 
@@ -180,7 +181,11 @@ def test_mesh_plan_validation_before_device():
     assert _create_mesh(cells=(2, -1, 4)) == -1
     assert _create_mesh(h=(0.5, 0.0, 1.0)) == -1
     assert _create_mesh(h=(0.5, float("nan"), 1.0)) == -1
-    assert _create_mesh(reserved=1) == -1
+    assert _create_mesh(basis=2) == -1                        # no such basis
+    assert _create_mesh(basis=-1) == -1
+    assert _create_mesh(n=3, basis=tpfdm.BASIS_HERMITE) == -2   # Hermite-type basis: n = 4 only
+    assert _create_mesh(n=5, basis=tpfdm.BASIS_HERMITE) == -2
+    assert _create_mesh(n=4, basis=tpfdm.BASIS_HERMITE, mapping=tpfdm.MAP_WAVE) == -2
     assert _create_mesh(cells=(2048, 2048, 1024)) == -1       # 2^32 cells
     assert _create_mesh(persistent=1) == -2
     lib = tpfdm.load()
