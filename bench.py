@@ -118,8 +118,12 @@ def main():
                     help="serve Poisson arrival streams of PCG solves at several rates (JSON lines)")
     ap.add_argument("--pcg", action="store_true",
                     help="time preconditioned-CG solves of the SIPG system on the serving mesh sizes (JSON lines)")
-    ap.add_argument("--pcg-mesh", default=None, metavar="P,M",
-                    help="with --pcg: only the unit cube of degree P with M cells per side")
+    ap.add_argument("--pcg-mesh", default=None, metavar="P,M[,BASIS]",
+                    help="with --pcg: only the unit cube of degree P with M cells per side "
+                         "(BASIS lagrange or hermite)")
+    ap.add_argument("--mg-paper", action="store_true",
+                    help="time the paper's solver configuration (MG-PCG, p = 3, <r, z>^{1/2} reduced by 1e-10) "
+                         "on 32^3 .. 128^3 cubes in both bases (JSON lines)")
     ap.add_argument("--sipg", action="store_true",
                     help="time only the coupled SIPG operator on the unit-cube meshes (JSON lines)")
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "f16", "bf16"],
@@ -145,6 +149,9 @@ def main():
 
     if args.suite:
         run_suite(args, stream)
+        return
+    if args.mg_paper:
+        run_mg_paper(args, stream)
         return
     if args.pcg:
         run_pcg(args, stream)
@@ -385,7 +392,10 @@ def run_suite(args, stream):
 
 # Coupled SIPG operator on uniformly refined unit cubes (the meshes of the
 # paper's face-kernel and operator measurements, Sec. 6.3 and 6.5).
-SIPG_SUITE = [(3, 128, ("f64", "f32")), (3, 64, ("f64",)), (2, 128, ("f64",))]
+# (degree, cells per side, dtypes, basis): the Lagrange basis, and the
+# Hermite-type basis (two-layer face access) at degree 3
+SIPG_SUITE = [(3, 128, ("f64", "f32"), "lagrange"), (3, 128, ("f64", "f32"), "hermite"),
+              (3, 64, ("f64",), "lagrange"), (3, 64, ("f64",), "hermite"), (2, 128, ("f64",), "lagrange")]
 
 
 def run_sipg(args, stream):
@@ -394,9 +404,10 @@ def run_sipg(args, stream):
     import torch
     from paper_2609_04534_amd import tpfdm, workloads
     codes = {"f64": (tpfdm.F64, torch.float64, 8), "f32": (tpfdm.F32, torch.float32, 4)}
-    for p, m, dts in SIPG_SUITE:
+    for p, m, dts, basis in SIPG_SUITE:
         mesh = workloads.unit_cube_mesh(p, m, seed=5)
-        plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h)
+        plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h,
+                               basis=tpfdm.BASIS_HERMITE if basis == "hermite" else tpfdm.BASIS_LAGRANGE)
         cu = torch.from_numpy(mesh.u).cuda()
         for dtn in dts:
             code, tdt, es = codes[dtn]
@@ -416,7 +427,7 @@ def run_sipg(args, stream):
             ms_v = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
             ms_c = time_launches(lambda k: V[k].copy_(U[k]), stream, reps, R)
             nd = mesh.ndof
-            print(json.dumps({"workload": mesh.name, "dtype": dtn, "ndof": nd, "buffer_sets": R,
+            print(json.dumps({"workload": mesh.name, "basis": basis, "dtype": dtn, "ndof": nd, "buffer_sets": R,
                               "sipg_ms": ms, "sipg_GDoF/s": nd / ms / 1e6, "sipg_GB/s": 2 * nd * es / ms / 1e6,
                               "face_ms": ms_f, "face_GDoF/s": nd / ms_f / 1e6,
                               "volume_ms": ms_v, "volume_GDoF/s": nd / ms_v / 1e6,
@@ -433,6 +444,8 @@ PCG_SUITE = [(p, m) for p in (2, 3) for m in (8, 16, 24, 32, 48)] + [(7, m) for 
 # Larger meshes timed with the multigrid preconditioner only (block-Jacobi
 # needs over a thousand iterations there).
 PCG_MG_ONLY = [(3, 64), (2, 96)]
+# Degree-3 meshes in the Hermite-type basis (two-layer face access), MG only.
+PCG_HERMITE = [(3, 24), (3, 48), (3, 64)]
 
 
 def run_pcg(args, stream):
@@ -441,19 +454,22 @@ def run_pcg(args, stream):
     summary), p50 / p99 over repeated solves, iterations."""
     import torch
     from paper_2609_04534_amd import tpfdm, workloads
-    suite = PCG_SUITE + PCG_MG_ONLY
+    suite = [(p, m, "lagrange") for p, m in PCG_SUITE + PCG_MG_ONLY] + [(p, m, "hermite") for p, m in PCG_HERMITE]
     if args.pcg_mesh:
-        suite = [tuple(int(v) for v in args.pcg_mesh.split(","))]
-    for p, m in suite:
+        f = args.pcg_mesh.split(",")
+        suite = [(int(f[0]), int(f[1]), f[2] if len(f) > 2 else "lagrange")]
+    for p, m, basis in suite:
         mesh = workloads.unit_cube_mesh(p, m, seed=7)
-        plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h)
+        plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h,
+                               basis=tpfdm.BASIS_HERMITE if basis == "hermite" else tpfdm.BASIS_LAGRANGE)
         plan.setup_inverse(tpfdm.OP_CELL)
         b = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
         plan.pack(torch.from_numpy(mesh.u).cuda(), b)
         x = torch.empty_like(b)
         solver = tpfdm.PCG(plan)
         mg = tpfdm.MG(plan) if p <= 3 else None
-        preconds = ("mg",) if (p, m) in PCG_MG_ONLY else ("block_jacobi", "mg") if mg else ("block_jacobi",)
+        preconds = (("mg",) if (p, m) in PCG_MG_ONLY or basis == "hermite"
+                    else ("block_jacobi", "mg") if mg else ("block_jacobi",))
         for precond in preconds:
             solver.set_multigrid(mg if precond == "mg" else None)
             for inner in (tpfdm.F64, tpfdm.F32):
@@ -468,7 +484,7 @@ def run_pcg(args, stream):
                     if i >= 2:
                         lat.append((t1 - t0) * 1e3)
                 p50 = float(np.percentile(lat, 50))
-                print(json.dumps({"workload": f"pcg_p{p}_{m}cube", "precond": precond,
+                print(json.dumps({"workload": f"pcg_p{p}_{m}cube", "basis": basis, "precond": precond,
                                   "inner": tpfdm.DTYPE_NAMES[inner], "ndof": mesh.ndof,
                                   "iterations": s["iterations"], "relres": s["relres"],
                                   "p50_ms": p50, "p99_ms": float(np.percentile(lat, 99)),
@@ -480,6 +496,50 @@ def run_pcg(args, stream):
         plan.destroy()
         del b, x
         torch.cuda.empty_cache()
+
+
+# The paper's solver configuration on globally refined unit cubes (p = 3,
+# 2^k cells per side down to a one-cell coarsest level): CG with one V-cycle,
+# stopped when <r, z>^{1/2} has decreased by 1e-10; solve throughput is
+# DoF / wall time of a whole solve.
+MG_PAPER = [(3, 32), (3, 64), (3, 128)]
+
+
+def run_mg_paper(args, stream):
+    import torch
+    from paper_2609_04534_amd import tpfdm, workloads
+    for p, m in MG_PAPER:
+        for basis in ("lagrange", "hermite"):
+            mesh = workloads.unit_cube_mesh(p, m, seed=11)
+            plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h,
+                                   basis=tpfdm.BASIS_HERMITE if basis == "hermite" else tpfdm.BASIS_LAGRANGE)
+            plan.setup_inverse(tpfdm.OP_CELL)
+            b = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
+            plan.pack(torch.from_numpy(mesh.u).cuda(), b)
+            x = torch.empty_like(b)
+            mg = tpfdm.MG(plan)
+            solver = tpfdm.PCG(plan)
+            solver.set_multigrid(mg)
+            solver.set_norm(tpfdm.PCG_PRECONDITIONED)
+            reps = 10 if m <= 64 else 4
+            lat, s = [], None
+            for i in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s = solver.solve(b, x, inner=tpfdm.F64, rtol=1e-10, maxit=100, check_every=4, stream=stream)
+                t1 = time.perf_counter()
+                if i >= 1:
+                    lat.append(t1 - t0)
+            t = float(np.median(lat))
+            print(json.dumps({"workload": f"mg_pcg_p{p}_{m}cube_precnorm_1e-10", "basis": basis,
+                              "ndof": mesh.ndof, "iterations": s["iterations"], "relres": s["relres"],
+                              "solve_ms": t * 1e3, "solve_MDoF/s": mesh.ndof / t / 1e6,
+                              "ms_per_iteration": t * 1e3 / max(1, s["iterations"])}), flush=True)
+            solver.destroy()
+            mg.destroy()
+            plan.destroy()
+            del b, x
+            torch.cuda.empty_cache()
 
 
 # Serving: arrival rates (requests/s), each with a bounded number of

@@ -379,6 +379,17 @@ tp_status tp_pcg_poll(tp_pcg* pcg, tp_pcg_summary* summary);
  * the solve's `inner` precision; null restores block-Jacobi; TP_ERR_ARG for
  * a multigrid of another plan, TP_ERR_STATE during a non-blocking solve; a
  * multigrid is destroyed only after its solvers are destroyed or reset. */
+/* Stopping test of tp_pcg_* solves (default TP_PCG_RESIDUAL):
+ * RESIDUAL: ||r||_2 <= rtol ||b||_2 with the recursively updated residual;
+ * PRECONDITIONED: the preconditioned residual norm <r, z>^{1/2} has
+ *   decreased by the factor rtol from its initial value (the rule of
+ *   Sec. 6.1; invariant under a change of basis).
+ * tp_pcg_set_norm applies to later solves of that solver (TP_ERR_STATE
+ * during a non-blocking solve, TP_ERR_ARG for another value).  The summary's
+ * relres is ||r||_2 / ||b||_2 under either test. */
+typedef enum { TP_PCG_RESIDUAL = 0, TP_PCG_PRECONDITIONED = 1 } tp_pcg_norm;
+tp_status tp_pcg_set_norm(tp_pcg* pcg, int32_t norm);
+
 typedef struct tp_mg tp_mg;
 tp_status tp_mg_create(tp_plan* plan, tp_mg** out);
 tp_status tp_mg_vcycle(tp_mg* mg, const double* b, double* x, hipStream_t stream);

@@ -115,8 +115,9 @@ class Hierarchy:
         return self.smooth(k, u, b)
 
 
-def mg_pcg(p: int, m: int, b, rtol: float, maxit: int = 200, bname: str = sipg.LAGRANGE):
+def mg_pcg(p: int, m: int, b, rtol: float, maxit: int = 200, bname: str = sipg.LAGRANGE,
+           criterion: str = "residual"):
     """CG on the finest level preconditioned by one V-cycle; returns
     (x, iterations, relative residual)."""
     H = Hierarchy(p, m, bname=bname)
-    return sipg.pcg(H.A[0], b, H.vcycle, rtol, maxit)
+    return sipg.pcg(H.A[0], b, H.vcycle, rtol, maxit, criterion=criterion)

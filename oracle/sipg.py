@@ -217,11 +217,14 @@ def block_jacobi(p: int, m, h, r, C: float = 2.0, bname: str = LAGRANGE) -> np.n
     return np.linalg.solve(D, r.T).T.reshape(-1)
 
 
-def pcg(A, b, prec, rtol: float, maxit: int, x0=None):
+def pcg(A, b, prec, rtol: float, maxit: int, x0=None, criterion: str = "residual"):
     """Textbook preconditioned conjugate gradients for the SPD system A x = b
-    (Hestenes-Stiefel recurrences), stopping when ||b - A x||_2 <= rtol ||b||_2
-    with the recursively updated residual.  prec(r) applies the
-    preconditioner.  Returns (x, iterations, ||r||_2 / ||b||_2)."""
+    (Hestenes-Stiefel recurrences).  criterion "residual": stop when
+    ||b - A x||_2 <= rtol ||b||_2 with the recursively updated residual;
+    "preconditioned": stop when the preconditioned residual norm
+    <r, z>^{1/2} has decreased by the factor rtol from its initial value
+    (the rule of Sec. 6.1).  prec(r) applies the preconditioner.  Returns
+    (x, iterations, ||r||_2 / ||b||_2)."""
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
     r = b - A @ x
@@ -231,8 +234,15 @@ def pcg(A, b, prec, rtol: float, maxit: int, x0=None):
     z = prec(r)
     pdir = z.copy()
     rz = r @ z
+    rz0 = rz
     it = 0
-    while np.linalg.norm(r) > rtol * nb and it < maxit:
+
+    def converged():
+        if criterion == "preconditioned":
+            return np.sqrt(rz) <= rtol * np.sqrt(rz0)
+        return np.linalg.norm(r) <= rtol * nb
+
+    while not converged() and it < maxit:
         q = A @ pdir
         alpha = rz / (pdir @ q)
         x += alpha * pdir

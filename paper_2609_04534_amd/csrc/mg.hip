@@ -50,7 +50,7 @@ __device__ __forceinline__ bool done_flag(const PcgState* st) { return st && st-
 
 // t = A u on one level (one cell per lane); the consumers form b - t as
 // they load, which keeps b out of this kernel's registers.
-template <int N>
+template <int N, bool HERM>
 __global__ __launch_bounds__(64, 2) void k_mg_apply(const double* __restrict__ u, double* __restrict__ t, MeshArgs G,
                                                   Pair<N, double> R, FaceRef<N, double> F,
                                                   const PcgState* __restrict__ st) {
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(64, 2) void k_mg_apply(const double* __restrict__ u
     const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
     double acc[N3];
-    sipg_cell<N, double, double, -1>(u, G, R, F, c, acc, sa, sbt);
+    sipg_cell<N, double, double, -1, HERM>(u, G, R, F, c, acc, sa, sbt);
     const int64_t base = G.offset + block_base(c, 6, N3);
 #pragma unroll
     for (int e = 0; e < N3; ++e) {
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(64, 2) void k_mg_jacobi0(const double* __restrict__
 // cell, A u_in from the cell and its six neighbours, the block inverse in
 // precision TI on the residual registers.  u_out must not alias u_in (other
 // lanes still read u_in).
-template <int N, typename TI>
+template <int N, typename TI, bool HERM>
 __global__ __launch_bounds__(64, 2) void k_mg_smooth(const double* __restrict__ b, const double* __restrict__ uin,
                                                    double* __restrict__ uout, MeshArgs G, Pair<N, double> R,
                                                    FaceRef<N, double> F, Eig<N, TI> E, double omega,
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(64, 2) void k_mg_smooth(const double* __restrict__ 
     const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
     double acc[N3];
-    sipg_cell<N, double, double, -1>(uin, G, R, F, c, acc, sa, sbt);
+    sipg_cell<N, double, double, -1, HERM>(uin, G, R, F, c, acc, sa, sbt);
     const int64_t base = G.offset + block_base(c, 6, N3);
     TI v[N3];
 #pragma unroll
@@ -346,7 +346,7 @@ struct tp_mg {
 
 namespace {
 
-template <int N, typename TI>
+template <int N, typename TI, bool HERM>
 tp_status vcycle_level(const tp_mg* m, size_t l, const double* b, double* u, const PcgState* st, hipStream_t s) {
     const Plan& plan = *m->plan;
     const MgLevel& L = m->lv[l];
@@ -370,19 +370,19 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const double* b, double* u, con
     // Chebyshev updates ping-pong between u and the level's scratch t; the
     // prolongation writes out of place so that the last update lands in u.
     auto step = [&](const double* from, double* to, int j) {
-        hipLaunchKernelGGL((k_mg_smooth<N, TI>), dim3(grid), dim3(64), 0, s, b, from, to, L.G, R, F, E, m->omega[j],
-                           st);
+        hipLaunchKernelGGL((k_mg_smooth<N, TI, HERM>), dim3(grid), dim3(64), 0, s, b, from, to, L.G, R, F, E,
+                           m->omega[j], st);
     };
     hipLaunchKernelGGL((k_mg_jacobi0<N, TI>), dim3(grid), dim3(64), 0, s, b, u, L.G, E, m->omega[0], st);
     step(u, L.t, 1);
     step(L.t, u, 2);
     const MgLevel& C = m->lv[l + 1];
-    hipLaunchKernelGGL((k_mg_apply<N>), dim3(grid), dim3(64), 0, s, u, L.t, L.G, R, F, st);
+    hipLaunchKernelGGL((k_mg_apply<N, HERM>), dim3(grid), dim3(64), 0, s, u, L.t, L.G, R, F, st);
     hipLaunchKernelGGL((k_mg_restrict<N>), dim3(static_cast<unsigned>((C.G.ncells + 63) / 64)), dim3(64), 0, s, b,
                        L.t, C.b, L.G, C.G, PT, st);
     tp_status stt = check_launch("level transfer");
     if (stt != TP_OK) return stt;
-    stt = vcycle_level<N, TI>(m, l + 1, C.b, C.u, st, s);
+    stt = vcycle_level<N, TI, HERM>(m, l + 1, C.b, C.u, st, s);
     if (stt != TP_OK) return stt;
     hipLaunchKernelGGL((k_mg_prolong<N>), dim3(grid), dim3(64), 0, s, C.u, u, L.t, L.G, C.G, P, st);
     step(L.t, u, 0);
@@ -394,9 +394,11 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const double* b, double* u, con
 template <typename TI>
 tp_status vcycle_dispatch(const tp_mg* m, const double* b, double* u, const PcgState* st, hipStream_t s) {
     switch (m->n) {
-        case 2: return vcycle_level<2, TI>(m, 0, b, u, st, s);
-        case 3: return vcycle_level<3, TI>(m, 0, b, u, st, s);
-        case 4: return vcycle_level<4, TI>(m, 0, b, u, st, s);
+        case 2: return vcycle_level<2, TI, false>(m, 0, b, u, st, s);
+        case 3: return vcycle_level<3, TI, false>(m, 0, b, u, st, s);
+        case 4:
+            return m->plan->basis == TP_BASIS_HERMITE ? vcycle_level<4, TI, true>(m, 0, b, u, st, s)
+                                                      : vcycle_level<4, TI, false>(m, 0, b, u, st, s);
         default: break;
     }
     return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
@@ -422,7 +424,7 @@ tp_status coarse_probe_n(const tp_mg* m, std::vector<double>& A) {
         const int64_t pos = L.G.offset + block_base(j / N3, 6, N3) + ((j % N3) << 6);
         hipError_t e = hipMemcpy(L.u + pos, &one, sizeof(double), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_error(e, "coarse probe");
-        hipLaunchKernelGGL((k_mg_apply<N>), dim3(grid), dim3(64), 0, nullptr, L.u, L.t, L.G, R, F,
+        hipLaunchKernelGGL((k_mg_apply<N, false>), dim3(grid), dim3(64), 0, nullptr, L.u, L.t, L.G, R, F,
                            static_cast<const PcgState*>(nullptr));
         e = hipMemcpy(col.data(), L.t, static_cast<size_t>(L.elems) * sizeof(double), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_error(e, "coarse probe");

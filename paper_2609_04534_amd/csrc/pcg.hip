@@ -29,8 +29,9 @@ namespace {
 
 __device__ __forceinline__ bool finite(double v) { return v == v && v <= 1.7976931348623157e308 && v >= -1.7976931348623157e308; }
 
-// 1.  q = A p, partial (p, q) per workgroup.
-template <int N, int LB>
+// 1.  q = A p, partial (p, q) per workgroup (HERM: the two-layer face
+// terms of the Hermite-type basis).
+template <int N, int LB, bool HERM = false>
 __global__ __launch_bounds__(64, 2) void k_pcg_aq(const double* __restrict__ p, double* __restrict__ q, MeshArgs G,
                                                 Pair<N, double> R, FaceRef<N, double> F,
                                                 const PcgState* __restrict__ st, double* __restrict__ part) {
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(64, 2) void k_pcg_aq(const double* __restrict__ p, 
     double dot = 0.0;
     if (c < G.ncells) {
         double acc[N3];
-        sipg_cell<N, double, double, LB>(p, G, R, F, c, acc, sa, sbt);
+        sipg_cell<N, double, double, LB, HERM>(p, G, R, F, c, acc, sa, sbt);
         const int64_t base = G.offset + block_base(c, lb, N3);
 #pragma unroll
         for (int e = 0; e < N3; ++e) {
@@ -70,9 +71,12 @@ __device__ __forceinline__ double block_sum(const double* __restrict__ part, int
     return r;
 }
 
-// 0.  After the start kernel: (r, z), (r, r), (b, b) -> state.
+// 0.  After the start kernel: (r, z), (r, r), (b, b) -> state.  norm 0:
+// converged when (r, r) <= rtol^2 (b, b); norm 1: when (r, z) <= rtol^2
+// (r_0, z_0), the preconditioned residual norm reduced by rtol.
 __global__ __launch_bounds__(256) void k_pcg_reduce_start(const double* __restrict__ part, int64_t count,
-                                                          PcgState* __restrict__ st, double rtol, int maxit) {
+                                                          PcgState* __restrict__ st, double rtol, int maxit,
+                                                          int norm) {
     __shared__ double red[256];
     const double rz = block_sum(part, count, red);
     const double rr = block_sum(part + count, count, red);
@@ -85,11 +89,11 @@ __global__ __launch_bounds__(256) void k_pcg_reduce_start(const double* __restri
         s.bb = bb;
         s.alpha = 0.0;
         s.beta = 0.0;
-        s.tol2 = rtol * rtol * bb;
+        s.tol2 = rtol * rtol * (norm ? rz : bb);
         s.iter = 0;
         s.maxit = maxit;
-        s.pad = 0;
-        s.done = !(finite(rz) && finite(rr) && finite(bb)) ? 2 : (rr <= s.tol2 ? 1 : (maxit <= 0 ? 3 : 0));
+        s.norm = norm;
+        s.done = !(finite(rz) && finite(rr) && finite(bb)) ? 2 : ((norm ? rz : rr) <= s.tol2 ? 1 : (maxit <= 0 ? 3 : 0));
         *st = s;
     }
 }
@@ -125,7 +129,7 @@ __global__ __launch_bounds__(256) void k_pcg_reduce_beta(const double* __restric
         const int it = st->iter + 1;
         st->iter = it;
         if (!finite(rz) || !finite(rr)) st->done = 2;
-        else if (rr <= st->tol2) st->done = 1;
+        else if ((st->norm ? rz : rr) <= st->tol2) st->done = 1;
         else if (it >= st->maxit) st->done = 3;
     }
 }
@@ -512,6 +516,7 @@ struct tp_pcg {
     int ti = 0;                 // precision of the running solve
     int phase = 0;              // 0 idle, 1 iterating, 2 copying the result out
     tp_mg* mg = nullptr;        // V-cycle preconditioner (null: block-Jacobi)
+    int norm = TP_PCG_RESIDUAL; // stopping test
 };
 
 namespace {
@@ -570,7 +575,8 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
     else
         hipLaunchKernelGGL((k_pcg_start_wave<N, TI>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q,
                            x, s->xw, s->r, s->z, s->p, G, tabS, s->part, cnt);
-    hipLaunchKernelGGL(k_pcg_reduce_start, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st, rtol, maxit);
+    hipLaunchKernelGGL(k_pcg_reduce_start, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st, rtol, maxit,
+                       s->norm);
     tp_status st = check_launch("PCG start");
     if (st != TP_OK) return st;
     // one chunk of iterations, captured once per solver and precision: every
@@ -585,10 +591,18 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             for (int i = 0; i < chunk; ++i) {
-                if constexpr (kLane)
-                    hipLaunchKernelGGL((k_pcg_aq<N, LB>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R, F, s->st,
-                                       s->part);
-                else if (vp)
+                if constexpr (kLane) {
+                    bool herm = false;
+                    if constexpr (N == 4) herm = plan.basis == TP_BASIS_HERMITE;
+                    if (herm) {
+                        if constexpr (N == 4)
+                            hipLaunchKernelGGL((k_pcg_aq<N, LB, true>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R,
+                                               F, s->st, s->part);
+                    } else {
+                        hipLaunchKernelGGL((k_pcg_aq<N, LB>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R, F, s->st,
+                                           s->part);
+                    }
+                } else if (vp)
                     hipLaunchKernelGGL((k_pcg_aq_wave<N, true>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, tabA, F,
                                        s->st, s->part);
                 else
@@ -817,6 +831,14 @@ tp_status tp_pcg_poll(tp_pcg* s, tp_pcg_summary* summary) {
     }
     if (st != TP_OK) s->phase = 0;
     return st == TP_OK ? TP_PENDING : st;
+}
+
+tp_status tp_pcg_set_norm(tp_pcg* s, int32_t norm) {
+    if (!s) return set_error(TP_ERR_ARG, "solver is null");
+    if (norm != TP_PCG_RESIDUAL && norm != TP_PCG_PRECONDITIONED) return set_error(TP_ERR_ARG, "invalid norm");
+    if (s->phase != 0) return set_error(TP_ERR_STATE, "a non-blocking solve is still running on this solver");
+    s->norm = norm;
+    return TP_OK;
 }
 
 tp_status tp_pcg_set_multigrid(tp_pcg* s, tp_mg* mg) {

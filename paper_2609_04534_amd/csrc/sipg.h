@@ -48,7 +48,8 @@ namespace tpfdm {
 // a non-finite scalar, 3 iteration limit.
 struct PcgState {
     double rz, pq, rr, bb, alpha, beta, tol2;
-    int iter, done, maxit, pad;
+    int iter, done, maxit;
+    int norm;   // stopping test on 0: (r, r), 1: (r, z) (tol2 scaled to match)
 };
 
 // Sum of a double over the 64 lanes of a wave.
@@ -207,11 +208,113 @@ __device__ __forceinline__ void lane_face(const TS* __restrict__ w, int lb, bool
     }
 }
 
+// The face term in the Hermite-type basis (eq. (hermite_traces_3d)): the
+// trace and the normal derivative of a cell at a face are its two layers
+// next to that face, so alpha and beta read two layers of the source (the
+// neighbour's layers next to the face, or on a boundary face the cell's
+// own), and the result lands in the cell's two layers next to the face:
+// alpha in the trace layer kend, beta in the derivative layer next to it.
+// Same weights as lane_face (only the endpoint derivative of the
+// derivative layer is nonzero in this basis), same two-pass tangential mass.
+template <int N, int D, bool UP, typename TS, typename TC, int LB>
+__device__ __forceinline__ void lane_face_h(const TS* __restrict__ w, int lb, bool interior, const TC* M,
+                                            const FaceRef<N, TC>& F, TC s, TC (&acc)[N * N * N], TC (*sa)[64],
+                                            TC (*sbt)[64]) {
+    static_assert(N >= 4, "the Hermite-type basis has n >= 4");
+    constexpr int kend = UP ? N - 1 : 0;
+    constexpr int kder = UP ? N - 2 : 1;
+    constexpr int LS = D == 0 ? N * N : D == 1 ? N : 1;   // stride of the normal index
+    const int l = LB >= 0 ? LB : lb;
+    const int lane = threadIdx.x;
+    // source layers k0, k0 + 1: 0, 1 when the face is interior at the upper
+    // end or boundary at the lower end, else n-2, n-1
+    const bool first = (UP == interior);
+    const TS* wk = w + (static_cast<int64_t>(first ? 0 : (N - 2) * LS) << l);
+    auto ld = [&](int q) { return ldc<TC>(wk + (static_cast<int64_t>(q) << l)); };
+    auto park_row = [&](TC(*dst)[64], int a, const TC* r, bool add) {
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            TC t = add ? dst[a * N + b][lane] : TC(0);
+#pragma unroll
+            for (int bb = 0; bb < N; ++bb) t = fma(M[b * N + bb], r[bb], t);
+            dst[a * N + b][lane] = t;
+        }
+    };
+    auto column = [&](TC(*src)[64], int b, TC (&out)[N]) {
+        TC col[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) col[a] = src[a * N + b][lane];
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            TC t = TC(0);
+#pragma unroll
+            for (int aa = 0; aa < N; ++aa) t = fma(M[a * N + aa], col[aa], t);
+            out[a] = t;
+        }
+    };
+    // alpha weights of all n layers (as in lane_face), then those of the two
+    // source layers selected per lane
+    TC ca[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const TC in = UP ? fma(TC(-0.5), F.g0[k], k == 0 ? -F.sigma : TC(0))
+                         : fma(TC(0.5), F.g1[k], k == N - 1 ? -F.sigma : TC(0));
+        const TC bd = UP ? TC(-0.5) * F.g1[k] : TC(0.5) * F.g0[k];
+        ca[k] = s * (interior ? in : bd);
+    }
+    const TC c0 = first ? ca[0] : ca[N - 2], c1 = first ? ca[1] : ca[N - 1];
+    const TC d0 = first ? TC(0.5) * s : TC(0), d1 = first ? TC(0) : TC(-0.5) * s;
+    {
+        TC sl[N][N], lay[N * N];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+#pragma unroll
+                for (int b = 0; b < N; ++b) lay[a * N + b] = ld(fq<N, D>(t, a, b));
+            const TC ct = t == 0 ? c0 : c1;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+#pragma unroll
+                for (int b = 0; b < N; ++b) sl[a][b] = t == 0 ? ct * lay[a * N + b] : fma(ct, lay[a * N + b], sl[a][b]);
+                pin(sl[a]);
+            }
+            // beta = d0 w_k0 + d1 w_k0+1: one weight is zero per lane
+            const TC dt = t == 0 ? d0 : d1;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                TC r[N];
+#pragma unroll
+                for (int b = 0; b < N; ++b) r[b] = dt * lay[a * N + b];
+                park_row(sbt, a, r, t != 0);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) park_row(sa, a, sl[a], false);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const TC gk = UP ? F.g1[kder] : F.g0[kder];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        TC at[N], bt[N];
+        column(sa, b, at);
+        column(sbt, b, bt);
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            acc[fq<N, D>(kend, a, b)] += at[a];
+            acc[fq<N, D>(kder, a, b)] = fma(gk, bt[a], acc[fq<N, D>(kder, a, b)]);
+        }
+    }
+}
+
 // (A u) of cell c into acc (the row of eq. (sipg) for one cell, see the
 // header): the six face terms first, then the cell-diagonal Kronecker sum
 // accumulated on top, so no face state is live while the volume product
 // holds its planes.  sa, sbt: the lane's LDS slabs (N^2 x 64 each).
-template <int N, typename TS, typename TC, int LB>
+template <int N, typename TS, typename TC, int LB, bool HERM = false>
 __device__ __forceinline__ void sipg_cell(const TS* __restrict__ u, const MeshArgs& G, const Pair<N, TC>& R,
                                           const FaceRef<N, TC>& F, int64_t c, TC (&acc)[N * N * N],
                                           TC (*sa)[64], TC (*sbt)[64]) {
@@ -231,20 +334,34 @@ __device__ __forceinline__ void sipg_cell(const TS* __restrict__ u, const MeshAr
     // the source cell of a face: the neighbour, or the cell itself on the
     // boundary (an index select, so the kernel stays one basic block)
     auto src = [&](bool interior, int64_t d) { return ub + block_base(interior ? c + d : c, lb, N3); };
+    // the face routine of the basis: Hermite-type (two layers) or Lagrange
+    auto face = [&](auto Dc, auto UPc, const TS* w, bool interior, TC sd) {
+        constexpr int D = decltype(Dc)::value;
+        constexpr bool UP = decltype(UPc)::value;
+        if constexpr (HERM)
+            lane_face_h<N, D, UP, TS, TC, LB>(w, lb, interior, R.m, F, sd, acc, sa, sbt);
+        else
+            lane_face<N, D, UP, TS, TC, LB>(w, lb, interior, R.m, F, sd, acc, sa, sbt);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using BF = std::integral_constant<bool, false>;
+    using BT = std::integral_constant<bool, true>;
     {
         const bool lo = cx > 0, hi = cx + 1 < static_cast<uint32_t>(G.mx);
-        lane_face<N, 0, false, TS, TC, LB>(src(lo, -syz), lb, lo, R.m, F, sx, acc, sa, sbt);
-        lane_face<N, 0, true, TS, TC, LB>(src(hi, syz), lb, hi, R.m, F, sx, acc, sa, sbt);
+        face(I0{}, BF{}, src(lo, -syz), lo, sx);
+        face(I0{}, BT{}, src(hi, syz), hi, sx);
     }
     {
         const bool lo = cy > 0, hi = cy + 1 < static_cast<uint32_t>(G.my);
-        lane_face<N, 1, false, TS, TC, LB>(src(lo, -G.mz), lb, lo, R.m, F, sy, acc, sa, sbt);
-        lane_face<N, 1, true, TS, TC, LB>(src(hi, G.mz), lb, hi, R.m, F, sy, acc, sa, sbt);
+        face(I1{}, BF{}, src(lo, -G.mz), lo, sy);
+        face(I1{}, BT{}, src(hi, G.mz), hi, sy);
     }
     {
         const bool lo = cz > 0, hi = cz + 1 < static_cast<uint32_t>(G.mz);
-        lane_face<N, 2, false, TS, TC, LB>(src(lo, -1), lb, lo, R.m, F, sz, acc, sa, sbt);
-        lane_face<N, 2, true, TS, TC, LB>(src(hi, 1), lb, hi, R.m, F, sz, acc, sa, sbt);
+        face(I2{}, BF{}, src(lo, -1), lo, sz);
+        face(I2{}, BT{}, src(hi, 1), hi, sz);
     }
     __builtin_amdgcn_sched_barrier(0);
     lane_apply<N, TC, false, true>([&](int q) { return ldc<TC>(own + (static_cast<int64_t>(q) << lb)); }, R, sx, sy,

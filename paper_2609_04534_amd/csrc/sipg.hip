@@ -7,7 +7,7 @@ namespace {
 
 // One cell per lane (n <= 4).  The cell's own block is read with cached
 // loads (it is also a face source of its neighbours); v is streamed out.
-template <int N, typename TS, typename TC, bool NT, int LB>
+template <int N, typename TS, typename TC, bool NT, int LB, bool HERM = false>
 __global__ __launch_bounds__(64, 2) void k_sipg_lane(const TS* __restrict__ u, TS* __restrict__ v, MeshArgs G,
                                                    Pair<N, TC> R, FaceRef<N, TC> F) {
     constexpr int N3 = N * N * N;
@@ -15,7 +15,7 @@ __global__ __launch_bounds__(64, 2) void k_sipg_lane(const TS* __restrict__ u, T
     const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
     TC acc[N3];
-    sipg_cell<N, TS, TC, LB>(u, G, R, F, c, acc, sa, sbt);
+    sipg_cell<N, TS, TC, LB, HERM>(u, G, R, F, c, acc, sa, sbt);
     const int lb = LB >= 0 ? LB : G.logB;
     TS* vb = v + G.offset + block_base(c, lb, N3);
 #pragma unroll
@@ -59,6 +59,20 @@ tp_status sipg_lane_n(const Plan& plan, const MeshArgs& G, bool face_only, const
     const unsigned grid = static_cast<unsigned>((G.ncells + 63) / 64);
     const TS* ui = static_cast<const TS*>(u);
     TS* vo = static_cast<TS*>(v);
+    if constexpr (N == 4) {   // the Hermite-type basis: two-layer face terms
+        if (plan.basis == TP_BASIS_HERMITE) {
+            if (G.logB == 6)
+                hipLaunchKernelGGL((k_sipg_lane<N, TS, TC, true, 6, true>), dim3(grid), dim3(64), 0, s, ui, vo, G, R,
+                                   F);
+            else if (lane_whole_lines<TS>(G.logB))
+                hipLaunchKernelGGL((k_sipg_lane<N, TS, TC, true, -1, true>), dim3(grid), dim3(64), 0, s, ui, vo, G,
+                                   R, F);
+            else
+                hipLaunchKernelGGL((k_sipg_lane<N, TS, TC, false, -1, true>), dim3(grid), dim3(64), 0, s, ui, vo, G,
+                                   R, F);
+            return check_launch("SIPG apply launch");
+        }
+    }
     if (G.logB == 6)
         hipLaunchKernelGGL((k_sipg_lane<N, TS, TC, true, 6>), dim3(grid), dim3(64), 0, s, ui, vo, G, R, F);
     else if (lane_whole_lines<TS>(G.logB))

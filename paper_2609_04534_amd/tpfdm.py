@@ -29,6 +29,7 @@ OP_NEUMANN, OP_CELL, OP_SIPG, OP_SIPG_FACE = 0, 1, 2, 3
 FACTOR_SCALED, FACTOR_GENERAL = 0, 1
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 BASIS_LAGRANGE, BASIS_HERMITE = 0, 1
+PCG_RESIDUAL, PCG_PRECONDITIONED = 0, 1
 
 # The public symbol set declared in include/tpfdm.h.
 EXPORTS = (
@@ -39,6 +40,7 @@ EXPORTS = (
     "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel", "tp_plan_create_mesh",
     "tp_pcg_create", "tp_pcg_solve", "tp_pcg_destroy", "tp_pcg_begin", "tp_pcg_poll",
     "tp_mg_create", "tp_mg_vcycle", "tp_mg_destroy", "tp_pcg_set_multigrid", "tp_change_basis",
+    "tp_pcg_set_norm",
 )
 KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
@@ -122,6 +124,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_mg_destroy": (i32, [vp]),
         "tp_pcg_set_multigrid": (i32, [vp, vp]),
         "tp_change_basis": (i32, [vp, i32, vp, vp, vp]),
+        "tp_pcg_set_norm": (i32, [vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -396,6 +399,11 @@ class PCG:
         self._h = h
         self.plan = plan
         self.mg = None
+
+    def set_norm(self, norm: int):
+        """Stopping test of later solves: PCG_RESIDUAL (||r|| <= rtol ||b||) or
+        PCG_PRECONDITIONED (<r, z>^{1/2} reduced by rtol)."""
+        _check(load().tp_pcg_set_norm(self._h, norm))
 
     def set_multigrid(self, mg: "MG | None"):
         """Precondition later solves with one V-cycle of mg (None: block-Jacobi)."""

@@ -190,6 +190,33 @@ def test_mg_pcg_nonblocking_and_switching_back():
     assert s1["iterations"] < s3["iterations"] // 4
 
 
+@pytest.mark.parametrize("basis", [tpfdm.BASIS_LAGRANGE, tpfdm.BASIS_HERMITE])
+def test_mg_pcg_preconditioned_criterion_matches_oracle(basis):
+    """The stopping rule of Sec. 6.1 (<r, z>^{1/2} reduced by rtol): the
+    oracle's iteration count in both bases."""
+    torch = _torch()
+    p, m = 3, 4
+    bname = sipg.HERMITE if basis == tpfdm.BASIS_HERMITE else sipg.LAGRANGE
+    b = _rhs(m ** 3 * 64, 77)
+    Hh = mg.Hierarchy(p, m, bname=bname)
+    xo, ito, relo = sipg.pcg(Hh.A[0], b, Hh.vcycle, 1e-10, 200, criterion="preconditioned")
+    with tpfdm.Plan.mesh(p + 1, (m,) * 3, (1.0 / m,) * 3, basis=basis) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
+        with tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+            solver.set_multigrid(V)
+            solver.set_norm(tpfdm.PCG_PRECONDITIONED)
+            bb = to_blocked(plan, b, tpfdm.F64)
+            bx = torch.empty_like(bb)
+            s = solver.solve(bb, bx, rtol=1e-10, maxit=200, check_every=4)
+            x = from_blocked(plan, bx, tpfdm.F64)
+    print(f"basis={basis} oracle_iters={ito} {s}")
+    assert s["converged"] and abs(s["iterations"] - ito) <= 1
+    if s["iterations"] == ito:
+        # the same iterate up to rounding: the oracle's residual and solution
+        assert abs(s["relres"] - relo) <= 0.05 * relo
+        assert np.linalg.norm(x - xo) <= 1e-8 * np.linalg.norm(xo)
+
+
 def test_mg_errors():
     torch = _torch()
     # no cell inverse set up
@@ -215,3 +242,6 @@ def test_mg_errors():
         buf = torch.zeros(p1.vector_elems, dtype=torch.float64, device="cuda")
         with pytest.raises(tpfdm.TpfdmError):
             V.vcycle(buf, buf)
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            solver.set_norm(2)
+        assert e.value.status == -1

@@ -200,3 +200,20 @@ def test_mg_pcg_in_the_hermite_basis():
     _, it_l, _ = mg.mg_pcg(p, m, hermite.to_lagrange(p, b, m ** 3), 1e-10)
     assert rel <= 1e-10 and np.linalg.norm(b - A @ x) <= 2e-10 * np.linalg.norm(b)
     assert it <= 16 and abs(it - it_l) <= 3
+
+
+def test_preconditioned_criterion_is_basis_invariant():
+    """Sec. 6.1's stopping rule on <r, z>^{1/2}: CG with the V-cycle on the
+    same problem written in the two bases (b_H = T3^T b_L) takes the same
+    number of iterations, and the iterates are related by the change of
+    basis (x_L = T3 x_H), because <r, z> is a pairing of a dual and a primal
+    vector.  (The 2-norm of the residual is not invariant.)"""
+    p, m = 3, 4
+    ncell = m ** 3
+    bL = np.random.default_rng(1).uniform(-1, 1, ncell * 64)
+    T = hermite.transform(p)
+    bH = (bL.reshape(ncell, -1) @ np.kron(np.kron(T, T), T)).reshape(-1)
+    xL, itL, _ = mg.mg_pcg(p, m, bL, 1e-10, criterion="preconditioned")
+    xH, itH, _ = mg.mg_pcg(p, m, bH, 1e-10, bname=sipg.HERMITE, criterion="preconditioned")
+    assert itL == itH
+    assert np.allclose(hermite.to_lagrange(p, xH, ncell), xL, atol=1e-9 * np.abs(xL).max())

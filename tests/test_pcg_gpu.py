@@ -62,6 +62,23 @@ def test_pcg_matches_oracle(n, cells, h, inner):
         assert abs(s["iterations"] - ito) <= max(3, ito // 10)
 
 
+def test_block_jacobi_pcg_preconditioned_criterion_matches_oracle():
+    torch = _torch()
+    n, cells, h = 3, (4, 5, 6), (0.25, 0.5, 0.4)
+    p = n - 1
+    b = _rhs(120, n, 12)
+    A = sipg.assemble(p, cells, h)
+    _, ito, _ = sipg.pcg(A, b, lambda r: sipg.block_jacobi(p, cells, h, r), 1e-9, 2000, criterion="preconditioned")
+    with tpfdm.Plan.mesh(n, cells, h) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
+        bb = to_blocked(plan, b, tpfdm.F64)
+        bx = torch.empty_like(bb)
+        with tpfdm.PCG(plan) as solver:
+            solver.set_norm(tpfdm.PCG_PRECONDITIONED)
+            s = solver.solve(bb, bx, rtol=1e-9, maxit=2000)
+    assert s["converged"] and abs(s["iterations"] - ito) <= 1
+
+
 def test_pcg_initial_guess_and_zero_rhs():
     torch = _torch()
     n, cells, h = 3, (4, 4, 4), (0.25, 0.25, 0.25)
