@@ -23,6 +23,9 @@ on GPUs", arXiv 2609.04534):
   with its mass and stiffness matrices, endpoint data, change of basis to the
   Lagrange basis and level transfers; ``sipg`` and ``mg`` take the basis as a
   parameter (``bname``).
+* ``patch``  -- vertex-patch blocks: the operator of the 2 x 2 x 2 cells
+  around a vertex as one tensor-product block of 2(p+1) points per
+  direction (1D patch factors from the cell block and the coupling blocks).
 * ``mg``     -- geometric multigrid for it: Chebyshev-accelerated
   block-Jacobi smoothing (eq. (chebyshev_weights), eq. (chebyshev_richardson)),
   polynomial-embedding transfers, a dense coarse solve, CG preconditioned by

@@ -263,3 +263,27 @@ def test_planted_hermite_mistake_is_caught(monkeypatch, target, replacement):
 
 def test_unmutated_hermite_suite_passes():
     assert not _run_all(HERMITE_PIN_SUITE)
+
+
+# ---------------------------------------------------------------- vertex patches
+import tests.test_oracle_patch as ppins  # noqa: E402
+from oracle import patch  # noqa: E402
+
+_ORIG_PATCH_FACTORS = patch.patch_factors
+
+
+def _swapped_coupling_blocks(p, C=2.0):
+    Mp, Kp, Ap = _ORIG_PATCH_FACTORS(p, C)
+    n = p + 1
+    Ap = Ap.copy()
+    Ap[:n, n:], Ap[n:, :n] = Ap[n:, :n].copy(), Ap[:n, n:].copy()   # N^{+-} where N^{-+} belongs
+    return Mp, Kp, Ap
+
+
+def test_planted_patch_mistake_is_caught(monkeypatch):
+    monkeypatch.setattr(patch, "patch_factors", _swapped_coupling_blocks)
+    assert _run_all([lambda: ppins.test_patch_block_is_the_restricted_mesh_operator(2, dense.CELL, sipg.FULL)])
+
+
+def test_unmutated_patch_suite_passes():
+    assert not _run_all([lambda: ppins.test_patch_block_is_the_restricted_mesh_operator(2, dense.CELL, sipg.FULL)])
