@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--pcg-mesh", default=None, metavar="P,M[,BASIS]",
                     help="with --pcg: only the unit cube of degree P with M cells per side "
                          "(BASIS lagrange or hermite)")
+    ap.add_argument("--patches", action="store_true",
+                    help="time the operator and the exact solve on vertex-patch blocks (JSON lines)")
     ap.add_argument("--mg-paper", action="store_true",
                     help="time the paper's solver configuration (MG-PCG, p = 3, <r, z>^{1/2} reduced by 1e-10) "
                          "on 32^3 .. 128^3 cubes in both bases (JSON lines)")
@@ -152,6 +154,9 @@ def main():
         return
     if args.mg_paper:
         run_mg_paper(args, stream)
+        return
+    if args.patches:
+        run_patches(args, stream)
         return
     if args.pcg:
         run_pcg(args, stream)
@@ -495,6 +500,53 @@ def run_pcg(args, stream):
             mg.destroy()
         plan.destroy()
         del b, x
+        torch.cuda.empty_cache()
+
+
+# Vertex patches of a uniformly refined unit cube: one block per interior
+# vertex, the 2 x 2 x 2 cells around it (n = 2(p+1)); (degree, cells per side,
+# dtypes).
+PATCH_SUITE = [(3, 64, ("f64", "f32", "f16")), (1, 128, ("f64", "f32"))]
+
+
+def run_patches(args, stream):
+    """Patch operator (TP_OP_CELL on patch blocks) and the exact patch solve
+    (apply_inverse): rates with HBM-resident buffers, one vector read and one
+    written per call (algorithmic bytes)."""
+    import torch
+    from paper_2609_04534_amd import tpfdm
+    codes = {"f64": (tpfdm.F64, torch.float64, 8), "f32": (tpfdm.F32, torch.float32, 4),
+             "f16": (tpfdm.F16, torch.float16, 2)}
+    for p, m, dts in PATCH_SUITE:
+        n = 2 * (p + 1)
+        nb = (m - 1) ** 3
+        h = np.full((nb, 3), 1.0 / m)
+        plan = tpfdm.Plan([tpfdm.GroupSpec(n, tpfdm.default_layout_B(n), h)], blocks=tpfdm.BLOCKS_PATCHES)
+        plan.setup_inverse(tpfdm.OP_CELL)
+        E, nd = plan.vector_elems, plan.ndof
+        u = torch.from_numpy(np.random.default_rng(9).uniform(-1, 1, nd)).cuda()
+        for dtn in dts:
+            code, tdt, es = codes[dtn]
+            R = int(min(8, max(1, -(-1.0e9 // (2 * E * es)))))
+            U = [torch.empty(E, dtype=tdt, device="cuda") for _ in range(R)]
+            for x in U:
+                plan.pack(u.to(tdt), x)
+            V = [torch.empty_like(U[0]) for _ in range(R)]
+            for k in range(3):
+                plan.apply(U[k % R], V[k % R], tpfdm.OP_CELL, stream=stream)
+                plan.apply_inverse(U[k % R], V[k % R], stream=stream)
+            reps = max(args.steps, 20)
+            ms_a = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_CELL, stream=stream), stream, reps, R)
+            ms_i = time_launches(lambda k: plan.apply_inverse(U[k], V[k], stream=stream), stream, reps, R)
+            ms_c = time_launches(lambda k: V[k].copy_(U[k]), stream, reps, R)
+            print(json.dumps({"workload": f"patches_p{p}_{m}cube", "n": n, "patches": nb, "dtype": dtn,
+                              "ndof": nd, "apply_ms": ms_a, "apply_GDoF/s": nd / ms_a / 1e6,
+                              "apply_GB/s": 2 * nd * es / ms_a / 1e6, "inverse_ms": ms_i,
+                              "inverse_GDoF/s": nd / ms_i / 1e6, "inverse_GB/s": 2 * nd * es / ms_i / 1e6,
+                              "copy_GB/s": 2 * E * es / ms_c / 1e6}), flush=True)
+            del U, V
+        plan.destroy()
+        del u
         torch.cuda.empty_cache()
 
 

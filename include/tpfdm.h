@@ -120,12 +120,31 @@ typedef enum {
     TP_MAP_WAVE = 2       /* one wave per tile of blocks, pencils staged through LDS   */
 } tp_mapping;
 
+/* What the blocks of a plan are.
+ * CELLS: each block is one cell of degree n-1 (the reference pair of
+ *   the n-point Gauss-Lobatto Lagrange basis).
+ * PATCHES: each block is a vertex patch, the 2 x 2 x 2 cells of degree
+ *   n/2 - 1 around a mesh vertex (n even, 4 <= n <= 8; groups given by the
+ *   cell lengths h, which all eight cells share).  Per direction the patch
+ *   holds two cells: the reference mass is blockdiag(M_hat, M_hat), the
+ *   Neumann operator blockdiag(K_hat, K_hat) (the cells' volume operators),
+ *   and TP_OP_CELL the patch block of the SIPG operator: the cell block
+ *   A_hat of each cell (interior stencil) and the coupling blocks of the
+ *   face between them (eq. (face_coupling)), penalty C p(p+1) with the
+ *   cells' p.  The patch operator is the SIPG operator of a Cartesian mesh
+ *   restricted to the patch's eight cells (Sec. 6.1 names such vertex-patch
+ *   local solves); apply_inverse and solve are its exact local solve by
+ *   fast diagonalization.  DoF order per direction: cell 0's points, then
+ *   cell 1's. */
+typedef enum { TP_BLOCKS_CELLS = 0, TP_BLOCKS_PATCHES = 1 } tp_blocks;
+
 typedef struct {
     double penalty_C;     /* SIPG penalty constant C of sigma = C p(p+1)/h (default 2) */
     int32_t persistent;   /* 1: every call runs as ONE launch over all groups (its
                              solve uses wave-per-tile bodies for every degree)      */
     int32_t mapping;      /* tp_mapping for apply / apply_inverse                      */
-    int32_t reserved[6];  /* must be zero                                             */
+    int32_t blocks;       /* tp_blocks (default TP_BLOCKS_CELLS); not for mesh plans  */
+    int32_t reserved[5];  /* must be zero                                             */
 } tp_plan_opts;
 
 typedef struct {

@@ -369,8 +369,17 @@ tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opt
     if (opts) o = *opts;
     if (!(o.penalty_C > 0.0) || !std::isfinite(o.penalty_C))
         return set_error(TP_ERR_ARG, "penalty_C must be finite and > 0");
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
         if (o.reserved[i] != 0) return set_error(TP_ERR_ARG, "reserved option fields must be zero");
+    if (o.blocks != TP_BLOCKS_CELLS && o.blocks != TP_BLOCKS_PATCHES) return set_error(TP_ERR_ARG, "invalid blocks");
+    if (o.blocks == TP_BLOCKS_PATCHES)
+        for (int gi = 0; gi < ngroups; ++gi) {
+            if (groups[gi].n % 2 != 0 || groups[gi].n < 4)
+                return set_error(TP_ERR_UNSUPPORTED,
+                                 "group " + std::to_string(gi) + ": patch blocks have n = 2 (p+1) in {4, 6, 8}");
+            if (groups[gi].M)
+                return set_error(TP_ERR_ARG, "group " + std::to_string(gi) + ": patch groups are given by h");
+        }
     if (o.mapping < TP_MAP_AUTO || o.mapping > TP_MAP_WAVE) return set_error(TP_ERR_ARG, "invalid mapping");
     if (basis == TP_BASIS_HERMITE) {
         // the even-odd wave kernels need a centrosymmetric basis: the
@@ -421,6 +430,7 @@ tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opt
     }
     p->penalty_C = o.penalty_C;
     p->basis = basis;
+    p->patches = o.blocks == TP_BLOCKS_PATCHES;
     p->persistent = o.persistent != 0;
     p->mapping = o.mapping;
     int64_t canon = 0, block0 = 0;
@@ -502,7 +512,10 @@ tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opt
         if (st != TP_OK) break;
         RefData& r = p->ref[g.n];
         if (r.built) continue;
-        reference_matrices(g.n, p->penalty_C, r.M, r.K, r.A);
+        if (p->patches)
+            patch_reference(g.n / 2, p->penalty_C, r.M, r.K, r.A);
+        else
+            reference_matrices(g.n, p->penalty_C, r.M, r.K, r.A);
         endpoint_derivatives(g.n, r.g0, r.g1);
         prolongation_1d(g.n, r.P0, r.P1);
         for (int i = 0; i < g.n; ++i)
@@ -591,6 +604,7 @@ tp_status tp_plan_create_mesh(const tp_mesh* mesh, const tp_plan_opts* opts, tp_
     if (!mesh) return set_error(TP_ERR_ARG, "mesh must be non-null");
     if (mesh->basis != TP_BASIS_LAGRANGE && mesh->basis != TP_BASIS_HERMITE)
         return set_error(TP_ERR_ARG, "invalid basis");
+    if (opts && opts->blocks != TP_BLOCKS_CELLS) return set_error(TP_ERR_UNSUPPORTED, "mesh plans hold cells");
     if (opts && opts->persistent) return set_error(TP_ERR_UNSUPPORTED, "mesh plans cannot be persistent");
     int64_t ncells = 1;
     for (int d = 0; d < 3; ++d) {

@@ -27,6 +27,9 @@ void hermite_transform(int n, double* T);
 bool invert_small(int n, const double* A, double* Ai);
 // X <- T^T X T.
 void congruence(int n, const double* T, double* X);
+// Reference 1D factors of a vertex patch of two cells of nc points each
+// (n = 2 nc): blockdiag mass and stiffness, and the patch operator.
+void patch_reference(int nc, double C, double* M, double* K, double* A);
 
 // Even-odd tables of the centrosymmetric 1D factors, one slot of kEOSlot
 // elements per (n, table, element type):
@@ -128,6 +131,7 @@ struct Plan {
     int64_t nitems = 0;
     // uniform box mesh of tp_plan_create_mesh (one group, cells in mesh order)
     int basis = 0;                 // tp_basis of every block's coefficients
+    bool patches = false;          // blocks are vertex patches (reference tables of two cells)
     bool mesh = false;
     int mesh_m[3] = {0, 0, 0};
     double mesh_h[3] = {0.0, 0.0, 0.0};

@@ -281,6 +281,41 @@ void congruence(int n, const double* T, double* X) {
         }
 }
 
+// A vertex patch along one direction: two adjacent cells of nc points
+// (degree nc - 1, the same length), n = 2 nc DoFs, cell 0's first.  Mass
+// and stiffness are block-diagonal (one cell each); the patch operator has
+// the cell block A_hat (the interior stencil: stiffness plus the own-side
+// blocks of both faces) on each cell and, off the diagonal, the coupling of
+// the face between them (eq. (face_coupling) with cell 0 on the '-' side):
+//   N^{-+}[i][j] = -sigma e1_i e0_j - 1/2 e1_i g0_j + 1/2 g1_i e0_j,
+// e0, e1 the unit vectors of the first and last point, g0, g1 the endpoint
+// derivatives, sigma = C p (p+1); N^{+-} is its transpose.
+void patch_reference(int nc, double C, double* M, double* K, double* A) {
+    const int n = 2 * nc;
+    double Mc[kMaxN * kMaxN], Kc[kMaxN * kMaxN], Ac[kMaxN * kMaxN], g0[kMaxN], g1[kMaxN];
+    reference_matrices(nc, C, Mc, Kc, Ac);
+    endpoint_derivatives(nc, g0, g1);
+    const double sigma = C * (nc - 1) * nc;
+    for (int i = 0; i < n * n; ++i) M[i] = K[i] = A[i] = 0.0;
+    for (int b = 0; b < 2; ++b)
+        for (int i = 0; i < nc; ++i)
+            for (int j = 0; j < nc; ++j) {
+                const int o = (b * nc + i) * n + b * nc + j;
+                M[o] = Mc[i * nc + j];
+                K[o] = Kc[i * nc + j];
+                A[o] = Ac[i * nc + j];
+            }
+    for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j) {
+            double v = 0.0;
+            if (i == nc - 1 && j == 0) v -= sigma;
+            if (i == nc - 1) v -= 0.5 * g0[j];
+            if (j == 0) v += 0.5 * g1[i];
+            A[i * n + nc + j] = v;
+            A[(nc + j) * n + i] = v;
+        }
+}
+
 // Generalized symmetric-definite eigenproblem P S = M S diag(lam).
 // Returns 0 on success, -1 when M is not SPD.
 int gen_eigen(int n, const double* M, const double* P, double* S, double* lam) {

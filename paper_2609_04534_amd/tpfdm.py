@@ -29,6 +29,7 @@ OP_NEUMANN, OP_CELL, OP_SIPG, OP_SIPG_FACE = 0, 1, 2, 3
 FACTOR_SCALED, FACTOR_GENERAL = 0, 1
 MAP_AUTO, MAP_LANE, MAP_WAVE = 0, 1, 2
 BASIS_LAGRANGE, BASIS_HERMITE = 0, 1
+BLOCKS_CELLS, BLOCKS_PATCHES = 0, 1
 PCG_RESIDUAL, PCG_PRECONDITIONED = 0, 1
 
 # The public symbol set declared in include/tpfdm.h.
@@ -61,7 +62,7 @@ class _Group(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("penalty_C", ctypes.c_double), ("persistent", ctypes.c_int32),
-                ("mapping", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("mapping", ctypes.c_int32), ("blocks", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class _Mesh(ctypes.Structure):
@@ -209,7 +210,8 @@ def default_layout_B(n: int) -> int:
 class Plan:
     """Owning wrapper of a tp_plan."""
 
-    def __init__(self, groups, penalty_C: float = 2.0, persistent: bool = False, mapping: int = MAP_AUTO):
+    def __init__(self, groups, penalty_C: float = 2.0, persistent: bool = False, mapping: int = MAP_AUTO,
+                 blocks: int = BLOCKS_CELLS):
         lib = load()
         self._keep = []
         arr = (_Group * max(1, len(groups)))()
@@ -243,6 +245,7 @@ class Plan:
         opts.penalty_C = penalty_C
         opts.persistent = 1 if persistent else 0
         opts.mapping = mapping
+        opts.blocks = blocks
         handle = ctypes.c_void_p()
         _check(lib.tp_plan_create(arr, len(groups), ctypes.byref(opts), ctypes.byref(handle)))
         self._h = handle

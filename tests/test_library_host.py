@@ -190,3 +190,21 @@ def test_mesh_plan_validation_before_device():
     assert _create_mesh(persistent=1) == -2
     lib = tpfdm.load()
     assert lib.tp_plan_create_mesh(None, None, None) == -1
+
+
+def test_patch_blocks_validation_before_device():
+    lib = tpfdm.load()
+    opts = tpfdm._Opts()
+    lib.tp_plan_opts_default(ctypes.byref(opts))
+    assert opts.blocks == tpfdm.BLOCKS_CELLS
+    opts.blocks = 2
+    assert _create([(4, 64, 10, 0)], ctypes.byref(opts)) == -1          # no such block kind
+    opts.blocks = tpfdm.BLOCKS_PATCHES
+    for n in (2, 3, 5, 7):                                               # patches have n = 2 (p+1) >= 4
+        assert _create([(n, 64, 10, 0)], ctypes.byref(opts)) == -2
+    m = tpfdm._Mesh()
+    m.n, m.layout_B = 4, 64
+    for d in range(3):
+        m.cells[d], m.h[d] = 2, 0.5
+    out = ctypes.c_void_p()
+    assert lib.tp_plan_create_mesh(ctypes.byref(m), ctypes.byref(opts), ctypes.byref(out)) == -2
