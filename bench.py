@@ -633,20 +633,23 @@ def run_serve(args):
 def sipg_counters():
     """Hardware-counter run of the coupled operator on the p=3 128^3 mesh in
     FP64: one plain device copy of a vector (the calibration), then three
-    applies of A and three of A^face."""
+    applies of A and three of A^face, in the Lagrange basis and then in the
+    Hermite-type basis (two-layer face access)."""
     import torch
     from paper_2609_04534_amd import tpfdm, workloads
     mesh = workloads.unit_cube_mesh(3, 128, seed=5)
-    with tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h) as plan:
-        u = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
-        plan.pack(torch.from_numpy(mesh.u).cuda(), u)
-        v = torch.empty_like(u)
-        v.copy_(u)
-        for _ in range(3):
-            plan.apply(u, v, tpfdm.OP_SIPG)
-        for _ in range(3):
-            plan.apply(u, v, tpfdm.OP_SIPG_FACE)
-        torch.cuda.synchronize()
+    for basis in (tpfdm.BASIS_LAGRANGE, tpfdm.BASIS_HERMITE):
+        with tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h, basis=basis) as plan:
+            u = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
+            plan.pack(torch.from_numpy(mesh.u).cuda(), u)
+            v = torch.empty_like(u)
+            v.copy_(u)
+            for _ in range(3):
+                plan.apply(u, v, tpfdm.OP_SIPG)
+            for _ in range(3):
+                plan.apply(u, v, tpfdm.OP_SIPG_FACE)
+            torch.cuda.synchronize()
+            del u, v
     _log("sipg counters run done")
 
 
