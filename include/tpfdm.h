@@ -434,6 +434,16 @@ int64_t tp_plan_nblocks(const tp_plan* plan);
 tp_status tp_reference_matrices(int32_t n, double penalty_C, double* M, double* K,
                                 double* A);
 
+/* Host-side reference data of a plan's blocks (no GPU needed): the tables a
+ * plan with this basis (tp_basis) and block kind (tp_blocks) uses, row-major
+ * n x n host arrays, any may be null.  M_hat, K_hat (the volume operator)
+ * and A_hat (the cell or patch block operator), and T, the change of basis
+ * (nodal values = T * coefficients; the identity for the Lagrange basis).
+ * Errors: TP_ERR_ARG (values), TP_ERR_UNSUPPORTED (the combinations plans
+ * reject: Hermite-type basis other than n = 4 cells, patches with odd n). */
+tp_status tp_reference_basis(int32_t n, int32_t basis, int32_t blocks, double penalty_C, double* M,
+                             double* K, double* A, double* T);
+
 /* Host-side generalized eigen-decomposition P_hat S = M_hat S diag(lam) with
  * S^T M_hat S = I, eigenvalues ascending, each column's largest-magnitude
  * entry positive.  S: row-major n x n host array (column j = eigenvector j),

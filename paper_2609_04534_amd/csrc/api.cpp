@@ -281,6 +281,10 @@ static tp_status group_solve(const Plan& p, const GroupInfo& g, const double* b,
     }
 }
 
+namespace {
+tp_status hermite_reference(int n, RefData& r);
+}
+
 extern "C" {
 
 const char* tp_last_error(void) { return g_last_error.c_str(); }
@@ -299,6 +303,39 @@ tp_status tp_reference_matrices(int32_t n, double penalty_C, double* M, double* 
     if (!(penalty_C > 0.0) || !std::isfinite(penalty_C))
         return set_error(TP_ERR_ARG, "penalty_C must be finite and > 0");
     reference_matrices(n, penalty_C, M, K, A);
+    return TP_OK;
+}
+
+tp_status tp_reference_basis(int32_t n, int32_t basis, int32_t blocks, double penalty_C, double* M, double* K,
+                             double* A, double* T) {
+    if (n < kMinN || n > kMaxN) return set_error(TP_ERR_UNSUPPORTED, "n must be in [2, 8]");
+    if (!(penalty_C > 0.0) || !std::isfinite(penalty_C))
+        return set_error(TP_ERR_ARG, "penalty_C must be finite and > 0");
+    if (basis != TP_BASIS_LAGRANGE && basis != TP_BASIS_HERMITE) return set_error(TP_ERR_ARG, "invalid basis");
+    if (blocks != TP_BLOCKS_CELLS && blocks != TP_BLOCKS_PATCHES) return set_error(TP_ERR_ARG, "invalid blocks");
+    if (basis == TP_BASIS_HERMITE && (n != 4 || blocks != TP_BLOCKS_CELLS))
+        return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis is supported for n = 4 cells");
+    if (blocks == TP_BLOCKS_PATCHES && (n % 2 != 0 || n < 4))
+        return set_error(TP_ERR_UNSUPPORTED, "patch blocks have n = 2 (p+1) in {4, 6, 8}");
+    RefData r;
+    if (blocks == TP_BLOCKS_PATCHES)
+        patch_reference(n / 2, penalty_C, r.M, r.K, r.A);
+    else
+        reference_matrices(n, penalty_C, r.M, r.K, r.A);
+    endpoint_derivatives(n, r.g0, r.g1);
+    prolongation_1d(n, r.P0, r.P1);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) r.T[i * n + j] = r.Ti[i * n + j] = i == j ? 1.0 : 0.0;
+    if (basis == TP_BASIS_HERMITE) {
+        tp_status st = hermite_reference(n, r);
+        if (st != TP_OK) return st;
+    }
+    for (int i = 0; i < n * n; ++i) {
+        if (M) M[i] = r.M[i];
+        if (K) K[i] = r.K[i];
+        if (A) A[i] = r.A[i];
+        if (T) T[i] = r.T[i];
+    }
     return TP_OK;
 }
 

@@ -41,7 +41,7 @@ EXPORTS = (
     "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel", "tp_plan_create_mesh",
     "tp_pcg_create", "tp_pcg_solve", "tp_pcg_destroy", "tp_pcg_begin", "tp_pcg_poll",
     "tp_mg_create", "tp_mg_vcycle", "tp_mg_destroy", "tp_pcg_set_multigrid", "tp_change_basis",
-    "tp_pcg_set_norm",
+    "tp_pcg_set_norm", "tp_reference_basis",
 )
 KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_pcg_set_multigrid": (i32, [vp, vp]),
         "tp_change_basis": (i32, [vp, i32, vp, vp, vp]),
         "tp_pcg_set_norm": (i32, [vp, i32]),
+        "tp_reference_basis": (i32, [i32, i32, i32, dbl, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -152,6 +153,14 @@ def reference_matrices(n: int, penalty_C: float = 2.0):
     A = np.zeros((n, n))
     _check(load().tp_reference_matrices(n, penalty_C, M.ctypes.data, K.ctypes.data, A.ctypes.data))
     return M, K, A
+
+
+def reference_basis(n: int, basis: int = BASIS_LAGRANGE, blocks: int = BLOCKS_CELLS, penalty_C: float = 2.0):
+    """(M_hat, K_hat, A_hat, T) a plan with this basis and block kind uses
+    (tp_reference_basis), computed by the library's host code."""
+    out = [np.zeros((n, n)) for _ in range(4)]
+    _check(load().tp_reference_basis(n, basis, blocks, penalty_C, *(a.ctypes.data for a in out)))
+    return tuple(out)
 
 
 def reference_eigen(n: int, penalty_C: float = 2.0, op: int = OP_CELL):

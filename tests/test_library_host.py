@@ -208,3 +208,37 @@ def test_patch_blocks_validation_before_device():
         m.cells[d], m.h[d] = 2, 0.5
     out = ctypes.c_void_p()
     assert lib.tp_plan_create_mesh(ctypes.byref(m), ctypes.byref(opts), ctypes.byref(out)) == -2
+
+
+@pytest.mark.parametrize("C", [2.0, 3.5])
+def test_hermite_reference_tables_match_oracle(C):
+    """The library's own Hermite-type tables (host code, no GPU) against the
+    oracle's, two independent implementations of the basis of
+    eq. (hermite_conditions)."""
+    from oracle import hermite
+    M, K, A, T = tpfdm.reference_basis(4, tpfdm.BASIS_HERMITE, penalty_C=C)
+    Mo, Ko = hermite.mass_stiffness(3)
+    assert np.allclose(M, Mo, atol=1e-14)
+    assert np.allclose(K, Ko, atol=1e-13)
+    assert np.allclose(A, hermite.penalized_stiffness(3, C), atol=1e-12)
+    assert np.allclose(T, hermite.transform(3), atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [4, 6, 8])
+def test_patch_reference_tables_match_oracle(n):
+    from oracle import patch
+    M, K, A, T = tpfdm.reference_basis(n, blocks=tpfdm.BLOCKS_PATCHES)
+    Mo, Ko, Ao = patch.patch_factors(n // 2 - 1)
+    assert np.allclose(M, Mo, atol=1e-14)
+    assert np.allclose(K, Ko, atol=1e-12 * np.abs(Ko).max())
+    assert np.allclose(A, Ao, atol=1e-12 * np.abs(Ao).max())
+    assert np.array_equal(T, np.eye(n))
+
+
+def test_reference_basis_errors():
+    lib = tpfdm.load()
+    assert lib.tp_reference_basis(5, tpfdm.BASIS_HERMITE, 0, 2.0, None, None, None, None) == -2
+    assert lib.tp_reference_basis(5, 0, tpfdm.BLOCKS_PATCHES, 2.0, None, None, None, None) == -2
+    assert lib.tp_reference_basis(4, 7, 0, 2.0, None, None, None, None) == -1
+    assert lib.tp_reference_basis(4, 0, 3, 2.0, None, None, None, None) == -1
+    assert lib.tp_reference_basis(4, 0, 0, -1.0, None, None, None, None) == -1
