@@ -400,7 +400,8 @@ def run_suite(args, stream):
 # (degree, cells per side, dtypes, basis): the Lagrange basis, and the
 # Hermite-type basis (two-layer face access) at degree 3
 SIPG_SUITE = [(3, 128, ("f64", "f32"), "lagrange"), (3, 128, ("f64", "f32"), "hermite"),
-              (3, 64, ("f64",), "lagrange"), (3, 64, ("f64",), "hermite"), (2, 128, ("f64",), "lagrange")]
+              (3, 64, ("f64",), "lagrange"), (3, 64, ("f64",), "hermite"), (2, 128, ("f64",), "lagrange"),
+              (7, 64, ("f64", "f32"), "lagrange")]
 
 
 def run_sipg(args, stream):

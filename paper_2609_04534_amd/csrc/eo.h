@@ -186,6 +186,13 @@ __device__ __forceinline__ void load_table(TC (&dst)[COUNT], const TC* __restric
     }
 }
 
+// Stages COUNT table entries in LDS (stab) for reads from there.
+template <typename TC, int COUNT>
+__device__ __forceinline__ void stage_table(const TC* __restrict__ tab, TC* stab) {
+    for (int e = threadIdx.x; e < COUNT; e += 64) stab[e] = tab[e];
+    wave_sync();
+}
+
 // ------------------------------------------------------------ tile bodies
 // Each body handles one tile with the lane's pencil coordinates pc and the
 // per-block scalings (sx, sy, sz); it starts with the lane's z-pencil in

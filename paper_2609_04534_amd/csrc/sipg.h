@@ -371,18 +371,20 @@ __device__ __forceinline__ void sipg_cell(const TS* __restrict__ u, const MeshAr
 // ============================================================ one cell per wave (n >= 5)
 // The cell's block lives in an LDS slab (Slab<N> layout, one pencil per lane
 // and phase, as in the even-odd wave kernels); the volume product is the
-// even-odd LDS apply with the cell-diagonal P_hat.  The six face terms are
-// slabs over the two tangential indices: lane (a, b) accumulates alpha and
+// even-odd LDS apply with the cell-diagonal P_hat, done first.  The six face
+// terms are slabs over the two tangential indices, kept in the volume
+// product's scratch once that is free: lane (a, b) accumulates alpha and
 // beta of every face from the source block's n values along the normal at
-// (a, b); the tangential mass M (.) M of all twelve slabs runs as two LDS
-// passes of one n-pencil per task (12 n tasks per pass spread over the
-// wave); finally lane (j, k) adds the face terms to its x-pencil of the
-// volume product.
+// (a, b); the tangential mass M (.) M of all twelve slabs runs as two
+// in-place LDS passes of one n-pencil per task (a task owns its row, then
+// its column; 12 n tasks per pass spread over the wave); finally lane (j, k)
+// adds the face terms to its x-pencil of the volume product.
 template <int N, typename T>
 struct WaveLds {
-    T s[Slab<N>::size], t1[Slab<N>::size], t2[Slab<N>::size];
-    T fs[2][12][N * N];                                    // face slabs, two pass buffers
+    T s[Slab<N>::size];          // the cell's block, then its volume product
+    T t[2 * Slab<N>::size];      // volume scratch t1 | t2, then the twelve face slabs
     T tab[2 * (EOShape<N>::SE + EOShape<N>::SO)];          // table staging
+    static_assert(12 * N * N <= 2 * Slab<N>::size, "face slabs exceed the volume scratch");
 };
 
 // The lane's x-pencil y[i] = (A u)_c at (i, j, k) with (j, k) = (pc.pa,
@@ -410,7 +412,18 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
     const uint32_t cy = rr % static_cast<uint32_t>(G.my);
     const uint32_t cx = rr / static_cast<uint32_t>(G.my);
     const T sx = static_cast<T>(G.sx), sy = static_cast<T>(G.sy), sz = static_cast<T>(G.sz);
-    // --- face slabs: alpha (2 f) and beta (2 f + 1) of face f = 2 axis + upper
+    // --- the cell's own block into the slab, volume product in place
+    if (pc.act) {
+        T x[N];
+        pencil_load<N, VP>(x, ub + block_base(c, lb, N3) + (static_cast<int64_t>((pa * N + pb) * N) << lb), lb);
+#pragma unroll
+        for (int k = 0; k < N; ++k) L.s[SL::at(pa, pb, k)] = x[k];
+    }
+    wave_sync();
+    eo_apply_lds<N, T>(pc, L.s, L.s, L.t, L.t + SL::size, ME, MO, PE, PO, sx, sy, sz);   // ends synced
+    // --- face slabs in the free scratch: alpha (2 f) and beta (2 f + 1) of
+    // face f = 2 axis + upper, slab sl at fs + sl n^2
+    T* fs = L.t;
     const int64_t syz = static_cast<int64_t>(G.my) * G.mz;
     auto face = [&](auto Dc, auto UPc, bool interior, int64_t d, T s) {
         constexpr int D = decltype(Dc)::value;
@@ -432,8 +445,8 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
                 if (k == 0) be = cb0 * wk;
                 if (k == N - 1) be = fma(cbn, wk, be);
             }
-            L.fs[0][2 * f][pa * N + pb] = al;
-            L.fs[0][2 * f + 1][pa * N + pb] = be;
+            fs[(2 * f) * N * N + pa * N + pb] = al;
+            fs[(2 * f + 1) * N * N + pa * N + pb] = be;
         }
     };
     using I0 = std::integral_constant<int, 0>;
@@ -447,15 +460,7 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
     face(I1{}, BT{}, cy + 1 < static_cast<uint32_t>(G.my), G.mz, sy);
     face(I2{}, BF{}, cz > 0, -1, sz);
     face(I2{}, BT{}, cz + 1 < static_cast<uint32_t>(G.mz), 1, sz);
-    // --- the cell's own block into the slab, volume product in place
-    if (pc.act) {
-        T x[N];
-        pencil_load<N, VP>(x, ub + block_base(c, lb, N3) + (static_cast<int64_t>((pa * N + pb) * N) << lb), lb);
-#pragma unroll
-        for (int k = 0; k < N; ++k) L.s[SL::at(pa, pb, k)] = x[k];
-    }
     wave_sync();
-    eo_apply_lds<N, T>(pc, L.s, L.s, L.t1, L.t2, ME, MO, PE, PO, sx, sy, sz);
     // --- tangential mass of the twelve slabs: rows (second index), then columns
     constexpr int HC = S::HC, H = S::H;
     auto mass_pencil = [&](const T (&xin)[N], T (&out)[N]) {
@@ -468,20 +473,20 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
         const int sl = task / N, a = task - (task / N) * N;
         T xin[N], out[N];
 #pragma unroll
-        for (int b = 0; b < N; ++b) xin[b] = L.fs[0][sl][a * N + b];
+        for (int b = 0; b < N; ++b) xin[b] = fs[sl * N * N + a * N + b];
         mass_pencil(xin, out);
 #pragma unroll
-        for (int b = 0; b < N; ++b) L.fs[1][sl][a * N + b] = out[b];
+        for (int b = 0; b < N; ++b) fs[sl * N * N + a * N + b] = out[b];
     }
     wave_sync();
     for (int task = threadIdx.x; task < 12 * N; task += 64) {
         const int sl = task / N, b = task - (task / N) * N;
         T xin[N], out[N];
 #pragma unroll
-        for (int a = 0; a < N; ++a) xin[a] = L.fs[1][sl][a * N + b];
+        for (int a = 0; a < N; ++a) xin[a] = fs[sl * N * N + a * N + b];
         mass_pencil(xin, out);
 #pragma unroll
-        for (int a = 0; a < N; ++a) L.fs[0][sl][a * N + b] = out[a];
+        for (int a = 0; a < N; ++a) fs[sl * N * N + a * N + b] = out[a];
     }
     wave_sync();
     // --- the lane's x-pencil of the volume product plus the face terms
@@ -497,22 +502,22 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
         }
         const T ej0 = j == 0 ? T(1) : T(0), ejn = j == N - 1 ? T(1) : T(0);
         const T ek0 = k == 0 ? T(1) : T(0), ekn = k == N - 1 ? T(1) : T(0);
-        const T ax0 = L.fs[0][0][j * N + k], bx0 = L.fs[0][1][j * N + k];
-        const T ax1 = L.fs[0][2][j * N + k], bx1 = L.fs[0][3][j * N + k];
+        const T ax0 = fs[0 * N * N + j * N + k], bx0 = fs[1 * N * N + j * N + k];
+        const T ax1 = fs[2 * N * N + j * N + k], bx1 = fs[3 * N * N + j * N + k];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             T v = L.s[SL::at(i, j, k)];
             v = fma(F.g0[i], bx0, fma(F.g1[i], bx1, v));                       // x faces, beta
             if (i == 0) v += ax0;                                               // x faces, alpha
             if (i == N - 1) v += ax1;
-            v = fma(ej0, L.fs[0][4][i * N + k], v);                             // y faces
-            v = fma(g0j, L.fs[0][5][i * N + k], v);
-            v = fma(ejn, L.fs[0][6][i * N + k], v);
-            v = fma(g1j, L.fs[0][7][i * N + k], v);
-            v = fma(ek0, L.fs[0][8][i * N + j], v);                             // z faces
-            v = fma(g0k, L.fs[0][9][i * N + j], v);
-            v = fma(ekn, L.fs[0][10][i * N + j], v);
-            v = fma(g1k, L.fs[0][11][i * N + j], v);
+            v = fma(ej0, fs[4 * N * N + i * N + k], v);                             // y faces
+            v = fma(g0j, fs[5 * N * N + i * N + k], v);
+            v = fma(ejn, fs[6 * N * N + i * N + k], v);
+            v = fma(g1j, fs[7 * N * N + i * N + k], v);
+            v = fma(ek0, fs[8 * N * N + i * N + j], v);                             // z faces
+            v = fma(g0k, fs[9 * N * N + i * N + j], v);
+            v = fma(ekn, fs[10 * N * N + i * N + j], v);
+            v = fma(g1k, fs[11 * N * N + i * N + j], v);
             y[i] = v;
         }
     }

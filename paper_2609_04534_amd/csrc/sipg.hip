@@ -28,11 +28,19 @@ __global__ __launch_bounds__(64, 2) void k_sipg_wave(const T* __restrict__ u, T*
                                                   const T* __restrict__ tab, FaceRef<N, T> F) {
     constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
     __shared__ WaveLds<N, T> L;
+    // FP64: the tables are read from LDS (in registers they would take half
+    // the register file); FP32: from registers
     T TB[TAB];
-    load_table<T, TAB>(TB, tab, L.tab);
+    const T* tb = TB;
+    if constexpr (sizeof(T) == 8) {
+        stage_table<T, TAB>(tab, L.tab);
+        tb = L.tab;
+    } else {
+        load_table<T, TAB>(TB, tab, L.tab);
+    }
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
     T y[N];
-    wave_sipg_cell<N, T, VP>(u, G, TB, F, c, L, y);
+    wave_sipg_cell<N, T, VP>(u, G, tb, F, c, L, y);
     const Pencil<N> pc(1);
     if (pc.act) {
         T* vb = v + G.offset + block_base(c, G.logB, N * N * N);
