@@ -2,9 +2,9 @@
 // plan: A x = b in FP64 with the cell-wise fast-diagonalization block-Jacobi
 // preconditioner of Sec. 5.2 (z = D^{-1} r, the cell blocks of
 // eq. (cell_block) with the interior stencil on every cell), applied in FP64
-// or FP32.  The paper's solver wraps this preconditioner in Chebyshev
-// smoothing inside a multigrid cycle (Sec. 5); here it preconditions CG
-// directly.
+// or FP32, or by one multigrid V-cycle (the paper's solver, Sec. 5: the same
+// block inverse inside Chebyshev smoothing on every level; mg.hip), set with
+// tp_pcg_set_multigrid.
 //
 // One iteration is five launches, none of which needs the host:
 //   1. q = A p with the per-workgroup partial sums of (p, q)
@@ -362,8 +362,9 @@ __device__ __forceinline__ void load_inverse_tables(const TI* __restrict__ tab, 
 }
 
 // z = D^{-1} r of the wave's cell in precision TI (rv: the lane's z-pencil of
-// r in FP64), written in FP64 at zp; returns the lane's partial (r, z).
-template <int N, typename TI>
+// r in FP64), written in FP64 at zp (one vector store per 16 bytes when VP:
+// the pencil is contiguous); returns the lane's partial (r, z).
+template <int N, typename TI, bool VP = false>
 __device__ __forceinline__ double wave_precondition(const double (&rv)[N], double* __restrict__ zp, int lb,
                                                     const Pencil<N>& pc, TI* slab, const TI* T, const TI* lam,
                                                     TI sx, TI sy, TI sz) {
@@ -376,12 +377,13 @@ __device__ __forceinline__ double wave_precondition(const double (&rv)[N], doubl
     eo_inverse_lds<N, TI>(pc, slab, T, T + EOShape<N>::SE, lam, sx, sy, sz);
     double rz = 0.0;
     if (pc.act) {
+        double zv[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            const double zv = static_cast<double>(slab[SL::at(pc.pa, pc.pb, k)]);
-            zp[static_cast<int64_t>(k) << lb] = zv;
-            rz = fma(rv[k], zv, rz);
+            zv[k] = static_cast<double>(slab[SL::at(pc.pa, pc.pb, k)]);
+            rz = fma(rv[k], zv[k], rz);
         }
+        pencil_store<N, VP>(zp, zv, lb);
     }
     return rz;
 }
@@ -439,8 +441,9 @@ __global__ __launch_bounds__(64, 2) void k_pcg_start_wave(const double* __restri
     }
 }
 
-// 3.  (see k_pcg_update), one cell per workgroup.
-template <int N, typename TI>
+// 3.  (see k_pcg_update), one cell per workgroup; VP: the lane's pencils are
+// contiguous (layout B = 1), moved with vector loads and stores.
+template <int N, typename TI, bool VP>
 __global__ __launch_bounds__(64, 2) void k_pcg_update_wave(double* __restrict__ x, double* __restrict__ r,
                                                          double* __restrict__ z, const double* __restrict__ p,
                                                          const double* __restrict__ q, MeshArgs G,
@@ -460,20 +463,25 @@ __global__ __launch_bounds__(64, 2) void k_pcg_update_wave(double* __restrict__ 
                        (static_cast<int64_t>((pc.pa * N + pc.pb) * N) << lb);
     double rv[N], rr = 0.0;
     if (pc.act) {
+        double xv[N], pv[N], qv[N];
+        pencil_load<N, VP>(xv, x + pb, lb);
+        pencil_load<N, VP>(pv, p + pb, lb);
+        pencil_load<N, VP>(qv, q + pb, lb);
+        pencil_load<N, VP>(rv, r + pb, lb);
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            const int64_t o = pb + (static_cast<int64_t>(k) << lb);
-            x[o] = fma(alpha, p[o], x[o]);
-            rv[k] = fma(-alpha, q[o], r[o]);
-            r[o] = rv[k];
+            xv[k] = fma(alpha, pv[k], xv[k]);
+            rv[k] = fma(-alpha, qv[k], rv[k]);
             rr = fma(rv[k], rv[k], rr);
         }
+        pencil_store<N, VP>(x + pb, xv, lb);
+        pencil_store<N, VP>(r + pb, rv, lb);
     } else {
 #pragma unroll
         for (int k = 0; k < N; ++k) rv[k] = 0.0;
     }
-    double rz = wave_precondition<N, TI>(rv, z + pb, lb, pc, slab, T, stab + TABM, static_cast<TI>(G.sx),
-                                         static_cast<TI>(G.sy), static_cast<TI>(G.sz));
+    double rz = wave_precondition<N, TI, VP>(rv, z + pb, lb, pc, slab, T, stab + TABM, static_cast<TI>(G.sx),
+                                             static_cast<TI>(G.sy), static_cast<TI>(G.sz));
     rz = wave_sum(rz);
     rr = wave_sum(rr);
     if (threadIdx.x == 0) {
@@ -627,9 +635,12 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                 } else if constexpr (kLane)
                     hipLaunchKernelGGL((k_pcg_update<N, TI, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->z,
                                        s->p, s->q, G, E, s->st, s->part, cnt);
+                else if (vp)
+                    hipLaunchKernelGGL((k_pcg_update_wave<N, TI, true>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r,
+                                       s->z, s->p, s->q, G, tabS, s->st, s->part, cnt);
                 else
-                    hipLaunchKernelGGL((k_pcg_update_wave<N, TI>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->z,
-                                       s->p, s->q, G, tabS, s->st, s->part, cnt);
+                    hipLaunchKernelGGL((k_pcg_update_wave<N, TI, false>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r,
+                                       s->z, s->p, s->q, G, tabS, s->st, s->part, cnt);
                 hipLaunchKernelGGL(k_pcg_reduce_beta, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
                 hipLaunchKernelGGL(k_pcg_dir, dim3(dgrid), dim3(256), 0, cs, s->z, s->p, s->elems, s->st);
             }
