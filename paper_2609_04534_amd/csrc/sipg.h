@@ -434,13 +434,18 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
         const T cb0 = first ? T(0.5) * s : T(0);
         const T cbn = first ? T(0) : T(-0.5) * s;
         if (pc.act) {
+            // normal to z the n values are the lane's contiguous pencil: one
+            // vector load per 16 bytes when VP
+            T wv[N];
+            if constexpr (D == 2)
+                pencil_load<N, VP>(wv, w + (static_cast<int64_t>(fq<N, D>(0, pa, pb)) << lb), lb);
             T al = T(0), be = T(0);
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const T in = UP ? fma(T(-0.5), F.g0[k], k == 0 ? -F.sigma : T(0))
                                 : fma(T(0.5), F.g1[k], k == N - 1 ? -F.sigma : T(0));
                 const T bd = UP ? T(-0.5) * F.g1[k] : T(0.5) * F.g0[k];
-                const T wk = ldc<T>(w + (static_cast<int64_t>(fq<N, D>(k, pa, pb)) << lb));
+                const T wk = D == 2 ? wv[k] : ldc<T>(w + (static_cast<int64_t>(fq<N, D>(k, pa, pb)) << lb));
                 al = fma(s * (interior ? in : bd), wk, al);
                 if (k == 0) be = cb0 * wk;
                 if (k == N - 1) be = fma(cbn, wk, be);
