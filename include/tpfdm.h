@@ -388,7 +388,9 @@ tp_status tp_pcg_poll(tp_pcg* pcg, tp_pcg_summary* summary);
  * vectors and kept for the life of the process (shared by hierarchies with
  * the same coarsest level).  Needs tp_setup_inverse(TP_OP_CELL,
  * TP_FACTOR_SCALED) on the plan (TP_ERR_STATE).  tp_mg_create allocates the
- * level vectors (host-synchronous); tp_mg_vcycle enqueues x <- V(b) (FP64
+ * level vectors (host-synchronous); the plan must outlive the object, and
+ * every V-cycle (alone or inside a solve) returns TP_ERR_STATE unless the
+ * plan's current inverse setup is still TP_OP_CELL, TP_FACTOR_SCALED; tp_mg_vcycle enqueues x <- V(b) (FP64
  * smoothing; b, x: distinct device vectors of the plan's layout, x
  * overwritten, TP_ERR_ARG when null or equal).  The level vectors are the
  * object's scratch: one V-cycle at a time per object, and a solver that uses

@@ -445,6 +445,9 @@ void free_mg(tp_mg* m) {
 
 namespace tpfdm {
 tp_status mg_enqueue_vcycle(const tp_mg* m, const double* b, double* u, const void* st, bool f32, hipStream_t s) {
+    // the smoother reads the plan's cell-block eigen tables at every enqueue
+    if (m->plan->inverse_op != TP_OP_CELL || m->plan->factor_mode != TP_FACTOR_SCALED)
+        return set_error(TP_ERR_STATE, "the plan's inverse setup is no longer TP_OP_CELL, TP_FACTOR_SCALED");
     const PcgState* ps = static_cast<const PcgState*>(st);
     return f32 ? vcycle_dispatch<float>(m, b, u, ps, s) : vcycle_dispatch<double>(m, b, u, ps, s);
 }

@@ -245,3 +245,10 @@ def test_mg_errors():
         with pytest.raises(tpfdm.TpfdmError) as e:
             solver.set_norm(2)
         assert e.value.status == -1
+    # the plan's inverse set up for another operator afterwards: refused
+    with _cube_plan(2, 2) as plan, tpfdm.MG(plan) as V:
+        buf = torch.zeros(plan.vector_elems, dtype=torch.float64, device="cuda")
+        plan.setup_inverse(tpfdm.OP_CELL, mode=tpfdm.FACTOR_GENERAL)
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            V.vcycle(buf, torch.zeros_like(buf))
+        assert e.value.status == -9
