@@ -177,15 +177,18 @@ tp_status tp_plan_create(const tp_group* groups, int32_t ngroups,
  * LAGRANGE: Lagrange polynomials on the n Gauss-Lobatto points of [0, 1]
  *   (coefficients = nodal values).
  * HERMITE: the Hermite-type basis of eq. (hermite_conditions), mesh plans
- *   with n = 4 (p = 3) only (TP_ERR_UNSUPPORTED otherwise, and with
+ *   with n >= 4 (p >= 3; TP_ERR_UNSUPPORTED for n < 4, and for n = 4 with
  *   TP_MAP_WAVE): coefficient 0 is the value and 1 the derivative at 0,
  *   n-2 the derivative and n-1 the value at 1, so a face term reads two
  *   layers of the neighbour (eq. (hermite_traces_3d)).  The endpoint
- *   functions are the cubic Hermite polynomials.  Every operator, inverse,
- *   solve, PCG and multigrid call acts on coefficients in this basis (the
- *   same discrete space and operator: A_H = T3^T A_L T3 with T3 = T (x) T
- *   (x) T cell by cell, T[i][j] = psi_j(x_i)); tp_change_basis converts
- *   to and from nodal values. */
+ *   functions are the cubic Hermite polynomials, the interior ones bubbles
+ *   x^2 (1-x)^2 times Lagrange polynomials on the interior nodes of the
+ *   (n-2)-point Gauss-Lobatto rule.  The coupled operator, tp_setup_inverse,
+ *   PCG and tp_change_basis act on coefficients in this basis (the same
+ *   discrete space and operator: A_H = T3^T A_L T3 with T3 = T (x) T (x) T
+ *   cell by cell, T[i][j] = psi_j(x_i)); with n = 4 also the block calls
+ *   (tp_apply with a block operator, tp_apply_inverse, tp_solve, graphs)
+ *   and multigrid, which return TP_ERR_UNSUPPORTED for n >= 5. */
 typedef enum { TP_BASIS_LAGRANGE = 0, TP_BASIS_HERMITE = 1 } tp_basis;
 
 typedef struct {
@@ -442,7 +445,7 @@ tp_status tp_reference_matrices(int32_t n, double penalty_C, double* M, double* 
  * and A_hat (the cell or patch block operator), and T, the change of basis
  * (nodal values = T * coefficients; the identity for the Lagrange basis).
  * Errors: TP_ERR_ARG (values), TP_ERR_UNSUPPORTED (the combinations plans
- * reject: Hermite-type basis other than n = 4 cells, patches with odd n). */
+ * reject: Hermite-type basis for n < 4 or for patches, patches with odd n). */
 tp_status tp_reference_basis(int32_t n, int32_t basis, int32_t blocks, double penalty_C, double* M,
                              double* K, double* A, double* T);
 

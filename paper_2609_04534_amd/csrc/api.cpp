@@ -283,6 +283,15 @@ static tp_status group_solve(const Plan& p, const GroupInfo& g, const double* b,
 
 namespace {
 tp_status hermite_reference(int n, RefData& r);
+// Mesh plans in the Hermite-type basis with n >= 5 serve the coupled
+// operator, PCG and the change of basis; their block calls are not built.
+bool hermite_wave(const Plan& p) {
+    return p.basis == TP_BASIS_HERMITE && !p.groups.empty() && p.groups[0].n > kLaneMaxN;
+}
+tp_status hermite_wave_error() {
+    return set_error(TP_ERR_UNSUPPORTED,
+                     "block calls on plans in the Hermite-type basis need n = 4 (n >= 5 serves the coupled operator)");
+}
 }
 
 extern "C" {
@@ -313,8 +322,8 @@ tp_status tp_reference_basis(int32_t n, int32_t basis, int32_t blocks, double pe
         return set_error(TP_ERR_ARG, "penalty_C must be finite and > 0");
     if (basis != TP_BASIS_LAGRANGE && basis != TP_BASIS_HERMITE) return set_error(TP_ERR_ARG, "invalid basis");
     if (blocks != TP_BLOCKS_CELLS && blocks != TP_BLOCKS_PATCHES) return set_error(TP_ERR_ARG, "invalid blocks");
-    if (basis == TP_BASIS_HERMITE && (n != 4 || blocks != TP_BLOCKS_CELLS))
-        return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis is supported for n = 4 cells");
+    if (basis == TP_BASIS_HERMITE && (n < 4 || blocks != TP_BLOCKS_CELLS))
+        return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis is supported for cells with n >= 4");
     if (blocks == TP_BLOCKS_PATCHES && (n % 2 != 0 || n < 4))
         return set_error(TP_ERR_UNSUPPORTED, "patch blocks have n = 2 (p+1) in {4, 6, 8}");
     RefData r;
@@ -419,13 +428,12 @@ tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opt
         }
     if (o.mapping < TP_MAP_AUTO || o.mapping > TP_MAP_WAVE) return set_error(TP_ERR_ARG, "invalid mapping");
     if (basis == TP_BASIS_HERMITE) {
-        // the even-odd wave kernels need a centrosymmetric basis: the
-        // Hermite-type one is served by the lane kernels (n = 4)
+        // degree p >= 3; n = 4 runs the lane kernels, n >= 5 the wave kernels
         for (int gi = 0; gi < ngroups; ++gi)
-            if (groups[gi].n != 4)
-                return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis is supported for n = 4 (p = 3)");
-        if (o.mapping == TP_MAP_WAVE)
-            return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis runs on the lane mapping");
+            if (groups[gi].n < 4)
+                return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis needs n >= 4 (p >= 3)");
+        if (o.mapping == TP_MAP_WAVE && ngroups > 0 && groups[0].n == 4)
+            return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis of n = 4 runs on the lane mapping");
     }
 
     // validate groups and their element ranges
@@ -562,6 +570,32 @@ tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opt
         if (p->basis == TP_BASIS_HERMITE) {
             st = hermite_reference(g.n, r);
             if (st != TP_OK) break;
+            if (g.n > kLaneMaxN) {
+                // the wave kernels work on the coefficients with the sign of
+                // the derivative-at-1 function flipped, where the matrices
+                // are centrosymmetric: tables of D X D, D = diag(hermite_sign)
+                const int hc = (g.n + 1) / 2, h = g.n / 2;
+                const int cnt = 2 * (hc * hc + h * h);
+                double Mf[kMaxN * kMaxN], Kf[kMaxN * kMaxN], Af[kMaxN * kMaxN], Ff[kMaxN * kMaxN];
+                for (int i = 0; i < g.n; ++i)
+                    for (int j = 0; j < g.n; ++j) {
+                        const double sg = hermite_sign(g.n, i) * hermite_sign(g.n, j);
+                        Mf[i * g.n + j] = sg * r.M[i * g.n + j];
+                        Kf[i * g.n + j] = sg * r.K[i * g.n + j];
+                        Af[i * g.n + j] = sg * r.A[i * g.n + j];
+                        Ff[i * g.n + j] = Af[i * g.n + j] - Kf[i * g.n + j];
+                    }
+                const double* P3[3] = {Kf, Af, Ff};
+                const int slot[3] = {EO_APPLY_K, EO_APPLY_A, EO_APPLY_F};
+                for (int t = 0; t < 3 && st == TP_OK; ++t) {
+                    if (!build_eo_apply(g.n, Mf, P3[t], tab)) {
+                        st = set_error(TP_ERR_UNSUPPORTED, "sign-flipped Hermite matrices are not centrosymmetric");
+                        break;
+                    }
+                    st = upload_eo(*p, g.n, slot[t], tab, cnt);
+                }
+                continue;
+            }
             const int n2 = g.n * g.n;
             for (int i = 0; i < n2; ++i) tab[i] = r.M[i], tab[n2 + i] = r.K[i];
             st = upload_eo(*p, g.n, EO_PLAIN_K, tab, 2 * n2);
@@ -602,7 +636,7 @@ tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opt
         st = upload_eo(*p, g.n, EO_PLAIN_A, tab, 2 * n2);
     }
     if (st == TP_OK) st = persistent_setup(*p);
-    if (st == TP_OK && p->ref[8].built) {  // MFMA operand tables of n = 8
+    if (st == TP_OK && p->ref[8].built && p->basis != TP_BASIS_HERMITE) {  // MFMA operand tables of n = 8
         const RefData& r8 = p->ref[8];
         for (int op = 0; op < 2 && st == TP_OK; ++op)
             for (int et = 0; et < 2 && st == TP_OK; ++et) {
@@ -688,6 +722,7 @@ tp_status tp_apply(tp_plan* plan, tp_operator op, const void* u, void* v, tp_dty
         if (!plan->mesh) return set_error(TP_ERR_UNSUPPORTED, "the coupled SIPG operator needs a mesh plan");
         return launch_sipg(*plan, plan->groups[0], op == TP_OP_SIPG_FACE, u, v, dtype, stream);
     }
+    if (hermite_wave(*plan)) return hermite_wave_error();
     if (plan->persistent) return launch_apply_persistent(*plan, op, u, v, dtype, stream);
     tp_status st = TP_OK;
     for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
@@ -735,8 +770,13 @@ tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, d
         double tab[kEOSlot];
         const int cnt = ((n + 1) / 2) * ((n + 1) / 2) + (n / 2) * (n / 2) + n;
         tp_status st = TP_OK;
-        if (plan->basis != TP_BASIS_HERMITE) {   // the lane kernels of the Hermite basis use plain factors
-            if (!build_eo_inverse(n, r.S, r.lam, tab))
+        if (plan->basis != TP_BASIS_HERMITE || n > kLaneMaxN) {   // the lane kernels use plain factors
+            // Hermite-type basis: eigenvectors of the sign-flipped pair (D S)
+            double Sf[kMaxN * kMaxN];
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j)
+                    Sf[i * n + j] = (plan->basis == TP_BASIS_HERMITE ? hermite_sign(n, i) : 1.0) * r.S[i * n + j];
+            if (!build_eo_inverse(n, Sf, r.lam, tab))
                 return set_error(TP_ERR_UNSUPPORTED, "eigenvectors of n=" + std::to_string(n) +
                                                          " are not split into symmetric and antisymmetric ones");
             st = upload_eo(*plan, n, EO_INV, tab, cnt);
@@ -749,7 +789,7 @@ tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, d
             st = upload_eo(*plan, n, EO_PLAIN_S, tab, n * n + n);
             if (st != TP_OK) return st;
         }
-        if (n == 8) {  // MFMA operand tables of the inverse
+        if (n == 8 && plan->basis != TP_BASIS_HERMITE) {  // MFMA operand tables of the inverse
             for (int et = 0; et < 2; ++et) {
                 std::vector<uint8_t> tabv;
                 build_mfma_tables(r.M, r.A, r.S, r.lam, et == 1, nullptr, &tabv);
@@ -769,6 +809,7 @@ tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode, d
 
 tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype, hipStream_t stream) {
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (hermite_wave(*plan)) return hermite_wave_error();
     if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
     if (plan->inverse_op < 0) return set_error(TP_ERR_STATE, "tp_setup_inverse has not succeeded on this plan");
     if (plan->vec_elems > 0 && (!r || !x)) return set_error(TP_ERR_ARG, "r and x must be non-null");
@@ -784,6 +825,7 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
 tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, double rtol, int32_t maxit,
                    int32_t* iters, double* relres, tp_solve_summary* summary, hipStream_t stream) {
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (hermite_wave(*plan)) return hermite_wave_error();
     if (plan->inverse_op < 0 || (plan->factor_mode == TP_FACTOR_SCALED && plan->inverse_op != TP_OP_CELL))
         return set_error(TP_ERR_STATE, "tp_solve needs tp_setup_inverse(TP_OP_CELL) first");
     if (inner != TP_F64 && inner != TP_F32 && inner != TP_F16 && inner != TP_BF16)
@@ -848,6 +890,7 @@ tp_status tp_graph_create(tp_plan* plan, tp_graph_op what, tp_operator op, tp_dt
                           void* out, double rtol, int32_t maxit, int32_t* iters, double* relres, tp_graph** graph) {
     if (!plan || !graph) return set_error(TP_ERR_ARG, "plan and graph must be non-null");
     *graph = nullptr;
+    if (hermite_wave(*plan)) return hermite_wave_error();
     if (what < TP_GRAPH_APPLY || what > TP_GRAPH_SOLVE) return set_error(TP_ERR_ARG, "invalid graph op");
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);

@@ -52,6 +52,50 @@ __global__ __launch_bounds__(64) void k_change_basis(const double* __restrict__ 
     for (int q = 0; q < N3; ++q) v[base + (static_cast<int64_t>(q) << logB)] = a[q];
 }
 
+// n >= 5: one cell per 64-thread workgroup, the block in LDS, each pass one
+// output value per thread and step.
+template <int N>
+__global__ __launch_bounds__(64) void k_change_basis_wave(const double* __restrict__ u, double* __restrict__ v,
+                                                          int64_t offset, int logB, BasisTab<N> X) {
+    constexpr int N3 = N * N * N;
+    __shared__ double a[N3], b[N3];
+    const int64_t base = offset + block_base(blockIdx.x, logB, N3);
+    for (int e = threadIdx.x; e < N3; e += 64) a[e] = u[base + (static_cast<int64_t>(e) << logB)];
+    __syncthreads();
+    // the three axes: out(i, j, k) = sum_m X[axis index][m] in(.. m ..)
+    for (int e = threadIdx.x; e < N3; e += 64) {
+        const int i = e / (N * N), jk = e % (N * N);
+        double s = 0.0;
+        for (int m = 0; m < N; ++m) s = fma(X.x[i * N + m], a[m * N * N + jk], s);
+        b[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < N3; e += 64) {
+        const int i = e / (N * N), j = (e / N) % N, k = e % N;
+        double s = 0.0;
+        for (int m = 0; m < N; ++m) s = fma(X.x[j * N + m], b[(i * N + m) * N + k], s);
+        a[e] = s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < N3; e += 64) {
+        const int ij = e / N, k = e % N;
+        double s = 0.0;
+        for (int m = 0; m < N; ++m) s = fma(X.x[k * N + m], a[ij * N + m], s);
+        v[base + (static_cast<int64_t>(e) << logB)] = s;
+    }
+}
+
+template <int N>
+tp_status change_basis_wave(const RefData& r, const GroupInfo& g, bool to_nodal, const double* u, double* v,
+                            hipStream_t stream) {
+    BasisTab<N> X;
+    for (int i = 0; i < N * N; ++i) X.x[i] = to_nodal ? r.T[i] : r.Ti[i];
+    hipLaunchKernelGGL((k_change_basis_wave<N>), dim3(static_cast<unsigned>(g.nblocks)), dim3(64), 0, stream, u, v,
+                       g.offset, g.logB, X);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TP_OK : hip_error(e, "change of basis launch");
+}
+
 }  // namespace
 }  // namespace tpfdm
 
@@ -71,7 +115,14 @@ extern "C" tp_status tp_change_basis(tp_plan* plan, int32_t to_nodal, const doub
                                             hipMemcpyDeviceToDevice, stream);
         return e == hipSuccess ? TP_OK : hip_error(e, "change of basis copy");
     }
-    if (g.n != 4) return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis is supported for n = 4");
+    switch (g.n) {
+        case 5: return change_basis_wave<5>(plan->ref[5], g, to_nodal != 0, u, v, stream);
+        case 6: return change_basis_wave<6>(plan->ref[6], g, to_nodal != 0, u, v, stream);
+        case 7: return change_basis_wave<7>(plan->ref[7], g, to_nodal != 0, u, v, stream);
+        case 8: return change_basis_wave<8>(plan->ref[8], g, to_nodal != 0, u, v, stream);
+        default: break;
+    }
+    if (g.n != 4) return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis needs n >= 4");
     const RefData& r = plan->ref[4];
     BasisTab<4> X;
     for (int i = 0; i < 16; ++i) X.x[i] = to_nodal ? r.T[i] : r.Ti[i];

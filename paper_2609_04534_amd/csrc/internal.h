@@ -23,6 +23,9 @@ int gen_eigen(int n, const double* M, const double* P, double* S, double* lam);
 void endpoint_derivatives(int n, double* g0, double* g1);
 void prolongation_1d(int n, double* P0, double* P1);
 // Hermite-type basis: T[i * n + j] = psi_j(x_i) at the Gauss-Lobatto nodes (n >= 4).
+// hermite_sign(n, i): -1 for the derivative-at-1 function (i = n - 2), else 1;
+// conjugated by this sign the basis is symmetric under x -> 1 - x.
+__host__ __device__ constexpr double hermite_sign(int n, int i) { return i == n - 2 ? -1.0 : 1.0; }
 void hermite_transform(int n, double* T);
 bool invert_small(int n, const double* A, double* Ai);
 // X <- T^T X T.

@@ -313,8 +313,9 @@ __global__ __launch_bounds__(64) void k_pcg_axpy(double* __restrict__ x, double*
 // vector updates; the preconditioner runs the even-odd FDM inverse of the
 // cell in an LDS slab; q = A p is the wave body of the coupled operator.
 
-// 1.  q = A p, partial (p, q) per workgroup (one cell).
-template <int N, bool VP>
+// 1.  q = A p, partial (p, q) per workgroup (one cell); HERM: the
+// Hermite-type basis (sign-flipped tables, see wave_sipg_cell).
+template <int N, bool VP, bool HERM>
 __global__ __launch_bounds__(64, 2) void k_pcg_aq_wave(const double* __restrict__ p, double* __restrict__ q,
                                                      MeshArgs G, const double* __restrict__ tab,
                                                      FaceRef<N, double> F, const PcgState* __restrict__ st,
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(64, 2) void k_pcg_aq_wave(const double* __restrict_
     }
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
     double y[N];
-    wave_sipg_cell<N, double, VP>(p, G, tb, F, c, L, y);
+    wave_sipg_cell<N, double, VP, HERM>(p, G, tb, F, c, L, y);
     const Pencil<N> pc(1);
     double dot = 0.0;
     if (pc.act) {
@@ -363,15 +364,20 @@ __device__ __forceinline__ void load_inverse_tables(const TI* __restrict__ tab, 
 
 // z = D^{-1} r of the wave's cell in precision TI (rv: the lane's z-pencil of
 // r in FP64), written in FP64 at zp (one vector store per 16 bytes when VP:
-// the pencil is contiguous); returns the lane's partial (r, z).
-template <int N, typename TI, bool VP = false>
+// the pencil is contiguous); returns the lane's partial (r, z).  HERM: the
+// inverse tables are those of the sign-flipped Hermite-type coefficients, so
+// r enters and z leaves the slab multiplied by its sign.
+template <int N, typename TI, bool VP = false, bool HERM = false>
 __device__ __forceinline__ double wave_precondition(const double (&rv)[N], double* __restrict__ zp, int lb,
                                                     const Pencil<N>& pc, TI* slab, const TI* T, const TI* lam,
                                                     TI sx, TI sy, TI sz) {
     using SL = Slab<N>;
+    auto sg = [&](int k) {
+        return HERM ? hermite_sign(N, pc.pa) * hermite_sign(N, pc.pb) * hermite_sign(N, k) : 1.0;
+    };
     if (pc.act) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) slab[SL::at(pc.pa, pc.pb, k)] = static_cast<TI>(rv[k]);
+        for (int k = 0; k < N; ++k) slab[SL::at(pc.pa, pc.pb, k)] = static_cast<TI>(sg(k) * rv[k]);
     }
     wave_sync();
     eo_inverse_lds<N, TI>(pc, slab, T, T + EOShape<N>::SE, lam, sx, sy, sz);
@@ -380,7 +386,7 @@ __device__ __forceinline__ double wave_precondition(const double (&rv)[N], doubl
         double zv[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            zv[k] = static_cast<double>(slab[SL::at(pc.pa, pc.pb, k)]);
+            zv[k] = sg(k) * static_cast<double>(slab[SL::at(pc.pa, pc.pb, k)]);
             rz = fma(rv[k], zv[k], rz);
         }
         pencil_store<N, VP>(zp, zv, lb);
@@ -389,7 +395,7 @@ __device__ __forceinline__ double wave_precondition(const double (&rv)[N], doubl
 }
 
 // Start (see k_pcg_start), one cell per workgroup.
-template <int N, typename TI>
+template <int N, typename TI, bool HERM>
 __global__ __launch_bounds__(64, 2) void k_pcg_start_wave(const double* __restrict__ b, const double* __restrict__ q,
                                                         const double* __restrict__ x0, double* __restrict__ x,
                                                         double* __restrict__ r, double* __restrict__ z,
@@ -422,7 +428,8 @@ __global__ __launch_bounds__(64, 2) void k_pcg_start_wave(const double* __restri
 #pragma unroll
         for (int k = 0; k < N; ++k) rv[k] = 0.0;
     }
-    double rz = wave_precondition<N, TI>(rv, z + pb, lb, pc, slab, T, stab + TABM, static_cast<TI>(G.sx),
+    double rz = wave_precondition<N, TI, false, HERM>(rv, z + pb, lb, pc, slab, T, stab + TABM,
+                                                      static_cast<TI>(G.sx),
                                          static_cast<TI>(G.sy), static_cast<TI>(G.sz));
     if (pc.act) {
 #pragma unroll
@@ -443,7 +450,7 @@ __global__ __launch_bounds__(64, 2) void k_pcg_start_wave(const double* __restri
 
 // 3.  (see k_pcg_update), one cell per workgroup; VP: the lane's pencils are
 // contiguous (layout B = 1), moved with vector loads and stores.
-template <int N, typename TI, bool VP>
+template <int N, typename TI, bool VP, bool HERM>
 __global__ __launch_bounds__(64, 2) void k_pcg_update_wave(double* __restrict__ x, double* __restrict__ r,
                                                          double* __restrict__ z, const double* __restrict__ p,
                                                          const double* __restrict__ q, MeshArgs G,
@@ -480,7 +487,7 @@ __global__ __launch_bounds__(64, 2) void k_pcg_update_wave(double* __restrict__ 
 #pragma unroll
         for (int k = 0; k < N; ++k) rv[k] = 0.0;
     }
-    double rz = wave_precondition<N, TI, VP>(rv, z + pb, lb, pc, slab, T, stab + TABM, static_cast<TI>(G.sx),
+    double rz = wave_precondition<N, TI, VP, HERM>(rv, z + pb, lb, pc, slab, T, stab + TABM, static_cast<TI>(G.sx),
                                              static_cast<TI>(G.sy), static_cast<TI>(G.sz));
     rz = wave_sum(rz);
     rr = wave_sum(rr);
@@ -567,6 +574,11 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
     // 16-byte pencils for the wave body: block-contiguous layout (the
     // solver's vectors are allocation-aligned)
     const bool vp = g.logB == 0 && (N * sizeof(double)) % 16 == 0;
+    // the wave kernels of the Hermite-type basis use sign-flipped tables and
+    // endpoint derivatives (see wave_sipg_cell)
+    const bool herm = !kLane && plan.basis == TP_BASIS_HERMITE;
+    FaceRef<N, double> Fw = F;
+    if (herm) flip_face_ref<N, double>(Fw);
     if (!x_zero) {
         tp_status st = launch_sipg(plan, g, false, x, s->q, TP_F64, stream);
         if (st != TP_OK) return st;
@@ -588,9 +600,12 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
     } else if constexpr (kLane)
         hipLaunchKernelGGL((k_pcg_start<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q, x,
                            s->xw, s->r, s->z, s->p, G, E, s->part, cnt);
+    else if (herm)
+        hipLaunchKernelGGL((k_pcg_start_wave<N, TI, true>), dim3(nwg), dim3(64), 0, stream, b,
+                           x_zero ? nullptr : s->q, x, s->xw, s->r, s->z, s->p, G, tabS, s->part, cnt);
     else
-        hipLaunchKernelGGL((k_pcg_start_wave<N, TI>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q,
-                           x, s->xw, s->r, s->z, s->p, G, tabS, s->part, cnt);
+        hipLaunchKernelGGL((k_pcg_start_wave<N, TI, false>), dim3(nwg), dim3(64), 0, stream, b,
+                           x_zero ? nullptr : s->q, x, s->xw, s->r, s->z, s->p, G, tabS, s->part, cnt);
     hipLaunchKernelGGL(k_pcg_reduce_start, dim3(1), dim3(256), 0, stream, s->part, cnt, s->st, rtol, maxit,
                        s->norm);
     tp_status st = check_launch("PCG start");
@@ -618,12 +633,19 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                         hipLaunchKernelGGL((k_pcg_aq<N, LB>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R, F, s->st,
                                            s->part);
                     }
+                } else if (herm) {
+                    if (vp)
+                        hipLaunchKernelGGL((k_pcg_aq_wave<N, true, true>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G,
+                                           tabA, Fw, s->st, s->part);
+                    else
+                        hipLaunchKernelGGL((k_pcg_aq_wave<N, false, true>), dim3(nwg), dim3(64), 0, cs, s->p, s->q,
+                                           G, tabA, Fw, s->st, s->part);
                 } else if (vp)
-                    hipLaunchKernelGGL((k_pcg_aq_wave<N, true>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, tabA, F,
-                                       s->st, s->part);
+                    hipLaunchKernelGGL((k_pcg_aq_wave<N, true, false>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G,
+                                       tabA, F, s->st, s->part);
                 else
-                    hipLaunchKernelGGL((k_pcg_aq_wave<N, false>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, tabA,
-                                       F, s->st, s->part);
+                    hipLaunchKernelGGL((k_pcg_aq_wave<N, false, false>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G,
+                                       tabA, F, s->st, s->part);
                 hipLaunchKernelGGL(k_pcg_reduce_alpha, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
                 if (s->mg) {
                     if constexpr (kLane) {
@@ -635,12 +657,19 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                 } else if constexpr (kLane)
                     hipLaunchKernelGGL((k_pcg_update<N, TI, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->z,
                                        s->p, s->q, G, E, s->st, s->part, cnt);
-                else if (vp)
-                    hipLaunchKernelGGL((k_pcg_update_wave<N, TI, true>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r,
-                                       s->z, s->p, s->q, G, tabS, s->st, s->part, cnt);
+                else if (herm) {
+                    if (vp)
+                        hipLaunchKernelGGL((k_pcg_update_wave<N, TI, true, true>), dim3(nwg), dim3(64), 0, cs, s->xw,
+                                           s->r, s->z, s->p, s->q, G, tabS, s->st, s->part, cnt);
+                    else
+                        hipLaunchKernelGGL((k_pcg_update_wave<N, TI, false, true>), dim3(nwg), dim3(64), 0, cs,
+                                           s->xw, s->r, s->z, s->p, s->q, G, tabS, s->st, s->part, cnt);
+                } else if (vp)
+                    hipLaunchKernelGGL((k_pcg_update_wave<N, TI, true, false>), dim3(nwg), dim3(64), 0, cs, s->xw,
+                                       s->r, s->z, s->p, s->q, G, tabS, s->st, s->part, cnt);
                 else
-                    hipLaunchKernelGGL((k_pcg_update_wave<N, TI, false>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r,
-                                       s->z, s->p, s->q, G, tabS, s->st, s->part, cnt);
+                    hipLaunchKernelGGL((k_pcg_update_wave<N, TI, false, false>), dim3(nwg), dim3(64), 0, cs, s->xw,
+                                       s->r, s->z, s->p, s->q, G, tabS, s->st, s->part, cnt);
                 hipLaunchKernelGGL(k_pcg_reduce_beta, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
                 hipLaunchKernelGGL(k_pcg_dir, dim3(dgrid), dim3(256), 0, cs, s->z, s->p, s->elems, s->st);
             }

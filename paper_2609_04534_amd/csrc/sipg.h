@@ -391,7 +391,12 @@ struct WaveLds {
 // pc.pb), for the active lanes; every lane of the wave must call it.
 // TB: ME | MO | PE | PO (even-odd halves of M_hat and of the cell-diagonal
 // P_hat); F: endpoint derivatives and the reference penalty.
-template <int N, typename T, bool VP>
+// HERM: the Hermite-type basis.  The even-odd tables then hold the matrices
+// conjugated by D = diag(hermite_sign) (centrosymmetric), so every value is
+// multiplied by its sign s(i) s(j) s(k) on load and on store, and the face
+// terms read only the layers 0, 1, n-2, n-1 along the normal (the others
+// carry no weight: eq. (hermite_traces_3d)).
+template <int N, typename T, bool VP, bool HERM = false>
 __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const MeshArgs& G, const T* TB,
                                                const FaceRef<N, T>& F, int64_t c, WaveLds<N, T>& L,
                                                T (&y)[N]) {
@@ -412,12 +417,14 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
     const uint32_t cy = rr % static_cast<uint32_t>(G.my);
     const uint32_t cx = rr / static_cast<uint32_t>(G.my);
     const T sx = static_cast<T>(G.sx), sy = static_cast<T>(G.sy), sz = static_cast<T>(G.sz);
+    auto sg = [](int i) { return HERM ? static_cast<T>(hermite_sign(N, i)) : T(1); };
+    const T sab = sg(pa) * sg(pb);   // sign of the lane's two tangential indices
     // --- the cell's own block into the slab, volume product in place
     if (pc.act) {
         T x[N];
         pencil_load<N, VP>(x, ub + block_base(c, lb, N3) + (static_cast<int64_t>((pa * N + pb) * N) << lb), lb);
 #pragma unroll
-        for (int k = 0; k < N; ++k) L.s[SL::at(pa, pb, k)] = x[k];
+        for (int k = 0; k < N; ++k) L.s[SL::at(pa, pb, k)] = HERM ? sab * sg(k) * x[k] : x[k];
     }
     wave_sync();
     eo_apply_lds<N, T>(pc, L.s, L.s, L.t, L.t + SL::size, ME, MO, PE, PO, sx, sy, sz);   // ends synced
@@ -437,15 +444,18 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
             // normal to z the n values are the lane's contiguous pencil: one
             // vector load per 16 bytes when VP
             T wv[N];
-            if constexpr (D == 2)
+            if constexpr (D == 2 && !HERM)
                 pencil_load<N, VP>(wv, w + (static_cast<int64_t>(fq<N, D>(0, pa, pb)) << lb), lb);
             T al = T(0), be = T(0);
 #pragma unroll
             for (int k = 0; k < N; ++k) {
+                if (HERM && k >= 2 && k < N - 2) continue;
                 const T in = UP ? fma(T(-0.5), F.g0[k], k == 0 ? -F.sigma : T(0))
                                 : fma(T(0.5), F.g1[k], k == N - 1 ? -F.sigma : T(0));
                 const T bd = UP ? T(-0.5) * F.g1[k] : T(0.5) * F.g0[k];
-                const T wk = D == 2 ? wv[k] : ldc<T>(w + (static_cast<int64_t>(fq<N, D>(k, pa, pb)) << lb));
+                T wk = D == 2 && !HERM ? wv[k]
+                                       : ldc<T>(w + (static_cast<int64_t>(fq<N, D>(k, pa, pb)) << lb));
+                if (HERM) wk *= sab * sg(k);
                 al = fma(s * (interior ? in : bd), wk, al);
                 if (k == 0) be = cb0 * wk;
                 if (k == N - 1) be = fma(cbn, wk, be);
@@ -523,7 +533,7 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
             v = fma(g0k, fs[9 * N * N + i * N + j], v);
             v = fma(ekn, fs[10 * N * N + i * N + j], v);
             v = fma(g1k, fs[11 * N * N + i * N + j], v);
-            y[i] = v;
+            y[i] = HERM ? sab * sg(i) * v : v;
         }
     }
     wave_sync();
@@ -567,6 +577,16 @@ void sipg_tables(const Plan& plan, bool face_only, Pair<N, TC>& R, FaceRef<N, TC
         F.g1[i] = static_cast<TC>(ref.g1[i]);
     }
     F.sigma = static_cast<TC>(plan.penalty_C * (N - 1) * N);
+}
+
+// The wave kernels of the Hermite-type basis work in the sign-flipped
+// coefficients (see wave_sipg_cell): endpoint derivatives D g.
+template <int N, typename T>
+void flip_face_ref(FaceRef<N, T>& F) {
+    for (int k = 0; k < N; ++k) {
+        F.g0[k] = static_cast<T>(hermite_sign(N, k)) * F.g0[k];
+        F.g1[k] = static_cast<T>(hermite_sign(N, k)) * F.g1[k];
+    }
 }
 
 }  // namespace tpfdm

@@ -22,8 +22,8 @@ __global__ __launch_bounds__(64, 2) void k_sipg_lane(const TS* __restrict__ u, T
     for (int q = 0; q < N3; ++q) stv<NT>(vb + (static_cast<int64_t>(q) << lb), acc[q]);
 }
 
-// One cell per wave (n >= 5).
-template <int N, typename T, bool VP>
+// One cell per wave (n >= 5); HERM: the Hermite-type basis.
+template <int N, typename T, bool VP, bool HERM>
 __global__ __launch_bounds__(64, 2) void k_sipg_wave(const T* __restrict__ u, T* __restrict__ v, MeshArgs G,
                                                   const T* __restrict__ tab, FaceRef<N, T> F) {
     constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(64, 2) void k_sipg_wave(const T* __restrict__ u, T*
     }
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
     T y[N];
-    wave_sipg_cell<N, T, VP>(u, G, tb, F, c, L, y);
+    wave_sipg_cell<N, T, VP, HERM>(u, G, tb, F, c, L, y);
     const Pencil<N> pc(1);
     if (pc.act) {
         T* vb = v + G.offset + block_base(c, G.logB, N * N * N);
@@ -103,10 +103,17 @@ tp_status sipg_wave_n(const Plan& plan, const MeshArgs& G, bool face_only, const
     // 16-byte pencils: block-contiguous layout and an aligned vector
     const bool vp = G.logB == 0 && (reinterpret_cast<uintptr_t>(ui + G.offset) % 16 == 0) &&
                     (N * sizeof(T)) % 16 == 0;
-    if (vp)
-        hipLaunchKernelGGL((k_sipg_wave<N, T, true>), dim3(grid), dim3(64), 0, s, ui, vo, G, tab, F);
-    else
-        hipLaunchKernelGGL((k_sipg_wave<N, T, false>), dim3(grid), dim3(64), 0, s, ui, vo, G, tab, F);
+    if (plan.basis == TP_BASIS_HERMITE) {
+        flip_face_ref<N, T>(F);
+        if (vp)
+            hipLaunchKernelGGL((k_sipg_wave<N, T, true, true>), dim3(grid), dim3(64), 0, s, ui, vo, G, tab, F);
+        else
+            hipLaunchKernelGGL((k_sipg_wave<N, T, false, true>), dim3(grid), dim3(64), 0, s, ui, vo, G, tab, F);
+    } else if (vp) {
+        hipLaunchKernelGGL((k_sipg_wave<N, T, true, false>), dim3(grid), dim3(64), 0, s, ui, vo, G, tab, F);
+    } else {
+        hipLaunchKernelGGL((k_sipg_wave<N, T, false, false>), dim3(grid), dim3(64), 0, s, ui, vo, G, tab, F);
+    }
     return check_launch("SIPG apply launch");
 }
 

@@ -183,8 +183,8 @@ def test_mesh_plan_validation_before_device():
     assert _create_mesh(h=(0.5, float("nan"), 1.0)) == -1
     assert _create_mesh(basis=2) == -1                        # no such basis
     assert _create_mesh(basis=-1) == -1
-    assert _create_mesh(n=3, basis=tpfdm.BASIS_HERMITE) == -2   # Hermite-type basis: n = 4 only
-    assert _create_mesh(n=5, basis=tpfdm.BASIS_HERMITE) == -2
+    assert _create_mesh(n=3, basis=tpfdm.BASIS_HERMITE) == -2   # Hermite-type basis: p >= 3
+    assert _create_mesh(n=2, basis=tpfdm.BASIS_HERMITE) == -2
     assert _create_mesh(n=4, basis=tpfdm.BASIS_HERMITE, mapping=tpfdm.MAP_WAVE) == -2
     assert _create_mesh(cells=(2048, 2048, 1024)) == -1       # 2^32 cells
     assert _create_mesh(persistent=1) == -2
@@ -210,18 +210,28 @@ def test_patch_blocks_validation_before_device():
     assert lib.tp_plan_create_mesh(ctypes.byref(m), ctypes.byref(opts), ctypes.byref(out)) == -2
 
 
-@pytest.mark.parametrize("C", [2.0, 3.5])
-def test_hermite_reference_tables_match_oracle(C):
+@pytest.mark.parametrize("n,C", [(4, 2.0), (4, 3.5), (5, 2.0), (6, 2.0), (7, 2.0), (8, 2.0)])
+def test_hermite_reference_tables_match_oracle(n, C):
     """The library's own Hermite-type tables (host code, no GPU) against the
     oracle's, two independent implementations of the basis of
     eq. (hermite_conditions)."""
     from oracle import hermite
-    M, K, A, T = tpfdm.reference_basis(4, tpfdm.BASIS_HERMITE, penalty_C=C)
-    Mo, Ko = hermite.mass_stiffness(3)
-    assert np.allclose(M, Mo, atol=1e-14)
-    assert np.allclose(K, Ko, atol=1e-13)
-    assert np.allclose(A, hermite.penalized_stiffness(3, C), atol=1e-12)
-    assert np.allclose(T, hermite.transform(3), atol=1e-15)
+    p = n - 1
+    M, K, A, T = tpfdm.reference_basis(n, tpfdm.BASIS_HERMITE, penalty_C=C)
+    Mo, Ko = hermite.mass_stiffness(p)
+    Ao = hermite.penalized_stiffness(p, C)
+    assert np.allclose(M, Mo, atol=1e-13 * np.abs(Mo).max())
+    assert np.allclose(K, Ko, atol=1e-12 * np.abs(Ko).max())
+    assert np.allclose(A, Ao, atol=1e-12 * np.abs(Ao).max())
+    assert np.allclose(T, hermite.transform(p), atol=1e-13)
+    # conjugated by the sign of the derivative-at-1 function the matrices are
+    # centrosymmetric (what the even-odd kernels of n >= 5 rely on)
+    d = np.ones(n)
+    d[n - 2] = -1.0
+    J = np.eye(n)[::-1]
+    for X in (M, K, A):
+        Xf = d[:, None] * X * d[None, :]
+        assert np.allclose(J @ Xf @ J, Xf, atol=1e-12 * np.abs(X).max())
 
 
 @pytest.mark.parametrize("n", [4, 6, 8])
@@ -237,7 +247,8 @@ def test_patch_reference_tables_match_oracle(n):
 
 def test_reference_basis_errors():
     lib = tpfdm.load()
-    assert lib.tp_reference_basis(5, tpfdm.BASIS_HERMITE, 0, 2.0, None, None, None, None) == -2
+    assert lib.tp_reference_basis(3, tpfdm.BASIS_HERMITE, 0, 2.0, None, None, None, None) == -2
+    assert lib.tp_reference_basis(6, tpfdm.BASIS_HERMITE, tpfdm.BLOCKS_PATCHES, 2.0, None, None, None, None) == -2
     assert lib.tp_reference_basis(5, 0, tpfdm.BLOCKS_PATCHES, 2.0, None, None, None, None) == -2
     assert lib.tp_reference_basis(4, 7, 0, 2.0, None, None, None, None) == -1
     assert lib.tp_reference_basis(4, 0, 3, 2.0, None, None, None, None) == -1

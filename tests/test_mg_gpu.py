@@ -252,3 +252,25 @@ def test_mg_errors():
         with pytest.raises(tpfdm.TpfdmError) as e:
             V.vcycle(buf, torch.zeros_like(buf))
         assert e.value.status == -9
+
+
+@pytest.mark.parametrize("multigrid", [False, True])
+def test_nonfinite_rhs_is_reported(multigrid):
+    """A NaN in b: the solve stops at once with TP_ERR_NONFINITE (the start
+    reduction sees it), with the V-cycle as with block-Jacobi; a following
+    finite solve on the same solver is unaffected."""
+    torch = _torch()
+    p, m = 2, 4
+    b = _rhs(m ** 3 * 27, 5)
+    with _cube_plan(p, m) as plan, tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+        if multigrid:
+            solver.set_multigrid(V)
+        bad = b.copy()
+        bad[17] = np.nan
+        bb = to_blocked(plan, bad, tpfdm.F64)
+        bx = torch.empty_like(bb)
+        s = solver.solve(bb, bx, rtol=1e-9, maxit=100, raise_on_failure=False)
+        assert s["status"] == -6 and not s["converged"] and s["iterations"] == 0
+        bb = to_blocked(plan, b, tpfdm.F64)
+        s = solver.solve(bb, bx, rtol=1e-9, maxit=2000)
+        assert s["converged"]
