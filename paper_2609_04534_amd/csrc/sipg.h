@@ -443,22 +443,45 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
         if (pc.act) {
             // normal to z the n values are the lane's contiguous pencil: one
             // vector load per 16 bytes when VP
-            T wv[N];
-            if constexpr (D == 2 && !HERM)
-                pencil_load<N, VP>(wv, w + (static_cast<int64_t>(fq<N, D>(0, pa, pb)) << lb), lb);
             T al = T(0), be = T(0);
+            if constexpr (HERM) {
+                // two source layers: 0, 1 when the face is interior at the
+                // upper end or boundary at the lower end, else n-2, n-1
+                // (the weights of the other layers vanish in this basis)
+                const int k0 = first ? 0 : N - 2;
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                if (HERM && k >= 2 && k < N - 2) continue;
-                const T in = UP ? fma(T(-0.5), F.g0[k], k == 0 ? -F.sigma : T(0))
-                                : fma(T(0.5), F.g1[k], k == N - 1 ? -F.sigma : T(0));
-                const T bd = UP ? T(-0.5) * F.g1[k] : T(0.5) * F.g0[k];
-                T wk = D == 2 && !HERM ? wv[k]
-                                       : ldc<T>(w + (static_cast<int64_t>(fq<N, D>(k, pa, pb)) << lb));
-                if (HERM) wk *= sab * sg(k);
-                al = fma(s * (interior ? in : bd), wk, al);
-                if (k == 0) be = cb0 * wk;
-                if (k == N - 1) be = fma(cbn, wk, be);
+                for (int t = 0; t < 2; ++t) {
+                    const int k = k0 + t;
+                    T wk = ldc<T>(w + (static_cast<int64_t>(D == 0 ? (k * N + pa) * N + pb
+                                                           : D == 1 ? (pa * N + k) * N + pb
+                                                                    : (pa * N + pb) * N + k) << lb));
+                    wk *= sab * sg(k);
+                    // alpha weight of layer k (as below), selected per lane
+                    T wgt = T(0);
+#pragma unroll
+                    for (int kk = 0; kk < N; ++kk) {
+                        const T in = UP ? fma(T(-0.5), F.g0[kk], kk == 0 ? -F.sigma : T(0))
+                                        : fma(T(0.5), F.g1[kk], kk == N - 1 ? -F.sigma : T(0));
+                        const T bd = UP ? T(-0.5) * F.g1[kk] : T(0.5) * F.g0[kk];
+                        wgt = kk == k ? s * (interior ? in : bd) : wgt;
+                    }
+                    al = fma(wgt, wk, al);
+                    be = fma(t == 0 ? cb0 : cbn, wk, be);
+                }
+            } else {
+                T wv[N];
+                if constexpr (D == 2)
+                    pencil_load<N, VP>(wv, w + (static_cast<int64_t>(fq<N, D>(0, pa, pb)) << lb), lb);
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const T in = UP ? fma(T(-0.5), F.g0[k], k == 0 ? -F.sigma : T(0))
+                                    : fma(T(0.5), F.g1[k], k == N - 1 ? -F.sigma : T(0));
+                    const T bd = UP ? T(-0.5) * F.g1[k] : T(0.5) * F.g0[k];
+                    const T wk = D == 2 ? wv[k] : ldc<T>(w + (static_cast<int64_t>(fq<N, D>(k, pa, pb)) << lb));
+                    al = fma(s * (interior ? in : bd), wk, al);
+                    if (k == 0) be = cb0 * wk;
+                    if (k == N - 1) be = fma(cbn, wk, be);
+                }
             }
             fs[(2 * f) * N * N + pa * N + pb] = al;
             fs[(2 * f + 1) * N * N + pa * N + pb] = be;
