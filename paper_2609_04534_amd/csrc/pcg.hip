@@ -630,10 +630,8 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                             hipLaunchKernelGGL((k_pcg_aq<N, LB, true>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R,
                                                F, s->st, s->part);
                     } else {
-                        // n = 4: the run-time layout shift spills less (as for the operator)
-                        constexpr int LBA = N == 4 ? -1 : LB;
-                        hipLaunchKernelGGL((k_pcg_aq<N, LBA>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R, F,
-                                           s->st, s->part);
+                        hipLaunchKernelGGL((k_pcg_aq<N, LB>), dim3(nwg), dim3(64), 0, cs, s->p, s->q, G, R, F, s->st,
+                                           s->part);
                     }
                 } else if (herm) {
                     if (vp)

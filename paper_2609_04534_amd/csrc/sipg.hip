@@ -81,9 +81,7 @@ tp_status sipg_lane_n(const Plan& plan, const MeshArgs& G, bool face_only, const
             return check_launch("SIPG apply launch");
         }
     }
-    // n = 4 FP64: the variant with the layout shift taken at run time keeps
-    // two spilled VGPRs instead of thirteen (about 2 % faster at 128^3)
-    if (G.logB == 6 && !(N == 4 && sizeof(TC) == 8))
+    if (G.logB == 6)
         hipLaunchKernelGGL((k_sipg_lane<N, TS, TC, true, 6>), dim3(grid), dim3(64), 0, s, ui, vo, G, R, F);
     else if (lane_whole_lines<TS>(G.logB))
         hipLaunchKernelGGL((k_sipg_lane<N, TS, TC, true, -1>), dim3(grid), dim3(64), 0, s, ui, vo, G, R, F);
