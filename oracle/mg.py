@@ -46,11 +46,18 @@ def chebyshev_weights(a: float = INTERVAL[0], b: float = INTERVAL[1], degree: in
     return [1.0 / (c - d * math.cos((2 * j - 1) * math.pi / (2 * degree))) for j in range(1, degree + 1)]
 
 
-def levels(m: int):
-    """Cells per side of every level, finest first."""
-    out = [m]
-    while out[-1] % 2 == 0:
-        out.append(out[-1] // 2)
+def levels(m):
+    """Cells of every level, finest first: m (an int for a cube, or the
+    three counts of a box), halved in every direction while all counts are
+    even."""
+    if np.isscalar(m):
+        out = [int(m)]
+        while out[-1] % 2 == 0:
+            out.append(out[-1] // 2)
+        return out
+    out = [tuple(int(v) for v in m)]
+    while all(v % 2 == 0 for v in out[-1]):
+        out.append(tuple(v // 2 for v in out[-1]))
     return out
 
 
@@ -65,34 +72,45 @@ def prolongation_1d(p: int, bname: str = sipg.LAGRANGE):
     return tuple(basis.lagrange_values(x, (x + c) / 2.0) for c in (0, 1))
 
 
-def prolongation(p: int, mc: int, bname: str = sipg.LAGRANGE) -> sp.csr_matrix:
-    """Fine (2 mc cells per side) <- coarse (mc) embedding, canonical orders."""
+def prolongation(p: int, mc, bname: str = sipg.LAGRANGE) -> sp.csr_matrix:
+    """Fine (2 mc cells per direction) <- coarse (mc) embedding, canonical
+    orders; mc an int for a cube or the three counts of a box."""
+    mc = (int(mc),) * 3 if np.isscalar(mc) else tuple(int(v) for v in mc)
     n3 = (p + 1) ** 3
     P1 = prolongation_1d(p, bname)
-    mf = 2 * mc
+    mf = tuple(2 * v for v in mc)
     rows, cols, vals = [], [], []
     li = np.repeat(np.arange(n3), n3)
     lj = np.tile(np.arange(n3), n3)
-    for f in range(mf ** 3):
-        fx, fy, fz = sipg.cell_coords((mf,) * 3, f)
-        c = sipg.cell_index((mc,) * 3, fx // 2, fy // 2, fz // 2)
+    for f in range(mf[0] * mf[1] * mf[2]):
+        fx, fy, fz = sipg.cell_coords(mf, f)
+        c = sipg.cell_index(mc, fx // 2, fy // 2, fz // 2)
         blk = np.kron(np.kron(P1[fx % 2], P1[fy % 2]), P1[fz % 2])
         rows.append(f * n3 + li)
         cols.append(c * n3 + lj)
         vals.append(blk.reshape(-1))
-    N = mf ** 3 * n3
+    N = mf[0] * mf[1] * mf[2] * n3
     return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                         shape=(N, mc ** 3 * n3)).tocsr()
+                         shape=(N, mc[0] * mc[1] * mc[2] * n3)).tocsr()
 
 
 class Hierarchy:
-    """Level operators, transfers and the coarse inverse of a unit cube."""
+    """Level operators, transfers and the coarse inverse of a unit cube with
+    m cells per side, or of a box with cells m = (mx, my, mz) of lengths h
+    (each level doubles the lengths)."""
 
-    def __init__(self, p: int, m: int, C: float = 2.0, bname: str = sipg.LAGRANGE):
+    def __init__(self, p: int, m, C: float = 2.0, bname: str = sipg.LAGRANGE, h=None):
         self.p = p
         self.bname = bname
         self.ms = levels(m)
-        self.A = [sipg.assemble(p, (ml,) * 3, (1.0 / ml,) * 3, sipg.FULL, C, bname) for ml in self.ms]
+        box = not np.isscalar(m)
+        self.cells = [ml if box else (ml,) * 3 for ml in self.ms]
+        if box:
+            h0 = tuple(float(v) for v in h)
+            self.hs = [tuple(v * 2 ** k for v in h0) for k in range(len(self.ms))]
+        else:
+            self.hs = [(1.0 / ml,) * 3 for ml in self.ms]
+        self.A = [sipg.assemble(p, c, hl, sipg.FULL, C, bname) for c, hl in zip(self.cells, self.hs)]
         self.P = [prolongation(p, self.ms[k + 1], bname) for k in range(len(self.ms) - 1)]
         self.coarse = np.linalg.inv(self.A[-1].toarray())
         self.omega = chebyshev_weights()
@@ -100,9 +118,8 @@ class Hierarchy:
 
     def smooth(self, k: int, u, b):
         """One Chebyshev application (three Richardson updates) on level k."""
-        ml = self.ms[k]
         for w in self.omega:
-            u = u + w * sipg.block_jacobi(self.p, (ml,) * 3, (1.0 / ml,) * 3, b - self.A[k] @ u, self.C, self.bname)
+            u = u + w * sipg.block_jacobi(self.p, self.cells[k], self.hs[k], b - self.A[k] @ u, self.C, self.bname)
         return u
 
     def vcycle(self, b, k: int = 0):

@@ -104,3 +104,24 @@ def test_mg_pcg_iteration_counts_are_small_and_mesh_independent(p, m):
     print(f"p={p} m={m} mg_iters={it} bj_iters={it_bj}")
     assert rel <= 1e-10 and it <= 16 and it < it_bj / 3
     assert np.linalg.norm(x - x_bj) <= 1e-7 * np.linalg.norm(x_bj)
+
+
+def test_box_hierarchy_reduces_to_the_cube_and_is_symmetric():
+    """The hierarchy of a box: on a cube it is the cube's hierarchy bit for
+    bit; on a box with unequal counts and lengths its V-cycle is symmetric
+    and positive, and its transfers preserve the mass."""
+    b = np.random.default_rng(3).uniform(-1, 1, 64 * 27)
+    Hc = mg.Hierarchy(2, 4)
+    Hb = mg.Hierarchy(2, (4, 4, 4), h=(0.25,) * 3)
+    assert np.array_equal(Hc.vcycle(b), Hb.vcycle(b))
+    H = mg.Hierarchy(2, (4, 8, 2), h=(0.25, 0.125, 0.4))
+    assert H.cells == [(4, 8, 2), (2, 4, 1)]
+    rng = np.random.default_rng(4)
+    a, c = rng.standard_normal((2, H.A[0].shape[0]))
+    Va, Vc = H.vcycle(a), H.vcycle(c)
+    assert abs(Va @ c - a @ Vc) <= 1e-11 * np.linalg.norm(Va) * np.linalg.norm(c)
+    assert Va @ a > 0
+    Mf = sipg.mass(2, H.cells[0], H.hs[0])
+    Mc = sipg.mass(2, H.cells[1], H.hs[1])
+    P = H.P[0]
+    assert np.abs((P.T @ Mf @ P - Mc).toarray()).max() <= 1e-13 * np.abs(Mc.toarray()).max()
