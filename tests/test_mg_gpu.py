@@ -64,6 +64,37 @@ def test_vcycle_matches_oracle(p, m):
         assert err <= 1e-11 * scale
 
 
+# boxes with unequal counts and lengths: (p, cells, h)
+BOX_CASES = [(2, (4, 8, 2), (0.25, 0.125, 0.4)), (3, (2, 4, 6), (0.5, 0.3, 0.2)), (1, (8, 4, 4), (0.1, 0.2, 0.3))]
+
+
+@pytest.mark.parametrize("p,cells,h", BOX_CASES)
+def test_vcycle_matches_oracle_on_boxes(p, cells, h):
+    """Boxes: the levels halve all three counts while all are even, each
+    level doubles its lengths; element by element against the oracle's box
+    hierarchy, and MG-PCG with its iteration count."""
+    torch = _torch()
+    H = mg.Hierarchy(p, cells, h=h)
+    nd = H.A[0].shape[0]
+    b = _rhs(nd, sum(cells) + p)
+    xo = H.vcycle(b)
+    _, ito, _ = sipg.pcg(H.A[0], b, H.vcycle, 1e-10, 200)
+    print(f"p={p} cells={cells} levels={H.cells} oracle_iters={ito}", flush=True)
+    with tpfdm.Plan.mesh(p + 1, cells, h) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
+        with tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+            bb = to_blocked(plan, b, tpfdm.F64)
+            bx = torch.full_like(bb, float("nan"))
+            V.vcycle(bb, bx)
+            x = from_blocked(plan, bx, tpfdm.F64)
+            solver.set_multigrid(V)
+            s = solver.solve(bb, torch.empty_like(bb), rtol=1e-10, maxit=200, check_every=4)
+    err = np.abs(x - xo).max() / np.abs(xo).max()
+    print(f"  vcycle rel err={err:.2e} {s}")
+    assert err <= 1e-11
+    assert s["converged"] and abs(s["iterations"] - ito) <= 1
+
+
 def test_vcycle_single_level_is_the_exact_solve():
     """m odd: the finest level is the coarsest, and the V-cycle is A^{-1} b."""
     torch = _torch()
