@@ -320,3 +320,35 @@ def test_wave_block_calls_are_rejected():
             with pytest.raises(tpfdm.TpfdmError) as e:
                 call()
             assert e.value.status == -2
+
+
+def test_wave_full_size_sampled_cells():
+    """p = 7 on 64^3 cells (134 M DoF, the benchmark mesh of the wave
+    kernels) in FP64: sampled cells (corners, edges, random) against the
+    oracle's row blocks in this basis."""
+    torch = _torch()
+    p, m = 7, 64
+    n3 = (p + 1) ** 3
+    cells, h = (m,) * 3, (1.0 / m,) * 3
+    ncell = m ** 3
+    rng = np.random.default_rng(77)
+    u = rng.uniform(-1, 1, ncell * n3)
+    corners = [sipg.cell_index(cells, a, b, c) for a in (0, m - 1) for b in (0, m - 1) for c in (0, m - 1)]
+    sample = sorted(set(corners + rng.choice(ncell, 12, replace=False).tolist()))
+    print(f"p={p} m={m}", flush=True)
+    with _plan_p(p, cells, h, setup=False) as plan:
+        bu = to_blocked(plan, u, tpfdm.F64)
+        bv = torch.empty_like(bu)
+        plan.apply(bu, bv, op=tpfdm.OP_SIPG)
+        v = from_blocked(plan, bv, tpfdm.F64).reshape(ncell, n3)[sample]
+        del bu, bv
+    ub = u.reshape(ncell, n3)
+    ref = np.zeros((len(sample), n3))
+    scale = 0.0
+    for r, c in enumerate(sample):
+        for nb, blk in sipg.cell_row_blocks(p, cells, h, c, bname=H):
+            ref[r] += blk @ ub[nb]
+            scale = max(scale, float(np.max(np.abs(blk) @ np.abs(ub[nb]))))
+    err = np.abs(v - ref).max() / scale
+    print(f"  sampled err={err:.2e}")
+    assert err <= TOL[tpfdm.F64]

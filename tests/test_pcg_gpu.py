@@ -149,7 +149,7 @@ def test_pcg_errors():
             assert e.value.status == -1
 
 
-@pytest.mark.parametrize("p,m,inner", [(3, 48, tpfdm.F32), (2, 32, tpfdm.F64)])
+@pytest.mark.parametrize("p,m,inner", [(3, 48, tpfdm.F32), (2, 32, tpfdm.F64), (7, 16, tpfdm.F64)])
 def test_pcg_serving_size_sampled_residual(p, m, inner):
     """The largest serving mesh: the solver's residual bound holds, and the
     oracle's true residual rows on sampled cells (corners, edges, interior)
