@@ -421,12 +421,15 @@ tp_status tp_mg_destroy(tp_mg* mg);
 tp_status tp_pcg_set_multigrid(tp_pcg* pcg, tp_mg* mg);
 
 /* Change of basis of a mesh plan's vectors (Sec. 3.1: the fixed n x n
- * matrix T per direction, used when interfacing with nodal data):
- * to_nodal = 1: v = (T (x) T (x) T) u cell by cell (Hermite coefficients to
- * nodal values); to_nodal = 0: v = (T^{-1} (x) T^{-1} (x) T^{-1}) u.  u, v:
- * distinct FP64 device vectors in the plan's layout (padding lanes are not
- * written).  On a Lagrange plan T = I and v is a copy of u.  Errors:
- * TP_ERR_ARG (null, aliasing, to_nodal not 0/1), TP_ERR_UNSUPPORTED (not a
+ * matrix T per direction, used when interfacing with nodal data, e.g. for
+ * output or right-hand-side evaluation), cell by cell, by mode (to_nodal):
+ *   1  v = (T (x) T (x) T) u: coefficients to nodal values;
+ *   0  v = (T^{-1} (x) T^{-1} (x) T^{-1}) u: nodal values to coefficients;
+ *   2  v = (T^T (x) T^T (x) T^T) u: a load vector assembled against the
+ *      nodal (Lagrange) basis to one against this basis (b_H = T3^T b_L).
+ * u, v: distinct FP64 device vectors in the plan's layout (padding lanes are
+ * not written).  On a Lagrange plan T = I and v is a copy of u.  Errors:
+ * TP_ERR_ARG (null, aliasing, mode not 0/1/2), TP_ERR_UNSUPPORTED (not a
  * mesh plan). */
 tp_status tp_change_basis(tp_plan* plan, int32_t to_nodal, const double* u, double* v, hipStream_t stream);
 

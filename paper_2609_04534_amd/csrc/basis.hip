@@ -85,11 +85,20 @@ __global__ __launch_bounds__(64) void k_change_basis_wave(const double* __restri
     }
 }
 
+// The 1D factor of a change-of-basis mode: 1 (values) T, 0 (coefficients)
+// T^{-1}, 2 (loads) T^T.
 template <int N>
-tp_status change_basis_wave(const RefData& r, const GroupInfo& g, bool to_nodal, const double* u, double* v,
+void basis_factor(const RefData& r, int mode, BasisTab<N>& X) {
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            X.x[i * N + j] = mode == 1 ? r.T[i * N + j] : mode == 0 ? r.Ti[i * N + j] : r.T[j * N + i];
+}
+
+template <int N>
+tp_status change_basis_wave(const RefData& r, const GroupInfo& g, int mode, const double* u, double* v,
                             hipStream_t stream) {
     BasisTab<N> X;
-    for (int i = 0; i < N * N; ++i) X.x[i] = to_nodal ? r.T[i] : r.Ti[i];
+    basis_factor<N>(r, mode, X);
     hipLaunchKernelGGL((k_change_basis_wave<N>), dim3(static_cast<unsigned>(g.nblocks)), dim3(64), 0, stream, u, v,
                        g.offset, g.logB, X);
     const hipError_t e = hipGetLastError();
@@ -105,7 +114,7 @@ extern "C" tp_status tp_change_basis(tp_plan* plan, int32_t to_nodal, const doub
                                      hipStream_t stream) {
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
     if (!plan->mesh) return set_error(TP_ERR_UNSUPPORTED, "change of basis needs a mesh plan");
-    if (to_nodal != 0 && to_nodal != 1) return set_error(TP_ERR_ARG, "to_nodal must be 0 or 1");
+    if (to_nodal < 0 || to_nodal > 2) return set_error(TP_ERR_ARG, "mode must be 0, 1 or 2");
     if (plan->vec_elems > 0 && (!u || !v)) return set_error(TP_ERR_ARG, "u and v must be non-null");
     if (u == v && u) return set_error(TP_ERR_ARG, "u and v must not alias");
     const GroupInfo& g = plan->groups[0];
@@ -116,16 +125,16 @@ extern "C" tp_status tp_change_basis(tp_plan* plan, int32_t to_nodal, const doub
         return e == hipSuccess ? TP_OK : hip_error(e, "change of basis copy");
     }
     switch (g.n) {
-        case 5: return change_basis_wave<5>(plan->ref[5], g, to_nodal != 0, u, v, stream);
-        case 6: return change_basis_wave<6>(plan->ref[6], g, to_nodal != 0, u, v, stream);
-        case 7: return change_basis_wave<7>(plan->ref[7], g, to_nodal != 0, u, v, stream);
-        case 8: return change_basis_wave<8>(plan->ref[8], g, to_nodal != 0, u, v, stream);
+        case 5: return change_basis_wave<5>(plan->ref[5], g, to_nodal, u, v, stream);
+        case 6: return change_basis_wave<6>(plan->ref[6], g, to_nodal, u, v, stream);
+        case 7: return change_basis_wave<7>(plan->ref[7], g, to_nodal, u, v, stream);
+        case 8: return change_basis_wave<8>(plan->ref[8], g, to_nodal, u, v, stream);
         default: break;
     }
     if (g.n != 4) return set_error(TP_ERR_UNSUPPORTED, "the Hermite-type basis needs n >= 4");
     const RefData& r = plan->ref[4];
     BasisTab<4> X;
-    for (int i = 0; i < 16; ++i) X.x[i] = to_nodal ? r.T[i] : r.Ti[i];
+    basis_factor<4>(r, to_nodal, X);
     const unsigned grid = static_cast<unsigned>((g.nblocks + 63) / 64);
     hipLaunchKernelGGL((k_change_basis<4>), dim3(grid), dim3(64), 0, stream, u, v, g.nblocks, g.offset, g.logB, X);
     const hipError_t e = hipGetLastError();

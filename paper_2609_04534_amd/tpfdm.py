@@ -371,10 +371,13 @@ class Plan:
             name += "/" + {1: "full", 2: "half", 0: "tile"}.get(code >> 4, "?")
         return name
 
-    def change_basis(self, u, v, to_nodal: bool, stream=None):
-        """v = (T (x) T (x) T) u (to_nodal) or the inverse, cell by cell
-        (tp_change_basis), blocked FP64 device vectors."""
-        _check(load().tp_change_basis(self.handle, 1 if to_nodal else 0, _ptr(u), _ptr(v), _stream(stream)))
+    def change_basis(self, u, v, to_nodal: bool = True, stream=None, loads: bool = False):
+        """v = (T (x) T (x) T) u (to_nodal), its inverse (not to_nodal), or
+        with loads=True the transpose T^T (x) T^T (x) T^T (a nodally assembled
+        load vector to this basis), cell by cell (tp_change_basis), blocked
+        FP64 device vectors."""
+        mode = 2 if loads else (1 if to_nodal else 0)
+        _check(load().tp_change_basis(self.handle, mode, _ptr(u), _ptr(v), _stream(stream)))
 
     def pack(self, canonical, blocked, stream=None):
         _check(load().tp_pack(self.handle, _ptr(canonical), _ptr(blocked), torch_dtype_code(canonical),

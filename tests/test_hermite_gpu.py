@@ -161,6 +161,24 @@ def test_vcycle_and_mg_pcg_match_oracle(m):
     assert s["converged"] and abs(s["iterations"] - ito) <= 1
 
 
+@pytest.mark.parametrize("p", [3, 7])
+def test_change_basis_of_loads(p):
+    """Mode 2 (loads): b_H = T3^T b_L cell by cell, against the oracle."""
+    torch = _torch()
+    cells = (2, 3, 2)
+    ncell = 12
+    n = p + 1
+    bL = np.random.default_rng(p + 50).uniform(-1, 1, ncell * n ** 3)
+    T = hermite.transform(p)
+    ref = (bL.reshape(ncell, -1) @ np.kron(np.kron(T, T), T)).reshape(-1)
+    with tpfdm.Plan.mesh(n, cells, (0.5, 0.4, 0.6), basis=tpfdm.BASIS_HERMITE) as plan:
+        bu = to_blocked(plan, bL, tpfdm.F64)
+        bv = torch.full_like(bu, float("nan"))
+        plan.change_basis(bu, bv, loads=True)
+        got = from_blocked(plan, bv, tpfdm.F64)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
 def test_solution_agrees_with_the_lagrange_plan():
     """The same discrete problem in both bases: solve A_H x_H = T3^T b_L,
     convert x_H to nodal values, compare with the Lagrange plan's solution."""
