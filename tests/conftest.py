@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # keep GPU tests from failing on machines without a GPU when selected
-    # explicitly by file; the driver selects them with -m gpu on the GPU machine.
+    # explicitly by file; a run on a machine with a GPU selects them with -m gpu.
     try:
         import torch
         has_gpu = torch.cuda.is_available()

@@ -4,8 +4,8 @@ Tolerances (per block, ||y - y*||_2 / ||y*||_2, max over blocks):
   FP64 apply and inverse: 1e-12.
   Mixed forms, against the FP64 oracle on the FP64 input (so the input's
   rounding to the storage type is included): derived from unit roundoff u of
-  the storage type times the growth of the contraction chain (see the design doc,
-  "Tolerances"):
+  the storage type times the growth of the contraction chain (three 1D
+  contractions per Kronecker term, a few u each, with margin):
       FP32  apply 2e-6,  inverse 5e-6
       FP16  apply 5e-3,  inverse 2e-2
       BF16  apply 4e-2,  inverse 1e-1
