@@ -57,7 +57,7 @@ __global__ __launch_bounds__(64, 2) void k_mg_apply(const double* __restrict__ u
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
     __shared__ double sa[N * N][64], sbt[N * N][64];
-    const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
+    const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, double, HERM>(G))) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
     double acc[N3];
     sipg_cell<N, double, double, -1, HERM>(u, G, R, F, c, acc, sa, sbt);
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(64, 2) void k_mg_smooth(const double* __restrict__ 
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
     __shared__ double sa[N * N][64], sbt[N * N][64];
-    const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
+    const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, double, HERM>(G))) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
     double acc[N3];
     sipg_cell<N, double, double, -1, HERM>(uin, G, R, F, c, acc, sa, sbt);

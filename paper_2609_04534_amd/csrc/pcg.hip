@@ -38,7 +38,7 @@ __global__ __launch_bounds__(64, 2) void k_pcg_aq(const double* __restrict__ p, 
     if (st->done) return;
     constexpr int N3 = N * N * N;
     __shared__ double sa[N * N][64], sbt[N * N][64];
-    const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
+    const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, double, HERM>(G))) * 64 + threadIdx.x;
     const int lb = LB >= 0 ? LB : G.logB;
     double dot = 0.0;
     if (c < G.ncells) {

@@ -12,7 +12,7 @@ __global__ __launch_bounds__(64, 2) void k_sipg_lane(const TS* __restrict__ u, T
                                                    Pair<N, TC> R, FaceRef<N, TC> F) {
     constexpr int N3 = N * N * N;
     __shared__ TC sa[N * N][64], sbt[N * N][64];
-    const int64_t c = static_cast<int64_t>(xcd_tile(blockIdx.x, gridDim.x)) * 64 + threadIdx.x;
+    const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, TS, HERM>(G))) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
     TC acc[N3];
     sipg_cell<N, TS, TC, LB, HERM>(u, G, R, F, c, acc, sa, sbt);
