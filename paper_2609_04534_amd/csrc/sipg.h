@@ -579,7 +579,7 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nwg) {
 // when kLaneSweep does not divide S; the part of the range past its last
 // whole row, and meshes whose planes are not whole tiles (S = 0), keep the
 // plain order.
-constexpr unsigned kLaneSweep = 32;
+constexpr unsigned kLaneSweep = 8;
 
 __device__ __forceinline__ unsigned lane_tile(unsigned b, unsigned nwg, unsigned S) {
     if (nwg % 8 != 0) return b;
@@ -599,10 +599,11 @@ __device__ __forceinline__ unsigned lane_tile(unsigned b, unsigned nwg, unsigned
 // Row length S for lane_tile: the tiles per x-plane of a mesh plan's cells
 // in the Lagrange basis when one plane of blocks (n^3 values of T per cell)
 // holds at least twice an XCD's 4 MiB L2, else 0 (plain order).  Measured on
-// the coupled operator at n = 4: the grouped order gains about 10% with
-// 8 MiB planes (FP64, 128^2 cells per plane) and loses 2-5% with 4-4.7 MiB
-// planes and in the Hermite-type basis, whose face terms read only two
-// layers of a neighbour.  Also 0 when a plane is not whole 64-cell tiles.
+// the coupled operator at n = 4: the grouped order (groups of 8; 4, 16, 32
+// and 64 were slower) takes 15% off the time with 8 MiB planes (FP64, 128^2
+// cells per plane) and adds 3-6% with 2-4.7 MiB planes; in the Hermite-type
+// basis, whose face terms read only two layers of a neighbour, it did not
+// pay.  Also 0 when a plane is not whole 64-cell tiles.
 template <int N, typename T, bool HERM>
 __device__ __forceinline__ unsigned plane_tiles(const MeshArgs& G) {
     constexpr int64_t kMinPlaneBytes = int64_t(8) << 20;

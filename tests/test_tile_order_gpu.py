@@ -1,8 +1,8 @@
 """GPU parity of the grouped tile order of the one-cell-per-lane mesh
 kernels (Lagrange basis, x-planes of 8 MiB or more: each XCD visits its
-tiles in groups of 32 carried through the x-planes).  The boxes are chosen
+tiles in groups of 8 carried through the x-planes).  The boxes are chosen
 so that the order is active, with whole groups per row, with a narrower
-last group (tiles per plane not a multiple of 32) and with a tail of
+last group (tiles per plane not a multiple of 8) and with a tail of
 plain-order tiles past the last whole row.  The output starts as NaN, so a
 tile the order skipped shows up; sampled cells (corners, edges, random)
 are checked against the oracle's row blocks, and an MG-preconditioned CG
@@ -46,9 +46,9 @@ def _sample(cells, rng, k=40):
     return sorted(set(corners + edges + rng.choice(mx * my * mz, k, replace=False).tolist()))
 
 
-# (cells, dtype): 20 x 136 x 128 has 272 tiles per plane (8 whole groups and
-# one of 16) and 136 tiles per XCD past its two whole planes
-BOXES = [((16, 128, 128), tpfdm.F64), ((20, 136, 128), tpfdm.F64), ((16, 256, 128), tpfdm.F32)]
+# (cells, dtype): 20 x 129 x 128 has 258 tiles per plane (32 whole groups
+# of 8 and one of 2) and 129 tiles per XCD past its two whole planes
+BOXES = [((16, 128, 128), tpfdm.F64), ((20, 129, 128), tpfdm.F64), ((16, 256, 128), tpfdm.F32)]
 
 
 @pytest.mark.parametrize("cells,dt", BOXES)
