@@ -135,3 +135,75 @@ def solve_factors(M_all, P_all, r_all, refine: int = 2) -> np.ndarray:
                  for d in range(3)]
         out[b] = solve_block(kronecker_sum(pairs), r_all[b], refine)
     return out
+
+
+# --------------------------------------------------------------------------
+# Whole-batch forms of the same dense operators, for checks at full size.
+#
+# For a block of lengths (h_x, h_y, h_z) every term of the Kronecker sum is a
+# scalar multiple of a reference term, e.g.
+#   kron(P_hat/h_x, h_y M_hat, h_z M_hat) = (h_y h_z / h_x) kron(P_hat, M_hat, M_hat),
+# so the dense n^3 x n^3 block matrix is s_x T_x + s_y T_y + s_z T_z with the
+# three reference Kronecker products T_d (eq. (eval_pipeline), eq. (cell_block))
+# and s_x = h_y h_z / h_x, s_y = h_x h_z / h_y, s_z = h_x h_y / h_z.  These
+# functions form exactly that matrix (never a sum-factorized or diagonalized
+# form); only the per-block scalars are pulled out of the products.
+
+def reference_terms(p: int, op: str, C: float = 2.0):
+    """(T_x, T_y, T_z) = kron(P,M,M), kron(M,P,M), kron(M,M,P) of the reference pair."""
+    M, P = reference_pair(p, op, C)
+    return (np.kron(np.kron(P, M), M), np.kron(np.kron(M, P), M), np.kron(np.kron(M, M), P))
+
+
+def term_scales(h_all) -> np.ndarray:
+    """(nblocks, 3) array of (s_x, s_y, s_z) for lengths (nblocks, 3)."""
+    h = np.asarray(h_all, dtype=np.float64).reshape(-1, 3)
+    hx, hy, hz = h[:, 0], h[:, 1], h[:, 2]
+    return np.stack([hy * hz / hx, hx * hz / hy, hx * hy / hz], axis=1)
+
+
+def apply_batch(p: int, h_all, u_all, op: str = NEUMANN, C: float = 2.0, absolute: bool = False) -> np.ndarray:
+    """v_b = A_b u_b for every block as three dense products over the whole
+    batch.  With absolute=True the entries of every T_d are replaced by their
+    absolute values (|A_b| u_b, a scale for error bounds)."""
+    T = reference_terms(p, op, C)
+    if absolute:
+        T = tuple(np.abs(t) for t in T)
+    s = term_scales(h_all)
+    u = np.asarray(u_all, dtype=np.float64)
+    return s[:, 0:1] * (u @ T[0].T) + s[:, 1:2] * (u @ T[1].T) + s[:, 2:3] * (u @ T[2].T)
+
+
+def residual_batch(p: int, h_all, x_all, r_all, op: str = CELL, C: float = 2.0) -> np.ndarray:
+    """r_b - D_b x_b for every block (FP64 dense products)."""
+    return np.asarray(r_all, dtype=np.float64) - apply_batch(p, h_all, x_all, op, C)
+
+
+def solve_batch(p: int, h_all, r_all, op: str = CELL, C: float = 2.0, refine: int = 2,
+                chunk: int = 64) -> np.ndarray:
+    """x_b = D_b^{-1} r_b for every block: the dense matrices of a chunk of
+    blocks, a batched LAPACK solve, and ``refine`` refinement steps with the
+    residual accumulated in long double (as ``solve_block``).  r_all may be
+    (nblocks, n^3) or (nblocks, n^3, k) for k right-hand sides per block."""
+    T = reference_terms(p, op, C)
+    s = term_scales(h_all)
+    r_all = np.asarray(r_all, dtype=np.float64)
+    multi = r_all.ndim == 3
+    R = r_all if multi else r_all[:, :, None]
+    out = np.empty_like(R)
+    T_ld = tuple(t.astype(np.longdouble) for t in T)
+    for c0 in range(0, R.shape[0], chunk):
+        c1 = min(R.shape[0], c0 + chunk)
+        sc = s[c0:c1]
+        D = (sc[:, 0, None, None] * T[0] + sc[:, 1, None, None] * T[1] + sc[:, 2, None, None] * T[2])
+        x = np.linalg.solve(D, R[c0:c1])
+        if refine:
+            D_ld = (sc[:, 0, None, None].astype(np.longdouble) * T_ld[0]
+                    + sc[:, 1, None, None].astype(np.longdouble) * T_ld[1]
+                    + sc[:, 2, None, None].astype(np.longdouble) * T_ld[2])
+            r_ld = R[c0:c1].astype(np.longdouble)
+            for _ in range(refine):
+                res = r_ld - np.matmul(D_ld, x.astype(np.longdouble))
+                x = x + np.linalg.solve(D, res.astype(np.float64))
+        out[c0:c1] = x
+    return out if multi else out[:, :, 0]

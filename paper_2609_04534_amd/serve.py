@@ -35,6 +35,7 @@ class Request:
     start: float = -1.0         # admission time
     done: float = -1.0          # completion time
     summary: dict = field(default_factory=dict)
+    rejected: bool = False      # its slot alone exceeds the memory budget: never run
 
 
 class _Slot:
@@ -88,8 +89,20 @@ def mg_bytes(p: int, m: int) -> int:
 def slot_bytes(plan, p: int = None, m: int = None, multigrid: bool = False) -> int:
     """Device memory of one slot: the solver's five vectors and partials plus
     b and x, and the V-cycle's levels when it has one."""
-    E = plan.vector_elems
-    nwg = (plan.nblocks + 63) // 64
+    return _slot_bytes(plan.vector_elems, plan.nblocks, p, m, multigrid)
+
+
+def class_slot_bytes(p: int, m: int, multigrid: bool = False) -> int:
+    """slot_bytes of the mesh class (p, m) in the default layout, computed
+    without creating its plan."""
+    n = p + 1
+    B = tpfdm.default_layout_B(n)
+    ncell = m ** 3
+    return _slot_bytes((ncell + B - 1) // B * B * n ** 3, ncell, p, m, multigrid)
+
+
+def _slot_bytes(E, nblocks, p, m, multigrid):
+    nwg = (nblocks + 63) // 64
     out = 7 * E * 8 + 3 * nwg * 8 + 256
     if multigrid:
         out += mg_bytes(p, m)
@@ -111,6 +124,7 @@ class Server:
         self.used = 0           # bytes of live slots (busy and idle)
         self.busy = []
         self.max_concurrent = 0
+        self.rejected = 0       # requests whose slot alone exceeds the budget
 
     def _plan(self, p, m):
         key = (p, m)
@@ -142,6 +156,17 @@ class Server:
         return self.multigrid and uses_multigrid(p)
 
     def _admit(self, req, now):
+        """True when the request leaves the queue: admitted, or rejected
+        because its slot alone needs more than the whole budget (it could
+        never run, and first-in-first-out admission would stall behind it)."""
+        if class_slot_bytes(req.p, req.m, self._mg(req.p)) > self.budget:
+            req.rejected = True
+            req.start = req.done = now
+            req.summary = {"status": "rejected", "converged": False, "iterations": 0,
+                           "reason": f"slot of {class_slot_bytes(req.p, req.m, self._mg(req.p))} bytes exceeds "
+                                     f"the budget of {self.budget} bytes"}
+            self.rejected += 1
+            return True
         if len(self.busy) >= self.max_inflight:
             return False
         s = self._slot_for(req.p, req.m)
@@ -222,8 +247,11 @@ def poisson_requests(rate: float, count: int, mix, seed: int):
 
 
 def latency_stats(reqs):
-    lat = np.array([r.done - r.arrival for r in reqs]) * 1e3
-    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    """Latency percentiles and throughput of the served (not rejected) requests."""
+    served = [r for r in reqs if not r.rejected]
+    lat = np.array([r.done - r.arrival for r in served]) * 1e3
+    span = max(r.done for r in served) - min(r.arrival for r in served)
     return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_ms": float(lat.mean()), "solves_per_s": len(reqs) / span,
-            "queue_p50_ms": float(np.percentile([(r.start - r.arrival) * 1e3 for r in reqs], 50))}
+            "mean_ms": float(lat.mean()), "solves_per_s": len(served) / span,
+            "queue_p50_ms": float(np.percentile([(r.start - r.arrival) * 1e3 for r in served], 50)),
+            "rejected": len(reqs) - len(served)}

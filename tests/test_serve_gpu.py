@@ -84,3 +84,27 @@ def test_served_solve_matches_direct_solution(multigrid):
         x = r.x.cpu().numpy()
         assert np.linalg.norm(b - A @ x) <= 2e-10 * np.linalg.norm(b)
         assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_oversized_request_is_rejected_and_the_rest_served():
+    """A request whose slot alone exceeds the budget leaves the queue as
+    rejected; the requests behind it are served as usual."""
+    import torch
+    budget = 4 * serve.class_slot_bytes(2, 6)
+    assert serve.class_slot_bytes(3, 16) > budget
+    reqs = serve.poisson_requests(rate=5000.0, count=5, mix=[(2, 4), (2, 6)], seed=9)
+    big = torch.zeros(16 ** 3 * 64, dtype=torch.float64, device="cuda")
+    reqs.insert(1, serve.Request(99, 3, 16, reqs[0].arrival, big))
+    srv = serve.Server(hbm_budget=budget, inner=tpfdm.F64, rtol=1e-8)
+    try:
+        done = srv.run(reqs)
+    finally:
+        srv.close()
+    assert srv.rejected == 1
+    for r in done:
+        if r.rid == 99:
+            assert r.rejected and r.x is None and r.summary["status"] == "rejected"
+        else:
+            assert not r.rejected and r.summary["converged"], r.rid
+    stats = serve.latency_stats(done)
+    assert stats["rejected"] == 1
