@@ -74,32 +74,224 @@ def time_launches(fn, stream, reps, sets):
     return start.elapsed_time(end) / reps
 
 
-def cpu_baseline(wl, budget_s=12.0):
-    """Time the FP64 dense oracle (apply + solve per block) on a bounded
-    sample of the workload's blocks; report DoF/s."""
+def _host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, int(os.cpu_count() or 0), int(avail or 0)
+
+
+_CPU_WL = None   # the workload the CPU-baseline worker processes read (inherited at fork)
+
+
+def _one_thread():
+    """Each worker process runs its BLAS single-threaded (one per core)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _dense_chunk(seed, chunk=64):
+    """One random chunk per group: dense apply, then the dense refined solve."""
     from oracle import dense
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
+    dof = nblk = 0
+    for g in _CPU_WL.groups:
+        idx = rng.integers(0, g.nblocks, size=max(1, min(chunk, g.nblocks)))
+        v = dense.apply_batch(g.p, g.h[idx], g.u[idx], dense.NEUMANN)
+        dense.solve_batch(g.p, g.h[idx], v, dense.CELL, chunk=chunk)
+        dof += len(idx) * g.n ** 3
+        nblk += len(idx)
+    return dof, nblk
+
+
+def _sumfact_part(args):
+    from oracle import dense, sumfact
+    gi, lo, hi = args
+    g = _CPU_WL.groups[gi]
+    v = sumfact.apply(g.p, g.h[lo:hi], g.u[lo:hi], dense.NEUMANN)
+    sumfact.inverse(g.p, g.h[lo:hi], v, dense.CELL)
+    return hi - lo
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """Time the FP64 dense oracle on the host on a bounded random sample of
+    the workload's blocks: the step's apply (dense Kronecker products,
+    oracle.dense.apply_batch) and the cell-block inverse (dense LAPACK solves
+    with long-double refinement, oracle.dense.solve_batch), in chunks of 64
+    blocks spread over one worker process per available host core.  Reports
+    DoF/s of the apply + inverse step, the cores actually busy (the workers'
+    CPU time / wall time) and the host CPU.  The sum-factorized CPU reference
+    (oracle.sumfact) is timed on the whole workload beside it, split the same
+    way.  Must run before the process initialises the GPU: the workers are
+    forked from it."""
+    import multiprocessing as mp
+    import resource
+    global _CPU_WL
+    _CPU_WL = wl
+    model, ncpu, avail = _host_cpu()
+    workers = max(1, avail)
+    ctx = mp.get_context("fork")
+
+    def child_cpu():
+        r = resource.getrusage(resource.RUSAGE_CHILDREN)
+        return r.ru_utime + r.ru_stime
+
+    c0 = child_cpu()
     t0 = time.perf_counter()
-    c0 = time.process_time()
-    dof = 0
-    nblk = 0
-    order = [(gi, b) for gi, g in enumerate(wl.groups) for b in range(g.nblocks)]
-    idx = rng.permutation(len(order))
-    for k in idx:
-        gi, b = order[k]
-        g = wl.groups[gi]
-        v = dense.apply(g.p, g.h[b:b + 1], g.u[b:b + 1], dense.NEUMANN)
-        dense.solve(g.p, g.h[b:b + 1], v, dense.CELL)
-        dof += g.n ** 3
-        nblk += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
-    return {"value": dof / wall / 1e9, "unit": "GDoF/s", "cores": max(1, int(round(cpu / wall))),
-            "kind": "oracle",
-            "sample": f"{nblk} random blocks of {wl.name} (dense Kronecker apply + dense solve with "
-                      f"long-double refinement, FP64), {wall:.1f} s wall"}
+    dof = nblk = 0
+    with ctx.Pool(workers, initializer=_one_thread) as pool:
+        seed = 0
+        while time.perf_counter() - t0 < budget_s:
+            for d, b in pool.map(_dense_chunk, range(seed, seed + workers)):
+                dof += d
+                nblk += b
+            seed += workers
+        wall = time.perf_counter() - t0
+        pool.close()
+        pool.join()
+    cpu = child_cpu() - c0
+    out = {"value": dof / wall / 1e9, "unit": "GDoF/s", "cores": max(1, int(round(cpu / wall))),
+           "kind": "oracle",
+           "sample": f"{nblk} random blocks of {wl.name} (dense Kronecker apply, then dense LAPACK solve of the "
+                     f"cell block with long-double refinement; FP64; {workers} worker processes), "
+                     f"{wall:.1f} s wall",
+           "host_cpu": model, "nproc": ncpu, "cores_available": avail}
+    parts = []
+    for gi, g in enumerate(wl.groups):
+        step = max(1, -(-g.nblocks // (4 * workers)))
+        parts += [(gi, lo, min(g.nblocks, lo + step)) for lo in range(0, g.nblocks, step)]
+    c0 = child_cpu()
+    t0 = time.perf_counter()
+    with ctx.Pool(workers, initializer=_one_thread) as pool:
+        pool.map(_sumfact_part, parts)
+        wall = time.perf_counter() - t0
+        pool.close()
+        pool.join()
+    cpu = child_cpu() - c0
+    out["sumfact"] = {"value": wl.ndof / wall / 1e9, "unit": "GDoF/s", "cores": max(1, int(round(cpu / wall))),
+                      "sample": f"whole {wl.name} (numpy contractions, FP64; {workers} worker processes), "
+                                f"{wall:.1f} s wall"}
+    _CPU_WL = None
+    return out
+
+
+def measure_ops(name, dtname, stream, reps=20):
+    """apply and apply_inverse of a workload in one storage precision with
+    buffer sets rotated past the last-level cache (HIP events on stream)."""
+    import torch
+    from paper_2609_04534_amd import tpfdm
+    codes = {"f64": (tpfdm.F64, torch.float64, 8), "f32": (tpfdm.F32, torch.float32, 4),
+             "f16": (tpfdm.F16, torch.float16, 2), "bf16": (tpfdm.BF16, torch.bfloat16, 2)}
+    code, tdt, es = codes[dtname]
+    wl, _ = build_workload(name)
+    plan = tpfdm.Plan(tpfdm.groups_for_workload(wl))
+    plan.setup_inverse(tpfdm.OP_CELL)
+    E, ndof = plan.vector_elems, plan.ndof
+    cu = torch.from_numpy(np.concatenate([g.u.reshape(-1) for g in wl.groups])).cuda().to(tdt)
+    vec_bytes = E * es
+    R = int(min(16, max(2, -(-1.0e9 // (3 * vec_bytes)))))
+    U = [torch.empty(E, dtype=tdt, device="cuda") for _ in range(R)]
+    for u in U:
+        plan.pack(cu, u)
+    V = [torch.empty_like(U[0]) for _ in range(R)]
+    X = [torch.empty_like(U[0]) for _ in range(R)]
+    for k in range(3):
+        plan.apply(U[k % R], V[k % R], tpfdm.OP_NEUMANN, stream=stream)
+        plan.apply_inverse(V[k % R], X[k % R], stream=stream)
+    ms_a = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
+    ms_i = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
+    ms_s = time_launches(lambda k: (plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream),
+                                    plan.apply_inverse(V[k], X[k], stream=stream)), stream, reps, R)
+    ab = algorithmic_bytes(wl, es)
+    kern = [[plan.kernel(i, 0, code, grid=True), plan.kernel(i, 1, code, grid=True)] for i in range(len(wl.groups))]
+    out = {"workload": name, "dtype": dtname, "ndof": ndof, "kernels": kern,
+           "step_GDoF/s": ndof / ms_s / 1e6, "ms_per_step": ms_s}
+    for key, ms, which in (("apply", ms_a, "apply"), ("apply_inverse", ms_i, "inverse")):
+        out[key] = {"ms": ms, "GDoF/s": ndof / ms / 1e6, "GB/s": ab / ms / 1e6,
+                    "hbm_frac": ab / ms / 1e6 / HBM_PEAK_GBS, "TFLOP/s": flops(wl, which) / ms / 1e9}
+    plan.destroy()
+    del U, V, X, cu
+    torch.cuda.empty_cache()
+    return out
+
+
+def true_relres(plan, b, x):
+    """||b - A x||_2 / ||b||_2 with the library's coupled operator in FP64."""
+    import torch
+    from paper_2609_04534_amd import tpfdm
+    ax = torch.empty_like(x)
+    plan.apply(x, ax, tpfdm.OP_SIPG)
+    torch.cuda.synchronize()
+    return float(torch.linalg.vector_norm(b - ax) / torch.linalg.vector_norm(b))
+
+
+# Mixed-precision MG-PCG: (degree, cells per side) and the stopping rules:
+# the paper's (Sec. 6.1: <r, z>^{1/2} reduced by 1e-10) and the serving
+# tolerance (||r||_2 <= 1e-8 ||b||_2)
+MIXED_MESHES = [(3, 128), (3, 64), (2, 96)]
+MIXED_RULES = [("precnorm", 1e-10), ("residual", 1e-8)]
+# (name, multigrid level storage, inner block-inverse precision)
+MIXED_CONFIGS = [("fp64", "f64", "f64"), ("fp64_storage_fp32_inner", "f64", "f32"),
+                 ("fp32_storage", "f32", "f32")]
+
+
+def run_mixed_mg(stream, meshes=MIXED_MESHES, reps=4, emit=True):
+    """MG-PCG with FP64 level vectors vs FP32 level vectors (z in FP32, x, r,
+    p and every dot product in FP64): median solve time, iterations and the
+    true final residual of each; one JSON line per mesh, rule and config."""
+    import torch
+    from paper_2609_04534_amd import tpfdm, workloads
+    dt = {"f64": tpfdm.F64, "f32": tpfdm.F32}
+    recs = []
+    for p, m in meshes:
+        mesh = workloads.unit_cube_mesh(p, m, seed=11)
+        plan = tpfdm.Plan.mesh(mesh.n, mesh.cells, mesh.h)
+        plan.setup_inverse(tpfdm.OP_CELL)
+        b = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
+        plan.pack(torch.from_numpy(mesh.u).cuda(), b)
+        x = torch.empty_like(b)
+        for rule, rtol in MIXED_RULES:
+            for cname, storage, inner in MIXED_CONFIGS:
+                V = tpfdm.MG(plan, storage=dt[storage])
+                solver = tpfdm.PCG(plan)
+                solver.set_multigrid(V)
+                solver.set_norm(tpfdm.PCG_PRECONDITIONED if rule == "precnorm" else tpfdm.PCG_RESIDUAL)
+                lat, s = [], None
+                for i in range(reps + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    s = solver.solve(b, x, inner=dt[inner], rtol=rtol, maxit=100, check_every=4, stream=stream)
+                    t1 = time.perf_counter()
+                    if i >= 1:
+                        lat.append(t1 - t0)
+                t = float(np.median(lat))
+                rec = {"workload": f"mg_pcg_p{p}_{m}cube", "rule": rule, "rtol": rtol, "config": cname,
+                       "level_storage": storage, "inner": inner, "ndof": mesh.ndof,
+                       "iterations": s["iterations"], "converged": bool(s["converged"]),
+                       "relres_recursive": s["relres"], "relres_true": true_relres(plan, b, x),
+                       "solve_ms": t * 1e3, "solve_MDoF/s": mesh.ndof / t / 1e6}
+                recs.append(rec)
+                if emit:
+                    print(json.dumps(rec), flush=True)
+                solver.destroy()
+                V.destroy()
+        plan.destroy()
+        del b, x
+        torch.cuda.empty_cache()
+    return recs
 
 
 def main():
@@ -130,6 +322,11 @@ def main():
                     help="time only the coupled SIPG operator on the unit-cube meshes (JSON lines)")
     ap.add_argument("--dtype", default=None, choices=["f64", "f32", "f16", "bf16"],
                     help="storage precision of the step (default: the workload's)")
+    ap.add_argument("--mixed", action="store_true",
+                    help="MG-PCG with FP64 vs FP32 multigrid level storage at the paper's and the serving "
+                         "stopping rules (JSON lines)")
+    ap.add_argument("--uneven", action="store_true",
+                    help="only the batched uneven-degree modes (per-group, single launch, tuned, graphs; JSON lines)")
     ap.add_argument("--counters", action="store_true",
                     help="no timing: launch a plain device copy of one vector, apply and "
                          "apply_inverse 3 times each and one FP64- and one FP32-inner solve "
@@ -139,6 +336,14 @@ def main():
         print(f"bench.py measures one GPU only: the blocks are independent and each GPU would run the "
               f"same kernels on its share; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+
+    headline = not (args.suite or args.mg_paper or args.patches or args.pcg or args.serve or args.sipg
+                    or args.uneven or args.mixed or args.counters)
+    cpu_base = None
+    if headline and not args.no_cpu_baseline:
+        # before anything initialises the GPU: the baseline forks its workers
+        _log("cpu baseline")
+        cpu_base = cpu_baseline(build_workload(args.workload)[0])
 
     import torch
     from paper_2609_04534_amd import tpfdm
@@ -151,6 +356,12 @@ def main():
 
     if args.suite:
         run_suite(args, stream)
+        return
+    if args.uneven:
+        run_uneven(args, stream)
+        return
+    if args.mixed:
+        run_mixed_mg(stream)
         return
     if args.mg_paper:
         run_mg_paper(args, stream)
@@ -301,14 +512,29 @@ def main():
                           "by_inner": by_inner,
                           "fastest_inner": min(by_inner, key=lambda k: by_inner[k]["p50_ms"])},
     }
-    if not args.no_cpu_baseline:
-        _log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(wl)
-    else:
-        out["cpu_baseline"] = None
     plan.destroy()
+    del U, V, X, bb, xs
+    torch.cuda.empty_cache()
+    # the metric's other degrees and precisions, same step, same measurement
+    extra = {}
+    for name, dtn in EXTRA_OPS:
+        _log(f"ops {name} {dtn}")
+        r = measure_ops(name, dtn, stream, reps=max(args.steps, 20))
+        extra[f"{name}/{dtn}"] = r
+    out["ops_other_workloads"] = extra
+    # mixed precision at equal final residual: MG-PCG with FP32 level storage
+    # against FP64 on the paper's configuration (p = 3, 128^3 cells)
+    _log("mixed-precision MG-PCG")
+    recs = run_mixed_mg(stream, meshes=[(3, 128)], reps=3, emit=False)
+    out["mixed_precision_mg_pcg"] = [
+        {k: r[k] for k in ("rule", "rtol", "config", "iterations", "relres_true", "solve_ms")} for r in recs]
+    out["cpu_baseline"] = cpu_base
     print(json.dumps(out), flush=True)
 
+
+# the headline line also carries these (workload, storage precision) cases
+EXTRA_OPS = [("p2_128cube", "f64"), ("p7_32cube_aniso", "f64"), ("p7_32cube_aniso", "f32"),
+             ("p7_32cube_aniso", "f16"), ("p7_32cube_aniso", "bf16")]
 
 SUITE = [
     ("p2_8cube_h1/8", ["f64", "f32"]),
@@ -669,11 +895,16 @@ def run_uneven(args, stream):
     cu = torch.from_numpy(np.concatenate([g.u.reshape(-1) for g in wl.groups])).cuda()
     cb = torch.from_numpy(np.concatenate([g.b.reshape(-1) for g in wl.groups])).cuda()
     reps = max(args.steps, 50)
-    for mode in ("per_group", "per_group_tuned", "per_group_graph", "persistent", "persistent_graph"):
+    for mode in ("per_group", "per_group_tuned", "per_group_graph", "persistent", "persistent_graph",
+                 "persistent_tuned", "persistent_tuned_graph"):
         plan = tpfdm.Plan(tpfdm.groups_for_workload(wl), persistent=mode.startswith("persistent"))
         plan.setup_inverse(tpfdm.OP_CELL)
-        if mode == "per_group_tuned":
-            plan.autotune(tpfdm.F32)
+        config = None
+        if "_tuned" in mode:
+            plan.autotune(tpfdm.F32, reps=50)
+        if mode.startswith("persistent"):
+            config = {f"p{g.p}": [plan.launch_config(i, c, tpfdm.F32) for c in (0, 1, 2)]
+                      for i, g in enumerate(wl.groups)}
         E = plan.vector_elems
         u = torch.empty(E, dtype=torch.float32, device="cuda")
         plan.pack(cu.float(), u)
@@ -711,7 +942,8 @@ def run_uneven(args, stream):
                           "inverse_ms": ms_i, "inverse_GDoF/s": plan.ndof / ms_i / 1e6,
                           "solve_p50_ms": float(np.percentile(lat, 50)),
                           "solve_p99_ms": float(np.percentile(lat, 99)),
-                          "solve_max_iters": summ["max_iters"], "solve_max_relres": summ["max_relres"]}),
+                          "solve_max_iters": summ["max_iters"], "solve_max_relres": summ["max_relres"],
+                          "launch_config": config}),
               flush=True)
         if mode.endswith("_graph"):
             ga.destroy(), gi.destroy(), gs.destroy()

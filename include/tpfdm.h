@@ -317,15 +317,31 @@ tp_status tp_unpack(tp_plan* plan, const void* blocked, void* canonical, tp_dtyp
  * every inner precision).  us: optional host array [ngroups][3] that receives
  * the best average microseconds per launch (apply, apply_inverse, solve; -1
  * where not measured).  reps <= 0 selects 10.  Host-synchronous; allocates
- * and frees its scratch.  TP_ERR_UNSUPPORTED for persistent plans. */
+ * and frees its scratch.
+ * For a persistent plan it tunes the single launch of each call instead
+ * (apply and apply_inverse in dtype, the solve with inner precision dtype):
+ * per group the tile body (one block per lane for n <= 4, or one wave per
+ * tile) and the tiles each workgroup runs (1, 2, 4, 8), the order of the
+ * groups' segments in the launch, and the solve's grid (occupancy grid,
+ * half of it, one workgroup per work item), by coordinate descent over
+ * whole-launch timings (at least 30 launches each), keeping the default when
+ * the tuned choice is not faster.  us[0..2] then receive the single
+ * launch's times, the rest -1.  Tile bodies and per-tile arithmetic are
+ * those of the per-group launches, so results are unchanged bit for bit.
+ * Graphs capture the launch configuration current at their creation: create
+ * them after tuning. */
 tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* us);
 
 /* Kernel family a call would use for a group in dtype, in the low 4 bits:
  * 0 one block per lane, 1 one wave per tile, 2 MFMA, 3 per-block factors
  * (GENERAL); for apply / apply_inverse with one wave per tile, bits 4-7 hold
  * the grid (1 full occupancy grid, 2 half, 0 one workgroup per tile).  call
- * 0 apply, 1 apply_inverse, 2 solve (dtype ignored).  -1 for a persistent
- * plan or an invalid argument.  MFMA assumes 16-byte aligned vectors. */
+ * 0 apply, 1 apply_inverse, 2 solve (dtype ignored).  MFMA assumes 16-byte
+ * aligned vectors.  For a persistent plan (dtype = the storage type, for the
+ * solve the inner precision): bits 0-3 the tile body (0 lane, 1 wave), bits
+ * 4-7 the solve grid (1 occupancy grid, 2 half, 0 one workgroup per item),
+ * bits 8-11 log2 of the tiles per workgroup, bits 12-27 the position of the
+ * group's segment in the launch.  -1 for an invalid argument. */
 int32_t tp_plan_group_kernel(const tp_plan* plan, int32_t group, int32_t call, tp_dtype dtype);
 
 /* Preconditioned conjugate gradients for the coupled SIPG system A x = b of
@@ -416,6 +432,18 @@ tp_status tp_pcg_set_norm(tp_pcg* pcg, int32_t norm);
 
 typedef struct tp_mg tp_mg;
 tp_status tp_mg_create(tp_plan* plan, tp_mg** out);
+/* The same hierarchy with its level vectors (right-hand sides, corrections,
+ * residual scratch, on every level) stored in `storage`: TP_F64 (as
+ * tp_mg_create) or TP_F32, which halves the bytes every smoothing, transfer
+ * and coarse kernel moves.  Arithmetic stays FP64 in registers (the
+ * smoother's block inverse in the solve's inner precision); values are
+ * rounded to FP32 where a level vector is stored.  A V-cycle first rounds
+ * b into the finest FP32 right-hand side; tp_mg_vcycle writes x back in
+ * FP64, and inside tp_pcg_* solves the preconditioned residual z stays in
+ * FP32 (the CG recurrences, x, r, p and every dot product remain FP64:
+ * (r, z) and p = z + beta p read z in FP32).  TP_ERR_UNSUPPORTED for other
+ * types. */
+tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out);
 tp_status tp_mg_vcycle(tp_mg* mg, const double* b, double* x, hipStream_t stream);
 tp_status tp_mg_destroy(tp_mg* mg);
 tp_status tp_pcg_set_multigrid(tp_pcg* pcg, tp_mg* mg);

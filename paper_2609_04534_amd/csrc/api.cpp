@@ -104,7 +104,6 @@ static void free_plan_memory(Plan* p) {
             if (p->mfma_apply_dev[i][j]) (void)hipFree(p->mfma_apply_dev[i][j]), p->mfma_apply_dev[i][j] = nullptr;
         if (p->mfma_inv_dev[i]) (void)hipFree(p->mfma_inv_dev[i]), p->mfma_inv_dev[i] = nullptr;
     }
-    if (p->items_dev) (void)hipFree(p->items_dev), p->items_dev = nullptr;
 }
 
 static tp_status alloc_dev(void** ptr, size_t bytes, const char* what) {
@@ -271,13 +270,14 @@ static tp_status group_inverse(const Plan& p, const GroupInfo& g, const void* r,
     }
 }
 static tp_status group_solve(const Plan& p, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
-                             double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base,
-                             int64_t* nparts, hipStream_t s) {
+                             double rtol, int maxit, int32_t* iters, double* relres, const SolveWork& w,
+                             int64_t part_base, int64_t* nparts, hipStream_t s) {
     switch (solve_kind(p, g)) {
         case KIND_GENERAL:
-            return launch_solve_gen(p, g, b, x, inner, rtol, maxit, iters, relres, part_base, nparts, s);
-        case KIND_LANE: return launch_solve_lane(p, g, b, x, inner, rtol, maxit, iters, relres, part_base, nparts, s);
-        default: return launch_solve(p, g, b, x, inner, rtol, maxit, iters, relres, part_base, nparts, s);
+            return launch_solve_gen(p, g, b, x, inner, rtol, maxit, iters, relres, w, part_base, nparts, s);
+        case KIND_LANE:
+            return launch_solve_lane(p, g, b, x, inner, rtol, maxit, iters, relres, w, part_base, nparts, s);
+        default: return launch_solve(p, g, b, x, inner, rtol, maxit, iters, relres, w, part_base, nparts, s);
     }
 }
 
@@ -660,6 +660,280 @@ tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opt
 }
 }  // namespace
 
+
+namespace tpfdm {
+// The block-local solve of tp_solve: the launches write their partial
+// summaries to w.parts and the reduction the summary to w.summary.
+tp_status solve_impl(tp_plan* plan, const double* b, double* x, tp_dtype inner, double rtol, int32_t maxit,
+                     int32_t* iters, double* relres, tp_solve_summary* summary, hipStream_t stream,
+                     const SolveWork& w) {
+    if (hermite_wave(*plan)) return hermite_wave_error();
+    if (plan->inverse_op < 0 || (plan->factor_mode == TP_FACTOR_SCALED && plan->inverse_op != TP_OP_CELL))
+        return set_error(TP_ERR_STATE, "tp_solve needs tp_setup_inverse(TP_OP_CELL) first");
+    if (inner != TP_F64 && inner != TP_F32 && inner != TP_F16 && inner != TP_BF16)
+        return set_error(TP_ERR_ARG, "invalid inner precision");
+    if (!(rtol >= 0.0) || !std::isfinite(rtol)) return set_error(TP_ERR_ARG, "rtol must be finite and >= 0");
+    if (maxit < 0) return set_error(TP_ERR_ARG, "maxit must be >= 0");
+    if (plan->vec_elems > 0 && (!b || !x)) return set_error(TP_ERR_ARG, "b and x must be non-null");
+    if (static_cast<const void*>(b) == static_cast<const void*>(x) && b)
+        return set_error(TP_ERR_ARG, "b and x must not alias");
+    tp_status st = TP_OK;
+    int64_t nparts = 0;
+    if (plan->persistent) {
+        st = launch_solve_persistent(*plan, b, x, inner, rtol, maxit, iters, relres, w, &nparts, stream);
+        if (st != TP_OK) return st;
+    } else {
+        for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
+            const GroupInfo& g = plan->groups[i];
+                int64_t np = 0;
+            st = group_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, w, nparts, &np, stream);
+            nparts += np;
+        }
+        if (st != TP_OK) return st;
+    }
+    st = launch_summary_reduce(w, nparts, stream);
+    if (st != TP_OK) return st;
+    if (summary) {
+        SolveSummary hs;
+        hipError_t e = hipMemcpyAsync(&hs, w.summary, sizeof(hs), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_error(e, "solve summary readback");
+        summary->max_iters = hs.max_iters;
+        summary->n_failed = hs.n_failed;
+        double mr;
+        std::memcpy(&mr, &hs.max_relres_bits, sizeof(mr));
+        summary->max_relres = mr;
+        if (hs.nonfinite > 0)
+            return set_error(TP_ERR_NONFINITE, std::to_string(hs.nonfinite) + " blocks had a non-finite residual");
+        if (hs.n_failed > 0)
+            return set_error(TP_ERR_NOT_CONVERGED, std::to_string(hs.n_failed) + " blocks missed rtol");
+    }
+    return TP_OK;
+}
+
+}  // namespace tpfdm
+
+namespace tpfdm {
+namespace {
+
+// Scratch vectors and timing of the autotuner: nsets pairs (U, V) of
+// plan-sized buffers of pseudo-random values, rotated so that one pass
+// streams from HBM rather than from the last-level cache, and, for the
+// solve, an FP64 right-hand side and iterate.
+struct TuneBench {
+    Plan* plan = nullptr;
+    int nsets = 1;
+    void* U[8] = {};
+    void* V[8] = {};
+    void *b = nullptr, *x = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int cur = 0;
+    int reps = 10;
+
+    tp_status init(Plan* p, tp_dtype dt, bool solve, int r) {
+        plan = p;
+        reps = r;
+        const size_t es = static_cast<size_t>(esize_of(dt));
+        const size_t ne = static_cast<size_t>(p->vec_elems);
+        const size_t pair_bytes = 2 * ne * es;
+        nsets = static_cast<int>(std::max<size_t>(1, std::min<size_t>(8, (768u << 20) / pair_bytes + 1)));
+        tp_status st = TP_OK;
+        for (int k = 0; st == TP_OK && k < nsets; ++k) {
+            st = alloc_dev(&U[k], ne * es, "autotune scratch");
+            if (st == TP_OK) st = alloc_dev(&V[k], ne * es, "autotune scratch");
+        }
+        if (st == TP_OK && solve) st = alloc_dev(&b, ne * sizeof(double), "autotune scratch");
+        if (st == TP_OK && solve) st = alloc_dev(&x, ne * sizeof(double), "autotune scratch");
+        hipError_t e = hipSuccess;
+        if (st == TP_OK) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (st == TP_OK && e == hipSuccess) e = hipEventCreate(&e0);
+        if (st == TP_OK && e == hipSuccess) e = hipEventCreate(&e1);
+        if (st == TP_OK && e != hipSuccess) st = hip_error(e, "autotune stream");
+        for (int k = 0; st == TP_OK && k < nsets; ++k)
+            st = launch_fill(U[k], static_cast<int64_t>(ne), dt, 1, false, s);
+        if (st == TP_OK && solve) st = launch_fill(b, static_cast<int64_t>(ne), TP_F64, 2, false, s);
+        if (st == TP_OK) {
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) st = hip_error(e, "autotune scratch fill");
+        }
+        return st;
+    }
+    // average microseconds of reps launches of f (after one warm-up); the
+    // stream is idle again on return
+    template <typename F>
+    tp_status time(F f, double* out) {
+        tp_status r = f();
+        for (int i = 0; r == TP_OK && i < reps; ++i) {
+            if (i == 0) {
+                hipError_t he = hipEventRecord(e0, s);
+                if (he != hipSuccess) return hip_error(he, "autotune event");
+            }
+            r = f();
+        }
+        if (r != TP_OK) return r;
+        hipError_t he = hipEventRecord(e1, s);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) return hip_error(he, "autotune timing");
+        *out = 1e3 * ms / reps;
+        return TP_OK;
+    }
+    ~TuneBench() {
+        if (s) (void)hipStreamSynchronize(s);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+        for (int k = 0; k < nsets; ++k) {
+            if (U[k]) (void)hipFree(U[k]);
+            if (V[k]) (void)hipFree(V[k]);
+        }
+        for (void* ptr : {b, x})
+            if (ptr) (void)hipFree(ptr);
+    }
+};
+
+// Tunes the single launch of a persistent plan for one call and dtype by
+// coordinate descent over its parameters: per group (in turn) the tile body
+// and the tiles per workgroup, then the segment order, then (solve) the
+// grid.  Each candidate is uploaded and timed as the whole launch; the best
+// of each step is kept.  A last comparison against the default
+// configuration (best of three alternating timings each) guards against a
+// choice that only won by noise.
+tp_status tune_persistent_call(Plan& plan, int call, tp_dtype dt, TuneBench& tb, double* best_us) {
+    PersistCfg& c = plan.pcfg[call][dt];
+    const size_t ng = plan.groups.size();
+    auto launch = [&]() -> tp_status {
+        tb.cur = (tb.cur + 1) % tb.nsets;
+        switch (call) {
+            case PCALL_APPLY:
+                return launch_apply_persistent(plan, TP_OP_NEUMANN, tb.U[tb.cur], tb.V[tb.cur], dt, tb.s);
+            case PCALL_INVERSE: return launch_inverse_persistent(plan, tb.U[tb.cur], tb.V[tb.cur], dt, tb.s);
+            default: {
+                int64_t np = 0;
+                tp_status r = launch_fill(tb.x, plan.vec_elems, TP_F64, 0, true, tb.s);
+                if (r == TP_OK)
+                    r = launch_solve_persistent(plan, static_cast<const double*>(tb.b), static_cast<double*>(tb.x),
+                                                dt, 1e-10, 20, nullptr, nullptr, plan_work(plan), &np, tb.s);
+                return r;
+            }
+        }
+    };
+    auto measure = [&](double* t) -> tp_status {
+        tp_status r = persistent_upload(plan, call, dt);   // the stream is idle between timings
+        if (r == TP_OK) r = tb.time(launch, t);
+        return r;
+    };
+    const PersistCfg dflt = c;
+    double best = 0.0;
+    tp_status st = measure(&best);
+    // per group: body and tiles per workgroup
+    for (size_t gi = 0; st == TP_OK && gi < ng; ++gi) {
+        const GroupInfo& g = plan.groups[gi];
+        if (g.nblocks == 0) continue;
+        const int8_t keep_lane = c.lane[gi], keep_tpw = c.tpw[gi];
+        int8_t best_lane = keep_lane, best_tpw = keep_tpw;
+        for (int lane = 0; st == TP_OK && lane < 2; ++lane) {
+            if (lane && (call == PCALL_SOLVE || !persistent_lane_ok(plan, g))) continue;
+            for (int8_t tpw : {int8_t(1), int8_t(2), int8_t(4), int8_t(8)}) {
+                if (lane == keep_lane && tpw == keep_tpw) continue;
+                c.lane[gi] = static_cast<int8_t>(lane);
+                c.tpw[gi] = tpw;
+                double t = 0.0;
+                st = measure(&t);
+                if (st != TP_OK) break;
+                if (t < best) best = t, best_lane = c.lane[gi], best_tpw = tpw;
+            }
+        }
+        c.lane[gi] = best_lane;
+        c.tpw[gi] = best_tpw;
+    }
+    // segment order: as given, reversed, by degree descending and ascending
+    if (st == TP_OK && ng > 1) {
+        std::vector<std::vector<int32_t>> orders;
+        std::vector<int32_t> o = c.order;
+        std::reverse(o.begin(), o.end());
+        orders.push_back(o);
+        o = c.order;
+        std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return plan.groups[a].n > plan.groups[b].n; });
+        orders.push_back(o);
+        std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return plan.groups[a].n < plan.groups[b].n; });
+        orders.push_back(o);
+        std::vector<int32_t> best_order = c.order;
+        for (const auto& cand : orders) {
+            if (cand == best_order) continue;
+            c.order = cand;
+            double t = 0.0;
+            st = measure(&t);
+            if (st != TP_OK) break;
+            if (t < best) best = t, best_order = cand;
+        }
+        c.order = best_order;
+    }
+    // solve grid: occupancy grid, half of it, one workgroup per item
+    if (st == TP_OK && call == PCALL_SOLVE) {
+        int8_t best_grid = c.grid;
+        for (int8_t gr : {int8_t(1), int8_t(2), int8_t(0)}) {
+            if (gr == best_grid) continue;
+            c.grid = gr;
+            if (persistent_upload(plan, call, dt) == TP_OK && gr == 0 && c.items > plan.partials_cap) continue;
+            double t = 0.0;
+            st = measure(&t);
+            if (st != TP_OK) break;
+            if (t < best) best = t, best_grid = gr;
+        }
+        c.grid = best_grid;
+    }
+    if (st == TP_OK) {
+        const PersistCfg tuned = c;
+        double tt = 1e300, td = 1e300;
+        for (int k = 0; st == TP_OK && k < 3; ++k) {
+            double t = 0.0;
+            c = dflt;
+            st = measure(&t);
+            td = std::min(td, t);
+            if (st != TP_OK) break;
+            c = tuned;
+            st = measure(&t);
+            tt = std::min(tt, t);
+        }
+        if (st == TP_OK && td <= tt) c = dflt, best = td;
+        else best = tt;
+        c.tuned = true;
+    }
+    if (st == TP_OK) st = persistent_upload(plan, call, dt);
+    if (st != TP_OK) {                 // leave the plan in its default state
+        c = dflt;
+        (void)persistent_upload(plan, call, dt);
+    }
+    *best_us = best;
+    return st;
+}
+
+tp_status autotune_persistent(Plan* plan, tp_dtype dtype, int reps, double* us) {
+    if (reps <= 0) reps = 10;
+    reps = std::max(reps, 30);       // single launches of a few microseconds need more samples
+    const size_t ng = plan->groups.size();
+    if (us)
+        for (size_t i = 0; i < 3 * ng; ++i) us[i] = -1.0;
+    if (plan->vec_elems == 0 || plan->nblocks == 0) return TP_OK;
+    const bool inv = plan->inverse_op >= 0 && plan->factor_mode == TP_FACTOR_SCALED;
+    const bool solve = inv && plan->inverse_op == TP_OP_CELL;
+    TuneBench tb;
+    tp_status st = tb.init(plan, dtype, solve, reps);
+    for (int call = 0; st == TP_OK && call < 3; ++call) {
+        if ((call == PCALL_INVERSE && !inv) || (call == PCALL_SOLVE && !solve)) continue;
+        double t = -1.0;
+        st = tune_persistent_call(*plan, call, dtype, tb, &t);
+        if (st == TP_OK && us) us[call] = t;
+    }
+    return st;
+}
+
+}  // namespace
+}  // namespace tpfdm
+
 extern "C" {
 
 tp_status tp_plan_destroy(tp_plan* plan) {
@@ -825,48 +1099,7 @@ tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype
 tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, double rtol, int32_t maxit,
                    int32_t* iters, double* relres, tp_solve_summary* summary, hipStream_t stream) {
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
-    if (hermite_wave(*plan)) return hermite_wave_error();
-    if (plan->inverse_op < 0 || (plan->factor_mode == TP_FACTOR_SCALED && plan->inverse_op != TP_OP_CELL))
-        return set_error(TP_ERR_STATE, "tp_solve needs tp_setup_inverse(TP_OP_CELL) first");
-    if (inner != TP_F64 && inner != TP_F32 && inner != TP_F16 && inner != TP_BF16)
-        return set_error(TP_ERR_ARG, "invalid inner precision");
-    if (!(rtol >= 0.0) || !std::isfinite(rtol)) return set_error(TP_ERR_ARG, "rtol must be finite and >= 0");
-    if (maxit < 0) return set_error(TP_ERR_ARG, "maxit must be >= 0");
-    if (plan->vec_elems > 0 && (!b || !x)) return set_error(TP_ERR_ARG, "b and x must be non-null");
-    if (static_cast<const void*>(b) == static_cast<const void*>(x) && b)
-        return set_error(TP_ERR_ARG, "b and x must not alias");
-    tp_status st = TP_OK;
-    int64_t nparts = 0;
-    if (plan->persistent) {
-        st = launch_solve_persistent(*plan, b, x, inner, rtol, maxit, iters, relres, &nparts, stream);
-        if (st != TP_OK) return st;
-    } else {
-        for (size_t i = 0; st == TP_OK && i < plan->groups.size(); ++i) {
-            const GroupInfo& g = plan->groups[i];
-                int64_t np = 0;
-            st = group_solve(*plan, g, b, x, inner, rtol, maxit, iters, relres, nparts, &np, stream);
-            nparts += np;
-        }
-        if (st != TP_OK) return st;
-    }
-    st = launch_summary_reduce(*plan, nparts, stream);
-    if (st != TP_OK) return st;
-    if (summary) {
-        SolveSummary hs;
-        hipError_t e = hipMemcpyAsync(&hs, plan->summary_dev, sizeof(hs), hipMemcpyDeviceToHost, stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return hip_error(e, "solve summary readback");
-        summary->max_iters = hs.max_iters;
-        summary->n_failed = hs.n_failed;
-        double mr;
-        std::memcpy(&mr, &hs.max_relres_bits, sizeof(mr));
-        summary->max_relres = mr;
-        if (hs.nonfinite > 0)
-            return set_error(TP_ERR_NONFINITE, std::to_string(hs.nonfinite) + " blocks had a non-finite residual");
-        if (hs.n_failed > 0)
-            return set_error(TP_ERR_NOT_CONVERGED, std::to_string(hs.n_failed) + " blocks missed rtol");
-    }
-    return TP_OK;
+    return solve_impl(plan, b, x, inner, rtol, maxit, iters, relres, summary, stream, plan_work(*plan));
 }
 
 tp_status tp_solve_summary_fetch(tp_plan* plan, tp_solve_summary* summary, hipStream_t stream) {
@@ -988,7 +1221,7 @@ tp_status tp_unpack(tp_plan* plan, const void* blocked, void* canonical, tp_dtyp
 tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* us) {
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
     if (!valid_dtype(dtype)) return set_error(TP_ERR_UNSUPPORTED, "invalid dtype");
-    if (plan->persistent) return set_error(TP_ERR_UNSUPPORTED, "persistent plans have no per-group kernel choice");
+    if (plan->persistent) return autotune_persistent(plan, dtype, reps, us);
     if (plan->basis == TP_BASIS_HERMITE)
         return set_error(TP_ERR_UNSUPPORTED, "plans in the Hermite-type basis run the lane kernels only");
     if (reps <= 0) reps = 10;
@@ -998,53 +1231,8 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
     if (plan->vec_elems == 0) return TP_OK;
     const bool inv = plan->inverse_op >= 0 && plan->factor_mode == TP_FACTOR_SCALED;
     const bool solve = inv && plan->inverse_op == TP_OP_CELL;
-    const size_t es = static_cast<size_t>(esize_of(dtype));
-    const size_t ne = static_cast<size_t>(plan->vec_elems);
-    // rotate over enough scratch pairs that one pass streams from HBM rather
-    // than from the last-level cache (>= 768 MB touched per rotation)
-    const size_t pair_bytes = 2 * ne * es;
-    const int nsets = static_cast<int>(std::max<size_t>(1, std::min<size_t>(8, (768u << 20) / pair_bytes + 1)));
-    void* U[8] = {};
-    void* V[8] = {};
-    void *u = nullptr, *v = nullptr, *b = nullptr, *x = nullptr;
-    hipStream_t s = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    tp_status st = TP_OK;
-    for (int k = 0; st == TP_OK && k < nsets; ++k) {
-        st = alloc_dev(&U[k], ne * es, "autotune scratch");
-        if (st == TP_OK) st = alloc_dev(&V[k], ne * es, "autotune scratch");
-    }
-    u = U[0];
-    v = V[0];
-    int cur = 0;  // scratch pair of the next timed call
-    if (st == TP_OK && solve) st = alloc_dev(&b, ne * sizeof(double), "autotune scratch");
-    if (st == TP_OK && solve) st = alloc_dev(&x, ne * sizeof(double), "autotune scratch");
-    hipError_t e = hipSuccess;
-    if (st == TP_OK) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (st == TP_OK && e == hipSuccess) e = hipEventCreate(&e0);
-    if (st == TP_OK && e == hipSuccess) e = hipEventCreate(&e1);
-    if (st == TP_OK && e != hipSuccess) st = hip_error(e, "autotune stream");
-    for (int k = 0; st == TP_OK && k < nsets; ++k) st = launch_fill(U[k], static_cast<int64_t>(ne), dtype, 1, false, s);
-    if (st == TP_OK && solve) st = launch_fill(b, static_cast<int64_t>(ne), TP_F64, 2, false, s);
-    // average microseconds of reps launches of f (after one warm-up)
-    auto timeit = [&](auto f, double* out) -> tp_status {
-        tp_status r = f();
-        for (int i = 0; r == TP_OK && i < reps; ++i) {
-            if (i == 0) {
-                hipError_t he = hipEventRecord(e0, s);
-                if (he != hipSuccess) return hip_error(he, "autotune event");
-            }
-            r = f();
-        }
-        if (r != TP_OK) return r;
-        hipError_t he = hipEventRecord(e1, s);
-        if (he == hipSuccess) he = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he != hipSuccess) return hip_error(he, "autotune timing");
-        *out = 1e3 * ms / reps;
-        return TP_OK;
-    };
+    TuneBench tb;
+    tp_status st = tb.init(plan, dtype, solve, reps);
     for (size_t gi = 0; st == TP_OK && gi < ng; ++gi) {
         GroupInfo& g = plan->groups[gi];
         if (g.nblocks == 0 || g.factors) continue;
@@ -1054,7 +1242,7 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
         cands.push_back({KIND_WAVE, 1});
         cands.push_back({KIND_WAVE, 2});
         cands.push_back({KIND_WAVE, 0});
-        if (mfma_eligible(g, dtype, u, v)) cands.push_back({KIND_MFMA, 1});
+        if (mfma_eligible(g, dtype, tb.U[0], tb.V[0])) cands.push_back({KIND_MFMA, 1});
         for (int call = 0; st == TP_OK && call < (inv ? 2 : 1); ++call) {
             int8_t* tk = call == 0 ? &g.tune_apply[dtype] : &g.tune_inverse[dtype];
             int8_t* td = call == 0 ? &g.div_apply[dtype] : &g.div_inverse[dtype];
@@ -1064,18 +1252,13 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
                 *tk = static_cast<int8_t>(c.kind);
                 *td = static_cast<int8_t>(c.div);
                 double t = 0.0;
-                st = call == 0 ? timeit(
-                                     [&] {
-                                         cur = (cur + 1) % nsets;
-                                         return group_apply(*plan, g, TP_OP_NEUMANN, U[cur], V[cur], dtype, s);
-                                     },
-                                     &t)
-                               : timeit(
-                                     [&] {
-                                         cur = (cur + 1) % nsets;
-                                         return group_inverse(*plan, g, U[cur], V[cur], dtype, s);
-                                     },
-                                     &t);
+                st = tb.time(
+                    [&] {
+                        tb.cur = (tb.cur + 1) % tb.nsets;
+                        return call == 0 ? group_apply(*plan, g, TP_OP_NEUMANN, tb.U[tb.cur], tb.V[tb.cur], dtype, tb.s)
+                                         : group_inverse(*plan, g, tb.U[tb.cur], tb.V[tb.cur], dtype, tb.s);
+                    },
+                    &t);
                 if (st != TP_OK) break;
                 if (t < best) best = t, bc = c;
             }
@@ -1089,13 +1272,13 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
             for (int8_t k : {static_cast<int8_t>(KIND_LANE), static_cast<int8_t>(KIND_WAVE)}) {
                 g.tune_solve = k;
                 double t = 0.0;
-                st = timeit(
+                st = tb.time(
                     [&] {
                         int64_t np = 0;
-                        tp_status r = launch_fill(x, static_cast<int64_t>(ne), TP_F64, 0, true, s);
+                        tp_status r = launch_fill(tb.x, plan->vec_elems, TP_F64, 0, true, tb.s);
                         if (r != TP_OK) return r;
-                        return group_solve(*plan, g, static_cast<const double*>(b), static_cast<double*>(x), TP_F64,
-                                           1e-10, 20, nullptr, nullptr, 0, &np, s);
+                        return group_solve(*plan, g, static_cast<const double*>(tb.b), static_cast<double*>(tb.x),
+                                           TP_F64, 1e-10, 20, nullptr, nullptr, plan_work(*plan), 0, &np, tb.s);
                     },
                     &t);
                 if (st != TP_OK) break;
@@ -1105,23 +1288,22 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
             if (us && st == TP_OK) us[3 * gi + 2] = best;
         }
     }
-    if (s) (void)hipStreamSynchronize(s);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (s) (void)hipStreamDestroy(s);
-    for (int k = 0; k < nsets; ++k) {
-        if (U[k]) (void)hipFree(U[k]);
-        if (V[k]) (void)hipFree(V[k]);
-    }
-    for (void* ptr : {b, x})
-        if (ptr) (void)hipFree(ptr);
     return st;
 }
 
 int32_t tp_plan_group_kernel(const tp_plan* plan, int32_t group, int32_t call, tp_dtype dtype) {
     if (!plan || group < 0 || group >= static_cast<int32_t>(plan->groups.size()) || !valid_dtype(dtype)) return -1;
     const GroupInfo& g = plan->groups[group];
-    if (plan->persistent) return -1;
+    if (plan->persistent) {
+        if (call < 0 || call > 2) return -1;
+        const PersistCfg& c = plan->pcfg[call][dtype];
+        int pos = 0;
+        while (pos < static_cast<int>(c.order.size()) && c.order[pos] != group) ++pos;
+        int ltpw = 0;
+        while ((1 << ltpw) < c.tpw[group]) ++ltpw;
+        const int kind = (call != PCALL_SOLVE && c.lane[group] && persistent_lane_ok(*plan, g)) ? KIND_LANE : KIND_WAVE;
+        return kind | (call == PCALL_SOLVE ? c.grid << 4 : 0) | (ltpw << 8) | (pos << 12);
+    }
     // alignment-independent view: MFMA eligibility assumes 16-byte aligned vectors
     alignas(16) static const double probe[2] = {0.0, 0.0};
     const void* a = probe;

@@ -379,18 +379,18 @@ __device__ __forceinline__ void eo_inverse_body(const Pencil<N>& pc, const TC (&
     wave_sync();
 }
 
-// dst = A src entirely in LDS (dst may alias src); t1, t2 scratch slabs.
+// dst = A x with the lane's z-pencil of x in registers, through LDS (dst
+// may alias t1); t1, t2 scratch slabs.  dst receives the product in slab
+// layout, written by x-pencils; the wave is synchronised on return.
 template <int N, typename TC>
-__device__ __forceinline__ void eo_apply_lds(const Pencil<N>& pc, const TC* src, TC* dst, TC* t1, TC* t2,
-                                             const TC* ME, const TC* MO, const TC* PE, const TC* PO, TC sx, TC sy,
-                                             TC sz) {
+__device__ __forceinline__ void eo_apply_regs(const Pencil<N>& pc, const TC (&x)[N], TC* dst, TC* t1, TC* t2,
+                                              const TC* ME, const TC* MO, const TC* PE, const TC* PO, TC sx, TC sy,
+                                              TC sz) {
     using L = Slab<N>;
     constexpr int HC = EOShape<N>::HC, H = EOShape<N>::H;
     const int pa = pc.pa, pb = pc.pb;
     if (pc.act) {
-        TC x[N], e[HC], o[H], E[HC], O[H], y[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) x[k] = src[L::at(pa, pb, k)];
+        TC e[HC], o[H], E[HC], O[H], y[N];
         eo_split<N>(x, e, o);
         eo_mul<N>(ME, MO, e, o, E, O);
         eo_join<N>(E, O, y);
@@ -446,30 +446,56 @@ __device__ __forceinline__ void eo_apply_lds(const Pencil<N>& pc, const TC* src,
     wave_sync();
 }
 
-// slab <- D^{-1} slab entirely in LDS (each phase updates its own pencils).
+// dst = A src entirely in LDS (dst may alias src); t1, t2 scratch slabs.
 template <int N, typename TC>
-__device__ __forceinline__ void eo_inverse_lds(const Pencil<N>& pc, TC* slab, const TC* SE, const TC* SO,
-                                               const TC* lam, TC sx, TC sy, TC sz) {
+__device__ __forceinline__ void eo_apply_lds(const Pencil<N>& pc, const TC* src, TC* dst, TC* t1, TC* t2,
+                                             const TC* ME, const TC* MO, const TC* PE, const TC* PO, TC sx, TC sy,
+                                             TC sz) {
+    using L = Slab<N>;
+    TC x[N];
+    if (pc.act)
+#pragma unroll
+        for (int k = 0; k < N; ++k) x[k] = src[L::at(pc.pa, pc.pb, k)];
+    eo_apply_regs<N, TC>(pc, x, dst, t1, t2, ME, MO, PE, PO, sx, sy, sz);
+}
+
+// r <- D^{-1} r with the lane's z-pencil of r in registers on entry and on
+// return, through the LDS slab (each phase updates its own pencils).
+template <int N, typename TC>
+__device__ __forceinline__ void eo_inverse_regs(const Pencil<N>& pc, TC (&r)[N], TC* slab, const TC* SE,
+                                                const TC* SO, const TC* lam, TC sx, TC sy, TC sz) {
     using L = Slab<N>;
     const int pa = pc.pa, pb = pc.pb;
     if (pc.act) {
-        TC a[N], y[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) a[k] = slab[L::at(pa, pb, k)];
-        eo_fwd<N>(SE, SO, a, y);
+        TC y[N];
+        eo_fwd<N>(SE, SO, r, y);
 #pragma unroll
         for (int c = 0; c < N; ++c) slab[L::at(pa, pb, c)] = y[c];
     }
     wave_sync();
     eo_inverse_mid<N>(pc, slab, SE, SO, lam, sx, sy, sz);
     if (pc.act) {
-        TC y[N], a[N];
+        TC y[N];
 #pragma unroll
         for (int c = 0; c < N; ++c) y[c] = slab[L::at(pa, pb, c)];
-        eo_bwd<N>(SE, SO, y, a);
-#pragma unroll
-        for (int k = 0; k < N; ++k) slab[L::at(pa, pb, k)] = a[k];
+        eo_bwd<N>(SE, SO, y, r);
     }
+    wave_sync();
+}
+
+// slab <- D^{-1} slab entirely in LDS (each phase updates its own pencils).
+template <int N, typename TC>
+__device__ __forceinline__ void eo_inverse_lds(const Pencil<N>& pc, TC* slab, const TC* SE, const TC* SO,
+                                               const TC* lam, TC sx, TC sy, TC sz) {
+    using L = Slab<N>;
+    TC a[N];
+    if (pc.act)
+#pragma unroll
+        for (int k = 0; k < N; ++k) a[k] = slab[L::at(pc.pa, pc.pb, k)];
+    eo_inverse_regs<N, TC>(pc, a, slab, SE, SO, lam, sx, sy, sz);
+    if (pc.act)
+#pragma unroll
+        for (int k = 0; k < N; ++k) slab[L::at(pc.pa, pc.pb, k)] = a[k];
     wave_sync();
 }
 
@@ -611,6 +637,167 @@ __device__ __forceinline__ void solve_tile(const double* __restrict__ b, double*
     wave_sync();
 }
 
+// Sum and maximum over the wave by an xor butterfly: every lane ends with
+// the same value, bit for bit (each step adds or compares the same pair).
+__device__ __forceinline__ double wave_allsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_allmax(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// LDS workspace of the register-resident solve tile: two FP64 scratch
+// slabs for the product (the first also holds the inner solve's slab, in
+// the inner precision) and the per-block reductions.
+template <int N>
+struct SolveLdsR {
+    static constexpr int SZ = Slab<N>::BPW * Slab<N>::size;
+    double t1[SZ], t2[SZ];
+    double part[2][64];
+    double red[3][Slab<N>::BPW];
+    int done[Slab<N>::BPW];
+};
+
+// Block-local iterative refinement of one tile with the iterate, the
+// right-hand side and the residual in registers: each active lane owns the
+// z-pencil (pa, pb) of its block w of x and b (read once from memory, x
+// written once), the product A x goes through the two LDS slabs
+// (apply_regs(pc, xr, dst, t1, t2), ending in slab layout in t1) and the
+// inner inverse takes and returns the lane's pencil in registers
+// (inverse_regs(pc, d, slab) in precision TI).  Per correction:
+//   r = b - D x (FP64), s = ||r||_inf, d = D~^{-1} (r / s) in TI (input and
+//   output rounded to FP16 / BF16 for RND), x <- x + s d (FP64),
+// until ||r||_2 <= rtol ||b||_2 or maxit corrections.  Per-block norms are
+// reduced over the block's pencils through LDS.
+template <int N, typename TI, int RND, bool VP, typename ApplyF, typename InvF>
+__device__ __forceinline__ void solve_tile_reg(const double* __restrict__ b, double* __restrict__ x,
+                                               const GArgs& G, int64_t g0, int nvalid, SolveLdsR<N>& S,
+                                               ApplyF apply_regs, InvF inverse_regs, double rtol, int maxit,
+                                               int32_t* __restrict__ iters, double* __restrict__ relres,
+                                               int64_t block0, SolveAcc& acc) {
+    using L = Slab<N>;
+    const Pencil<N> pc(nvalid);
+    const int lane = threadIdx.x;
+    const int so = (pc.w < L::BPW ? pc.w : 0) * L::size;
+    double xr[N], br[N];
+    bool nz = false;
+    double bsq = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) xr[k] = br[k] = 0.0;
+    if (pc.act) {
+        pencil_load<N, VP>(xr, pencil_ptr<N>(static_cast<const double*>(x), G, g0 + pc.w, pc.pa, pc.pb), G.logB);
+        pencil_load<N, VP>(br, pencil_ptr<N>(b, G, g0 + pc.w, pc.pa, pc.pb), G.logB);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            nz = nz || xr[k] != 0.0;
+            bsq = fma(br[k], br[k], bsq);
+        }
+    }
+    // the residual of an all-zero x is b: the first product is skipped
+    // when every x of the tile is zero on entry
+    bool need_apply = __any(nz);
+    // per-block sums: over the whole wave when the tile is one block (n >= 6),
+    // else over the block's lanes through LDS
+    constexpr bool kOne = L::BPW == 1;
+    double bn;
+    if constexpr (kOne) {
+        bn = wave_allsum(bsq);
+    } else {
+        S.part[0][lane] = bsq;
+        wave_sync();
+        if (pc.act && pc.pa == 0 && pc.pb == 0) {
+            double sacc = 0.0;
+            for (int l = 0; l < L::N2; ++l) sacc += S.part[0][lane + l];
+            S.red[0][pc.w] = sacc;
+            S.done[pc.w] = 0;
+        }
+        wave_sync();
+        bn = pc.act ? S.red[0][pc.w] : 0.0;
+    }
+    bool done_before = false;   // (one-block tiles) the block met its test in an earlier pass
+    int it = 0;
+    double rel = 0.0;
+    if (pc.act && bn == 0.0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) xr[k] = 0.0;
+    for (;;) {
+        double r[N];
+        if (need_apply) {
+            apply_regs(pc, xr, S.t1 + so, S.t1 + so, S.t2 + so);
+#pragma unroll
+            for (int k = 0; k < N; ++k) r[k] = pc.act ? br[k] - S.t1[so + L::at(pc.pa, pc.pb, k)] : 0.0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < N; ++k) r[k] = br[k];
+        }
+        double rr = 0.0, rmax = 0.0;
+        if (pc.act)
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                rr = fma(r[k], r[k], rr);
+                rmax = fmax(rmax, fabs(r[k]));
+            }
+        double rsq_b, rmax_b;
+        bool mine_done = true;
+        if constexpr (kOne) {
+            rsq_b = wave_allsum(rr);
+            rmax_b = wave_allmax(rmax);
+            if (!done_before) {
+                rel = bn == 0.0 ? 0.0 : sqrt(rsq_b / bn);
+                mine_done = !(rel > rtol) || it >= maxit;
+            }
+            done_before = mine_done;
+            if (mine_done) break;   // wave-uniform: the tile is one block
+        } else {
+            S.part[0][lane] = rr;
+            S.part[1][lane] = rmax;
+            wave_sync();
+            if (pc.act && pc.pa == 0 && pc.pb == 0) {
+                double s2 = 0.0, m = 0.0;
+                for (int l = 0; l < L::N2; ++l) {
+                    s2 += S.part[0][lane + l];
+                    m = fmax(m, S.part[1][lane + l]);
+                }
+                S.red[1][pc.w] = s2;
+                S.red[2][pc.w] = m;
+            }
+            wave_sync();
+            if (pc.act && !S.done[pc.w]) {
+                rel = bn == 0.0 ? 0.0 : sqrt(S.red[1][pc.w] / bn);
+                mine_done = !(rel > rtol) || it >= maxit;
+            }
+            wave_sync();
+            if (pc.act && pc.pa == 0 && pc.pb == 0 && mine_done) S.done[pc.w] = 1;
+            if (!__any(pc.act && !mine_done)) break;
+            rmax_b = pc.act ? S.red[2][pc.w] : 0.0;
+        }
+        (void)rsq_b;
+        const double inv_s = (pc.act && !mine_done && rmax_b > 0.0) ? 1.0 / rmax_b : 0.0;
+        TI d[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) d[k] = round_to<RND>(static_cast<TI>(r[k] * inv_s));
+        inverse_regs(pc, d, reinterpret_cast<TI*>(S.t1) + so);
+        if (pc.act && !mine_done) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) xr[k] = fma(rmax_b, static_cast<double>(round_to<RND>(d[k])), xr[k]);
+            ++it;
+        }
+        need_apply = true;
+    }
+    if (pc.act) pencil_store<N, VP>(const_cast<double*>(pencil_ptr<N>(x, G, g0 + pc.w, pc.pa, pc.pb)), xr, G.logB);
+    if (pc.act && pc.pa == 0 && pc.pb == 0) {
+        const int64_t gidx = block0 + g0 + pc.w;
+        if (iters) iters[gidx] = it;
+        if (relres) relres[gidx] = rel;
+        acc.add(it, rel, rtol);
+    }
+    wave_sync();
+}
+
 // Factor tables of a tile kernel, in registers.  FP64 tables go through LDS
 // so that they land in VGPRs; FP32 tables use wave-uniform loads (SGPRs).
 template <int N, typename TC>
@@ -631,23 +818,30 @@ struct InvTab {
 };
 
 // The solve tile with the even-odd reference operators: per-block scalings
-// from the edge lengths, factor tables in registers.
-template <int N, typename TI, int RND>
+// from the edge lengths, iterate and residual in registers
+// (solve_tile_reg).  tA: the apply table ME|MO|PE|PO (FP64), tS: the inverse
+// table SE|SO (TI), lam: the eigenvalues (TI); each may point to registers
+// or to LDS.
+template <int N, typename TI, int RND, bool VP>
 __device__ __forceinline__ void eo_solve_tile(const double* __restrict__ b, double* __restrict__ x, const GArgs& G,
-                                              int64_t g0, int nvalid, SolveLds<N, TI>& S,
-                                              const ApplyTab<N, double>& A, const InvTab<N, TI>& I, const TI* lam,
-                                              double rtol, int maxit, int32_t* __restrict__ iters,
-                                              double* __restrict__ relres, int64_t block0, SolveAcc& acc) {
+                                              int64_t g0, int nvalid, SolveLdsR<N>& S, const double* tA,
+                                              const TI* tS, const TI* lam, double rtol, int maxit,
+                                              int32_t* __restrict__ iters, double* __restrict__ relres,
+                                              int64_t block0, SolveAcc& acc) {
+    using E = EOShape<N>;
     const Pencil<N> pc(nvalid);
     double sx = 1.0, sy = 1.0, sz = 1.0;
     if (pc.act) block_scales(G.h, g0 + pc.w, sx, sy, sz);
     const TI sxi = static_cast<TI>(sx), syi = static_cast<TI>(sy), szi = static_cast<TI>(sz);
-    solve_tile<N, TI, RND>(
+    solve_tile_reg<N, TI, RND, VP>(
         b, x, G, g0, nvalid, S,
-        [&](const Pencil<N>& p, const double* src, double* dst, double* t1, double* t2) {
-            eo_apply_lds<N, double>(p, src, dst, t1, t2, A.ME(), A.MO(), A.PE(), A.PO(), sx, sy, sz);
+        [&](const Pencil<N>& p, const double (&xr)[N], double* dst, double* t1, double* t2) {
+            eo_apply_regs<N, double>(p, xr, dst, t1, t2, tA, tA + E::SE, tA + E::SE + E::SO, tA + 2 * E::SE + E::SO,
+                                     sx, sy, sz);
         },
-        [&](const Pencil<N>& p, TI* slab) { eo_inverse_lds<N, TI>(p, slab, I.SE(), I.SO(), lam, sxi, syi, szi); },
+        [&](const Pencil<N>& p, TI (&d)[N], TI* slab) {
+            eo_inverse_regs<N, TI>(p, d, slab, tS, tS + E::SE, lam, sxi, syi, szi);
+        },
         rtol, maxit, iters, relres, block0, acc);
 }
 

@@ -123,27 +123,38 @@ __global__ __launch_bounds__(64, 2) void k_inverse_eo(const TS* __restrict__ r, 
     }
 }
 
+// Minimum resident waves per SIMD the solve kernel is compiled for.  FP64
+// inner inverse: n <= 6 fits 128 VGPRs (four waves); at n = 7 that spills,
+// and at n = 8 three waves with more registers measured faster (125 vs
+// 144 us on 32768 blocks) than four.  The FP32 inner one measured faster at
+// 165 VGPRs (n = 8) than squeezed into 128.
+template <int N, typename TI>
+constexpr int solve_min_waves() {
+    return sizeof(TI) == 8 ? (N >= 7 ? 3 : 4) : 2;
+}
+
 // Block-local iterative refinement over all tiles of a group (persistent grid).
-template <int N, typename TI, int RND>
-__global__ __launch_bounds__(64, 2) void k_solve_eo(const double* __restrict__ b, double* __restrict__ x, GArgs G,
+template <int N, typename TI, int RND, bool VP>
+__global__ __launch_bounds__(64, (solve_min_waves<N, TI>())) void k_solve_eo(const double* __restrict__ b, double* __restrict__ x, GArgs G,
                                                     const double* __restrict__ tabA, const TI* __restrict__ tabS,
                                                     int64_t ntiles, double rtol, int maxit,
                                                     int32_t* __restrict__ iters, double* __restrict__ relres,
                                                     int64_t block0, SolvePartial* parts) {
     using L = Slab<N>;
     using S = EOShape<N>;
-    __shared__ SolveLds<N, TI> lds;
-    __shared__ double stabA[ApplyTab<N, double>::COUNT];
+    __shared__ SolveLdsR<N> lds;
     __shared__ TI stabS[S::SE + S::SO + N];
-    ApplyTab<N, double> A;
-    InvTab<N, TI> I;
-    table_to_regs(A.v, tabA, stabA, ApplyTab<N, double>::COUNT);
-    table_to_regs<TI, InvTab<N, TI>::COUNT, false>(I.v, tabS, stabS, S::SE + S::SO + N);
+    // the 1D tables are read where they are used at wave-uniform addresses
+    // (scalar loads into SGPRs); in VGPRs the FP64 ones would take 192
+    // registers at n = 8 and halve the resident waves, from LDS every
+    // contraction would wait on LDS.  Only the eigenvalues, indexed per
+    // lane, go through LDS.
+    stage_table<TI, S::SE + S::SO + N>(tabS, stabS);
     const TI* lam = stabS + S::SE + S::SO;
     SolveAcc acc;
     for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x)
-        eo_solve_tile<N, TI, RND>(b, x, G, t * L::BPW, nvalid_of<N>(G, t), lds, A, I, lam, rtol, maxit, iters, relres,
-                                  block0, acc);
+        eo_solve_tile<N, TI, RND, VP>(b, x, G, t * L::BPW, nvalid_of<N>(G, t), lds, tabA, tabS, lam, rtol, maxit,
+                                      iters, relres, block0, acc);
     acc.flush(parts + blockIdx.x);
 }
 
@@ -231,33 +242,43 @@ tp_status inverse_eo_n(const Plan& plan, const GroupInfo& g, const void* r, void
 
 template <int N, typename TI, int RND>
 tp_status solve_eo_n(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol, int maxit,
-                     int32_t* iters, double* relres, int64_t part_base, int64_t* nparts, hipStream_t s) {
+                     int32_t* iters, double* relres, const SolveWork& w, int64_t part_base, int64_t* nparts,
+                     hipStream_t s) {
     const int64_t ntiles = eo_tiles<N>(g);
     const double* tabA = reinterpret_cast<const double*>(eo_table(plan, N, EO_APPLY_A, 0));
     const TI* tabS = reinterpret_cast<const TI*>(eo_table(plan, N, EO_INV, sizeof(TI) == 8 ? 0 : 1));
     GArgs a{g.h, g.nblocks, g.offset, g.logB};
-    static int64_t gc = 0;
-    if (gc == 0) gc = persistent_grid(plan, reinterpret_cast<const void*>(&k_solve_eo<N, TI, RND>), INT64_MAX);
+    const bool vp = vector_pencils<N, double>(g, b, x);
+    const void* kern = vp ? reinterpret_cast<const void*>(&k_solve_eo<N, TI, RND, true>)
+                          : reinterpret_cast<const void*>(&k_solve_eo<N, TI, RND, false>);
+    static int64_t grid_cache[2] = {0, 0};
+    int64_t& gc = grid_cache[vp ? 1 : 0];
+    if (gc == 0) gc = persistent_grid(plan, kern, INT64_MAX);
     const int64_t grid = std::min(gc, ntiles);
-    if (part_base + grid > plan.partials_cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
+    if (part_base + grid > w.cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
     *nparts = grid;
-    hipLaunchKernelGGL((k_solve_eo<N, TI, RND>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x, a, tabA, tabS,
-                       ntiles, rtol, maxit, iters, relres, g.block0,
-                       static_cast<SolvePartial*>(plan.partials_dev) + part_base);
+    SolvePartial* parts = w.parts + part_base;
+    if (vp)
+        hipLaunchKernelGGL((k_solve_eo<N, TI, RND, true>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x, a,
+                           tabA, tabS, ntiles, rtol, maxit, iters, relres, g.block0, parts);
+    else
+        hipLaunchKernelGGL((k_solve_eo<N, TI, RND, false>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x,
+                           a, tabA, tabS, ntiles, rtol, maxit, iters, relres, g.block0, parts);
     return check("solve launch");
 }
 
 template <typename TI, int RND>
 tp_status solve_eo_dispatch(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol,
-                            int maxit, int32_t* iters, double* relres, int64_t pb, int64_t* np, hipStream_t s) {
+                            int maxit, int32_t* iters, double* relres, const SolveWork& w, int64_t pb, int64_t* np,
+                            hipStream_t s) {
     switch (g.n) {
-        case 2: return solve_eo_n<2, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 3: return solve_eo_n<3, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 4: return solve_eo_n<4, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 5: return solve_eo_n<5, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 6: return solve_eo_n<6, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 7: return solve_eo_n<7, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 8: return solve_eo_n<8, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 2: return solve_eo_n<2, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 3: return solve_eo_n<3, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 4: return solve_eo_n<4, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 5: return solve_eo_n<5, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 6: return solve_eo_n<6, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 7: return solve_eo_n<7, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 8: return solve_eo_n<8, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
 }
@@ -305,19 +326,20 @@ tp_status launch_apply_eo(const Plan& plan, const GroupInfo& g, int op, const vo
 }
 
 tp_status launch_solve(const Plan& plan, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
-                       double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base, int64_t* nparts,
+                       double rtol, int maxit, int32_t* iters, double* relres, const SolveWork& w, int64_t part_base,
+                       int64_t* nparts,
                        hipStream_t s) {
     *nparts = 0;
     if (g.nblocks == 0) return TP_OK;
     switch (inner) {
         case TP_F64:
-            return solve_eo_dispatch<double, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_eo_dispatch<double, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         case TP_F32:
-            return solve_eo_dispatch<float, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_eo_dispatch<float, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         case TP_F16:
-            return solve_eo_dispatch<float, RND_F16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_eo_dispatch<float, RND_F16>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         case TP_BF16:
-            return solve_eo_dispatch<float, RND_BF16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_eo_dispatch<float, RND_BF16>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported inner precision");
 }

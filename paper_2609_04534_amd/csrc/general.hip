@@ -317,16 +317,17 @@ tp_status inverse_gen_n(const Plan& plan, const GroupInfo& g, const void* r, voi
 
 template <int N, typename TI, int RND>
 tp_status solve_gen_n(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol, int maxit,
-                      int32_t* iters, double* relres, int64_t part_base, int64_t* nparts, hipStream_t s) {
+                      int32_t* iters, double* relres, const SolveWork& w, int64_t part_base, int64_t* nparts,
+                       hipStream_t s) {
     const int64_t ntiles = (g.nblocks + Slab<N>::BPW - 1) / Slab<N>::BPW;
     const TI* eig = static_cast<const TI*>(sizeof(TI) == 8 ? static_cast<const void*>(g.eig)
                                                            : static_cast<const void*>(g.eig32));
     GArgs a{g.h, g.nblocks, g.offset, g.logB};
     const int64_t grid = std::min<int64_t>(gen_grid(plan, ntiles), static_cast<int64_t>(plan.cus) * kMaxWgPerCu);
-    if (part_base + grid > plan.partials_cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
+    if (part_base + grid > w.cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
     hipLaunchKernelGGL((k_solve_gen<N, TI, RND>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b, x, a, g.fac,
                        eig, ntiles, rtol, maxit, iters, relres, g.block0,
-                       static_cast<SolvePartial*>(plan.partials_dev) + part_base);
+                       w.parts + part_base);
     *nparts = grid;
     return check_gen("solve (block factors) launch");
 }
@@ -361,15 +362,16 @@ tp_status inverse_gen_dispatch(const Plan& plan, const GroupInfo& g, const void*
 
 template <typename TI, int RND>
 tp_status solve_gen_dispatch(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol, int maxit,
-                             int32_t* iters, double* relres, int64_t pb, int64_t* np, hipStream_t s) {
+                             int32_t* iters, double* relres, const SolveWork& w, int64_t pb, int64_t* np,
+                             hipStream_t s) {
     switch (g.n) {
-        case 2: return solve_gen_n<2, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 3: return solve_gen_n<3, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 4: return solve_gen_n<4, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 5: return solve_gen_n<5, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 6: return solve_gen_n<6, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 7: return solve_gen_n<7, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
-        case 8: return solve_gen_n<8, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, pb, np, s);
+        case 2: return solve_gen_n<2, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 3: return solve_gen_n<3, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 4: return solve_gen_n<4, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 5: return solve_gen_n<5, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 6: return solve_gen_n<6, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 7: return solve_gen_n<7, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
+        case 8: return solve_gen_n<8, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, pb, np, s);
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
 }
@@ -402,20 +404,20 @@ tp_status launch_inverse_gen(const Plan& plan, const GroupInfo& g, const void* r
 }
 
 tp_status launch_solve_gen(const Plan& plan, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
-                           double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base,
-                           int64_t* nparts, hipStream_t s) {
+                           double rtol, int maxit, int32_t* iters, double* relres, const SolveWork& w,
+                           int64_t part_base, int64_t* nparts, hipStream_t s) {
     *nparts = 0;
     if (g.nblocks == 0) return TP_OK;
     if (!g.eig || !g.fac) return set_error(TP_ERR_STATE, "group has no block factors");
     switch (inner) {
         case TP_F64:
-            return solve_gen_dispatch<double, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_gen_dispatch<double, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         case TP_F32:
-            return solve_gen_dispatch<float, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_gen_dispatch<float, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         case TP_F16:
-            return solve_gen_dispatch<float, RND_F16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_gen_dispatch<float, RND_F16>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         case TP_BF16:
-            return solve_gen_dispatch<float, RND_BF16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_gen_dispatch<float, RND_BF16>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported inner precision");
 }

@@ -99,13 +99,21 @@ struct GroupInfo {
 // Kernel families of a group's call (tp_plan_group_kernel reports these).
 enum { KIND_LANE = 0, KIND_WAVE = 1, KIND_MFMA = 2, KIND_GENERAL = 3 };
 
-// One work item of the persistent kernel: a tile of lane-mapped blocks or a
-// single wave-mapped block.
-struct WorkItem {
-    int32_t group;
-    int32_t count;        // blocks in this item
-    int64_t first;        // first block index within the group
+// Single-launch configuration of a persistent plan for one call (apply,
+// apply_inverse, solve) and dtype: per group the tile body (one block per
+// lane for n <= 4, or one wave per tile) and the tiles each workgroup runs,
+// the order of the groups' segments in the launch, and for the solve the
+// grid.  Defaults follow the plan's mapping; tp_plan_autotune replaces them
+// with measured choices.
+struct PersistCfg {
+    std::vector<int8_t> lane;     // per group: 1 = lane-per-block body
+    std::vector<int8_t> tpw;      // per group: consecutive tiles per workgroup (1, 2, 4, 8)
+    std::vector<int32_t> order;   // group index of each segment, in launch order
+    int8_t grid = 1;              // solve: 1 occupancy grid, 2 half of it, 0 one workgroup per item
+    int64_t items = 0;            // work items of the launch (set when uploaded)
+    bool tuned = false;
 };
+enum { PCALL_APPLY = 0, PCALL_INVERSE = 1, PCALL_SOLVE = 2 };
 
 struct Plan {
     int device = 0;
@@ -126,12 +134,11 @@ struct Plan {
     // MFMA operand tables for n = 8 FP16 / BF16: apply [K or A][f16 or bf16], inverse [f16 or bf16]
     void* mfma_apply_dev[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void* mfma_inv_dev[2] = {nullptr, nullptr};
-    void* segs_dev = nullptr;      // persistent-kernel segment table (one per group)
+    void* segs_dev = nullptr;      // persistent-kernel segment tables: one per (call, dtype), ngroups each
+    PersistCfg pcfg[3][4];         // their configurations [PCALL_*][tp_dtype]
     void* eo_dev = nullptr;        // even-odd tables, (kMaxN+1) x EO_NTAB x 2 slots
     int64_t wave_grid = 2048;      // persistent grid of the wave kernels
     int cus = 256;                 // compute units of the plan's device
-    WorkItem* items_dev = nullptr;
-    int64_t nitems = 0;
     // uniform box mesh of tp_plan_create_mesh (one group, cells in mesh order)
     int basis = 0;                 // tp_basis of every block's coefficients
     bool patches = false;          // blocks are vertex patches (reference tables of two cells)
@@ -160,6 +167,19 @@ struct SolveSummary {
     unsigned long long max_relres_bits;
 };
 
+// Where a solve launch writes its per-workgroup partial summaries (at most
+// cap of them) and where the reduction puts the summary (the plan's own
+// workspace, plan_work).
+struct SolveWork {
+    SolvePartial* parts;
+    int64_t cap;
+    SolveSummary* summary;
+};
+inline SolveWork plan_work(const Plan& p) {
+    return SolveWork{static_cast<SolvePartial*>(p.partials_dev), p.partials_cap,
+                     static_cast<SolveSummary*>(p.summary_dev)};
+}
+
 // thread-local last error
 tp_status set_error(tp_status st, const std::string& msg);
 tp_status hip_error(int err, const char* what);
@@ -174,19 +194,19 @@ tp_status launch_inverse(const Plan& plan, const GroupInfo& g, const void* r, vo
 // partials + part_base and report the number written in *nparts.
 tp_status launch_solve(const Plan& plan, const GroupInfo& g, const double* b, double* x,
                        tp_dtype inner, double rtol, int maxit, int32_t* iters,
-                       double* relres, int64_t part_base, int64_t* nparts, hipStream_t s);
+                       double* relres, const SolveWork& w, int64_t part_base, int64_t* nparts, hipStream_t s);
 // Lane-per-block solve (n <= 4); same contract as launch_solve.
 tp_status launch_solve_lane(const Plan& plan, const GroupInfo& g, const double* b, double* x,
                             tp_dtype inner, double rtol, int maxit, int32_t* iters,
-                            double* relres, int64_t part_base, int64_t* nparts, hipStream_t s);
+                            double* relres, const SolveWork& w, int64_t part_base, int64_t* nparts, hipStream_t s);
 // GENERAL mode: per-block factors and eigen-decompositions (general.hip).
 tp_status launch_apply_gen(const Plan& plan, const GroupInfo& g, const void* u, void* v, tp_dtype dt,
                            hipStream_t s);
 tp_status launch_inverse_gen(const Plan& plan, const GroupInfo& g, const void* r, void* x, tp_dtype dt,
                              hipStream_t s);
 tp_status launch_solve_gen(const Plan& plan, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
-                           double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base,
-                           int64_t* nparts, hipStream_t s);
+                           double rtol, int maxit, int32_t* iters, double* relres, const SolveWork& w,
+                           int64_t part_base, int64_t* nparts, hipStream_t s);
 // Fills n elements of dtype dt with pseudo-random values in [-1, 1]
 // (a counter hash of the element index and seed), or zero when zero is set.
 tp_status launch_fill(void* dst, int64_t n, tp_dtype dt, uint64_t seed, bool zero, hipStream_t s);
@@ -210,16 +230,32 @@ tp_status launch_inverse_mfma(const Plan& plan, const GroupInfo& g, const void* 
                               hipStream_t s);
 
 // Persistent single-launch paths over all groups of a plan.
+// persistent_setup allocates the segment tables and uploads the default
+// configuration of every call and dtype; persistent_upload rewrites the
+// table of one (call, dtype) from plan.pcfg (host-synchronous: no launch
+// that reads that table may be in flight).
 tp_status persistent_setup(Plan& plan);
+tp_status persistent_upload(Plan& plan, int call, int dt);
+// Whether group g may run the lane-per-block body in a single launch.
+bool persistent_lane_ok(const Plan& plan, const GroupInfo& g);
 tp_status launch_apply_persistent(const Plan& plan, int op, const void* u, void* v, tp_dtype dt, hipStream_t s);
 tp_status launch_inverse_persistent(const Plan& plan, const void* r, void* x, tp_dtype dt, hipStream_t s);
 tp_status launch_solve_persistent(const Plan& plan, const double* b, double* x, tp_dtype inner, double rtol,
-                                  int maxit, int32_t* iters, double* relres, int64_t* nparts, hipStream_t s);
+                                  int maxit, int32_t* iters, double* relres, const SolveWork& w, int64_t* nparts,
+                                  hipStream_t s);
 // Multigrid V-cycle of a mesh plan (mg.hip): u = V(b) on the finest level,
 // every kernel skipped once the PCG state st (nullable) is done; the dot
 // kernel writes per-tile partials of (a, b).
 tp_status mg_enqueue_vcycle(const tp_mg* m, const double* b, double* u, const void* st, bool f32, hipStream_t s);
-tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const double* b, double* part, const void* st,
+// With FP32 level storage the V-cycle's result stays on the device in the
+// hierarchy's finest FP32 vector (u may then be null): mg_result32 returns
+// it, mg_enqueue_widen copies it to an FP64 vector; null / TP_ERR_STATE for
+// FP64 storage.
+int mg_storage(const tp_mg* m);
+const float* mg_result32(const tp_mg* m);
+tp_status mg_enqueue_widen(const tp_mg* m, double* dst, hipStream_t s);
+// Partial (a, b) per 64-cell tile with b in FP64 or (b32) FP32.
+tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const void* b, bool b32, double* part, const void* st,
                          hipStream_t s);
 const tp_plan* mg_plan(const tp_mg* m);
 // Coupled SIPG operator of a mesh plan (sipg.hip): A u, or A^face u when face_only.
@@ -227,7 +263,7 @@ tp_status launch_sipg(const Plan& plan, const GroupInfo& g, bool face_only, cons
                       hipStream_t s);
 tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize,
                       bool to_blocked, hipStream_t s);
-tp_status launch_summary_reduce(const Plan& plan, int64_t nparts, hipStream_t s);
+tp_status launch_summary_reduce(const SolveWork& w, int64_t nparts, hipStream_t s);
 
 }  // namespace tpfdm
 

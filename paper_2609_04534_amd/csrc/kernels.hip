@@ -256,7 +256,8 @@ tp_status inverse_dispatch(const GroupInfo& g, const RefData& ref, const void* r
 
 template <int N, typename TI, int RND>
 tp_status solve_lane_n(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol, int maxit,
-                       int32_t* iters, double* relres, int64_t part_base, int64_t* nparts, hipStream_t s) {
+                       int32_t* iters, double* relres, const SolveWork& w, int64_t part_base, int64_t* nparts,
+                       hipStream_t s) {
     const RefData& ref = plan.ref[N];
     const auto PA = make_pair<N, double>(ref.M, ref.A);
     const auto E = make_eig<N, TI>(ref);
@@ -269,8 +270,8 @@ tp_status solve_lane_n(const Plan& plan, const GroupInfo& g, const double* b, do
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64, 0) != hipSuccess || occ <= 0) occ = 1;
     occ = std::min(occ, kMaxWgPerCu);
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(ntiles, static_cast<int64_t>(plan.cus) * occ));
-    if (part_base + grid > plan.partials_cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
-    SolvePartial* parts = static_cast<SolvePartial*>(plan.partials_dev) + part_base;
+    if (part_base + grid > w.cap) return set_error(TP_ERR_UNSUPPORTED, "too many solve workgroups");
+    SolvePartial* parts = w.parts + part_base;
     const int64_t block0 = g.block0;
     if (g.logB == 6)
         hipLaunchKernelGGL((k_solve_lane<N, TI, RND, true, 6>), dim3(static_cast<unsigned>(grid)), dim3(64), 0, s, b,
@@ -287,11 +288,12 @@ tp_status solve_lane_n(const Plan& plan, const GroupInfo& g, const double* b, do
 
 template <typename TI, int RND>
 tp_status solve_lane_dispatch(const Plan& plan, const GroupInfo& g, const double* b, double* x, double rtol, int maxit,
-                              int32_t* iters, double* relres, int64_t part_base, int64_t* nparts, hipStream_t s) {
+                              int32_t* iters, double* relres, const SolveWork& w, int64_t part_base, int64_t* nparts,
+                       hipStream_t s) {
     switch (g.n) {
-        case 2: return solve_lane_n<2, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
-        case 3: return solve_lane_n<3, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
-        case 4: return solve_lane_n<4, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+        case 2: return solve_lane_n<2, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
+        case 3: return solve_lane_n<3, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
+        case 4: return solve_lane_n<4, TI, RND>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         default: break;
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported n");
@@ -325,19 +327,19 @@ tp_status launch_inverse(const Plan& plan, const GroupInfo& g, const void* r, vo
 }
 
 tp_status launch_solve_lane(const Plan& plan, const GroupInfo& g, const double* b, double* x, tp_dtype inner,
-                            double rtol, int maxit, int32_t* iters, double* relres, int64_t part_base,
-                            int64_t* nparts, hipStream_t s) {
+                            double rtol, int maxit, int32_t* iters, double* relres, const SolveWork& w,
+                            int64_t part_base, int64_t* nparts, hipStream_t s) {
     *nparts = 0;
     if (g.nblocks == 0) return TP_OK;
     switch (inner) {
         case TP_F64:
-            return solve_lane_dispatch<double, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_lane_dispatch<double, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         case TP_F32:
-            return solve_lane_dispatch<float, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_lane_dispatch<float, RND_NONE>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         case TP_F16:
-            return solve_lane_dispatch<float, RND_F16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_lane_dispatch<float, RND_F16>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
         case TP_BF16:
-            return solve_lane_dispatch<float, RND_BF16>(plan, g, b, x, rtol, maxit, iters, relres, part_base, nparts, s);
+            return solve_lane_dispatch<float, RND_BF16>(plan, g, b, x, rtol, maxit, iters, relres, w, part_base, nparts, s);
     }
     return set_error(TP_ERR_UNSUPPORTED, "unsupported inner precision");
 }
@@ -391,9 +393,9 @@ tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize,
     return check_launch("pack launch");
 }
 
-tp_status launch_summary_reduce(const Plan& plan, int64_t nparts, hipStream_t s) {
-    hipLaunchKernelGGL(k_summary_reduce, dim3(1), dim3(256), 0, s, static_cast<const SolvePartial*>(plan.partials_dev),
-                       nparts, static_cast<SolveSummary*>(plan.summary_dev));
+tp_status launch_summary_reduce(const SolveWork& w, int64_t nparts, hipStream_t s) {
+    hipLaunchKernelGGL(k_summary_reduce, dim3(1), dim3(256), 0, s, static_cast<const SolvePartial*>(w.parts), nparts,
+                       w.summary);
     return check_launch("solve summary reduction");
 }
 

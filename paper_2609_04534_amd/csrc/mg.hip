@@ -48,31 +48,35 @@ namespace {
 
 __device__ __forceinline__ bool done_flag(const PcgState* st) { return st && st->done; }
 
+// Level vectors are stored in TS (double, or float for the FP32-storage
+// hierarchy); every kernel computes in FP64 (the smoother's block inverse in
+// TI) and rounds only where it stores.
+
 // t = A u on one level (one cell per lane); the consumers form b - t as
 // they load, which keeps b out of this kernel's registers.
-template <int N, bool HERM>
-__global__ __launch_bounds__(64, 2) void k_mg_apply(const double* __restrict__ u, double* __restrict__ t, MeshArgs G,
+template <int N, bool HERM, typename TS>
+__global__ __launch_bounds__(64, 2) void k_mg_apply(const TS* __restrict__ u, TS* __restrict__ t, MeshArgs G,
                                                   Pair<N, double> R, FaceRef<N, double> F,
                                                   const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
     __shared__ double sa[N * N][64], sbt[N * N][64];
-    const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, double, HERM>(G))) * 64 + threadIdx.x;
+    const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, TS, HERM>(G))) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
     double acc[N3];
-    sipg_cell<N, double, double, -1, HERM>(u, G, R, F, c, acc, sa, sbt);
+    sipg_cell<N, TS, double, -1, HERM>(u, G, R, F, c, acc, sa, sbt);
     const int64_t base = G.offset + block_base(c, 6, N3);
 #pragma unroll
     for (int e = 0; e < N3; ++e) {
         const int64_t o = base + (static_cast<int64_t>(e) << 6);
-        t[o] = acc[e];
+        t[o] = static_cast<TS>(acc[e]);
     }
 }
 
 // u = omega D^{-1} b: the first Chebyshev update from u = 0 (no operator
 // application), the block inverse in precision TI.
-template <int N, typename TI>
-__global__ __launch_bounds__(64, 2) void k_mg_jacobi0(const double* __restrict__ b, double* __restrict__ u,
+template <int N, typename TI, typename TS>
+__global__ __launch_bounds__(64, 2) void k_mg_jacobi0(const TS* __restrict__ b, TS* __restrict__ u,
                                                     MeshArgs G, Eig<N, TI> E, double omega,
                                                     const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -85,7 +89,8 @@ __global__ __launch_bounds__(64, 2) void k_mg_jacobi0(const double* __restrict__
     for (int e = 0; e < N3; ++e) v[e] = static_cast<TI>(b[base + (static_cast<int64_t>(e) << 6)]);
     lane_fdm_inplace<N, TI>(v, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy), static_cast<TI>(G.sz));
 #pragma unroll
-    for (int e = 0; e < N3; ++e) u[base + (static_cast<int64_t>(e) << 6)] = omega * static_cast<double>(v[e]);
+    for (int e = 0; e < N3; ++e)
+        u[base + (static_cast<int64_t>(e) << 6)] = static_cast<TS>(omega * static_cast<double>(v[e]));
 }
 
 // One Chebyshev update in a single pass (the factorized form: no residual
@@ -93,27 +98,28 @@ __global__ __launch_bounds__(64, 2) void k_mg_jacobi0(const double* __restrict__
 // cell, A u_in from the cell and its six neighbours, the block inverse in
 // precision TI on the residual registers.  u_out must not alias u_in (other
 // lanes still read u_in).
-template <int N, typename TI, bool HERM>
-__global__ __launch_bounds__(64, 2) void k_mg_smooth(const double* __restrict__ b, const double* __restrict__ uin,
-                                                   double* __restrict__ uout, MeshArgs G, Pair<N, double> R,
+template <int N, typename TI, bool HERM, typename TS>
+__global__ __launch_bounds__(64, 2) void k_mg_smooth(const TS* __restrict__ b, const TS* __restrict__ uin,
+                                                   TS* __restrict__ uout, MeshArgs G, Pair<N, double> R,
                                                    FaceRef<N, double> F, Eig<N, TI> E, double omega,
                                                    const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
     __shared__ double sa[N * N][64], sbt[N * N][64];
-    const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, double, HERM>(G))) * 64 + threadIdx.x;
+    const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, TS, HERM>(G))) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
     double acc[N3];
-    sipg_cell<N, double, double, -1, HERM>(uin, G, R, F, c, acc, sa, sbt);
+    sipg_cell<N, TS, double, -1, HERM>(uin, G, R, F, c, acc, sa, sbt);
     const int64_t base = G.offset + block_base(c, 6, N3);
     TI v[N3];
 #pragma unroll
-    for (int e = 0; e < N3; ++e) v[e] = static_cast<TI>(b[base + (static_cast<int64_t>(e) << 6)] - acc[e]);
+    for (int e = 0; e < N3; ++e)
+        v[e] = static_cast<TI>(static_cast<double>(b[base + (static_cast<int64_t>(e) << 6)]) - acc[e]);
     lane_fdm_inplace<N, TI>(v, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy), static_cast<TI>(G.sz));
 #pragma unroll
     for (int e = 0; e < N3; ++e) {
         const int64_t o = base + (static_cast<int64_t>(e) << 6);
-        uout[o] = fma(omega, static_cast<double>(v[e]), uin[o]);
+        uout[o] = static_cast<TS>(fma(omega, static_cast<double>(v[e]), static_cast<double>(uin[o])));
     }
 }
 
@@ -152,9 +158,9 @@ __device__ __forceinline__ void kron3_accumulate(LoadF load, const double* X, co
 
 // b_coarse = P^T (b_fine - t_fine), t_fine = A u_fine: one coarse cell per
 // lane, summed over its children.
-template <int N>
-__global__ __launch_bounds__(64, 2) void k_mg_restrict(const double* __restrict__ bf, const double* __restrict__ tf,
-                                                     double* __restrict__ bc,
+template <int N, typename TS>
+__global__ __launch_bounds__(64, 2) void k_mg_restrict(const TS* __restrict__ bf, const TS* __restrict__ tf,
+                                                     TS* __restrict__ bc,
                                                      MeshArgs Gf, MeshArgs Gc, ProlTab<N> PT,
                                                      const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -177,20 +183,20 @@ __global__ __launch_bounds__(64, 2) void k_mg_restrict(const double* __restrict_
         kron3_accumulate<N>(
             [&](int q) {
                 const int64_t o = fb + (static_cast<int64_t>(q) << 6);
-                return bf[o] - tf[o];
+                return static_cast<double>(bf[o]) - static_cast<double>(tf[o]);
             },
             PT.p[bx], PT.p[by], PT.p[bz], acc);
     }
     const int64_t base = Gc.offset + block_base(c, 6, N3);
 #pragma unroll
-    for (int e = 0; e < N3; ++e) bc[base + (static_cast<int64_t>(e) << 6)] = acc[e];
+    for (int e = 0; e < N3; ++e) bc[base + (static_cast<int64_t>(e) << 6)] = static_cast<TS>(acc[e]);
 }
 
 // u_out = u_fine + P u_coarse: one fine cell per lane, the child's embedding
 // selected per lane.
-template <int N>
-__global__ __launch_bounds__(64, 2) void k_mg_prolong(const double* __restrict__ uc, const double* __restrict__ uf,
-                                                    double* __restrict__ uout,
+template <int N, typename TS>
+__global__ __launch_bounds__(64, 2) void k_mg_prolong(const TS* __restrict__ uc, const TS* __restrict__ uf,
+                                                    TS* __restrict__ uout,
                                                     MeshArgs Gf, MeshArgs Gc, ProlTab<N> P,
                                                     const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -210,41 +216,41 @@ __global__ __launch_bounds__(64, 2) void k_mg_prolong(const double* __restrict__
         Y[e] = (fy & 1) ? P.p[1][e] : P.p[0][e];
         Z[e] = (fz & 1) ? P.p[1][e] : P.p[0][e];
     }
-    const double* w = uc + Gc.offset + block_base(c, 6, N3);
+    const TS* w = uc + Gc.offset + block_base(c, 6, N3);
     double acc[N3];
 #pragma unroll
     for (int e = 0; e < N3; ++e) acc[e] = 0.0;
-    kron3_accumulate<N>([&](int q) { return w[static_cast<int64_t>(q) << 6]; }, X, Y, Z, acc);
+    kron3_accumulate<N>([&](int q) { return static_cast<double>(w[static_cast<int64_t>(q) << 6]); }, X, Y, Z, acc);
     const int64_t base = Gf.offset + block_base(f, 6, N3);
 #pragma unroll
     for (int e = 0; e < N3; ++e) {
         const int64_t o = base + (static_cast<int64_t>(e) << 6);
-        uout[o] = uf[o] + acc[e];
+        uout[o] = static_cast<TS>(static_cast<double>(uf[o]) + acc[e]);
     }
 }
 
 // u = A0^{-1} b on the coarsest level: b gathered into LDS in canonical
 // order, one row of the (column-major) inverse per thread.
-template <int N>
-__global__ __launch_bounds__(256) void k_mg_coarse(const double* __restrict__ inv, const double* __restrict__ b,
-                                                   double* __restrict__ u, int64_t n0, int64_t offset,
+template <int N, typename TS>
+__global__ __launch_bounds__(256) void k_mg_coarse(const double* __restrict__ inv, const TS* __restrict__ b,
+                                                   TS* __restrict__ u, int64_t n0, int64_t offset,
                                                    const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
     __shared__ double sb[kMaxCoarse];
     for (int64_t e = threadIdx.x; e < n0; e += 256)
-        sb[e] = b[offset + block_base(e / N3, 6, N3) + ((e % N3) << 6)];
+        sb[e] = static_cast<double>(b[offset + block_base(e / N3, 6, N3) + ((e % N3) << 6)]);
     __syncthreads();
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (i >= n0) return;
     double s = 0.0;
     for (int64_t j = 0; j < n0; ++j) s = fma(inv[j * n0 + i], sb[j], s);
-    u[offset + block_base(i / N3, 6, N3) + ((i % N3) << 6)] = s;
+    u[offset + block_base(i / N3, 6, N3) + ((i % N3) << 6)] = static_cast<TS>(s);
 }
 
 // Partial (a, b) per 64-cell tile (the layout of the PCG partials).
-template <int N>
-__global__ __launch_bounds__(64) void k_mg_dot(const double* __restrict__ a, const double* __restrict__ b,
+template <int N, typename TS>
+__global__ __launch_bounds__(64) void k_mg_dot(const double* __restrict__ a, const TS* __restrict__ b,
                                                MeshArgs G, double* __restrict__ part,
                                                const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -256,11 +262,22 @@ __global__ __launch_bounds__(64) void k_mg_dot(const double* __restrict__ a, con
 #pragma unroll
         for (int e = 0; e < N3; ++e) {
             const int64_t o = base + (static_cast<int64_t>(e) << 6);
-            s = fma(a[o], b[o], s);
+            s = fma(a[o], static_cast<double>(b[o]), s);
         }
     }
     s = wave_sum(s);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// dst = src converted element by element (the finest level's right-hand
+// side into the FP32-storage hierarchy, its result back to FP64).
+template <typename TD, typename TSRC>
+__global__ __launch_bounds__(256) void k_mg_convert(const TSRC* __restrict__ src, TD* __restrict__ dst, int64_t n,
+                                                    const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * 256)
+        dst[i] = static_cast<TD>(src[i]);
 }
 
 tp_status check_launch(const char* what) {
@@ -330,14 +347,15 @@ using namespace tpfdm;
 struct MgLevel {
     MeshArgs G;
     int64_t elems = 0;
-    double* t = nullptr;   // residual scratch
-    double* b = nullptr;   // right-hand side (levels below the finest)
-    double* u = nullptr;   // correction (levels below the finest)
+    void* t = nullptr;     // residual scratch
+    void* b = nullptr;     // right-hand side (levels below the finest; every level with FP32 storage)
+    void* u = nullptr;     // correction (levels below the finest; every level with FP32 storage)
 };
 
 struct tp_mg {
     tp_plan* plan = nullptr;
     int n = 0;
+    int storage = TP_F64;           // element type of the level vectors (TP_F64 or TP_F32)
     std::vector<MgLevel> lv;
     double omega[3] = {0.0, 0.0, 0.0};
     double* coarse_inv = nullptr;   // shared, not owned
@@ -346,14 +364,16 @@ struct tp_mg {
 
 namespace {
 
-template <int N, typename TI, bool HERM>
-tp_status vcycle_level(const tp_mg* m, size_t l, const double* b, double* u, const PcgState* st, hipStream_t s) {
+template <int N, typename TI, bool HERM, typename TS>
+tp_status vcycle_level(const tp_mg* m, size_t l, const TS* b, TS* u, const PcgState* st, hipStream_t s) {
     const Plan& plan = *m->plan;
     const MgLevel& L = m->lv[l];
+    TS* Lt = static_cast<TS*>(L.t);
     const unsigned grid = static_cast<unsigned>((L.G.ncells + 63) / 64);
     if (l + 1 == m->lv.size()) {
         const unsigned cg = static_cast<unsigned>((m->n0 + 255) / 256);
-        hipLaunchKernelGGL((k_mg_coarse<N>), dim3(cg), dim3(256), 0, s, m->coarse_inv, b, u, m->n0, L.G.offset, st);
+        hipLaunchKernelGGL((k_mg_coarse<N, TS>), dim3(cg), dim3(256), 0, s, m->coarse_inv, b, u, m->n0, L.G.offset,
+                           st);
         return check_launch("coarse solve");
     }
     Pair<N, double> R;
@@ -369,36 +389,38 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const double* b, double* u, con
             for (int j = 0; j < N; ++j) PT.p[c][i * N + j] = P.p[c][j * N + i];
     // Chebyshev updates ping-pong between u and the level's scratch t; the
     // prolongation writes out of place so that the last update lands in u.
-    auto step = [&](const double* from, double* to, int j) {
-        hipLaunchKernelGGL((k_mg_smooth<N, TI, HERM>), dim3(grid), dim3(64), 0, s, b, from, to, L.G, R, F, E,
+    auto step = [&](const TS* from, TS* to, int j) {
+        hipLaunchKernelGGL((k_mg_smooth<N, TI, HERM, TS>), dim3(grid), dim3(64), 0, s, b, from, to, L.G, R, F, E,
                            m->omega[j], st);
     };
-    hipLaunchKernelGGL((k_mg_jacobi0<N, TI>), dim3(grid), dim3(64), 0, s, b, u, L.G, E, m->omega[0], st);
-    step(u, L.t, 1);
-    step(L.t, u, 2);
+    hipLaunchKernelGGL((k_mg_jacobi0<N, TI, TS>), dim3(grid), dim3(64), 0, s, b, u, L.G, E, m->omega[0], st);
+    step(u, Lt, 1);
+    step(Lt, u, 2);
     const MgLevel& C = m->lv[l + 1];
-    hipLaunchKernelGGL((k_mg_apply<N, HERM>), dim3(grid), dim3(64), 0, s, u, L.t, L.G, R, F, st);
-    hipLaunchKernelGGL((k_mg_restrict<N>), dim3(static_cast<unsigned>((C.G.ncells + 63) / 64)), dim3(64), 0, s, b,
-                       L.t, C.b, L.G, C.G, PT, st);
+    TS* Cb = static_cast<TS*>(C.b);
+    TS* Cu = static_cast<TS*>(C.u);
+    hipLaunchKernelGGL((k_mg_apply<N, HERM, TS>), dim3(grid), dim3(64), 0, s, u, Lt, L.G, R, F, st);
+    hipLaunchKernelGGL((k_mg_restrict<N, TS>), dim3(static_cast<unsigned>((C.G.ncells + 63) / 64)), dim3(64), 0, s, b,
+                       Lt, Cb, L.G, C.G, PT, st);
     tp_status stt = check_launch("level transfer");
     if (stt != TP_OK) return stt;
-    stt = vcycle_level<N, TI, HERM>(m, l + 1, C.b, C.u, st, s);
+    stt = vcycle_level<N, TI, HERM, TS>(m, l + 1, Cb, Cu, st, s);
     if (stt != TP_OK) return stt;
-    hipLaunchKernelGGL((k_mg_prolong<N>), dim3(grid), dim3(64), 0, s, C.u, u, L.t, L.G, C.G, P, st);
-    step(L.t, u, 0);
-    step(u, L.t, 1);
-    step(L.t, u, 2);
+    hipLaunchKernelGGL((k_mg_prolong<N, TS>), dim3(grid), dim3(64), 0, s, Cu, u, Lt, L.G, C.G, P, st);
+    step(Lt, u, 0);
+    step(u, Lt, 1);
+    step(Lt, u, 2);
     return check_launch("smoothing");
 }
 
-template <typename TI>
-tp_status vcycle_dispatch(const tp_mg* m, const double* b, double* u, const PcgState* st, hipStream_t s) {
+template <typename TI, typename TS>
+tp_status vcycle_dispatch(const tp_mg* m, const TS* b, TS* u, const PcgState* st, hipStream_t s) {
     switch (m->n) {
-        case 2: return vcycle_level<2, TI, false>(m, 0, b, u, st, s);
-        case 3: return vcycle_level<3, TI, false>(m, 0, b, u, st, s);
+        case 2: return vcycle_level<2, TI, false, TS>(m, 0, b, u, st, s);
+        case 3: return vcycle_level<3, TI, false, TS>(m, 0, b, u, st, s);
         case 4:
-            return m->plan->basis == TP_BASIS_HERMITE ? vcycle_level<4, TI, true>(m, 0, b, u, st, s)
-                                                      : vcycle_level<4, TI, false>(m, 0, b, u, st, s);
+            return m->plan->basis == TP_BASIS_HERMITE ? vcycle_level<4, TI, true, TS>(m, 0, b, u, st, s)
+                                                      : vcycle_level<4, TI, false, TS>(m, 0, b, u, st, s);
         default: break;
     }
     return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
@@ -416,29 +438,54 @@ tp_status coarse_probe_n(const tp_mg* m, std::vector<double>& A) {
     A.assign(static_cast<size_t>(n0 * n0), 0.0);
     std::vector<double> col(static_cast<size_t>(L.elems));
     const unsigned grid = static_cast<unsigned>((L.G.ncells + 63) / 64);
-    // column j = A e_j, with L.u = e_j as the probe
-    for (int64_t j = 0; j < n0; ++j) {
-        tp_status st = launch_fill(L.u, L.elems, TP_F64, 0, true, nullptr);
-        if (st != TP_OK) return st;
+    // FP64 probe vectors of the coarsest level (freed on return)
+    double *pu = nullptr, *pt = nullptr;
+    const size_t vb = static_cast<size_t>(L.elems) * sizeof(double);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&pu), vb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pt), vb);
+    tp_status st = e == hipSuccess ? TP_OK : hip_error(e, "coarse probe vectors");
+    // column j = A e_j, with pu = e_j as the probe
+    for (int64_t j = 0; st == TP_OK && j < n0; ++j) {
+        st = launch_fill(pu, L.elems, TP_F64, 0, true, nullptr);
+        if (st != TP_OK) break;
         const double one = 1.0;
         const int64_t pos = L.G.offset + block_base(j / N3, 6, N3) + ((j % N3) << 6);
-        hipError_t e = hipMemcpy(L.u + pos, &one, sizeof(double), hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_error(e, "coarse probe");
-        hipLaunchKernelGGL((k_mg_apply<N, false>), dim3(grid), dim3(64), 0, nullptr, L.u, L.t, L.G, R, F,
+        e = hipMemcpy(pu + pos, &one, sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            st = hip_error(e, "coarse probe");
+            break;
+        }
+        hipLaunchKernelGGL((k_mg_apply<N, false, double>), dim3(grid), dim3(64), 0, nullptr, pu, pt, L.G, R, F,
                            static_cast<const PcgState*>(nullptr));
-        e = hipMemcpy(col.data(), L.t, static_cast<size_t>(L.elems) * sizeof(double), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_error(e, "coarse probe");
+        e = hipMemcpy(col.data(), pt, vb, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            st = hip_error(e, "coarse probe");
+            break;
+        }
         for (int64_t i = 0; i < n0; ++i)
             A[i * n0 + j] = col[static_cast<size_t>(L.G.offset + block_base(i / N3, 6, N3) + ((i % N3) << 6))];
     }
-    return TP_OK;
+    if (pu) (void)hipFree(pu);
+    if (pt) (void)hipFree(pt);
+    return st;
 }
 
 void free_mg(tp_mg* m) {
     for (auto& L : m->lv)
-        for (double* p : {L.t, L.b, L.u})
+        for (void* p : {L.t, L.b, L.u})
             if (p) (void)hipFree(p);
     m->lv.clear();
+}
+
+tp_status convert_launch(const void* src, void* dst, bool to_f32, int64_t n, const PcgState* st, hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192));
+    if (to_f32)
+        hipLaunchKernelGGL((k_mg_convert<float, double>), dim3(grid), dim3(256), 0, s, static_cast<const double*>(src),
+                           static_cast<float*>(dst), n, st);
+    else
+        hipLaunchKernelGGL((k_mg_convert<double, float>), dim3(grid), dim3(256), 0, s, static_cast<const float*>(src),
+                           static_cast<double*>(dst), n, st);
+    return check_launch("multigrid conversion");
 }
 
 }  // namespace
@@ -449,21 +496,55 @@ tp_status mg_enqueue_vcycle(const tp_mg* m, const double* b, double* u, const vo
     if (m->plan->inverse_op != TP_OP_CELL || m->plan->factor_mode != TP_FACTOR_SCALED)
         return set_error(TP_ERR_STATE, "the plan's inverse setup is no longer TP_OP_CELL, TP_FACTOR_SCALED");
     const PcgState* ps = static_cast<const PcgState*>(st);
-    return f32 ? vcycle_dispatch<float>(m, b, u, ps, s) : vcycle_dispatch<double>(m, b, u, ps, s);
+    if (m->storage == TP_F32) {
+        // b into the hierarchy's FP32 right-hand side, the cycle, and (when
+        // u is given) the FP32 result back to FP64
+        const MgLevel& L0 = m->lv[0];
+        tp_status r = convert_launch(b, L0.b, true, L0.elems, ps, s);
+        if (r != TP_OK) return r;
+        const float* b32 = static_cast<const float*>(L0.b);
+        float* u32 = static_cast<float*>(L0.u);
+        r = f32 ? vcycle_dispatch<float, float>(m, b32, u32, ps, s) : vcycle_dispatch<double, float>(m, b32, u32, ps, s);
+        if (r != TP_OK || !u) return r;
+        return convert_launch(u32, u, false, L0.elems, ps, s);
+    }
+    return f32 ? vcycle_dispatch<float, double>(m, b, u, ps, s) : vcycle_dispatch<double, double>(m, b, u, ps, s);
 }
 
-tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const double* b, double* part, const void* st,
+int mg_storage(const tp_mg* m) { return m->storage; }
+
+const float* mg_result32(const tp_mg* m) {
+    return m->storage == TP_F32 ? static_cast<const float*>(m->lv[0].u) : nullptr;
+}
+
+tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const void* b, bool b32, double* part, const void* st,
                          hipStream_t s) {
     const MgLevel& L = m->lv[0];
     const unsigned grid = static_cast<unsigned>((L.G.ncells + 63) / 64);
     const PcgState* ps = static_cast<const PcgState*>(st);
+    const double* bd = static_cast<const double*>(b);
+    const float* bf = static_cast<const float*>(b);
     switch (m->n) {
-        case 2: hipLaunchKernelGGL((k_mg_dot<2>), dim3(grid), dim3(64), 0, s, a, b, L.G, part, ps); break;
-        case 3: hipLaunchKernelGGL((k_mg_dot<3>), dim3(grid), dim3(64), 0, s, a, b, L.G, part, ps); break;
-        case 4: hipLaunchKernelGGL((k_mg_dot<4>), dim3(grid), dim3(64), 0, s, a, b, L.G, part, ps); break;
+        case 2:
+            if (b32) hipLaunchKernelGGL((k_mg_dot<2, float>), dim3(grid), dim3(64), 0, s, a, bf, L.G, part, ps);
+            else hipLaunchKernelGGL((k_mg_dot<2, double>), dim3(grid), dim3(64), 0, s, a, bd, L.G, part, ps);
+            break;
+        case 3:
+            if (b32) hipLaunchKernelGGL((k_mg_dot<3, float>), dim3(grid), dim3(64), 0, s, a, bf, L.G, part, ps);
+            else hipLaunchKernelGGL((k_mg_dot<3, double>), dim3(grid), dim3(64), 0, s, a, bd, L.G, part, ps);
+            break;
+        case 4:
+            if (b32) hipLaunchKernelGGL((k_mg_dot<4, float>), dim3(grid), dim3(64), 0, s, a, bf, L.G, part, ps);
+            else hipLaunchKernelGGL((k_mg_dot<4, double>), dim3(grid), dim3(64), 0, s, a, bd, L.G, part, ps);
+            break;
         default: return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
     }
     return check_launch("dot");
+}
+
+tp_status mg_enqueue_widen(const tp_mg* m, double* dst, hipStream_t s) {
+    if (m->storage != TP_F32) return set_error(TP_ERR_STATE, "the multigrid stores its levels in FP64");
+    return convert_launch(m->lv[0].u, dst, false, m->lv[0].elems, nullptr, s);
 }
 
 const tp_plan* mg_plan(const tp_mg* m) { return m->plan; }
@@ -471,10 +552,14 @@ const tp_plan* mg_plan(const tp_mg* m) { return m->plan; }
 
 extern "C" {
 
-tp_status tp_mg_create(tp_plan* plan, tp_mg** out) {
+tp_status tp_mg_create(tp_plan* plan, tp_mg** out) { return tp_mg_create_typed(plan, TP_F64, out); }
+
+tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out) {
     if (!out) return set_error(TP_ERR_ARG, "out must be non-null");
     *out = nullptr;
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    if (storage != TP_F64 && storage != TP_F32)
+        return set_error(TP_ERR_UNSUPPORTED, "multigrid level vectors are stored in FP64 or FP32");
     if (!plan->mesh) return set_error(TP_ERR_UNSUPPORTED, "multigrid needs a mesh plan");
     const GroupInfo& g = plan->groups[0];
     if (g.n > kLaneMaxN) return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
@@ -485,6 +570,8 @@ tp_status tp_mg_create(tp_plan* plan, tp_mg** out) {
     if (!m) return set_error(TP_ERR_OOM, "host allocation failed");
     m->plan = plan;
     m->n = g.n;
+    m->storage = storage;
+    const size_t es = storage == TP_F32 ? sizeof(float) : sizeof(double);
     const double a = 0.2, b = 2.0, c = 0.5 * (a + b), d = 0.5 * (b - a);
     for (int j = 1; j <= 3; ++j) m->omega[j - 1] = 1.0 / (c - d * std::cos((2 * j - 1) * 3.141592653589793 / 6.0));
     // levels
@@ -504,11 +591,13 @@ tp_status tp_mg_create(tp_plan* plan, tp_mg** out) {
         L.G.sy = hx * hz / hy;
         L.G.sz = hx * hy / hz;
         L.elems = (L.G.ncells + 63) / 64 * n3 * 64;
-        const size_t vb = static_cast<size_t>(L.elems) * sizeof(double);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&L.t), vb);
-        if (!m->lv.empty()) {
-            if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&L.b), vb);
-            if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&L.u), vb);
+        const size_t vb = static_cast<size_t>(L.elems) * es;
+        if (e == hipSuccess) e = hipMalloc(&L.t, vb);
+        // the finest level works on the caller's b and u, except with FP32
+        // storage, whose finest level has its own FP32 copies
+        if (!m->lv.empty() || storage == TP_F32) {
+            if (e == hipSuccess) e = hipMalloc(&L.b, vb);
+            if (e == hipSuccess) e = hipMalloc(&L.u, vb);
         }
         m->lv.push_back(L);
         if (e != hipSuccess || mx % 2 || my % 2 || mz % 2) break;
@@ -529,11 +618,11 @@ tp_status tp_mg_create(tp_plan* plan, tp_mg** out) {
         return set_error(TP_ERR_UNSUPPORTED, "the coarsest level (" + std::to_string(m->n0) +
                                                  " unknowns) is too large for its dense solve");
     }
-    if (m->lv.size() == 1) {   // no coarser level: the finest is solved densely; it needs b and u scratch
+    if (m->lv.size() == 1 && !m->lv[0].b) {   // no coarser level: the finest is solved densely; it needs b and u scratch
         MgLevel& L0 = m->lv[0];
-        const size_t vb = static_cast<size_t>(L0.elems) * sizeof(double);
-        e = hipMalloc(reinterpret_cast<void**>(&L0.b), vb);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&L0.u), vb);
+        const size_t vb = static_cast<size_t>(L0.elems) * es;
+        e = hipMalloc(&L0.b, vb);
+        if (e == hipSuccess) e = hipMalloc(&L0.u, vb);
         if (e != hipSuccess) {
             free_mg(m);
             delete m;

@@ -236,13 +236,15 @@ __global__ __launch_bounds__(64, 2) void k_pcg_update(double* __restrict__ x, do
 
 // 5.  p = z + beta p over the whole vector (padding lanes included: they are
 // never read as cell data).
-__global__ __launch_bounds__(256) void k_pcg_dir(const double* __restrict__ z, double* __restrict__ p, int64_t n,
+// z in FP64, or in FP32 when it is the result of an FP32-storage V-cycle.
+template <typename TZ>
+__global__ __launch_bounds__(256) void k_pcg_dir(const TZ* __restrict__ z, double* __restrict__ p, int64_t n,
                                                  const PcgState* __restrict__ st) {
     if (st->done) return;
     const double beta = st->beta;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * 256)
-        p[i] = fma(beta, p[i], z[i]);
+        p[i] = fma(beta, p[i], static_cast<double>(z[i]));
 }
 
 // ---------------------------------------------------------------- multigrid preconditioning
@@ -588,12 +590,20 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
         if constexpr (kLane) {
             hipLaunchKernelGGL((k_pcg_start_res<N, LB>), dim3(nwg), dim3(64), 0, stream, b,
                                x_zero ? nullptr : s->q, x, s->xw, s->r, G, s->part, cnt);
-            tp_status st = mg_enqueue_vcycle(s->mg, s->r, s->z, nullptr, f32, stream);
-            if (st == TP_OK) st = mg_enqueue_dot(s->mg, s->r, s->z, s->part, nullptr, stream);
+            // with FP32 level storage z stays in the hierarchy's FP32 vector
+            const bool z32 = mg_storage(s->mg) == TP_F32;
+            const void* zp = z32 ? static_cast<const void*>(mg_result32(s->mg)) : static_cast<const void*>(s->z);
+            tp_status st = mg_enqueue_vcycle(s->mg, s->r, z32 ? nullptr : s->z, nullptr, f32, stream);
+            if (st == TP_OK) st = mg_enqueue_dot(s->mg, s->r, zp, z32, s->part, nullptr, stream);
             if (st != TP_OK) return st;
-            const hipError_t e = hipMemcpyAsync(s->p, s->z, static_cast<size_t>(s->elems) * sizeof(double),
-                                                hipMemcpyDeviceToDevice, stream);
-            if (e != hipSuccess) return hip_error(e, "PCG start");
+            if (z32) {
+                st = mg_enqueue_widen(s->mg, s->p, stream);
+                if (st != TP_OK) return st;
+            } else {
+                const hipError_t e = hipMemcpyAsync(s->p, s->z, static_cast<size_t>(s->elems) * sizeof(double),
+                                                    hipMemcpyDeviceToDevice, stream);
+                if (e != hipSuccess) return hip_error(e, "PCG start");
+            }
         } else {
             return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
         }
@@ -651,8 +661,12 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                     if constexpr (kLane) {
                         hipLaunchKernelGGL((k_pcg_axpy<N, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->p, s->q,
                                            G, s->st, s->part, cnt);
-                        (void)mg_enqueue_vcycle(s->mg, s->r, s->z, s->st, f32, cs);
-                        (void)mg_enqueue_dot(s->mg, s->r, s->z, s->part, s->st, cs);
+                        const bool z32 = mg_storage(s->mg) == TP_F32;
+                        (void)mg_enqueue_vcycle(s->mg, s->r, z32 ? nullptr : s->z, s->st, f32, cs);
+                        (void)mg_enqueue_dot(s->mg, s->r,
+                                             z32 ? static_cast<const void*>(mg_result32(s->mg))
+                                                 : static_cast<const void*>(s->z),
+                                             z32, s->part, s->st, cs);
                     }
                 } else if constexpr (kLane)
                     hipLaunchKernelGGL((k_pcg_update<N, TI, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->z,
@@ -671,7 +685,11 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                     hipLaunchKernelGGL((k_pcg_update_wave<N, TI, false, false>), dim3(nwg), dim3(64), 0, cs, s->xw,
                                        s->r, s->z, s->p, s->q, G, tabS, s->st, s->part, cnt);
                 hipLaunchKernelGGL(k_pcg_reduce_beta, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
-                hipLaunchKernelGGL(k_pcg_dir, dim3(dgrid), dim3(256), 0, cs, s->z, s->p, s->elems, s->st);
+                if (s->mg && mg_storage(s->mg) == TP_F32)
+                    hipLaunchKernelGGL(k_pcg_dir<float>, dim3(dgrid), dim3(256), 0, cs, mg_result32(s->mg), s->p,
+                                       s->elems, s->st);
+                else
+                    hipLaunchKernelGGL(k_pcg_dir<double>, dim3(dgrid), dim3(256), 0, cs, s->z, s->p, s->elems, s->st);
             }
             const hipError_t e2 = hipStreamEndCapture(cs, &gr);
             if (e2 != hipSuccess) e = e2;

@@ -41,7 +41,7 @@ EXPORTS = (
     "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel", "tp_plan_create_mesh",
     "tp_pcg_create", "tp_pcg_solve", "tp_pcg_destroy", "tp_pcg_begin", "tp_pcg_poll",
     "tp_mg_create", "tp_mg_vcycle", "tp_mg_destroy", "tp_pcg_set_multigrid", "tp_change_basis",
-    "tp_pcg_set_norm", "tp_reference_basis",
+    "tp_pcg_set_norm", "tp_reference_basis", "tp_mg_create_typed",
 )
 KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_pcg_begin": (i32, [vp, vp, vp, i32, i32, dbl, i32, i32, vp]),
         "tp_pcg_poll": (i32, [vp, ctypes.POINTER(_PcgSummary)]),
         "tp_mg_create": (i32, [vp, ctypes.POINTER(vp)]),
+        "tp_mg_create_typed": (i32, [vp, i32, ctypes.POINTER(vp)]),
         "tp_mg_vcycle": (i32, [vp, vp, vp, vp]),
         "tp_mg_destroy": (i32, [vp]),
         "tp_pcg_set_multigrid": (i32, [vp, vp]),
@@ -357,7 +358,9 @@ class Plan:
 
     def autotune(self, dtype: int = F64, reps: int = 10):
         """Time the kernel variants per group (tp_plan_autotune) and keep the
-        fastest; returns [(apply_us, inverse_us, solve_us)] per group."""
+        fastest; returns [(apply_us, inverse_us, solve_us)] per group.  For a
+        persistent plan the first entry holds the tuned single launch's times
+        (solve: inner precision = dtype) and the others are -1."""
         us = (ctypes.c_double * (3 * max(1, len(self.groups))))()
         _check(load().tp_plan_autotune(self.handle, dtype, reps, us))
         return [tuple(us[3 * i:3 * i + 3]) for i in range(len(self.groups))]
@@ -370,6 +373,20 @@ class Plan:
         if grid and name == "wave" and call != 2:
             name += "/" + {1: "full", 2: "half", 0: "tile"}.get(code >> 4, "?")
         return name
+
+    def launch_config(self, group: int, call: int, dtype: int = F64) -> dict:
+        """A persistent plan's single-launch choice for a group
+        (tp_plan_group_kernel): its tile body (lane / wave), tiles per
+        workgroup, the position of its segment in the launch and, for the
+        solve (call 2), the grid (full / half / item)."""
+        code = load().tp_plan_group_kernel(self.handle, group, call, dtype)
+        if code < 0:
+            raise TpfdmError(-1, "no launch configuration (not a persistent plan, or invalid argument)")
+        out = {"body": KIND_NAMES[code & 15], "tiles_per_workgroup": 1 << ((code >> 8) & 15),
+               "position": (code >> 12) & 0xFFFF}
+        if call == 2:
+            out["grid"] = {1: "full", 2: "half", 0: "item"}.get((code >> 4) & 15, "?")
+        return out
 
     def change_basis(self, u, v, to_nodal: bool = True, stream=None, loads: bool = False):
         """v = (T (x) T (x) T) u (to_nodal), its inverse (not to_nodal), or
@@ -476,11 +493,17 @@ class PCG:
 class MG:
     """Multigrid V-cycle for the coupled SIPG system of a mesh plan (tp_mg_*)."""
 
-    def __init__(self, plan: "Plan"):
+    def __init__(self, plan: "Plan", storage: int = F64):
+        """storage: element type of the level vectors (F64, or F32 via
+        tp_mg_create_typed)."""
         h = ctypes.c_void_p()
-        _check(load().tp_mg_create(plan.handle, ctypes.byref(h)))
+        if storage == F64:
+            _check(load().tp_mg_create(plan.handle, ctypes.byref(h)))
+        else:
+            _check(load().tp_mg_create_typed(plan.handle, storage, ctypes.byref(h)))
         self._h = h
         self.plan = plan
+        self.storage = storage
 
     @property
     def handle(self):

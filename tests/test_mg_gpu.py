@@ -305,3 +305,57 @@ def test_nonfinite_rhs_is_reported(multigrid):
         bb = to_blocked(plan, b, tpfdm.F64)
         s = solver.solve(bb, bx, rtol=1e-9, maxit=2000)
         assert s["converged"]
+
+
+# ------------------------------------------------------------------ FP32 level storage
+@pytest.mark.parametrize("p,m", [(1, 8), (2, 4), (3, 4), (3, 6)])
+def test_vcycle_fp32_storage_matches_oracle(p, m):
+    """Level vectors stored in FP32 (tp_mg_create_typed): FP64 arithmetic,
+    rounded to FP32 where stored; the V-cycle agrees with the oracle's FP64
+    V-cycle to a few FP32 roundings of the solution's scale per sweep."""
+    torch = _torch()
+    H = _hierarchy(p, m)
+    nd = m ** 3 * (p + 1) ** 3
+    b = _rhs(nd, 40 + 10 * m + p)
+    xo = H.vcycle(b)
+    with _cube_plan(p, m) as plan, tpfdm.MG(plan, storage=tpfdm.F32) as V:
+        bb = to_blocked(plan, b, tpfdm.F64)
+        bx = torch.full_like(bb, float("nan"))
+        V.vcycle(bb, bx)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    err = np.abs(x - xo).max() / np.abs(xo).max()
+    print(f"p={p} m={m} FP32-storage V-cycle rel err {err:.2e}")
+    assert np.all(np.isfinite(x))
+    assert err <= 2e-5
+
+
+@pytest.mark.parametrize("p,m,inner", [(2, 8, tpfdm.F32), (3, 8, tpfdm.F32), (3, 4, tpfdm.F64)])
+def test_mg_pcg_fp32_storage_reaches_the_oracle_residual(p, m, inner):
+    """MG-PCG with FP32 level storage (z in FP32; x, r, p and the dot
+    products in FP64) reaches the same true residual as the FP64 solve,
+    measured with the oracle's operator, within the FP64 solve's iteration
+    count + 1."""
+    torch = _torch()
+    cells, h = (m,) * 3, (1.0 / m,) * 3
+    A = sipg.assemble(p, cells, h)
+    b = _rhs(A.shape[0], 60 + p + m)
+    rtol = 1e-10
+    res = {}
+    with _cube_plan(p, m) as plan:
+        bb = to_blocked(plan, b, tpfdm.F64)
+        for storage in (tpfdm.F64, tpfdm.F32):
+            with tpfdm.MG(plan, storage=storage) as V, tpfdm.PCG(plan) as solver:
+                solver.set_multigrid(V)
+                bx = torch.full_like(bb, float("nan"))
+                s = solver.solve(bb, bx, inner=inner, rtol=rtol, maxit=100, check_every=4)
+                x = from_blocked(plan, bx, tpfdm.F64)
+            true = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+            res[storage] = (s, true, x)
+            print(f"p={p} m={m} storage={tpfdm.DTYPE_NAMES[storage]} {s} true relres {true:.2e}")
+    s64, t64, x64 = res[tpfdm.F64]
+    s32, t32, x32 = res[tpfdm.F32]
+    assert s64["converged"] and s32["converged"]
+    assert s32["iterations"] <= s64["iterations"] + 1
+    assert t64 <= 2 * rtol and t32 <= 2 * rtol
+    xs = spl.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x32 - xs) <= 1e-7 * np.linalg.norm(xs)

@@ -558,6 +558,10 @@ def test_default_kernel_choices_and_persistent_autotune():
     with make_plan(workloads.random_blocks(7, 10, seed=33)) as plan:
         assert plan.kernel(0, 0, tpfdm.F16) == "mfma" and plan.kernel(0, 0, tpfdm.F64) == "wave"
     with make_plan(wl, persistent=True) as plan:
-        with pytest.raises(tpfdm.TpfdmError) as e:
-            plan.autotune(tpfdm.F32)
-        assert e.value.status == -2
+        # defaults of the single launch: the lane body for n <= 4 in apply and
+        # inverse, wave tiles in the solve, one tile per workgroup, groups in order
+        for gi, g in enumerate(wl.groups):
+            c = plan.launch_config(gi, 0, tpfdm.F32)
+            assert c == {"body": "lane" if g.n <= 4 else "wave", "tiles_per_workgroup": 1, "position": gi}
+            c = plan.launch_config(gi, 2, tpfdm.F32)
+            assert c["body"] == "wave" and c["grid"] == "full" and c["position"] == gi
