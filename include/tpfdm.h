@@ -272,6 +272,24 @@ tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner,
                    double rtol, int32_t maxit, int32_t* iters, double* relres,
                    tp_solve_summary* summary, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tp_solve
+ * with the same arguments, kernels and results (bit for bit), except that
+ * the per-workgroup partial summaries and the reduced summary go to a
+ * static device workspace of the library (a file-scope device array of
+ * 384 KiB + 256 B, one per GPU, held until the process ends) instead of the
+ * plan's workspace.  The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine; the plan, b and x are the caller's).  It
+ * rejects, with TP_ERR_ARG and before any launch, plans whose solve may
+ * need more than 16384 partial summaries (a bound of one per tile, at most
+ * 8192 per group's launch on a 256-CU device).  Every call on a GPU shares
+ * that GPU's workspace and overwrites it: calls that overlap on one GPU
+ * (other streams or threads) race, and tp_solve_summary_fetch does not see
+ * these solves (pass summary instead). */
+tp_status tp_solve_static(tp_plan* plan, const double* b, double* x, tp_dtype inner,
+                          double rtol, int32_t maxit, int32_t* iters, double* relres,
+                          tp_solve_summary* summary, hipStream_t stream);
+
 /* The summary (max iterations, failures, max relative residual) of the most
  * recent tp_solve on this plan, including solves replayed from a graph.
  * Synchronises the stream.  Returns TP_ERR_NOT_CONVERGED / TP_ERR_NONFINITE

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libtpfdm.so")
 
 ARCH = "gfx950"
 HOST_SOURCES = ["api.cpp", "refdata.cpp"]
-DEVICE_SOURCES = ["kernels.hip", "eo.hip", "persistent.hip", "mfma.hip", "general.hip", "sipg.hip", "pcg.hip", "mg.hip", "basis.hip"]
+DEVICE_SOURCES = ["kernels.hip", "eo.hip", "persistent.hip", "mfma.hip", "general.hip", "sipg.hip", "pcg.hip", "mg.hip", "basis.hip", "static_scratch.hip"]
 
 
 def hipcc() -> str:

@@ -662,8 +662,9 @@ tp_status plan_create(const tp_group* groups, int32_t ngroups, const tp_plan_opt
 
 
 namespace tpfdm {
-// The block-local solve of tp_solve: the launches write their partial
-// summaries to w.parts and the reduction the summary to w.summary.
+// The block-local solve of tp_solve and tp_solve_static: the launches write
+// their partial summaries to w.parts and the reduction the summary to
+// w.summary.
 tp_status solve_impl(tp_plan* plan, const double* b, double* x, tp_dtype inner, double rtol, int32_t maxit,
                      int32_t* iters, double* relres, tp_solve_summary* summary, hipStream_t stream,
                      const SolveWork& w) {
@@ -709,6 +710,21 @@ tp_status solve_impl(tp_plan* plan, const double* b, double* x, tp_dtype inner, 
             return set_error(TP_ERR_NOT_CONVERGED, std::to_string(hs.n_failed) + " blocks missed rtol");
     }
     return TP_OK;
+}
+
+// Upper bound on the per-workgroup partial summaries one solve of the plan
+// writes: every solve launch runs at most one workgroup per tile and at
+// most kMaxWgPerCu resident workgroups per compute unit.
+int64_t solve_parts_bound(const Plan& p) {
+    const int64_t per_launch = static_cast<int64_t>(p.cus) * kMaxWgPerCu;
+    if (p.persistent) return per_launch;
+    int64_t total = 0;
+    for (const auto& g : p.groups) {
+        const int bpw = g.n * g.n >= 64 ? 1 : 64 / (g.n * g.n);
+        const int64_t tiles = std::max<int64_t>((g.nblocks + 63) / 64, (g.nblocks + bpw - 1) / bpw);
+        total += std::min(tiles, per_launch);
+    }
+    return total;
 }
 
 }  // namespace tpfdm
@@ -1100,6 +1116,20 @@ tp_status tp_solve(tp_plan* plan, const double* b, double* x, tp_dtype inner, do
                    int32_t* iters, double* relres, tp_solve_summary* summary, hipStream_t stream) {
     if (!plan) return set_error(TP_ERR_ARG, "plan is null");
     return solve_impl(plan, b, x, inner, rtol, maxit, iters, relres, summary, stream, plan_work(*plan));
+}
+
+tp_status tp_solve_static(tp_plan* plan, const double* b, double* x, tp_dtype inner, double rtol, int32_t maxit,
+                          int32_t* iters, double* relres, tp_solve_summary* summary, hipStream_t stream) {
+    if (!plan) return set_error(TP_ERR_ARG, "plan is null");
+    SolveWork w{};
+    tp_status st = static_solve_work(&w);
+    if (st != TP_OK) return st;
+    const int64_t need = solve_parts_bound(*plan);
+    if (need > w.cap)
+        return set_error(TP_ERR_ARG, "tp_solve_static: the solve of this plan may need " + std::to_string(need) +
+                                         " per-workgroup partial summaries, more than the static workspace holds (" +
+                                         std::to_string(w.cap) + "); use tp_solve");
+    return solve_impl(plan, b, x, inner, rtol, maxit, iters, relres, summary, stream, w);
 }
 
 tp_status tp_solve_summary_fetch(tp_plan* plan, tp_solve_summary* summary, hipStream_t stream) {

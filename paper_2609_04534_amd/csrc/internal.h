@@ -168,8 +168,8 @@ struct SolveSummary {
 };
 
 // Where a solve launch writes its per-workgroup partial summaries (at most
-// cap of them) and where the reduction puts the summary (the plan's own
-// workspace, plan_work).
+// cap of them) and where the reduction puts the summary: the plan's own
+// workspace for tp_solve, the library's static scratch for tp_solve_static.
 struct SolveWork {
     SolvePartial* parts;
     int64_t cap;
@@ -179,6 +179,10 @@ inline SolveWork plan_work(const Plan& p) {
     return SolveWork{static_cast<SolvePartial*>(p.partials_dev), p.partials_cap,
                      static_cast<SolveSummary*>(p.summary_dev)};
 }
+
+// The static device workspace of tp_solve_static (static_scratch.hip): its
+// address on the current device, looked up on the first call per device.
+tp_status static_solve_work(SolveWork* out);
 
 // thread-local last error
 tp_status set_error(tp_status st, const std::string& msg);

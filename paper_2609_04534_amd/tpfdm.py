@@ -41,7 +41,7 @@ EXPORTS = (
     "tp_graph_destroy", "tp_plan_autotune", "tp_plan_group_kernel", "tp_plan_create_mesh",
     "tp_pcg_create", "tp_pcg_solve", "tp_pcg_destroy", "tp_pcg_begin", "tp_pcg_poll",
     "tp_mg_create", "tp_mg_vcycle", "tp_mg_destroy", "tp_pcg_set_multigrid", "tp_change_basis",
-    "tp_pcg_set_norm", "tp_reference_basis", "tp_mg_create_typed",
+    "tp_pcg_set_norm", "tp_reference_basis", "tp_solve_static", "tp_mg_create_typed",
 )
 KIND_NAMES = {0: "lane", 1: "wave", 2: "mfma", 3: "general"}
 GRAPH_APPLY, GRAPH_INVERSE, GRAPH_SOLVE = 0, 1, 2
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "tp_setup_inverse": (i32, [vp, i32, i32, dbl]),
         "tp_apply_inverse": (i32, [vp, vp, vp, i32, vp]),
         "tp_solve": (i32, [vp, vp, vp, i32, dbl, i32, vp, vp, ctypes.POINTER(_Summary), vp]),
+        "tp_solve_static": (i32, [vp, vp, vp, i32, dbl, i32, vp, vp, ctypes.POINTER(_Summary), vp]),
         "tp_pack": (i32, [vp, vp, vp, i32, vp]),
         "tp_unpack": (i32, [vp, vp, vp, i32, vp]),
         "tp_reference_matrices": (i32, [i32, dbl, vp, vp, vp]),
@@ -325,11 +326,13 @@ class Plan:
         _check(load().tp_apply_inverse(self.handle, _ptr(r), _ptr(x), torch_dtype_code(r), _stream(stream)))
 
     def solve(self, b, x, inner: int = F32, rtol: float = 1e-10, maxit: int = 50, iters=None, relres=None,
-              summary: bool = True, stream=None, raise_on_failure: bool = True):
-        """Returns the summary dict (or None when summary=False)."""
+              summary: bool = True, stream=None, raise_on_failure: bool = True, static: bool = False):
+        """Returns the summary dict (or None when summary=False).  static=True
+        calls tp_solve_static (no allocation; the library's static workspace)."""
         s = _Summary()
-        st = load().tp_solve(self.handle, _ptr(b), _ptr(x), inner, rtol, maxit, _ptr(iters), _ptr(relres),
-                             ctypes.byref(s) if summary else None, _stream(stream))
+        fn = load().tp_solve_static if static else load().tp_solve
+        st = fn(self.handle, _ptr(b), _ptr(x), inner, rtol, maxit, _ptr(iters), _ptr(relres),
+                ctypes.byref(s) if summary else None, _stream(stream))
         if st != TP_OK and (raise_on_failure or st not in (-5, -6)):
             _check(st)
         if not summary:
