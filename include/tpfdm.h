@@ -363,7 +363,7 @@ tp_status tp_plan_autotune(tp_plan* plan, tp_dtype dtype, int32_t reps, double* 
 int32_t tp_plan_group_kernel(const tp_plan* plan, int32_t group, int32_t call, tp_dtype dtype);
 
 /* Preconditioned conjugate gradients for the coupled SIPG system A x = b of
- * a mesh plan (n <= 4), FP64 throughout except the preconditioner: the
+ * a mesh plan (every n), FP64 throughout except the preconditioner: the
  * cell-wise fast-diagonalization block-Jacobi z = D^{-1} r of Sec. 5.2 (the
  * cell blocks of eq. (cell_block), interior stencil on every cell), applied
  * in `inner` precision (TP_F64, or TP_F32 on the FP64 vectors).  Needs
@@ -411,8 +411,10 @@ tp_status tp_pcg_begin(tp_pcg* pcg, const double* b, double* x, int32_t x_is_zer
                        int32_t maxit, int32_t check_every, hipStream_t stream);
 tp_status tp_pcg_poll(tp_pcg* pcg, tp_pcg_summary* summary);
 
-/* Geometric multigrid for the coupled system of a mesh plan (n <= 4, layout
- * B = 64): the V-cycle the paper uses to precondition CG (Sec. 5, Sec. 6.1).
+/* Geometric multigrid for the coupled system of a mesh plan (n <= 4 with the
+ * default layout B = 64; n = 5..8 with the default layout B = 1, in the
+ * Lagrange basis, on one-cell-per-wave kernels): the V-cycle the paper uses
+ * to precondition CG (Sec. 5, Sec. 6.1).
  * Levels: the mesh and its uniform coarsenings (cells halved while all three
  * counts are even, lengths doubled, each level's own operator); per level
  * one pre- and one post-smoothing application of the degree-three
@@ -460,7 +462,7 @@ tp_status tp_mg_create(tp_plan* plan, tp_mg** out);
  * FP64, and inside tp_pcg_* solves the preconditioned residual z stays in
  * FP32 (the CG recurrences, x, r, p and every dot product remain FP64:
  * (r, z) and p = z + beta p read z in FP32).  TP_ERR_UNSUPPORTED for other
- * types. */
+ * types, and for FP32 storage with n >= 5. */
 tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out);
 tp_status tp_mg_vcycle(tp_mg* mg, const double* b, double* x, hipStream_t stream);
 tp_status tp_mg_destroy(tp_mg* mg);

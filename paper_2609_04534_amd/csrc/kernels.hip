@@ -44,7 +44,7 @@ __global__ __launch_bounds__(64, 2) void k_apply_lane(const TS* __restrict__ u, 
 }
 
 template <int N, typename TS, typename TC, bool NT, int LB>
-__global__ __launch_bounds__(64, 2) void k_inverse_lane(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
+__global__ __launch_bounds__(64, 3) void k_inverse_lane(const TS* __restrict__ r, TS* __restrict__ x, GArgs G,
                                                       Eig<N, TC> E) {
     const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (g >= G.nblocks) return;

@@ -31,6 +31,7 @@
 #include <new>
 #include <thread>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "sipg.h"
@@ -233,19 +234,19 @@ __global__ __launch_bounds__(64, 2) void k_mg_prolong(const TS* __restrict__ uc,
 // order, one row of the (column-major) inverse per thread.
 template <int N, typename TS>
 __global__ __launch_bounds__(256) void k_mg_coarse(const double* __restrict__ inv, const TS* __restrict__ b,
-                                                   TS* __restrict__ u, int64_t n0, int64_t offset,
+                                                   TS* __restrict__ u, int64_t n0, int64_t offset, int lb,
                                                    const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
     __shared__ double sb[kMaxCoarse];
     for (int64_t e = threadIdx.x; e < n0; e += 256)
-        sb[e] = static_cast<double>(b[offset + block_base(e / N3, 6, N3) + ((e % N3) << 6)]);
+        sb[e] = static_cast<double>(b[offset + block_base(e / N3, lb, N3) + ((e % N3) << lb)]);
     __syncthreads();
     const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (i >= n0) return;
     double s = 0.0;
     for (int64_t j = 0; j < n0; ++j) s = fma(inv[j * n0 + i], sb[j], s);
-    u[offset + block_base(i / N3, 6, N3) + ((i % N3) << 6)] = static_cast<TS>(s);
+    u[offset + block_base(i / N3, lb, N3) + ((i % N3) << lb)] = static_cast<TS>(s);
 }
 
 // Partial (a, b) per 64-cell tile (the layout of the PCG partials).
@@ -267,6 +268,269 @@ __global__ __launch_bounds__(64) void k_mg_dot(const double* __restrict__ a, con
     }
     s = wave_sum(s);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// ---------------------------------------------------------------- n >= 5
+// One cell per wave (layout B = 1, FP64 level vectors): lane (a, b) owns
+// the z-pencil (a, b, 0..n-1) of the cell for loads and stores; the
+// operator row is the wave body of the coupled operator (wave_sipg_cell,
+// output by x-pencils), the block inverse the even-odd fast
+// diagonalization in an LDS slab, and the transfers three 1D contractions
+// through an LDS slab.
+
+// Pencil base of lane (pa, pb)'s z-pencil of cell c.
+template <int N>
+__device__ __forceinline__ int64_t zpencil_base(const MeshArgs& G, int64_t c, const Pencil<N>& pc) {
+    return G.offset + block_base(c, G.logB, N * N * N) + (static_cast<int64_t>((pc.pa * N + pc.pb) * N) << G.logB);
+}
+
+// t = A u, one cell per wave.
+template <int N, bool VP>
+__global__ __launch_bounds__(64, 2) void k_mg_apply_wave(const double* __restrict__ u, double* __restrict__ t,
+                                                       MeshArgs G, const double* __restrict__ tab,
+                                                       FaceRef<N, double> F, const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
+    __shared__ WaveLds<N, double> L;
+    stage_table<double, TAB>(tab, L.tab);
+    const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
+    double y[N];
+    wave_sipg_cell<N, double, VP, false>(u, G, L.tab, F, c, L, y);
+    const Pencil<N> pc(1);
+    if (pc.act) {
+        double* tb = t + G.offset + block_base(c, G.logB, N * N * N);
+#pragma unroll
+        for (int i = 0; i < N; ++i) tb[static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << G.logB] = y[i];
+    }
+}
+
+// z-pencil in, z = omega D^{-1} r of the wave's cell in precision TI in the
+// slab, the lane's z-pencil of it returned (every lane of the wave calls it).
+template <int N, typename TI>
+__device__ __forceinline__ void wave_block_inverse(const Pencil<N>& pc, TI* slab, const TI* T, const TI* lam,
+                                                   const MeshArgs& G, double (&r)[N]) {
+    using SL = Slab<N>;
+    eo_inverse_lds<N, TI>(pc, slab, T, T + EOShape<N>::SE, lam, static_cast<TI>(G.sx), static_cast<TI>(G.sy),
+                          static_cast<TI>(G.sz));
+    if (pc.act)
+#pragma unroll
+        for (int k = 0; k < N; ++k) r[k] = static_cast<double>(slab[SL::at(pc.pa, pc.pb, k)]);
+}
+
+// u = omega D^{-1} b (the first Chebyshev update from u = 0), one cell per wave.
+template <int N, typename TI, bool VP>
+__global__ __launch_bounds__(64, 2) void k_mg_jacobi0_wave(const double* __restrict__ b, double* __restrict__ u,
+                                                         MeshArgs G, const TI* __restrict__ tabS, double omega,
+                                                         const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    using SL = Slab<N>;
+    constexpr int TABM = EOShape<N>::SE + EOShape<N>::SO;
+    __shared__ TI slab[SL::size];
+    __shared__ TI stab[TABM + N];
+    for (int e = threadIdx.x; e < TABM + N; e += 64) stab[e] = tabS[e];
+    const int64_t c = blockIdx.x;
+    const Pencil<N> pc(1);
+    const int64_t pb = zpencil_base<N>(G, c, pc);
+    double v[N];
+    if (pc.act) {
+        pencil_load<N, VP>(v, b + pb, G.logB);
+#pragma unroll
+        for (int k = 0; k < N; ++k) slab[SL::at(pc.pa, pc.pb, k)] = static_cast<TI>(v[k]);
+    }
+    wave_sync();
+    wave_block_inverse<N, TI>(pc, slab, stab, stab + TABM, G, v);
+    if (pc.act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] *= omega;
+        pencil_store<N, VP>(u + pb, v, G.logB);
+    }
+}
+
+// One Chebyshev update u_out = u_in + omega D^{-1} (b - A u_in) of the
+// wave's cell: the operator row by x-pencils, the residual into the slab in
+// precision TI, the block inverse, the update by z-pencils.
+template <int N, typename TI, bool VP>
+__global__ __launch_bounds__(64, 2) void k_mg_smooth_wave(const double* __restrict__ b,
+                                                        const double* __restrict__ uin, double* __restrict__ uout,
+                                                        MeshArgs G, const double* __restrict__ tab,
+                                                        FaceRef<N, double> F, const TI* __restrict__ tabS,
+                                                        double omega, const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    using SL = Slab<N>;
+    constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
+    constexpr int TABM = EOShape<N>::SE + EOShape<N>::SO;
+    static_assert(SL::size * sizeof(TI) <= 2 * SL::size * sizeof(double), "slab exceeds the volume scratch");
+    __shared__ WaveLds<N, double> L;
+    __shared__ TI stab[TABM + N];
+    stage_table<double, TAB>(tab, L.tab);
+    for (int e = threadIdx.x; e < TABM + N; e += 64) stab[e] = tabS[e];
+    const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
+    double y[N];
+    wave_sipg_cell<N, double, VP, false>(uin, G, L.tab, F, c, L, y);   // ends synced
+    const Pencil<N> pc(1);
+    TI* slab = reinterpret_cast<TI*>(L.t);
+    const double* bb = b + G.offset + block_base(c, G.logB, N * N * N);
+    if (pc.act)
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int64_t o = static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << G.logB;
+            slab[SL::at(i, pc.pa, pc.pb)] = static_cast<TI>(bb[o] - y[i]);
+        }
+    wave_sync();
+    double d[N];
+    wave_block_inverse<N, TI>(pc, slab, stab, stab + TABM, G, d);
+    if (pc.act) {
+        const int64_t pb = zpencil_base<N>(G, c, pc);
+        double uv[N];
+        pencil_load<N, VP>(uv, uin + pb, G.logB);
+#pragma unroll
+        for (int k = 0; k < N; ++k) uv[k] = fma(omega, d[k], uv[k]);
+        pencil_store<N, VP>(uout + pb, uv, G.logB);
+    }
+}
+
+// (X (x) Y (x) Z) applied to the slab's block, in place, X acting on x:
+// the lane's z-pencil z enters in registers; on return the lane holds its
+// x-pencil (x0..x_{n-1} at (pa, pb) = (j, k)) of the result in out.
+template <int N>
+__device__ __forceinline__ void wave_kron3(const Pencil<N>& pc, double* slab, const double* X, const double* Y,
+                                           const double* Z, const double (&z)[N], double (&out)[N]) {
+    using SL = Slab<N>;
+    if (pc.act) {   // z: lane (i, j)
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < N; ++kk) sacc = fma(Z[k * N + kk], z[kk], sacc);
+            slab[SL::at(pc.pa, pc.pb, k)] = sacc;
+        }
+    }
+    wave_sync();
+    if (pc.act) {   // y: lane (i, k)
+        double v[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) v[j] = slab[SL::at(pc.pa, j, pc.pb)];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < N; ++jj) sacc = fma(Y[j * N + jj], v[jj], sacc);
+            slab[SL::at(pc.pa, j, pc.pb)] = sacc;
+        }
+    }
+    wave_sync();
+    if (pc.act) {   // x: lane (j, k)
+        double v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = slab[SL::at(i, pc.pa, pc.pb)];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int ii = 0; ii < N; ++ii) sacc = fma(X[i * N + ii], v[ii], sacc);
+            out[i] = sacc;
+        }
+    }
+    wave_sync();
+}
+
+// b_coarse = P^T (b_fine - t_fine), one coarse cell per wave, summed over
+// its eight children.
+template <int N, bool VP>
+__global__ __launch_bounds__(64, 2) void k_mg_restrict_wave(const double* __restrict__ bf,
+                                                          const double* __restrict__ tf, double* __restrict__ bc,
+                                                          MeshArgs Gf, MeshArgs Gc, ProlTab<N> PT,
+                                                          const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    __shared__ double slab[Slab<N>::size];
+    __shared__ double tabs[2 * N * N];
+    for (int e = threadIdx.x; e < 2 * N * N; e += 64) tabs[e] = PT.p[e / (N * N)][e % (N * N)];
+    wave_sync();
+    const int64_t c = blockIdx.x;
+    const uint32_t cu = static_cast<uint32_t>(c);
+    const uint32_t cz = cu % static_cast<uint32_t>(Gc.mz);
+    const uint32_t rr = cu / static_cast<uint32_t>(Gc.mz);
+    const uint32_t cy = rr % static_cast<uint32_t>(Gc.my);
+    const uint32_t cx = rr / static_cast<uint32_t>(Gc.my);
+    const Pencil<N> pc(1);
+    double acc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc[i] = 0.0;
+    for (int ch = 0; ch < 8; ++ch) {
+        const int bx = ch >> 2, by = (ch >> 1) & 1, bz = ch & 1;
+        const int64_t f = (static_cast<int64_t>(2 * cx + bx) * Gf.my + (2 * cy + by)) * Gf.mz + (2 * cz + bz);
+        double z[N], out[N];
+        if (pc.act) {
+            const int64_t pb = zpencil_base<N>(Gf, f, pc);
+            double tv[N];
+            pencil_load<N, VP>(z, bf + pb, Gf.logB);
+            pencil_load<N, VP>(tv, tf + pb, Gf.logB);
+#pragma unroll
+            for (int k = 0; k < N; ++k) z[k] -= tv[k];
+        }
+        wave_kron3<N>(pc, slab, tabs + bx * N * N, tabs + by * N * N, tabs + bz * N * N, z, out);
+        if (pc.act)
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc[i] += out[i];
+    }
+    if (pc.act) {
+        double* cb = bc + Gc.offset + block_base(c, Gc.logB, N * N * N);
+#pragma unroll
+        for (int i = 0; i < N; ++i) cb[static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << Gc.logB] = acc[i];
+    }
+}
+
+// u_out = u_fine + P u_coarse, one fine cell per wave.
+template <int N, bool VP>
+__global__ __launch_bounds__(64, 2) void k_mg_prolong_wave(const double* __restrict__ uc,
+                                                         const double* __restrict__ uf, double* __restrict__ uout,
+                                                         MeshArgs Gf, MeshArgs Gc, ProlTab<N> P,
+                                                         const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    __shared__ double slab[Slab<N>::size];
+    __shared__ double tabs[2 * N * N];
+    for (int e = threadIdx.x; e < 2 * N * N; e += 64) tabs[e] = P.p[e / (N * N)][e % (N * N)];
+    wave_sync();
+    const int64_t f = blockIdx.x;
+    const uint32_t fu = static_cast<uint32_t>(f);
+    const uint32_t fz = fu % static_cast<uint32_t>(Gf.mz);
+    const uint32_t rr = fu / static_cast<uint32_t>(Gf.mz);
+    const uint32_t fy = rr % static_cast<uint32_t>(Gf.my);
+    const uint32_t fx = rr / static_cast<uint32_t>(Gf.my);
+    const int64_t c = (static_cast<int64_t>(fx / 2) * Gc.my + fy / 2) * Gc.mz + fz / 2;
+    const Pencil<N> pc(1);
+    double z[N], out[N];
+    if (pc.act) pencil_load<N, VP>(z, uc + zpencil_base<N>(Gc, c, pc), Gc.logB);
+    wave_kron3<N>(pc, slab, tabs + (fx & 1) * N * N, tabs + (fy & 1) * N * N, tabs + (fz & 1) * N * N, z, out);
+    if (pc.act) {
+        const int64_t base = Gf.offset + block_base(f, Gf.logB, N * N * N);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const int64_t o = base + (static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << Gf.logB);
+            uout[o] = uf[o] + out[i];
+        }
+    }
+}
+
+// Partial (a, b) per cell, one cell per wave.
+template <int N, bool VP>
+__global__ __launch_bounds__(64) void k_mg_dot_wave(const double* __restrict__ a, const double* __restrict__ b,
+                                                    MeshArgs G, double* __restrict__ part,
+                                                    const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    const int64_t c = blockIdx.x;
+    const Pencil<N> pc(1);
+    double s = 0.0;
+    if (pc.act) {
+        const int64_t pb = zpencil_base<N>(G, c, pc);
+        double av[N], bv[N];
+        pencil_load<N, VP>(av, a + pb, G.logB);
+        pencil_load<N, VP>(bv, b + pb, G.logB);
+#pragma unroll
+        for (int k = 0; k < N; ++k) s = fma(av[k], bv[k], s);
+    }
+    s = wave_sum(s);
+    if (threadIdx.x == 0) part[c] = s;
 }
 
 // dst = src converted element by element (the finest level's right-hand
@@ -373,7 +637,7 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const TS* b, TS* u, const PcgSt
     if (l + 1 == m->lv.size()) {
         const unsigned cg = static_cast<unsigned>((m->n0 + 255) / 256);
         hipLaunchKernelGGL((k_mg_coarse<N, TS>), dim3(cg), dim3(256), 0, s, m->coarse_inv, b, u, m->n0, L.G.offset,
-                           st);
+                           L.G.logB, st);
         return check_launch("coarse solve");
     }
     Pair<N, double> R;
@@ -413,6 +677,57 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const TS* b, TS* u, const PcgSt
     return check_launch("smoothing");
 }
 
+// The same V-cycle for n >= 5 on the wave kernels (FP64 level vectors,
+// layout B = 1: pencils move as 16-byte vectors).
+template <int N, typename TI, bool VP>
+tp_status vcycle_level_wave(const tp_mg* m, size_t l, const double* b, double* u, const PcgState* st,
+                            hipStream_t s) {
+    const Plan& plan = *m->plan;
+    const MgLevel& L = m->lv[l];
+    double* Lt = static_cast<double*>(L.t);
+    const unsigned grid = static_cast<unsigned>(L.G.ncells);
+    if (l + 1 == m->lv.size()) {
+        const unsigned cg = static_cast<unsigned>((m->n0 + 255) / 256);
+        hipLaunchKernelGGL((k_mg_coarse<N, double>), dim3(cg), dim3(256), 0, s, m->coarse_inv, b, u, m->n0,
+                           L.G.offset, L.G.logB, st);
+        return check_launch("coarse solve");
+    }
+    FaceRef<N, double> F;
+    {
+        Pair<N, double> R;
+        sipg_tables<N, double>(plan, false, R, F);
+    }
+    const double* tabA = reinterpret_cast<const double*>(eo_table(plan, N, EO_APPLY_A, 0));
+    const TI* tabS = reinterpret_cast<const TI*>(eo_table(plan, N, EO_INV, sizeof(TI) == 8 ? 0 : 1));
+    ProlTab<N> P, PT;
+    for (int i = 0; i < N * N; ++i) P.p[0][i] = plan.ref[N].P0[i], P.p[1][i] = plan.ref[N].P1[i];
+    for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) PT.p[c][i * N + j] = P.p[c][j * N + i];
+    auto step = [&](const double* from, double* to, int j) {
+        hipLaunchKernelGGL((k_mg_smooth_wave<N, TI, VP>), dim3(grid), dim3(64), 0, s, b, from, to, L.G, tabA, F,
+                           tabS, m->omega[j], st);
+    };
+    hipLaunchKernelGGL((k_mg_jacobi0_wave<N, TI, VP>), dim3(grid), dim3(64), 0, s, b, u, L.G, tabS, m->omega[0], st);
+    step(u, Lt, 1);
+    step(Lt, u, 2);
+    const MgLevel& C = m->lv[l + 1];
+    double* Cb = static_cast<double*>(C.b);
+    double* Cu = static_cast<double*>(C.u);
+    hipLaunchKernelGGL((k_mg_apply_wave<N, VP>), dim3(grid), dim3(64), 0, s, u, Lt, L.G, tabA, F, st);
+    hipLaunchKernelGGL((k_mg_restrict_wave<N, VP>), dim3(static_cast<unsigned>(C.G.ncells)), dim3(64), 0, s, b, Lt,
+                       Cb, L.G, C.G, PT, st);
+    tp_status stt = check_launch("level transfer");
+    if (stt != TP_OK) return stt;
+    stt = vcycle_level_wave<N, TI, VP>(m, l + 1, Cb, Cu, st, s);
+    if (stt != TP_OK) return stt;
+    hipLaunchKernelGGL((k_mg_prolong_wave<N, VP>), dim3(grid), dim3(64), 0, s, Cu, u, Lt, L.G, C.G, P, st);
+    step(Lt, u, 0);
+    step(u, Lt, 1);
+    step(Lt, u, 2);
+    return check_launch("smoothing");
+}
+
 template <typename TI, typename TS>
 tp_status vcycle_dispatch(const tp_mg* m, const TS* b, TS* u, const PcgState* st, hipStream_t s) {
     switch (m->n) {
@@ -423,7 +738,21 @@ tp_status vcycle_dispatch(const tp_mg* m, const TS* b, TS* u, const PcgState* st
                                                       : vcycle_level<4, TI, false, TS>(m, 0, b, u, st, s);
         default: break;
     }
-    return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
+    if constexpr (std::is_same<TS, double>::value) {
+        // 16-byte pencil accesses when the caller's finest b and u allow them
+        // (the level vectors are allocation-aligned)
+        const bool vp = reinterpret_cast<uintptr_t>(b) % 16 == 0 && reinterpret_cast<uintptr_t>(u) % 16 == 0;
+        switch (m->n) {
+            case 5: return vcycle_level_wave<5, TI, false>(m, 0, b, u, st, s);
+            case 6: return vp ? vcycle_level_wave<6, TI, true>(m, 0, b, u, st, s)
+                              : vcycle_level_wave<6, TI, false>(m, 0, b, u, st, s);
+            case 7: return vcycle_level_wave<7, TI, false>(m, 0, b, u, st, s);
+            case 8: return vp ? vcycle_level_wave<8, TI, true>(m, 0, b, u, st, s)
+                              : vcycle_level_wave<8, TI, false>(m, 0, b, u, st, s);
+            default: break;
+        }
+    }
+    return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 8, with FP32 level storage n <= 4");
 }
 
 template <int N>
@@ -449,21 +778,27 @@ tp_status coarse_probe_n(const tp_mg* m, std::vector<double>& A) {
         st = launch_fill(pu, L.elems, TP_F64, 0, true, nullptr);
         if (st != TP_OK) break;
         const double one = 1.0;
-        const int64_t pos = L.G.offset + block_base(j / N3, 6, N3) + ((j % N3) << 6);
+        const int64_t pos = L.G.offset + block_base(j / N3, L.G.logB, N3) + ((j % N3) << L.G.logB);
         e = hipMemcpy(pu + pos, &one, sizeof(double), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             st = hip_error(e, "coarse probe");
             break;
         }
-        hipLaunchKernelGGL((k_mg_apply<N, false, double>), dim3(grid), dim3(64), 0, nullptr, pu, pt, L.G, R, F,
-                           static_cast<const PcgState*>(nullptr));
+        if constexpr (N <= kLaneMaxN)
+            hipLaunchKernelGGL((k_mg_apply<N, false, double>), dim3(grid), dim3(64), 0, nullptr, pu, pt, L.G, R, F,
+                               static_cast<const PcgState*>(nullptr));
+        else
+            hipLaunchKernelGGL((k_mg_apply_wave<N, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0,
+                               nullptr, pu, pt, L.G, reinterpret_cast<const double*>(eo_table(plan, N, EO_APPLY_A, 0)),
+                               F, static_cast<const PcgState*>(nullptr));
         e = hipMemcpy(col.data(), pt, vb, hipMemcpyDeviceToHost);
         if (e != hipSuccess) {
             st = hip_error(e, "coarse probe");
             break;
         }
         for (int64_t i = 0; i < n0; ++i)
-            A[i * n0 + j] = col[static_cast<size_t>(L.G.offset + block_base(i / N3, 6, N3) + ((i % N3) << 6))];
+            A[i * n0 + j] =
+                col[static_cast<size_t>(L.G.offset + block_base(i / N3, L.G.logB, N3) + ((i % N3) << L.G.logB))];
     }
     if (pu) (void)hipFree(pu);
     if (pt) (void)hipFree(pt);
@@ -537,8 +872,21 @@ tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const void* b, bool b3
             if (b32) hipLaunchKernelGGL((k_mg_dot<4, float>), dim3(grid), dim3(64), 0, s, a, bf, L.G, part, ps);
             else hipLaunchKernelGGL((k_mg_dot<4, double>), dim3(grid), dim3(64), 0, s, a, bd, L.G, part, ps);
             break;
-        default: return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
+        case 5: hipLaunchKernelGGL((k_mg_dot_wave<5, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0, s,
+                                   a, bd, L.G, part, ps);
+            break;
+        case 6: hipLaunchKernelGGL((k_mg_dot_wave<6, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0, s,
+                                   a, bd, L.G, part, ps);
+            break;
+        case 7: hipLaunchKernelGGL((k_mg_dot_wave<7, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0, s,
+                                   a, bd, L.G, part, ps);
+            break;
+        case 8: hipLaunchKernelGGL((k_mg_dot_wave<8, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0, s,
+                                   a, bd, L.G, part, ps);
+            break;
+        default: return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 8");
     }
+    if (m->n > kLaneMaxN && b32) return set_error(TP_ERR_UNSUPPORTED, "FP32 level storage needs n <= 4");
     return check_launch("dot");
 }
 
@@ -562,8 +910,14 @@ tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out) {
         return set_error(TP_ERR_UNSUPPORTED, "multigrid level vectors are stored in FP64 or FP32");
     if (!plan->mesh) return set_error(TP_ERR_UNSUPPORTED, "multigrid needs a mesh plan");
     const GroupInfo& g = plan->groups[0];
-    if (g.n > kLaneMaxN) return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
-    if (g.logB != 6) return set_error(TP_ERR_UNSUPPORTED, "multigrid needs the layout B = 64");
+    if (g.n <= kLaneMaxN && g.logB != 6)
+        return set_error(TP_ERR_UNSUPPORTED, "multigrid needs the layout B = 64 for n <= 4");
+    if (g.n > kLaneMaxN && g.logB != 0)
+        return set_error(TP_ERR_UNSUPPORTED, "multigrid needs the layout B = 1 for n >= 5");
+    if (g.n > kLaneMaxN && plan->basis == TP_BASIS_HERMITE)
+        return set_error(TP_ERR_UNSUPPORTED, "multigrid in the Hermite-type basis supports n = 4");
+    if (g.n > kLaneMaxN && storage != TP_F64)
+        return set_error(TP_ERR_UNSUPPORTED, "FP32 level storage needs n <= 4");
     if (plan->inverse_op != TP_OP_CELL || plan->factor_mode != TP_FACTOR_SCALED)
         return set_error(TP_ERR_STATE, "multigrid needs tp_setup_inverse(TP_OP_CELL, TP_FACTOR_SCALED) first");
     tp_mg* m = new (std::nothrow) tp_mg();
@@ -583,14 +937,15 @@ tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out) {
         MgLevel L;
         L.G.ncells = int64_t(mx) * my * mz;
         L.G.offset = 0;
-        L.G.logB = 6;
+        L.G.logB = g.logB;
         L.G.mx = mx;
         L.G.my = my;
         L.G.mz = mz;
         L.G.sx = hy * hz / hx;
         L.G.sy = hx * hz / hy;
         L.G.sz = hx * hy / hz;
-        L.elems = (L.G.ncells + 63) / 64 * n3 * 64;
+        const int64_t B = int64_t(1) << g.logB;
+        L.elems = (L.G.ncells + B - 1) / B * n3 * B;
         const size_t vb = static_cast<size_t>(L.elems) * es;
         if (e == hipSuccess) e = hipMalloc(&L.t, vb);
         // the finest level works on the caller's b and u, except with FP32
@@ -644,7 +999,11 @@ tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out) {
         switch (g.n) {
             case 2: st = coarse_probe_n<2>(m, A); break;
             case 3: st = coarse_probe_n<3>(m, A); break;
-            default: st = coarse_probe_n<4>(m, A); break;
+            case 4: st = coarse_probe_n<4>(m, A); break;
+            case 5: st = coarse_probe_n<5>(m, A); break;
+            case 6: st = coarse_probe_n<6>(m, A); break;
+            case 7: st = coarse_probe_n<7>(m, A); break;
+            default: st = coarse_probe_n<8>(m, A); break;
         }
         if (st == TP_OK && !spd_inverse(m->n0, A, inv))
             st = set_error(TP_ERR_NOT_SPD, "the coarsest level operator is not positive definite");

@@ -518,6 +518,81 @@ Eig<N, T> mesh_eig(const RefData& ref) {
 
 using namespace tpfdm;
 
+// The same two residual kernels for n >= 5, one cell per wave (lane (a, b)
+// owns the z-pencil (a, b, 0..n-1); per-cell partials).
+template <int N, bool VP>
+__global__ __launch_bounds__(64) void k_pcg_start_res_wave(const double* __restrict__ b,
+                                                           const double* __restrict__ q,
+                                                           const double* __restrict__ x0, double* __restrict__ x,
+                                                           double* __restrict__ r, MeshArgs G,
+                                                           double* __restrict__ part, int64_t count) {
+    const int64_t c = blockIdx.x;
+    const Pencil<N> pc(1);
+    const int lb = G.logB;
+    double rr = 0.0, bb = 0.0;
+    if (pc.act) {
+        const int64_t pb = G.offset + block_base(c, lb, N * N * N) +
+                           (static_cast<int64_t>((pc.pa * N + pc.pb) * N) << lb);
+        double bv[N], rv[N], xv[N];
+        pencil_load<N, VP>(bv, b + pb, lb);
+        if (q) {
+            double qv[N];
+            pencil_load<N, VP>(qv, q + pb, lb);
+            pencil_load<N, VP>(xv, x0 + pb, lb);
+#pragma unroll
+            for (int k = 0; k < N; ++k) rv[k] = bv[k] - qv[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < N; ++k) rv[k] = bv[k], xv[k] = 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            rr = fma(rv[k], rv[k], rr);
+            bb = fma(bv[k], bv[k], bb);
+        }
+        pencil_store<N, VP>(x + pb, xv, lb);
+        pencil_store<N, VP>(r + pb, rv, lb);
+    }
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    if (threadIdx.x == 0) {
+        part[count + c] = rr;
+        part[2 * count + c] = bb;
+    }
+}
+
+template <int N, bool VP>
+__global__ __launch_bounds__(64) void k_pcg_axpy_wave(double* __restrict__ x, double* __restrict__ r,
+                                                      const double* __restrict__ p, const double* __restrict__ q,
+                                                      MeshArgs G, const PcgState* __restrict__ st,
+                                                      double* __restrict__ part, int64_t count) {
+    if (st->done) return;
+    const double alpha = st->alpha;
+    const int64_t c = blockIdx.x;
+    const Pencil<N> pc(1);
+    const int lb = G.logB;
+    double rr = 0.0;
+    if (pc.act) {
+        const int64_t pb = G.offset + block_base(c, lb, N * N * N) +
+                           (static_cast<int64_t>((pc.pa * N + pc.pb) * N) << lb);
+        double xv[N], rv[N], pv[N], qv[N];
+        pencil_load<N, VP>(xv, x + pb, lb);
+        pencil_load<N, VP>(rv, r + pb, lb);
+        pencil_load<N, VP>(pv, p + pb, lb);
+        pencil_load<N, VP>(qv, q + pb, lb);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            xv[k] = fma(alpha, pv[k], xv[k]);
+            rv[k] = fma(-alpha, qv[k], rv[k]);
+            rr = fma(rv[k], rv[k], rr);
+        }
+        pencil_store<N, VP>(x + pb, xv, lb);
+        pencil_store<N, VP>(r + pb, rv, lb);
+    }
+    rr = wave_sum(rr);
+    if (threadIdx.x == 0) part[count + c] = rr;
+}
+
 // Workspace of one solver instance (plan-sized vectors and partials).
 struct tp_pcg {
     tp_plan* plan = nullptr;
@@ -605,7 +680,18 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                 if (e != hipSuccess) return hip_error(e, "PCG start");
             }
         } else {
-            return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 4");
+            if (vp)
+                hipLaunchKernelGGL((k_pcg_start_res_wave<N, true>), dim3(nwg), dim3(64), 0, stream, b,
+                                   x_zero ? nullptr : s->q, x, s->xw, s->r, G, s->part, cnt);
+            else
+                hipLaunchKernelGGL((k_pcg_start_res_wave<N, false>), dim3(nwg), dim3(64), 0, stream, b,
+                                   x_zero ? nullptr : s->q, x, s->xw, s->r, G, s->part, cnt);
+            tp_status st = mg_enqueue_vcycle(s->mg, s->r, s->z, nullptr, f32, stream);
+            if (st == TP_OK) st = mg_enqueue_dot(s->mg, s->r, s->z, false, s->part, nullptr, stream);
+            if (st != TP_OK) return st;
+            const hipError_t e = hipMemcpyAsync(s->p, s->z, static_cast<size_t>(s->elems) * sizeof(double),
+                                                hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return hip_error(e, "PCG start");
         }
     } else if constexpr (kLane)
         hipLaunchKernelGGL((k_pcg_start<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q, x,
@@ -658,7 +744,16 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                                        tabA, F, s->st, s->part);
                 hipLaunchKernelGGL(k_pcg_reduce_alpha, dim3(1), dim3(256), 0, cs, s->part, cnt, s->st);
                 if (s->mg) {
-                    if constexpr (kLane) {
+                    if constexpr (!kLane) {
+                        if (vp)
+                            hipLaunchKernelGGL((k_pcg_axpy_wave<N, true>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r,
+                                               s->p, s->q, G, s->st, s->part, cnt);
+                        else
+                            hipLaunchKernelGGL((k_pcg_axpy_wave<N, false>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r,
+                                               s->p, s->q, G, s->st, s->part, cnt);
+                        (void)mg_enqueue_vcycle(s->mg, s->r, s->z, s->st, f32, cs);
+                        (void)mg_enqueue_dot(s->mg, s->r, s->z, false, s->part, s->st, cs);
+                    } else {
                         hipLaunchKernelGGL((k_pcg_axpy<N, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->p, s->q,
                                            G, s->st, s->part, cnt);
                         const bool z32 = mg_storage(s->mg) == TP_F32;

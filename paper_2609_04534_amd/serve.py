@@ -9,9 +9,10 @@ kernels of different solves overlap on the GPU.  A request is admitted (in
 arrival order) as soon as a solver slot for its mesh class is free or the
 device-memory budget has room for a new one; finished solves return their
 slot to a per-class free pool, and idle slots of other classes are released
-when a new class needs the memory.  With multigrid on, the solves of degree
-p <= 3 are preconditioned by one V-cycle per iteration (tp_mg_*), the others
-by block-Jacobi.  Marshalling and scheduling only: every step of a solve runs
+when a new class needs the memory.  With multigrid on, the solves whose
+coarsest level fits the dense coarse solve (uses_multigrid) are
+preconditioned by one V-cycle per iteration (tp_mg_*), the others by
+block-Jacobi.  Marshalling and scheduling only: every step of a solve runs
 in the library's kernels.
 """
 from __future__ import annotations
@@ -65,9 +66,14 @@ class _Slot:
         self.b = self.x = None
 
 
-def uses_multigrid(p: int) -> bool:
-    """The V-cycle covers degrees with one cell per lane (p <= 3)."""
-    return p <= 3
+def uses_multigrid(p: int, m: int) -> bool:
+    """The V-cycle covers every degree whose coarsest level (the odd part of
+    m per side) has at most 2048 unknowns for its dense solve: every m of the
+    mix for p <= 3, powers of two for p = 7."""
+    odd = m
+    while odd % 2 == 0:
+        odd //= 2
+    return odd ** 3 * (p + 1) ** 3 <= 2048
 
 
 def mg_bytes(p: int, m: int) -> int:
@@ -75,9 +81,10 @@ def mg_bytes(p: int, m: int) -> int:
     every level plus right-hand side and correction below the finest (the
     shared coarse inverse is not counted)."""
     n3 = (p + 1) ** 3
+    B = tpfdm.default_layout_B(p + 1)
     total, ml, first = 0, m, True
     while True:
-        E = (ml ** 3 + 63) // 64 * 64 * n3
+        E = (ml ** 3 + B - 1) // B * B * n3
         total += (1 if first else 3) * E * 8
         first = False
         if ml % 2:
@@ -140,7 +147,7 @@ class Server:
         key = (p, m)
         if self.free.get(key):
             return self.free[key].pop()
-        mgc = self._mg(p)
+        mgc = self._mg(p, m)
         need = slot_bytes(self._plan(p, m), p, m, mgc)
         for k in list(self.free):
             while self.used + need > self.budget and self.free[k]:
@@ -152,18 +159,18 @@ class Server:
         self.used += need
         return _Slot(self._plan(p, m), p, m, mgc)
 
-    def _mg(self, p):
-        return self.multigrid and uses_multigrid(p)
+    def _mg(self, p, m):
+        return self.multigrid and uses_multigrid(p, m)
 
     def _admit(self, req, now):
         """True when the request leaves the queue: admitted, or rejected
         because its slot alone needs more than the whole budget (it could
         never run, and first-in-first-out admission would stall behind it)."""
-        if class_slot_bytes(req.p, req.m, self._mg(req.p)) > self.budget:
+        if class_slot_bytes(req.p, req.m, self._mg(req.p, req.m)) > self.budget:
             req.rejected = True
             req.start = req.done = now
             req.summary = {"status": "rejected", "converged": False, "iterations": 0,
-                           "reason": f"slot of {class_slot_bytes(req.p, req.m, self._mg(req.p))} bytes exceeds "
+                           "reason": f"slot of {class_slot_bytes(req.p, req.m, self._mg(req.p, req.m))} bytes exceeds "
                                      f"the budget of {self.budget} bytes"}
             self.rejected += 1
             return True

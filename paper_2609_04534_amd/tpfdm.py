@@ -89,6 +89,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libtpfdm.so not found at {path}; run `python -m paper_2609_04534_amd.build`")
+    # torch's ROCm libraries are loaded first, so that the library's HIP
+    # runtime finds the HSA runtime the tensors it is handed come from
+    # (loaded the other way round, the library saw no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {

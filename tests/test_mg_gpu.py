@@ -260,8 +260,9 @@ def test_mg_errors():
         with pytest.raises(tpfdm.TpfdmError) as e:
             tpfdm.MG(plan)
         assert e.value.status == -2
-    # n >= 5
-    with _cube_plan(5, 2) as plan:
+    # n >= 5 in the Hermite-type basis
+    with tpfdm.Plan.mesh(6, (2, 2, 2), (0.5,) * 3, basis=tpfdm.BASIS_HERMITE) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
         with pytest.raises(tpfdm.TpfdmError) as e:
             tpfdm.MG(plan)
         assert e.value.status == -2
@@ -359,3 +360,55 @@ def test_mg_pcg_fp32_storage_reaches_the_oracle_residual(p, m, inner):
     assert t64 <= 2 * rtol and t32 <= 2 * rtol
     xs = spl.spsolve(A.tocsc(), b)
     assert np.linalg.norm(x32 - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+# ------------------------------------------------------------------ n >= 5 (one cell per wave)
+@pytest.mark.parametrize("p,m", [(4, 4), (6, 2), (7, 2)])
+def test_vcycle_wave_degrees_match_oracle(p, m):
+    """The V-cycle for n >= 5 (wave kernels, layout B = 1) element by element
+    against the oracle's hierarchy."""
+    torch = _torch()
+    H = _hierarchy(p, m)
+    nd = m ** 3 * (p + 1) ** 3
+    b = _rhs(nd, 70 + p + m)
+    xo = H.vcycle(b)
+    with _cube_plan(p, m) as plan, tpfdm.MG(plan) as V:
+        bb = to_blocked(plan, b, tpfdm.F64)
+        bx = torch.full_like(bb, float("nan"))
+        V.vcycle(bb, bx)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    err = np.abs(x - xo).max() / np.abs(xo).max()
+    print(f"p={p} m={m} levels={H.ms} V-cycle rel err {err:.2e}")
+    assert err <= 1e-11
+
+
+@pytest.mark.parametrize("p,m,inner", [(4, 4, tpfdm.F64), (7, 2, tpfdm.F64), (7, 2, tpfdm.F32)])
+def test_mg_pcg_wave_degrees_iteration_count(p, m, inner):
+    """MG-PCG for n >= 5 takes the oracle's MG-PCG iteration count (+-1) and
+    reaches its true residual."""
+    torch = _torch()
+    H = _hierarchy(p, m)
+    b = _rhs(H.A[0].shape[0], 80 + p + m)
+    rtol = 1e-10
+    _, ito, _ = sipg.pcg(H.A[0], b, H.vcycle, rtol, 200)
+    with _cube_plan(p, m) as plan, tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+        solver.set_multigrid(V)
+        bb = to_blocked(plan, b, tpfdm.F64)
+        bx = torch.full_like(bb, float("nan"))
+        s = solver.solve(bb, bx, inner=inner, rtol=rtol, maxit=200, check_every=4)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    true = np.linalg.norm(b - H.A[0] @ x) / np.linalg.norm(b)
+    print(f"p={p} m={m} inner={tpfdm.DTYPE_NAMES[inner]} oracle_iters={ito} {s} true relres {true:.2e}")
+    assert s["converged"] and abs(s["iterations"] - ito) <= 1
+    assert true <= 2 * rtol
+
+
+def test_mg_wave_rejects_what_it_does_not_cover():
+    with _cube_plan(7, 3) as plan:   # coarsest level 27 cells of 512 unknowns
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            tpfdm.MG(plan)
+        assert e.value.status == -2
+    with _cube_plan(5, 2) as plan:
+        with pytest.raises(tpfdm.TpfdmError) as e:
+            tpfdm.MG(plan, storage=tpfdm.F32)
+        assert e.value.status == -2
