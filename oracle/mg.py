@@ -22,6 +22,15 @@ Paper passages followed:
 Levels of an m-cell-per-side unit cube: m, m/2, ... while even; the
 coarsest has the odd part of m cells per side (1 for powers of two).  Every
 level is rediscretized with its own cell size (and penalty).
+
+Optional degree-coarsened coarsest level (``coarse_degree``; a reading, not
+the paper's configuration, whose meshes halve down to one cell): one more
+level on the coarsest cells with the polynomial degree lowered to
+``coarse_degree``, reached by the cellwise embedding E of Q_pc into Q_p
+(Sec. 5's level transfers with the degree in place of the cell size), with
+the Galerkin operator E^T A E.  For nested spaces with exact quadrature this
+is the degree-pc SIPG form with the fine level's penalty C p (p+1) / h, which
+the pins check.
 Pins (tests/test_oracle_mg.py): the Chebyshev error polynomial of
 eq. (chebyshev_error_polynomial) in closed form, exact prolongation of
 polynomials, P^T M_fine P = M_coarse, the smoother's error propagator, the
@@ -94,12 +103,30 @@ def prolongation(p: int, mc, bname: str = sipg.LAGRANGE) -> sp.csr_matrix:
                          shape=(N, mc[0] * mc[1] * mc[2] * n3)).tocsr()
 
 
+def degree_embedding_1d(p: int, pc: int) -> np.ndarray:
+    """E[i, j] = l^pc_j(x^p_i): the degree-pc Lagrange function j (Gauss-Lobatto
+    nodes of [0, 1]) at node i of the degree-p basis; E c holds the degree-p
+    nodal values of the degree-pc polynomial with nodal values c."""
+    return basis.lagrange_values(basis.gll_nodes(pc), basis.gll_nodes(p))
+
+
+def degree_embedding(p: int, pc: int, cells) -> sp.csr_matrix:
+    """Cellwise embedding of Q_pc into Q_p on the same cells (canonical
+    orders): block diagonal, each block the Kronecker cube of the 1D one."""
+    E1 = degree_embedding_1d(p, pc)
+    blk = sp.csr_matrix(np.kron(np.kron(E1, E1), E1))
+    ncell = int(np.prod(cells))
+    return sp.block_diag([blk] * ncell, format="csr")
+
+
 class Hierarchy:
     """Level operators, transfers and the coarse inverse of a unit cube with
     m cells per side, or of a box with cells m = (mx, my, mz) of lengths h
-    (each level doubles the lengths)."""
+    (each level doubles the lengths).  With coarse_degree (Lagrange basis,
+    1 <= coarse_degree < p) one more level of that degree on the coarsest
+    cells, with the Galerkin operator E^T A E, is the one solved exactly."""
 
-    def __init__(self, p: int, m, C: float = 2.0, bname: str = sipg.LAGRANGE, h=None):
+    def __init__(self, p: int, m, C: float = 2.0, bname: str = sipg.LAGRANGE, h=None, coarse_degree=None):
         self.p = p
         self.bname = bname
         self.ms = levels(m)
@@ -112,6 +139,17 @@ class Hierarchy:
             self.hs = [(1.0 / ml,) * 3 for ml in self.ms]
         self.A = [sipg.assemble(p, c, hl, sipg.FULL, C, bname) for c, hl in zip(self.cells, self.hs)]
         self.P = [prolongation(p, self.ms[k + 1], bname) for k in range(len(self.ms) - 1)]
+        self.degrees = [p] * len(self.ms)
+        if coarse_degree is not None:
+            if bname != sipg.LAGRANGE or not 1 <= coarse_degree < p:
+                raise ValueError("coarse_degree needs the Lagrange basis and 1 <= coarse_degree < p")
+            E = degree_embedding(p, coarse_degree, self.cells[-1])
+            self.ms.append(self.ms[-1])
+            self.cells.append(self.cells[-1])
+            self.hs.append(self.hs[-1])
+            self.A.append((E.T @ self.A[-1] @ E).tocsr())
+            self.P.append(E)
+            self.degrees.append(coarse_degree)
         self.coarse = np.linalg.inv(self.A[-1].toarray())
         self.omega = chebyshev_weights()
         self.C = C

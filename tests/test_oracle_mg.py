@@ -125,3 +125,81 @@ def test_box_hierarchy_reduces_to_the_cube_and_is_symmetric():
     Mc = sipg.mass(2, H.cells[1], H.hs[1])
     P = H.P[0]
     assert np.abs((P.T @ Mf @ P - Mc).toarray()).max() <= 1e-13 * np.abs(Mc.toarray()).max()
+
+
+# ------------------------------------------------ degree-coarsened coarsest level
+@pytest.mark.parametrize("p", [2, 3, 5, 7])
+def test_degree_embedding_reproduces_trilinear_functions(p):
+    """E maps the degree-1 nodal values of q in Q_1 to its degree-p nodal
+    values (the degree-1 nodes are the cell's end points 0 and 1)."""
+    rng = np.random.default_rng(20 + p)
+    fac = [rng.uniform(-1, 1, 2) for _ in range(3)]
+    q = lambda x: [P.polyval(x, f) for f in fac]
+    xc, xf = np.array([0.0, 1.0]), basis.gll_nodes(p)
+    coarse = np.einsum("i,j,k->ijk", *q(xc)).reshape(-1)
+    fine = np.einsum("i,j,k->ijk", *q(xf)).reshape(-1)
+    E = mg.degree_embedding(p, 1, (1, 1, 1))
+    assert np.max(np.abs(E @ coarse - fine)) < 1e-14
+    # a partition of unity per direction, and the end nodes are kept
+    E1 = mg.degree_embedding_1d(p, 1)
+    assert np.max(np.abs(E1.sum(axis=1) - 1.0)) < 1e-15
+    assert np.allclose(E1[0], [1.0, 0.0]) and np.allclose(E1[-1], [0.0, 1.0])
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_degree_embedding_preserves_the_mass(p):
+    """Nested spaces with exact quadrature: E^T M_p E = M_1 on the same cells."""
+    cells, h = (2, 3, 1), (0.5, 1.0 / 3, 0.7)
+    E = mg.degree_embedding(p, 1, cells)
+    Mf, Mc = sipg.mass(p, cells, h), sipg.mass(1, cells, h)
+    assert np.abs((E.T @ Mf @ E - Mc).toarray()).max() <= 1e-14 * np.abs(Mc.toarray()).max()
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_galerkin_degree_level_is_the_degree_one_form_with_the_fine_penalty(p):
+    """E^T A_p E is the degree-1 SIPG operator assembled with the penalty of
+    degree p: sigma = C p (p+1) / h = C' 1 (1+1) / h for C' = C p (p+1) / 2
+    (all integrals exact for the embedded functions)."""
+    cells, h, C = (3, 2, 1), (1.0 / 3, 0.5, 0.8), 2.0
+    H = mg.Hierarchy(p, cells, C=C, h=h, coarse_degree=1)
+    assert H.degrees == [p, 1] and H.cells == [cells, cells]
+    A1 = sipg.assemble(1, cells, h, sipg.FULL, C * p * (p + 1) / 2.0)
+    assert np.abs((H.A[1] - A1).toarray()).max() <= 1e-12 * np.abs(A1.toarray()).max()
+    # rediscretizing at degree 1 with its own penalty is a different operator
+    A1own = sipg.assemble(1, cells, h, sipg.FULL, C)
+    assert np.abs((H.A[1] - A1own).toarray()).max() > 1e-3 * np.abs(A1.toarray()).max()
+
+
+def test_degree_coarsened_vcycle_is_symmetric_and_converges():
+    """The V-cycle with the degree-1 coarsest level: symmetric and positive,
+    and CG with it converges in a number of iterations of the same order as
+    with the exact coarse solve of the degree-p coarsest level."""
+    p, m = 2, 6
+    H = mg.Hierarchy(p, m, coarse_degree=1)
+    assert H.cells == [(6,) * 3, (3,) * 3, (3,) * 3] and H.degrees == [2, 2, 1]
+    rng = np.random.default_rng(5)
+    a, c = rng.standard_normal((2, H.A[0].shape[0]))
+    Va, Vc = H.vcycle(a), H.vcycle(c)
+    assert abs(Va @ c - a @ Vc) <= 1e-11 * np.linalg.norm(Va) * np.linalg.norm(c)
+    assert Va @ a > 0
+    b = rng.uniform(-1, 1, H.A[0].shape[0])
+    _, it_deg, rel = sipg.pcg(H.A[0], b, H.vcycle, 1e-10, 200)
+    _, it_exact, _ = sipg.pcg(H.A[0], b, mg.Hierarchy(p, m).vcycle, 1e-10, 200)
+    print(f"p={p} m={m} iterations: degree-coarsened {it_deg}, exact coarse {it_exact}")
+    assert rel <= 1e-10 and it_deg <= it_exact + 6
+
+
+def test_degree_coarsening_planted_transpose_is_caught():
+    """A plausible slip (the embedding's transpose layout, i.e. kron order
+    reversed per direction with swapped factors) must break the Galerkin pin."""
+    p, cells, h = 2, (2, 1, 1), (0.5, 1.0, 1.0)
+    E1 = mg.degree_embedding_1d(p, 1)
+    bad = sp_block([np.kron(np.kron(E1[::-1], E1), E1)] * 2)
+    A = sipg.assemble(p, cells, h)
+    A1 = sipg.assemble(1, cells, h, sipg.FULL, 2.0 * p * (p + 1) / 2.0)
+    assert np.abs((bad.T @ A @ bad - A1).toarray()).max() > 1e-3 * np.abs(A1.toarray()).max()
+
+
+def sp_block(blocks):
+    import scipy.sparse as sp
+    return sp.block_diag([sp.csr_matrix(b) for b in blocks], format="csr")
