@@ -679,17 +679,18 @@ def run_sipg(args, stream):
 PCG_SUITE = [(p, m) for p in (2, 3) for m in (8, 16, 24, 32, 48)] + [(7, m) for m in (8, 16, 24)]
 # Larger meshes timed with the multigrid preconditioner only (block-Jacobi
 # needs over a thousand iterations there).
-PCG_MG_ONLY = [(3, 64), (2, 96)]
+PCG_MG_ONLY = [(3, 64), (2, 96), (7, 32), (7, 48)]
 # Degree-3 meshes in the Hermite-type basis (two-layer face access), MG only.
 PCG_HERMITE = [(3, 24), (3, 48), (3, 64)]
 
 
 def run_pcg(args, stream):
-    """Per mesh, preconditioner (block-Jacobi; one multigrid V-cycle for
-    p <= 3) and its precision: wall latency of whole solves (launch to host
-    summary), p50 / p99 over repeated solves, iterations."""
+    """Per mesh, preconditioner (block-Jacobi; one multigrid V-cycle where
+    the serving loop uses one) and its precision: wall latency of whole
+    solves (launch to host summary), p50 / p99 over repeated solves,
+    iterations."""
     import torch
-    from paper_2609_04534_amd import tpfdm, workloads
+    from paper_2609_04534_amd import serve, tpfdm, workloads
     suite = [(p, m, "lagrange") for p, m in PCG_SUITE + PCG_MG_ONLY] + [(p, m, "hermite") for p, m in PCG_HERMITE]
     if args.pcg_mesh:
         f = args.pcg_mesh.split(",")
@@ -703,7 +704,7 @@ def run_pcg(args, stream):
         plan.pack(torch.from_numpy(mesh.u).cuda(), b)
         x = torch.empty_like(b)
         solver = tpfdm.PCG(plan)
-        mg = tpfdm.MG(plan) if p <= 3 else None
+        mg = tpfdm.MG(plan) if serve.uses_multigrid(p, m) and basis == "lagrange" or p <= 3 else None
         preconds = (("mg",) if (p, m) in PCG_MG_ONLY or basis == "hermite"
                     else ("block_jacobi", "mg") if mg else ("block_jacobi",))
         for precond in preconds:
@@ -831,12 +832,13 @@ def run_mg_paper(args, stream):
 # Degree 7 is drawn at m = 8 and 16 only: with block-Jacobi alone a degree-7
 # solve at m = 32 or 48 runs for seconds, longer than a bounded run allows.
 SERVE_RATES = [50, 200, 500, 2000]
-SERVE_MIX = [(p, m) for p in (2, 3) for m in (8, 16, 24, 32, 48)] + [(7, 8), (7, 16)]
+SERVE_MIX = [(p, m) for p in (2, 3, 7) for m in (8, 16, 24, 32, 48)]
 
 
 def run_serve(args):
-    """The serving mix at every rate, first with the V-cycle preconditioner
-    for p <= 3 (block-Jacobi for p = 7), then with block-Jacobi throughout."""
+    """The 15-class serving mix at every rate with the V-cycle preconditioner
+    (every class), then with block-Jacobi throughout at the two lower rates
+    (its degree-7 solves on 48^3 cells take seconds each)."""
     import torch
     from paper_2609_04534_amd import serve, tpfdm
     for multigrid in (True, False):
@@ -845,8 +847,9 @@ def run_serve(args):
         # before the measured runs (one request of every class)
         warm = [serve.poisson_requests(rate=1e6, count=1, mix=[c], seed=i)[0] for i, c in enumerate(SERVE_MIX)]
         srv.run(warm)
+        _log(f"serve warm-up done (multigrid={multigrid})")
         del warm
-        for rate in SERVE_RATES:
+        for rate in (SERVE_RATES if multigrid else SERVE_RATES[:2]):
             count = int(min(120, max(20, rate * 1.0)))
             reqs = serve.poisson_requests(rate=float(rate), count=count, mix=SERVE_MIX, seed=rate)
             srv.max_concurrent = 0

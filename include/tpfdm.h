@@ -422,10 +422,14 @@ tp_status tp_pcg_poll(tp_pcg* pcg, tp_pcg_summary* summary);
  * (eq. (chebyshev_weights), eq. (chebyshev_richardson): three Richardson
  * updates with the cell-block fast-diagonalization inverse); transfers by
  * polynomial embedding into the eight children and its transpose; the
- * coarsest level (at most 2048 unknowns, else TP_ERR_UNSUPPORTED) solved
- * with a dense inverse assembled once by applying its operator to unit
- * vectors and kept for the life of the process (shared by hierarchies with
- * the same coarsest level).  Needs tp_setup_inverse(TP_OP_CELL,
+ * coarsest level (at most 2048 unknowns) solved with a dense inverse
+ * assembled once by applying its operator to unit vectors and kept for the
+ * life of the process (shared by hierarchies with the same coarsest level).
+ * For n >= 5, when the coarsest geometric level has more than 2048
+ * unknowns, one more level of degree 1 on the same cells (at most 256
+ * cells) is the one solved densely: reached by the cellwise embedding E of
+ * the trilinear polynomials into degree p and its transpose, with the
+ * Galerkin operator E^T A E.  A larger coarsest level is TP_ERR_UNSUPPORTED.  Needs tp_setup_inverse(TP_OP_CELL,
  * TP_FACTOR_SCALED) on the plan (TP_ERR_STATE).  tp_mg_create allocates the
  * level vectors (host-synchronous); the plan must outlive the object, and
  * every V-cycle (alone or inside a solve) returns TP_ERR_STATE unless the

@@ -533,6 +533,69 @@ __global__ __launch_bounds__(64) void k_mg_dot_wave(const double* __restrict__ a
     if (threadIdx.x == 0) part[c] = s;
 }
 
+// The degree-coarsened coarsest level (n >= 5, Lagrange basis), used when
+// the coarsest geometric level is too large for the dense solve: on the
+// same cells the degree drops to 1 (eight unknowns per cell in canonical
+// order, contiguous per cell), reached by the cellwise embedding
+// E = E1 (x) E1 (x) E1 of Q_1 into Q_p, E1[i] = (1 - x_i, x_i) at the nodes
+// x_i of [0, 1]; its operator is the Galerkin product E^T A E.
+template <int N>
+struct DegTab {
+    double e[N][2];
+};
+
+// bc = E^T (b - t), one thread per coarse unknown (cell, jx, jy, jz).
+template <int N>
+__global__ __launch_bounds__(64) void k_mg_deg_restrict(const double* __restrict__ b, const double* __restrict__ t,
+                                                        double* __restrict__ bc, MeshArgs G, DegTab<N> E,
+                                                        const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    if (idx >= G.ncells * 8) return;
+    const int64_t c = idx >> 3;
+    const int jx = static_cast<int>(idx >> 2) & 1, jy = static_cast<int>(idx >> 1) & 1, jz = static_cast<int>(idx) & 1;
+    const int64_t base = G.offset + block_base(c, G.logB, N * N * N);
+    double s = 0.0;
+    for (int a = 0; a < N; ++a)
+        for (int q = 0; q < N; ++q) {
+            const double wab = E.e[a][jx] * E.e[q][jy];
+            for (int k = 0; k < N; ++k) {
+                const int64_t o = base + (static_cast<int64_t>((a * N + q) * N + k) << G.logB);
+                s = fma(wab * E.e[k][jz], b[o] - t[o], s);
+            }
+        }
+    bc[idx] = s;
+}
+
+// uout = u + E uc, one thread per fine unknown.
+template <int N>
+__global__ __launch_bounds__(64) void k_mg_deg_prolong(const double* __restrict__ uc, const double* __restrict__ u,
+                                                       double* __restrict__ uout, MeshArgs G, DegTab<N> E,
+                                                       const PcgState* __restrict__ st) {
+    if (done_flag(st)) return;
+    constexpr int N3 = N * N * N;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * 64 + threadIdx.x;
+    if (idx >= G.ncells * N3) return;
+    const int64_t c = idx / N3;
+    const int q = static_cast<int>(idx % N3);
+    const int a = q / (N * N), y = (q / N) % N, k = q % N;
+    const double* v = uc + c * 8;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s = fma(E.e[a][j >> 2] * E.e[y][(j >> 1) & 1] * E.e[k][j & 1], v[j], s);
+    const int64_t o = G.offset + block_base(c, G.logB, N3) + (static_cast<int64_t>(q) << G.logB);
+    uout[o] = u[o] + s;
+}
+
+template <int N>
+DegTab<N> deg_table() {
+    DegTab<N> E;
+    double x[N];
+    gll_points(N, x);
+    for (int i = 0; i < N; ++i) E.e[i][0] = 1.0 - x[i], E.e[i][1] = x[i];
+    return E;
+}
+
 // dst = src converted element by element (the finest level's right-hand
 // side into the FP32-storage hierarchy, its result back to FP64).
 template <typename TD, typename TSRC>
@@ -594,11 +657,11 @@ bool spd_inverse(int64_t n, std::vector<double>& A, std::vector<double>& inv) {
 // Coarse inverses are shared by every hierarchy with the same coarsest level
 // on a device and kept until the process ends.
 struct CoarseKey {
-    int device, n, basis, mx, my, mz;
+    int device, n, basis, deg, mx, my, mz;
     double hx, hy, hz, C;
     bool operator<(const CoarseKey& o) const {
-        return std::tie(device, n, basis, mx, my, mz, hx, hy, hz, C) <
-               std::tie(o.device, o.n, o.basis, o.mx, o.my, o.mz, o.hx, o.hy, o.hz, o.C);
+        return std::tie(device, n, basis, deg, mx, my, mz, hx, hy, hz, C) <
+               std::tie(o.device, o.n, o.basis, o.deg, o.mx, o.my, o.mz, o.hx, o.hy, o.hz, o.C);
     }
 };
 static std::mutex g_coarse_mutex;
@@ -624,6 +687,11 @@ struct tp_mg {
     double omega[3] = {0.0, 0.0, 0.0};
     double* coarse_inv = nullptr;   // shared, not owned
     int64_t n0 = 0;
+    // degree-coarsened coarsest level (n >= 5): degree 1 on the last
+    // geometric level's cells, right-hand side and correction of n0 values
+    bool deg = false;
+    double* deg_b = nullptr;
+    double* deg_u = nullptr;
 };
 
 namespace {
@@ -686,7 +754,8 @@ tp_status vcycle_level_wave(const tp_mg* m, size_t l, const double* b, double* u
     const MgLevel& L = m->lv[l];
     double* Lt = static_cast<double*>(L.t);
     const unsigned grid = static_cast<unsigned>(L.G.ncells);
-    if (l + 1 == m->lv.size()) {
+    const bool last = l + 1 == m->lv.size();
+    if (last && !m->deg) {
         const unsigned cg = static_cast<unsigned>((m->n0 + 255) / 256);
         hipLaunchKernelGGL((k_mg_coarse<N, double>), dim3(cg), dim3(256), 0, s, m->coarse_inv, b, u, m->n0,
                            L.G.offset, L.G.logB, st);
@@ -711,6 +780,25 @@ tp_status vcycle_level_wave(const tp_mg* m, size_t l, const double* b, double* u
     hipLaunchKernelGGL((k_mg_jacobi0_wave<N, TI, VP>), dim3(grid), dim3(64), 0, s, b, u, L.G, tabS, m->omega[0], st);
     step(u, Lt, 1);
     step(Lt, u, 2);
+    if (last) {
+        // coarse correction on the degree-1 level: E^T (b - A u), its dense
+        // solve, u + E u_c
+        const DegTab<N> E = deg_table<N>();
+        hipLaunchKernelGGL((k_mg_apply_wave<N, VP>), dim3(grid), dim3(64), 0, s, u, Lt, L.G, tabA, F, st);
+        hipLaunchKernelGGL((k_mg_deg_restrict<N>), dim3(static_cast<unsigned>((m->n0 + 63) / 64)), dim3(64), 0, s, b,
+                           Lt, m->deg_b, L.G, E, st);
+        hipLaunchKernelGGL((k_mg_coarse<2, double>), dim3(static_cast<unsigned>((m->n0 + 255) / 256)), dim3(256), 0, s,
+                           m->coarse_inv, m->deg_b, m->deg_u, m->n0, int64_t(0), 0, st);
+        hipLaunchKernelGGL((k_mg_deg_prolong<N>),
+                           dim3(static_cast<unsigned>((L.G.ncells * N * N * N + 63) / 64)), dim3(64), 0, s, m->deg_u,
+                           u, Lt, L.G, E, st);
+        tp_status stt = check_launch("degree-level correction");
+        if (stt != TP_OK) return stt;
+        step(Lt, u, 0);
+        step(u, Lt, 1);
+        step(Lt, u, 2);
+        return check_launch("smoothing");
+    }
     const MgLevel& C = m->lv[l + 1];
     double* Cb = static_cast<double*>(C.b);
     double* Cu = static_cast<double*>(C.u);
@@ -805,11 +893,73 @@ tp_status coarse_probe_n(const tp_mg* m, std::vector<double>& A) {
     return st;
 }
 
+// The Galerkin operator E^T A E of the degree-1 level, column by column:
+// E e_j on the last geometric level, A of it, then E^T of that.
+template <int N>
+tp_status coarse_probe_deg(const tp_mg* m, std::vector<double>& A) {
+    const Plan& plan = *m->plan;
+    const MgLevel& L = m->lv.back();
+    FaceRef<N, double> F;
+    {
+        Pair<N, double> R;
+        sipg_tables<N, double>(plan, false, R, F);
+    }
+    const double* tabA = reinterpret_cast<const double*>(eo_table(plan, N, EO_APPLY_A, 0));
+    const DegTab<N> E = deg_table<N>();
+    const int64_t n0 = m->n0;
+    A.assign(static_cast<size_t>(n0 * n0), 0.0);
+    std::vector<double> col(static_cast<size_t>(n0));
+    // FP64 probe vectors (freed on return): zero, E e_j and A E e_j on the
+    // last geometric level, e_j and the column on the degree-1 level
+    double *zf = nullptr, *pu = nullptr, *pt = nullptr, *ec = nullptr, *cc = nullptr;
+    const size_t vb = static_cast<size_t>(L.elems) * sizeof(double);
+    const size_t cb = static_cast<size_t>(n0) * sizeof(double);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&zf), vb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pu), vb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pt), vb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&ec), cb);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&cc), cb);
+    tp_status st = e == hipSuccess ? TP_OK : hip_error(e, "degree-level probe vectors");
+    if (st == TP_OK) st = launch_fill(zf, L.elems, TP_F64, 0, true, nullptr);
+    if (st == TP_OK) st = launch_fill(pu, L.elems, TP_F64, 0, true, nullptr);
+    const PcgState* none = nullptr;
+    const unsigned gf = static_cast<unsigned>((L.G.ncells * N * N * N + 63) / 64);
+    const unsigned gc = static_cast<unsigned>((n0 + 63) / 64);
+    for (int64_t j = 0; st == TP_OK && j < n0; ++j) {
+        st = launch_fill(ec, n0, TP_F64, 0, true, nullptr);
+        if (st != TP_OK) break;
+        const double one = 1.0;
+        e = hipMemcpy(ec + j, &one, sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            st = hip_error(e, "degree-level probe");
+            break;
+        }
+        hipLaunchKernelGGL((k_mg_deg_prolong<N>), dim3(gf), dim3(64), 0, nullptr, ec, zf, pu, L.G, E, none);
+        hipLaunchKernelGGL((k_mg_apply_wave<N, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0, nullptr,
+                           pu, pt, L.G, tabA, F, none);
+        hipLaunchKernelGGL((k_mg_deg_restrict<N>), dim3(gc), dim3(64), 0, nullptr, pt, zf, cc, L.G, E, none);
+        st = check_launch("degree-level probe");
+        if (st != TP_OK) break;
+        e = hipMemcpy(col.data(), cc, cb, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            st = hip_error(e, "degree-level probe");
+            break;
+        }
+        for (int64_t i = 0; i < n0; ++i) A[i * n0 + j] = col[static_cast<size_t>(i)];
+    }
+    for (double* q : {zf, pu, pt, ec, cc})
+        if (q) (void)hipFree(q);
+    return st;
+}
+
 void free_mg(tp_mg* m) {
     for (auto& L : m->lv)
         for (void* p : {L.t, L.b, L.u})
             if (p) (void)hipFree(p);
     m->lv.clear();
+    for (double* p : {m->deg_b, m->deg_u})
+        if (p) (void)hipFree(p);
+    m->deg_b = m->deg_u = nullptr;
 }
 
 tp_status convert_launch(const void* src, void* dst, bool to_f32, int64_t n, const PcgState* st, hipStream_t s) {
@@ -967,13 +1117,28 @@ tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out) {
     }
     const MgLevel& Lc = m->lv.back();
     m->n0 = Lc.G.ncells * n3;
+    if (m->n0 > kMaxCoarse && g.n > kLaneMaxN && Lc.G.ncells * 8 <= kMaxCoarse) {
+        // too large for the dense solve at degree p: one more level of
+        // degree 1 on the same cells (Lagrange basis; n >= 5 only)
+        m->deg = true;
+        m->n0 = Lc.G.ncells * 8;
+        const size_t cb = static_cast<size_t>(m->n0) * sizeof(double);
+        e = hipMalloc(reinterpret_cast<void**>(&m->deg_b), cb);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&m->deg_u), cb);
+        if (e != hipSuccess) {
+            free_mg(m);
+            delete m;
+            (void)hipGetLastError();
+            return set_error(TP_ERR_OOM, "multigrid workspace allocation failed");
+        }
+    }
     if (m->n0 > kMaxCoarse) {
         free_mg(m);
         delete m;
         return set_error(TP_ERR_UNSUPPORTED, "the coarsest level (" + std::to_string(m->n0) +
                                                  " unknowns) is too large for its dense solve");
     }
-    if (m->lv.size() == 1 && !m->lv[0].b) {   // no coarser level: the finest is solved densely; it needs b and u scratch
+    if (m->lv.size() == 1 && !m->lv[0].b && !m->deg) {   // no coarser level: the finest is solved densely; it needs b and u scratch
         MgLevel& L0 = m->lv[0];
         const size_t vb = static_cast<size_t>(L0.elems) * es;
         e = hipMalloc(&L0.b, vb);
@@ -988,7 +1153,7 @@ tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out) {
     // the coarse inverse, shared per device and coarsest level
     int dev = 0;
     (void)hipGetDevice(&dev);
-    const CoarseKey key{dev, g.n, plan->basis, Lc.G.mx, Lc.G.my, Lc.G.mz, hx, hy, hz, plan->penalty_C};
+    const CoarseKey key{dev, g.n, plan->basis, m->deg ? 1 : 0, Lc.G.mx, Lc.G.my, Lc.G.mz, hx, hy, hz, plan->penalty_C};
     std::lock_guard<std::mutex> lock(g_coarse_mutex);
     auto it = g_coarse.find(key);
     if (it != g_coarse.end()) {
@@ -996,14 +1161,23 @@ tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out) {
     } else {
         std::vector<double> A, inv;
         tp_status st = TP_OK;
-        switch (g.n) {
-            case 2: st = coarse_probe_n<2>(m, A); break;
-            case 3: st = coarse_probe_n<3>(m, A); break;
-            case 4: st = coarse_probe_n<4>(m, A); break;
-            case 5: st = coarse_probe_n<5>(m, A); break;
-            case 6: st = coarse_probe_n<6>(m, A); break;
-            case 7: st = coarse_probe_n<7>(m, A); break;
-            default: st = coarse_probe_n<8>(m, A); break;
+        if (m->deg) {
+            switch (g.n) {
+                case 5: st = coarse_probe_deg<5>(m, A); break;
+                case 6: st = coarse_probe_deg<6>(m, A); break;
+                case 7: st = coarse_probe_deg<7>(m, A); break;
+                default: st = coarse_probe_deg<8>(m, A); break;
+            }
+        } else {
+            switch (g.n) {
+                case 2: st = coarse_probe_n<2>(m, A); break;
+                case 3: st = coarse_probe_n<3>(m, A); break;
+                case 4: st = coarse_probe_n<4>(m, A); break;
+                case 5: st = coarse_probe_n<5>(m, A); break;
+                case 6: st = coarse_probe_n<6>(m, A); break;
+                case 7: st = coarse_probe_n<7>(m, A); break;
+                default: st = coarse_probe_n<8>(m, A); break;
+            }
         }
         if (st == TP_OK && !spd_inverse(m->n0, A, inv))
             st = set_error(TP_ERR_NOT_SPD, "the coarsest level operator is not positive definite");

@@ -10,9 +10,9 @@ arrival order) as soon as a solver slot for its mesh class is free or the
 device-memory budget has room for a new one; finished solves return their
 slot to a per-class free pool, and idle slots of other classes are released
 when a new class needs the memory.  With multigrid on, the solves whose
-coarsest level fits the dense coarse solve (uses_multigrid) are
-preconditioned by one V-cycle per iteration (tp_mg_*), the others by
-block-Jacobi.  Marshalling and scheduling only: every step of a solve runs
+coarsest level fits the dense coarse solve (uses_multigrid; every class of
+the mix) are preconditioned by one V-cycle per iteration (tp_mg_*), the
+others by block-Jacobi.  Marshalling and scheduling only: every step of a solve runs
 in the library's kernels.
 """
 from __future__ import annotations
@@ -67,13 +67,14 @@ class _Slot:
 
 
 def uses_multigrid(p: int, m: int) -> bool:
-    """The V-cycle covers every degree whose coarsest level (the odd part of
-    m per side) has at most 2048 unknowns for its dense solve: every m of the
-    mix for p <= 3, powers of two for p = 7."""
+    """The V-cycle covers a mesh when its coarsest level (the odd part of m
+    cells per side) has at most 2048 unknowns for the dense solve, at degree
+    p or, for p >= 4, on the degree-1 level the library adds on the same
+    cells: every m of the mix for p = 2, 3 and 7."""
     odd = m
     while odd % 2 == 0:
         odd //= 2
-    return odd ** 3 * (p + 1) ** 3 <= 2048
+    return odd ** 3 * (p + 1) ** 3 <= 2048 or (p >= 4 and odd ** 3 * 8 <= 2048)
 
 
 def mg_bytes(p: int, m: int) -> int:

@@ -404,7 +404,8 @@ def test_mg_pcg_wave_degrees_iteration_count(p, m, inner):
 
 
 def test_mg_wave_rejects_what_it_does_not_cover():
-    with _cube_plan(7, 3) as plan:   # coarsest level 27 cells of 512 unknowns
+    # coarsest level 343 cells: too many for the dense solve even at degree 1
+    with _cube_plan(7, 7) as plan:
         with pytest.raises(tpfdm.TpfdmError) as e:
             tpfdm.MG(plan)
         assert e.value.status == -2
@@ -412,3 +413,40 @@ def test_mg_wave_rejects_what_it_does_not_cover():
         with pytest.raises(tpfdm.TpfdmError) as e:
             tpfdm.MG(plan, storage=tpfdm.F32)
         assert e.value.status == -2
+
+
+# coarsest geometric level above 2048 unknowns: the degree-1 level on its
+# cells is solved densely; (p, cells, h)
+DEGREE_CASES = [(7, (3, 3, 1), (0.3, 0.3, 0.5)), (7, (3, 3, 3), (1.0 / 3,) * 3),
+                (6, (6, 6, 2), (1.0 / 6, 1.0 / 6, 0.5)), (4, (6, 6, 6), (1.0 / 6,) * 3)]
+
+
+@pytest.mark.parametrize("p,cells,h", DEGREE_CASES)
+def test_vcycle_degree_level_matches_oracle(p, cells, h):
+    """The V-cycle with the degree-coarsened coarsest level (Galerkin E^T A E
+    probed on the GPU, the oracle forms it from its sparse matrices) element
+    by element, and MG-PCG with the oracle's iteration count."""
+    torch = _torch()
+    H = mg.Hierarchy(p, cells, h=h, coarse_degree=1)
+    nd = H.A[0].shape[0]
+    b = _rhs(nd, 90 + p + sum(cells))
+    xo = H.vcycle(b)
+    _, ito, _ = sipg.pcg(H.A[0], b, H.vcycle, 1e-10, 200)
+    print(f"p={p} cells={cells} levels={H.cells} degrees={H.degrees} oracle_iters={ito}", flush=True)
+    with tpfdm.Plan.mesh(p + 1, cells, h) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
+        with tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+            bb = to_blocked(plan, b, tpfdm.F64)
+            bx = torch.full_like(bb, float("nan"))
+            V.vcycle(bb, bx)
+            x = from_blocked(plan, bx, tpfdm.F64)
+            solver.set_multigrid(V)
+            bs = torch.zeros_like(bb)
+            s = solver.solve(bb, bs, rtol=1e-10, maxit=200, check_every=4)
+            xs = from_blocked(plan, bs, tpfdm.F64)
+    err = np.abs(x - xo).max() / np.abs(xo).max()
+    true = np.linalg.norm(b - H.A[0] @ xs) / np.linalg.norm(b)
+    print(f"  vcycle rel err={err:.2e} {s} true relres {true:.2e}")
+    assert err <= 1e-11
+    assert s["converged"] and abs(s["iterations"] - ito) <= 1
+    assert true <= 2e-10
