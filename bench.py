@@ -298,7 +298,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="p3_64cube_affine")
     ap.add_argument("--rotate", type=int, default=4)
     ap.add_argument("--solve-calls", type=int, default=200)
@@ -408,10 +408,12 @@ def main():
     _log(f"ndof={ndof} vector_elems={E} sets={R}")
 
     if args.counters:
-        # calibration: a plain copy of exactly one vector (vector_elems * esize bytes
-        # read and written), then the two kernels of the step
+        # calibration: a plain elementwise kernel over exactly one vector
+        # (vector_elems * esize bytes read and written; torch's copy_ would
+        # go to a DMA engine, which the shader counters do not see), then
+        # the two kernels of the step
         for k in range(3):
-            V[k % R].copy_(U[k % R])
+            torch.mul(U[k % R], 1.0, out=V[k % R])
         for k in range(3):
             plan.apply(U[k % R], V[k % R], tpfdm.OP_NEUMANN, stream=stream)
         for k in range(3):
@@ -437,8 +439,13 @@ def main():
     _log("warmup done")
     ms_step = time_launches(step, stream, args.steps, R)
     _log(f"step {ms_step:.4f} ms")
-    reps = max(args.steps, 20)
+    # each kernel alone: 10 untimed launches, then at least 100 timed ones
+    reps = max(args.steps, 100)
+    for k in range(10):
+        plan.apply(U[k % R], V[k % R], tpfdm.OP_NEUMANN, stream=stream)
     ms_apply = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
+    for k in range(10):
+        plan.apply_inverse(V[k % R], X[k % R], stream=stream)
     ms_inv = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
     _log(f"apply {ms_apply:.4f} ms, inverse {ms_inv:.4f} ms")
 

@@ -48,8 +48,9 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 constexpr int kMfmaApplyHalves = 3 * 2 * 4 * 64 * 8 + 64 * 8;
 constexpr int kMfmaInvHalves = 2 * 2 * 4 * 64 * 8 + 2 * 64 * 4;
 constexpr int kMfmaInvBytes = kMfmaInvHalves * 2 + 8 * 4;
-// Tiles of a wave whose loads are in flight ahead of the one computed.
-constexpr int kPF = 4;
+// Tiles of a wave whose loads are in flight ahead of the one computed
+// (measured at p = 7, 32768 blocks, FP16: 2 and 4 were slower than 3).
+constexpr int kPF = 3;
 
 namespace {
 
@@ -258,20 +259,39 @@ __global__ __launch_bounds__(64, 2) void k_apply_mfma(const TS* __restrict__ u, 
             load_full_h(hring[p], G, tp);
             load_full_a(ring[p], u, G, tp);
         }
-        // the ring slot is a compile-time index (the loop is unrolled kPF
-        // times) and prefetches past the wave's last tile re-read that tile,
-        // so each wait covers only the oldest tile's loads
-        while (t < nfull) {
+        // the ring slot is a compile-time index (the main loop is unrolled
+        // kPF times and has no early exit, so every pass issues the same
+        // memory instructions and each wait covers only the oldest tile's
+        // loads, not the prefetches and stores behind it); prefetches past
+        // the wave's last tile re-read that tile
+        const int64_t cnt = (tlast - t) / G2 + 1;   // tiles of this wave
+        int64_t i = 0;
+        for (; i + kPF <= cnt; i += kPF) {
 #pragma unroll
             for (int slot = 0; slot < kPF; ++slot) {
-                if (t >= nfull) break;
-                const uint4 cur[2] = {ring[slot][0], ring[slot][1]};
+                // the slot is refilled only after its tile has consumed it,
+                // so the new loads land in the slot's own registers (a copy
+                // out of registers with a load in flight would wait for it);
+                // no instruction crosses into the next slot's tile, which
+                // would wait for that younger tile's loads
+                __builtin_amdgcn_sched_barrier(0);
                 float sx, sy, sz;
                 scales_of(hring[slot], sx, sy, sz);
                 const int64_t tn = std::min(t + kPF * G2, tlast);
                 load_full_h(hring[slot], G, tn);
+                tile(ring[slot], sx, sy, sz, t);
                 load_full_a(ring[slot], u, G, tn);
-                tile(cur, sx, sy, sz, t);
+                out_flush<true>(ot, v, G, t);
+                t += G2;
+            }
+        }
+        // the last cnt - i < kPF tiles are already in ring slots 0, 1, ...
+#pragma unroll
+        for (int slot = 0; slot < kPF - 1; ++slot) {
+            if (i + slot < cnt) {
+                float sx, sy, sz;
+                scales_of(hring[slot], sx, sy, sz);
+                tile(ring[slot], sx, sy, sz, t);
                 out_flush<true>(ot, v, G, t);
                 t += G2;
             }
@@ -377,20 +397,39 @@ __global__ __launch_bounds__(64, 2) void k_inverse_mfma(const TS* __restrict__ r
             load_full_h(hring[p], G, tp);
             load_full_a(ring[p], r, G, tp);
         }
-        // the ring slot is a compile-time index (the loop is unrolled kPF
-        // times) and prefetches past the wave's last tile re-read that tile,
-        // so each wait covers only the oldest tile's loads
-        while (t < nfull) {
+        // the ring slot is a compile-time index (the main loop is unrolled
+        // kPF times and has no early exit, so every pass issues the same
+        // memory instructions and each wait covers only the oldest tile's
+        // loads, not the prefetches and stores behind it); prefetches past
+        // the wave's last tile re-read that tile
+        const int64_t cnt = (tlast - t) / G2 + 1;   // tiles of this wave
+        int64_t i = 0;
+        for (; i + kPF <= cnt; i += kPF) {
 #pragma unroll
             for (int slot = 0; slot < kPF; ++slot) {
-                if (t >= nfull) break;
-                const uint4 cur[2] = {ring[slot][0], ring[slot][1]};
+                // the slot is refilled only after its tile has consumed it,
+                // so the new loads land in the slot's own registers (a copy
+                // out of registers with a load in flight would wait for it);
+                // no instruction crosses into the next slot's tile, which
+                // would wait for that younger tile's loads
+                __builtin_amdgcn_sched_barrier(0);
                 float sx, sy, sz;
                 scales_of(hring[slot], sx, sy, sz);
                 const int64_t tn = std::min(t + kPF * G2, tlast);
                 load_full_h(hring[slot], G, tn);
+                tile(ring[slot], sx, sy, sz, t);
                 load_full_a(ring[slot], r, G, tn);
-                tile(cur, sx, sy, sz, t);
+                out_flush<true>(ot, x, G, t);
+                t += G2;
+            }
+        }
+        // the last cnt - i < kPF tiles are already in ring slots 0, 1, ...
+#pragma unroll
+        for (int slot = 0; slot < kPF - 1; ++slot) {
+            if (i + slot < cnt) {
+                float sx, sy, sz;
+                scales_of(hring[slot], sx, sy, sz);
+                tile(ring[slot], sx, sy, sz, t);
                 out_flush<true>(ot, x, G, t);
                 t += G2;
             }
