@@ -188,6 +188,37 @@ def cpu_baseline(wl, budget_s=12.0):
     return out
 
 
+def cpu_sumfact_all(workers=None):
+    """The sum-factorized CPU reference (oracle.sumfact: apply, then the
+    cell-block inverse, FP64) on each whole benchmark workload, split over
+    one forked worker process per available core (BLAS single-threaded in
+    each).  Like cpu_baseline, it runs before the process touches the GPU."""
+    import multiprocessing as mp
+    global _CPU_WL
+    _, _, avail = _host_cpu()
+    workers = workers or max(1, avail)
+    ctx = mp.get_context("fork")
+    out = {}
+    for name in ("p2_128cube", "p3_64cube_affine", "p7_32cube_aniso", "uneven_p237_20000"):
+        wl = build_workload(name)[0]
+        _CPU_WL = wl
+        parts = []
+        for gi, g in enumerate(wl.groups):
+            step = max(1, -(-g.nblocks // (4 * workers)))
+            parts += [(gi, lo, min(g.nblocks, lo + step)) for lo in range(0, g.nblocks, step)]
+        t0 = time.perf_counter()
+        with ctx.Pool(workers, initializer=_one_thread) as pool:
+            pool.map(_sumfact_part, parts)
+            wall = time.perf_counter() - t0
+            pool.close()
+            pool.join()
+        out[name] = {"value": wl.ndof / wall / 1e9, "unit": "GDoF/s", "ndof": wl.ndof, "wall_s": round(wall, 2),
+                     "workers": workers}
+        _CPU_WL = None
+        del wl
+    return out
+
+
 def measure_ops(name, dtname, stream, reps=20):
     """apply and apply_inverse of a workload in one storage precision with
     buffer sets rotated past the last-level cache (HIP events on stream)."""
@@ -344,6 +375,7 @@ def main():
         # before anything initialises the GPU: the baseline forks its workers
         _log("cpu baseline")
         cpu_base = cpu_baseline(build_workload(args.workload)[0])
+        cpu_base["sumfact_by_workload"] = cpu_sumfact_all()
 
     import torch
     from paper_2609_04534_amd import tpfdm
