@@ -8,9 +8,9 @@
 // E = A_E e (ceil(n/2) x ceil(n/2)) and O = A_O o (floor(n/2) x floor(n/2)).
 // The generalized eigenvectors of such a pencil are symmetric or
 // antisymmetric, so S^T x and S y split the same way.  This halves the
-// multiply-adds and the size of the matrices; the halved matrices live in
-// VGPRs (loaded once per workgroup through LDS), which keeps the scalar
-// register file free for addressing.
+// multiply-adds and the size of the matrices; the halved matrices are read
+// at wave-uniform addresses (FP32, and FP64 from n = 5 on: scalar
+// registers) or held in VGPRs (FP64 below n = 5).
 //
 // Mapping: one wave per tile of BPW blocks, each block's slab in LDS, one
 // pencil per lane and phase (see Slab/Pencil); a persistent grid loops over
@@ -25,6 +25,14 @@ namespace tpfdm {
 
 namespace {
 
+// From this n on, the FP64 apply and inverse read their halved matrices at
+// wave-uniform global addresses (scalar loads into SGPRs, served by the
+// scalar cache) instead of holding them in VGPRs: at n = 8 that frees 125
+// of 232 VGPRs in apply and 60 of 148 in the inverse, for two more waves
+// per SIMD (measured on 16.8 M DoF: apply 10-22 % and inverse up to 8 %
+// faster for n = 5..8, results bit-identical).
+constexpr int kEoScalarTabN = 5;
+
 // v = A u.  Table: ME | MO | PE | PO.
 // Per tile: z-phase from the prefetched pencil registers, y-phase and
 // x-phase through LDS, x-phase results stored straight to global memory
@@ -37,13 +45,18 @@ __global__ __launch_bounds__(64, 2) void k_apply_eo(const TS* __restrict__ u, TS
     constexpr int HC = S::HC, H = S::H;
     constexpr int TAB = 2 * (S::SE + S::SO);
     __shared__ TC s1[L::BPW * L::size], s2[L::BPW * L::size];
-    __shared__ TC stab[TAB];
-    TC T[TAB];
-    load_table<TC, TAB>(T, tab, stab);
-    const TC* ME = T;
-    const TC* MO = T + S::SE;
-    const TC* PE = T + S::SE + S::SO;
-    const TC* PO = T + 2 * S::SE + S::SO;
+    // FP64 tables at n = 8 (64 values) are read at wave-uniform global
+    // addresses (scalar loads into SGPRs, from the scalar cache) instead of
+    // being held in 128 VGPRs; smaller or FP32 tables stay in registers
+    constexpr bool kScalarTab = sizeof(TC) == 8 && N >= kEoScalarTabN;
+    __shared__ TC stab[kScalarTab ? 1 : TAB];
+    TC T[kScalarTab ? 1 : TAB];
+    if constexpr (!kScalarTab) load_table<TC, TAB>(T, tab, stab);
+    const TC* Tb = kScalarTab ? tab : T;
+    const TC* ME = Tb;
+    const TC* MO = Tb + S::SE;
+    const TC* PE = Tb + S::SE + S::SO;
+    const TC* PO = Tb + 2 * S::SE + S::SO;
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
     const int lane = threadIdx.x;
@@ -84,16 +97,18 @@ __global__ __launch_bounds__(64, 2) void k_inverse_eo(const TS* __restrict__ r, 
     __shared__ TC stab[TABM + N];
     for (int e = threadIdx.x; e < TABM + N; e += 64) stab[e] = tab[e];
     wave_sync();
-    TC T[TABM];
-    if constexpr (sizeof(TC) == 8) {
+    constexpr bool kScalarTab = sizeof(TC) == 8 && N >= kEoScalarTabN;
+    TC T[kScalarTab ? 1 : TABM];
+    if constexpr (kScalarTab) {
+    } else if constexpr (sizeof(TC) == 8) {
 #pragma unroll
         for (int i = 0; i < TABM; ++i) T[i] = stab[i];
     } else {
 #pragma unroll
         for (int i = 0; i < TABM; ++i) T[i] = tab[i];
     }
-    const TC* SE = T;
-    const TC* SO = T + S::SE;
+    const TC* SE = kScalarTab ? tab : T;
+    const TC* SO = (kScalarTab ? tab : T) + S::SE;
     const TC* lam = stab + TABM;
     int64_t t = blockIdx.x;
     if (t >= ntiles) return;
