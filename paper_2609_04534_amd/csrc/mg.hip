@@ -292,10 +292,10 @@ __global__ __launch_bounds__(64, 2) void k_mg_apply_wave(const double* __restric
     if (done_flag(st)) return;
     constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
     __shared__ WaveLds<N, double> L;
-    stage_table<double, TAB>(tab, L.tab);
+    static_assert(TAB > 0, "table");   // read at wave-uniform global addresses (scalar loads)
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
     double y[N];
-    wave_sipg_cell<N, double, VP, false>(u, G, L.tab, F, c, L, y);
+    wave_sipg_cell<N, double, VP, false>(u, G, tab, F, c, L, y);
     const Pencil<N> pc(1);
     if (pc.act) {
         double* tb = t + G.offset + block_base(c, G.logB, N * N * N);
@@ -362,11 +362,11 @@ __global__ __launch_bounds__(64, 2) void k_mg_smooth_wave(const double* __restri
     static_assert(SL::size * sizeof(TI) <= 2 * SL::size * sizeof(double), "slab exceeds the volume scratch");
     __shared__ WaveLds<N, double> L;
     __shared__ TI stab[TABM + N];
-    stage_table<double, TAB>(tab, L.tab);
+    static_assert(TAB > 0, "table");   // read at wave-uniform global addresses (scalar loads)
     for (int e = threadIdx.x; e < TABM + N; e += 64) stab[e] = tabS[e];
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
     double y[N];
-    wave_sipg_cell<N, double, VP, false>(uin, G, L.tab, F, c, L, y);   // ends synced
+    wave_sipg_cell<N, double, VP, false>(uin, G, tab, F, c, L, y);   // ends synced
     const Pencil<N> pc(1);
     TI* slab = reinterpret_cast<TI*>(L.t);
     const double* bb = b + G.offset + block_base(c, G.logB, N * N * N);

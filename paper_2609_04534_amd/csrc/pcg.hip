@@ -325,19 +325,12 @@ __global__ __launch_bounds__(64, 2) void k_pcg_aq_wave(const double* __restrict_
     if (st->done) return;
     constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
     __shared__ WaveLds<N, double> L;
-    // FP64: the tables are read from LDS (in registers they would take half
-    // the register file); FP32: from registers
-    double TB[TAB];
-    const double* tb = TB;
-    if constexpr (sizeof(double) == 8) {
-        stage_table<double, TAB>(tab, L.tab);
-        tb = L.tab;
-    } else {
-        load_table<double, TAB>(TB, tab, L.tab);
-    }
+    // the FP64 tables are read at wave-uniform global addresses (scalar
+    // loads), not from registers or LDS
+    static_assert(TAB > 0, "table");
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
     double y[N];
-    wave_sipg_cell<N, double, VP, HERM>(p, G, tb, F, c, L, y);
+    wave_sipg_cell<N, double, VP, HERM>(p, G, tab, F, c, L, y);
     const Pencil<N> pc(1);
     double dot = 0.0;
     if (pc.act) {

@@ -28,13 +28,13 @@ __global__ __launch_bounds__(64, 2) void k_sipg_wave(const T* __restrict__ u, T*
                                                   const T* __restrict__ tab, FaceRef<N, T> F) {
     constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
     __shared__ WaveLds<N, T> L;
-    // FP64: the tables are read from LDS (in registers they would take half
-    // the register file); FP32: from registers
-    T TB[TAB];
+    // FP64: the tables are read at wave-uniform global addresses (scalar
+    // loads; in VGPRs they would take half the register file, from LDS they
+    // would compete with the slab traffic); FP32: from registers
+    T TB[sizeof(T) == 8 ? 1 : TAB];
     const T* tb = TB;
     if constexpr (sizeof(T) == 8) {
-        stage_table<T, TAB>(tab, L.tab);
-        tb = L.tab;
+        tb = tab;
     } else {
         load_table<T, TAB>(TB, tab, L.tab);
     }
