@@ -23,3 +23,16 @@ def test_oversized_requests_are_rejected_without_running():
     for r in done:
         assert r.rejected and r.x is None and r.summary["status"] == "rejected"
         assert "exceeds the budget" in r.summary["reason"]
+
+
+def test_every_class_of_the_serving_mix_uses_multigrid():
+    """All 15 classes (p in {2, 3, 7}, m in {8, 16, 24, 32, 48}) have a
+    coarsest level the library solves densely: at degree p for p <= 3, and
+    for p = 7 either one cell (m a power of two) or the degree-1 level on
+    3^3 cells (216 unknowns); larger odd parts are left to block-Jacobi."""
+    for p in (2, 3, 7):
+        for m in (8, 16, 24, 32, 48):
+            assert serve.uses_multigrid(p, m), (p, m)
+    assert not serve.uses_multigrid(7, 7)      # 343 cells: 2744 unknowns even at degree 1
+    assert not serve.uses_multigrid(3, 5)      # 125 cells of degree 3 (lane kernels keep their degree)
+    assert serve.uses_multigrid(4, 40)         # odd part 5: 125 cells x 8 = 1000
