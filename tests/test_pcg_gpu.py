@@ -175,3 +175,32 @@ def test_pcg_serving_size_sampled_residual(p, m, inner):
     rows = mesh.u.reshape(-1, n3)[sample] - Ax
     # each sampled row of the true residual is a piece of r with ||r|| <= ~1e-8 ||b||
     assert np.linalg.norm(rows) <= 1e-7 * np.linalg.norm(mesh.u)
+
+
+@pytest.mark.parametrize("m", [24, 48])
+def test_mg_pcg_degree_level_at_serving_size(m):
+    """Degree 7 on the serving meshes whose coarsest geometric level is 3^3
+    cells (24^3 and 48^3): MG-PCG through the degree-1 coarsest level
+    converges in a multigrid-like iteration count, and the oracle's true
+    residual rows on sampled cells of the GPU solution are small."""
+    torch = _torch()
+    p = 7
+    mesh = workloads.unit_cube_mesh(p, m, seed=11)
+    n, cells, h = mesh.n, mesh.cells, mesh.h
+    print(f"p={p} m={m}", flush=True)
+    with tpfdm.Plan.mesh(n, cells, h) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
+        bb = to_blocked(plan, mesh.u, tpfdm.F64)
+        bx = torch.empty_like(bb)
+        with tpfdm.MG(plan) as V, tpfdm.PCG(plan) as solver:
+            solver.set_multigrid(V)
+            s = solver.solve(bb, bx, inner=tpfdm.F64, rtol=1e-8, maxit=200, check_every=4)
+        x = from_blocked(plan, bx, tpfdm.F64)
+    print(f"  {s}")
+    assert s["converged"] and s["relres"] <= 1e-8 and s["iterations"] <= 24
+    corners = [sipg.cell_index(cells, a, b_, c) for a in (0, m - 1) for b_ in (0, m - 1) for c in (0, m - 1)]
+    rng = np.random.default_rng(2)
+    sample = sorted(set(corners + rng.choice(m ** 3, 16, replace=False).tolist()))
+    Ax = sipg.cell_apply(p, cells, h, x, sample)
+    rows = mesh.u.reshape(-1, n ** 3)[sample] - Ax
+    assert np.linalg.norm(rows) <= 1e-7 * np.linalg.norm(mesh.u)
