@@ -95,6 +95,14 @@ def test_vectors_beyond_2_31_elements(p, B, dt, tol_apply, tol_inv):
             del diffs
             print(f"  max |D^-1 D u - u| / max |u| = {err:.2e}", flush=True)
             assert err <= 1e-12
+            # the block-local solve of D x = D u from x = 0, FP64 inner
+            x.zero_()
+            summ = plan.solve(v, x, inner=tpfdm.F64, rtol=1e-10, maxit=10)
+            diffs = [a - b for a, b in zip(_valid_parts(x, B, n3, nblocks), _valid_parts(u, B, n3, nblocks))]
+            err = _max_abs(diffs) / _max_abs(_valid_parts(u, B, n3, nblocks))
+            del diffs
+            print(f"  solve {summ}, max |x - u| / max |u| = {err:.2e}", flush=True)
+            assert summ["n_failed"] == 0 and summ["max_relres"] <= 1e-10 and err <= 1e-9
         # blocks whose elements lie past 2^31 against the dense oracle
         for g in (nblocks - 1, nblocks - B - 1, LIMIT // n3 + 1):
             ub = _block_values(u, B, n3, g)
@@ -109,3 +117,50 @@ def test_vectors_beyond_2_31_elements(p, B, dt, tol_apply, tol_inv):
     finally:
         plan.destroy()
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("p,cells,basis", [(3, (320, 322, 328), tpfdm.BASIS_LAGRANGE),
+                                           (3, (320, 322, 328), tpfdm.BASIS_HERMITE),
+                                           (7, (160, 162, 164), tpfdm.BASIS_LAGRANGE)])
+def test_sipg_operator_beyond_2_31_elements(p, cells, basis):
+    """The coupled operator on a mesh whose vectors exceed 2^31 elements:
+    rows of sampled cells (corners, faces, interior, the last cells) against
+    the oracle's row blocks of the same cells, their neighbours' blocks read
+    back from the GPU."""
+    from oracle import sipg
+    torch = _torch()
+    n = p + 1
+    n3 = n ** 3
+    h = tuple(1.0 / c for c in cells)
+    ncell = cells[0] * cells[1] * cells[2]
+    bname = sipg.HERMITE if basis == tpfdm.BASIS_HERMITE else sipg.LAGRANGE
+    with tpfdm.Plan.mesh(n, cells, h, basis=basis) as plan:
+        E = plan.vector_elems
+        assert E > LIMIT
+        B = tpfdm.default_layout_B(n)
+        print(f"p={p} cells={cells} basis={bname} elems={E}", flush=True)
+        gen = torch.Generator(device="cuda").manual_seed(7)
+        u = torch.rand(E, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+        v = torch.full_like(u, float("nan"))
+        plan.apply(u, v, tpfdm.OP_SIPG)
+        torch.cuda.synchronize()
+        for q in _valid_parts(v, B, n3, ncell):
+            assert bool(torch.isfinite(q).all())
+        mx, my, mz = cells
+        sample = {sipg.cell_index(cells, a, b_, c) for a in (0, mx - 1) for b_ in (0, my - 1) for c in (0, mz - 1)}
+        sample |= {ncell - 1, ncell - 2, ncell - mz, sipg.cell_index(cells, mx - 1, my // 2, mz // 2),
+                   LIMIT // n3 + 7}
+        worst = 0.0
+        for c in sorted(sample):
+            row = np.zeros(n3)
+            scale = np.zeros(n3)
+            for nb, blk in sipg.cell_row_blocks(p, cells, h, int(c), sipg.FULL, 2.0, bname):
+                ub = _block_values(u, B, n3, nb)
+                row += blk @ ub
+                scale += np.abs(blk) @ np.abs(ub)
+            got = _block_values(v, B, n3, int(c))
+            worst = max(worst, float(np.max(np.abs(got - row) / np.max(scale))))
+        print(f"  {len(sample)} sampled rows: max error / row scale {worst:.2e}", flush=True)
+        assert worst <= 1e-13
+        del u, v
+    torch.cuda.empty_cache()
