@@ -158,7 +158,10 @@ typedef struct tp_plan tp_plan;
 /* Default options: C = 2, non-persistent, automatic mapping. */
 void tp_plan_opts_default(tp_plan_opts* opts);
 
-/* Create a plan over ngroups groups on the current HIP device.  Validates the
+/* Create a plan over ngroups groups on the current HIP device (the batch of
+ * independent cell or patch blocks of Sec. 2, each a scaled reference cell
+ * whose operator is the sum-factorized form of Sec. 3.1,
+ * eq. (eval_pipeline)).  Validates the
  * groups (n, B, sizes, non-overlapping element ranges, h finite and > 0),
  * copies h into plan-owned device memory, builds the 1D reference matrices
  * for every degree used, and allocates the solve workspace.  Host-synchronous.
@@ -253,8 +256,10 @@ tp_status tp_setup_inverse(tp_plan* plan, tp_operator op, tp_factor_mode mode,
 tp_status tp_apply_inverse(tp_plan* plan, const void* r, void* x, tp_dtype dtype,
                            hipStream_t stream);
 
-/* Solve D x = b for every block by iterative refinement, one launch per
- * group (one in all for a persistent plan):
+/* Solve D x = b for every block, D the cell block of Sec. 5.2,
+ * eq. (cell_block), whose exact inverse is the fast diagonalization of
+ * tp_apply_inverse; by iterative refinement, one launch per group (one in
+ * all for a persistent plan):
  *   r = b - D x (FP64);  s = ||r||_inf;  d = D~^{-1}(r/s) in `inner` precision;
  *   x <- x + s d  (FP64)
  * until ||r||_2 / ||b||_2 <= rtol or maxit corrections.  inner: TP_F64 and
