@@ -359,7 +359,7 @@ __global__ __launch_bounds__(64, 2) void k_mg_smooth_wave(const double* __restri
     using SL = Slab<N>;
     constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
     constexpr int TABM = EOShape<N>::SE + EOShape<N>::SO;
-    static_assert(SL::size * sizeof(TI) <= 2 * SL::size * sizeof(double), "slab exceeds the volume scratch");
+    static_assert(SL::size * sizeof(TI) <= sizeof(WaveLds<N, double>::t), "slab exceeds the volume scratch");
     __shared__ WaveLds<N, double> L;
     __shared__ TI stab[TABM + N];
     static_assert(TAB > 0, "table");   // read at wave-uniform global addresses (scalar loads)

@@ -379,12 +379,16 @@ __device__ __forceinline__ void sipg_cell(const TS* __restrict__ u, const MeshAr
 // in-place LDS passes of one n-pencil per task (a task owns its row, then
 // its column; 12 n tasks per pass spread over the wave); finally lane (j, k)
 // adds the face terms to its x-pencil of the volume product.
+// The volume product's second scratch slab is the block's own slab s: each
+// lane overwrites only the slab positions it has itself just read (its
+// pencil in the first phase, its x-pencil in the last), so s, one scratch
+// slab and the face slabs are all the LDS a wave needs (10.75 KB at n = 8
+// in FP64: 14 waves per CU instead of 11).
 template <int N, typename T>
 struct WaveLds {
-    T s[Slab<N>::size];          // the cell's block, then its volume product
-    T t[2 * Slab<N>::size];      // volume scratch t1 | t2, then the twelve face slabs
-    T tab[2 * (EOShape<N>::SE + EOShape<N>::SO)];          // table staging
-    static_assert(12 * N * N <= 2 * Slab<N>::size, "face slabs exceed the volume scratch");
+    static constexpr int kT = 12 * N * N > Slab<N>::size ? 12 * N * N : Slab<N>::size;
+    T s[Slab<N>::size];          // the cell's block, then its volume product (and scratch t2)
+    T t[kT];                     // volume scratch t1, then the twelve face slabs
 };
 
 // The lane's x-pencil y[i] = (A u)_c at (i, j, k) with (j, k) = (pc.pa,
@@ -427,7 +431,7 @@ __device__ __forceinline__ void wave_sipg_cell(const T* __restrict__ u, const Me
         for (int k = 0; k < N; ++k) L.s[SL::at(pa, pb, k)] = HERM ? sab * sg(k) * x[k] : x[k];
     }
     wave_sync();
-    eo_apply_lds<N, T>(pc, L.s, L.s, L.t, L.t + SL::size, ME, MO, PE, PO, sx, sy, sz);   // ends synced
+    eo_apply_lds<N, T>(pc, L.s, L.s, L.t, L.s, ME, MO, PE, PO, sx, sy, sz);   // ends synced
     // --- face slabs in the free scratch: alpha (2 f) and beta (2 f + 1) of
     // face f = 2 axis + upper, slab sl at fs + sl n^2
     T* fs = L.t;

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(64, 2) void k_sipg_wave(const T* __restrict__ u, T*
     if constexpr (sizeof(T) == 8) {
         tb = tab;
     } else {
-        load_table<T, TAB>(TB, tab, L.tab);
+        load_table<T, TAB>(TB, tab, nullptr);   // FP32: straight from the global table
     }
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
     T y[N];
