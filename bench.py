@@ -219,9 +219,12 @@ def cpu_sumfact_all(workers=None):
     return out
 
 
-def measure_ops(name, dtname, stream, reps=20):
+def measure_ops(name, dtname, stream, reps=100):
     """apply and apply_inverse of a workload in one storage precision with
-    buffer sets rotated past the last-level cache (HIP events on stream)."""
+    buffer sets rotated past the last-level cache (HIP events on stream;
+    as for the headline kernels, 10 untimed and 100 timed launches each:
+    sustained back-to-back launches run slower than short bursts on this
+    GPU, so short loops would flatter the rate)."""
     import torch
     from paper_2609_04534_amd import tpfdm
     codes = {"f64": (tpfdm.F64, torch.float64, 8), "f32": (tpfdm.F32, torch.float32, 4),
@@ -242,7 +245,11 @@ def measure_ops(name, dtname, stream, reps=20):
     for k in range(3):
         plan.apply(U[k % R], V[k % R], tpfdm.OP_NEUMANN, stream=stream)
         plan.apply_inverse(V[k % R], X[k % R], stream=stream)
+    for k in range(10):
+        plan.apply(U[k % R], V[k % R], tpfdm.OP_NEUMANN, stream=stream)
     ms_a = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
+    for k in range(10):
+        plan.apply_inverse(V[k % R], X[k % R], stream=stream)
     ms_i = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
     ms_s = time_launches(lambda k: (plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream),
                                     plan.apply_inverse(V[k], X[k], stream=stream)), stream, reps, R)
@@ -558,7 +565,7 @@ def main():
     extra = {}
     for name, dtn in EXTRA_OPS:
         _log(f"ops {name} {dtn}")
-        r = measure_ops(name, dtn, stream, reps=max(args.steps, 20))
+        r = measure_ops(name, dtn, stream, reps=max(args.steps, 100))
         extra[f"{name}/{dtn}"] = r
     out["ops_other_workloads"] = extra
     # mixed precision at equal final residual: MG-PCG with FP32 level storage
