@@ -60,11 +60,15 @@ def flops(wl, which):
     return sum(g.nblocks * per(g.n) for g in wl.groups)
 
 
-def time_launches(fn, stream, reps, sets):
-    """Average milliseconds per call of fn(k) over reps calls, HIP events on stream."""
+def time_launches(fn, stream, reps, sets, warm=3):
+    """Average milliseconds per call of fn(k) over reps calls, HIP events on
+    stream, after warm untimed calls (the first launch of a kernel loads its
+    code object, milliseconds that are no part of the kernel's time)."""
     import torch
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
+    for i in range(warm):
+        fn(i % sets)
     torch.cuda.synchronize()
     start.record(stream)
     for i in range(reps):
@@ -476,7 +480,7 @@ def main():
         step(i % R)
     torch.cuda.synchronize()
     _log("warmup done")
-    ms_step = time_launches(step, stream, args.steps, R)
+    ms_step = time_launches(step, stream, args.steps, R, warm=0)
     _log(f"step {ms_step:.4f} ms")
     # each kernel alone: 10 untimed launches, then at least 100 timed ones
     reps = max(args.steps, 100)
