@@ -129,6 +129,9 @@ struct Plan {
     int64_t nblocks = 0;
     // device workspace
     void* summary_dev = nullptr;   // solve summary of the last solve
+    void* summary_host = nullptr;  // pinned, host-coherent copy of it (tp_solve's readback)
+    void* summary_host_dev = nullptr;  // the same memory's device address
+    int summary_seq = 0;           // tag of the last summary written there
     void* partials_dev = nullptr;  // SolvePartial per workgroup of the last solve
     int64_t partials_cap = 0;
     // MFMA operand tables for n = 8 FP16 / BF16: apply [K or A][f16 or bf16], inverse [f16 or bf16]
@@ -174,10 +177,11 @@ struct SolveWork {
     SolvePartial* parts;
     int64_t cap;
     SolveSummary* summary;
+    SolveSummary* host = nullptr;   // device address of pinned host memory for the readback, or null
 };
 inline SolveWork plan_work(const Plan& p) {
     return SolveWork{static_cast<SolvePartial*>(p.partials_dev), p.partials_cap,
-                     static_cast<SolveSummary*>(p.summary_dev)};
+                     static_cast<SolveSummary*>(p.summary_dev), static_cast<SolveSummary*>(p.summary_host_dev)};
 }
 
 // The static device workspace of tp_solve_static (static_scratch.hip): its
@@ -267,7 +271,7 @@ tp_status launch_sipg(const Plan& plan, const GroupInfo& g, bool face_only, cons
                       hipStream_t s);
 tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize,
                       bool to_blocked, hipStream_t s);
-tp_status launch_summary_reduce(const SolveWork& w, int64_t nparts, hipStream_t s);
+tp_status launch_summary_reduce(const SolveWork& w, int64_t nparts, SolveSummary* host_out, int tag, hipStream_t s);
 
 }  // namespace tpfdm
 

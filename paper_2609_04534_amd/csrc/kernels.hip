@@ -107,9 +107,11 @@ __global__ void k_unpack(const E* __restrict__ blocked, E* __restrict__ canon, i
     }
 }
 
-// Reduces the per-workgroup partial summaries of one solve into the summary.
+// Reduces the per-workgroup partial summaries of one solve into the summary,
+// and into host_out (pinned host memory) when that is given, tagged.
 __global__ __launch_bounds__(256) void k_summary_reduce(const SolvePartial* __restrict__ parts, int64_t count,
-                                                        SolveSummary* __restrict__ out) {
+                                                        SolveSummary* __restrict__ out,
+                                                        SolveSummary* __restrict__ host_out, int tag) {
     __shared__ int smi[256], snf[256], snn[256];
     __shared__ double smr[256];
     int mi = 0, nf = 0, nn = 0;
@@ -136,11 +138,14 @@ __global__ __launch_bounds__(256) void k_summary_reduce(const SolvePartial* __re
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out->max_iters = smi[0];
-        out->n_failed = snf[0];
-        out->nonfinite = snn[0];
-        out->pad = 0;
-        out->max_relres_bits = static_cast<unsigned long long>(__double_as_longlong(smr[0]));
+        SolveSummary r;
+        r.max_iters = smi[0];
+        r.n_failed = snf[0];
+        r.nonfinite = snn[0];
+        r.pad = tag;
+        r.max_relres_bits = static_cast<unsigned long long>(__double_as_longlong(smr[0]));
+        *out = r;
+        if (host_out) *host_out = r;
     }
 }
 
@@ -393,9 +398,9 @@ tp_status launch_pack(const GroupInfo& g, const void* src, void* dst, int esize,
     return check_launch("pack launch");
 }
 
-tp_status launch_summary_reduce(const SolveWork& w, int64_t nparts, hipStream_t s) {
+tp_status launch_summary_reduce(const SolveWork& w, int64_t nparts, SolveSummary* host_out, int tag, hipStream_t s) {
     hipLaunchKernelGGL(k_summary_reduce, dim3(1), dim3(256), 0, s, static_cast<const SolvePartial*>(w.parts), nparts,
-                       w.summary);
+                       w.summary, host_out, tag);
     return check_launch("solve summary reduction");
 }
 

@@ -350,6 +350,30 @@ def test_solve_maxit_reports_not_converged():
         assert e.value.status == -5
 
 
+def test_solve_summaries_of_consecutive_calls():
+    """Each call's summary is its own: calls whose outcomes differ alternate,
+    and every returned summary equals the expected outcome and the summary
+    read back from the plan's device copy."""
+    torch = _torch()
+    wl = workloads.random_blocks(7, 8, seed=13, h_range=(0.5, 4.0), with_rhs=True)
+    with make_plan(wl) as plan:
+        plan.setup_inverse()
+        bb = to_blocked(plan, canon([wl.groups[0].b]), tpfdm.F64)
+        bx = torch.zeros_like(bb)
+        for k in range(12):
+            bx.zero_()
+            if k % 2 == 0:
+                s = plan.solve(bb, bx, inner=tpfdm.F32, rtol=1e-14, maxit=1, raise_on_failure=False)
+                assert s["status"] == "TP_ERR_NOT_CONVERGED" and s["n_failed"] == 8 and s["max_iters"] == 1
+            else:
+                s = plan.solve(bb, bx, inner=tpfdm.F32, rtol=1e-10, maxit=20)
+                assert s["status"] == "TP_OK" and s["n_failed"] == 0 and s["max_iters"] >= 2
+                assert s["max_relres"] <= 1e-10
+            d = plan.solve_summary()
+            assert (d["max_iters"], d["n_failed"], d["max_relres"]) == (s["max_iters"], s["n_failed"],
+                                                                       s["max_relres"])
+
+
 def test_solve_nonfinite_rhs_is_reported():
     torch = _torch()
     wl = workloads.random_blocks(3, 10, seed=14, with_rhs=True)
