@@ -625,7 +625,7 @@ def run_suite(args, stream):
             for k in range(3):
                 plan.apply(U[k % R], V[k % R], tpfdm.OP_NEUMANN, stream=stream)
                 plan.apply_inverse(V[k % R], X[k % R], stream=stream)
-            reps = max(args.steps, 20)
+            reps = max(args.steps, 100)
             ms_a = time_launches(lambda k: plan.apply(U[k], V[k], tpfdm.OP_NEUMANN, stream=stream), stream, reps, R)
             ms_i = time_launches(lambda k: plan.apply_inverse(V[k], X[k], stream=stream), stream, reps, R)
             # a plain device copy of the same vector: the bandwidth reachable at this size
