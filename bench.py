@@ -755,11 +755,15 @@ def run_pcg(args, stream):
         x = torch.empty_like(b)
         solver = tpfdm.PCG(plan)
         mg = tpfdm.MG(plan) if serve.uses_multigrid(p, m) and basis == "lagrange" or p <= 3 else None
+        # the FP32-inner solves keep the level vectors in FP32 where they can (n <= 4)
+        mg32 = (tpfdm.MG(plan, storage=tpfdm.F32)
+                if mg is not None and serve.mg_storage(p, tpfdm.F32) == tpfdm.F32 else None)
         preconds = (("mg",) if (p, m) in PCG_MG_ONLY or basis == "hermite"
                     else ("block_jacobi", "mg") if mg else ("block_jacobi",))
         for precond in preconds:
-            solver.set_multigrid(mg if precond == "mg" else None)
             for inner in (tpfdm.F64, tpfdm.F32):
+                V = (mg32 or mg) if inner == tpfdm.F32 else mg
+                solver.set_multigrid(V if precond == "mg" else None)
                 reps = 30 if m <= 24 or (precond == "mg" and m <= 48) else 10
                 lat, s = [], None
                 for i in range(reps + 2):
@@ -773,13 +777,15 @@ def run_pcg(args, stream):
                 p50 = float(np.percentile(lat, 50))
                 print(json.dumps({"workload": f"pcg_p{p}_{m}cube", "basis": basis, "precond": precond,
                                   "inner": tpfdm.DTYPE_NAMES[inner], "ndof": mesh.ndof,
+                                  "level_storage": (tpfdm.DTYPE_NAMES[V.storage] if precond == "mg" else None),
                                   "iterations": s["iterations"], "relres": s["relres"],
                                   "p50_ms": p50, "p99_ms": float(np.percentile(lat, 99)),
                                   "ms_per_iteration": p50 / max(1, s["iterations"]),
                                   "solves_per_s": 1e3 / p50}), flush=True)
         solver.destroy()
-        if mg:
-            mg.destroy()
+        for V in (mg, mg32):
+            if V is not None:
+                V.destroy()
         plan.destroy()
         del b, x
         torch.cuda.empty_cache()

@@ -50,22 +50,29 @@ namespace {
 __device__ __forceinline__ bool done_flag(const PcgState* st) { return st && st->done; }
 
 // Level vectors are stored in TS (double, or float for the FP32-storage
-// hierarchy); every kernel computes in FP64 (the smoother's block inverse in
-// TI) and rounds only where it stores.
+// hierarchy).  The operator rows of the smoother and of the residual are
+// computed in MgTC<TS>: FP64 for FP64 storage, FP32 for FP32 storage (there
+// the level vectors carry FP32 rounding already, and the FP32 rows take half
+// the registers and LDS of FP64 ones); the smoother's block inverse runs in
+// TI, the transfers and the first update in FP64, and every kernel rounds
+// only where it stores.
+template <typename TS>
+using MgTC = typename std::conditional<std::is_same<TS, float>::value, float, double>::type;
 
 // t = A u on one level (one cell per lane); the consumers form b - t as
 // they load, which keeps b out of this kernel's registers.
 template <int N, bool HERM, typename TS>
 __global__ __launch_bounds__(64, 2) void k_mg_apply(const TS* __restrict__ u, TS* __restrict__ t, MeshArgs G,
-                                                  Pair<N, double> R, FaceRef<N, double> F,
+                                                  Pair<N, MgTC<TS>> R, FaceRef<N, MgTC<TS>> F,
                                                   const PcgState* __restrict__ st) {
+    using TC = MgTC<TS>;
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
-    __shared__ double sa[N * N][64], sbt[N * N][64];
+    __shared__ TC sa[N * N][64], sbt[N * N][64];
     const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, TS, HERM>(G))) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
-    double acc[N3];
-    sipg_cell<N, TS, double, -1, HERM>(u, G, R, F, c, acc, sa, sbt);
+    TC acc[N3];
+    sipg_cell<N, TS, TC, -1, HERM>(u, G, R, F, c, acc, sa, sbt);
     const int64_t base = G.offset + block_base(c, 6, N3);
 #pragma unroll
     for (int e = 0; e < N3; ++e) {
@@ -101,21 +108,22 @@ __global__ __launch_bounds__(64, 2) void k_mg_jacobi0(const TS* __restrict__ b, 
 // lanes still read u_in).
 template <int N, typename TI, bool HERM, typename TS>
 __global__ __launch_bounds__(64, 2) void k_mg_smooth(const TS* __restrict__ b, const TS* __restrict__ uin,
-                                                   TS* __restrict__ uout, MeshArgs G, Pair<N, double> R,
-                                                   FaceRef<N, double> F, Eig<N, TI> E, double omega,
+                                                   TS* __restrict__ uout, MeshArgs G, Pair<N, MgTC<TS>> R,
+                                                   FaceRef<N, MgTC<TS>> F, Eig<N, TI> E, double omega,
                                                    const PcgState* __restrict__ st) {
+    using TC = MgTC<TS>;
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
-    __shared__ double sa[N * N][64], sbt[N * N][64];
+    __shared__ TC sa[N * N][64], sbt[N * N][64];
     const int64_t c = static_cast<int64_t>(lane_tile(blockIdx.x, gridDim.x, plane_tiles<N, TS, HERM>(G))) * 64 + threadIdx.x;
     if (c >= G.ncells) return;
-    double acc[N3];
-    sipg_cell<N, TS, double, -1, HERM>(uin, G, R, F, c, acc, sa, sbt);
+    TC acc[N3];
+    sipg_cell<N, TS, TC, -1, HERM>(uin, G, R, F, c, acc, sa, sbt);
     const int64_t base = G.offset + block_base(c, 6, N3);
     TI v[N3];
 #pragma unroll
     for (int e = 0; e < N3; ++e)
-        v[e] = static_cast<TI>(static_cast<double>(b[base + (static_cast<int64_t>(e) << 6)]) - acc[e]);
+        v[e] = static_cast<TI>(static_cast<TC>(b[base + (static_cast<int64_t>(e) << 6)]) - acc[e]);
     lane_fdm_inplace<N, TI>(v, E, static_cast<TI>(G.sx), static_cast<TI>(G.sy), static_cast<TI>(G.sz));
 #pragma unroll
     for (int e = 0; e < N3; ++e) {
@@ -708,9 +716,9 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const TS* b, TS* u, const PcgSt
                            L.G.logB, st);
         return check_launch("coarse solve");
     }
-    Pair<N, double> R;
-    FaceRef<N, double> F;
-    sipg_tables<N, double>(plan, false, R, F);
+    Pair<N, MgTC<TS>> R;
+    FaceRef<N, MgTC<TS>> F;
+    sipg_tables<N, MgTC<TS>>(plan, false, R, F);
     Eig<N, TI> E;
     for (int i = 0; i < N * N; ++i) E.s[i] = static_cast<TI>(plan.ref[N].S[i]);
     for (int i = 0; i < N; ++i) E.lam[i] = static_cast<TI>(plan.ref[N].lam[i]);

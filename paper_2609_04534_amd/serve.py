@@ -44,7 +44,7 @@ class _Slot:
     stream; with multigrid, the slot's own V-cycle object (its level vectors
     are scratch that concurrent solves must not share)."""
 
-    def __init__(self, plan, p, m, multigrid):
+    def __init__(self, plan, p, m, multigrid, storage=tpfdm.F64):
         import torch
         self.plan = plan
         self.cls = (p, m)
@@ -52,7 +52,7 @@ class _Slot:
         self.solver = tpfdm.PCG(plan)
         self.mg = None
         if multigrid:
-            self.mg = tpfdm.MG(plan)
+            self.mg = tpfdm.MG(plan, storage)
             self.solver.set_multigrid(self.mg)
         E = plan.vector_elems
         self.b = torch.empty(E, dtype=torch.float64, device="cuda")
@@ -77,16 +77,24 @@ def uses_multigrid(p: int, m: int) -> bool:
     return odd ** 3 * (p + 1) ** 3 <= 2048 or (p >= 4 and odd ** 3 * 8 <= 2048)
 
 
-def mg_bytes(p: int, m: int) -> int:
+def mg_storage(p: int, inner: int) -> int:
+    """Element type of a slot's multigrid level vectors: FP32 when the solve's
+    inner precision is below FP64 and the degree has FP32 level storage
+    (n <= 4), FP64 otherwise."""
+    return tpfdm.F32 if inner != tpfdm.F64 and p + 1 <= 4 else tpfdm.F64
+
+
+def mg_bytes(p: int, m: int, storage: int = tpfdm.F64) -> int:
     """Device memory of a V-cycle object on an m^3 cube: a residual vector on
     every level plus right-hand side and correction below the finest (the
-    shared coarse inverse is not counted)."""
+    shared coarse inverse is not counted), in the level storage type."""
     n3 = (p + 1) ** 3
     B = tpfdm.default_layout_B(p + 1)
+    es = 4 if storage == tpfdm.F32 else 8
     total, ml, first = 0, m, True
     while True:
         E = (ml ** 3 + B - 1) // B * B * n3
-        total += (1 if first else 3) * E * 8
+        total += (1 if first else 3) * E * es
         first = False
         if ml % 2:
             break
@@ -94,26 +102,27 @@ def mg_bytes(p: int, m: int) -> int:
     return total
 
 
-def slot_bytes(plan, p: int = None, m: int = None, multigrid: bool = False) -> int:
+def slot_bytes(plan, p: int = None, m: int = None, multigrid: bool = False, storage: int = tpfdm.F64) -> int:
     """Device memory of one slot: the solver's five vectors and partials plus
-    b and x, and the V-cycle's levels when it has one."""
-    return _slot_bytes(plan.vector_elems, plan.nblocks, p, m, multigrid)
+    b and x, and the V-cycle's levels (of the given storage type) when it
+    has one."""
+    return _slot_bytes(plan.vector_elems, plan.nblocks, p, m, multigrid, storage)
 
 
-def class_slot_bytes(p: int, m: int, multigrid: bool = False) -> int:
+def class_slot_bytes(p: int, m: int, multigrid: bool = False, storage: int = tpfdm.F64) -> int:
     """slot_bytes of the mesh class (p, m) in the default layout, computed
     without creating its plan."""
     n = p + 1
     B = tpfdm.default_layout_B(n)
     ncell = m ** 3
-    return _slot_bytes((ncell + B - 1) // B * B * n ** 3, ncell, p, m, multigrid)
+    return _slot_bytes((ncell + B - 1) // B * B * n ** 3, ncell, p, m, multigrid, storage)
 
 
-def _slot_bytes(E, nblocks, p, m, multigrid):
+def _slot_bytes(E, nblocks, p, m, multigrid, storage=tpfdm.F64):
     nwg = (nblocks + 63) // 64
     out = 7 * E * 8 + 3 * nwg * 8 + 256
     if multigrid:
-        out += mg_bytes(p, m)
+        out += mg_bytes(p, m, storage)
     return out
 
 
@@ -149,29 +158,34 @@ class Server:
         if self.free.get(key):
             return self.free[key].pop()
         mgc = self._mg(p, m)
-        need = slot_bytes(self._plan(p, m), p, m, mgc)
+        st = mg_storage(p, self.inner)
+        need = slot_bytes(self._plan(p, m), p, m, mgc, st)
         for k in list(self.free):
             while self.used + need > self.budget and self.free[k]:
                 s = self.free[k].pop()
-                self.used -= slot_bytes(s.plan, *s.cls, s.mg is not None)
+                self.used -= slot_bytes(s.plan, *s.cls, s.mg is not None,
+                                        s.mg.storage if s.mg is not None else tpfdm.F64)
                 s.destroy()
         if self.used + need > self.budget:
             return None
         self.used += need
-        return _Slot(self._plan(p, m), p, m, mgc)
+        return _Slot(self._plan(p, m), p, m, mgc, st)
 
     def _mg(self, p, m):
         return self.multigrid and uses_multigrid(p, m)
+
+    def _class_bytes(self, p, m):
+        return class_slot_bytes(p, m, self._mg(p, m), mg_storage(p, self.inner))
 
     def _admit(self, req, now):
         """True when the request leaves the queue: admitted, or rejected
         because its slot alone needs more than the whole budget (it could
         never run, and first-in-first-out admission would stall behind it)."""
-        if class_slot_bytes(req.p, req.m, self._mg(req.p, req.m)) > self.budget:
+        if self._class_bytes(req.p, req.m) > self.budget:
             req.rejected = True
             req.start = req.done = now
             req.summary = {"status": "rejected", "converged": False, "iterations": 0,
-                           "reason": f"slot of {class_slot_bytes(req.p, req.m, self._mg(req.p, req.m))} bytes exceeds "
+                           "reason": f"slot of {self._class_bytes(req.p, req.m)} bytes exceeds "
                                      f"the budget of {self.budget} bytes"}
             self.rejected += 1
             return True

@@ -20,7 +20,8 @@ def _alone(req, inner, multigrid):
         bb = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
         plan.pack(req.b, bb)
         bx = torch.empty_like(bb)
-        mg = tpfdm.MG(plan) if multigrid and serve.uses_multigrid(req.p, req.m) else None
+        mg = (tpfdm.MG(plan, serve.mg_storage(req.p, inner))
+              if multigrid and serve.uses_multigrid(req.p, req.m) else None)
         with tpfdm.PCG(plan) as solver:
             solver.set_multigrid(mg)
             s = solver.solve(bb, bx, inner=inner, rtol=1e-8, maxit=20000, check_every=4 if mg else 8)

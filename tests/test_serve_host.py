@@ -1,7 +1,7 @@
 """Host-side admission logic of the serving loop (no GPU): a request whose
 solver slot alone exceeds the memory budget is rejected instead of blocking
 the first-in-first-out queue behind it."""
-from paper_2609_04534_amd import serve
+from paper_2609_04534_amd import serve, tpfdm
 
 
 def test_class_slot_bytes_matches_the_layout():
@@ -36,3 +36,14 @@ def test_every_class_of_the_serving_mix_uses_multigrid():
     assert not serve.uses_multigrid(7, 7)      # 343 cells: 2744 unknowns even at degree 1
     assert not serve.uses_multigrid(3, 5)      # 125 cells of degree 3 (lane kernels keep their degree)
     assert serve.uses_multigrid(4, 40)         # odd part 5: 125 cells x 8 = 1000
+
+
+def test_multigrid_level_storage_follows_the_inner_precision():
+    """Slots of an FP32-inner server keep FP32 multigrid level vectors where
+    the library has them (n <= 4), at half the bytes; n = 8 stays FP64."""
+    assert serve.mg_storage(2, tpfdm.F32) == tpfdm.F32 and serve.mg_storage(3, tpfdm.F32) == tpfdm.F32
+    assert serve.mg_storage(3, tpfdm.F64) == tpfdm.F64
+    assert serve.mg_storage(7, tpfdm.F32) == tpfdm.F64
+    assert 2 * serve.mg_bytes(3, 16, tpfdm.F32) == serve.mg_bytes(3, 16)
+    assert (serve.class_slot_bytes(3, 16, True, tpfdm.F32) - serve.class_slot_bytes(3, 16)
+            == serve.mg_bytes(3, 16, tpfdm.F32))
