@@ -755,9 +755,8 @@ def run_pcg(args, stream):
         x = torch.empty_like(b)
         solver = tpfdm.PCG(plan)
         mg = tpfdm.MG(plan) if serve.uses_multigrid(p, m) and basis == "lagrange" or p <= 3 else None
-        # the FP32-inner solves keep the level vectors in FP32 where they can (n <= 4)
-        mg32 = (tpfdm.MG(plan, storage=tpfdm.F32)
-                if mg is not None and serve.mg_storage(p, tpfdm.F32) == tpfdm.F32 else None)
+        # the FP32-inner solves keep the level vectors in FP32
+        mg32 = tpfdm.MG(plan, storage=serve.mg_storage(p, tpfdm.F32)) if mg is not None else None
         preconds = (("mg",) if (p, m) in PCG_MG_ONLY or basis == "hermite"
                     else ("block_jacobi", "mg") if mg else ("block_jacobi",))
         for precond in preconds:

@@ -1,4 +1,4 @@
-// Geometric multigrid for the coupled SIPG operator of a mesh plan (n <= 4):
+// Geometric multigrid for the coupled SIPG operator of a mesh plan (n <= 8):
 // the V-cycle the paper uses to precondition CG (Sec. 5, Sec. 6.1).
 //
 // Levels: the plan's box and its uniform coarsenings (cells halved in every
@@ -21,8 +21,9 @@
 // dense inverse, assembled once by applying the level operator to unit
 // vectors (as the paper assembles its coarse LU) and inverted on the host.
 //
-// Every vector of a level is in the B = 64 blocked layout, one cell per lane;
-// every kernel returns at once when the solve state passed to it is done,
+// For n <= 4 every vector of a level is in the B = 64 blocked layout, one
+// cell per lane; for n >= 5 in the B = 1 layout, one cell per wave.  Every
+// kernel returns at once when the solve state passed to it is done,
 // so a V-cycle can sit inside a captured chunk of CG iterations.
 #include <algorithm>
 #include <cmath>
@@ -279,7 +280,8 @@ __global__ __launch_bounds__(64) void k_mg_dot(const double* __restrict__ a, con
 }
 
 // ---------------------------------------------------------------- n >= 5
-// One cell per wave (layout B = 1, FP64 level vectors): lane (a, b) owns
+// One cell per wave (layout B = 1, FP64 or FP32 level vectors; the
+// operator rows in the storage type, the transfers in FP64): lane (a, b) owns
 // the z-pencil (a, b, 0..n-1) of the cell for loads and stores; the
 // operator row is the wave body of the coupled operator (wave_sipg_cell,
 // output by x-pencils), the block inverse the even-odd fast
@@ -292,23 +294,37 @@ __device__ __forceinline__ int64_t zpencil_base(const MeshArgs& G, int64_t c, co
     return G.offset + block_base(c, G.logB, N * N * N) + (static_cast<int64_t>((pc.pa * N + pc.pb) * N) << G.logB);
 }
 
-// t = A u, one cell per wave.
-template <int N, bool VP>
-__global__ __launch_bounds__(64, 2) void k_mg_apply_wave(const double* __restrict__ u, double* __restrict__ t,
-                                                       MeshArgs G, const double* __restrict__ tab,
-                                                       FaceRef<N, double> F, const PcgState* __restrict__ st) {
+// The even-odd tables of a wave operator row: FP64 ones are read where they
+// are used at wave-uniform global addresses (scalar loads), FP32 ones are
+// loaded into registers once.
+template <typename T, int TAB>
+__device__ __forceinline__ const T* wave_row_tables(T (&regs)[sizeof(T) == 8 ? 1 : TAB], const T* tab) {
+    if constexpr (sizeof(T) == 8) {
+        return tab;
+    } else {
+        load_table<T, TAB>(regs, tab, nullptr);
+        return regs;
+    }
+}
+
+// t = A u, one cell per wave; the row in the level storage type T.
+template <int N, bool VP, typename T = double>
+__global__ __launch_bounds__(64, 2) void k_mg_apply_wave(const T* __restrict__ u, T* __restrict__ t,
+                                                       MeshArgs G, const T* __restrict__ tab,
+                                                       FaceRef<N, T> F, const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
     constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
-    __shared__ WaveLds<N, double> L;
-    static_assert(TAB > 0, "table");   // read at wave-uniform global addresses (scalar loads)
+    __shared__ WaveLds<N, T> L;
+    T regs[sizeof(T) == 8 ? 1 : TAB];
+    const T* tb = wave_row_tables<T, TAB>(regs, tab);
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
-    double y[N];
-    wave_sipg_cell<N, double, VP, false>(u, G, tab, F, c, L, y);
+    T y[N];
+    wave_sipg_cell<N, T, VP, false>(u, G, tb, F, c, L, y);
     const Pencil<N> pc(1);
     if (pc.act) {
-        double* tb = t + G.offset + block_base(c, G.logB, N * N * N);
+        T* out = t + G.offset + block_base(c, G.logB, N * N * N);
 #pragma unroll
-        for (int i = 0; i < N; ++i) tb[static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << G.logB] = y[i];
+        for (int i = 0; i < N; ++i) out[static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << G.logB] = y[i];
     }
 }
 
@@ -326,8 +342,8 @@ __device__ __forceinline__ void wave_block_inverse(const Pencil<N>& pc, TI* slab
 }
 
 // u = omega D^{-1} b (the first Chebyshev update from u = 0), one cell per wave.
-template <int N, typename TI, bool VP>
-__global__ __launch_bounds__(64, 2) void k_mg_jacobi0_wave(const double* __restrict__ b, double* __restrict__ u,
+template <int N, typename TI, bool VP, typename TS = double>
+__global__ __launch_bounds__(64, 2) void k_mg_jacobi0_wave(const TS* __restrict__ b, TS* __restrict__ u,
                                                          MeshArgs G, const TI* __restrict__ tabS, double omega,
                                                          const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -357,27 +373,31 @@ __global__ __launch_bounds__(64, 2) void k_mg_jacobi0_wave(const double* __restr
 // One Chebyshev update u_out = u_in + omega D^{-1} (b - A u_in) of the
 // wave's cell: the operator row by x-pencils, the residual into the slab in
 // precision TI, the block inverse, the update by z-pencils.
-template <int N, typename TI, bool VP>
-__global__ __launch_bounds__(64, 2) void k_mg_smooth_wave(const double* __restrict__ b,
-                                                        const double* __restrict__ uin, double* __restrict__ uout,
-                                                        MeshArgs G, const double* __restrict__ tab,
-                                                        FaceRef<N, double> F, const TI* __restrict__ tabS,
+template <int N, typename TI, bool VP, typename T = double>
+__global__ __launch_bounds__(64, 2) void k_mg_smooth_wave(const T* __restrict__ b,
+                                                        const T* __restrict__ uin, T* __restrict__ uout,
+                                                        MeshArgs G, const T* __restrict__ tab,
+                                                        FaceRef<N, T> F, const TI* __restrict__ tabS,
                                                         double omega, const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
     using SL = Slab<N>;
     constexpr int TAB = 2 * (EOShape<N>::SE + EOShape<N>::SO);
     constexpr int TABM = EOShape<N>::SE + EOShape<N>::SO;
-    static_assert(SL::size * sizeof(TI) <= sizeof(WaveLds<N, double>::t), "slab exceeds the volume scratch");
-    __shared__ WaveLds<N, double> L;
+    __shared__ __align__(16) WaveLds<N, T> L;
+    // the inverse's slab: the face scratch when it fits there, else the
+    // whole (by then free) operator scratch, block slab included
+    constexpr bool kInT = SL::size * sizeof(TI) <= sizeof(WaveLds<N, T>::t);
+    static_assert(SL::size * sizeof(TI) <= sizeof(WaveLds<N, T>), "slab exceeds the operator scratch");
     __shared__ TI stab[TABM + N];
-    static_assert(TAB > 0, "table");   // read at wave-uniform global addresses (scalar loads)
     for (int e = threadIdx.x; e < TABM + N; e += 64) stab[e] = tabS[e];
+    T regs[sizeof(T) == 8 ? 1 : TAB];
+    const T* tb = wave_row_tables<T, TAB>(regs, tab);
     const int64_t c = xcd_tile(blockIdx.x, gridDim.x);
-    double y[N];
-    wave_sipg_cell<N, double, VP, false>(uin, G, tab, F, c, L, y);   // ends synced
+    T y[N];
+    wave_sipg_cell<N, T, VP, false>(uin, G, tb, F, c, L, y);   // ends synced
     const Pencil<N> pc(1);
-    TI* slab = reinterpret_cast<TI*>(L.t);
-    const double* bb = b + G.offset + block_base(c, G.logB, N * N * N);
+    TI* slab = kInT ? reinterpret_cast<TI*>(L.t) : reinterpret_cast<TI*>(&L);
+    const T* bb = b + G.offset + block_base(c, G.logB, N * N * N);
     if (pc.act)
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -444,9 +464,9 @@ __device__ __forceinline__ void wave_kron3(const Pencil<N>& pc, double* slab, co
 
 // b_coarse = P^T (b_fine - t_fine), one coarse cell per wave, summed over
 // its eight children.
-template <int N, bool VP>
-__global__ __launch_bounds__(64, 2) void k_mg_restrict_wave(const double* __restrict__ bf,
-                                                          const double* __restrict__ tf, double* __restrict__ bc,
+template <int N, bool VP, typename TS = double>
+__global__ __launch_bounds__(64, 2) void k_mg_restrict_wave(const TS* __restrict__ bf,
+                                                          const TS* __restrict__ tf, TS* __restrict__ bc,
                                                           MeshArgs Gf, MeshArgs Gc, ProlTab<N> PT,
                                                           const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -482,16 +502,17 @@ __global__ __launch_bounds__(64, 2) void k_mg_restrict_wave(const double* __rest
             for (int i = 0; i < N; ++i) acc[i] += out[i];
     }
     if (pc.act) {
-        double* cb = bc + Gc.offset + block_base(c, Gc.logB, N * N * N);
+        TS* cb = bc + Gc.offset + block_base(c, Gc.logB, N * N * N);
 #pragma unroll
-        for (int i = 0; i < N; ++i) cb[static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << Gc.logB] = acc[i];
+        for (int i = 0; i < N; ++i)
+            cb[static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << Gc.logB] = static_cast<TS>(acc[i]);
     }
 }
 
 // u_out = u_fine + P u_coarse, one fine cell per wave.
-template <int N, bool VP>
-__global__ __launch_bounds__(64, 2) void k_mg_prolong_wave(const double* __restrict__ uc,
-                                                         const double* __restrict__ uf, double* __restrict__ uout,
+template <int N, bool VP, typename TS = double>
+__global__ __launch_bounds__(64, 2) void k_mg_prolong_wave(const TS* __restrict__ uc,
+                                                         const TS* __restrict__ uf, TS* __restrict__ uout,
                                                          MeshArgs Gf, MeshArgs Gc, ProlTab<N> P,
                                                          const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -515,14 +536,14 @@ __global__ __launch_bounds__(64, 2) void k_mg_prolong_wave(const double* __restr
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const int64_t o = base + (static_cast<int64_t>((i * N + pc.pa) * N + pc.pb) << Gf.logB);
-            uout[o] = uf[o] + out[i];
+            uout[o] = static_cast<TS>(static_cast<double>(uf[o]) + out[i]);
         }
     }
 }
 
 // Partial (a, b) per cell, one cell per wave.
-template <int N, bool VP>
-__global__ __launch_bounds__(64) void k_mg_dot_wave(const double* __restrict__ a, const double* __restrict__ b,
+template <int N, bool VP, typename TB = double>
+__global__ __launch_bounds__(64) void k_mg_dot_wave(const double* __restrict__ a, const TB* __restrict__ b,
                                                     MeshArgs G, double* __restrict__ part,
                                                     const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -553,8 +574,8 @@ struct DegTab {
 };
 
 // bc = E^T (b - t), one thread per coarse unknown (cell, jx, jy, jz).
-template <int N>
-__global__ __launch_bounds__(64) void k_mg_deg_restrict(const double* __restrict__ b, const double* __restrict__ t,
+template <int N, typename TS = double>
+__global__ __launch_bounds__(64) void k_mg_deg_restrict(const TS* __restrict__ b, const TS* __restrict__ t,
                                                         double* __restrict__ bc, MeshArgs G, DegTab<N> E,
                                                         const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
@@ -569,16 +590,16 @@ __global__ __launch_bounds__(64) void k_mg_deg_restrict(const double* __restrict
             const double wab = E.e[a][jx] * E.e[q][jy];
             for (int k = 0; k < N; ++k) {
                 const int64_t o = base + (static_cast<int64_t>((a * N + q) * N + k) << G.logB);
-                s = fma(wab * E.e[k][jz], b[o] - t[o], s);
+                s = fma(wab * E.e[k][jz], static_cast<double>(b[o]) - static_cast<double>(t[o]), s);
             }
         }
     bc[idx] = s;
 }
 
 // uout = u + E uc, one thread per fine unknown.
-template <int N>
-__global__ __launch_bounds__(64) void k_mg_deg_prolong(const double* __restrict__ uc, const double* __restrict__ u,
-                                                       double* __restrict__ uout, MeshArgs G, DegTab<N> E,
+template <int N, typename TS = double>
+__global__ __launch_bounds__(64) void k_mg_deg_prolong(const double* __restrict__ uc, const TS* __restrict__ u,
+                                                       TS* __restrict__ uout, MeshArgs G, DegTab<N> E,
                                                        const PcgState* __restrict__ st) {
     if (done_flag(st)) return;
     constexpr int N3 = N * N * N;
@@ -592,7 +613,7 @@ __global__ __launch_bounds__(64) void k_mg_deg_prolong(const double* __restrict_
 #pragma unroll
     for (int j = 0; j < 8; ++j) s = fma(E.e[a][j >> 2] * E.e[y][(j >> 1) & 1] * E.e[k][j & 1], v[j], s);
     const int64_t o = G.offset + block_base(c, G.logB, N3) + (static_cast<int64_t>(q) << G.logB);
-    uout[o] = u[o] + s;
+    uout[o] = static_cast<TS>(static_cast<double>(u[o]) + s);
 }
 
 template <int N>
@@ -753,51 +774,53 @@ tp_status vcycle_level(const tp_mg* m, size_t l, const TS* b, TS* u, const PcgSt
     return check_launch("smoothing");
 }
 
-// The same V-cycle for n >= 5 on the wave kernels (FP64 level vectors,
-// layout B = 1: pencils move as 16-byte vectors).
-template <int N, typename TI, bool VP>
-tp_status vcycle_level_wave(const tp_mg* m, size_t l, const double* b, double* u, const PcgState* st,
+// The same V-cycle for n >= 5 on the wave kernels (layout B = 1: pencils
+// move as 16-byte vectors where VP), level vectors and operator rows in TS
+// (FP64, or FP32 for the FP32-storage hierarchy).
+template <int N, typename TI, bool VP, typename TS>
+tp_status vcycle_level_wave(const tp_mg* m, size_t l, const TS* b, TS* u, const PcgState* st,
                             hipStream_t s) {
     const Plan& plan = *m->plan;
     const MgLevel& L = m->lv[l];
-    double* Lt = static_cast<double*>(L.t);
+    TS* Lt = static_cast<TS*>(L.t);
     const unsigned grid = static_cast<unsigned>(L.G.ncells);
     const bool last = l + 1 == m->lv.size();
     if (last && !m->deg) {
         const unsigned cg = static_cast<unsigned>((m->n0 + 255) / 256);
-        hipLaunchKernelGGL((k_mg_coarse<N, double>), dim3(cg), dim3(256), 0, s, m->coarse_inv, b, u, m->n0,
+        hipLaunchKernelGGL((k_mg_coarse<N, TS>), dim3(cg), dim3(256), 0, s, m->coarse_inv, b, u, m->n0,
                            L.G.offset, L.G.logB, st);
         return check_launch("coarse solve");
     }
-    FaceRef<N, double> F;
+    FaceRef<N, TS> F;
     {
-        Pair<N, double> R;
-        sipg_tables<N, double>(plan, false, R, F);
+        Pair<N, TS> R;
+        sipg_tables<N, TS>(plan, false, R, F);
     }
-    const double* tabA = reinterpret_cast<const double*>(eo_table(plan, N, EO_APPLY_A, 0));
+    const TS* tabA = reinterpret_cast<const TS*>(eo_table(plan, N, EO_APPLY_A, sizeof(TS) == 8 ? 0 : 1));
     const TI* tabS = reinterpret_cast<const TI*>(eo_table(plan, N, EO_INV, sizeof(TI) == 8 ? 0 : 1));
     ProlTab<N> P, PT;
     for (int i = 0; i < N * N; ++i) P.p[0][i] = plan.ref[N].P0[i], P.p[1][i] = plan.ref[N].P1[i];
     for (int c = 0; c < 2; ++c)
         for (int i = 0; i < N; ++i)
             for (int j = 0; j < N; ++j) PT.p[c][i * N + j] = P.p[c][j * N + i];
-    auto step = [&](const double* from, double* to, int j) {
-        hipLaunchKernelGGL((k_mg_smooth_wave<N, TI, VP>), dim3(grid), dim3(64), 0, s, b, from, to, L.G, tabA, F,
+    auto step = [&](const TS* from, TS* to, int j) {
+        hipLaunchKernelGGL((k_mg_smooth_wave<N, TI, VP, TS>), dim3(grid), dim3(64), 0, s, b, from, to, L.G, tabA, F,
                            tabS, m->omega[j], st);
     };
-    hipLaunchKernelGGL((k_mg_jacobi0_wave<N, TI, VP>), dim3(grid), dim3(64), 0, s, b, u, L.G, tabS, m->omega[0], st);
+    hipLaunchKernelGGL((k_mg_jacobi0_wave<N, TI, VP, TS>), dim3(grid), dim3(64), 0, s, b, u, L.G, tabS, m->omega[0],
+                       st);
     step(u, Lt, 1);
     step(Lt, u, 2);
     if (last) {
         // coarse correction on the degree-1 level: E^T (b - A u), its dense
         // solve, u + E u_c
         const DegTab<N> E = deg_table<N>();
-        hipLaunchKernelGGL((k_mg_apply_wave<N, VP>), dim3(grid), dim3(64), 0, s, u, Lt, L.G, tabA, F, st);
-        hipLaunchKernelGGL((k_mg_deg_restrict<N>), dim3(static_cast<unsigned>((m->n0 + 63) / 64)), dim3(64), 0, s, b,
-                           Lt, m->deg_b, L.G, E, st);
+        hipLaunchKernelGGL((k_mg_apply_wave<N, VP, TS>), dim3(grid), dim3(64), 0, s, u, Lt, L.G, tabA, F, st);
+        hipLaunchKernelGGL((k_mg_deg_restrict<N, TS>), dim3(static_cast<unsigned>((m->n0 + 63) / 64)), dim3(64), 0, s,
+                           b, Lt, m->deg_b, L.G, E, st);
         hipLaunchKernelGGL((k_mg_coarse<2, double>), dim3(static_cast<unsigned>((m->n0 + 255) / 256)), dim3(256), 0, s,
                            m->coarse_inv, m->deg_b, m->deg_u, m->n0, int64_t(0), 0, st);
-        hipLaunchKernelGGL((k_mg_deg_prolong<N>),
+        hipLaunchKernelGGL((k_mg_deg_prolong<N, TS>),
                            dim3(static_cast<unsigned>((L.G.ncells * N * N * N + 63) / 64)), dim3(64), 0, s, m->deg_u,
                            u, Lt, L.G, E, st);
         tp_status stt = check_launch("degree-level correction");
@@ -808,16 +831,16 @@ tp_status vcycle_level_wave(const tp_mg* m, size_t l, const double* b, double* u
         return check_launch("smoothing");
     }
     const MgLevel& C = m->lv[l + 1];
-    double* Cb = static_cast<double*>(C.b);
-    double* Cu = static_cast<double*>(C.u);
-    hipLaunchKernelGGL((k_mg_apply_wave<N, VP>), dim3(grid), dim3(64), 0, s, u, Lt, L.G, tabA, F, st);
-    hipLaunchKernelGGL((k_mg_restrict_wave<N, VP>), dim3(static_cast<unsigned>(C.G.ncells)), dim3(64), 0, s, b, Lt,
-                       Cb, L.G, C.G, PT, st);
+    TS* Cb = static_cast<TS*>(C.b);
+    TS* Cu = static_cast<TS*>(C.u);
+    hipLaunchKernelGGL((k_mg_apply_wave<N, VP, TS>), dim3(grid), dim3(64), 0, s, u, Lt, L.G, tabA, F, st);
+    hipLaunchKernelGGL((k_mg_restrict_wave<N, VP, TS>), dim3(static_cast<unsigned>(C.G.ncells)), dim3(64), 0, s, b,
+                       Lt, Cb, L.G, C.G, PT, st);
     tp_status stt = check_launch("level transfer");
     if (stt != TP_OK) return stt;
-    stt = vcycle_level_wave<N, TI, VP>(m, l + 1, Cb, Cu, st, s);
+    stt = vcycle_level_wave<N, TI, VP, TS>(m, l + 1, Cb, Cu, st, s);
     if (stt != TP_OK) return stt;
-    hipLaunchKernelGGL((k_mg_prolong_wave<N, VP>), dim3(grid), dim3(64), 0, s, Cu, u, Lt, L.G, C.G, P, st);
+    hipLaunchKernelGGL((k_mg_prolong_wave<N, VP, TS>), dim3(grid), dim3(64), 0, s, Cu, u, Lt, L.G, C.G, P, st);
     step(Lt, u, 0);
     step(u, Lt, 1);
     step(Lt, u, 2);
@@ -834,21 +857,23 @@ tp_status vcycle_dispatch(const tp_mg* m, const TS* b, TS* u, const PcgState* st
                                                       : vcycle_level<4, TI, false, TS>(m, 0, b, u, st, s);
         default: break;
     }
-    if constexpr (std::is_same<TS, double>::value) {
+    {
         // 16-byte pencil accesses when the caller's finest b and u allow them
-        // (the level vectors are allocation-aligned)
+        // (the level vectors are allocation-aligned) and a pencil is a whole
+        // number of 16-byte vectors
         const bool vp = reinterpret_cast<uintptr_t>(b) % 16 == 0 && reinterpret_cast<uintptr_t>(u) % 16 == 0;
+        constexpr bool v6 = (6 * sizeof(TS)) % 16 == 0;
         switch (m->n) {
-            case 5: return vcycle_level_wave<5, TI, false>(m, 0, b, u, st, s);
-            case 6: return vp ? vcycle_level_wave<6, TI, true>(m, 0, b, u, st, s)
-                              : vcycle_level_wave<6, TI, false>(m, 0, b, u, st, s);
-            case 7: return vcycle_level_wave<7, TI, false>(m, 0, b, u, st, s);
-            case 8: return vp ? vcycle_level_wave<8, TI, true>(m, 0, b, u, st, s)
-                              : vcycle_level_wave<8, TI, false>(m, 0, b, u, st, s);
+            case 5: return vcycle_level_wave<5, TI, false, TS>(m, 0, b, u, st, s);
+            case 6: return vp && v6 ? vcycle_level_wave<6, TI, v6, TS>(m, 0, b, u, st, s)
+                                    : vcycle_level_wave<6, TI, false, TS>(m, 0, b, u, st, s);
+            case 7: return vcycle_level_wave<7, TI, false, TS>(m, 0, b, u, st, s);
+            case 8: return vp ? vcycle_level_wave<8, TI, true, TS>(m, 0, b, u, st, s)
+                              : vcycle_level_wave<8, TI, false, TS>(m, 0, b, u, st, s);
             default: break;
         }
     }
-    return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 8, with FP32 level storage n <= 4");
+    return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 8");
 }
 
 template <int N>
@@ -1030,21 +1055,40 @@ tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const void* b, bool b3
             if (b32) hipLaunchKernelGGL((k_mg_dot<4, float>), dim3(grid), dim3(64), 0, s, a, bf, L.G, part, ps);
             else hipLaunchKernelGGL((k_mg_dot<4, double>), dim3(grid), dim3(64), 0, s, a, bd, L.G, part, ps);
             break;
-        case 5: hipLaunchKernelGGL((k_mg_dot_wave<5, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0, s,
-                                   a, bd, L.G, part, ps);
+        case 5:
+            if (b32)
+                hipLaunchKernelGGL((k_mg_dot_wave<5, false, float>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64),
+                                   0, s, a, bf, L.G, part, ps);
+            else
+                hipLaunchKernelGGL((k_mg_dot_wave<5, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0,
+                                   s, a, bd, L.G, part, ps);
             break;
-        case 6: hipLaunchKernelGGL((k_mg_dot_wave<6, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0, s,
-                                   a, bd, L.G, part, ps);
+        case 6:
+            if (b32)
+                hipLaunchKernelGGL((k_mg_dot_wave<6, false, float>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64),
+                                   0, s, a, bf, L.G, part, ps);
+            else
+                hipLaunchKernelGGL((k_mg_dot_wave<6, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0,
+                                   s, a, bd, L.G, part, ps);
             break;
-        case 7: hipLaunchKernelGGL((k_mg_dot_wave<7, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0, s,
-                                   a, bd, L.G, part, ps);
+        case 7:
+            if (b32)
+                hipLaunchKernelGGL((k_mg_dot_wave<7, false, float>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64),
+                                   0, s, a, bf, L.G, part, ps);
+            else
+                hipLaunchKernelGGL((k_mg_dot_wave<7, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0,
+                                   s, a, bd, L.G, part, ps);
             break;
-        case 8: hipLaunchKernelGGL((k_mg_dot_wave<8, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0, s,
-                                   a, bd, L.G, part, ps);
+        case 8:
+            if (b32)
+                hipLaunchKernelGGL((k_mg_dot_wave<8, false, float>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64),
+                                   0, s, a, bf, L.G, part, ps);
+            else
+                hipLaunchKernelGGL((k_mg_dot_wave<8, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0,
+                                   s, a, bd, L.G, part, ps);
             break;
         default: return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 8");
     }
-    if (m->n > kLaneMaxN && b32) return set_error(TP_ERR_UNSUPPORTED, "FP32 level storage needs n <= 4");
     return check_launch("dot");
 }
 
@@ -1074,8 +1118,6 @@ tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out) {
         return set_error(TP_ERR_UNSUPPORTED, "multigrid needs the layout B = 1 for n >= 5");
     if (g.n > kLaneMaxN && plan->basis == TP_BASIS_HERMITE)
         return set_error(TP_ERR_UNSUPPORTED, "multigrid in the Hermite-type basis supports n = 4");
-    if (g.n > kLaneMaxN && storage != TP_F64)
-        return set_error(TP_ERR_UNSUPPORTED, "FP32 level storage needs n <= 4");
     if (plan->inverse_op != TP_OP_CELL || plan->factor_mode != TP_FACTOR_SCALED)
         return set_error(TP_ERR_STATE, "multigrid needs tp_setup_inverse(TP_OP_CELL, TP_FACTOR_SCALED) first");
     tp_mg* m = new (std::nothrow) tp_mg();

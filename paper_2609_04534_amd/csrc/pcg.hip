@@ -679,12 +679,19 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
             else
                 hipLaunchKernelGGL((k_pcg_start_res_wave<N, false>), dim3(nwg), dim3(64), 0, stream, b,
                                    x_zero ? nullptr : s->q, x, s->xw, s->r, G, s->part, cnt);
-            tp_status st = mg_enqueue_vcycle(s->mg, s->r, s->z, nullptr, f32, stream);
-            if (st == TP_OK) st = mg_enqueue_dot(s->mg, s->r, s->z, false, s->part, nullptr, stream);
+            const bool z32 = mg_storage(s->mg) == TP_F32;
+            const void* zp = z32 ? static_cast<const void*>(mg_result32(s->mg)) : static_cast<const void*>(s->z);
+            tp_status st = mg_enqueue_vcycle(s->mg, s->r, z32 ? nullptr : s->z, nullptr, f32, stream);
+            if (st == TP_OK) st = mg_enqueue_dot(s->mg, s->r, zp, z32, s->part, nullptr, stream);
             if (st != TP_OK) return st;
-            const hipError_t e = hipMemcpyAsync(s->p, s->z, static_cast<size_t>(s->elems) * sizeof(double),
-                                                hipMemcpyDeviceToDevice, stream);
-            if (e != hipSuccess) return hip_error(e, "PCG start");
+            if (z32) {
+                st = mg_enqueue_widen(s->mg, s->p, stream);
+                if (st != TP_OK) return st;
+            } else {
+                const hipError_t e = hipMemcpyAsync(s->p, s->z, static_cast<size_t>(s->elems) * sizeof(double),
+                                                    hipMemcpyDeviceToDevice, stream);
+                if (e != hipSuccess) return hip_error(e, "PCG start");
+            }
         }
     } else if constexpr (kLane)
         hipLaunchKernelGGL((k_pcg_start<N, TI, LB>), dim3(nwg), dim3(64), 0, stream, b, x_zero ? nullptr : s->q, x,
@@ -744,8 +751,12 @@ tp_status pcg_prepare(const Plan& plan, const GroupInfo& g, tp_pcg* s, const dou
                         else
                             hipLaunchKernelGGL((k_pcg_axpy_wave<N, false>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r,
                                                s->p, s->q, G, s->st, s->part, cnt);
-                        (void)mg_enqueue_vcycle(s->mg, s->r, s->z, s->st, f32, cs);
-                        (void)mg_enqueue_dot(s->mg, s->r, s->z, false, s->part, s->st, cs);
+                        const bool z32 = mg_storage(s->mg) == TP_F32;
+                        (void)mg_enqueue_vcycle(s->mg, s->r, z32 ? nullptr : s->z, s->st, f32, cs);
+                        (void)mg_enqueue_dot(s->mg, s->r,
+                                             z32 ? static_cast<const void*>(mg_result32(s->mg))
+                                                 : static_cast<const void*>(s->z),
+                                             z32, s->part, s->st, cs);
                     } else {
                         hipLaunchKernelGGL((k_pcg_axpy<N, LB>), dim3(nwg), dim3(64), 0, cs, s->xw, s->r, s->p, s->q,
                                            G, s->st, s->part, cnt);

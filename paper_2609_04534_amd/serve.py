@@ -79,9 +79,8 @@ def uses_multigrid(p: int, m: int) -> bool:
 
 def mg_storage(p: int, inner: int) -> int:
     """Element type of a slot's multigrid level vectors: FP32 when the solve's
-    inner precision is below FP64 and the degree has FP32 level storage
-    (n <= 4), FP64 otherwise."""
-    return tpfdm.F32 if inner != tpfdm.F64 and p + 1 <= 4 else tpfdm.F64
+    inner precision is below FP64, FP64 otherwise (every degree)."""
+    return tpfdm.F32 if inner != tpfdm.F64 else tpfdm.F64
 
 
 def mg_bytes(p: int, m: int, storage: int = tpfdm.F64) -> int:

@@ -309,11 +309,13 @@ def test_nonfinite_rhs_is_reported(multigrid):
 
 
 # ------------------------------------------------------------------ FP32 level storage
-@pytest.mark.parametrize("p,m", [(1, 8), (2, 4), (3, 4), (3, 6)])
+@pytest.mark.parametrize("p,m", [(1, 8), (2, 4), (3, 4), (3, 6), (4, 4), (6, 2), (7, 2)])
 def test_vcycle_fp32_storage_matches_oracle(p, m):
-    """Level vectors stored in FP32 (tp_mg_create_typed): FP64 arithmetic,
-    rounded to FP32 where stored; the V-cycle agrees with the oracle's FP64
-    V-cycle to a few FP32 roundings of the solution's scale per sweep."""
+    """Level vectors stored in FP32 (tp_mg_create_typed), the smoother's and
+    the residual's operator rows computed in FP32, the transfers in FP64;
+    the V-cycle agrees with the oracle's FP64 V-cycle to a few FP32
+    roundings of the solution's scale per sweep (lane kernels for n <= 4,
+    wave kernels for n >= 5)."""
     torch = _torch()
     H = _hierarchy(p, m)
     nd = m ** 3 * (p + 1) ** 3
@@ -330,7 +332,8 @@ def test_vcycle_fp32_storage_matches_oracle(p, m):
     assert err <= 2e-5
 
 
-@pytest.mark.parametrize("p,m,inner", [(2, 8, tpfdm.F32), (3, 8, tpfdm.F32), (3, 4, tpfdm.F64)])
+@pytest.mark.parametrize("p,m,inner", [(2, 8, tpfdm.F32), (3, 8, tpfdm.F32), (3, 4, tpfdm.F64),
+                                       (4, 4, tpfdm.F32), (7, 2, tpfdm.F32), (7, 2, tpfdm.F64)])
 def test_mg_pcg_fp32_storage_reaches_the_oracle_residual(p, m, inner):
     """MG-PCG with FP32 level storage (z in FP32; x, r, p and the dot
     products in FP64) reaches the same true residual as the FP64 solve,
@@ -409,9 +412,9 @@ def test_mg_wave_rejects_what_it_does_not_cover():
         with pytest.raises(tpfdm.TpfdmError) as e:
             tpfdm.MG(plan)
         assert e.value.status == -2
-    with _cube_plan(5, 2) as plan:
+    with _cube_plan(7, 2) as plan:
         with pytest.raises(tpfdm.TpfdmError) as e:
-            tpfdm.MG(plan, storage=tpfdm.F32)
+            tpfdm.MG(plan, storage=tpfdm.F16)
         assert e.value.status == -2
 
 
@@ -449,4 +452,34 @@ def test_vcycle_degree_level_matches_oracle(p, cells, h):
     print(f"  vcycle rel err={err:.2e} {s} true relres {true:.2e}")
     assert err <= 1e-11
     assert s["converged"] and abs(s["iterations"] - ito) <= 1
+    assert true <= 2e-10
+
+
+@pytest.mark.parametrize("p,cells,h", [DEGREE_CASES[1], DEGREE_CASES[2]])
+def test_vcycle_degree_level_fp32_storage(p, cells, h):
+    """FP32 level vectors on a hierarchy that ends on the degree-1 level (its
+    right-hand side, correction and dense solve in FP64): the V-cycle within
+    FP32 roundings of the oracle's, MG-PCG with an FP32 inner precision in
+    the oracle's iteration count + 1 to its true residual."""
+    torch = _torch()
+    H = mg.Hierarchy(p, cells, h=h, coarse_degree=1)
+    b = _rhs(H.A[0].shape[0], 95 + p + sum(cells))
+    xo = H.vcycle(b)
+    _, ito, _ = sipg.pcg(H.A[0], b, H.vcycle, 1e-10, 200)
+    with tpfdm.Plan.mesh(p + 1, cells, h) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
+        with tpfdm.MG(plan, storage=tpfdm.F32) as V, tpfdm.PCG(plan) as solver:
+            bb = to_blocked(plan, b, tpfdm.F64)
+            bx = torch.full_like(bb, float("nan"))
+            V.vcycle(bb, bx)
+            x = from_blocked(plan, bx, tpfdm.F64)
+            solver.set_multigrid(V)
+            bs = torch.zeros_like(bb)
+            s = solver.solve(bb, bs, inner=tpfdm.F32, rtol=1e-10, maxit=200, check_every=4)
+            xs = from_blocked(plan, bs, tpfdm.F64)
+    err = np.abs(x - xo).max() / np.abs(xo).max()
+    true = np.linalg.norm(b - H.A[0] @ xs) / np.linalg.norm(b)
+    print(f"p={p} cells={cells} FP32 levels: vcycle rel err={err:.2e} oracle_iters={ito} {s} true relres {true:.2e}")
+    assert np.all(np.isfinite(x)) and err <= 2e-5
+    assert s["converged"] and s["iterations"] <= ito + 1
     assert true <= 2e-10

@@ -39,11 +39,12 @@ def test_every_class_of_the_serving_mix_uses_multigrid():
 
 
 def test_multigrid_level_storage_follows_the_inner_precision():
-    """Slots of an FP32-inner server keep FP32 multigrid level vectors where
-    the library has them (n <= 4), at half the bytes; n = 8 stays FP64."""
-    assert serve.mg_storage(2, tpfdm.F32) == tpfdm.F32 and serve.mg_storage(3, tpfdm.F32) == tpfdm.F32
-    assert serve.mg_storage(3, tpfdm.F64) == tpfdm.F64
-    assert serve.mg_storage(7, tpfdm.F32) == tpfdm.F64
+    """Slots of an FP32-inner server keep FP32 multigrid level vectors, at
+    half the bytes; an FP64-inner server FP64 ones."""
+    for p in (2, 3, 7):
+        assert serve.mg_storage(p, tpfdm.F32) == tpfdm.F32
+        assert serve.mg_storage(p, tpfdm.F64) == tpfdm.F64
+    assert 2 * serve.mg_bytes(7, 16, tpfdm.F32) == serve.mg_bytes(7, 16)
     assert 2 * serve.mg_bytes(3, 16, tpfdm.F32) == serve.mg_bytes(3, 16)
     assert (serve.class_slot_bytes(3, 16, True, tpfdm.F32) - serve.class_slot_bytes(3, 16)
             == serve.mg_bytes(3, 16, tpfdm.F32))
