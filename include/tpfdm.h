@@ -464,14 +464,15 @@ tp_status tp_mg_create(tp_plan* plan, tp_mg** out);
 /* The same hierarchy with its level vectors (right-hand sides, corrections,
  * residual scratch, on every level) stored in `storage`: TP_F64 (as
  * tp_mg_create) or TP_F32, which halves the bytes every smoothing, transfer
- * and coarse kernel moves.  Arithmetic stays FP64 in registers (the
- * smoother's block inverse in the solve's inner precision); values are
- * rounded to FP32 where a level vector is stored.  A V-cycle first rounds
- * b into the finest FP32 right-hand side; tp_mg_vcycle writes x back in
- * FP64, and inside tp_pcg_* solves the preconditioned residual z stays in
- * FP32 (the CG recurrences, x, r, p and every dot product remain FP64:
- * (r, z) and p = z + beta p read z in FP32).  TP_ERR_UNSUPPORTED for other
- * types, and for FP32 storage with n >= 5. */
+ * and coarse kernel moves.  With TP_F32 the operator rows of the smoothing
+ * updates and of the residual are computed in FP32 as well, the smoother's
+ * block inverse in the solve's inner precision, the transfers and the
+ * degree-1 coarsest level (n >= 5) in FP64; values are rounded to FP32
+ * where a level vector is stored.  A V-cycle first rounds b into the finest
+ * FP32 right-hand side; tp_mg_vcycle writes x back in FP64, and inside
+ * tp_pcg_* solves the preconditioned residual z stays in FP32 (the CG
+ * recurrences, x, r, p and every dot product remain FP64: (r, z) and
+ * p = z + beta p read z in FP32).  TP_ERR_UNSUPPORTED for other types. */
 tp_status tp_mg_create_typed(tp_plan* plan, tp_dtype storage, tp_mg** out);
 tp_status tp_mg_vcycle(tp_mg* mg, const double* b, double* x, hipStream_t stream);
 tp_status tp_mg_destroy(tp_mg* mg);
