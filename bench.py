@@ -856,26 +856,31 @@ def run_mg_paper(args, stream):
             b = torch.empty(plan.vector_elems, dtype=torch.float64, device="cuda")
             plan.pack(torch.from_numpy(mesh.u).cuda(), b)
             x = torch.empty_like(b)
-            mg = tpfdm.MG(plan)
             solver = tpfdm.PCG(plan)
-            solver.set_multigrid(mg)
             solver.set_norm(tpfdm.PCG_PRECONDITIONED)
-            reps = 10 if m <= 64 else 4
-            lat, s = [], None
-            for i in range(reps + 1):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                s = solver.solve(b, x, inner=tpfdm.F64, rtol=1e-10, maxit=100, check_every=4, stream=stream)
-                t1 = time.perf_counter()
-                if i >= 1:
-                    lat.append(t1 - t0)
-            t = float(np.median(lat))
-            print(json.dumps({"workload": f"mg_pcg_p{p}_{m}cube_precnorm_1e-10", "basis": basis,
-                              "ndof": mesh.ndof, "iterations": s["iterations"], "relres": s["relres"],
-                              "solve_ms": t * 1e3, "solve_MDoF/s": mesh.ndof / t / 1e6,
-                              "ms_per_iteration": t * 1e3 / max(1, s["iterations"])}), flush=True)
+            # the paper's configuration (FP64 throughout), then the mixed form:
+            # FP32 level vectors and inner precision, FP64 CG
+            for storage, inner in ((tpfdm.F64, tpfdm.F64), (tpfdm.F32, tpfdm.F32)):
+                mg = tpfdm.MG(plan, storage=storage)
+                solver.set_multigrid(mg)
+                reps = 10 if m <= 64 else 4
+                lat, s = [], None
+                for i in range(reps + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    s = solver.solve(b, x, inner=inner, rtol=1e-10, maxit=100, check_every=4, stream=stream)
+                    t1 = time.perf_counter()
+                    if i >= 1:
+                        lat.append(t1 - t0)
+                t = float(np.median(lat))
+                print(json.dumps({"workload": f"mg_pcg_p{p}_{m}cube_precnorm_1e-10", "basis": basis,
+                                  "level_storage": tpfdm.DTYPE_NAMES[storage], "inner": tpfdm.DTYPE_NAMES[inner],
+                                  "ndof": mesh.ndof, "iterations": s["iterations"], "relres": s["relres"],
+                                  "solve_ms": t * 1e3, "solve_MDoF/s": mesh.ndof / t / 1e6,
+                                  "ms_per_iteration": t * 1e3 / max(1, s["iterations"])}), flush=True)
+                solver.set_multigrid(None)
+                mg.destroy()
             solver.destroy()
-            mg.destroy()
             plan.destroy()
             del b, x
             torch.cuda.empty_cache()
