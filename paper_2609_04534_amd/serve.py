@@ -127,7 +127,7 @@ def _slot_bytes(E, nblocks, p, m, multigrid, storage=tpfdm.F64):
 
 class Server:
     def __init__(self, hbm_budget: int, inner: int = tpfdm.F32, rtol: float = 1e-8, maxit: int = 20000,
-                 check_every: int = 8, max_inflight: int = 32, multigrid: bool = False):
+                 check_every: int = 8, max_inflight: int = 16, multigrid: bool = False):
         self.budget = int(hbm_budget)
         self.multigrid = multigrid      # one V-cycle as the preconditioner where it applies
         self.max_inflight = max_inflight
