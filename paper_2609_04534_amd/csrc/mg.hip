@@ -995,6 +995,18 @@ void free_mg(tp_mg* m) {
     m->deg_b = m->deg_u = nullptr;
 }
 
+template <int N, bool VP>
+void launch_dot_wave(const MgLevel& L, const double* a, const void* b, bool b32, double* part, const PcgState* ps,
+                     hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(L.G.ncells);
+    if (b32)
+        hipLaunchKernelGGL((k_mg_dot_wave<N, VP, float>), dim3(grid), dim3(64), 0, s, a, static_cast<const float*>(b),
+                           L.G, part, ps);
+    else
+        hipLaunchKernelGGL((k_mg_dot_wave<N, VP, double>), dim3(grid), dim3(64), 0, s, a, static_cast<const double*>(b),
+                           L.G, part, ps);
+}
+
 tp_status convert_launch(const void* src, void* dst, bool to_f32, int64_t n, const PcgState* st, hipStream_t s) {
     const unsigned grid = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 8192));
     if (to_f32)
@@ -1038,6 +1050,9 @@ const float* mg_result32(const tp_mg* m) {
 tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const void* b, bool b32, double* part, const void* st,
                          hipStream_t s) {
     const MgLevel& L = m->lv[0];
+    // 16-byte pencil loads for n = 8 (and n = 6 with FP64 b) when both
+    // vectors are 16-byte aligned (solver and level vectors are)
+    const bool vp = reinterpret_cast<uintptr_t>(a) % 16 == 0 && reinterpret_cast<uintptr_t>(b) % 16 == 0;
     const unsigned grid = static_cast<unsigned>((L.G.ncells + 63) / 64);
     const PcgState* ps = static_cast<const PcgState*>(st);
     const double* bd = static_cast<const double*>(b);
@@ -1055,37 +1070,15 @@ tp_status mg_enqueue_dot(const tp_mg* m, const double* a, const void* b, bool b3
             if (b32) hipLaunchKernelGGL((k_mg_dot<4, float>), dim3(grid), dim3(64), 0, s, a, bf, L.G, part, ps);
             else hipLaunchKernelGGL((k_mg_dot<4, double>), dim3(grid), dim3(64), 0, s, a, bd, L.G, part, ps);
             break;
-        case 5:
-            if (b32)
-                hipLaunchKernelGGL((k_mg_dot_wave<5, false, float>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64),
-                                   0, s, a, bf, L.G, part, ps);
-            else
-                hipLaunchKernelGGL((k_mg_dot_wave<5, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0,
-                                   s, a, bd, L.G, part, ps);
-            break;
+        case 5: launch_dot_wave<5, false>(L, a, b, b32, part, ps, s); break;
         case 6:
-            if (b32)
-                hipLaunchKernelGGL((k_mg_dot_wave<6, false, float>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64),
-                                   0, s, a, bf, L.G, part, ps);
-            else
-                hipLaunchKernelGGL((k_mg_dot_wave<6, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0,
-                                   s, a, bd, L.G, part, ps);
+            if (vp && !b32) launch_dot_wave<6, true>(L, a, b, b32, part, ps, s);
+            else launch_dot_wave<6, false>(L, a, b, b32, part, ps, s);
             break;
-        case 7:
-            if (b32)
-                hipLaunchKernelGGL((k_mg_dot_wave<7, false, float>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64),
-                                   0, s, a, bf, L.G, part, ps);
-            else
-                hipLaunchKernelGGL((k_mg_dot_wave<7, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0,
-                                   s, a, bd, L.G, part, ps);
-            break;
+        case 7: launch_dot_wave<7, false>(L, a, b, b32, part, ps, s); break;
         case 8:
-            if (b32)
-                hipLaunchKernelGGL((k_mg_dot_wave<8, false, float>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64),
-                                   0, s, a, bf, L.G, part, ps);
-            else
-                hipLaunchKernelGGL((k_mg_dot_wave<8, false>), dim3(static_cast<unsigned>(L.G.ncells)), dim3(64), 0,
-                                   s, a, bd, L.G, part, ps);
+            if (vp) launch_dot_wave<8, true>(L, a, b, b32, part, ps, s);
+            else launch_dot_wave<8, false>(L, a, b, b32, part, ps, s);
             break;
         default: return set_error(TP_ERR_UNSUPPORTED, "multigrid supports n <= 8");
     }
