@@ -483,3 +483,33 @@ def test_vcycle_degree_level_fp32_storage(p, cells, h):
     assert np.all(np.isfinite(x)) and err <= 2e-5
     assert s["converged"] and s["iterations"] <= ito + 1
     assert true <= 2e-10
+
+
+@pytest.mark.parametrize("p,cells,h", BOX_CASES + [(7, (2, 4, 2), (0.5, 0.25, 0.4)), (5, (4, 2, 2), (0.2, 0.4, 0.3))])
+def test_vcycle_fp32_storage_on_boxes(p, cells, h):
+    """FP32 level vectors on boxes with unequal counts and lengths (lane
+    kernels for n <= 4, wave kernels for n >= 5): the V-cycle within FP32
+    roundings of the oracle's FP64 one, MG-PCG with an FP32 inner precision
+    within the oracle's iteration count + 1 to its true residual."""
+    torch = _torch()
+    H = mg.Hierarchy(p, cells, h=h)
+    b = _rhs(H.A[0].shape[0], 3 * sum(cells) + p)
+    xo = H.vcycle(b)
+    _, ito, _ = sipg.pcg(H.A[0], b, H.vcycle, 1e-10, 200)
+    with tpfdm.Plan.mesh(p + 1, cells, h) as plan:
+        plan.setup_inverse(tpfdm.OP_CELL)
+        with tpfdm.MG(plan, storage=tpfdm.F32) as V, tpfdm.PCG(plan) as solver:
+            bb = to_blocked(plan, b, tpfdm.F64)
+            bx = torch.full_like(bb, float("nan"))
+            V.vcycle(bb, bx)
+            x = from_blocked(plan, bx, tpfdm.F64)
+            solver.set_multigrid(V)
+            bs = torch.zeros_like(bb)
+            s = solver.solve(bb, bs, inner=tpfdm.F32, rtol=1e-10, maxit=200, check_every=4)
+            xs = from_blocked(plan, bs, tpfdm.F64)
+    err = np.abs(x - xo).max() / np.abs(xo).max()
+    true = np.linalg.norm(b - H.A[0] @ xs) / np.linalg.norm(b)
+    print(f"p={p} cells={cells} FP32 levels: vcycle rel err={err:.2e} oracle_iters={ito} {s} true {true:.2e}")
+    assert np.all(np.isfinite(x)) and err <= 2e-5
+    assert s["converged"] and s["iterations"] <= ito + 1
+    assert true <= 2e-10
